@@ -1,0 +1,243 @@
+"""Python face of the plain FP64 CPU oracle (``tdp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the package's smoke
+check and by the benchmark's CPU-baseline leg, never by the product path.
+
+Every array is in the netlist's own (external) pin and cell numbering.  The
+C library is compiled by ``build_oracle()`` (gcc, -O2, IEEE double).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tdp_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libtdp_oracle.so")
+_lib = None
+
+
+def build_oracle() -> str:
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", _LIB_PATH, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build_oracle()
+        _lib = ctypes.CDLL(_LIB_PATH)
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _netlist_args(nl) -> list:
+    keep = [_i32(nl["pin_cell"]), _f32(nl["pin_off_x"]), _f32(nl["pin_off_y"]),
+            _i32(nl["net_ptr"]), _i32(nl["net_pins"]), _i32(nl["cell_type"]),
+            _i32(nl["cell_in_ptr"]), _i32(nl["cell_in_pins"]), _i32(nl["cell_out_pin"]),
+            np.ascontiguousarray(nl["cell_is_ff"], dtype=np.uint8)]
+    args = [ctypes.c_int(int(nl["num_cells"])), ctypes.c_int(int(nl["num_pins"])),
+            ctypes.c_int(int(nl["num_nets"]))] + [_p(a) for a in keep]
+    return args, keep
+
+
+def _lib_args(lib) -> list:
+    nt = int(lib["num_types"])
+    keep = [_f32(lib["slew_axis"]).reshape(nt, -1), _f32(lib["load_axis"]).reshape(nt, -1),
+            _f32(lib["delay_lut"]), _f32(lib["slew_lut"]), _f32(lib["pin_cap"])]
+    n_slew = keep[0].shape[1]
+    n_load = keep[1].shape[1]
+    args = [ctypes.c_int(nt), ctypes.c_int(n_slew), ctypes.c_int(n_load)] + [_p(a) for a in keep] + [
+        ctypes.c_double(float(np.float32(lib["r_per_um"]))),
+        ctypes.c_double(float(np.float32(lib["c_per_um"]))),
+        ctypes.c_double(float(np.float32(lib["delay_scale"])))]
+    return args, keep
+
+
+def lut_eval(slew_axis, load_axis, table, slew, load) -> np.ndarray:
+    """Bilinear table lookup with clamping (one table)."""
+    L = _load()
+    sa, la, tb = _f32(slew_axis), _f32(load_axis), _f32(table)
+    s, l = _f64(slew), _f64(load)
+    out = np.empty(s.shape[0], np.float64)
+    L.ora_lut_eval(ctypes.c_int(sa.shape[0]), ctypes.c_int(la.shape[0]), _p(sa), _p(la), _p(tb),
+                   ctypes.c_int(s.shape[0]), _p(s), _p(l), _p(out))
+    return out
+
+
+def sta(nl, lib, x=None, y=None, clock_period: Optional[float] = None) -> Dict[str, np.ndarray]:
+    """Full static timing analysis.  Returns per-pin arrays and WNS/TNS."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    T = float(nl["clock_period"] if clock_period is None else clock_period)
+    P, N = int(nl["num_pins"]), int(nl["num_cells"])
+    out = {k: np.empty(P, np.float64) for k in ("at", "slew", "rat", "slack", "dnet", "load", "darc")}
+    crit = np.empty(N, np.int32)
+    summ = np.zeros(3, np.float64)
+    na, k1 = _netlist_args(nl)
+    la, k2 = _lib_args(lib)
+    rc = L.ora_sta(*na, *la, _p(x), _p(y), ctypes.c_double(T), ctypes.c_double(float(nl["setup"])),
+                   ctypes.c_double(float(nl["input_slew"])), ctypes.c_double(float(nl["clock_slew"])),
+                   _p(out["at"]), _p(out["slew"]), _p(out["rat"]), _p(out["slack"]), _p(out["dnet"]),
+                   _p(out["load"]), _p(out["darc"]), _p(crit), _p(summ))
+    if rc != 0:
+        raise ValueError("timing graph has a cycle")
+    out["crit"] = crit
+    out["wns"], out["tns"], out["n_fail"] = float(summ[0]), float(summ[1]), int(summ[2])
+    out["clock_period"] = T
+    return out
+
+
+def endpoint_pins(nl) -> np.ndarray:
+    ff = np.nonzero(np.asarray(nl["cell_is_ff"]) != 0)[0]
+    ptr = np.asarray(nl["cell_in_ptr"])
+    return np.asarray(nl["cell_in_pins"])[ptr[ff]]
+
+
+def extract(nl, lib, st, n: int = -1, k: int = 1, K: int = 1 << 30,
+            slack_limit: float = float("inf")) -> Dict[str, np.ndarray]:
+    """report_timing_endpoint(n, k): up to k worst paths at each of the n
+    worst endpoints (n < 0: the violated ones), ordered by (slack, endpoint
+    pin, rank) and cut to K."""
+    L = _load()
+    P = int(nl["num_pins"])
+    E = int(np.count_nonzero(nl["cell_is_ff"]))
+    nsel_max = E
+    max_paths = max(1, min(K, nsel_max * k))
+    pin_cap = max(16, max_paths * (2 * int(nl.get("depth", 64)) + 8))
+    # the longest possible path is bounded by the pin count; grow on demand
+    while True:
+        path_ptr = np.zeros(max_paths + 1, np.int32)
+        path_pins = np.zeros(pin_cap, np.int32)
+        path_ep = np.zeros(max_paths, np.int32)
+        path_rank = np.zeros(max_paths, np.int32)
+        path_slack = np.zeros(max_paths, np.float64)
+        sel_ep = np.zeros(max(1, E), np.int32)
+        ep_next = np.zeros(max(1, E), np.float64)
+        num_sel = np.zeros(1, np.int32)
+        na, k1 = _netlist_args(nl)
+        arrs = [_f64(st["at"]), _f64(st["rat"]), _f64(st["dnet"]), _f64(st["darc"]), _i32(st["crit"])]
+        rc = L.ora_extract(*na, *[_p(a) for a in arrs], ctypes.c_int(n), ctypes.c_int(k),
+                           ctypes.c_int(min(K, max_paths)), ctypes.c_double(slack_limit), _p(path_ptr),
+                           _p(path_pins), ctypes.c_int(pin_cap), _p(path_ep), _p(path_rank),
+                           _p(path_slack), _p(sel_ep), _p(ep_next), _p(num_sel))
+        if rc == -2:
+            pin_cap *= 2
+            continue
+        if rc < 0:
+            raise ValueError("timing graph has a cycle")
+        break
+    m = rc
+    ns = int(num_sel[0])
+    return {"num_paths": m, "path_ptr": path_ptr[:m + 1].copy(),
+            "path_pins": path_pins[:path_ptr[m]].copy(), "path_ep": path_ep[:m].copy(),
+            "path_rank": path_rank[:m].copy(), "path_slack": path_slack[:m].copy(),
+            "sel_ep": sel_ep[:ns].copy(), "ep_next": ep_next[:ns].copy(), "k": k}
+
+
+def path_list(paths) -> list:
+    ptr, pins = paths["path_ptr"], paths["path_pins"]
+    return [pins[ptr[i]:ptr[i + 1]].tolist() for i in range(paths["num_paths"])]
+
+
+class PairState:
+    """The maintained pin-pair set P with its weights (dense over pin ids)."""
+
+    def __init__(self, num_pins: int):
+        self.in_p = np.zeros(num_pins, np.uint8)
+        self.w = np.zeros(num_pins, np.float64)
+
+    def pairs(self):
+        sinks = np.nonzero(self.in_p)[0].astype(np.int32)
+        return sinks, self.w[sinks].copy()
+
+
+def pairs_update(state: PairState, paths, wns: float, rule: int = 0, w0: float = 10.0,
+                 w1: float = 0.2) -> PairState:
+    L = _load()
+    m = int(paths["num_paths"])
+    ptr, pins, sl = _i32(paths["path_ptr"]), _i32(paths["path_pins"]), _f64(paths["path_slack"])
+    if ptr.shape[0] == 0:
+        ptr = np.zeros(1, np.int32)
+    if pins.shape[0] == 0:
+        pins = np.zeros(1, np.int32)
+    if sl.shape[0] == 0:
+        sl = np.zeros(1, np.float64)
+    L.ora_pairs(ctypes.c_int(state.w.shape[0]), ctypes.c_int(m), _p(ptr), _p(pins), _p(sl),
+                ctypes.c_double(wns), ctypes.c_int(rule), ctypes.c_double(w0), ctypes.c_double(w1),
+                _p(state.in_p), _p(state.w))
+    return state
+
+
+def p2p(nl, pair_sink, pair_w, x=None, y=None):
+    """PP = sum w * ((X_s - X_t)^2 + (Y_s - Y_t)^2) and its cell gradient."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    N = int(nl["num_cells"])
+    gx, gy = np.empty(N, np.float64), np.empty(N, np.float64)
+    loss = np.zeros(1, np.float64)
+    ps, pw = _i32(pair_sink), _f64(pair_w)
+    if ps.shape[0] == 0:
+        ps, pw = np.zeros(1, np.int32), np.zeros(1, np.float64)
+    na, keep = _netlist_args(nl)
+    fixed = np.ascontiguousarray(nl["cell_fixed"], dtype=np.uint8)
+    L.ora_p2p(*na, _p(fixed), _p(x), _p(y), ctypes.c_int(len(pair_sink)), _p(ps), _p(pw),
+              _p(loss), _p(gx), _p(gy))
+    return float(loss[0]), gx, gy
+
+
+def stns(nl, lib, st, gamma: float = 10.0, x=None, y=None):
+    """Smoothed TNS (frozen cell arcs and start-point arrivals from `st`)."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    N = int(nl["num_cells"])
+    gx, gy = np.empty(N, np.float64), np.empty(N, np.float64)
+    val = np.zeros(1, np.float64)
+    na, k1 = _netlist_args(nl)
+    la, k2 = _lib_args(lib)
+    fixed = np.ascontiguousarray(nl["cell_fixed"], dtype=np.uint8)
+    at0, darc = _f64(st["at"]), _f64(st["darc"])
+    rc = L.ora_stns(*na, *la, _p(fixed), _p(x), _p(y), _p(at0), _p(darc),
+                    ctypes.c_double(float(st["clock_period"])), ctypes.c_double(float(nl["setup"])),
+                    ctypes.c_double(gamma), _p(val), _p(gx), _p(gy))
+    if rc != 0:
+        raise ValueError("timing graph has a cycle")
+    return float(val[0]), gx, gy
+
+
+def wa(nl, gamma: float = 5.0, x=None, y=None):
+    """Weighted-average wirelength over all nets, both axes, and its gradient."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    N = int(nl["num_cells"])
+    gx, gy = np.empty(N, np.float64), np.empty(N, np.float64)
+    val = np.zeros(1, np.float64)
+    na, keep = _netlist_args(nl)
+    fixed = np.ascontiguousarray(nl["cell_fixed"], dtype=np.uint8)
+    L.ora_wa(*na, _p(fixed), _p(x), _p(y), ctypes.c_double(gamma), _p(val), _p(gx), _p(gy))
+    return float(val[0]), gx, gy

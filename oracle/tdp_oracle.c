@@ -1,0 +1,752 @@
+/*
+ * Plain FP64 CPU oracle for the timing-driven placement hot path of
+ * "Timing-Driven Global Placement by Efficient Critical Path Extraction"
+ * (Shi et al., arXiv 2503.11674).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the package's smoke check
+ * and the benchmark's CPU-baseline leg may load this library.  It shares no
+ * code, header or table with the HIP implementation: it takes the same
+ * netlist arrays (external pin / cell numbering) and computes everything with
+ * straightforward loops in double precision, single threaded.
+ *
+ * What it computes, and where the paper defines it:
+ *   ora_sta      - static timing analysis on the timing DAG (Sec. II-B, Eq. 2):
+ *                  arrival times forward, required times backward,
+ *                  slack = required - arrival at every pin; WNS and TNS over
+ *                  violated endpoints, both 0 when none violates (Eqs. 3-4).
+ *                  Net delay is R*C, with R and C linear in wire length
+ *                  (Sec. III-C, Eq. 7), i.e. r*c*L^2 with L the Manhattan
+ *                  distance; cell arcs come from slew x load tables.
+ *   ora_extract  - report_timing_endpoint(n, k) (Sec. III-B, Table I): the n
+ *                  most critical endpoints, and the k worst paths at each.
+ *                  Reached by deviation (sidetrack) enumeration from the
+ *                  arrival-time tree, in order of path slack.
+ *   ora_pairs    - the maintained pin-pair set P and the weight rule of
+ *                  Eq. 9 (Sec. III-D), or the stateless exponential rule.
+ *   ora_p2p      - PP = sum w * Q(i, j), Q the squared Euclidean pin distance
+ *                  (Eqs. 8 and 10), with its gradient on cell positions.
+ *   ora_stns     - a log-sum-exp smoothed TNS with its adjoint (not in the
+ *                  paper; definition below).
+ *   ora_wa       - weighted-average wirelength (the WL_e of Eq. 1, the
+ *                  published weighted-average model) with its gradient.
+ *
+ * Pin roles: a port (pin_cell == -1) is a primary input and drives a net;
+ * a combinational cell has input pins (net sinks) and one output pin (a net
+ * driver); a flip-flop has a D pin (net sink, timing endpoint) and a Q pin
+ * (net driver, timing startpoint).  The clock is ideal: a flip-flop's
+ * clock-to-Q arc is looked up at the clock slew and the Q pin's load.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ROLE_PORT 0
+#define ROLE_CIN 1
+#define ROLE_COUT 2
+#define ROLE_FFD 3
+#define ROLE_FFQ 4
+
+typedef struct {
+  int num_cells, num_pins, num_nets;
+  const int32_t *pin_cell;
+  const float *pin_off_x, *pin_off_y;
+  const int32_t *net_ptr, *net_pins;
+  const int32_t *cell_type, *cell_in_ptr, *cell_in_pins, *cell_out_pin;
+  const uint8_t *cell_is_ff;
+} onl;
+
+typedef struct {
+  int num_types, n_slew, n_load;
+  const float *slew_axis, *load_axis, *delay_lut, *slew_lut, *pin_cap;
+  double r, c, scale;
+} olib;
+
+/* ------------------------------------------------------------------------ */
+/* derived connectivity                                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int *role;       /* [P] */
+  int *driver;     /* [P] driver pin of a sink pin, -1 otherwise */
+  int *net_of;     /* [P] net the pin belongs to */
+  int *in_index;   /* [P] arc index of a comb input pin within its cell */
+  int *topo;       /* [P] pins in a topological order */
+} oconn;
+
+static void conn_free(oconn *c) {
+  free(c->role); free(c->driver); free(c->net_of); free(c->in_index); free(c->topo);
+}
+
+/* returns 0, or -1 if the timing graph has a cycle / dangling structure */
+static int conn_build(const onl *n, oconn *c) {
+  int P = n->num_pins, N = n->num_cells, M = n->num_nets;
+  c->role = (int *)malloc(sizeof(int) * P);
+  c->driver = (int *)malloc(sizeof(int) * P);
+  c->net_of = (int *)malloc(sizeof(int) * P);
+  c->in_index = (int *)malloc(sizeof(int) * P);
+  c->topo = (int *)malloc(sizeof(int) * P);
+  for (int p = 0; p < P; ++p) { c->role[p] = ROLE_PORT; c->driver[p] = -1; c->net_of[p] = -1; c->in_index[p] = -1; }
+  for (int cell = 0; cell < N; ++cell) {
+    int ff = n->cell_is_ff[cell];
+    for (int k = n->cell_in_ptr[cell]; k < n->cell_in_ptr[cell + 1]; ++k) {
+      int p = n->cell_in_pins[k];
+      c->role[p] = ff ? ROLE_FFD : ROLE_CIN;
+      c->in_index[p] = k - n->cell_in_ptr[cell];
+    }
+    c->role[n->cell_out_pin[cell]] = ff ? ROLE_FFQ : ROLE_COUT;
+  }
+  for (int net = 0; net < M; ++net) {
+    int d = n->net_pins[n->net_ptr[net]];
+    c->net_of[d] = net;
+    for (int k = n->net_ptr[net] + 1; k < n->net_ptr[net + 1]; ++k) {
+      c->driver[n->net_pins[k]] = d;
+      c->net_of[n->net_pins[k]] = net;
+    }
+  }
+  /* Kahn's algorithm over pins.  Arcs: driver -> sink (net arcs) and comb
+   * input -> comb output (cell arcs). */
+  int *indeg = (int *)calloc(P, sizeof(int));
+  for (int p = 0; p < P; ++p) {
+    if (c->driver[p] >= 0) indeg[p] += 1;
+    if (c->role[p] == ROLE_COUT) {
+      int cell = n->pin_cell[p];
+      indeg[p] += n->cell_in_ptr[cell + 1] - n->cell_in_ptr[cell];
+    }
+  }
+  int head = 0, tail = 0;
+  for (int p = 0; p < P; ++p) if (indeg[p] == 0) c->topo[tail++] = p;
+  while (head < tail) {
+    int p = c->topo[head++];
+    int r = c->role[p];
+    if (r == ROLE_PORT || r == ROLE_COUT || r == ROLE_FFQ) {
+      int net = c->net_of[p];
+      if (net >= 0)
+        for (int k = n->net_ptr[net] + 1; k < n->net_ptr[net + 1]; ++k) {
+          int t = n->net_pins[k];
+          if (--indeg[t] == 0) c->topo[tail++] = t;
+        }
+    } else if (r == ROLE_CIN) {
+      int o = n->cell_out_pin[n->pin_cell[p]];
+      if (--indeg[o] == 0) c->topo[tail++] = o;
+    }
+  }
+  free(indeg);
+  return tail == P ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* lookup table: clamp to the axis range, bilinear in (slew, load)          */
+/* ------------------------------------------------------------------------ */
+static double lut_eval(const olib *L, const float *tables, int type, double slew, double load) {
+  const float *sa = L->slew_axis + (size_t)type * L->n_slew;
+  const float *la = L->load_axis + (size_t)type * L->n_load;
+  const float *T = tables + (size_t)type * L->n_slew * L->n_load;
+  double s = slew, l = load;
+  if (s < sa[0]) s = sa[0];
+  if (s > sa[L->n_slew - 1]) s = sa[L->n_slew - 1];
+  if (l < la[0]) l = la[0];
+  if (l > la[L->n_load - 1]) l = la[L->n_load - 1];
+  int i = 0;
+  while (i + 1 < L->n_slew - 1 && sa[i + 1] <= s) ++i;
+  int j = 0;
+  while (j + 1 < L->n_load - 1 && la[j + 1] <= l) ++j;
+  double tau = (s - sa[i]) / ((double)sa[i + 1] - sa[i]);
+  double ups = (l - la[j]) / ((double)la[j + 1] - la[j]);
+  double t00 = T[i * L->n_load + j], t10 = T[(i + 1) * L->n_load + j];
+  double t01 = T[i * L->n_load + j + 1], t11 = T[(i + 1) * L->n_load + j + 1];
+  return (1 - tau) * (1 - ups) * t00 + tau * (1 - ups) * t10 + (1 - tau) * ups * t01 + tau * ups * t11;
+}
+
+int ora_lut_eval(int n_slew, int n_load, const float *slew_axis, const float *load_axis,
+                 const float *table, int count, const double *slew, const double *load, double *out) {
+  olib L;
+  memset(&L, 0, sizeof L);
+  L.num_types = 1; L.n_slew = n_slew; L.n_load = n_load;
+  L.slew_axis = slew_axis; L.load_axis = load_axis;
+  for (int q = 0; q < count; ++q) out[q] = lut_eval(&L, table, 0, slew[q], load[q]);
+  return 0;
+}
+
+static void pin_xy(const onl *n, const float *x, const float *y, int p, double *px, double *py) {
+  int cell = n->pin_cell[p];
+  double bx = cell >= 0 ? (double)x[cell] : 0.0;
+  double by = cell >= 0 ? (double)y[cell] : 0.0;
+  *px = bx + (double)n->pin_off_x[p];
+  *py = by + (double)n->pin_off_y[p];
+}
+
+#define NETLIST_ARGS                                                                             \
+  int num_cells, int num_pins, int num_nets, const int32_t *pin_cell, const float *pin_off_x,    \
+      const float *pin_off_y, const int32_t *net_ptr, const int32_t *net_pins,                   \
+      const int32_t *cell_type, const int32_t *cell_in_ptr, const int32_t *cell_in_pins,         \
+      const int32_t *cell_out_pin, const uint8_t *cell_is_ff
+#define LIB_ARGS                                                                                 \
+  int num_types, int n_slew, int n_load, const float *slew_axis, const float *load_axis,         \
+      const float *delay_lut, const float *slew_lut, const float *pin_cap, double r_per_um,      \
+      double c_per_um, double delay_scale
+
+#define FILL_NETLIST(nn)                                                                         \
+  onl nn;                                                                                        \
+  nn.num_cells = num_cells; nn.num_pins = num_pins; nn.num_nets = num_nets;                      \
+  nn.pin_cell = pin_cell; nn.pin_off_x = pin_off_x; nn.pin_off_y = pin_off_y;                    \
+  nn.net_ptr = net_ptr; nn.net_pins = net_pins; nn.cell_type = cell_type;                        \
+  nn.cell_in_ptr = cell_in_ptr; nn.cell_in_pins = cell_in_pins; nn.cell_out_pin = cell_out_pin;  \
+  nn.cell_is_ff = cell_is_ff
+#define FILL_LIB(ll)                                                                             \
+  olib ll;                                                                                       \
+  ll.num_types = num_types; ll.n_slew = n_slew; ll.n_load = n_load; ll.slew_axis = slew_axis;    \
+  ll.load_axis = load_axis; ll.delay_lut = delay_lut; ll.slew_lut = slew_lut;                    \
+  ll.pin_cap = pin_cap; ll.r = r_per_um; ll.c = c_per_um; ll.scale = delay_scale
+
+/* ------------------------------------------------------------------------ */
+/* STA                                                                       */
+/* ------------------------------------------------------------------------ */
+/* Outputs (all indexed by external pin id unless noted):
+ *   at, slew, rat, slack  [P]
+ *   dnet  [P]  net delay into a sink pin (0 elsewhere)
+ *   load  [P]  load seen by a driver pin (0 elsewhere)
+ *   darc  [P]  cell-arc delay from a comb input pin to its output (0 elsewhere)
+ *   crit  [N]  arc index of the input that sets a comb cell's output arrival
+ *              (lowest index on ties), -1 for flip-flops
+ *   summary[3] = {WNS, TNS, number of violated endpoints}
+ * Returns 0, or -1 if the timing graph has a cycle. */
+int ora_sta(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double clock_period,
+            double setup, double input_slew, double clock_slew, double *at, double *slew,
+            double *rat, double *slack, double *dnet, double *load, double *darc, int32_t *crit,
+            double *summary) {
+  FILL_NETLIST(n);
+  FILL_LIB(L);
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  int P = num_pins, N = num_cells, M = num_nets;
+  const double kappa = L.scale * L.r * L.c;
+  for (int p = 0; p < P; ++p) {
+    at[p] = -INFINITY; slew[p] = 0; rat[p] = INFINITY; slack[p] = INFINITY;
+    dnet[p] = 0; load[p] = 0; darc[p] = 0;
+  }
+  for (int cell = 0; cell < N; ++cell) crit[cell] = -1;
+
+  /* net pass: Manhattan length, RC net delay, star-model driver load */
+  for (int net = 0; net < M; ++net) {
+    int s = net_pins[net_ptr[net]];
+    double xs, ys;
+    pin_xy(&n, x, y, s, &xs, &ys);
+    double ld = 0.0;
+    for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
+      int t = net_pins[k];
+      double xt, yt;
+      pin_xy(&n, x, y, t, &xt, &yt);
+      double len = fabs(xs - xt) + fabs(ys - yt);
+      dnet[t] = kappa * len * len;
+      ld += (double)pin_cap[cell_type[pin_cell[t]]] + L.c * len;
+    }
+    load[s] = ld;
+  }
+
+  /* forward arrival times in topological order */
+  for (int q = 0; q < P; ++q) {
+    int p = c.topo[q];
+    switch (c.role[p]) {
+      case ROLE_PORT:
+        at[p] = 0.0;
+        slew[p] = input_slew;
+        break;
+      case ROLE_FFQ: {
+        int type = cell_type[pin_cell[p]];
+        at[p] = lut_eval(&L, delay_lut, type, clock_slew, load[p]);
+        slew[p] = lut_eval(&L, slew_lut, type, clock_slew, load[p]);
+        break;
+      }
+      case ROLE_CIN:
+      case ROLE_FFD:
+        if (c.driver[p] >= 0) {
+          at[p] = at[c.driver[p]] + dnet[p];
+          slew[p] = slew[c.driver[p]];
+        }
+        break;
+      case ROLE_COUT: {
+        int cell = pin_cell[p], type = cell_type[cell];
+        double best = -INFINITY, sl = 0.0;
+        int arg = -1;
+        for (int k = cell_in_ptr[cell]; k < cell_in_ptr[cell + 1]; ++k) {
+          int i = cell_in_pins[k];
+          if (at[i] == -INFINITY) continue;
+          double d = lut_eval(&L, delay_lut, type, slew[i], load[p]);
+          double so = lut_eval(&L, slew_lut, type, slew[i], load[p]);
+          darc[i] = d;
+          double a = at[i] + d;
+          if (a > best) { best = a; arg = k - cell_in_ptr[cell]; }
+          if (so > sl) sl = so;
+        }
+        at[p] = best;
+        slew[p] = sl;
+        crit[cell] = arg;
+        break;
+      }
+    }
+  }
+
+  /* endpoints: required time at a D pin is the clock period minus setup */
+  double wns = 0.0, tns = 0.0;
+  long nfail = 0;
+  for (int p = 0; p < P; ++p)
+    if (c.role[p] == ROLE_FFD) {
+      rat[p] = clock_period - setup;
+      double s = rat[p] - at[p];
+      if (at[p] == -INFINITY) s = INFINITY;
+      if (s < 0) { nfail++; tns += s; if (s < wns) wns = s; }
+    }
+  summary[0] = wns; summary[1] = tns; summary[2] = (double)nfail;
+
+  /* backward required times in reverse topological order */
+  for (int q = P - 1; q >= 0; --q) {
+    int p = c.topo[q];
+    int r = c.role[p];
+    if (r == ROLE_CIN) {
+      int o = cell_out_pin[pin_cell[p]];
+      rat[p] = rat[o] == INFINITY ? INFINITY : rat[o] - darc[p];
+    } else if (r == ROLE_PORT || r == ROLE_COUT || r == ROLE_FFQ) {
+      double best = INFINITY;
+      int net = c.net_of[p];
+      if (net >= 0)
+        for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
+          int t = net_pins[k];
+          if (rat[t] == INFINITY) continue;
+          double v = rat[t] - dnet[t];
+          if (v < best) best = v;
+        }
+      rat[p] = best;
+    }
+  }
+  for (int p = 0; p < P; ++p)
+    slack[p] = (rat[p] == INFINITY || at[p] == -INFINITY) ? INFINITY : rat[p] - at[p];
+  conn_free(&c);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* k worst paths per endpoint                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct { double cost; long seq; int parent; int dev; int u; } ocand;
+
+typedef struct { ocand *a; int n, cap; } oheap;
+
+static int cand_less(const ocand *x, const ocand *y) {
+  if (x->cost != y->cost) return x->cost < y->cost;
+  return x->seq < y->seq;
+}
+static void heap_push(oheap *h, ocand v) {
+  if (h->n == h->cap) { h->cap = h->cap ? 2 * h->cap : 64; h->a = (ocand *)realloc(h->a, sizeof(ocand) * h->cap); }
+  int i = h->n++;
+  h->a[i] = v;
+  while (i > 0) {
+    int par = (i - 1) / 2;
+    if (!cand_less(&h->a[i], &h->a[par])) break;
+    ocand t = h->a[i]; h->a[i] = h->a[par]; h->a[par] = t;
+    i = par;
+  }
+}
+static ocand heap_pop(oheap *h) {
+  ocand top = h->a[0];
+  h->a[0] = h->a[--h->n];
+  int i = 0;
+  for (;;) {
+    int l = 2 * i + 1, r = l + 1, m = i;
+    if (l < h->n && cand_less(&h->a[l], &h->a[m])) m = l;
+    if (r < h->n && cand_less(&h->a[r], &h->a[m])) m = r;
+    if (m == i) break;
+    ocand t = h->a[i]; h->a[i] = h->a[m]; h->a[m] = t;
+    i = m;
+  }
+  return top;
+}
+
+typedef struct { double slack; int ep; int rank; int start; int len; } opath;
+
+static int opath_cmp(const void *a, const void *b) {
+  const opath *x = (const opath *)a, *y = (const opath *)b;
+  if (x->slack != y->slack) return x->slack < y->slack ? -1 : 1;
+  if (x->ep != y->ep) return x->ep < y->ep ? -1 : 1;
+  return x->rank < y->rank ? -1 : (x->rank > y->rank);
+}
+
+typedef struct { double slack; int pin; } oep;
+static int oep_cmp(const void *a, const void *b) {
+  const oep *x = (const oep *)a, *y = (const oep *)b;
+  if (x->slack != y->slack) return x->slack < y->slack ? -1 : 1;
+  return x->pin < y->pin ? -1 : (x->pin > y->pin);
+}
+
+/* Inputs: the STA results of ora_sta for the same netlist.
+ * n_sel < 0 selects the violated endpoints.  Up to k paths per endpoint are
+ * returned, ordered by (path slack, endpoint pin, rank) and cut to K; paths
+ * whose slack is >= slack_limit are not expanded.  For every selected
+ * endpoint, ep_next[] receives the slack of its (k+1)-th path (+inf if none),
+ * so a caller can tell how far rank k sits from the next path.
+ * Outputs: path_ptr[K+1], path_pins[pin_cap], path_ep[K], path_rank[K],
+ * path_slack[K]; sel_ep[E] / ep_next[E] for the selected endpoints in
+ * selection order.  Returns the number of paths, -1 on a cycle, -2 if an
+ * output capacity is too small, -3 if k is outside 1..4000. */
+int ora_extract(NETLIST_ARGS, const double *at, const double *rat, const double *dnet,
+                const double *darc, const int32_t *crit, int n_sel, int k, int K,
+                double slack_limit, int32_t *path_ptr, int32_t *path_pins, int pins_capacity,
+                int32_t *path_ep, int32_t *path_rank, double *path_slack, int32_t *sel_ep,
+                double *ep_next, int32_t *num_sel) {
+  FILL_NETLIST(n);
+  oconn c;
+  if (k < 1 || k > 4000) return -3;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  int P = num_pins;
+
+  /* endpoint order: (slack, pin id) */
+  int E = 0;
+  for (int p = 0; p < P; ++p) if (c.role[p] == ROLE_FFD) E++;
+  oep *eps = (oep *)malloc(sizeof(oep) * (E > 0 ? E : 1));
+  E = 0;
+  for (int p = 0; p < P; ++p)
+    if (c.role[p] == ROLE_FFD) {
+      double s = (at[p] == -INFINITY) ? INFINITY : rat[p] - at[p];
+      eps[E].slack = s; eps[E].pin = p; E++;
+    }
+  qsort(eps, E, sizeof(oep), oep_cmp);
+  int nsel = n_sel;
+  if (nsel < 0) { nsel = 0; while (nsel < E && eps[nsel].slack < 0) nsel++; }
+  if (nsel > E) nsel = E;
+  *num_sel = nsel;
+
+  int maxlen = 2 * P + 2;
+  opath *paths = NULL;
+  int npaths = 0, pcap = 0;
+  int32_t *pool = NULL;
+  long pool_n = 0, pool_cap = 0;
+  int *chain_pins = (int *)malloc(sizeof(int) * maxlen);
+
+  for (int q = 0; q < nsel; ++q) {
+    int e = eps[q].pin;
+    sel_ep[q] = e;
+    ep_next[q] = INFINITY;
+    double s_e = eps[q].slack;
+    if (s_e == INFINITY) continue;
+    oheap h = {0, 0, 0};
+    ocand *popped = (ocand *)malloc(sizeof(ocand) * (k + 1));
+    int npop = 0;
+    long seq = 0;
+    ocand root = {0.0, seq++, -1, -1, c.driver[e]};
+    heap_push(&h, root);
+    while (h.n > 0 && npop < k + 1) {
+      ocand p = heap_pop(&h);
+      if (s_e + p.cost >= slack_limit) break;
+      if (npop == k) { ep_next[q] = s_e + p.cost; break; }
+      popped[npop] = p;
+      int me = npop++;
+      /* children: one more deviation on the arrival-tree chain from p.u */
+      int v = p.u;
+      while (c.role[v] == ROLE_COUT) {
+        int cell = pin_cell[v];
+        int b = cell_in_ptr[cell];
+        for (int j = 0; b + j < cell_in_ptr[cell + 1]; ++j) {
+          if (j == crit[cell]) continue;
+          int i = cell_in_pins[b + j];
+          if (at[i] == -INFINITY) continue;
+          double delta = at[v] - (at[i] + darc[i]);
+          ocand ch = {p.cost + delta, seq++, me, i, c.driver[i]};
+          heap_push(&h, ch);
+        }
+        v = c.driver[cell_in_pins[b + crit[cell]]];
+      }
+    }
+    /* materialise each popped path */
+    for (int r = 0; r < npop; ++r) {
+      int devs[4096];
+      int nd = 0;
+      for (int a = r; a >= 0 && popped[a].dev >= 0; a = popped[a].parent) devs[nd++] = popped[a].dev;
+      /* devs[nd-1] is the deviation nearest the endpoint */
+      int len = 0, di = nd - 1;
+      chain_pins[len++] = e;
+      int v = c.driver[e];
+      for (;;) {
+        chain_pins[len++] = v;
+        if (c.role[v] != ROLE_COUT) break;
+        int cell = pin_cell[v];
+        int in;
+        if (di >= 0 && pin_cell[devs[di]] == cell) in = devs[di--];
+        else in = cell_in_pins[cell_in_ptr[cell] + crit[cell]];
+        chain_pins[len++] = in;
+        v = c.driver[in];
+      }
+      /* reverse into start -> end order and recompute the path slack */
+      if (pool_n + len > pool_cap) {
+        pool_cap = (pool_n + len) * 2 + 1024;
+        pool = (int32_t *)realloc(pool, sizeof(int32_t) * pool_cap);
+      }
+      int start = chain_pins[len - 1];
+      double arr = at[start];
+      for (int a = 0; a < len; ++a) {
+        int pin = chain_pins[len - 1 - a];
+        pool[pool_n + a] = pin;
+        if (a == 0) continue;
+        int role = c.role[pin];
+        if (role == ROLE_CIN || role == ROLE_FFD) arr += dnet[pin];
+        else if (role == ROLE_COUT) arr += darc[chain_pins[len - a]];
+      }
+      if (npaths == pcap) { pcap = pcap ? 2 * pcap : 1024; paths = (opath *)realloc(paths, sizeof(opath) * pcap); }
+      paths[npaths].slack = rat[e] - arr;
+      paths[npaths].ep = e;
+      paths[npaths].rank = r;
+      paths[npaths].start = (int)pool_n;
+      paths[npaths].len = len;
+      npaths++;
+      pool_n += len;
+    }
+    free(popped);
+    free(h.a);
+  }
+  qsort(paths, npaths, sizeof(opath), opath_cmp);
+  int nout = npaths < K ? npaths : K;
+  long total = 0;
+  for (int a = 0; a < nout; ++a) total += paths[a].len;
+  int rc = nout;
+  if (total > pins_capacity) {
+    rc = -2;
+  } else {
+    path_ptr[0] = 0;
+    for (int a = 0; a < nout; ++a) {
+      memcpy(path_pins + path_ptr[a], pool + paths[a].start, sizeof(int32_t) * paths[a].len);
+      path_ptr[a + 1] = path_ptr[a] + paths[a].len;
+      path_ep[a] = paths[a].ep;
+      path_rank[a] = paths[a].rank;
+      path_slack[a] = paths[a].slack;
+    }
+  }
+  free(paths); free(pool); free(chain_pins); free(eps);
+  conn_free(&c);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* pin-pair set and weights (Eq. 9)                                          */
+/* ------------------------------------------------------------------------ */
+/* The pairs of a path are its net arcs (driver pin, sink pin); a sink pin has
+ * exactly one driver, so the sink pin id names the pair.  Paths are taken in
+ * the order given (ascending path slack).
+ * rule 0 (Eq. 9, stateful): skipped when wns == 0; only paths with negative
+ *   slack count; a pair not yet in P enters with w0, a pair already in P gains
+ *   w1 * slack / WNS.  in_p[] and w[] carry P across calls.
+ * rule 1 (exponential, stateless): w = sum over the paths through the pair of
+ *   exp(-slack / max(|WNS|, 1 ps)); P is this call's pairs.
+ * in_p[P] (uint8) and w[P] (double) are indexed by sink pin id. */
+int ora_pairs(int num_pins, int num_paths, const int32_t *path_ptr, const int32_t *path_pins,
+              const double *path_slack, double wns, int rule, double w0, double w1,
+              uint8_t *in_p, double *w) {
+  if (rule == 1) {
+    for (int p = 0; p < num_pins; ++p) { in_p[p] = 0; w[p] = 0.0; }
+    double scale = fabs(wns) > 1.0 ? fabs(wns) : 1.0;
+    for (int a = 0; a < num_paths; ++a) {
+      double contrib = exp(-path_slack[a] / scale);
+      for (int q = path_ptr[a] + 1; q < path_ptr[a + 1]; q += 2) {
+        int t = path_pins[q];
+        in_p[t] = 1;
+        w[t] += contrib;
+      }
+    }
+    return 0;
+  }
+  if (wns == 0.0) return 0;
+  for (int a = 0; a < num_paths; ++a) {
+    double s = path_slack[a];
+    if (!(s < 0)) continue;
+    for (int q = path_ptr[a] + 1; q < path_ptr[a + 1]; q += 2) {
+      int t = path_pins[q];
+      if (!in_p[t]) { in_p[t] = 1; w[t] = w0; }
+      else w[t] += w1 * (s / wns);
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PP loss (Eqs. 8, 10) and its gradient                                     */
+/* ------------------------------------------------------------------------ */
+/* pairs: sink pin ids pair_sink[Q] with weights pair_w[Q]; the driver is the
+ * sink's net driver.  grad_x/grad_y [N] are overwritten; fixed cells and
+ * ports get no gradient.  Returns PP via *loss. */
+int ora_p2p(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float *y, int num_pairs,
+            const int32_t *pair_sink, const double *pair_w, double *loss, double *grad_x,
+            double *grad_y) {
+  FILL_NETLIST(n);
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  for (int cell = 0; cell < num_cells; ++cell) { grad_x[cell] = 0; grad_y[cell] = 0; }
+  double pp = 0.0;
+  for (int a = 0; a < num_pairs; ++a) {
+    int t = pair_sink[a], s = c.driver[t];
+    double xs, ys, xt, yt;
+    pin_xy(&n, x, y, s, &xs, &ys);
+    pin_xy(&n, x, y, t, &xt, &yt);
+    double w = pair_w[a];
+    pp += w * ((xs - xt) * (xs - xt) + (ys - yt) * (ys - yt));
+    int cs = pin_cell[s], ct = pin_cell[t];
+    if (cs >= 0 && !cell_fixed[cs]) { grad_x[cs] += 2 * w * (xs - xt); grad_y[cs] += 2 * w * (ys - yt); }
+    if (ct >= 0 && !cell_fixed[ct]) { grad_x[ct] += 2 * w * (xt - xs); grad_y[ct] += 2 * w * (yt - ys); }
+  }
+  *loss = pp;
+  conn_free(&c);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* smoothed TNS and its adjoint                                              */
+/* ------------------------------------------------------------------------ */
+/* Not in the paper; this is the definition.  Cell-arc delays (darc) and
+ * start-point arrivals (at0 at ports and Q pins) are frozen from a hard
+ * timing run; net delays follow the positions.
+ *   sink t:         A(t) = A(drv) + dnet(t)
+ *   comb output o:  A(o) = m + g*ln sum_j exp((a_j - m)/g), a_j = A(i_j) + darc(i_j)
+ *   endpoint e:     s(e) = (T - setup) - A(e)
+ *   value:          -g * sum_e softplus(-s(e)/g)
+ * The gradient on cell positions goes through dnet = kappa * L^2,
+ * L = |dx| + |dy| (sign(0) = 0).  grad_x/grad_y [N] are overwritten. */
+int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, const float *y,
+             const double *at0, const double *darc, double clock_period, double setup,
+             double gamma, double *value, double *grad_x, double *grad_y) {
+  FILL_NETLIST(n);
+  FILL_LIB(L);
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  int P = num_pins;
+  const double kappa = L.scale * L.r * L.c;
+  double *A = (double *)malloc(sizeof(double) * P);
+  double *Ab = (double *)calloc(P, sizeof(double));
+  double *dn = (double *)calloc(P, sizeof(double));
+  for (int p = 0; p < P; ++p) A[p] = -INFINITY;
+  for (int net = 0; net < num_nets; ++net) {
+    int s = net_pins[net_ptr[net]];
+    double xs, ys;
+    pin_xy(&n, x, y, s, &xs, &ys);
+    for (int k2 = net_ptr[net] + 1; k2 < net_ptr[net + 1]; ++k2) {
+      int t = net_pins[k2];
+      double xt, yt;
+      pin_xy(&n, x, y, t, &xt, &yt);
+      double len = fabs(xs - xt) + fabs(ys - yt);
+      dn[t] = kappa * len * len;
+    }
+  }
+  for (int q = 0; q < P; ++q) {
+    int p = c.topo[q];
+    int r = c.role[p];
+    if (r == ROLE_PORT || r == ROLE_FFQ) A[p] = at0[p];
+    else if (r == ROLE_CIN || r == ROLE_FFD) { if (c.driver[p] >= 0) A[p] = A[c.driver[p]] + dn[p]; }
+    else {
+      int cell = pin_cell[p];
+      double m = -INFINITY;
+      for (int k2 = cell_in_ptr[cell]; k2 < cell_in_ptr[cell + 1]; ++k2) {
+        int i = cell_in_pins[k2];
+        double a = A[i] + darc[i];
+        if (a > m) m = a;
+      }
+      double sum = 0.0;
+      for (int k2 = cell_in_ptr[cell]; k2 < cell_in_ptr[cell + 1]; ++k2) {
+        int i = cell_in_pins[k2];
+        sum += exp((A[i] + darc[i] - m) / gamma);
+      }
+      A[p] = m + gamma * log(sum);
+    }
+  }
+  double val = 0.0;
+  for (int p = 0; p < P; ++p)
+    if (c.role[p] == ROLE_FFD && A[p] != -INFINITY) {
+      double s = (clock_period - setup) - A[p];
+      double z = -s / gamma;
+      double sp = (z > 0 ? z : 0.0) + log1p(exp(-fabs(z)));
+      val += -gamma * sp;
+      Ab[p] = -1.0 / (1.0 + exp(-z));   /* d value / d A(e) = -sigmoid(z) */
+    }
+  *value = val;
+  for (int q = P - 1; q >= 0; --q) {
+    int p = c.topo[q];
+    int r = c.role[p];
+    if (r == ROLE_COUT) {
+      int cell = pin_cell[p];
+      for (int k2 = cell_in_ptr[cell]; k2 < cell_in_ptr[cell + 1]; ++k2) {
+        int i = cell_in_pins[k2];
+        Ab[i] += Ab[p] * exp((A[i] + darc[i] - A[p]) / gamma);
+      }
+    } else if (r == ROLE_CIN || r == ROLE_FFD) {
+      if (c.driver[p] >= 0) Ab[c.driver[p]] += Ab[p];
+    }
+  }
+  for (int cell = 0; cell < num_cells; ++cell) { grad_x[cell] = 0; grad_y[cell] = 0; }
+  for (int net = 0; net < num_nets; ++net) {
+    int s = net_pins[net_ptr[net]];
+    double xs, ys;
+    pin_xy(&n, x, y, s, &xs, &ys);
+    int cs = pin_cell[s];
+    for (int k2 = net_ptr[net] + 1; k2 < net_ptr[net + 1]; ++k2) {
+      int t = net_pins[k2];
+      double xt, yt;
+      pin_xy(&n, x, y, t, &xt, &yt);
+      double len = fabs(xs - xt) + fabs(ys - yt);
+      double dx = xs - xt, dy = ys - yt;
+      double sx = (dx > 0) - (dx < 0), sy = (dy > 0) - (dy < 0);
+      double gx = Ab[t] * 2.0 * kappa * len * sx;   /* d value / d X_s */
+      double gy = Ab[t] * 2.0 * kappa * len * sy;
+      int ct = pin_cell[t];
+      if (cs >= 0 && !cell_fixed[cs]) { grad_x[cs] += gx; grad_y[cs] += gy; }
+      if (ct >= 0 && !cell_fixed[ct]) { grad_x[ct] -= gx; grad_y[ct] -= gy; }
+    }
+  }
+  free(A); free(Ab); free(dn);
+  conn_free(&c);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* weighted-average wirelength                                               */
+/* ------------------------------------------------------------------------ */
+/* Per net and axis, over all pins of the net (driver and sinks, ports too):
+ *   WA = sum x e^{x/g} / sum e^{x/g} - sum x e^{-x/g} / sum e^{-x/g},
+ * evaluated with the exponents shifted by the net's max (resp. min).  The
+ * value is summed over nets and both axes; grad_x/grad_y [N] are overwritten
+ * with d value / d cell position (fixed cells and ports get none). */
+static double wa_axis(int cnt, const double *v, double g, double *dv) {
+  double mx = v[0], mn = v[0];
+  for (int i = 1; i < cnt; ++i) { if (v[i] > mx) mx = v[i]; if (v[i] < mn) mn = v[i]; }
+  double sa = 0, sxa = 0, sb = 0, sxb = 0;
+  for (int i = 0; i < cnt; ++i) {
+    double a = exp((v[i] - mx) / g), b = exp(-(v[i] - mn) / g);
+    sa += a; sxa += v[i] * a; sb += b; sxb += v[i] * b;
+  }
+  double fp = sxa / sa, fm = sxb / sb;
+  for (int i = 0; i < cnt; ++i) {
+    double a = exp((v[i] - mx) / g), b = exp(-(v[i] - mn) / g);
+    dv[i] = a / sa * (1.0 + (v[i] - fp) / g) - b / sb * (1.0 - (v[i] - fm) / g);
+  }
+  return fp - fm;
+}
+
+int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float *y, double gamma,
+           double *value, double *grad_x, double *grad_y) {
+  FILL_NETLIST(n);
+  (void)cell_type; (void)cell_in_ptr; (void)cell_in_pins; (void)cell_out_pin; (void)cell_is_ff;
+  int maxdeg = 1;
+  for (int net = 0; net < num_nets; ++net) {
+    int d = net_ptr[net + 1] - net_ptr[net];
+    if (d > maxdeg) maxdeg = d;
+  }
+  double *vx = (double *)malloc(sizeof(double) * maxdeg), *vy = (double *)malloc(sizeof(double) * maxdeg);
+  double *gx = (double *)malloc(sizeof(double) * maxdeg), *gy = (double *)malloc(sizeof(double) * maxdeg);
+  for (int cell = 0; cell < num_cells; ++cell) { grad_x[cell] = 0; grad_y[cell] = 0; }
+  double total = 0.0;
+  for (int net = 0; net < num_nets; ++net) {
+    int b = net_ptr[net], cnt = net_ptr[net + 1] - b;
+    for (int i = 0; i < cnt; ++i) pin_xy(&n, x, y, net_pins[b + i], &vx[i], &vy[i]);
+    total += wa_axis(cnt, vx, gamma, gx) + wa_axis(cnt, vy, gamma, gy);
+    for (int i = 0; i < cnt; ++i) {
+      int cell = pin_cell[net_pins[b + i]];
+      if (cell >= 0 && !cell_fixed[cell]) { grad_x[cell] += gx[i]; grad_y[cell] += gy[i]; }
+    }
+  }
+  *value = total;
+  free(vx); free(vy); free(gx); free(gy);
+  return 0;
+}
