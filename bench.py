@@ -1,0 +1,218 @@
+"""Throughput of the timing-driven placement hot path on one MI355X.
+
+One step = static timing analysis (net delays, forward arrivals, endpoint
+WNS/TNS, backward required times and slack), report_timing_endpoint(n_fail, k)
+with k = K // n_fail, the Eq. 9 pin-pair update, weighted-average wirelength
+forward+backward and the pin-to-pin loss forward+backward, on the 2M-cell
+synthetic workload (clustered placement, depth 100, 12 % flip-flops, K = 100k
+paths).  Cell positions are fixed across steps, so every step does the same
+work.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload C5|C3|C2|C1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+BETA = 2.5e-5          # weight of the pin-to-pin term in the objective (Sec. IV)
+WA_GAMMA = 5.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C5")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
+    return ap.parse_args()
+
+
+def stage_bytes(info, counts, side_k):
+    """Algorithmic bytes per stage of one step (float32 values, int32 ids; an
+    array element counts once per pass, a gather counts its element size)."""
+    N, P, M, D, E, n_start, n_comb, S = info
+    A = S - E
+    km = side_k if side_k > 1 else 0
+    b = {}
+    b["netpass"] = 28 * M + 28 * S + 12 * n_start
+    b["forward"] = n_comb * (37 + 16 * km) + 24 * A
+    b["endpoint"] = 32 * E
+    b["backward"] = 20 * M + 12 * S + 16 * A
+    nsel, nslots, npaths, npins = counts["nsel"], counts["nslots"], counts["paths"], counts["path_pins"]
+    b["select"] = 16 * E
+    b["search"] = nsel * (16 + counts["k"] * (8 * km + 40))
+    b["order"] = 4 * (24 * nslots) + 28 * nslots + 16 * npaths
+    b["walk"] = 20 * npins + 24 * npaths
+    occ = npins // 2
+    b["pairs"] = 2 * (12 * occ + 8 * npaths) + 9 * S + 36 * counts["pairs"] + 40 * counts["pairs"]
+    b["p2p_fwd"] = 36 * counts["pairs"]
+    b["p2p_bwd"] = 2 * 24 * counts["pairs"] + 36 * counts["touched"]
+    b["wa"] = 36 * P + 8 * M + 28 * N
+    return b
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU layout is described in "
+              f"DESIGN.md but not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2503_11674_amd import netgen
+    from paper_2503_11674_amd.tdp import TimingGraph, STAGES
+
+    cfg = netgen.CONFIGS[a.workload]
+    t0 = time.time()
+    nl = netgen.make_netlist(cfg)
+    lib = netgen.make_library()
+    print(f"[bench] generated {a.workload}: {nl['num_cells']} cells {nl['num_pins']} pins "
+          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(nl["x"], device=dev)
+    y = torch.tensor(nl["y"], device=dev)
+    K = cfg.top_k_paths
+    E = int(np.count_nonzero(nl["cell_is_ff"]))
+    n_fail_target = E // 20
+    k = max(1, K // max(1, n_fail_target))
+    g = TimingGraph(nl, lib, max_paths=K, max_k=k)
+    # clock period: floor(5 %) of the endpoints fail at the initial placement
+    # (arrival times do not depend on the period)
+    g.sta_update(x, y)
+    at = g.export()["at"].cpu().numpy()
+    ep = nl["cell_in_pins"][nl["cell_in_ptr"][np.nonzero(nl["cell_is_ff"])[0]]]
+    T = netgen.clock_period_for_fail_fraction(at[ep], 0.05)
+    g.set_clock(T)
+    nl["clock_period"] = np.float32(T)
+    info = (g.num_cells, g.num_pins, g.num_nets, g.depth, g.num_endpoints, g.num_startpoints, g.num_comb,
+            g.num_sinks)
+
+    gx = torch.zeros_like(x)
+    gy = torch.zeros_like(y)
+    wl = torch.zeros((), device=dev)
+    pp = torch.zeros((), device=dev)
+    beta = torch.full((), BETA, device=dev)
+
+    def step():
+        # every call launches on the stream that is current at call time (the
+        # capture stream while a HIP graph is recorded)
+        g.sta_update(x, y)
+        g.extract_paths(n=-1, k=k, K=K)
+        g.pairs_update(rule=0, w0=10.0, w1=0.2)
+        gx.zero_()
+        gy.zero_()
+        g.wa_fwd_bwd(x, y, WA_GAMMA, gx, gy, out=wl)
+        g.p2p_loss_fwd(x, y, out=pp)
+        g.p2p_loss_bwd(x, y, beta, gx, gy)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    g.pairs_reset()
+    wns, tns, nfail = g.summary()
+    graph = None
+    if a.graph:
+        step()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+    print(f"[bench] T={T:.1f} ps wns={wns:.1f} tns={tns:.1f} n_fail={nfail} k={k}; timing {a.steps} steps",
+          file=sys.stderr, flush=True)
+    # timed region; stage events ride on the same stream (eager mode)
+    g.profile(graph is None)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(a.steps):
+        if graph is not None:
+            graph.replay()
+        else:
+            step()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    prof = g.profile_read() if graph is None else {}
+    g.profile(False)
+    ms_step = 1000.0 * t_total / a.steps
+
+    npaths, npins = g.paths_count()
+    counts = {"paths": npaths, "path_pins": npins, "pairs": g.pairs_count(), "k": k,
+              "nsel": nfail, "nslots": nfail * k, "touched": 0}
+    counts["touched"] = 2 * counts["pairs"]
+    sb = stage_bytes(info, counts, g.max_k if g.max_k == 1 else 1 << (g.max_k - 1).bit_length())
+    stages = {}
+    for s in STAGES:
+        ms, calls = prof.get(s, (0.0, 0))
+        if calls:
+            per = ms / calls
+            stages[s] = {"ms": round(per, 4), "GBps": round(sb.get(s, 0) / (per * 1e-3) / 1e9, 1)}
+    sta_ms = sum(stages[s]["ms"] for s in ("netpass", "forward", "endpoint", "backward") if s in stages)
+    ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
+    loss_ms = sum(stages[s]["ms"] for s in ("p2p_fwd", "p2p_bwd") if s in stages)
+    pins = g.num_pins
+    dom = max(stages, key=lambda s: stages[s]["ms"]) if stages else None
+    roof = None
+    if dom:
+        ach = sb[dom] / (stages[dom]["ms"] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+                "bytes_per_step": int(sb[dom])}
+    out = {
+        "metric": "timing-graph pins/s for STA+top-K extraction; p2p loss fwd+bwd GB/s",
+        "value": round(pins / (ms_step * 1e-3), 1),
+        "unit": "pins/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {nl['num_cells']} cells, {pins} pins, depth {g.depth}, "
+                               f"{E} endpoints, (n_fail, k, K) = ({nfail}, {k}, {K}), clustered placement "
+                               f"in {cfg.die:.0f} um die; step = STA + extraction + Eq. 9 pairs + WA + p2p "
+                               f"fwd/bwd", "parallelism": "none"},
+        "sta_extract_pins_per_s": round(pins / ((sta_ms + ext_ms) * 1e-3), 1) if sta_ms else None,
+        "p2p_fwd_bwd_GBps": round((sb["p2p_fwd"] + sb["p2p_bwd"]) / (loss_ms * 1e-3) / 1e9, 2) if loss_ms else None,
+        "stages": stages,
+        "roofline": roof,
+        "graph_replay": bool(graph is not None),
+        "timing": {"wns": wns, "tns": tns, "n_fail": nfail, "paths": npaths, "path_pins": npins,
+                   "pairs": counts["pairs"]},
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(nl, lib, k, K, pins)
+    print(json.dumps(out))
+
+
+def cpu_baseline(nl, lib, k, K, pins):
+    """The FP64 CPU oracle, single threaded, on the same workload: one step
+    (STA, extraction, pairs, WA and p2p forward+backward)."""
+    from oracle import ref
+
+    t0 = time.perf_counter()
+    st = ref.sta(nl, lib)
+    pa = ref.extract(nl, lib, st, n=-1, k=k, K=K)
+    t1 = time.perf_counter()
+    ps = ref.PairState(nl["num_pins"])
+    ref.pairs_update(ps, pa, st["wns"])
+    s, w = ps.pairs()
+    ref.wa(nl, WA_GAMMA)
+    ref.p2p(nl, s, w)
+    t2 = time.perf_counter()
+    return {"value": round(pins / (t2 - t0), 1), "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": "one full step of the same workload (STA + extraction + pairs + WA + p2p fwd/bwd), FP64",
+            "seconds": round(t2 - t0, 3), "sta_extract_pins_per_s": round(pins / (t1 - t0), 1)}
+
+
+if __name__ == "__main__":
+    main()

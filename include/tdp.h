@@ -1,0 +1,256 @@
+/*
+ * tdp.h - C ABI of the MI355X timing-driven-placement hot path.
+ *
+ * Shi et al., "Timing-Driven Global Placement by Efficient Critical Path
+ * Extraction" (arXiv 2503.11674).  The library runs, on one GPU:
+ *   1. static timing analysis on the timing DAG (Sec. II-B, Eq. 2-4): RC net
+ *      delays from pin positions (Sec. III-C, Eq. 7), slew x load table cell
+ *      arcs, arrival times forward, required times backward, slack per pin,
+ *      WNS / TNS over the violated endpoints;
+ *   2. report_timing_endpoint(n, k) (Sec. III-B, Table I): the n most
+ *      critical endpoints and the k worst paths at each;
+ *   3. the maintained pin-pair set P with the weight update of Eq. 9
+ *      (Sec. III-D), and the pin-to-pin loss PP = sum w * Q (Eqs. 8, 10) with
+ *      its gradient on cell positions;
+ * plus a log-sum-exp smoothed TNS with its adjoint, weighted-average
+ * wirelength (the WL term of Eq. 1) and a batched form over many designs.
+ *
+ * Conventions (every entry point):
+ *  - Return a tdp_status; nothing throws across the ABI.  A failed call leaves
+ *    the graph as it was; tdp_last_error() gives a message.
+ *  - "host" pointers are read during the call only; the caller keeps them.
+ *    "device" pointers are HIP device memory on the graph's device; the
+ *    caller owns them.  Device outputs are written asynchronously on the
+ *    given stream (NULL = the default stream); calls that return values to
+ *    the host synchronise that stream and say so.
+ *  - Units: positions um, times ps, capacitances fF.
+ *  - Pins and cells are numbered by the caller ("external" numbering).  Cell
+ *    positions x[], y[] are float arrays indexed by external cell id.
+ *  - After the first call of each kind (which may allocate), the update,
+ *    extraction, pair and loss calls neither allocate nor synchronise, so a
+ *    caller can capture them in a hipGraph.
+ */
+#ifndef TDP_H_
+#define TDP_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tdp_graph_s *tdp_graph;
+
+typedef enum {
+  TDP_OK = 0,
+  TDP_E_INVALID = 1,     /* malformed netlist / library / argument */
+  TDP_E_CYCLE = 2,       /* the timing graph is not acyclic */
+  TDP_E_NOMEM = 3,       /* device or host allocation failed */
+  TDP_E_DEVICE = 4,      /* a HIP call failed */
+  TDP_E_CAPACITY = 5,    /* request exceeds a capacity fixed at build */
+  TDP_E_STATE = 6,       /* call out of order (e.g. extract before update) */
+  TDP_E_UNSUPPORTED = 7
+} tdp_status;
+
+typedef enum { TDP_F32 = 0, TDP_F64 = 1 } tdp_precision;
+
+/* Timing graph (host arrays, read during build only).
+ *  pin_cell[num_pins]      owning cell, or -1 for a primary-input port
+ *  pin_off_x/y[num_pins]   pin offset from its cell's position; for a port,
+ *                          its absolute position
+ *  net_ptr[num_nets+1], net_pins[...]   CSR; each net lists its driver first,
+ *                          then its sinks.  Every port and every cell output
+ *                          drives exactly one net (which may have no sink);
+ *                          every input pin is a sink of exactly one net.
+ *  cell_type[num_cells]    index into the library
+ *  cell_in_ptr/cell_in_pins  CSR of each cell's input pins, in arc order;
+ *                          a flip-flop has exactly one (its D pin)
+ *  cell_out_pin[num_cells] output pin (Q for a flip-flop)
+ *  cell_is_ff[num_cells]   1: D is a timing endpoint, Q a timing startpoint
+ *  cell_fixed[num_cells]   1: no gradient is written for the cell (may be NULL)
+ *  clock_period_ps, setup_ps  required time at a D pin = period - setup
+ *  input_slew_ps           transition at the primary inputs
+ *  clock_slew_ps           clock transition used for clock-to-Q arcs (ideal
+ *                          clock: every D/Q pin sees the edge at time 0) */
+typedef struct {
+  int32_t num_cells, num_pins, num_nets;
+  const int32_t *pin_cell;
+  const float *pin_off_x, *pin_off_y;
+  const int32_t *net_ptr, *net_pins;
+  const int32_t *cell_type;
+  const int32_t *cell_in_ptr, *cell_in_pins;
+  const int32_t *cell_out_pin;
+  const uint8_t *cell_is_ff, *cell_fixed;
+  float clock_period_ps, setup_ps, input_slew_ps, clock_slew_ps;
+} tdp_netlist;
+
+/* Cell library (host arrays, copied at build).
+ *  slew_axis[num_types][n_slew], load_axis[num_types][n_load]: strictly
+ *    increasing breakpoints; lookups clamp to the axis range and interpolate
+ *    bilinearly between breakpoints.
+ *  delay_lut, slew_lut [num_types][n_slew][n_load]: arc delay and output
+ *    transition (slew_lut may equal delay_lut).
+ *  pin_cap[num_types]: input-pin capacitance.
+ *  Net delay into a sink = delay_scale * r_per_um * c_per_um * L^2, with L the
+ *  Manhattan driver-to-sink distance (Eq. 7: R and C both linear in length);
+ *  a driver's load = sum over its sinks of (pin_cap + c_per_um * L). */
+typedef struct {
+  int32_t num_types, n_slew, n_load;
+  const float *slew_axis, *load_axis;
+  const float *delay_lut, *slew_lut;
+  const float *pin_cap;
+  float r_per_um, c_per_um, delay_scale;
+} tdp_library;
+
+/* Extracted paths (device views owned by the graph; valid until the next
+ * tdp_extract_paths on the same graph).  Path i has pins
+ * path_pins[path_ptr[i] .. path_ptr[i+1]) in start -> endpoint order, as
+ * external pin ids: the start pin (port or Q), then for each combinational
+ * cell on the path its input pin and output pin, then the D pin.
+ * path_slack is float (TDP_F32) or double (TDP_F64).  *d_num_paths is a
+ * device int32 (tdp_paths_count() reads it to the host). */
+typedef struct {
+  int32_t max_paths;
+  const int32_t *d_num_paths;
+  const int32_t *path_ptr;       /* [max_paths + 1] */
+  const int32_t *path_pins;      /* [max_paths * (2 * depth + 2)] */
+  const int32_t *path_ep;        /* [max_paths] endpoint (D) pin */
+  const int32_t *path_rank;      /* [max_paths] 0 = worst path at its endpoint */
+  const void *path_slack;        /* [max_paths] */
+} tdp_paths;
+
+/* ---------------------------------------------------------------- build */
+/* Validate and levelise the timing graph, renumber it for the device and
+ * upload it.  max_paths bounds n*k of any later extraction, max_k bounds k
+ * (1..32; max_k > 1 makes every update also keep, per cell, the max_k
+ * cheapest deviations along its critical fan-in chain).  Errors:
+ * TDP_E_INVALID (index out of range, a pin in zero or two nets, a port that
+ * is not a driver, a combinational cell without inputs, a flip-flop without
+ * exactly one input, bad axes), TDP_E_CYCLE (combinational loop). */
+tdp_status tdp_sta_build(const tdp_netlist *netlist, const tdp_library *lib, tdp_precision prec,
+                         int32_t max_paths, int32_t max_k, int device, tdp_graph *out);
+
+/* Batched form: the graphs of `count` netlists become one disjoint union
+ * (instance-major numbering, external ids offset by the preceding instances'
+ * pin and cell counts); every later call runs all instances in the same
+ * launches.  Per-instance quantities (WNS/TNS, endpoint selection, K) are
+ * kept per instance.  max_paths_each bounds n*k per instance. */
+tdp_status tdp_batch_build(const tdp_netlist *const *netlists, int32_t count, const tdp_library *lib,
+                           tdp_precision prec, int32_t max_paths_each, int32_t max_k, int device,
+                           tdp_graph *out);
+/* Host copies of the union's offsets: pin_base[count+1], cell_base[count+1]. */
+tdp_status tdp_batch_offsets(tdp_graph, int32_t *pin_base, int32_t *cell_base);
+
+void tdp_destroy(tdp_graph);
+
+/* Change the required time at every D pin (period - setup). */
+tdp_status tdp_sta_set_clock(tdp_graph, float clock_period_ps, float setup_ps);
+
+/* ------------------------------------------------------------------ STA */
+/* Full timing update from cell positions (device float [num_cells] each):
+ * net delays and loads, arrival times and transitions forward by level,
+ * endpoint slacks and WNS / TNS / violated-endpoint count, required times and
+ * slack backward.  Asynchronous. */
+tdp_status tdp_sta_update(tdp_graph, const float *d_x, const float *d_y, hipStream_t);
+
+/* WNS and TNS (Eqs. 3-4; both 0 without violations) and the number of
+ * violated endpoints of the last update.  Synchronises the stream.  For a
+ * batched graph this is the union's; see tdp_batch_summary. */
+tdp_status tdp_sta_summary(tdp_graph, double *wns, double *tns, int32_t *n_fail, hipStream_t);
+tdp_status tdp_batch_summary(tdp_graph, double *wns, double *tns, int32_t *n_fail, hipStream_t);
+
+/* Per-pin results of the last update in external pin order, as double device
+ * arrays [num_pins] (any pointer may be NULL):
+ *   at, rat, slack, slew; dnet (net delay into a sink pin, 0 elsewhere),
+ *   load (at a driver pin, 0 elsewhere), darc (cell-arc delay from a
+ *   combinational input pin to its output, 0 elsewhere).
+ * Unconstrained pins (no endpoint downstream) have rat = slack = +inf. */
+tdp_status tdp_sta_export(tdp_graph, double *d_at, double *d_rat, double *d_slack, double *d_slew,
+                          double *d_dnet, double *d_load, double *d_darc, hipStream_t);
+/* Arc index of the input that sets each combinational cell's arrival
+ * (lowest index on ties), -1 for flip-flops; int32 device [num_cells]. */
+tdp_status tdp_sta_export_crit(tdp_graph, int32_t *d_crit, hipStream_t);
+
+/* ------------------------------------------------------------- paths */
+/* report_timing_endpoint(n, k): endpoints ordered by (slack, pin id); n >= 0
+ * takes the first n, n < 0 the violated ones (device-side count, no host
+ * round trip).  At each selected endpoint the k paths of smallest slack are
+ * found by slack-ordered deviation expansion from the arrival-time tree;
+ * paths whose slack is >= slack_limit are dropped.  All paths are ordered by
+ * (slack, endpoint pin id, rank) and cut to K.  Errors: TDP_E_CAPACITY if
+ * n*k > max_paths (n < 0: number of endpoints * k) or k > max_k, TDP_E_STATE
+ * before the first update. */
+tdp_status tdp_extract_paths(tdp_graph, int32_t n, int32_t k, int32_t K, float slack_limit,
+                             hipStream_t, tdp_paths *out);
+/* Number of paths and of path pins of the last extraction (synchronises). */
+tdp_status tdp_paths_count(tdp_graph, int32_t *num_paths, int32_t *num_pins, hipStream_t);
+
+/* --------------------------------------------------------------- pairs */
+/* Update the maintained pin-pair set P from the last extraction (Eq. 9).
+ * A pair is a net arc (driver pin, sink pin) on an extracted path, named by
+ * its sink pin.  rule 0 (Eq. 9): skipped when WNS = 0; paths with negative
+ * slack are taken in extraction order; a pair not in P enters with w0, a pair
+ * already in P (this round or earlier) gains w1 * slack / WNS.  rule 1:
+ * stateless, w = sum over this extraction's paths through the pair of
+ * exp(-slack / max(|WNS|, 1 ps)).  P persists across calls under rule 0. */
+tdp_status tdp_pairs_update(tdp_graph, int32_t rule, float w0, float w1, hipStream_t);
+tdp_status tdp_pairs_reset(tdp_graph, hipStream_t);
+/* Checkpoint / resume of P: dense per external pin (weight, membership), host
+ * arrays [num_pins].  Export synchronises; import rebuilds the pair list. */
+tdp_status tdp_pairs_export(tdp_graph, float *h_w, uint8_t *h_in_p, hipStream_t);
+tdp_status tdp_pairs_import(tdp_graph, const float *h_w, const uint8_t *h_in_p, hipStream_t);
+tdp_status tdp_pairs_count(tdp_graph, int32_t *num_pairs, hipStream_t);
+
+/* ---------------------------------------------------------------- loss */
+/* PP = sum over P of w * ((X_s - X_t)^2 + (Y_s - Y_t)^2), X = cell position +
+ * pin offset (Eqs. 8, 10).  *d_loss (device float) is overwritten. */
+tdp_status tdp_p2p_loss_fwd(tdp_graph, const float *d_x, const float *d_y, float *d_loss, hipStream_t);
+/* d_gx/d_gy [num_cells] += (*d_gout) * dPP/dx, dPP/dy; fixed cells and
+ * ports get nothing.  Deterministic (fixed summation order per cell). */
+tdp_status tdp_p2p_loss_bwd(tdp_graph, const float *d_x, const float *d_y, const float *d_gout,
+                            float *d_gx, float *d_gy, hipStream_t);
+
+/* Smoothed TNS: cell-arc delays and start arrivals frozen from the last
+ * update, net delays from d_x/d_y; log-sum-exp over fan-in with temperature
+ * gamma_ps, value = -gamma * sum over endpoints of softplus(-slack/gamma).
+ * fwd overwrites *d_val; bwd (same positions as the last fwd) adds
+ * (*d_gout) * gradient into d_gx/d_gy. */
+tdp_status tdp_stns_fwd(tdp_graph, const float *d_x, const float *d_y, float gamma_ps, float *d_val,
+                        hipStream_t);
+tdp_status tdp_stns_bwd(tdp_graph, const float *d_gout, float *d_gx, float *d_gy, hipStream_t);
+
+/* Weighted-average wirelength over every net (driver and sinks, ports too),
+ * both axes, temperature gamma_um.  *d_wl (device float) is overwritten;
+ * d_gx/d_gy [num_cells] += gradient (movable cells only). */
+tdp_status tdp_wa_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float gamma_um, float *d_wl,
+                          float *d_gx, float *d_gy, hipStream_t);
+
+/* ------------------------------------------------------------ tooling */
+/* Stage timing: when enabled, every call records HIP events around its
+ * stages on its stream.  tdp_profile_read synchronises and returns the
+ * accumulated milliseconds per stage (see TDP_STAGE_*) and the number of
+ * timed calls per stage, then clears them. */
+enum {
+  TDP_STAGE_NETPASS = 0, TDP_STAGE_FORWARD, TDP_STAGE_ENDPOINT, TDP_STAGE_BACKWARD,
+  TDP_STAGE_SELECT, TDP_STAGE_SEARCH, TDP_STAGE_ORDER, TDP_STAGE_WALK, TDP_STAGE_PAIRS,
+  TDP_STAGE_P2P_FWD, TDP_STAGE_P2P_BWD, TDP_STAGE_STNS, TDP_STAGE_WA, TDP_NUM_STAGES
+};
+tdp_status tdp_profile_enable(tdp_graph, int32_t on);
+tdp_status tdp_profile_read(tdp_graph, double *ms, int32_t *calls);
+
+/* Launch tuning for the sweeps (block size, cells per thread); 0 keeps the
+ * current value.  Used by the autotuner. */
+tdp_status tdp_set_tuning(tdp_graph, int32_t block, int32_t level_chunk, int32_t sweep_mode);
+
+/* Sizes of the graph: num_cells, num_pins, num_nets, depth, endpoints,
+ * startpoints, combinational cells, sink pins (8 int32, host). */
+tdp_status tdp_graph_info(tdp_graph, int32_t *info8);
+
+const char *tdp_status_str(tdp_status);
+const char *tdp_last_error(tdp_graph);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDP_H_ */

@@ -229,15 +229,19 @@ def stns(nl, lib, st, gamma: float = 10.0, x=None, y=None):
     return float(val[0]), gx, gy
 
 
-def wa(nl, gamma: float = 5.0, x=None, y=None):
-    """Weighted-average wirelength over all nets, both axes, and its gradient."""
+def wa(nl, gamma: float = 5.0, x=None, y=None, with_abs: bool = False):
+    """Weighted-average wirelength over all nets, both axes, and its gradient
+    (with_abs: also the per-cell sums of the pin terms' magnitudes)."""
     L = _load()
     x = _f32(nl["x"] if x is None else x)
     y = _f32(nl["y"] if y is None else y)
     N = int(nl["num_cells"])
     gx, gy = np.empty(N, np.float64), np.empty(N, np.float64)
+    ax, ay = np.empty(N, np.float64), np.empty(N, np.float64)
     val = np.zeros(1, np.float64)
     na, keep = _netlist_args(nl)
     fixed = np.ascontiguousarray(nl["cell_fixed"], dtype=np.uint8)
-    L.ora_wa(*na, _p(fixed), _p(x), _p(y), ctypes.c_double(gamma), _p(val), _p(gx), _p(gy))
+    L.ora_wa(*na, _p(fixed), _p(x), _p(y), ctypes.c_double(gamma), _p(val), _p(gx), _p(gy), _p(ax), _p(ay))
+    if with_abs:
+        return float(val[0]), gx, gy, ax, ay
     return float(val[0]), gx, gy

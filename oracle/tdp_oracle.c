@@ -724,8 +724,10 @@ static double wa_axis(int cnt, const double *v, double g, double *dv) {
   return fp - fm;
 }
 
+/* gabs_x/gabs_y (optional, [N]) receive, per cell, the sum of the magnitudes
+ * of its pins' terms: the scale of the rounding error of the gradient. */
 int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float *y, double gamma,
-           double *value, double *grad_x, double *grad_y) {
+           double *value, double *grad_x, double *grad_y, double *gabs_x, double *gabs_y) {
   FILL_NETLIST(n);
   (void)cell_type; (void)cell_in_ptr; (void)cell_in_pins; (void)cell_out_pin; (void)cell_is_ff;
   int maxdeg = 1;
@@ -735,7 +737,11 @@ int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float 
   }
   double *vx = (double *)malloc(sizeof(double) * maxdeg), *vy = (double *)malloc(sizeof(double) * maxdeg);
   double *gx = (double *)malloc(sizeof(double) * maxdeg), *gy = (double *)malloc(sizeof(double) * maxdeg);
-  for (int cell = 0; cell < num_cells; ++cell) { grad_x[cell] = 0; grad_y[cell] = 0; }
+  for (int cell = 0; cell < num_cells; ++cell) {
+    grad_x[cell] = 0; grad_y[cell] = 0;
+    if (gabs_x) gabs_x[cell] = 0;
+    if (gabs_y) gabs_y[cell] = 0;
+  }
   double total = 0.0;
   for (int net = 0; net < num_nets; ++net) {
     int b = net_ptr[net], cnt = net_ptr[net + 1] - b;
@@ -743,7 +749,11 @@ int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float 
     total += wa_axis(cnt, vx, gamma, gx) + wa_axis(cnt, vy, gamma, gy);
     for (int i = 0; i < cnt; ++i) {
       int cell = pin_cell[net_pins[b + i]];
-      if (cell >= 0 && !cell_fixed[cell]) { grad_x[cell] += gx[i]; grad_y[cell] += gy[i]; }
+      if (cell >= 0 && !cell_fixed[cell]) {
+        grad_x[cell] += gx[i]; grad_y[cell] += gy[i];
+        if (gabs_x) gabs_x[cell] += fabs(gx[i]);
+        if (gabs_y) gabs_y[cell] += fabs(gy[i]);
+      }
     }
   }
   *value = total;

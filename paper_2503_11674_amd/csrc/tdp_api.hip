@@ -1,0 +1,548 @@
+// C ABI entry points (include/tdp.h): argument checks, device allocation,
+// precision dispatch.  Every failure returns a status and leaves the graph
+// unchanged; nothing throws across the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "tdp_impl.h"
+#include "tdp_prims.h"
+
+using namespace tdp;
+
+namespace {
+
+thread_local std::string g_loose_error;  // errors before a graph exists
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+  }
+};
+
+tdp_status fail(tdp_graph g, tdp_status st, const std::string &msg) {
+  if (g) g->last_error = msg;
+  else g_loose_error = msg;
+  return st;
+}
+
+tdp_status check_launch(tdp_graph g, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(g, TDP_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return TDP_OK;
+}
+
+template <typename P>
+bool dalloc(tdp_graph g, P *&ptr, size_t count, size_t elem = sizeof(P), int fill = 0) {
+  void *p = nullptr;
+  size_t bytes = std::max<size_t>(count * elem, 16);
+  if (hipMalloc(&p, bytes) != hipSuccess) return false;
+  if (hipMemset(p, fill, bytes) != hipSuccess) {
+    hipFree(p);
+    return false;
+  }
+  g->allocs.push_back(p);
+  ptr = (P *)p;
+  return true;
+}
+
+template <typename P>
+bool upload(tdp_graph g, P *&ptr, const std::vector<P> &h) {
+  if (!dalloc(g, ptr, h.size())) return false;
+  if (h.empty()) return true;
+  return hipMemcpy(ptr, h.data(), sizeof(P) * h.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+void free_all(tdp_graph g) {
+  for (void *p : g->allocs) hipFree(p);
+  g->allocs.clear();
+  for (auto &m : g->prof.marks) {
+    hipEventDestroy(m.a);
+    hipEventDestroy(m.b);
+  }
+  g->prof.marks.clear();
+  for (auto &e : g->prof.open)
+    if (e) { hipEventDestroy(e); e = nullptr; }
+}
+
+// host-side copies kept for export / import
+struct HostSide {
+  std::vector<int32_t> snk_ext;
+};
+
+tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_library *lib, tdp_precision prec,
+                        int32_t max_paths, int32_t per_inst_paths, int32_t max_k, int device, tdp_graph *out) {
+  if (!out) return fail(nullptr, TDP_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (prec != TDP_F32 && prec != TDP_F64) return fail(nullptr, TDP_E_INVALID, "unknown precision");
+  if (max_k < 1 || max_k > TDP_MAX_K) return fail(nullptr, TDP_E_INVALID, "max_k must be in 1..32");
+  if (max_paths < 1) return fail(nullptr, TDP_E_INVALID, "max_paths must be >= 1");
+  if (prec == TDP_F64 && count > 1)
+    return fail(nullptr, TDP_E_UNSUPPORTED, "batched graphs are single precision only");
+  // host-side validation first: it needs no device
+  HostTopo H;
+  std::string err;
+  tdp_status st = build_host_topology(nls, count, lib, H, err);
+  if (st != TDP_OK) return fail(nullptr, st, err);
+  // the tables are staged in LDS by the forward sweep
+  if ((size_t)lib->num_types * (lib->n_slew + lib->n_load + 2 * lib->n_slew * lib->n_load) > 8192)
+    return fail(nullptr, TDP_E_UNSUPPORTED, "library tables exceed 32 KB");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, TDP_E_DEVICE, "no such HIP device");
+
+  tdp_graph g = new (std::nothrow) tdp_graph_s();
+  if (!g) return fail(nullptr, TDP_E_NOMEM, "host allocation failed");
+  DeviceGuard dg(device);
+  g->device = device;
+  g->prec = prec;
+  g->esz = prec == TDP_F64 ? 8 : 4;
+  g->lv = H.lv;
+  Topo &T = g->topo;
+  T = H.dims;
+  g->r = lib->r_per_um;
+  g->c = lib->c_per_um;
+  g->scale = lib->delay_scale;
+  g->clock_period = nls[0]->clock_period_ps;
+  g->setup = nls[0]->setup_ps;
+  g->input_slew = nls[0]->input_slew_ps;
+  g->clock_slew = nls[0]->clock_slew_ps;
+  g->max_paths = max_paths;
+  g->max_k = max_k;
+  g->side_k = 1;
+  while (g->side_k < max_k) g->side_k <<= 1;
+  if (max_k == 1) g->side_k = 1;
+  g->max_out = max_paths;
+  g->max_out_inst = per_inst_paths;
+  g->slot_cap = std::max(1, T.E * max_k);
+  g->pin_cap = max_paths * (2 * T.D + 2);
+  g->key_bits32 = T.num_inst <= 1 ? 32 : (T.num_inst <= 256 ? 40 : 48);
+  int max_inst_e = 1;
+  for (int i = 0; i < T.num_inst; ++i) max_inst_e = std::max(max_inst_e, H.lv.ep_base[i + 1] - H.lv.ep_base[i]);
+  g->ep_chunks = std::min(64, std::max(1, (max_inst_e + 4095) / 4096));
+
+  bool ok = true;
+  // library
+  const int nt = lib->num_types, ns = lib->n_slew, nl = lib->n_load;
+  float *sa = nullptr, *la = nullptr, *dl = nullptr, *sl = nullptr;
+  ok = ok && dalloc(g, sa, (size_t)nt * ns) && dalloc(g, la, (size_t)nt * nl) &&
+       dalloc(g, dl, (size_t)nt * ns * nl) && dalloc(g, sl, (size_t)nt * ns * nl);
+  if (ok) {
+    ok = hipMemcpy(sa, lib->slew_axis, sizeof(float) * nt * ns, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(la, lib->load_axis, sizeof(float) * nt * nl, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(dl, lib->delay_lut, sizeof(float) * nt * ns * nl, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(sl, lib->slew_lut, sizeof(float) * nt * ns * nl, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  g->lut = LutView{nt, ns, nl, sa, la, dl, sl};
+  // topology
+  ok = ok && upload(g, T.drv_cell, H.drv_cell) && upload(g, T.drv_ox, H.drv_ox) && upload(g, T.drv_oy, H.drv_oy) &&
+       upload(g, T.drv_ext, H.drv_ext) && upload(g, T.net_ptr, H.net_ptr) && upload(g, T.net_sink, H.net_sink) &&
+       upload(g, T.net_cpin, H.net_cpin) && upload(g, T.snk_cell, H.snk_cell) && upload(g, T.snk_ox, H.snk_ox) &&
+       upload(g, T.snk_oy, H.snk_oy) && upload(g, T.snk_drv, H.snk_drv) && upload(g, T.snk_ext, H.snk_ext) &&
+       upload(g, T.snk_comb, H.snk_comb) && upload(g, T.comb_type, H.comb_type) &&
+       upload(g, T.comb_inptr, H.comb_inptr) && upload(g, T.comb_ext, H.comb_ext) && upload(g, T.ff_ext, H.ff_ext) &&
+       upload(g, T.ff_type, H.ff_type) && upload(g, T.ff_inst, H.ff_inst) &&
+       upload(g, T.ext_pin_int, H.ext_pin_int) && upload(g, T.cell_int, H.cell_int) &&
+       upload(g, T.cell_fixed, H.cell_fixed) && upload(g, g->d_ep_base, H.lv.ep_base) &&
+       upload(g, T.fw_t, H.fw_t) && upload(g, T.fw_seg, H.fw_seg) && upload(g, T.nm_pin, H.nm_pin) &&
+       upload(g, T.nm_cell, H.nm_cell) && upload(g, T.nm_ox, H.nm_ox) && upload(g, T.nm_oy, H.nm_oy) &&
+       upload(g, T.nm_seg, H.nm_seg) && upload(g, T.big_net, H.big_net);
+  g->h_snk_ext = H.snk_ext;
+  // timing state
+  const size_t es = g->esz;
+  ok = ok && dalloc(g, g->load, T.M, es) && dalloc(g, g->dnet, T.S, es) && dalloc(g, g->at, T.P, es) &&
+       dalloc(g, g->slew, T.M, es) && dalloc(g, g->rat, T.P, es) && dalloc(g, g->slack, T.P, es) &&
+       dalloc(g, g->darc, T.A, es) && dalloc(g, g->crit, T.n_comb) && dalloc(g, g->hop, (size_t)T.n_comb * 4) &&
+       dalloc(g, g->cdep, T.M) && dalloc(g, g->ep_slack, T.E, es) &&
+       dalloc(g, g->red_ep, (size_t)3 * T.num_inst * g->ep_chunks) && dalloc(g, g->red_loss, 4096) &&
+       dalloc(g, g->red_wa, 4096) && dalloc(g, g->summary, (size_t)4 * T.num_inst) &&
+       dalloc(g, g->inst_nfail, T.num_inst) && dalloc(g, g->d_err, 4) && dalloc(g, g->consts, 4);
+  if (ok && g->side_k > 1)
+    ok = dalloc(g, g->side_cost, (size_t)T.n_comb * g->side_k, es) &&
+         dalloc(g, g->side_pin, (size_t)T.n_comb * g->side_k);
+  if (ok) {
+    const float one[4] = {1.f, 0.f, 0.f, 0.f};
+    ok = hipMemcpy(g->consts, one, sizeof one, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  // extraction
+  const int sc = g->slot_cap, mo = g->max_out, ni = T.num_inst;
+  const int scan_cap = std::max({T.S, T.N, T.E, mo, sc, sort_hist_size(sc)});
+  ok = ok && dalloc(g, g->sel_flag, T.E) && dalloc(g, g->sel_pos, T.E) && dalloc(g, g->sel_list, T.E) &&
+       dalloc(g, g->d_nsel, 1) && dalloc(g, g->inst_nsel, ni) && dalloc(g, g->inst_nvalid, ni) &&
+       dalloc(g, g->inst_seg, ni) && dalloc(g, g->inst_outb, ni) && dalloc(g, g->inst_kept, ni) &&
+       dalloc(g, g->inst_selb, ni) && dalloc(g, g->sel_npop, T.E) &&
+       dalloc(g, g->slot_key, sc, es) && dalloc(g, g->slot_dev, sc) && dalloc(g, g->slot_par, sc) &&
+       dalloc(g, g->slot_len, sc) && dalloc(g, g->slot_cells, sc) && dalloc(g, g->d_nslots, 1) &&
+       dalloc(g, g->sort_k0, sc) && dalloc(g, g->sort_k1, sc) && dalloc(g, g->sort_v0, sc) &&
+       dalloc(g, g->sort_v1, sc) && dalloc(g, g->sort_hist, sort_hist_size(sc)) &&
+       dalloc(g, g->scan_tmp, scan_tmp_size(scan_cap)) && dalloc(g, g->out_slot, mo) &&
+       dalloc(g, g->out_len, mo) && dalloc(g, g->path_ptr, (size_t)mo + 1) && dalloc(g, g->path_pins, g->pin_cap) &&
+       dalloc(g, g->path_int, g->pin_cap) && dalloc(g, g->path_ep, mo) && dalloc(g, g->path_epi, mo) &&
+       dalloc(g, g->path_rank, mo) && dalloc(g, g->d_num_paths, 1) && dalloc(g, g->path_slack, mo, es);
+  // pairs
+  ok = ok && dalloc(g, g->pw, T.S) && dalloc(g, g->pin_p, T.S) && dalloc(g, g->pacc, T.S) &&
+       dalloc(g, g->pfirst, T.S, sizeof(int32_t), 0x7F) && dalloc(g, g->pflag, T.S) && dalloc(g, g->d_npairs, 1) &&
+       dalloc(g, g->pair_sink, T.S) && dalloc(g, g->pair_cs, T.S) && dalloc(g, g->pair_ct, T.S) &&
+       dalloc(g, g->pair_dox, T.S) && dalloc(g, g->pair_doy, T.S) && dalloc(g, g->pair_w, T.S) &&
+       dalloc(g, g->cell_cnt, T.N) && dalloc(g, g->cell_ptr, (size_t)T.N + 1) && dalloc(g, g->cell_cur, T.N) &&
+       dalloc(g, g->cell_flag, T.N) && dalloc(g, g->touched, T.N) && dalloc(g, g->d_ntouched, 1) &&
+       dalloc(g, g->inc_other, (size_t)2 * T.S) && dalloc(g, g->inc_key, (size_t)2 * T.S) &&
+       dalloc(g, g->inc_dx, (size_t)2 * T.S) && dalloc(g, g->inc_dy, (size_t)2 * T.S) &&
+       dalloc(g, g->inc_w, (size_t)2 * T.S);
+  // smoothed TNS, WA
+  ok = ok && dalloc(g, g->st_at, T.P, es) && dalloc(g, g->st_adj, T.P, es) && dalloc(g, g->st_dnet, T.S, es) &&
+       dalloc(g, g->wa_gpin, (size_t)2 * T.P);
+  if (!ok || hipDeviceSynchronize() != hipSuccess) {
+    free_all(g);
+    delete g;
+    return fail(nullptr, TDP_E_NOMEM, "device allocation or upload failed");
+  }
+  *out = g;
+  return TDP_OK;
+}
+
+#define GUARD(g)                                                     \
+  if (!(g)) return fail(nullptr, TDP_E_INVALID, "graph is NULL"); \
+  DeviceGuard _dg((g)->device)
+
+template <typename F>
+tdp_status dispatch(tdp_graph g, F &&f) {
+  if (g->prec == TDP_F64) f((double)0);
+  else f((float)0);
+  return TDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdp_status tdp_sta_build(const tdp_netlist *netlist, const tdp_library *lib, tdp_precision prec, int32_t max_paths,
+                         int32_t max_k, int device, tdp_graph *out) {
+  const tdp_netlist *one[1] = {netlist};
+  return build_common(one, 1, lib, prec, max_paths, max_paths, max_k, device, out);
+}
+
+tdp_status tdp_batch_build(const tdp_netlist *const *netlists, int32_t count, const tdp_library *lib,
+                           tdp_precision prec, int32_t max_paths_each, int32_t max_k, int device, tdp_graph *out) {
+  if (!netlists || count < 1) return fail(nullptr, TDP_E_INVALID, "no netlists");
+  for (int i = 1; i < count; ++i)
+    if (!netlists[i] || !netlists[0] || netlists[i]->clock_period_ps != netlists[0]->clock_period_ps ||
+        netlists[i]->setup_ps != netlists[0]->setup_ps || netlists[i]->input_slew_ps != netlists[0]->input_slew_ps ||
+        netlists[i]->clock_slew_ps != netlists[0]->clock_slew_ps)
+      return fail(nullptr, TDP_E_INVALID, "batched netlists must share clock period, setup and slews");
+  int64_t cap = (int64_t)max_paths_each * count;
+  if (max_paths_each < 1 || cap > (1 << 30)) return fail(nullptr, TDP_E_INVALID, "bad max_paths_each");
+  return build_common(netlists, count, lib, prec, (int32_t)cap, max_paths_each, max_k, device, out);
+}
+
+tdp_status tdp_batch_offsets(tdp_graph g, int32_t *pin_base, int32_t *cell_base) {
+  if (!g) return fail(nullptr, TDP_E_INVALID, "graph is NULL");
+  for (int i = 0; i <= g->topo.num_inst; ++i) {
+    if (pin_base) pin_base[i] = g->lv.pin_base[i];
+    if (cell_base) cell_base[i] = g->lv.cell_base[i];
+  }
+  return TDP_OK;
+}
+
+void tdp_destroy(tdp_graph g) {
+  if (!g) return;
+  DeviceGuard dg(g->device);
+  hipDeviceSynchronize();
+  free_all(g);
+  delete g;
+}
+
+tdp_status tdp_sta_set_clock(tdp_graph g, float period, float setup) {
+  GUARD(g);
+  if (!std::isfinite(period) || !std::isfinite(setup)) return fail(g, TDP_E_INVALID, "clock not finite");
+  g->clock_period = period;
+  g->setup = setup;
+  return TDP_OK;
+}
+
+tdp_status tdp_sta_update(tdp_graph g, const float *x, const float *y, hipStream_t s) {
+  GUARD(g);
+  if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
+  dispatch(g, [&](auto z) { sta_update_impl<decltype(z)>(g, x, y, s); });
+  tdp_status st = check_launch(g, "sta_update");
+  if (st == TDP_OK) g->updated = true;
+  return st;
+}
+
+tdp_status tdp_sta_summary(tdp_graph g, double *wns, double *tns, int32_t *n_fail, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  const int ni = g->topo.num_inst;
+  std::vector<double> h(4 * ni);
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(h.data(), g->summary, sizeof(double) * 4 * ni, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "summary copy failed");
+  double w = 0, t = 0, n = 0;
+  for (int i = 0; i < ni; ++i) {
+    w = std::min(w, h[4 * i]);
+    t += h[4 * i + 1];
+    n += h[4 * i + 2];
+  }
+  if (wns) *wns = w;
+  if (tns) *tns = t;
+  if (n_fail) *n_fail = (int32_t)n;
+  return TDP_OK;
+}
+
+tdp_status tdp_batch_summary(tdp_graph g, double *wns, double *tns, int32_t *n_fail, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  const int ni = g->topo.num_inst;
+  std::vector<double> h(4 * ni);
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(h.data(), g->summary, sizeof(double) * 4 * ni, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "summary copy failed");
+  for (int i = 0; i < ni; ++i) {
+    if (wns) wns[i] = h[4 * i];
+    if (tns) tns[i] = h[4 * i + 1];
+    if (n_fail) n_fail[i] = (int32_t)h[4 * i + 2];
+  }
+  return TDP_OK;
+}
+
+tdp_status tdp_sta_export(tdp_graph g, double *at, double *rat, double *slack, double *slew, double *dnet,
+                          double *load, double *darc, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  dispatch(g, [&](auto z) { sta_export_impl<decltype(z)>(g, at, rat, slack, slew, dnet, load, darc, s); });
+  return check_launch(g, "sta_export");
+}
+
+tdp_status tdp_sta_export_crit(tdp_graph g, int32_t *crit, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (!crit) return fail(g, TDP_E_INVALID, "crit is NULL");
+  sta_export_crit(g, crit, s);
+  return check_launch(g, "sta_export_crit");
+}
+
+tdp_status tdp_extract_paths(tdp_graph g, int32_t n, int32_t k, int32_t K, float slack_limit, hipStream_t s,
+                             tdp_paths *out) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (k < 1 || k > g->max_k) return fail(g, TDP_E_CAPACITY, "k outside 1..max_k");
+  if (K < 0) return fail(g, TDP_E_INVALID, "K < 0");
+  if (std::isnan(slack_limit)) return fail(g, TDP_E_INVALID, "slack_limit is NaN");
+  const int Keff = std::min(K, g->max_out_inst);
+  dispatch(g, [&](auto z) { extract_impl<decltype(z)>(g, n, k, Keff, slack_limit, s); });
+  tdp_status st = check_launch(g, "extract_paths");
+  if (st != TDP_OK) return st;
+  g->extracted = true;
+  g->last_k = k;
+  if (out) {
+    out->max_paths = g->max_out;
+    out->d_num_paths = g->d_num_paths;
+    out->path_ptr = g->path_ptr;
+    out->path_pins = g->path_pins;
+    out->path_ep = g->path_ep;
+    out->path_rank = g->path_rank;
+    out->path_slack = g->path_slack;
+  }
+  return TDP_OK;
+}
+
+tdp_status tdp_paths_count(tdp_graph g, int32_t *num_paths, int32_t *num_pins, hipStream_t s) {
+  GUARD(g);
+  if (!g->extracted) return fail(g, TDP_E_STATE, "no extraction yet");
+  int32_t n = 0, pins = 0, err = 0;
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(&n, g->d_num_paths, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&pins, g->path_ptr + n, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "count copy failed");
+  if (err) return fail(g, TDP_E_DEVICE, "internal: a path walk did not match its length");
+  if (num_paths) *num_paths = n;
+  if (num_pins) *num_pins = pins;
+  return TDP_OK;
+}
+
+tdp_status tdp_pairs_update(tdp_graph g, int32_t rule, float w0, float w1, hipStream_t s) {
+  GUARD(g);
+  if (!g->extracted) return fail(g, TDP_E_STATE, "no extraction yet");
+  if (rule != 0 && rule != 1) return fail(g, TDP_E_INVALID, "rule must be 0 or 1");
+  if (!std::isfinite(w0) || !std::isfinite(w1)) return fail(g, TDP_E_INVALID, "weights not finite");
+  dispatch(g, [&](auto z) { pairs_update_impl<decltype(z)>(g, rule, w0, w1, s); });
+  return check_launch(g, "pairs_update");
+}
+
+static __global__ void k_zero_pairs(int S, float *w, uint8_t *in_p) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < S) {
+    w[t] = 0.f;
+    in_p[t] = 0;
+  }
+}
+
+tdp_status tdp_pairs_reset(tdp_graph g, hipStream_t s) {
+  GUARD(g);
+  const int S = g->topo.S;
+  hipLaunchKernelGGL(k_zero_pairs, dim3((S + 255) / 256), dim3(256), 0, s, S, g->pw, g->pin_p);
+  pairs_rebuild(g, s);
+  return check_launch(g, "pairs_reset");
+}
+
+tdp_status tdp_pairs_export(tdp_graph g, float *h_w, uint8_t *h_in_p, hipStream_t s) {
+  GUARD(g);
+  const int S = g->topo.S, P = g->topo.P;
+  std::vector<float> w(S);
+  std::vector<uint8_t> m(S);
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(w.data(), g->pw, sizeof(float) * S, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(m.data(), g->pin_p, S, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "pair copy failed");
+  if (h_w) std::fill(h_w, h_w + P, 0.f);
+  if (h_in_p) std::fill(h_in_p, h_in_p + P, (uint8_t)0);
+  for (int t = 0; t < S; ++t) {
+    const int p = g->h_snk_ext[t];
+    if (h_w) h_w[p] = w[t];
+    if (h_in_p) h_in_p[p] = m[t];
+  }
+  return TDP_OK;
+}
+
+tdp_status tdp_pairs_import(tdp_graph g, const float *h_w, const uint8_t *h_in_p, hipStream_t s) {
+  GUARD(g);
+  if (!h_w || !h_in_p) return fail(g, TDP_E_INVALID, "NULL arrays");
+  const int S = g->topo.S;
+  std::vector<float> w(S);
+  std::vector<uint8_t> m(S);
+  for (int t = 0; t < S; ++t) {
+    const int p = g->h_snk_ext[t];
+    if (!std::isfinite(h_w[p])) return fail(g, TDP_E_INVALID, "weight not finite");
+    w[t] = h_in_p[p] ? h_w[p] : 0.f;
+    m[t] = h_in_p[p] ? 1 : 0;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(g->pw, w.data(), sizeof(float) * S, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->pin_p, m.data(), S, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "pair upload failed");
+  pairs_rebuild(g, s);
+  return check_launch(g, "pairs_import");
+}
+
+tdp_status tdp_pairs_count(tdp_graph g, int32_t *num_pairs, hipStream_t s) {
+  GUARD(g);
+  int32_t n = 0;
+  if (hipStreamSynchronize(s) != hipSuccess || hipMemcpy(&n, g->d_npairs, 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "count copy failed");
+  if (num_pairs) *num_pairs = n;
+  return TDP_OK;
+}
+
+tdp_status tdp_p2p_loss_fwd(tdp_graph g, const float *x, const float *y, float *loss, hipStream_t s) {
+  GUARD(g);
+  if (!x || !y || !loss) return fail(g, TDP_E_INVALID, "NULL argument");
+  p2p_fwd_impl(g, x, y, loss, s);
+  return check_launch(g, "p2p_loss_fwd");
+}
+
+tdp_status tdp_p2p_loss_bwd(tdp_graph g, const float *x, const float *y, const float *gout, float *gx, float *gy,
+                            hipStream_t s) {
+  GUARD(g);
+  if (!x || !y || !gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
+  p2p_bwd_impl(g, x, y, gout ? gout : g->consts, gx, gy, s);
+  return check_launch(g, "p2p_loss_bwd");
+}
+
+tdp_status tdp_stns_fwd(tdp_graph g, const float *x, const float *y, float gamma, float *val, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (!x || !y || !val) return fail(g, TDP_E_INVALID, "NULL argument");
+  if (!(gamma > 0) || !std::isfinite(gamma)) return fail(g, TDP_E_INVALID, "gamma must be > 0");
+  dispatch(g, [&](auto z) { stns_fwd_impl<decltype(z)>(g, x, y, gamma, val, s); });
+  tdp_status st = check_launch(g, "stns_fwd");
+  if (st == TDP_OK) g->stns_ready = true;
+  return st;
+}
+
+tdp_status tdp_stns_bwd(tdp_graph g, const float *gout, float *gx, float *gy, hipStream_t s) {
+  GUARD(g);
+  if (!g->stns_ready) return fail(g, TDP_E_STATE, "no smoothed-TNS forward yet");
+  if (!gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
+  dispatch(g, [&](auto z) { stns_bwd_impl<decltype(z)>(g, gout ? gout : g->consts, gx, gy, s); });
+  return check_launch(g, "stns_bwd");
+}
+
+tdp_status tdp_wa_fwd_bwd(tdp_graph g, const float *x, const float *y, float gamma, float *wl, float *gx, float *gy,
+                          hipStream_t s) {
+  GUARD(g);
+  if (!x || !y || !wl || !gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
+  if (!(gamma > 0) || !std::isfinite(gamma)) return fail(g, TDP_E_INVALID, "gamma must be > 0");
+  wa_impl(g, x, y, gamma, wl, gx, gy, s);
+  return check_launch(g, "wa_fwd_bwd");
+}
+
+tdp_status tdp_profile_enable(tdp_graph g, int32_t on) {
+  GUARD(g);
+  g->prof.on = on != 0;
+  return TDP_OK;
+}
+
+tdp_status tdp_profile_read(tdp_graph g, double *ms, int32_t *calls) {
+  GUARD(g);
+  for (auto &m : g->prof.marks) {
+    float e = 0.f;
+    if (hipEventSynchronize(m.b) == hipSuccess && hipEventElapsedTime(&e, m.a, m.b) == hipSuccess) {
+      g->prof.ms[m.stage] += e;
+      g->prof.calls[m.stage] += 1;
+    }
+    hipEventDestroy(m.a);
+    hipEventDestroy(m.b);
+  }
+  g->prof.marks.clear();
+  for (int i = 0; i < TDP_NUM_STAGES; ++i) {
+    if (ms) ms[i] = g->prof.ms[i];
+    if (calls) calls[i] = g->prof.calls[i];
+    g->prof.ms[i] = 0;
+    g->prof.calls[i] = 0;
+  }
+  return TDP_OK;
+}
+
+tdp_status tdp_set_tuning(tdp_graph g, int32_t block, int32_t level_chunk, int32_t sweep_mode) {
+  GUARD(g);
+  if (block < 0 || level_chunk < 0 || sweep_mode < 0) return fail(g, TDP_E_INVALID, "negative tuning value");
+  if (block) g->tune_block = block;
+  if (level_chunk) g->tune_chunk = level_chunk;
+  g->sweep_mode = sweep_mode;
+  return TDP_OK;
+}
+
+tdp_status tdp_graph_info(tdp_graph g, int32_t *info8) {
+  GUARD(g);
+  if (!info8) return fail(g, TDP_E_INVALID, "NULL argument");
+  const Topo &T = g->topo;
+  const int32_t v[8] = {T.N, T.P, T.M, T.D, T.E, T.n_start, T.n_comb, T.S};
+  std::memcpy(info8, v, sizeof v);
+  return TDP_OK;
+}
+
+const char *tdp_status_str(tdp_status st) {
+  switch (st) {
+    case TDP_OK: return "ok";
+    case TDP_E_INVALID: return "invalid argument";
+    case TDP_E_CYCLE: return "combinational cycle";
+    case TDP_E_NOMEM: return "out of memory";
+    case TDP_E_DEVICE: return "device error";
+    case TDP_E_CAPACITY: return "capacity exceeded";
+    case TDP_E_STATE: return "call out of order";
+    case TDP_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char *tdp_last_error(tdp_graph g) { return g ? g->last_error.c_str() : g_loose_error.c_str(); }
+
+}  // extern "C"

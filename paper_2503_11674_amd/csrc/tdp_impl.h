@@ -1,0 +1,45 @@
+// Declarations shared by the kernel files and the entry points.
+#pragma once
+
+#include <algorithm>
+
+#include "tdp_internal.h"
+
+namespace tdp {
+
+// stage timing with HIP events on the caller's stream
+inline void prof_begin(tdp_graph g, int stage, hipStream_t s) {
+  if (!g->prof.on) return;
+  hipEvent_t a;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  hipEventRecord(a, s);
+  g->prof.open[stage] = a;
+}
+inline void prof_end(tdp_graph g, int stage, hipStream_t s) {
+  if (!g->prof.on || !g->prof.open[stage]) return;
+  hipEvent_t b;
+  if (hipEventCreate(&b) != hipSuccess) return;
+  hipEventRecord(b, s);
+  g->prof.marks.push_back({stage, g->prof.open[stage], b});
+  g->prof.open[stage] = nullptr;
+}
+
+template <typename T> void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
+template <typename T>
+void sta_export_impl(tdp_graph g, double *at, double *rat, double *slack, double *slew, double *dnet,
+                     double *load, double *darc, hipStream_t s);
+void sta_export_crit(tdp_graph g, int32_t *out, hipStream_t s);
+template <typename T> void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream_t s);
+template <typename T> void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s);
+void pairs_rebuild(tdp_graph g, hipStream_t s);
+void pairs_compact(tdp_graph g, hipStream_t s);
+void p2p_fwd_impl(tdp_graph g, const float *x, const float *y, float *loss, hipStream_t s);
+void p2p_bwd_impl(tdp_graph g, const float *x, const float *y, const float *gout, float *gx, float *gy,
+                  hipStream_t s);
+template <typename T>
+void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, float *val, hipStream_t s);
+template <typename T> void stns_bwd_impl(tdp_graph g, const float *gout, float *gx, float *gy, hipStream_t s);
+void wa_impl(tdp_graph g, const float *x, const float *y, float gamma, float *wl, float *gx, float *gy,
+             hipStream_t s);
+
+}  // namespace tdp

@@ -1,0 +1,218 @@
+// Internal definitions of the HIP timing library (not part of the ABI).
+//
+// Device numbering (chosen at build, see tdp_build.cpp):
+//   drivers  v in [0, M):  [primary-input ports][flip-flop Q pins][combinational
+//            outputs in (level, external cell id) order]; driver v drives net v.
+//            Combinational cell c (level-major index) owns driver n_start + c.
+//   sinks    t in [0, S):  [combinational input pins, cell-major, arc order]
+//            [flip-flop D pins in ascending external pin id];  A = number of
+//            combinational inputs, so the D pin of flip-flop f is sink A + f.
+//   pins     per-pin arrays use [drivers | sinks]: pin M + t is sink t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tdp.h"
+
+#define TDP_MAX_K 32
+
+namespace tdp {
+
+// ---------------------------------------------------------------- library
+struct LutView {
+  int nt, ns, nl;
+  const float *slew_axis;   // [nt][ns]
+  const float *load_axis;   // [nt][nl]
+  const float *delay;       // [nt][ns][nl]
+  const float *slew;        // [nt][ns][nl]
+};
+
+// Bilinear lookup with clamping: the breakpoint interval is the last one whose
+// left end is <= the value (the top interval for values at or past the end).
+template <typename T>
+__device__ __forceinline__ void lut_pair(const LutView &L, int type, T s, T l, T &d_out, T &s_out) {
+  const float *sa = L.slew_axis + type * L.ns;
+  const float *la = L.load_axis + type * L.nl;
+  T s0 = (T)sa[0], s1 = (T)sa[L.ns - 1];
+  T l0 = (T)la[0], l1 = (T)la[L.nl - 1];
+  s = s < s0 ? s0 : (s > s1 ? s1 : s);
+  l = l < l0 ? l0 : (l > l1 ? l1 : l);
+  int i = 0;
+  while (i + 1 < L.ns - 1 && (T)sa[i + 1] <= s) ++i;
+  int j = 0;
+  while (j + 1 < L.nl - 1 && (T)la[j + 1] <= l) ++j;
+  T tau = (s - (T)sa[i]) / ((T)sa[i + 1] - (T)sa[i]);
+  T ups = (l - (T)la[j]) / ((T)la[j + 1] - (T)la[j]);
+  int base = (type * L.ns + i) * L.nl + j;
+  T w00 = (1 - tau) * (1 - ups), w10 = tau * (1 - ups), w01 = (1 - tau) * ups, w11 = tau * ups;
+  d_out = w00 * (T)L.delay[base] + w10 * (T)L.delay[base + L.nl] + w01 * (T)L.delay[base + 1] +
+          w11 * (T)L.delay[base + L.nl + 1];
+  s_out = w00 * (T)L.slew[base] + w10 * (T)L.slew[base + L.nl] + w01 * (T)L.slew[base + 1] +
+          w11 * (T)L.slew[base + L.nl + 1];
+}
+
+// ---------------------------------------------------------------- topology
+// Device topology; plain data so kernels take it by value.
+struct Topo {
+  int32_t N = 0, P = 0, M = 0, S = 0, A = 0, E = 0;
+  int32_t n_pi = 0, n_ff = 0, n_start = 0, n_comb = 0, D = 0;
+  int32_t num_inst = 1;
+  // drivers [M]
+  int32_t *drv_cell = nullptr;  // external cell, -1 for a port
+  float *drv_ox = nullptr, *drv_oy = nullptr;
+  int32_t *drv_ext = nullptr;   // external pin id
+  int32_t *net_ptr = nullptr;   // [M+1] into net_sink
+  int32_t *net_sink = nullptr;  // [S] sinks of each net
+  double *net_cpin = nullptr;   // [M] sum of sink pin capacitances
+  // sinks [S]
+  int32_t *snk_cell = nullptr;
+  float *snk_ox = nullptr, *snk_oy = nullptr;
+  int32_t *snk_drv = nullptr;   // driver of the sink's net
+  int32_t *snk_ext = nullptr;
+  int32_t *snk_comb = nullptr;  // [A] combinational cell of an input pin
+  // combinational cells [n_comb]
+  uint8_t *comb_type = nullptr;
+  int32_t *comb_inptr = nullptr;  // [n_comb+1] into sinks [0, A)
+  int32_t *comb_ext = nullptr;
+  // flip-flops [n_ff]
+  int32_t *ff_ext = nullptr;
+  uint8_t *ff_type = nullptr;
+  int32_t *ff_inst = nullptr;    // instance of each flip-flop (batched graphs)
+  // maps
+  int32_t *ext_pin_int = nullptr;  // [P] external pin -> internal pin
+  int32_t *cell_int = nullptr;     // [N] external cell -> comb index, or -(ff index)-1
+  uint8_t *cell_fixed = nullptr;   // [N]
+  // 64-lane chunks of combinational inputs: a cell's inputs never straddle a
+  // chunk; chunks are level-pure.  fw_t = sink id (-1 = padding lane),
+  // fw_seg = head lane | tail lane << 8 of the lane's cell.
+  int32_t n_fw_chunks = 0;
+  int32_t *fw_t = nullptr;
+  int16_t *fw_seg = nullptr;
+  // 64-lane chunks of nets (driver lane first, then its sinks); a net never
+  // straddles a chunk; chunks are level-pure by driver level.  Nets with more
+  // than 63 sinks are "big" and handled one thread per net.
+  int32_t n_nm_chunks = 0, n_big = 0;
+  int32_t *nm_pin = nullptr;     // internal pin (driver v or M + t), -1 = padding
+  int32_t *nm_cell = nullptr;    // external cell, -1 for a port or padding
+  float *nm_ox = nullptr, *nm_oy = nullptr;
+  int16_t *nm_seg = nullptr;
+  int32_t *big_net = nullptr;    // [n_big] drivers of big nets, level-major
+};
+
+constexpr int CHUNK = 64;
+
+struct HostLevels {
+  std::vector<int32_t> fw_lvl;    // [D+1]: level l input chunks are [fw_lvl[l-1], fw_lvl[l])
+  std::vector<int32_t> nm_lvl;    // [D+2]: level l net chunks are [nm_lvl[l], nm_lvl[l+1]) (0 = start points)
+  std::vector<int32_t> big_lvl;   // [D+2]: level l big nets are [big_lvl[l], big_lvl[l+1])
+  std::vector<int32_t> lvl;       // [D+1]: level l cells are [lvl[l-1], lvl[l])
+  std::vector<int32_t> ep_base;   // [num_inst+1] endpoint range per instance
+  std::vector<int32_t> pin_base;  // [num_inst+1]
+  std::vector<int32_t> cell_base; // [num_inst+1]
+};
+
+// host-side image of the device topology, produced by the build
+struct HostTopo {
+  Topo dims;  // sizes only
+  HostLevels lv;
+  std::vector<int32_t> drv_cell, drv_ext, net_ptr, net_sink, snk_cell, snk_drv, snk_ext, snk_comb,
+      comb_inptr, comb_ext, ff_ext, ff_inst, ext_pin_int, cell_int;
+  std::vector<float> drv_ox, drv_oy, snk_ox, snk_oy;
+  std::vector<double> net_cpin;
+  std::vector<int32_t> fw_t, nm_pin, nm_cell, big_net;
+  std::vector<int16_t> fw_seg, nm_seg;
+  std::vector<float> nm_ox, nm_oy;
+  std::vector<uint8_t> comb_type, ff_type, cell_fixed;
+};
+
+tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, const tdp_library *lib,
+                               HostTopo &out, std::string &err);
+
+// ---------------------------------------------------------------- graph
+struct Profiler {
+  bool on = false;
+  hipEvent_t open[TDP_NUM_STAGES] = {};
+  struct Mark { int stage; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+  double ms[TDP_NUM_STAGES] = {0};
+  int calls[TDP_NUM_STAGES] = {0};
+};
+
+}  // namespace tdp
+
+struct tdp_graph_s {
+  int device = 0;
+  tdp_precision prec = TDP_F32;
+  int esz = 4;  // bytes per timing value
+  tdp::Topo topo;
+  tdp::HostLevels lv;
+  tdp::LutView lut{};
+  float r = 0, c = 0, scale = 0;
+  float clock_period = 0, setup = 0, input_slew = 0, clock_slew = 0;
+  int32_t max_paths = 0, max_k = 1, side_k = 1, max_out = 0, max_out_inst = 0, slot_cap = 0, pin_cap = 0;
+  int32_t key_bits32 = 40, ep_chunks = 1;
+  int32_t tune_block = 256, tune_chunk = 1, sweep_mode = 0;
+  std::string last_error;
+  bool updated = false, extracted = false, pairs_built = false, stns_ready = false;
+  std::vector<void *> allocs;  // every device allocation, freed at destroy
+  std::vector<int32_t> h_snk_ext;  // host copy: external pin of each sink
+  int32_t *d_err = nullptr;    // device flag for internal consistency errors
+  float *consts = nullptr;     // [4] device constants: {1, 0, 0, 0}
+
+  // timing state (element type per precision)
+  void *load = nullptr, *dnet = nullptr, *at = nullptr, *slew = nullptr, *rat = nullptr,
+       *slack = nullptr, *darc = nullptr;
+  int32_t *crit = nullptr;       // [n_comb] arc index of the critical input
+  int32_t *hop = nullptr;        // [n_comb][4] {critical sink, its driver, their external ids}
+  int32_t *cdep = nullptr;       // [M] combinational cells on the critical chain
+  void *side_cost = nullptr;     // [n_comb][side_k] cheapest deviations along the chain
+  int32_t *side_pin = nullptr;   // [n_comb][side_k]
+  void *ep_slack = nullptr;      // [E]
+  double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;
+  double *summary = nullptr;     // [4 * num_inst]: wns, tns, n_fail, 0
+  int32_t *inst_nfail = nullptr, *d_ep_base = nullptr;
+
+  // extraction
+  int32_t *sel_flag = nullptr, *sel_pos = nullptr, *sel_list = nullptr, *d_nsel = nullptr;
+  int32_t *inst_nsel = nullptr, *inst_nvalid = nullptr, *inst_seg = nullptr, *inst_outb = nullptr,
+          *inst_kept = nullptr, *inst_selb = nullptr, *sel_npop = nullptr;
+  void *slot_key = nullptr;      // path slack per slot
+  int32_t *slot_dev = nullptr, *slot_par = nullptr, *slot_len = nullptr, *slot_cells = nullptr,
+          *d_nslots = nullptr;
+  uint64_t *sort_k0 = nullptr, *sort_k1 = nullptr;
+  uint32_t *sort_v0 = nullptr, *sort_v1 = nullptr;
+  int32_t *sort_hist = nullptr, *scan_tmp = nullptr;
+  int32_t *out_slot = nullptr, *out_len = nullptr;
+  int32_t *path_ptr = nullptr, *path_pins = nullptr, *path_int = nullptr, *path_ep = nullptr,
+          *path_epi = nullptr, *path_rank = nullptr, *d_num_paths = nullptr;
+  void *path_slack = nullptr;
+  int32_t last_k = 1;
+
+  // pairs
+  float *pw = nullptr;                 // [S] weight per sink pin
+  uint8_t *pin_p = nullptr;            // [S] membership in P
+  unsigned long long *pacc = nullptr;  // [S] fixed-point accumulator
+  int32_t *pfirst = nullptr;           // [S] first occurrence (path index)
+  int32_t *pflag = nullptr;            // [S] compaction positions
+  int32_t *d_npairs = nullptr;
+  int32_t *pair_sink = nullptr, *pair_cs = nullptr, *pair_ct = nullptr;
+  float *pair_dox = nullptr, *pair_doy = nullptr, *pair_w = nullptr;
+  int32_t *cell_cnt = nullptr, *cell_ptr = nullptr, *cell_cur = nullptr, *cell_flag = nullptr,
+          *touched = nullptr, *d_ntouched = nullptr;
+  int32_t *inc_other = nullptr, *inc_key = nullptr;
+  float *inc_dx = nullptr, *inc_dy = nullptr, *inc_w = nullptr;
+
+  // smoothed TNS
+  void *st_at = nullptr, *st_adj = nullptr, *st_dnet = nullptr;
+  float st_gamma = 0;
+  const float *st_x = nullptr, *st_y = nullptr;
+
+  // weighted-average wirelength: per-pin gradient [2P]
+  float *wa_gpin = nullptr;
+
+  tdp::Profiler prof;
+};

@@ -1,0 +1,342 @@
+// Pin-pair set P, weights (Eq. 9) and the pin-to-pin loss (Eqs. 8, 10).
+//
+// Pairs are the net arcs (driver, sink) of the extracted paths; a sink pin has
+// one driver, so the sink names the pair and P is a dense per-sink array.
+//
+// Eq. 9 takes the paths in order: a pair not in P enters with w0, a pair in P
+// gains w1 * slack / WNS.  The sum over one round does not depend on the order
+// except for which occurrence inserts the pair, so the device form is
+//   new pair:      w = w0 + w1 * (sum of slack/WNS - first occurrence's)
+//   existing pair: w = w  + w1 * (sum of slack/WNS)
+// where "first" is the smallest output index.  The sums are accumulated as
+// 2^-32 fixed point in 64-bit integer atomics, so the result is independent of
+// thread timing; a second pass, run by the first occurrence, applies the
+// update and clears the accumulators.
+//
+// The loss uses a compact pair list (ascending sink id) and, for the gradient,
+// a per-cell incidence list in a fixed order so that every cell sums its terms
+// in the same order on every run (no floating-point atomics).
+#include "tdp_impl.h"
+#include "tdp_prims.h"
+
+namespace tdp {
+
+constexpr double FIX_ONE = 4294967296.0;  // 2^32
+
+template <typename T>
+__device__ __forceinline__ bool pair_contrib(int rule, T slack, double wns, unsigned long long &v) {
+  if (rule == 0) {
+    if (!(wns < 0.0) || !((double)slack < 0.0)) return false;
+    v = (unsigned long long)llrint((double)slack / wns * FIX_ONE);
+    return true;
+  }
+  const double sc = fabs(wns) > 1.0 ? fabs(wns) : 1.0;
+  v = (unsigned long long)llrint(exp(-(double)slack / sc) * FIX_ONE);
+  return true;
+}
+
+// one wavefront per path: its lanes take the path's sinks
+template <typename T>
+__global__ void __launch_bounds__(256) k_pairs_acc(Topo tp, int rule, const int32_t *__restrict__ d_num_paths,
+                                                    const int32_t *__restrict__ path_ptr,
+                                                    const int32_t *__restrict__ path_int,
+                                                    const int32_t *__restrict__ path_epi,
+                                                    const T *__restrict__ path_slack,
+                                                    const double *__restrict__ summary,
+                                                    unsigned long long *__restrict__ acc, int32_t *__restrict__ first) {
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * (blockDim.x >> 6);
+  const int n = *d_num_paths;
+  for (int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < n; q += nw) {
+    const double wns = summary[4 * tp.ff_inst[path_epi[q]]];
+    unsigned long long v;
+    if (!pair_contrib<T>(rule, path_slack[q], wns, v)) continue;
+    const int b = path_ptr[q], e = path_ptr[q + 1];
+    for (int i = b + 1 + 2 * lane; i < e; i += 128) {
+      const int t = path_int[i] - tp.M;
+      if (t < 0 || t >= tp.S) continue;
+      atomicAdd(&acc[t], v);
+      atomicMin(&first[t], q);
+    }
+  }
+}
+
+// every sink pin: apply this round's sum to the pairs it touched (the first
+// occurrence inserts under Eq. 9), clear the accumulators, flag P's members
+template <typename T>
+__global__ void k_pairs_apply(Topo tp, int rule, float w0, float w1, int max_out, const int32_t *__restrict__ path_epi,
+                              const T *__restrict__ path_slack, const double *__restrict__ summary,
+                              unsigned long long *__restrict__ acc, int32_t *__restrict__ first,
+                              float *__restrict__ w, uint8_t *__restrict__ in_p, int32_t *__restrict__ flag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tp.S) return;
+  const int q = first[t];
+  if (q >= 0 && q < max_out) {
+    const unsigned long long sum = acc[t];
+    const double wns = summary[4 * tp.ff_inst[path_epi[q]]];
+    unsigned long long v = 0;
+    pair_contrib<T>(rule, path_slack[q], wns, v);
+    if (rule == 0) {
+      if (in_p[t]) {
+        w[t] = (float)((double)w[t] + (double)w1 * ((double)sum / FIX_ONE));
+      } else {
+        w[t] = (float)((double)w0 + (double)w1 * ((double)(sum - v) / FIX_ONE));
+        in_p[t] = 1;
+      }
+    } else {
+      w[t] = (float)((double)sum / FIX_ONE);
+      in_p[t] = 1;
+    }
+    acc[t] = 0ull;
+    first[t] = 0x7fffffff;
+  }
+  flag[t] = in_p[t] ? 1 : 0;
+}
+
+// stateless rule: drop the previous round's pairs
+__global__ void k_pairs_clear_list(const int32_t *__restrict__ d_npairs, const int32_t *__restrict__ pair_sink,
+                                   float *__restrict__ w, uint8_t *__restrict__ in_p) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= *d_npairs) return;
+  const int t = pair_sink[q];
+  w[t] = 0.f;
+  in_p[t] = 0;
+}
+
+__global__ void k_pairs_flags(int S, const uint8_t *__restrict__ in_p, int32_t *__restrict__ flag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < S) flag[t] = in_p[t] ? 1 : 0;
+}
+
+// compact list + per-pair loss record + incidence counts per cell
+__global__ void k_pairs_records(Topo tp, const uint8_t *__restrict__ in_p, const int32_t *__restrict__ pos,
+                                const float *__restrict__ w, int32_t *__restrict__ pair_sink,
+                                int32_t *__restrict__ pair_cs, int32_t *__restrict__ pair_ct,
+                                float *__restrict__ pair_dox, float *__restrict__ pair_doy,
+                                float *__restrict__ pair_w, int32_t *__restrict__ cell_cnt) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tp.S || !in_p[t]) return;
+  const int q = pos[t];
+  const int s = tp.snk_drv[t];
+  const int cs = tp.drv_cell[s], ct = tp.snk_cell[t];
+  pair_sink[q] = t;
+  pair_cs[q] = cs;
+  pair_ct[q] = ct;
+  pair_dox[q] = tp.drv_ox[s] - tp.snk_ox[t];
+  pair_doy[q] = tp.drv_oy[s] - tp.snk_oy[t];
+  pair_w[q] = w[t];
+  if (!tp.cell_fixed[ct]) atomicAdd(&cell_cnt[ct], 1);
+  if (cs >= 0 && !tp.cell_fixed[cs]) atomicAdd(&cell_cnt[cs], 1);
+}
+
+__global__ void k_cell_flags(int N, const int32_t *__restrict__ cnt, int32_t *__restrict__ flag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < N) flag[c] = cnt[c] > 0 ? 1 : 0;
+}
+
+__global__ void k_cell_touched(int N, const int32_t *__restrict__ cnt, const int32_t *__restrict__ tpos,
+                               int32_t *__restrict__ touched) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < N && cnt[c] > 0) touched[tpos[c]] = c;
+}
+
+// incidence of pair q at a cell: the other cell (-1 for a port), this pin's
+// offset minus the other pin's, the weight; key orders the cell's list
+__global__ void k_inc_fill(Topo tp, const int32_t *__restrict__ d_npairs, const int32_t *__restrict__ pair_cs,
+                           const int32_t *__restrict__ pair_ct, const float *__restrict__ pair_dox,
+                           const float *__restrict__ pair_doy, const float *__restrict__ pair_w,
+                           const int32_t *__restrict__ cell_ptr, int32_t *__restrict__ cell_cur,
+                           int32_t *__restrict__ inc_other, float *__restrict__ inc_dx, float *__restrict__ inc_dy,
+                           float *__restrict__ inc_w, int32_t *__restrict__ inc_key) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= *d_npairs) return;
+  const int cs = pair_cs[q], ct = pair_ct[q];
+  if (!tp.cell_fixed[ct]) {
+    const int slot = cell_ptr[ct] + atomicAdd(&cell_cur[ct], 1);
+    inc_other[slot] = cs;
+    inc_dx[slot] = -pair_dox[q];
+    inc_dy[slot] = -pair_doy[q];
+    inc_w[slot] = pair_w[q];
+    inc_key[slot] = 2 * q;
+  }
+  if (cs >= 0 && !tp.cell_fixed[cs]) {
+    const int slot = cell_ptr[cs] + atomicAdd(&cell_cur[cs], 1);
+    inc_other[slot] = ct;
+    inc_dx[slot] = pair_dox[q];
+    inc_dy[slot] = pair_doy[q];
+    inc_w[slot] = pair_w[q];
+    inc_key[slot] = 2 * q + 1;
+  }
+}
+
+// order each touched cell's incidences by key (insertion sort; lists are
+// short) and reset the per-cell counters for the next build
+__global__ void k_inc_sort(const int32_t *__restrict__ d_ntouched, const int32_t *__restrict__ touched,
+                           const int32_t *__restrict__ cell_ptr, int32_t *__restrict__ cell_cnt,
+                           int32_t *__restrict__ cell_cur, int32_t *__restrict__ inc_other,
+                           float *__restrict__ inc_dx, float *__restrict__ inc_dy, float *__restrict__ inc_w,
+                           int32_t *__restrict__ inc_key) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *d_ntouched) return;
+  const int c = touched[i];
+  const int b = cell_ptr[c], e = cell_ptr[c + 1];
+  for (int a = b + 1; a < e; ++a) {
+    const int key = inc_key[a], o = inc_other[a];
+    const float dx = inc_dx[a], dy = inc_dy[a], w = inc_w[a];
+    int z = a - 1;
+    while (z >= b && inc_key[z] > key) {
+      inc_key[z + 1] = inc_key[z];
+      inc_other[z + 1] = inc_other[z];
+      inc_dx[z + 1] = inc_dx[z];
+      inc_dy[z + 1] = inc_dy[z];
+      inc_w[z + 1] = inc_w[z];
+      --z;
+    }
+    inc_key[z + 1] = key;
+    inc_other[z + 1] = o;
+    inc_dx[z + 1] = dx;
+    inc_dy[z + 1] = dy;
+    inc_w[z + 1] = w;
+  }
+  cell_cnt[c] = 0;
+  cell_cur[c] = 0;
+}
+
+// ------------------------------------------------------------------ loss
+constexpr int LOSS_BLOCKS = 512;
+
+__global__ void __launch_bounds__(256) k_p2p_fwd(const int32_t *__restrict__ d_npairs,
+                                                  const int32_t *__restrict__ pair_cs,
+                                                  const int32_t *__restrict__ pair_ct,
+                                                  const float *__restrict__ pair_dox,
+                                                  const float *__restrict__ pair_doy,
+                                                  const float *__restrict__ pair_w, const float *__restrict__ x,
+                                                  const float *__restrict__ y, double *__restrict__ part) {
+  __shared__ double sh[256];
+  const int n = *d_npairs;
+  double acc = 0.0;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const int cs = pair_cs[q], ct = pair_ct[q];
+    const float xs = cs >= 0 ? x[cs] : 0.f, ys = cs >= 0 ? y[cs] : 0.f;
+    const float dx = xs - x[ct] + pair_dox[q];
+    const float dy = ys - y[ct] + pair_doy[q];
+    acc += (double)(pair_w[q] * (dx * dx + dy * dy));
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_sum_parts(int n, const double *__restrict__ part, float *__restrict__ out,
+                                                    double *__restrict__ out64) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += part[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (out) *out = (float)sh[0];
+    if (out64) *out64 = sh[0];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_p2p_bwd(const int32_t *__restrict__ d_ntouched,
+                                                  const int32_t *__restrict__ touched,
+                                                  const int32_t *__restrict__ cell_ptr,
+                                                  const int32_t *__restrict__ inc_other,
+                                                  const float *__restrict__ inc_dx, const float *__restrict__ inc_dy,
+                                                  const float *__restrict__ inc_w, const float *__restrict__ x,
+                                                  const float *__restrict__ y, const float *__restrict__ gout,
+                                                  float *__restrict__ gx, float *__restrict__ gy) {
+  const int n = *d_ntouched;
+  const float g = *gout;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int c = touched[i];
+    const float xc = x[c], yc = y[c];
+    float ax = 0.f, ay = 0.f;
+    for (int a = cell_ptr[c]; a < cell_ptr[c + 1]; ++a) {
+      const int o = inc_other[a];
+      const float xo = o >= 0 ? x[o] : 0.f, yo = o >= 0 ? y[o] : 0.f;
+      const float w2 = 2.f * inc_w[a];
+      ax += w2 * (xc - xo + inc_dx[a]);
+      ay += w2 * (yc - yo + inc_dy[a]);
+    }
+    gx[c] += g * ax;
+    gy[c] += g * ay;
+  }
+}
+
+// ------------------------------------------------------------- launchers
+static inline int nb(long long n, int b) { return n > 0 ? (int)((n + b - 1) / b) : 1; }
+
+template <typename T>
+void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s) {
+  const Topo &tp = g->topo;
+  prof_begin(g, TDP_STAGE_PAIRS, s);
+  if (rule == 1 && g->pairs_built)
+    hipLaunchKernelGGL(k_pairs_clear_list, dim3(nb(tp.S, 256)), dim3(256), 0, s, g->d_npairs, g->pair_sink, g->pw,
+                       g->pin_p);
+  hipLaunchKernelGGL(k_pairs_acc<T>, dim3(std::min(2048, nb(g->max_out, 4))), dim3(256), 0, s, tp, rule,
+                     g->d_num_paths, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack, g->summary,
+                     g->pacc, g->pfirst);
+  hipLaunchKernelGGL(k_pairs_apply<T>, dim3(nb(tp.S, 256)), dim3(256), 0, s, tp, rule, w0, w1, g->max_out,
+                     g->path_epi, (const T *)g->path_slack, g->summary, g->pacc, g->pfirst, g->pw, g->pin_p,
+                     g->pflag);
+  pairs_compact(g, s);
+  prof_end(g, TDP_STAGE_PAIRS, s);
+}
+
+void pairs_rebuild(tdp_graph g, hipStream_t s) {
+  const Topo &tp = g->topo;
+  hipLaunchKernelGGL(k_pairs_flags, dim3(nb(tp.S, 256)), dim3(256), 0, s, tp.S, g->pin_p, g->pflag);
+  pairs_compact(g, s);
+}
+
+// pflag holds the membership flags; build the pair list and the per-cell lists
+void pairs_compact(tdp_graph g, hipStream_t s) {
+  const Topo &tp = g->topo;
+  scan_exclusive(g->pflag, g->pflag, tp.S, nullptr, g->d_npairs, g->scan_tmp, s);
+  hipLaunchKernelGGL(k_pairs_records, dim3(nb(tp.S, 256)), dim3(256), 0, s, tp, g->pin_p, g->pflag, g->pw,
+                     g->pair_sink, g->pair_cs, g->pair_ct, g->pair_dox, g->pair_doy, g->pair_w, g->cell_cnt);
+  // cell_ptr = exclusive scan of counts; touched list = compaction of cells with any
+  scan_exclusive(g->cell_cnt, g->cell_ptr, tp.N, nullptr, g->cell_ptr + tp.N, g->scan_tmp, s);
+  hipLaunchKernelGGL(k_cell_flags, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp.N, g->cell_cnt, g->cell_flag);
+  scan_exclusive(g->cell_flag, g->cell_flag, tp.N, nullptr, g->d_ntouched, g->scan_tmp, s);
+  hipLaunchKernelGGL(k_cell_touched, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp.N, g->cell_cnt, g->cell_flag,
+                     g->touched);
+  hipLaunchKernelGGL(k_inc_fill, dim3(nb(tp.S, 256)), dim3(256), 0, s, tp, g->d_npairs, g->pair_cs, g->pair_ct,
+                     g->pair_dox, g->pair_doy, g->pair_w, g->cell_ptr, g->cell_cur, g->inc_other, g->inc_dx,
+                     g->inc_dy, g->inc_w, g->inc_key);
+  hipLaunchKernelGGL(k_inc_sort, dim3(nb(tp.N, 256)), dim3(256), 0, s, g->d_ntouched, g->touched, g->cell_ptr,
+                     g->cell_cnt, g->cell_cur, g->inc_other, g->inc_dx, g->inc_dy, g->inc_w, g->inc_key);
+  g->pairs_built = true;
+}
+
+void p2p_fwd_impl(tdp_graph g, const float *x, const float *y, float *loss, hipStream_t s) {
+  prof_begin(g, TDP_STAGE_P2P_FWD, s);
+  hipLaunchKernelGGL(k_p2p_fwd, dim3(LOSS_BLOCKS), dim3(256), 0, s, g->d_npairs, g->pair_cs, g->pair_ct, g->pair_dox,
+                     g->pair_doy, g->pair_w, x, y, g->red_loss);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, LOSS_BLOCKS, g->red_loss, loss, (double *)nullptr);
+  prof_end(g, TDP_STAGE_P2P_FWD, s);
+}
+
+void p2p_bwd_impl(tdp_graph g, const float *x, const float *y, const float *gout, float *gx, float *gy,
+                  hipStream_t s) {
+  prof_begin(g, TDP_STAGE_P2P_BWD, s);
+  hipLaunchKernelGGL(k_p2p_bwd, dim3(LOSS_BLOCKS * 2), dim3(256), 0, s, g->d_ntouched, g->touched, g->cell_ptr,
+                     g->inc_other, g->inc_dx, g->inc_dy, g->inc_w, x, y, gout, gx, gy);
+  prof_end(g, TDP_STAGE_P2P_BWD, s);
+}
+
+template void pairs_update_impl<float>(tdp_graph, int, float, float, hipStream_t);
+template void pairs_update_impl<double>(tdp_graph, int, float, float, hipStream_t);
+
+}  // namespace tdp

@@ -1,0 +1,361 @@
+// Differentiable objectives: a log-sum-exp smoothed TNS with its adjoint, and
+// weighted-average wirelength.  Both give gradients on cell positions with a
+// fixed summation order per cell (gathers over the cell's own pins and nets;
+// no floating-point atomics).
+//
+// Smoothed TNS (not in the paper; this is its definition here): cell-arc
+// delays and start-point arrivals are frozen from the last timing update, net
+// delays follow the positions (kappa * L^2, L Manhattan).
+//   sink t:          A(t) = A(drv) + dnet(t)
+//   comb output o:   A(o) = m + g ln sum_j exp((a_j - m)/g), a_j = A(in_j) + d_arc(in_j)
+//   endpoint e:      s(e) = (period - setup) - A(e)
+//   value:           -g * sum_e softplus(-s(e)/g)
+// The adjoint runs the levels top-down: dv/dA(e) = -sigmoid(-s(e)/g); an
+// output passes its adjoint to input j in proportion to softmax_j(a/g); a
+// driver collects the adjoints of its sinks.  dv/d dnet(t) is the adjoint at
+// t, and d dnet/dX_s = 2 kappa L sign(X_s - X_t) = -d dnet/dX_t.
+//
+// Weighted-average wirelength (the smoothed WL of Eq. 1): per net and axis,
+// sum x e^{x/g} / sum e^{x/g} - sum x e^{-x/g} / sum e^{-x/g}, with the
+// exponents shifted by the net's max and min.
+#include "tdp_impl.h"
+#include "tdp_wave.h"
+
+namespace tdp {
+
+static inline int nb(long long n, int b) { return n > 0 ? (int)((n + b - 1) / b) : 1; }
+
+template <typename T>
+__device__ __forceinline__ T sgn(T v) {
+  return (T)((v > (T)0) - (v < (T)0));
+}
+
+template <typename T>
+__global__ void k_st_net(Topo tp, const float *__restrict__ x, const float *__restrict__ y, T kappa,
+                         T *__restrict__ dnl) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= tp.M) return;
+  const int dc = tp.drv_cell[v];
+  const T xs = (dc >= 0 ? (T)x[dc] : (T)0) + (T)tp.drv_ox[v];
+  const T ys = (dc >= 0 ? (T)y[dc] : (T)0) + (T)tp.drv_oy[v];
+  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
+    const int t = tp.net_sink[k];
+    const int sc = tp.snk_cell[t];
+    const T len = fabs(xs - ((T)x[sc] + (T)tp.snk_ox[t])) + fabs(ys - ((T)y[sc] + (T)tp.snk_oy[t]));
+    dnl[t] = kappa * len * len;
+  }
+}
+
+template <typename T>
+__global__ void k_st_start(Topo tp, const T *__restrict__ at, T *__restrict__ sa) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < tp.n_start) sa[v] = at[v];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_fwd(Topo tp, int c0, int c1, T gam, const T *__restrict__ dnl,
+                                                 const T *__restrict__ darc, T *__restrict__ sa) {
+  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  const int b = tp.comb_inptr[c], e = tp.comb_inptr[c + 1];
+  T m = -__builtin_huge_val();
+  for (int t = b; t < e; ++t) {
+    const T ai = sa[tp.snk_drv[t]] + dnl[t];
+    sa[tp.M + t] = ai;
+    const T a = ai + darc[t];
+    m = a > m ? a : m;
+  }
+  T sum = 0;
+  for (int t = b; t < e; ++t) sum += exp((sa[tp.M + t] + darc[t] - m) / gam);
+  sa[tp.n_start + c] = m + gam * log(sum);
+}
+
+// endpoint values and adjoint seeds; per-block partial sums of the value
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_end(Topo tp, T req, T gam, const T *__restrict__ dnl,
+                                                 T *__restrict__ sa, T *__restrict__ adj,
+                                                 double *__restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < tp.E; f += gridDim.x * blockDim.x) {
+    const int t = tp.A + f;
+    const T a = sa[tp.snk_drv[t]] + dnl[t];
+    sa[tp.M + t] = a;
+    const T z = (a - req) / gam;  // -slack / g
+    const T sp = (z > 0 ? z : (T)0) + log1p(exp(-fabs(z)));
+    acc += (double)(-gam * sp);
+    adj[tp.M + t] = -(T)1 / ((T)1 + exp(-z));
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_bwd(Topo tp, int c0, int c1, T gam, const T *__restrict__ darc,
+                                                 const T *__restrict__ sa, T *__restrict__ adj) {
+  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= c1) return;
+  const int v = tp.n_start + c;
+  T ab = 0;
+  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) ab += adj[tp.M + tp.net_sink[k]];
+  adj[v] = ab;
+  const T av = sa[v];
+  for (int t = tp.comb_inptr[c]; t < tp.comb_inptr[c + 1]; ++t)
+    adj[tp.M + t] = ab * exp((sa[tp.M + t] + darc[t] - av) / gam);
+}
+
+// gradient per cell: its output pin's net arcs and its input pins' net arcs
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
+                                                  T kappa, const T *__restrict__ adj, const float *__restrict__ gout,
+                                                  float *__restrict__ gx, float *__restrict__ gy) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= tp.N || tp.cell_fixed[cell]) return;
+  const int ci = tp.cell_int[cell];
+  int v, t0, t1;
+  if (ci >= 0) {
+    v = tp.n_start + ci;
+    t0 = tp.comb_inptr[ci];
+    t1 = tp.comb_inptr[ci + 1];
+  } else {
+    const int f = -ci - 1;
+    v = tp.n_pi + f;
+    t0 = tp.A + f;
+    t1 = t0 + 1;
+  }
+  T ax = 0, ay = 0;
+  {  // this cell drives the net of v
+    const T xs = (T)x[cell] + (T)tp.drv_ox[v], ys = (T)y[cell] + (T)tp.drv_oy[v];
+    for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
+      const int t = tp.net_sink[k];
+      const int sc = tp.snk_cell[t];
+      const T dx = xs - ((T)x[sc] + (T)tp.snk_ox[t]), dy = ys - ((T)y[sc] + (T)tp.snk_oy[t]);
+      const T g = adj[tp.M + t] * (T)2 * kappa * (fabs(dx) + fabs(dy));
+      ax += g * sgn(dx);
+      ay += g * sgn(dy);
+    }
+  }
+  for (int t = t0; t < t1; ++t) {  // this cell's input pins are sinks
+    const int s = tp.snk_drv[t];
+    const int dc = tp.drv_cell[s];
+    const T xs = (dc >= 0 ? (T)x[dc] : (T)0) + (T)tp.drv_ox[s], ys = (dc >= 0 ? (T)y[dc] : (T)0) + (T)tp.drv_oy[s];
+    const T dx = xs - ((T)x[cell] + (T)tp.snk_ox[t]), dy = ys - ((T)y[cell] + (T)tp.snk_oy[t]);
+    const T g = adj[tp.M + t] * (T)2 * kappa * (fabs(dx) + fabs(dy));
+    ax -= g * sgn(dx);
+    ay -= g * sgn(dy);
+  }
+  const float go = *gout;
+  gx[cell] += go * (float)ax;
+  gy[cell] += go * (float)ay;
+}
+
+__global__ void __launch_bounds__(256) k_sum_parts2(int n, const double *__restrict__ part, float *__restrict__ out) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += part[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (float)sh[0];
+}
+
+constexpr int RED_BLOCKS = 512;
+
+template <typename T>
+void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, float *val, hipStream_t s) {
+  const Topo &tp = g->topo;
+  prof_begin(g, TDP_STAGE_STNS, s);
+  const T kappa = (T)g->scale * (T)g->r * (T)g->c;
+  const T gam = (T)gamma;
+  hipLaunchKernelGGL(k_st_net<T>, dim3(nb(tp.M, 256)), dim3(256), 0, s, tp, x, y, kappa, (T *)g->st_dnet);
+  if (tp.n_start > 0)
+    hipLaunchKernelGGL(k_st_start<T>, dim3(nb(tp.n_start, 256)), dim3(256), 0, s, tp, (const T *)g->at,
+                       (T *)g->st_at);
+  for (int l = 1; l <= tp.D; ++l) {
+    const int c0 = g->lv.lvl[l - 1], c1 = g->lv.lvl[l];
+    if (c1 > c0)
+      hipLaunchKernelGGL(k_st_fwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
+                         (const T *)g->st_dnet, (const T *)g->darc, (T *)g->st_at);
+  }
+  const T req = (T)g->clock_period - (T)g->setup;
+  hipLaunchKernelGGL(k_st_end<T>, dim3(RED_BLOCKS), dim3(256), 0, s, tp, req, gam, (const T *)g->st_dnet,
+                     (T *)g->st_at, (T *)g->st_adj, g->red_loss);
+  hipLaunchKernelGGL(k_sum_parts2, dim3(1), dim3(256), 0, s, RED_BLOCKS, g->red_loss, val);
+  g->st_gamma = gamma;
+  g->st_x = x;
+  g->st_y = y;
+  g->stns_ready = true;
+  prof_end(g, TDP_STAGE_STNS, s);
+}
+
+template <typename T>
+void stns_bwd_impl(tdp_graph g, const float *gout, float *gx, float *gy, hipStream_t s) {
+  const Topo &tp = g->topo;
+  prof_begin(g, TDP_STAGE_STNS, s);
+  const T kappa = (T)g->scale * (T)g->r * (T)g->c;
+  const T gam = (T)g->st_gamma;
+  for (int l = tp.D; l >= 1; --l) {
+    const int c0 = g->lv.lvl[l - 1], c1 = g->lv.lvl[l];
+    if (c1 > c0)
+      hipLaunchKernelGGL(k_st_bwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
+                         (const T *)g->darc, (const T *)g->st_at, (T *)g->st_adj);
+  }
+  hipLaunchKernelGGL(k_st_grad<T>, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->st_x, g->st_y, kappa,
+                     (const T *)g->st_adj, gout, gx, gy);
+  prof_end(g, TDP_STAGE_STNS, s);
+}
+
+// ------------------------------------------------------------------- WA
+// Coordinates enter relative to the net's max (the e^{x/g} side) and min (the
+// e^{-x/g} side): d = x - max <= 0, e = x - min >= 0, so the weighted means
+// and the (x - mean) terms stay small numbers in single precision.
+//   WA = (max - min) + sum d a / sum a - sum e b / sum b,  a = e^{d/g}, b = e^{-e/g}
+//   dWA/dx = a/sum a (1 + (d - sum d a / sum a)/g) - b/sum b (1 - (e - sum e b / sum b)/g)
+
+// one axis for one lane of a chunked net; returns the net's WA on that axis
+__device__ __forceinline__ float wa_lane(float X, bool valid, int lane, int head, int tail, float ig, float &grad) {
+  const float mx = seg_max(valid ? X : -3.0e38f, lane, head, tail);
+  const float mn = seg_min(valid ? X : 3.0e38f, lane, head, tail);
+  const float d = valid ? X - mx : 0.f, e = valid ? X - mn : 0.f;
+  const float a = valid ? expf(d * ig) : 0.f, b = valid ? expf(-e * ig) : 0.f;
+  const float sa = seg_sum(a, lane, head, tail), sda = seg_sum(a * d, lane, head, tail);
+  const float sb = seg_sum(b, lane, head, tail), seb = seg_sum(b * e, lane, head, tail);
+  const float fp = valid ? sda / sa : 0.f, fm = valid ? seb / sb : 0.f;
+  grad = valid ? a / sa * (1.f + (d - fp) * ig) - b / sb * (1.f - (e - fm) * ig) : 0.f;
+  return valid ? (mx - mn) + fp - fm : 0.f;
+}
+
+// chunked nets: value partials and the gradient of each pin (internal pin order)
+__global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
+                                                 float gam, float *__restrict__ gpin, double *__restrict__ part) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  const float ig = 1.0f / gam;
+  const int lane = wave_lane();
+  for (int chunk = blockIdx.x * 4 + (threadIdx.x >> 6); chunk < tp.n_nm_chunks; chunk += gridDim.x * 4) {
+    const int k = chunk * CHUNK + lane;
+    const int p = tp.nm_pin[k];
+    const int sg = tp.nm_seg[k];
+    const int head = sg & 63, tail = (sg >> 8) & 63;
+    const int cell = tp.nm_cell[k];
+    const bool valid = p >= 0;
+    const float X = (cell >= 0 ? x[cell] : 0.f) + tp.nm_ox[k];
+    const float Y = (cell >= 0 ? y[cell] : 0.f) + tp.nm_oy[k];
+    float gxp, gyp;
+    const float wx = wa_lane(X, valid, lane, head, tail, ig, gxp);
+    const float wy = wa_lane(Y, valid, lane, head, tail, ig, gyp);
+    if (valid) {
+      gpin[2 * p] = gxp;
+      gpin[2 * p + 1] = gyp;
+      if (lane == head) acc += (double)wx + (double)wy;
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// nets wider than a chunk: one thread per net, same arithmetic
+__global__ void __launch_bounds__(64) k_wa_big(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
+                                                float gam, float *__restrict__ gpin, double *__restrict__ part) {
+  __shared__ double sh[64];
+  double acc = 0.0;
+  const float ig = 1.0f / gam;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < tp.n_big; i += gridDim.x * blockDim.x) {
+    const int v = tp.big_net[i];
+    const int b = tp.net_ptr[v], e = tp.net_ptr[v + 1];
+    const int dc = tp.drv_cell[v];
+    for (int axis = 0; axis < 2; ++axis) {
+      const float *pc = axis ? y : x;
+      const float *so = axis ? tp.snk_oy : tp.snk_ox;
+      const float pd = (dc >= 0 ? pc[dc] : 0.f) + (axis ? tp.drv_oy[v] : tp.drv_ox[v]);
+      float mx = pd, mn = pd;
+      for (int k = b; k < e; ++k) {
+        const int t = tp.net_sink[k];
+        const float q = pc[tp.snk_cell[t]] + so[t];
+        mx = fmaxf(mx, q);
+        mn = fminf(mn, q);
+      }
+      float sa = 0.f, sda = 0.f, sb = 0.f, seb = 0.f;
+      for (int k = b - 1; k < e; ++k) {
+        const float q = k < b ? pd : pc[tp.snk_cell[tp.net_sink[k]]] + so[tp.net_sink[k]];
+        const float d = q - mx, ee = q - mn;
+        const float a = expf(d * ig), bb = expf(-ee * ig);
+        sa += a; sda += a * d; sb += bb; seb += bb * ee;
+      }
+      const float fp = sda / sa, fm = seb / sb;
+      acc += (double)((mx - mn) + fp - fm);
+      for (int k = b - 1; k < e; ++k) {
+        const int t = k < b ? -1 : tp.net_sink[k];
+        const float q = k < b ? pd : pc[tp.snk_cell[t]] + so[t];
+        const float d = q - mx, ee = q - mn;
+        const float a = expf(d * ig), bb = expf(-ee * ig);
+        const float gr = a / sa * (1.f + (d - fp) * ig) - bb / sb * (1.f - (ee - fm) * ig);
+        gpin[2 * (k < b ? v : tp.M + t) + axis] = gr;
+      }
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_wa_cell(Topo tp, const float *__restrict__ gpin, float *__restrict__ gx,
+                                                  float *__restrict__ gy) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= tp.N || tp.cell_fixed[cell]) return;
+  const int ci = tp.cell_int[cell];
+  int v, t0, t1;
+  if (ci >= 0) {
+    v = tp.n_start + ci;
+    t0 = tp.comb_inptr[ci];
+    t1 = tp.comb_inptr[ci + 1];
+  } else {
+    const int f = -ci - 1;
+    v = tp.n_pi + f;
+    t0 = tp.A + f;
+    t1 = t0 + 1;
+  }
+  float ax = gpin[2 * v], ay = gpin[2 * v + 1];
+  for (int t = t0; t < t1; ++t) {
+    ax += gpin[2 * (tp.M + t)];
+    ay += gpin[2 * (tp.M + t) + 1];
+  }
+  gx[cell] += ax;
+  gy[cell] += ay;
+}
+
+void wa_impl(tdp_graph g, const float *x, const float *y, float gamma, float *wl, float *gx, float *gy,
+             hipStream_t s) {
+  const Topo &tp = g->topo;
+  prof_begin(g, TDP_STAGE_WA, s);
+  constexpr int WB = RED_BLOCKS * 4, BB = 64;  // partial slots: chunked nets, then big nets
+  hipLaunchKernelGGL(k_wa_net, dim3(WB), dim3(256), 0, s, tp, x, y, gamma, g->wa_gpin, g->red_wa);
+  hipLaunchKernelGGL(k_wa_big, dim3(BB), dim3(64), 0, s, tp, x, y, gamma, g->wa_gpin, g->red_wa + WB);
+  hipLaunchKernelGGL(k_sum_parts2, dim3(1), dim3(256), 0, s, WB + BB, g->red_wa, wl);
+  hipLaunchKernelGGL(k_wa_cell, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->wa_gpin, gx, gy);
+  prof_end(g, TDP_STAGE_WA, s);
+}
+
+template void stns_fwd_impl<float>(tdp_graph, const float *, const float *, float, float *, hipStream_t);
+template void stns_fwd_impl<double>(tdp_graph, const float *, const float *, float, float *, hipStream_t);
+template void stns_bwd_impl<float>(tdp_graph, const float *, float *, float *, hipStream_t);
+template void stns_bwd_impl<double>(tdp_graph, const float *, float *, float *, hipStream_t);
+
+}  // namespace tdp

@@ -1,0 +1,74 @@
+// Wavefront (64-lane) helpers: segmented reductions over contiguous lane
+// ranges [head, tail].  Every lane of the wave must call them (they shuffle);
+// the result is the same for every lane of a segment and is computed in a
+// fixed order, so it does not depend on timing.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace tdp {
+
+__device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
+
+template <typename T>
+__device__ __forceinline__ T seg_sum(T v, int lane, int head, int tail) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T u = __shfl_up(v, d, 64);
+    if (lane - d >= head) v += u;
+  }
+  return __shfl(v, tail, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_max(T v, int lane, int head, int tail) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T u = __shfl_up(v, d, 64);
+    if (lane - d >= head) v = u > v ? u : v;
+  }
+  return __shfl(v, tail, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_min(T v, int lane, int head, int tail) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    T u = __shfl_up(v, d, 64);
+    if (lane - d >= head) v = u < v ? u : v;
+  }
+  return __shfl(v, tail, 64);
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    int u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// the library's tables staged in LDS: [slew axes][load axes][delay][slew]
+template <typename T>
+__device__ __forceinline__ void lut_lds(const float *__restrict__ s_lut, int nt, int ns, int nl, int type, T s,
+                                        T l, T &d_out, T &s_out) {
+  const float *sa = s_lut + type * ns;
+  const float *la = s_lut + nt * ns + type * nl;
+  const T s0 = (T)sa[0], s1 = (T)sa[ns - 1], l0 = (T)la[0], l1 = (T)la[nl - 1];
+  s = s < s0 ? s0 : (s > s1 ? s1 : s);
+  l = l < l0 ? l0 : (l > l1 ? l1 : l);
+  // the interval is the last one whose left end is <= the value
+  int i = 0, j = 0;
+  for (int q = 1; q <= ns - 2; ++q) i += ((T)sa[q] <= s);
+  for (int q = 1; q <= nl - 2; ++q) j += ((T)la[q] <= l);
+  const T tau = (s - (T)sa[i]) / ((T)sa[i + 1] - (T)sa[i]);
+  const T ups = (l - (T)la[j]) / ((T)la[j + 1] - (T)la[j]);
+  const float *D = s_lut + nt * (ns + nl);
+  const float *S = D + nt * ns * nl;
+  const int base = (type * ns + i) * nl + j;
+  const T w00 = (1 - tau) * (1 - ups), w10 = tau * (1 - ups), w01 = (1 - tau) * ups, w11 = tau * ups;
+  d_out = w00 * (T)D[base] + w10 * (T)D[base + nl] + w01 * (T)D[base + 1] + w11 * (T)D[base + nl + 1];
+  s_out = w00 * (T)S[base] + w10 * (T)S[base + nl] + w01 * (T)S[base + 1] + w11 * (T)S[base + nl + 1];
+}
+
+}  // namespace tdp

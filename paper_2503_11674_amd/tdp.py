@@ -1,0 +1,401 @@
+"""Python binding of the HIP timing library (``libtdp.so``, ``include/tdp.h``).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory and the current stream.  Importing this module
+fails loudly if the compiled library is missing; there is no CPU fallback.
+
+Module-level functions carry the C names (``tdp_sta_build`` ...).
+``TimingGraph`` owns a graph handle; ``P2PLoss`` and ``SmoothTNS`` are the
+autograd Functions for the pin-to-pin loss (Eqs. 8, 10) and the smoothed TNS.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdp.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_11674_amd.build_lib`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+TDP_F32, TDP_F64 = 0, 1
+STAGES = ["netpass", "forward", "endpoint", "backward", "select", "search", "order", "walk", "pairs",
+          "p2p_fwd", "p2p_bwd", "stns", "wa"]
+_STATUS = {0: "ok", 1: "invalid argument", 2: "combinational cycle", 3: "out of memory", 4: "device error",
+           5: "capacity exceeded", 6: "call out of order", 7: "unsupported"}
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_f32 = ctypes.c_float
+
+
+class tdp_netlist(ctypes.Structure):
+    _fields_ = [("num_cells", _i32), ("num_pins", _i32), ("num_nets", _i32), ("pin_cell", _p),
+                ("pin_off_x", _p), ("pin_off_y", _p), ("net_ptr", _p), ("net_pins", _p), ("cell_type", _p),
+                ("cell_in_ptr", _p), ("cell_in_pins", _p), ("cell_out_pin", _p), ("cell_is_ff", _p),
+                ("cell_fixed", _p), ("clock_period_ps", _f32), ("setup_ps", _f32), ("input_slew_ps", _f32),
+                ("clock_slew_ps", _f32)]
+
+
+class tdp_library(ctypes.Structure):
+    _fields_ = [("num_types", _i32), ("n_slew", _i32), ("n_load", _i32), ("slew_axis", _p), ("load_axis", _p),
+                ("delay_lut", _p), ("slew_lut", _p), ("pin_cap", _p), ("r_per_um", _f32), ("c_per_um", _f32),
+                ("delay_scale", _f32)]
+
+
+class tdp_paths(ctypes.Structure):
+    _fields_ = [("max_paths", _i32), ("d_num_paths", _p), ("path_ptr", _p), ("path_pins", _p), ("path_ep", _p),
+                ("path_rank", _p), ("path_slack", _p)]
+
+
+def _sig(name, *args):
+    f = getattr(_lib, name)
+    f.restype = ctypes.c_int
+    f.argtypes = list(args)
+    return f
+
+
+_P = ctypes.POINTER
+tdp_sta_build = _sig("tdp_sta_build", _P(tdp_netlist), _P(tdp_library), ctypes.c_int, _i32, _i32, ctypes.c_int,
+                     _P(_p))
+tdp_batch_build = _sig("tdp_batch_build", _P(_P(tdp_netlist)), _i32, _P(tdp_library), ctypes.c_int, _i32, _i32,
+                       ctypes.c_int, _P(_p))
+tdp_batch_offsets = _sig("tdp_batch_offsets", _p, _p, _p)
+tdp_destroy = _lib.tdp_destroy
+tdp_destroy.restype = None
+tdp_destroy.argtypes = [_p]
+tdp_sta_set_clock = _sig("tdp_sta_set_clock", _p, _f32, _f32)
+tdp_sta_update = _sig("tdp_sta_update", _p, _p, _p, _p)
+tdp_sta_summary = _sig("tdp_sta_summary", _p, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i32), _p)
+tdp_batch_summary = _sig("tdp_batch_summary", _p, _p, _p, _p, _p)
+tdp_sta_export = _sig("tdp_sta_export", _p, _p, _p, _p, _p, _p, _p, _p, _p)
+tdp_sta_export_crit = _sig("tdp_sta_export_crit", _p, _p, _p)
+tdp_extract_paths = _sig("tdp_extract_paths", _p, _i32, _i32, _i32, _f32, _p, _P(tdp_paths))
+tdp_paths_count = _sig("tdp_paths_count", _p, _P(_i32), _P(_i32), _p)
+tdp_pairs_update = _sig("tdp_pairs_update", _p, _i32, _f32, _f32, _p)
+tdp_pairs_reset = _sig("tdp_pairs_reset", _p, _p)
+tdp_pairs_export = _sig("tdp_pairs_export", _p, _p, _p, _p)
+tdp_pairs_import = _sig("tdp_pairs_import", _p, _p, _p, _p)
+tdp_pairs_count = _sig("tdp_pairs_count", _p, _P(_i32), _p)
+tdp_p2p_loss_fwd = _sig("tdp_p2p_loss_fwd", _p, _p, _p, _p, _p)
+tdp_p2p_loss_bwd = _sig("tdp_p2p_loss_bwd", _p, _p, _p, _p, _p, _p, _p)
+tdp_stns_fwd = _sig("tdp_stns_fwd", _p, _p, _p, _f32, _p, _p)
+tdp_stns_bwd = _sig("tdp_stns_bwd", _p, _p, _p, _p, _p)
+tdp_wa_fwd_bwd = _sig("tdp_wa_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p)
+tdp_profile_enable = _sig("tdp_profile_enable", _p, _i32)
+tdp_profile_read = _sig("tdp_profile_read", _p, _p, _p)
+tdp_set_tuning = _sig("tdp_set_tuning", _p, _i32, _i32, _i32)
+tdp_graph_info = _sig("tdp_graph_info", _p, _p)
+tdp_status_str = _lib.tdp_status_str
+tdp_status_str.restype = ctypes.c_char_p
+tdp_status_str.argtypes = [ctypes.c_int]
+tdp_last_error = _lib.tdp_last_error
+tdp_last_error.restype = ctypes.c_char_p
+tdp_last_error.argtypes = [_p]
+
+EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destroy", "tdp_sta_set_clock",
+            "tdp_sta_update", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit",
+            "tdp_extract_paths", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
+            "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd", "tdp_stns_fwd",
+            "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
+            "tdp_graph_info", "tdp_status_str", "tdp_last_error"]
+
+
+class TdpError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(st: int, g=None):
+    if st != 0:
+        msg = tdp_last_error(g)
+        raise TdpError(st, msg.decode() if msg else "")
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _cuda_f32(t: torch.Tensor) -> torch.Tensor:
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    return t
+
+
+class _NetlistHolder:
+    """Keeps the numpy arrays of a netlist alive behind a tdp_netlist."""
+
+    def __init__(self, nl: Dict):
+        a = lambda k, dt: np.ascontiguousarray(nl[k], dtype=dt)
+        self.keep = {
+            "pin_cell": a("pin_cell", np.int32), "pin_off_x": a("pin_off_x", np.float32),
+            "pin_off_y": a("pin_off_y", np.float32), "net_ptr": a("net_ptr", np.int32),
+            "net_pins": a("net_pins", np.int32), "cell_type": a("cell_type", np.int32),
+            "cell_in_ptr": a("cell_in_ptr", np.int32), "cell_in_pins": a("cell_in_pins", np.int32),
+            "cell_out_pin": a("cell_out_pin", np.int32), "cell_is_ff": a("cell_is_ff", np.uint8),
+            "cell_fixed": np.ascontiguousarray(nl.get("cell_fixed", np.zeros(int(nl["num_cells"]), np.uint8)),
+                                               dtype=np.uint8),
+        }
+        k = self.keep
+        self.s = tdp_netlist(int(nl["num_cells"]), int(nl["num_pins"]), int(nl["num_nets"]),
+                             *[k[n].ctypes.data for n in ("pin_cell", "pin_off_x", "pin_off_y", "net_ptr",
+                                                          "net_pins", "cell_type", "cell_in_ptr", "cell_in_pins",
+                                                          "cell_out_pin", "cell_is_ff", "cell_fixed")],
+                             float(nl["clock_period"]), float(nl["setup"]), float(nl["input_slew"]),
+                             float(nl["clock_slew"]))
+
+
+class _LibraryHolder:
+    def __init__(self, lib: Dict):
+        nt = int(lib["num_types"])
+        self.keep = [np.ascontiguousarray(lib[k], dtype=np.float32) for k in
+                     ("slew_axis", "load_axis", "delay_lut", "slew_lut", "pin_cap")]
+        ns = self.keep[0].reshape(nt, -1).shape[1]
+        nl = self.keep[1].reshape(nt, -1).shape[1]
+        self.s = tdp_library(nt, ns, nl, *[a.ctypes.data for a in self.keep], float(lib["r_per_um"]),
+                             float(lib["c_per_um"]), float(lib["delay_scale"]))
+
+
+class TimingGraph:
+    """A timing graph on one GPU: STA, top-K path extraction, the pin-pair set
+    and the differentiable losses over it."""
+
+    def __init__(self, netlist, lib: Dict, precision: str = "f32", max_paths: int = 1 << 16, max_k: int = 1,
+                 device: int = 0):
+        self.prec = TDP_F64 if precision == "f64" else TDP_F32
+        self.device = device
+        self._lib_h = _LibraryHolder(lib)
+        h = ctypes.c_void_p()
+        if isinstance(netlist, (list, tuple)):
+            self._nl_h = [_NetlistHolder(n) for n in netlist]
+            arr = (_P(tdp_netlist) * len(self._nl_h))(*[ctypes.pointer(n.s) for n in self._nl_h])
+            _check(tdp_batch_build(arr, len(self._nl_h), ctypes.byref(self._lib_h.s), self.prec, max_paths, max_k,
+                                   device, ctypes.byref(h)))
+            self.num_inst = len(self._nl_h)
+        else:
+            self._nl_h = [_NetlistHolder(netlist)]
+            _check(tdp_sta_build(ctypes.byref(self._nl_h[0].s), ctypes.byref(self._lib_h.s), self.prec, max_paths,
+                                 max_k, device, ctypes.byref(h)))
+            self.num_inst = 1
+        self.h = h.value
+        info = np.zeros(8, np.int32)
+        _check(tdp_graph_info(self.h, info.ctypes.data), self.h)
+        (self.num_cells, self.num_pins, self.num_nets, self.depth, self.num_endpoints, self.num_startpoints,
+         self.num_comb, self.num_sinks) = [int(v) for v in info]
+        self.max_paths = max_paths
+        self.max_k = max_k
+        self._paths = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            tdp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- STA
+    def set_clock(self, period: float, setup: float = 0.0):
+        _check(tdp_sta_set_clock(self.h, period, setup), self.h)
+
+    def sta_update(self, x: torch.Tensor, y: torch.Tensor, stream=None):
+        _check(tdp_sta_update(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _stream(stream)), self.h)
+
+    def summary(self, stream=None):
+        w, t, n = ctypes.c_double(), ctypes.c_double(), _i32()
+        _check(tdp_sta_summary(self.h, ctypes.byref(w), ctypes.byref(t), ctypes.byref(n), _stream(stream)), self.h)
+        return w.value, t.value, n.value
+
+    def batch_summary(self, stream=None):
+        w = np.zeros(self.num_inst)
+        t = np.zeros(self.num_inst)
+        n = np.zeros(self.num_inst, np.int32)
+        _check(tdp_batch_summary(self.h, w.ctypes.data, t.ctypes.data, n.ctypes.data, _stream(stream)), self.h)
+        return w, t, n
+
+    def batch_offsets(self):
+        pb = np.zeros(self.num_inst + 1, np.int32)
+        cb = np.zeros(self.num_inst + 1, np.int32)
+        _check(tdp_batch_offsets(self.h, pb.ctypes.data, cb.ctypes.data), self.h)
+        return pb, cb
+
+    def export(self, stream=None) -> Dict[str, torch.Tensor]:
+        dev = torch.device("cuda", self.device)
+        out = {k: torch.empty(self.num_pins, dtype=torch.float64, device=dev)
+               for k in ("at", "rat", "slack", "slew", "dnet", "load", "darc")}
+        _check(tdp_sta_export(self.h, *[_ptr(out[k]) for k in ("at", "rat", "slack", "slew", "dnet", "load", "darc")],
+                              _stream(stream)), self.h)
+        crit = torch.empty(self.num_cells, dtype=torch.int32, device=dev)
+        _check(tdp_sta_export_crit(self.h, _ptr(crit), _stream(stream)), self.h)
+        out["crit"] = crit
+        return out
+
+    # ----------------------------------------------------------- paths
+    def extract_paths(self, n: int = -1, k: int = 1, K: Optional[int] = None,
+                      slack_limit: float = math.inf, stream=None) -> tdp_paths:
+        p = tdp_paths()
+        K = self.max_paths if K is None else K
+        _check(tdp_extract_paths(self.h, n, k, K, slack_limit, _stream(stream), ctypes.byref(p)), self.h)
+        self._paths = p
+        return p
+
+    def paths_count(self, stream=None):
+        n, pins = _i32(), _i32()
+        _check(tdp_paths_count(self.h, ctypes.byref(n), ctypes.byref(pins), _stream(stream)), self.h)
+        return n.value, pins.value
+
+    def paths(self, stream=None) -> Dict[str, np.ndarray]:
+        """Host copy of the last extraction (synchronises)."""
+        m, npins = self.paths_count(stream)
+        p = self._paths
+        dev = torch.device("cuda", self.device)
+
+        def grab(ptr, n, dt):
+            t = torch.empty(max(n, 1), dtype=dt, device=dev)
+            if n > 0:
+                _copy_dev(t, ptr, n * t.element_size())
+            return t[:n].cpu().numpy()
+
+        sdt = torch.float64 if self.prec == TDP_F64 else torch.float32
+        return {"num_paths": m,
+                "path_ptr": grab(p.path_ptr, m + 1, torch.int32),
+                "path_pins": grab(p.path_pins, npins, torch.int32),
+                "path_ep": grab(p.path_ep, m, torch.int32),
+                "path_rank": grab(p.path_rank, m, torch.int32),
+                "path_slack": grab(p.path_slack, m, sdt).astype(np.float64)}
+
+    # ----------------------------------------------------------- pairs
+    def pairs_update(self, rule: int = 0, w0: float = 10.0, w1: float = 0.2, stream=None):
+        _check(tdp_pairs_update(self.h, rule, w0, w1, _stream(stream)), self.h)
+
+    def pairs_reset(self, stream=None):
+        _check(tdp_pairs_reset(self.h, _stream(stream)), self.h)
+
+    def pairs_export(self, stream=None):
+        w = np.zeros(self.num_pins, np.float32)
+        m = np.zeros(self.num_pins, np.uint8)
+        _check(tdp_pairs_export(self.h, w.ctypes.data, m.ctypes.data, _stream(stream)), self.h)
+        return w, m
+
+    def pairs_import(self, w: np.ndarray, in_p: np.ndarray, stream=None):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        m = np.ascontiguousarray(in_p, dtype=np.uint8)
+        _check(tdp_pairs_import(self.h, w.ctypes.data, m.ctypes.data, _stream(stream)), self.h)
+
+    def pairs_count(self, stream=None) -> int:
+        n = _i32()
+        _check(tdp_pairs_count(self.h, ctypes.byref(n), _stream(stream)), self.h)
+        return n.value
+
+    # ----------------------------------------------------------- losses
+    def p2p_loss_fwd(self, x, y, out=None, stream=None) -> torch.Tensor:
+        out = torch.empty((), dtype=torch.float32, device=x.device) if out is None else out
+        _check(tdp_p2p_loss_fwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _ptr(out), _stream(stream)), self.h)
+        return out
+
+    def p2p_loss_bwd(self, x, y, gout, gx, gy, stream=None):
+        _check(tdp_p2p_loss_bwd(self.h, _ptr(x), _ptr(y), _ptr(gout), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
+
+    def stns_fwd(self, x, y, gamma: float = 10.0, out=None, stream=None) -> torch.Tensor:
+        out = torch.empty((), dtype=torch.float32, device=x.device) if out is None else out
+        _check(tdp_stns_fwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _stream(stream)), self.h)
+        return out
+
+    def stns_bwd(self, gout, gx, gy, stream=None):
+        _check(tdp_stns_bwd(self.h, _ptr(gout), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
+
+    def wa_fwd_bwd(self, x, y, gamma: float, gx, gy, out=None, stream=None) -> torch.Tensor:
+        out = torch.empty((), dtype=torch.float32, device=x.device) if out is None else out
+        _check(tdp_wa_fwd_bwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _ptr(gx), _ptr(gy),
+                              _stream(stream)), self.h)
+        return out
+
+    # ----------------------------------------------------------- tooling
+    def profile(self, on: bool = True):
+        _check(tdp_profile_enable(self.h, 1 if on else 0), self.h)
+
+    def profile_read(self) -> Dict[str, tuple]:
+        ms = np.zeros(len(STAGES), np.float64)
+        calls = np.zeros(len(STAGES), np.int32)
+        _check(tdp_profile_read(self.h, ms.ctypes.data, calls.ctypes.data), self.h)
+        return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
+
+    def set_tuning(self, block: int = 0, level_chunk: int = 0, sweep_mode: int = 0):
+        _check(tdp_set_tuning(self.h, block, level_chunk, sweep_mode), self.h)
+
+
+def _copy_dev(dst: torch.Tensor, src_ptr: int, nbytes: int):
+    """Device-to-device copy from a library-owned buffer into a tensor."""
+    hip = _hip()
+    rc = hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src_ptr), ctypes.c_size_t(nbytes),
+                       ctypes.c_int(3))
+    if rc != 0:
+        raise TdpError(4, f"hipMemcpy failed ({rc})")
+
+
+_hip_lib = None
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        _hip_lib = ctypes.CDLL("libamdhip64.so")
+        _hip_lib.hipMemcpy.restype = ctypes.c_int
+        _hip_lib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return _hip_lib
+
+
+class P2PLoss(torch.autograd.Function):
+    """PP(x, y) over the graph's current pin-pair set (Eqs. 8, 10)."""
+
+    @staticmethod
+    def forward(ctx, x, y, graph: TimingGraph):
+        ctx.graph = graph
+        ctx.save_for_backward(x, y)
+        return graph.p2p_loss_fwd(x.contiguous(), y.contiguous())
+
+    @staticmethod
+    def backward(ctx, gout):
+        x, y = ctx.saved_tensors
+        gx = torch.zeros_like(x)
+        gy = torch.zeros_like(y)
+        ctx.graph.p2p_loss_bwd(x, y, gout.contiguous().float(), gx, gy)
+        return gx, gy, None
+
+
+class SmoothTNS(torch.autograd.Function):
+    """Log-sum-exp smoothed TNS with frozen cell arcs (hand-written adjoint)."""
+
+    @staticmethod
+    def forward(ctx, x, y, graph: TimingGraph, gamma: float = 10.0):
+        ctx.graph = graph
+        ctx.save_for_backward(x, y)
+        return graph.stns_fwd(x.contiguous(), y.contiguous(), gamma)
+
+    @staticmethod
+    def backward(ctx, gout):
+        x, y = ctx.saved_tensors
+        gx = torch.zeros_like(x)
+        gy = torch.zeros_like(y)
+        ctx.graph.stns_bwd(gout.contiguous().float(), gx, gy)
+        return gx, gy, None, None

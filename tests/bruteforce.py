@@ -59,6 +59,12 @@ class Graph:
     def is_start(self, v):
         return self.role[v] in ("port", "ffq")
 
+    def is_path(self, pl):
+        """pl is a start-point-to-endpoint chain of timing arcs."""
+        if not pl or not self.is_start(pl[0]) or self.role[pl[-1]] != "ffd":
+            return False
+        return all(a in self.preds(b) for a, b in zip(pl[:-1], pl[1:]))
+
     def paths_to(self, v):
         """All start -> v paths, as pin lists in start -> v order."""
         if self.is_start(v):
