@@ -239,9 +239,18 @@ enum {
 tdp_status tdp_profile_enable(tdp_graph, int32_t on);
 tdp_status tdp_profile_read(tdp_graph, double *ms, int32_t *calls);
 
-/* Launch tuning for the sweeps (block size, cells per thread); 0 keeps the
- * current value.  Used by the autotuner. */
-tdp_status tdp_set_tuning(tdp_graph, int32_t block, int32_t level_chunk, int32_t sweep_mode);
+/* Launch tuning of the timing sweeps, used by the autotuner.
+ *  sweep_mode 0: one launch per level (any graph);
+ *  sweep_mode 1: one persistent launch per sweep in which each 64-lane chunk
+ *    of pins waits for the values it reads (single precision, every net with
+ *    at most 63 sinks; the default where possible); TDP_E_UNSUPPORTED
+ *    otherwise.  Every wait is bounded: a wait that runs out of polls makes
+ *    all waves stop waiting, and tdp_sta_summary then returns TDP_E_DEVICE.
+ *  sweep_mode 2: self-test of those bounded waits: as 1, but the start
+ *    points are never published, so every wait gives up.
+ *  flow_blocks: 256-thread blocks of the persistent launches (0 keeps);
+ *  spin_log2: log2 of the poll budget per wait (0 keeps, 1..30). */
+tdp_status tdp_set_tuning(tdp_graph, int32_t flow_blocks, int32_t spin_log2, int32_t sweep_mode);
 
 /* Sizes of the graph: num_cells, num_pins, num_nets, depth, endpoints,
  * startpoints, combinational cells, sink pins (8 int32, host). */

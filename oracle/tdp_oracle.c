@@ -708,7 +708,10 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
  * evaluated with the exponents shifted by the net's max (resp. min).  The
  * value is summed over nets and both axes; grad_x/grad_y [N] are overwritten
  * with d value / d cell position (fixed cells and ports get none). */
-static double wa_axis(int cnt, const double *v, double g, double *dv) {
+/* dabs (optional) receives |first term| + |second term| of each pin's
+ * derivative: the two cancel for coincident pins, so their magnitudes, not
+ * the difference, set the scale of rounding error. */
+static double wa_axis(int cnt, const double *v, double g, double *dv, double *dabs) {
   double mx = v[0], mn = v[0];
   for (int i = 1; i < cnt; ++i) { if (v[i] > mx) mx = v[i]; if (v[i] < mn) mn = v[i]; }
   double sa = 0, sxa = 0, sb = 0, sxb = 0;
@@ -719,7 +722,9 @@ static double wa_axis(int cnt, const double *v, double g, double *dv) {
   double fp = sxa / sa, fm = sxb / sb;
   for (int i = 0; i < cnt; ++i) {
     double a = exp((v[i] - mx) / g), b = exp(-(v[i] - mn) / g);
-    dv[i] = a / sa * (1.0 + (v[i] - fp) / g) - b / sb * (1.0 - (v[i] - fm) / g);
+    double t1 = a / sa * (1.0 + (v[i] - fp) / g), t2 = b / sb * (1.0 - (v[i] - fm) / g);
+    dv[i] = t1 - t2;
+    if (dabs) dabs[i] = fabs(t1) + fabs(t2);
   }
   return fp - fm;
 }
@@ -737,6 +742,7 @@ int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float 
   }
   double *vx = (double *)malloc(sizeof(double) * maxdeg), *vy = (double *)malloc(sizeof(double) * maxdeg);
   double *gx = (double *)malloc(sizeof(double) * maxdeg), *gy = (double *)malloc(sizeof(double) * maxdeg);
+  double *ax = (double *)malloc(sizeof(double) * maxdeg), *ay = (double *)malloc(sizeof(double) * maxdeg);
   for (int cell = 0; cell < num_cells; ++cell) {
     grad_x[cell] = 0; grad_y[cell] = 0;
     if (gabs_x) gabs_x[cell] = 0;
@@ -746,17 +752,17 @@ int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float 
   for (int net = 0; net < num_nets; ++net) {
     int b = net_ptr[net], cnt = net_ptr[net + 1] - b;
     for (int i = 0; i < cnt; ++i) pin_xy(&n, x, y, net_pins[b + i], &vx[i], &vy[i]);
-    total += wa_axis(cnt, vx, gamma, gx) + wa_axis(cnt, vy, gamma, gy);
+    total += wa_axis(cnt, vx, gamma, gx, ax) + wa_axis(cnt, vy, gamma, gy, ay);
     for (int i = 0; i < cnt; ++i) {
       int cell = pin_cell[net_pins[b + i]];
       if (cell >= 0 && !cell_fixed[cell]) {
         grad_x[cell] += gx[i]; grad_y[cell] += gy[i];
-        if (gabs_x) gabs_x[cell] += fabs(gx[i]);
-        if (gabs_y) gabs_y[cell] += fabs(gy[i]);
+        if (gabs_x) gabs_x[cell] += ax[i];
+        if (gabs_y) gabs_y[cell] += ay[i];
       }
     }
   }
   *value = total;
-  free(vx); free(vy); free(gx); free(gy);
+  free(vx); free(vy); free(gx); free(gy); free(ax); free(ay);
   return 0;
 }

@@ -167,6 +167,17 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   if (ok && g->side_k > 1)
     ok = dalloc(g, g->side_cost, (size_t)T.n_comb * g->side_k, es) &&
          dalloc(g, g->side_pin, (size_t)T.n_comb * g->side_k);
+  // dataflow sweeps: single precision, every net fits one 64-lane chunk
+  g->flow_ok = prec == TDP_F32 && T.n_big == 0;
+  g->sweep_mode = g->flow_ok ? 1 : 0;
+  if (ok && g->flow_ok) {
+    ok = dalloc(g, g->flow_w, T.M) && dalloc(g, g->flow_r, T.M) && dalloc(g, g->flow_cd, T.M) &&
+         dalloc(g, g->flow_se, (size_t)T.n_comb * g->side_k) && dalloc(g, g->tickets, 4);
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+    g->flow_blocks = cus * 2;  // 8 waves per CU, 4 per block
+  }
   if (ok) {
     const float one[4] = {1.f, 0.f, 0.f, 0.f};
     ok = hipMemcpy(g->consts, one, sizeof one, hipMemcpyHostToDevice) == hipSuccess;
@@ -281,9 +292,12 @@ tdp_status tdp_sta_summary(tdp_graph g, double *wns, double *tns, int32_t *n_fai
   if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
   const int ni = g->topo.num_inst;
   std::vector<double> h(4 * ni);
+  int32_t err = 0;
   if (hipStreamSynchronize(s) != hipSuccess ||
-      hipMemcpy(h.data(), g->summary, sizeof(double) * 4 * ni, hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(h.data(), g->summary, sizeof(double) * 4 * ni, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(g, TDP_E_DEVICE, "summary copy failed");
+  if (err & 2) return fail(g, TDP_E_DEVICE, "a dataflow sweep gave up waiting (results are invalid)");
   double w = 0, t = 0, n = 0;
   for (int i = 0; i < ni; ++i) {
     w = std::min(w, h[4 * i]);
@@ -362,7 +376,8 @@ tdp_status tdp_paths_count(tdp_graph g, int32_t *num_paths, int32_t *num_pins, h
       hipMemcpy(&pins, g->path_ptr + n, 4, hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(g, TDP_E_DEVICE, "count copy failed");
-  if (err) return fail(g, TDP_E_DEVICE, "internal: a path walk did not match its length");
+  if (err & 1) return fail(g, TDP_E_DEVICE, "internal: a path walk did not match its length");
+  if (err & 2) return fail(g, TDP_E_DEVICE, "a dataflow sweep gave up waiting (results are invalid)");
   if (num_paths) *num_paths = n;
   if (num_pins) *num_pins = pins;
   return TDP_OK;
@@ -511,11 +526,15 @@ tdp_status tdp_profile_read(tdp_graph g, double *ms, int32_t *calls) {
   return TDP_OK;
 }
 
-tdp_status tdp_set_tuning(tdp_graph g, int32_t block, int32_t level_chunk, int32_t sweep_mode) {
+tdp_status tdp_set_tuning(tdp_graph g, int32_t flow_blocks, int32_t spin_log2, int32_t sweep_mode) {
   GUARD(g);
-  if (block < 0 || level_chunk < 0 || sweep_mode < 0) return fail(g, TDP_E_INVALID, "negative tuning value");
-  if (block) g->tune_block = block;
-  if (level_chunk) g->tune_chunk = level_chunk;
+  if (flow_blocks < 0 || flow_blocks > (1 << 20)) return fail(g, TDP_E_INVALID, "flow_blocks out of range");
+  if (spin_log2 != 0 && (spin_log2 < 1 || spin_log2 > 30)) return fail(g, TDP_E_INVALID, "spin_log2 out of range");
+  if (sweep_mode < 0 || sweep_mode > 2) return fail(g, TDP_E_INVALID, "sweep_mode must be 0, 1 or 2");
+  if (sweep_mode >= 1 && !g->flow_ok)
+    return fail(g, TDP_E_UNSUPPORTED, "dataflow sweeps need single precision and nets of at most 63 sinks");
+  if (flow_blocks) g->flow_blocks = flow_blocks;
+  if (spin_log2) g->spin_limit = 1 << spin_log2;
   g->sweep_mode = sweep_mode;
   return TDP_OK;
 }

@@ -172,6 +172,14 @@ struct tdp_graph_s {
   void *side_cost = nullptr;     // [n_comb][side_k] cheapest deviations along the chain
   int32_t *side_pin = nullptr;   // [n_comb][side_k]
   void *ep_slack = nullptr;      // [E]
+  // dataflow sweeps (single precision): published words polled by consumers
+  uint64_t *flow_w = nullptr;    // [M] {arrival, transition} of a driver; all ones = not yet
+  uint32_t *flow_r = nullptr;    // [M] required time of a driver; all ones = not yet
+  uint32_t *flow_cd = nullptr;   // [M] chain depth + 1 of a driver; 0 = not yet
+  uint64_t *flow_se = nullptr;   // [n_comb][side_k] deviation entries {cost, sink}; all ones = not yet
+  int32_t *tickets = nullptr;    // [4] work counters of the persistent sweeps
+  int32_t flow_blocks = 0, spin_limit = 1 << 20;
+  bool flow_ok = false;          // the graph can use the dataflow sweeps
   double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;
   double *summary = nullptr;     // [4 * num_inst]: wns, tns, n_fail, 0
   int32_t *inst_nfail = nullptr, *d_ep_base = nullptr;

@@ -61,6 +61,66 @@ __global__ void __launch_bounds__(256) k_pairs_acc(Topo tp, int rule, const int3
   }
 }
 
+// Same sums, aggregated per block first: a block takes a run of consecutive
+// paths (which share most of their pins: they are adjacent in slack order),
+// merges its occurrences in an LDS hash table with integer atomics, and sends
+// one global atomic per distinct pin.  Pins shared by thousands of paths then
+// see one update per block instead of one per path.
+constexpr int HASH_SLOTS = 4096;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int per_block,
+                                                        const int32_t *__restrict__ d_num_paths,
+                                                        const int32_t *__restrict__ path_ptr,
+                                                        const int32_t *__restrict__ path_int,
+                                                        const int32_t *__restrict__ path_epi,
+                                                        const T *__restrict__ path_slack,
+                                                        const double *__restrict__ summary,
+                                                        unsigned long long *__restrict__ acc,
+                                                        int32_t *__restrict__ first) {
+  __shared__ int32_t hkey[HASH_SLOTS];
+  __shared__ unsigned long long hacc[HASH_SLOTS];
+  __shared__ int32_t hfirst[HASH_SLOTS];
+  for (int i = threadIdx.x; i < HASH_SLOTS; i += blockDim.x) {
+    hkey[i] = -1;
+    hacc[i] = 0ull;
+    hfirst[i] = 0x7fffffff;
+  }
+  __syncthreads();
+  const int n = *d_num_paths;
+  const int q0 = blockIdx.x * per_block;
+  const int q1 = min(n, q0 + per_block);
+  const int lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+  for (int q = q0 + (threadIdx.x >> 6); q < q1; q += nwv) {
+    const double wns = summary[4 * tp.ff_inst[path_epi[q]]];
+    unsigned long long v;
+    if (!pair_contrib<T>(rule, path_slack[q], wns, v)) continue;
+    const int b = path_ptr[q], e = path_ptr[q + 1];
+    for (int i = b + 1 + 2 * lane; i < e; i += 128) {
+      const int t = path_int[i] - tp.M;
+      if (t < 0 || t >= tp.S) continue;
+      unsigned h = ((unsigned)t * 2654435761u) >> 20;
+      for (int probe = 0; probe < HASH_SLOTS; ++probe) {
+        const int k = atomicCAS(&hkey[h], -1, t);
+        if (k == -1 || k == t) {
+          atomicAdd(&hacc[h], v);
+          atomicMin(&hfirst[h], q);
+          break;
+        }
+        h = (h + 1) & (HASH_SLOTS - 1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < HASH_SLOTS; i += blockDim.x) {
+    const int t = hkey[i];
+    if (t >= 0) {
+      atomicAdd(&acc[t], hacc[i]);
+      atomicMin(&first[t], hfirst[i]);
+    }
+  }
+}
+
 // every sink pin: apply this round's sum to the pairs it touched (the first
 // occurrence inserts under Eq. 9), clear the accumulators, flag P's members
 template <typename T>
@@ -284,9 +344,17 @@ void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s)
   if (rule == 1 && g->pairs_built)
     hipLaunchKernelGGL(k_pairs_clear_list, dim3(nb(tp.S, 256)), dim3(256), 0, s, g->d_npairs, g->pair_sink, g->pw,
                        g->pin_p);
-  hipLaunchKernelGGL(k_pairs_acc<T>, dim3(std::min(2048, nb(g->max_out, 4))), dim3(256), 0, s, tp, rule,
-                     g->d_num_paths, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack, g->summary,
-                     g->pacc, g->pfirst);
+  // a path has at most depth + 1 sinks; keep a block's occurrences within
+  // 80 % of the hash table, otherwise fall back to plain global atomics
+  const int per_block = (HASH_SLOTS * 4 / 5) / (tp.D + 1);
+  if (per_block >= 1)
+    hipLaunchKernelGGL(k_pairs_acc_lds<T>, dim3(nb(g->max_out, per_block)), dim3(256), 0, s, tp, rule, per_block,
+                       g->d_num_paths, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack, g->summary,
+                       g->pacc, g->pfirst);
+  else
+    hipLaunchKernelGGL(k_pairs_acc<T>, dim3(std::min(2048, nb(g->max_out, 4))), dim3(256), 0, s, tp, rule,
+                       g->d_num_paths, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack, g->summary,
+                       g->pacc, g->pfirst);
   hipLaunchKernelGGL(k_pairs_apply<T>, dim3(nb(tp.S, 256)), dim3(256), 0, s, tp, rule, w0, w1, g->max_out,
                      g->path_epi, (const T *)g->path_slack, g->summary, g->pacc, g->pfirst, g->pw, g->pin_p,
                      g->pflag);

@@ -256,7 +256,7 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
                                                const int32_t *__restrict__ path_ptr, int32_t *__restrict__ path_pins,
                                                int32_t *__restrict__ path_int, int32_t *__restrict__ path_ep,
                                                int32_t *__restrict__ path_epi, int32_t *__restrict__ path_rank,
-                                               T *__restrict__ path_slack, int32_t *__restrict__ err) {
+                                               T *__restrict__ path_slack, int32_t *__restrict__ err, int pin_cap) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= *d_num_paths) return;
   const int slot = out_slot[q];
@@ -276,7 +276,12 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
     a = slot_par[base + a];
   }
   const int lo = path_ptr[q];
-  int pos = path_ptr[q + 1] - 1;
+  const int hi = path_ptr[q + 1];
+  if (lo < 0 || hi > pin_cap || hi - lo < 2) {  // only after a failed update
+    atomicOr(err, 1);
+    return;
+  }
+  int pos = hi - 1;
   const int et = tp.A + f;
   path_pins[pos] = tp.snk_ext[et];
   path_int[pos] = tp.M + et;
@@ -392,7 +397,7 @@ void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream
   hipLaunchKernelGGL(k_walk<T>, dim3(nb(g->max_out, 128)), dim3(128), 0, s, tp, k, g->d_num_paths, g->out_slot,
                      g->sel_list, g->slot_dev, g->slot_par, (const T *)g->slot_key, (const int4 *)g->hop,
                      g->path_ptr, g->path_pins, g->path_int, g->path_ep, g->path_epi, g->path_rank,
-                     (T *)g->path_slack, g->d_err);
+                     (T *)g->path_slack, g->d_err, g->pin_cap);
   prof_end(g, TDP_STAGE_WALK, s);
 }
 

@@ -110,13 +110,21 @@ constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) { return (uint32_t)(k >> shift) & 0xFFu; }
 
+// tiles are counted from the live length, so the histogram and its scan cover
+// only live tiles; the count of histogram entries goes to *hist_n
+__global__ void k_rs_size(int cap, const int32_t *d_n, int32_t *__restrict__ hist_n) {
+  const int n = live_count(cap, d_n);
+  *hist_n = 256 * ((n + RS_TILE - 1) / RS_TILE);
+}
+
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const uint64_t *__restrict__ keys, int cap,
-                                                       const int32_t *d_n, int shift, int ntiles,
-                                                       int32_t *__restrict__ hist) {
+                                                       const int32_t *d_n, int shift, int32_t *__restrict__ hist) {
   __shared__ int cnt[256];
+  const int n = live_count(cap, d_n);
+  const int ntiles = (n + RS_TILE - 1) / RS_TILE;
+  if ((int)blockIdx.x >= ntiles) return;
   cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int n = live_count(cap, d_n);
   const int base = blockIdx.x * RS_TILE;
   for (int j = 0; j < RS_ITEMS; ++j) {
     int i = base + j * RS_BLOCK + threadIdx.x;
@@ -128,16 +136,18 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const uint64_t *__restrict
 
 __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const uint64_t *__restrict__ kin,
                                                           const uint32_t *__restrict__ vin, int cap,
-                                                          const int32_t *d_n, int shift, int ntiles,
+                                                          const int32_t *d_n, int shift,
                                                           const int32_t *__restrict__ offs,
                                                           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
   __shared__ int run[256];
   __shared__ int wcnt[4][256];
+  const int n = live_count(cap, d_n);
+  const int ntiles = (n + RS_TILE - 1) / RS_TILE;
+  if ((int)blockIdx.x >= ntiles) return;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   run[tid] = offs[tid * ntiles + blockIdx.x];
   wcnt[0][tid] = wcnt[1][tid] = wcnt[2][tid] = wcnt[3][tid] = 0;
   __syncthreads();
-  const int n = live_count(cap, d_n);
   const int base = blockIdx.x * RS_TILE;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int j = 0; j < RS_ITEMS; ++j) {
@@ -178,13 +188,14 @@ void radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int cap,
                 int32_t *hist, int32_t *scan_tmp, hipStream_t s) {
   if (cap <= 0) return;
   const int ntiles = (cap + RS_TILE - 1) / RS_TILE;
+  int32_t *hist_n = hist + 256 * ntiles;  // the extra slot of sort_hist_size
+  hipLaunchKernelGGL(k_rs_size, dim3(1), dim3(1), 0, s, cap, d_n, hist_n);
   uint64_t *ka = k0, *kb = k1;
   uint32_t *va = v0, *vb = v1;
   for (int shift = 0; shift < bits; shift += 8) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(RS_BLOCK), 0, s, ka, cap, d_n, shift, ntiles, hist);
-    scan_exclusive(hist, hist, 256 * ntiles, nullptr, nullptr, scan_tmp, s);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(RS_BLOCK), 0, s, ka, va, cap, d_n, shift, ntiles, hist,
-                       kb, vb);
+    hipLaunchKernelGGL(k_rs_hist, dim3(ntiles), dim3(RS_BLOCK), 0, s, ka, cap, d_n, shift, hist);
+    scan_exclusive(hist, hist, 256 * ntiles, hist_n, nullptr, scan_tmp, s);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntiles), dim3(RS_BLOCK), 0, s, ka, va, cap, d_n, shift, hist, kb, vb);
     std::swap(ka, kb);
     std::swap(va, vb);
   }

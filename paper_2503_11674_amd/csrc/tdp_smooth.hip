@@ -220,17 +220,26 @@ void stns_bwd_impl(tdp_graph g, const float *gout, float *gx, float *gy, hipStre
 //   WA = (max - min) + sum d a / sum a - sum e b / sum b,  a = e^{d/g}, b = e^{-e/g}
 //   dWA/dx = a/sum a (1 + (d - sum d a / sum a)/g) - b/sum b (1 - (e - sum e b / sum b)/g)
 
-// one axis for one lane of a chunked net; returns the net's WA on that axis
-__device__ __forceinline__ float wa_lane(float X, bool valid, int lane, int head, int tail, float ig, float &grad) {
+// one axis for one lane of a chunked net; returns the net's WA on that axis.
+// A pin's coordinate is (cell position c) + (offset o); differences are taken
+// as (c_i - c_m) + (o_i - o_m), which keeps them exact to within the rounding
+// of the result instead of carrying the rounding of c + o at die scale.
+__device__ __forceinline__ float wa_lane(float c, float o, bool valid, int lane, int head, int tail, float ig,
+                                         float &grad) {
+  const float X = c + o;
   const float mx = seg_max(valid ? X : -3.0e38f, lane, head, tail);
   const float mn = seg_min(valid ? X : 3.0e38f, lane, head, tail);
-  const float d = valid ? X - mx : 0.f, e = valid ? X - mn : 0.f;
+  const int am = seg_min((valid && X == mx) ? lane : 64, lane, head, tail) & 63;
+  const int an = seg_min((valid && X == mn) ? lane : 64, lane, head, tail) & 63;
+  const float cm = __shfl(c, am, 64), om = __shfl(o, am, 64);
+  const float cn = __shfl(c, an, 64), on = __shfl(o, an, 64);
+  const float d = valid ? (c - cm) + (o - om) : 0.f, e = valid ? (c - cn) + (o - on) : 0.f;
   const float a = valid ? expf(d * ig) : 0.f, b = valid ? expf(-e * ig) : 0.f;
   const float sa = seg_sum(a, lane, head, tail), sda = seg_sum(a * d, lane, head, tail);
   const float sb = seg_sum(b, lane, head, tail), seb = seg_sum(b * e, lane, head, tail);
   const float fp = valid ? sda / sa : 0.f, fm = valid ? seb / sb : 0.f;
   grad = valid ? a / sa * (1.f + (d - fp) * ig) - b / sb * (1.f - (e - fm) * ig) : 0.f;
-  return valid ? (mx - mn) + fp - fm : 0.f;
+  return valid ? ((cm - cn) + (om - on)) + fp - fm : 0.f;
 }
 
 // chunked nets: value partials and the gradient of each pin (internal pin order)
@@ -247,11 +256,9 @@ __global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float *__restrict
     const int head = sg & 63, tail = (sg >> 8) & 63;
     const int cell = tp.nm_cell[k];
     const bool valid = p >= 0;
-    const float X = (cell >= 0 ? x[cell] : 0.f) + tp.nm_ox[k];
-    const float Y = (cell >= 0 ? y[cell] : 0.f) + tp.nm_oy[k];
     float gxp, gyp;
-    const float wx = wa_lane(X, valid, lane, head, tail, ig, gxp);
-    const float wy = wa_lane(Y, valid, lane, head, tail, ig, gyp);
+    const float wx = wa_lane(cell >= 0 ? x[cell] : 0.f, tp.nm_ox[k], valid, lane, head, tail, ig, gxp);
+    const float wy = wa_lane(cell >= 0 ? y[cell] : 0.f, tp.nm_oy[k], valid, lane, head, tail, ig, gyp);
     if (valid) {
       gpin[2 * p] = gxp;
       gpin[2 * p + 1] = gyp;

@@ -42,19 +42,78 @@ __device__ __forceinline__ void stage_lut(const LutView &L, float *s_lut) {
   __syncthreads();
 }
 
+// published words of the dataflow sweeps (relaxed device-scope atomics; a
+// consumer polls one word, so no fences are needed)
+constexpr uint64_t W_EMPTY = ~0ull;
+constexpr uint32_t R_EMPTY = ~0u;
+
+__device__ __forceinline__ uint64_t pub_ld(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t pub_ld(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void pub_st(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void pub_st(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t pack2(float lo, float hi) {
+  return (uint64_t)__float_as_uint(lo) | ((uint64_t)__float_as_uint(hi) << 32);
+}
+
+// Poll *p until it differs from `empty`.  The wait is bounded: after `limit`
+// polls (or once another wave has given up) it sets bit 2 of *err and returns
+// `empty`, so every wave always finishes.
+template <typename U>
+__device__ __forceinline__ U wait_pub(const U *p, U empty, int32_t *err, int limit) {
+  U v = pub_ld(p);
+  int it = 0;
+  while (v == empty) {
+    if (++it > limit) {
+      atomicOr(err, 2);
+      break;
+    }
+    if ((it & 31) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+    __builtin_amdgcn_s_sleep(1);
+    v = pub_ld(p);
+  }
+  return v;
+}
+
+struct FlowInit {
+  uint64_t *w = nullptr;
+  uint32_t *r = nullptr, *cd = nullptr;
+  uint64_t *se = nullptr;
+  int32_t *tickets = nullptr;
+  int32_t *err = nullptr;  // cleared at the start of every update
+  int km = 0;
+  int seed = 1;  // 0: start points are never published (self-test of the bounded waits)
+};
+
 template <typename T>
 __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, int v, T ld, T in_slew, T clk_slew,
-                                            T *__restrict__ at, T *__restrict__ slew, int32_t *__restrict__ cdep) {
-  if (v < tp.n_pi) {
-    at[v] = 0;
-    slew[v] = in_slew;
-    cdep[v] = 0;
-  } else if (v < tp.n_start) {
-    T d, s;
-    lut_pair<T>(L, tp.ff_type[v - tp.n_pi], clk_slew, ld, d, s);
-    at[v] = d;
+                                            T *__restrict__ at, T *__restrict__ slew, int32_t *__restrict__ cdep,
+                                            const FlowInit &fl) {
+  T a = 0, s = in_slew;
+  if (v >= tp.n_pi && v < tp.n_start) lut_pair<T>(L, tp.ff_type[v - tp.n_pi], clk_slew, ld, a, s);
+  if (v < tp.n_start) {
+    at[v] = a;
     slew[v] = s;
     cdep[v] = 0;
+  }
+  if (fl.w) {  // reset (or seed) the words the dataflow sweeps poll
+    fl.r[v] = R_EMPTY;
+    if (v < tp.n_start) {
+      fl.w[v] = fl.seed ? pack2((float)a, (float)s) : W_EMPTY;
+      fl.cd[v] = fl.seed ? 1 : 0;
+    } else {
+      fl.w[v] = W_EMPTY;
+      fl.cd[v] = 0;
+      const size_t b = (size_t)(v - tp.n_start) * fl.km;
+      for (int j = 0; j < fl.km; ++j) fl.se[b + j] = W_EMPTY;
+    }
   }
 }
 
@@ -64,7 +123,9 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
                                                   const float *__restrict__ y, T kappa, T cw, T in_slew,
                                                   T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
                                                   T *__restrict__ at, T *__restrict__ slew,
-                                                  int32_t *__restrict__ cdep) {
+                                                  int32_t *__restrict__ cdep, FlowInit fl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && fl.err) *fl.err = 0;
+  if (fl.tickets && blockIdx.x == 0 && threadIdx.x < 4) fl.tickets[threadIdx.x] = 0;
   const int lane = wave_lane();
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
@@ -83,7 +144,7 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
   if (p >= 0 && lane == head) {
     const T ld = (T)tp.net_cpin[p] + cw * wl;
     load[p] = ld;
-    start_point<T>(tp, L, p, ld, in_slew, clk_slew, at, slew, cdep);
+    start_point<T>(tp, L, p, ld, in_slew, clk_slew, at, slew, cdep, fl);
   }
 }
 
@@ -108,7 +169,7 @@ __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, c
   }
   const T ld = (T)tp.net_cpin[v] + cw * wl;
   load[v] = ld;
-  start_point<T>(tp, L, v, ld, in_slew, clk_slew, at, slew, cdep);
+  start_point<T>(tp, L, v, ld, in_slew, clk_slew, at, slew, cdep, FlowInit{});
 }
 
 // insert (c, p) into the ascending list (kc, kp); an entry equal to existing
@@ -162,7 +223,9 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
   }
   const T best = seg_max(a, lane, head, tail);
   const T so = seg_max(o, lane, head, tail);
-  const int argl = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
+  // first input attaining the maximum (the head when none does, e.g. NaN)
+  const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
+  const int argl = arg0 <= tail ? arg0 : head;
   const int tc = __shfl(t, argl & 63, 64);
   const int pred = __shfl(s, argl & 63, 64);
   const bool is_head = valid && lane == head;
@@ -339,6 +402,155 @@ __global__ void k_backward_big(Topo tp, int i0, int i1, const T *__restrict__ dn
   give_inputs<T>(tp, v, r, darc, at, rat, slack);
 }
 
+// ------------------------------------------------------ dataflow sweeps
+// One persistent launch per sweep.  Each wave takes the next 64-lane chunk
+// from a ticket counter (forward: level order; backward: reverse level
+// order), waits until the words it reads are published, computes exactly
+// what the per-level kernels compute, and publishes its own words.  A chunk
+// only waits on chunks with a smaller ticket, which running waves have
+// already taken, so the sweep always completes; every wait is also bounded.
+//
+// Forward, phase 1: a lane polls its driver's {arrival, transition} word.
+// Phase 2 (head lanes, after the cell's word is out): the chain depth and the
+// deviation list follow the critical input, one polled word per entry.
+template <int KM>
+__global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const float *__restrict__ load,
+                                                       const float *__restrict__ dnet, float *__restrict__ at,
+                                                       float *__restrict__ slew, float *__restrict__ darc,
+                                                       int32_t *__restrict__ crit, int4 *__restrict__ hop,
+                                                       int32_t *__restrict__ cdep, float *__restrict__ side_cost,
+                                                       int32_t *__restrict__ side_pin, uint64_t *__restrict__ fw,
+                                                       uint32_t *__restrict__ fcd, uint64_t *__restrict__ fse,
+                                                       int32_t *__restrict__ ticket, int32_t *__restrict__ err,
+                                                       int limit) {
+  extern __shared__ float s_lut[];
+  stage_lut(L, s_lut);
+  const int lane = wave_lane();
+  for (;;) {
+    int chunk = 0;
+    if (lane == 0) chunk = atomicAdd(ticket, 1);
+    chunk = __shfl(chunk, 0, 64);
+    if (chunk >= tp.n_fw_chunks) break;
+    const int k = chunk * CHUNK + lane;
+    const int t = tp.fw_t[k];
+    const int sg = tp.fw_seg[k];
+    const int head = sg & 63, tail = (sg >> 8) & 63;
+    const bool valid = t >= 0;
+    int c = 0, s = 0;
+    float a = -__builtin_huge_valf(), o = 0.f;
+    if (valid) {
+      c = tp.snk_comb[t];
+      s = tp.snk_drv[t];
+      const float ld = load[tp.n_start + c];
+      const float dn = dnet[t];
+      const int ty = tp.comb_type[c];
+      const uint64_t w = wait_pub(&fw[s], W_EMPTY, err, limit);
+      const float a_in = __uint_as_float((uint32_t)w) + dn;
+      float d;
+      lut_lds<float>(s_lut, L.nt, L.ns, L.nl, ty, __uint_as_float((uint32_t)(w >> 32)), ld, d, o);
+      at[tp.M + t] = a_in;
+      darc[t] = d;
+      a = a_in + d;
+    }
+    const float best = seg_max(a, lane, head, tail);
+    const float so = seg_max(o, lane, head, tail);
+    // first input attaining the maximum (the head when none does, e.g. NaN)
+  const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
+  const int argl = arg0 <= tail ? arg0 : head;
+    const int tc = __shfl(t, argl & 63, 64);
+    const int pred = __shfl(s, argl & 63, 64);
+    const bool is_head = valid && lane == head;
+    const int v = tp.n_start + c;
+    if (is_head) {
+      at[v] = best;
+      slew[v] = so;
+      crit[c] = argl - head;
+      hop[c] = make_int4(tc, pred, tp.snk_ext[tc], tp.drv_ext[pred]);
+      pub_st(&fw[v], pack2(best, so));
+    }
+    // phase 2: chain depth (+1 in the published word) and deviation list
+    uint32_t cdp = 0;
+    if (is_head) {
+      cdp = wait_pub(&fcd[pred], 0u, err, limit);
+      cdep[v] = (int32_t)cdp;
+    }
+    if constexpr (KM > 1) {
+      const float dl = (valid && lane != argl) ? best - a : __builtin_huge_valf();
+      const int width = wave_max_int(valid ? tail - head + 1 : 0);
+      float kc[KM];
+      int32_t kp[KM];
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        kc[j] = __builtin_huge_valf();
+        kp[j] = -1;
+      }
+      if (is_head && pred >= tp.n_start) {
+        const size_t pb = (size_t)(pred - tp.n_start) * KM;
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+          const uint64_t e = wait_pub(&fse[pb + j], W_EMPTY, err, limit);
+          kc[j] = __uint_as_float((uint32_t)e);
+          kp[j] = (int32_t)(uint32_t)(e >> 32);
+        }
+      }
+      for (int r = 0; r < width; ++r) {
+        const int j = tail - r;
+        const float dj = __shfl(dl, j & 63, 64);
+        const int tj = __shfl(t, j & 63, 64);
+        if (is_head && j >= head && dj < __builtin_huge_valf()) insert_front<float, KM>(kc, kp, dj, tj);
+      }
+      if (is_head) {
+        const size_t cb = (size_t)c * KM;
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+          side_cost[cb + j] = kc[j];
+          side_pin[cb + j] = kp[j];
+          pub_st(&fse[cb + j], (uint64_t)__float_as_uint(kc[j]) | ((uint64_t)(uint32_t)kp[j] << 32));
+        }
+      }
+    }
+    if (is_head) pub_st(&fcd[v], cdp + 1);
+  }
+}
+
+// Backward: a sink lane polls the required time of its cell's output (the D
+// pin of a flip-flop needs nothing); the driver lane publishes its own.
+__global__ void __launch_bounds__(256) k_backward_flow(Topo tp, float req, const float *__restrict__ dnet,
+                                                        const float *__restrict__ darc, const float *__restrict__ at,
+                                                        float *__restrict__ rat, float *__restrict__ slack,
+                                                        uint32_t *__restrict__ fr, int32_t *__restrict__ ticket,
+                                                        int32_t *__restrict__ err, int limit) {
+  const int lane = wave_lane();
+  const float inf = __builtin_huge_valf();
+  for (;;) {
+    int q = 0;
+    if (lane == 0) q = atomicAdd(ticket, 1);
+    q = __shfl(q, 0, 64);
+    if (q >= tp.n_nm_chunks) break;
+    const int chunk = tp.n_nm_chunks - 1 - q;
+    const int k = chunk * CHUNK + lane;
+    const int p = tp.nm_pin[k];
+    const int sg = tp.nm_seg[k];
+    const int head = sg & 63, tail = (sg >> 8) & 63;
+    float r = inf;
+    if (p >= 0 && lane != head) {
+      const int t = p - tp.M;
+      float rt = req;
+      if (t < tp.A) {
+        const uint32_t ro = wait_pub(&fr[tp.n_start + tp.snk_comb[t]], R_EMPTY, err, limit);
+        const float r_out = __uint_as_float(ro);
+        rt = r_out != inf ? r_out - darc[t] : inf;
+      }
+      if (rt != inf) r = rt - dnet[t];
+    }
+    r = seg_min(r, lane, head, tail);
+    if (p >= 0 && lane == head) {
+      give_inputs<float>(tp, p, r, darc, at, rat, slack);
+      pub_st(&fr[p], __float_as_uint(r));
+    }
+  }
+}
+
 // --------------------------------------------------------------- export
 template <typename T>
 __global__ void __launch_bounds__(256) k_export(Topo tp, const T *__restrict__ at, const T *__restrict__ rat,
@@ -395,23 +607,59 @@ static void forward_level(tdp_graph g, int ch0, int ch1, hipStream_t s) {
   }
 }
 
+template <int KM>
+static void launch_forward_flow(tdp_graph g, hipStream_t s) {
+  const Topo &tp = g->topo;
+  hipLaunchKernelGGL((k_forward_flow<KM>), dim3(g->flow_blocks), dim3(256), lut_bytes(g->lut), s, tp, g->lut,
+                     (const float *)g->load, (const float *)g->dnet, (float *)g->at, (float *)g->slew,
+                     (float *)g->darc, g->crit, (int4 *)g->hop, g->cdep, (float *)g->side_cost, g->side_pin,
+                     g->flow_w, g->flow_cd, g->flow_se, g->tickets, g->d_err, g->spin_limit);
+}
+
+static void forward_flow(tdp_graph g, hipStream_t s) {
+  switch (g->side_k) {
+    case 1: launch_forward_flow<1>(g, s); break;
+    case 2: launch_forward_flow<2>(g, s); break;
+    case 4: launch_forward_flow<4>(g, s); break;
+    case 8: launch_forward_flow<8>(g, s); break;
+    case 16: launch_forward_flow<16>(g, s); break;
+    default: launch_forward_flow<32>(g, s); break;
+  }
+}
+
 template <typename T>
 void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   const Topo &tp = g->topo;
   const T kappa = (T)g->scale * (T)g->r * (T)g->c;
+  const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;
+  FlowInit fl;
+  fl.err = g->d_err;
+  if (flow) {
+    fl.w = g->flow_w;
+    fl.r = g->flow_r;
+    fl.cd = g->flow_cd;
+    fl.se = g->flow_se;
+    fl.tickets = g->tickets;
+    fl.km = g->side_k > 1 ? g->side_k : 0;
+    fl.seed = g->sweep_mode == 2 ? 0 : 1;
+  }
   prof_begin(g, TDP_STAGE_NETPASS, s);
   hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, x, y, kappa,
                      (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
-                     (T *)g->slew, g->cdep);
+                     (T *)g->slew, g->cdep, fl);
   if (tp.n_big > 0)
     hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, kappa,
                        (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
                        (T *)g->slew, g->cdep);
   prof_end(g, TDP_STAGE_NETPASS, s);
   prof_begin(g, TDP_STAGE_FORWARD, s);
-  for (int l = 1; l <= tp.D; ++l) {
-    const int ch0 = g->lv.fw_lvl[l - 1], ch1 = g->lv.fw_lvl[l];
-    if (ch1 > ch0) forward_level<T>(g, ch0, ch1, s);
+  if (flow) {
+    forward_flow(g, s);
+  } else {
+    for (int l = 1; l <= tp.D; ++l) {
+      const int ch0 = g->lv.fw_lvl[l - 1], ch1 = g->lv.fw_lvl[l];
+      if (ch1 > ch0) forward_level<T>(g, ch0, ch1, s);
+    }
   }
   prof_end(g, TDP_STAGE_FORWARD, s);
   prof_begin(g, TDP_STAGE_ENDPOINT, s);
@@ -425,6 +673,13 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
                      g->summary, g->inst_nfail);
   prof_end(g, TDP_STAGE_ENDPOINT, s);
   prof_begin(g, TDP_STAGE_BACKWARD, s);
+  if (flow) {
+    hipLaunchKernelGGL(k_backward_flow, dim3(g->flow_blocks), dim3(256), 0, s, tp, (float)req, (const float *)g->dnet,
+                       (const float *)g->darc, (const float *)g->at, (float *)g->rat, (float *)g->slack, g->flow_r,
+                       g->tickets + 1, g->d_err, g->spin_limit);
+    prof_end(g, TDP_STAGE_BACKWARD, s);
+    return;
+  }
   for (int l = tp.D; l >= 0; --l) {
     const int ch0 = g->lv.nm_lvl[l], ch1 = g->lv.nm_lvl[l + 1];
     if (ch1 > ch0)

@@ -340,8 +340,10 @@ class TimingGraph:
         _check(tdp_profile_read(self.h, ms.ctypes.data, calls.ctypes.data), self.h)
         return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
 
-    def set_tuning(self, block: int = 0, level_chunk: int = 0, sweep_mode: int = 0):
-        _check(tdp_set_tuning(self.h, block, level_chunk, sweep_mode), self.h)
+    def set_tuning(self, flow_blocks: int = 0, spin_log2: int = 0, sweep_mode: int = 1):
+        """sweep_mode 0: one launch per level; 1: persistent dataflow sweeps;
+        2: self-test of the dataflow sweeps' bounded waits."""
+        _check(tdp_set_tuning(self.h, flow_blocks, spin_log2, sweep_mode), self.h)
 
 
 def _copy_dev(dst: torch.Tensor, src_ptr: int, nbytes: int):

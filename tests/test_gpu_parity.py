@@ -394,6 +394,51 @@ def test_batch_matches_single_instances(library):
         g.close()
 
 
+# ------------------------------------------------------------ sweep modes
+def test_level_and_dataflow_sweeps_agree_bitwise(library):
+    """The persistent dataflow sweeps compute exactly what the one-launch-per-
+    level sweeps compute (same operations in the same order per value)."""
+    tdp = _tdp()
+    c = case("C2", library)
+    nl = c["nl"]
+    outs = []
+    for mode in (0, 1):
+        g = tdp.TimingGraph(nl, library, max_paths=c["K"], max_k=c["k"])
+        g.set_tuning(sweep_mode=mode)
+        g.sta_update(c["x"], c["y"])
+        o = {k: v.cpu().numpy() for k, v in g.export().items()}
+        g.extract_paths(n=-1, k=c["k"], K=c["K"])
+        p = g.paths()
+        outs.append((o, p, g.summary()))
+        g.close()
+    (o0, p0, s0), (o1, p1, s1) = outs
+    for key in o0:
+        assert np.array_equal(o0[key], o1[key]), key
+    for key in ("path_ptr", "path_pins", "path_ep", "path_rank", "path_slack"):
+        assert np.array_equal(p0[key], p1[key]), key
+    assert s0 == s1
+
+
+def test_dataflow_wait_gives_up_cleanly(library):
+    """Self-test of the bounded waits: with the start points withheld every
+    wait runs out of polls, the kernels still finish and the summary reports
+    a device error; the next normal update is correct again."""
+    tdp = _tdp()
+    nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), library)
+    st = ref.sta(nl, library)
+    g = tdp.TimingGraph(nl, library, max_paths=200, max_k=10)
+    x, y = _xy(nl)
+    g.set_tuning(spin_log2=4, sweep_mode=2)
+    g.sta_update(x, y)
+    with pytest.raises(tdp.TdpError) as e:
+        g.summary()
+    assert e.value.status == 4
+    g.set_tuning(spin_log2=20, sweep_mode=1)
+    g.sta_update(x, y)
+    wns, tns, nf = g.summary()
+    assert nf == st["n_fail"] and abs(wns - st["wns"]) <= 1e-4 * abs(st["wns"])
+
+
 # ------------------------------------------------------------------ errors
 def test_error_paths(library):
     tdp = _tdp()
