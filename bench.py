@@ -9,6 +9,11 @@ paths).  Cell positions are fixed across steps, so every step does the same
 work.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--workload C5|C3|C2|C1] [--no-cpu]
+
+--workload C4 measures the batched form instead: timing update + extraction
+(k = 10, K = 5,000 per instance) over 32 uneven netlists and 8 placement
+snapshots of a 500k-cell netlist, as one union graph replayed from a captured
+HIP graph, against the same 40 instances launched one graph at a time.
 """
 from __future__ import annotations
 
@@ -37,6 +42,8 @@ def parse():
     ap.add_argument("--workload", default="C5")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch configuration)")
+    ap.add_argument("--sweep-mode", type=int, default=-1, help="force a sweep form (0 per level, 1 dataflow)")
     return ap.parse_args()
 
 
@@ -75,6 +82,8 @@ def main():
     from paper_2503_11674_amd import netgen
     from paper_2503_11674_amd.tdp import TimingGraph, STAGES
 
+    if a.workload == "C4":
+        return bench_batch(a)
     cfg = netgen.CONFIGS[a.workload]
     t0 = time.time()
     nl = netgen.make_netlist(cfg)
@@ -102,9 +111,9 @@ def main():
 
     gx = torch.zeros_like(x)
     gy = torch.zeros_like(y)
-    wl = torch.zeros((), device=dev)
-    pp = torch.zeros((), device=dev)
-    beta = torch.full((), BETA, device=dev)
+    wl = torch.zeros((), dtype=torch.float64, device=dev)
+    pp = torch.zeros((), dtype=torch.float64, device=dev)
+    beta = torch.full((), BETA, dtype=torch.float64, device=dev)
 
     def step():
         # every call launches on the stream that is current at call time (the
@@ -118,6 +127,14 @@ def main():
         g.p2p_loss_fwd(x, y, out=pp)
         g.p2p_loss_bwd(x, y, beta, gx, gy)
 
+    tune = None
+    if a.sweep_mode >= 0:
+        g.set_tuning(sweep_mode=a.sweep_mode)
+        tune = {"forced_sweep_mode": a.sweep_mode}
+    elif not a.no_tune:
+        tune = g.autotune(x, y, n=-1, k=k, K=K, reps=3)
+    if tune:
+        print(f"[bench] autotuner: {tune}", file=sys.stderr, flush=True)
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -186,11 +203,108 @@ def main():
         "stages": stages,
         "roofline": roof,
         "graph_replay": bool(graph is not None),
+        "tuning": tune,
         "timing": {"wns": wns, "tns": tns, "n_fail": nfail, "paths": npaths, "path_pins": npins,
                    "pairs": counts["pairs"]},
     }
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nl, lib, k, K, pins)
+    print(json.dumps(out))
+
+
+def bench_batch(a):
+    """Batched timing update + extraction against per-instance launches."""
+    import torch
+
+    from paper_2503_11674_amd import netgen
+    from paper_2503_11674_amd.tdp import TimingGraph
+
+    t0 = time.time()
+    nls = netgen.batch_workload()
+    lib = netgen.make_library()
+    k, K = 10, 5000
+    dev = torch.device("cuda", 0)
+    print(f"[bench] generated {len(nls)} instances, {sum(n['num_cells'] for n in nls)} cells "
+          f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    singles = []
+    for nl in nls:
+        x = torch.tensor(nl["x"], device=dev)
+        y = torch.tensor(nl["y"], device=dev)
+        g = TimingGraph(nl, lib, max_paths=K, max_k=k)
+        g.sta_update(x, y)
+        at = g.export()["at"].cpu().numpy()
+        ep = nl["cell_in_pins"][nl["cell_in_ptr"][np.nonzero(nl["cell_is_ff"])[0]]]
+        T = netgen.clock_period_for_fail_fraction(at[ep], 0.05)
+        g.set_clock(T)
+        nl["clock_period"] = np.float32(T)
+        singles.append((g, x, y))
+    gb = TimingGraph(nls, lib, max_paths=K, max_k=k)
+    xb = torch.cat([s[1] for s in singles])
+    yb = torch.cat([s[2] for s in singles])
+    pins = gb.num_pins
+    print(f"[bench] union graph: {gb.num_cells} cells, {pins} pins", file=sys.stderr, flush=True)
+    tune_b = None if a.no_tune else gb.autotune(xb, yb, n=-1, k=k, K=K, reps=3)
+    tune_s = None if a.no_tune else [g.autotune(x, y, n=-1, k=k, K=K, reps=2) for g, x, y in singles]
+
+    def batched():
+        gb.sta_update(xb, yb)
+        gb.extract_paths(n=-1, k=k, K=K)
+
+    def per_instance():
+        for g, x, y in singles:
+            g.sta_update(x, y)
+            g.extract_paths(n=-1, k=k, K=K)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    def captured(fn):
+        fn()
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            fn()
+        torch.cuda.synchronize()
+        return gr
+
+    for _ in range(a.warmup):
+        batched()
+        per_instance()
+    gr_b = captured(batched)
+    gr_s = captured(per_instance)
+    print(f"[bench] timing {a.steps} steps of each form", file=sys.stderr, flush=True)
+    t_b = timed(gr_b.replay, a.steps)
+    t_s_graph = timed(gr_s.replay, a.steps)
+    t_s_eager = timed(per_instance, a.steps)
+    t_b_eager = timed(batched, a.steps)
+    # the union's selections are the instances' own: same path counts
+    nb = gb.paths_count()
+    ns = [g.paths_count() for g, _, _ in singles]
+    wb, _, fb = gb.batch_summary()
+    out = {
+        "metric": "timing-graph pins/s for STA+top-K extraction; p2p loss fwd+bwd GB/s",
+        "value": round(pins / t_b, 1), "unit": "pins/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1000 * t_b, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"C4: {len(nls)} instances (32 netlists of 10k-300k cells, depth 20-80, and 8 "
+                               f"jittered snapshots of a 500k-cell netlist), {gb.num_cells} cells, {pins} pins; "
+                               f"step = timing update + extraction (n_fail, k={k}, K={K} per instance)",
+                   "parallelism": "none"},
+        "batched_graph_ms": round(1000 * t_b, 4),
+        "batched_eager_ms": round(1000 * t_b_eager, 4),
+        "per_instance_graph_ms": round(1000 * t_s_graph, 4),
+        "per_instance_eager_ms": round(1000 * t_s_eager, 4),
+        "speedup_vs_per_instance_eager": round(t_s_eager / t_b, 3),
+        "speedup_vs_per_instance_graph": round(t_s_graph / t_b, 3),
+        "paths": {"batched": nb[0], "per_instance": int(sum(n[0] for n in ns))},
+        "n_fail": {"batched": int(fb.sum()), "min_instance": int(fb.min())},
+        "tuning": {"batched": tune_b, "per_instance": tune_s[:3] if tune_s else None},
+    }
     print(json.dumps(out))
 
 

@@ -204,26 +204,30 @@ tdp_status tdp_pairs_count(tdp_graph, int32_t *num_pairs, hipStream_t);
 
 /* ---------------------------------------------------------------- loss */
 /* PP = sum over P of w * ((X_s - X_t)^2 + (Y_s - Y_t)^2), X = cell position +
- * pin offset (Eqs. 8, 10).  *d_loss (device float) is overwritten. */
-tdp_status tdp_p2p_loss_fwd(tdp_graph, const float *d_x, const float *d_y, float *d_loss, hipStream_t);
-/* d_gx/d_gy [num_cells] += (*d_gout) * dPP/dx, dPP/dy; fixed cells and
+ * pin offset (Eqs. 8, 10).  *d_loss (one device double) is overwritten.
+ * Each term is evaluated in the graph's precision and the terms are summed
+ * in double in a fixed order. */
+tdp_status tdp_p2p_loss_fwd(tdp_graph, const float *d_x, const float *d_y, double *d_loss, hipStream_t);
+/* d_gx/d_gy [num_cells] += (*d_gout) * dPP/dx, dPP/dy, with d_gout one
+ * device double (NULL: 1); fixed cells and
  * ports get nothing.  Deterministic (fixed summation order per cell). */
-tdp_status tdp_p2p_loss_bwd(tdp_graph, const float *d_x, const float *d_y, const float *d_gout,
+tdp_status tdp_p2p_loss_bwd(tdp_graph, const float *d_x, const float *d_y, const double *d_gout,
                             float *d_gx, float *d_gy, hipStream_t);
 
 /* Smoothed TNS: cell-arc delays and start arrivals frozen from the last
  * update, net delays from d_x/d_y; log-sum-exp over fan-in with temperature
  * gamma_ps, value = -gamma * sum over endpoints of softplus(-slack/gamma).
  * fwd overwrites *d_val; bwd (same positions as the last fwd) adds
- * (*d_gout) * gradient into d_gx/d_gy. */
-tdp_status tdp_stns_fwd(tdp_graph, const float *d_x, const float *d_y, float gamma_ps, float *d_val,
+ * (*d_gout) * gradient into d_gx/d_gy.  d_val and d_gout are single device
+ * doubles (d_gout NULL: 1). */
+tdp_status tdp_stns_fwd(tdp_graph, const float *d_x, const float *d_y, float gamma_ps, double *d_val,
                         hipStream_t);
-tdp_status tdp_stns_bwd(tdp_graph, const float *d_gout, float *d_gx, float *d_gy, hipStream_t);
+tdp_status tdp_stns_bwd(tdp_graph, const double *d_gout, float *d_gx, float *d_gy, hipStream_t);
 
 /* Weighted-average wirelength over every net (driver and sinks, ports too),
- * both axes, temperature gamma_um.  *d_wl (device float) is overwritten;
+ * both axes, temperature gamma_um.  *d_wl (one device double) is overwritten;
  * d_gx/d_gy [num_cells] += gradient (movable cells only). */
-tdp_status tdp_wa_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float gamma_um, float *d_wl,
+tdp_status tdp_wa_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float gamma_um, double *d_wl,
                           float *d_gx, float *d_gy, hipStream_t);
 
 /* ------------------------------------------------------------ tooling */
@@ -248,9 +252,23 @@ tdp_status tdp_profile_read(tdp_graph, double *ms, int32_t *calls);
  *    all waves stop waiting, and tdp_sta_summary then returns TDP_E_DEVICE.
  *  sweep_mode 2: self-test of those bounded waits: as 1, but the start
  *    points are never published, so every wait gives up.
- *  flow_blocks: 256-thread blocks of the persistent launches (0 keeps);
- *  spin_log2: log2 of the poll budget per wait (0 keeps, 1..30). */
-tdp_status tdp_set_tuning(tdp_graph, int32_t flow_blocks, int32_t spin_log2, int32_t sweep_mode);
+ *  flow_waves: 64-lane waves per workgroup of the dataflow sweeps (1, 2 or
+ *    4; 0 keeps; default 4);
+ *  spin_log2: log2 of the poll budget per wait (0 keeps, 1..30).
+ * Results do not depend on the tuning: both sweep forms compute every value
+ * with the same operations in the same order. */
+tdp_status tdp_set_tuning(tdp_graph, int32_t flow_waves, int32_t spin_log2, int32_t sweep_mode);
+
+/* Autotuner: on the caller's positions, times the timing update followed by
+ * extract_paths(n, k, K) (k = 0: the update alone) under every sweep
+ * configuration the graph supports (per-level launches; dataflow sweeps with
+ * 1, 2 or 4 waves per workgroup), one warm-up and `reps` timed runs each
+ * (1..1000), and keeps the fastest.  h_choice (3 int32, host, may be NULL)
+ * receives {sweep_mode, flow_waves, microseconds per run}.  Synchronises;
+ * on return the graph holds the chosen configuration's results for these
+ * positions.  Errors as tdp_sta_update / tdp_extract_paths. */
+tdp_status tdp_autotune(tdp_graph, const float *d_x, const float *d_y, int32_t n, int32_t k, int32_t K,
+                        int32_t reps, int32_t *h_choice, hipStream_t);
 
 /* Sizes of the graph: num_cells, num_pins, num_nets, depth, endpoints,
  * startpoints, combinational cells, sink pins (8 int32, host). */

@@ -231,7 +231,8 @@ def stns(nl, lib, st, gamma: float = 10.0, x=None, y=None):
 
 def wa(nl, gamma: float = 5.0, x=None, y=None, with_abs: bool = False):
     """Weighted-average wirelength over all nets, both axes, and its gradient
-    (with_abs: also the per-cell sums of the pin terms' magnitudes)."""
+    (with_abs: also, per cell, the summed magnitudes of the summands of its
+    pins' derivatives, the scale of the rounding error)."""
     L = _load()
     x = _f32(nl["x"] if x is None else x)
     y = _f32(nl["y"] if y is None else y)

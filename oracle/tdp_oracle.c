@@ -724,13 +724,15 @@ static double wa_axis(int cnt, const double *v, double g, double *dv, double *da
     double a = exp((v[i] - mx) / g), b = exp(-(v[i] - mn) / g);
     double t1 = a / sa * (1.0 + (v[i] - fp) / g), t2 = b / sb * (1.0 - (v[i] - fm) / g);
     dv[i] = t1 - t2;
-    if (dabs) dabs[i] = fabs(t1) + fabs(t2);
+    /* magnitudes of the four summands a/sa, a/sa (v - fp)/g, b/sb, b/sb (v - fm)/g */
+    if (dabs) dabs[i] = a / sa * (1.0 + fabs(v[i] - fp) / g) + b / sb * (1.0 + fabs(v[i] - fm) / g);
   }
   return fp - fm;
 }
 
-/* gabs_x/gabs_y (optional, [N]) receive, per cell, the sum of the magnitudes
- * of its pins' terms: the scale of the rounding error of the gradient. */
+/* gabs_x/gabs_y (optional, [N]) receive, per cell, the sum over its pins of
+ * the magnitudes of the summands of each pin's derivative: the scale of the
+ * rounding error of the gradient. */
 int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float *y, double gamma,
            double *value, double *grad_x, double *grad_y, double *gabs_x, double *gabs_y) {
   FILL_NETLIST(n);

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
+#include <vector>
 #include <new>
 
 #include "tdp_impl.h"
@@ -151,9 +153,8 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        upload(g, T.ff_type, H.ff_type) && upload(g, T.ff_inst, H.ff_inst) &&
        upload(g, T.ext_pin_int, H.ext_pin_int) && upload(g, T.cell_int, H.cell_int) &&
        upload(g, T.cell_fixed, H.cell_fixed) && upload(g, g->d_ep_base, H.lv.ep_base) &&
-       upload(g, T.fw_t, H.fw_t) && upload(g, T.fw_seg, H.fw_seg) && upload(g, T.nm_pin, H.nm_pin) &&
-       upload(g, T.nm_cell, H.nm_cell) && upload(g, T.nm_ox, H.nm_ox) && upload(g, T.nm_oy, H.nm_oy) &&
-       upload(g, T.nm_seg, H.nm_seg) && upload(g, T.big_net, H.big_net);
+       upload(g, T.fw_rec, H.fw_rec) && upload(g, T.nm_rec, H.nm_rec) &&
+       upload(g, T.nm_ox, H.nm_ox) && upload(g, T.nm_oy, H.nm_oy) && upload(g, T.big_net, H.big_net);
   g->h_snk_ext = H.snk_ext;
   // timing state
   const size_t es = g->esz;
@@ -173,13 +174,9 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   if (ok && g->flow_ok) {
     ok = dalloc(g, g->flow_w, T.M) && dalloc(g, g->flow_r, T.M) && dalloc(g, g->flow_cd, T.M) &&
          dalloc(g, g->flow_se, (size_t)T.n_comb * g->side_k) && dalloc(g, g->tickets, 4);
-    hipDeviceProp_t prop;
-    int cus = 256;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
-    g->flow_blocks = cus * 2;  // 8 waves per CU, 4 per block
   }
   if (ok) {
-    const float one[4] = {1.f, 0.f, 0.f, 0.f};
+    const double one[4] = {1.0, 0.0, 0.0, 0.0};
     ok = hipMemcpy(g->consts, one, sizeof one, hipMemcpyHostToDevice) == hipSuccess;
   }
   // extraction
@@ -209,7 +206,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        dalloc(g, g->inc_w, (size_t)2 * T.S);
   // smoothed TNS, WA
   ok = ok && dalloc(g, g->st_at, T.P, es) && dalloc(g, g->st_adj, T.P, es) && dalloc(g, g->st_dnet, T.S, es) &&
-       dalloc(g, g->wa_gpin, (size_t)2 * T.P);
+       dalloc(g, g->wa_gpin, (size_t)2 * T.P) && dalloc(g, g->xy, T.N);
   if (!ok || hipDeviceSynchronize() != hipSuccess) {
     free_all(g);
     delete g;
@@ -456,22 +453,22 @@ tdp_status tdp_pairs_count(tdp_graph g, int32_t *num_pairs, hipStream_t s) {
   return TDP_OK;
 }
 
-tdp_status tdp_p2p_loss_fwd(tdp_graph g, const float *x, const float *y, float *loss, hipStream_t s) {
+tdp_status tdp_p2p_loss_fwd(tdp_graph g, const float *x, const float *y, double *loss, hipStream_t s) {
   GUARD(g);
   if (!x || !y || !loss) return fail(g, TDP_E_INVALID, "NULL argument");
-  p2p_fwd_impl(g, x, y, loss, s);
+  dispatch(g, [&](auto z) { p2p_fwd_impl<decltype(z)>(g, x, y, loss, s); });
   return check_launch(g, "p2p_loss_fwd");
 }
 
-tdp_status tdp_p2p_loss_bwd(tdp_graph g, const float *x, const float *y, const float *gout, float *gx, float *gy,
+tdp_status tdp_p2p_loss_bwd(tdp_graph g, const float *x, const float *y, const double *gout, float *gx, float *gy,
                             hipStream_t s) {
   GUARD(g);
   if (!x || !y || !gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
-  p2p_bwd_impl(g, x, y, gout ? gout : g->consts, gx, gy, s);
+  dispatch(g, [&](auto z) { p2p_bwd_impl<decltype(z)>(g, x, y, gout ? gout : g->consts, gx, gy, s); });
   return check_launch(g, "p2p_loss_bwd");
 }
 
-tdp_status tdp_stns_fwd(tdp_graph g, const float *x, const float *y, float gamma, float *val, hipStream_t s) {
+tdp_status tdp_stns_fwd(tdp_graph g, const float *x, const float *y, float gamma, double *val, hipStream_t s) {
   GUARD(g);
   if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
   if (!x || !y || !val) return fail(g, TDP_E_INVALID, "NULL argument");
@@ -482,7 +479,7 @@ tdp_status tdp_stns_fwd(tdp_graph g, const float *x, const float *y, float gamma
   return st;
 }
 
-tdp_status tdp_stns_bwd(tdp_graph g, const float *gout, float *gx, float *gy, hipStream_t s) {
+tdp_status tdp_stns_bwd(tdp_graph g, const double *gout, float *gx, float *gy, hipStream_t s) {
   GUARD(g);
   if (!g->stns_ready) return fail(g, TDP_E_STATE, "no smoothed-TNS forward yet");
   if (!gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
@@ -490,7 +487,7 @@ tdp_status tdp_stns_bwd(tdp_graph g, const float *gout, float *gx, float *gy, hi
   return check_launch(g, "stns_bwd");
 }
 
-tdp_status tdp_wa_fwd_bwd(tdp_graph g, const float *x, const float *y, float gamma, float *wl, float *gx, float *gy,
+tdp_status tdp_wa_fwd_bwd(tdp_graph g, const float *x, const float *y, float gamma, double *wl, float *gx, float *gy,
                           hipStream_t s) {
   GUARD(g);
   if (!x || !y || !wl || !gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
@@ -526,16 +523,84 @@ tdp_status tdp_profile_read(tdp_graph g, double *ms, int32_t *calls) {
   return TDP_OK;
 }
 
-tdp_status tdp_set_tuning(tdp_graph g, int32_t flow_blocks, int32_t spin_log2, int32_t sweep_mode) {
+tdp_status tdp_set_tuning(tdp_graph g, int32_t flow_waves, int32_t spin_log2, int32_t sweep_mode) {
   GUARD(g);
-  if (flow_blocks < 0 || flow_blocks > (1 << 20)) return fail(g, TDP_E_INVALID, "flow_blocks out of range");
+  if (flow_waves != 0 && flow_waves != 1 && flow_waves != 2 && flow_waves != 4)
+    return fail(g, TDP_E_INVALID, "flow_waves must be 0, 1, 2 or 4");
   if (spin_log2 != 0 && (spin_log2 < 1 || spin_log2 > 30)) return fail(g, TDP_E_INVALID, "spin_log2 out of range");
   if (sweep_mode < 0 || sweep_mode > 2) return fail(g, TDP_E_INVALID, "sweep_mode must be 0, 1 or 2");
   if (sweep_mode >= 1 && !g->flow_ok)
     return fail(g, TDP_E_UNSUPPORTED, "dataflow sweeps need single precision and nets of at most 63 sinks");
-  if (flow_blocks) g->flow_blocks = flow_blocks;
+  if (flow_waves) g->flow_waves = flow_waves;
   if (spin_log2) g->spin_limit = 1 << spin_log2;
   g->sweep_mode = sweep_mode;
+  return TDP_OK;
+}
+
+tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, int32_t k, int32_t K, int32_t reps,
+                        int32_t *choice, hipStream_t s) {
+  GUARD(g);
+  if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
+  if (reps < 1 || reps > 1000) return fail(g, TDP_E_INVALID, "reps must be 1..1000");
+  if (k < 0 || k > g->max_k) return fail(g, TDP_E_CAPACITY, "k outside 0..max_k");
+  struct Cand {
+    int mode, waves;
+  };
+  std::vector<Cand> cands = {{0, g->flow_waves}};
+  if (g->flow_ok)
+    for (int w : {1, 2, 4}) cands.push_back({1, w});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return fail(g, TDP_E_DEVICE, "event creation failed");
+  }
+  const bool prof = g->prof.on;
+  g->prof.on = false;
+  const float no_limit = std::numeric_limits<float>::infinity();
+  Cand best_c = {g->sweep_mode, g->flow_waves};
+  float best = std::numeric_limits<float>::infinity();
+  tdp_status st = TDP_OK;
+  auto run = [&]() {
+    tdp_status r = tdp_sta_update(g, x, y, s);
+    if (r == TDP_OK && k > 0) r = tdp_extract_paths(g, n, k, K, no_limit, s, nullptr);
+    return r;
+  };
+  for (const Cand &c : cands) {
+    g->sweep_mode = c.mode;
+    g->flow_waves = c.waves;
+    st = run();  // warm-up
+    if (st == TDP_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(g, TDP_E_DEVICE, "event record failed");
+    for (int r = 0; r < reps && st == TDP_OK; ++r) st = run();
+    if (st == TDP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+      st = fail(g, TDP_E_DEVICE, "event wait failed");
+    if (st != TDP_OK) break;
+    int32_t err = 0;
+    if (hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost) != hipSuccess) {
+      st = fail(g, TDP_E_DEVICE, "status copy failed");
+      break;
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    ms /= (float)reps;
+    if (err == 0 && ms < best) {  // a sweep whose waits gave up does not qualify
+      best = ms;
+      best_c = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  g->sweep_mode = best_c.mode;
+  g->flow_waves = best_c.waves;
+  g->prof.on = prof;
+  if (st != TDP_OK) return st;
+  // leave the results of the chosen configuration behind
+  st = run();
+  if (st != TDP_OK) return st;
+  if (choice) {
+    choice[0] = best_c.mode;
+    choice[1] = best_c.waves;
+    choice[2] = std::isfinite(best) ? (int32_t)std::lround(best * 1000.0f) : -1;
+  }
   return TDP_OK;
 }
 

@@ -359,15 +359,14 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
       for (int c = 0; c < nls[i]->num_cells; ++c) H.cell_fixed[H.lv.cell_base[i] + c] = nls[i]->cell_fixed[c] ? 1 : 0;
 
   // ---------------------------------------------------------- 64-lane chunks
-  auto seg = [](int head, int tail) { return (int16_t)(head | (tail << 8)); };
+  auto seg = [](int head, int tail) { return head | (tail << 8); };
   // combinational inputs, cell by cell, one level after another
   {
     int64_t lane = 0;
     auto pad = [&]() {
       while (lane % CHUNK) {
         const int l = (int)(lane % CHUNK);
-        H.fw_t.push_back(-1);
-        H.fw_seg.push_back(seg(l, l));
+        H.fw_rec.push_back(make_int4(-1, 0, 0, seg(l, l)));
         ++lane;
       }
     };
@@ -379,8 +378,7 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
         if (lane % CHUNK + n > CHUNK) pad();
         const int head = (int)(lane % CHUNK);
         for (int t = H.comb_inptr[c]; t < H.comb_inptr[c + 1]; ++t) {
-          H.fw_t.push_back(t);
-          H.fw_seg.push_back(seg(head, head + n - 1));
+          H.fw_rec.push_back(make_int4(t, H.snk_drv[t], c, seg(head, head + n - 1) | (int)H.comb_type[c] << 16));
           ++lane;
         }
       }
@@ -395,11 +393,9 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
     auto pad = [&]() {
       while (lane % CHUNK) {
         const int l = (int)(lane % CHUNK);
-        H.nm_pin.push_back(-1);
-        H.nm_cell.push_back(-1);
+        H.nm_rec.push_back(make_int4(-1, -1, -1, seg(l, l)));
         H.nm_ox.push_back(0.f);
         H.nm_oy.push_back(0.f);
-        H.nm_seg.push_back(seg(l, l));
         ++lane;
       }
     };
@@ -416,19 +412,16 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
         }
         if (lane % CHUNK + n > CHUNK) pad();
         const int head = (int)(lane % CHUNK);
-        H.nm_pin.push_back(v);
-        H.nm_cell.push_back(H.drv_cell[v]);
+        H.nm_rec.push_back(make_int4(v, H.drv_cell[v], -1, seg(head, head + n - 1)));
         H.nm_ox.push_back(H.drv_ox[v]);
         H.nm_oy.push_back(H.drv_oy[v]);
-        H.nm_seg.push_back(seg(head, head + n - 1));
         ++lane;
         for (int k = H.net_ptr[v]; k < H.net_ptr[v + 1]; ++k) {
           const int t = H.net_sink[k];
-          H.nm_pin.push_back(T.M + t);
-          H.nm_cell.push_back(H.snk_cell[t]);
+          const int vo = t < T.A ? T.n_start + H.snk_comb[t] : -1;
+          H.nm_rec.push_back(make_int4(T.M + t, H.snk_cell[t], vo, seg(head, head + n - 1)));
           H.nm_ox.push_back(H.snk_ox[t]);
           H.nm_oy.push_back(H.snk_oy[t]);
-          H.nm_seg.push_back(seg(head, head + n - 1));
           ++lane;
         }
       }

@@ -87,19 +87,20 @@ struct Topo {
   int32_t *cell_int = nullptr;     // [N] external cell -> comb index, or -(ff index)-1
   uint8_t *cell_fixed = nullptr;   // [N]
   // 64-lane chunks of combinational inputs: a cell's inputs never straddle a
-  // chunk; chunks are level-pure.  fw_t = sink id (-1 = padding lane),
-  // fw_seg = head lane | tail lane << 8 of the lane's cell.
+  // chunk; chunks are level-pure.  One record per lane: {sink t (-1 =
+  // padding), its driver, its combinational cell, head lane | tail lane << 8 |
+  // cell type << 16}, so a lane finds everything static in one load.
   int32_t n_fw_chunks = 0;
-  int32_t *fw_t = nullptr;
-  int16_t *fw_seg = nullptr;
+  int4 *fw_rec = nullptr;
   // 64-lane chunks of nets (driver lane first, then its sinks); a net never
   // straddles a chunk; chunks are level-pure by driver level.  Nets with more
   // than 63 sinks are "big" and handled one thread per net.
+  // One record per lane: {internal pin (driver v or M + t; -1 = padding),
+  // external cell (-1 for a port or padding), for a combinational-input sink
+  // the output driver of its cell (else -1), head lane | tail lane << 8}.
   int32_t n_nm_chunks = 0, n_big = 0;
-  int32_t *nm_pin = nullptr;     // internal pin (driver v or M + t), -1 = padding
-  int32_t *nm_cell = nullptr;    // external cell, -1 for a port or padding
+  int4 *nm_rec = nullptr;
   float *nm_ox = nullptr, *nm_oy = nullptr;
-  int16_t *nm_seg = nullptr;
   int32_t *big_net = nullptr;    // [n_big] drivers of big nets, level-major
 };
 
@@ -123,8 +124,8 @@ struct HostTopo {
       comb_inptr, comb_ext, ff_ext, ff_inst, ext_pin_int, cell_int;
   std::vector<float> drv_ox, drv_oy, snk_ox, snk_oy;
   std::vector<double> net_cpin;
-  std::vector<int32_t> fw_t, nm_pin, nm_cell, big_net;
-  std::vector<int16_t> fw_seg, nm_seg;
+  std::vector<int4> fw_rec, nm_rec;
+  std::vector<int32_t> big_net;
   std::vector<float> nm_ox, nm_oy;
   std::vector<uint8_t> comb_type, ff_type, cell_fixed;
 };
@@ -161,7 +162,7 @@ struct tdp_graph_s {
   std::vector<void *> allocs;  // every device allocation, freed at destroy
   std::vector<int32_t> h_snk_ext;  // host copy: external pin of each sink
   int32_t *d_err = nullptr;    // device flag for internal consistency errors
-  float *consts = nullptr;     // [4] device constants: {1, 0, 0, 0}
+  double *consts = nullptr;    // [4] device constants: {1, 0, 0, 0}
 
   // timing state (element type per precision)
   void *load = nullptr, *dnet = nullptr, *at = nullptr, *slew = nullptr, *rat = nullptr,
@@ -178,7 +179,7 @@ struct tdp_graph_s {
   uint32_t *flow_cd = nullptr;   // [M] chain depth + 1 of a driver; 0 = not yet
   uint64_t *flow_se = nullptr;   // [n_comb][side_k] deviation entries {cost, sink}; all ones = not yet
   int32_t *tickets = nullptr;    // [4] work counters of the persistent sweeps
-  int32_t flow_blocks = 0, spin_limit = 1 << 20;
+  int32_t flow_waves = 4, spin_limit = 1 << 20;
   bool flow_ok = false;          // the graph can use the dataflow sweeps
   double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;
   double *summary = nullptr;     // [4 * num_inst]: wns, tns, n_fail, 0
@@ -221,6 +222,7 @@ struct tdp_graph_s {
 
   // weighted-average wirelength: per-pin gradient [2P]
   float *wa_gpin = nullptr;
+  float2 *xy = nullptr;        // [N] positions packed by the update and WA calls
 
   tdp::Profiler prof;
 };

@@ -265,6 +265,8 @@ __global__ void k_inc_sort(const int32_t *__restrict__ d_ntouched, const int32_t
 // ------------------------------------------------------------------ loss
 constexpr int LOSS_BLOCKS = 512;
 
+// each pair's term in the graph's precision T, summed in double
+template <typename T>
 __global__ void __launch_bounds__(256) k_p2p_fwd(const int32_t *__restrict__ d_npairs,
                                                   const int32_t *__restrict__ pair_cs,
                                                   const int32_t *__restrict__ pair_ct,
@@ -277,10 +279,10 @@ __global__ void __launch_bounds__(256) k_p2p_fwd(const int32_t *__restrict__ d_n
   double acc = 0.0;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
     const int cs = pair_cs[q], ct = pair_ct[q];
-    const float xs = cs >= 0 ? x[cs] : 0.f, ys = cs >= 0 ? y[cs] : 0.f;
-    const float dx = xs - x[ct] + pair_dox[q];
-    const float dy = ys - y[ct] + pair_doy[q];
-    acc += (double)(pair_w[q] * (dx * dx + dy * dy));
+    const T xs = cs >= 0 ? (T)x[cs] : (T)0, ys = cs >= 0 ? (T)y[cs] : (T)0;
+    const T dx = xs - (T)x[ct] + (T)pair_dox[q];
+    const T dy = ys - (T)y[ct] + (T)pair_doy[q];
+    acc += (double)((T)pair_w[q] * (dx * dx + dy * dy));
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -291,8 +293,7 @@ __global__ void __launch_bounds__(256) k_p2p_fwd(const int32_t *__restrict__ d_n
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void __launch_bounds__(256) k_sum_parts(int n, const double *__restrict__ part, float *__restrict__ out,
-                                                    double *__restrict__ out64) {
+__global__ void __launch_bounds__(256) k_sum_parts(int n, const double *__restrict__ part, double *__restrict__ out) {
   __shared__ double sh[256];
   double a = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) a += part[i];
@@ -302,35 +303,33 @@ __global__ void __launch_bounds__(256) k_sum_parts(int n, const double *__restri
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    if (out) *out = (float)sh[0];
-    if (out64) *out64 = sh[0];
-  }
+  if (threadIdx.x == 0) *out = sh[0];
 }
 
+template <typename T>
 __global__ void __launch_bounds__(256) k_p2p_bwd(const int32_t *__restrict__ d_ntouched,
                                                   const int32_t *__restrict__ touched,
                                                   const int32_t *__restrict__ cell_ptr,
                                                   const int32_t *__restrict__ inc_other,
                                                   const float *__restrict__ inc_dx, const float *__restrict__ inc_dy,
                                                   const float *__restrict__ inc_w, const float *__restrict__ x,
-                                                  const float *__restrict__ y, const float *__restrict__ gout,
+                                                  const float *__restrict__ y, const double *__restrict__ gout,
                                                   float *__restrict__ gx, float *__restrict__ gy) {
   const int n = *d_ntouched;
-  const float g = *gout;
+  const T g = (T)*gout;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int c = touched[i];
-    const float xc = x[c], yc = y[c];
-    float ax = 0.f, ay = 0.f;
+    const T xc = (T)x[c], yc = (T)y[c];
+    T ax = 0, ay = 0;
     for (int a = cell_ptr[c]; a < cell_ptr[c + 1]; ++a) {
       const int o = inc_other[a];
-      const float xo = o >= 0 ? x[o] : 0.f, yo = o >= 0 ? y[o] : 0.f;
-      const float w2 = 2.f * inc_w[a];
-      ax += w2 * (xc - xo + inc_dx[a]);
-      ay += w2 * (yc - yo + inc_dy[a]);
+      const T xo = o >= 0 ? (T)x[o] : (T)0, yo = o >= 0 ? (T)y[o] : (T)0;
+      const T w2 = (T)2 * (T)inc_w[a];
+      ax += w2 * (xc - xo + (T)inc_dx[a]);
+      ay += w2 * (yc - yo + (T)inc_dy[a]);
     }
-    gx[c] += g * ax;
-    gy[c] += g * ay;
+    gx[c] += (float)(g * ax);
+    gy[c] += (float)(g * ay);
   }
 }
 
@@ -388,23 +387,31 @@ void pairs_compact(tdp_graph g, hipStream_t s) {
   g->pairs_built = true;
 }
 
-void p2p_fwd_impl(tdp_graph g, const float *x, const float *y, float *loss, hipStream_t s) {
+template <typename T>
+void p2p_fwd_impl(tdp_graph g, const float *x, const float *y, double *loss, hipStream_t s) {
   prof_begin(g, TDP_STAGE_P2P_FWD, s);
-  hipLaunchKernelGGL(k_p2p_fwd, dim3(LOSS_BLOCKS), dim3(256), 0, s, g->d_npairs, g->pair_cs, g->pair_ct, g->pair_dox,
+  hipLaunchKernelGGL(k_p2p_fwd<T>, dim3(LOSS_BLOCKS), dim3(256), 0, s, g->d_npairs, g->pair_cs, g->pair_ct, g->pair_dox,
                      g->pair_doy, g->pair_w, x, y, g->red_loss);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, LOSS_BLOCKS, g->red_loss, loss, (double *)nullptr);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, LOSS_BLOCKS, g->red_loss, loss);
   prof_end(g, TDP_STAGE_P2P_FWD, s);
 }
 
-void p2p_bwd_impl(tdp_graph g, const float *x, const float *y, const float *gout, float *gx, float *gy,
+template <typename T>
+void p2p_bwd_impl(tdp_graph g, const float *x, const float *y, const double *gout, float *gx, float *gy,
                   hipStream_t s) {
   prof_begin(g, TDP_STAGE_P2P_BWD, s);
-  hipLaunchKernelGGL(k_p2p_bwd, dim3(LOSS_BLOCKS * 2), dim3(256), 0, s, g->d_ntouched, g->touched, g->cell_ptr,
+  hipLaunchKernelGGL(k_p2p_bwd<T>, dim3(LOSS_BLOCKS * 2), dim3(256), 0, s, g->d_ntouched, g->touched, g->cell_ptr,
                      g->inc_other, g->inc_dx, g->inc_dy, g->inc_w, x, y, gout, gx, gy);
   prof_end(g, TDP_STAGE_P2P_BWD, s);
 }
 
 template void pairs_update_impl<float>(tdp_graph, int, float, float, hipStream_t);
 template void pairs_update_impl<double>(tdp_graph, int, float, float, hipStream_t);
+template void p2p_fwd_impl<float>(tdp_graph, const float *, const float *, double *, hipStream_t);
+template void p2p_fwd_impl<double>(tdp_graph, const float *, const float *, double *, hipStream_t);
+template void p2p_bwd_impl<float>(tdp_graph, const float *, const float *, const double *, float *, float *,
+                                  hipStream_t);
+template void p2p_bwd_impl<double>(tdp_graph, const float *, const float *, const double *, float *, float *,
+                                   hipStream_t);
 
 }  // namespace tdp

@@ -206,6 +206,15 @@ void radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int cap,
   }
 }
 
+// ------------------------------------------------------ packed positions
+__global__ void k_pack_xy(const float *__restrict__ x, const float *__restrict__ y, float2 *__restrict__ xy, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) xy[i] = make_float2(x[i], y[i]);
+}
+void pack_xy(const float *x, const float *y, float2 *xy, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_pack_xy, dim3((n + 255) / 256), dim3(256), 0, s, x, y, xy, n);
+}
+
 // ---------------------------------------------------------- small fills
 __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;

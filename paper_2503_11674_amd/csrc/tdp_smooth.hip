@@ -19,6 +19,7 @@
 // sum x e^{x/g} / sum e^{x/g} - sum x e^{-x/g} / sum e^{-x/g}, with the
 // exponents shifted by the net's max and min.
 #include "tdp_impl.h"
+#include "tdp_prims.h"
 #include "tdp_wave.h"
 
 namespace tdp {
@@ -36,12 +37,13 @@ __global__ void k_st_net(Topo tp, const float *__restrict__ x, const float *__re
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= tp.M) return;
   const int dc = tp.drv_cell[v];
-  const T xs = (dc >= 0 ? (T)x[dc] : (T)0) + (T)tp.drv_ox[v];
-  const T ys = (dc >= 0 ? (T)y[dc] : (T)0) + (T)tp.drv_oy[v];
+  // (cell - cell) + (offset - offset): see the net pass
+  const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
+  const T ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
   for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
     const int t = tp.net_sink[k];
     const int sc = tp.snk_cell[t];
-    const T len = fabs(xs - ((T)x[sc] + (T)tp.snk_ox[t])) + fabs(ys - ((T)y[sc] + (T)tp.snk_oy[t]));
+    const T len = fabs((cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t])) + fabs((cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]));
     dnl[t] = kappa * len * len;
   }
 }
@@ -112,7 +114,7 @@ __global__ void __launch_bounds__(256) k_st_bwd(Topo tp, int c0, int c1, T gam, 
 // gradient per cell: its output pin's net arcs and its input pins' net arcs
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
-                                                  T kappa, const T *__restrict__ adj, const float *__restrict__ gout,
+                                                  T kappa, const T *__restrict__ adj, const double *__restrict__ gout,
                                                   float *__restrict__ gx, float *__restrict__ gy) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= tp.N || tp.cell_fixed[cell]) return;
@@ -130,11 +132,11 @@ __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restric
   }
   T ax = 0, ay = 0;
   {  // this cell drives the net of v
-    const T xs = (T)x[cell] + (T)tp.drv_ox[v], ys = (T)y[cell] + (T)tp.drv_oy[v];
+    const T cx = (T)x[cell], cy = (T)y[cell], ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
     for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
       const int t = tp.net_sink[k];
       const int sc = tp.snk_cell[t];
-      const T dx = xs - ((T)x[sc] + (T)tp.snk_ox[t]), dy = ys - ((T)y[sc] + (T)tp.snk_oy[t]);
+      const T dx = (cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t]), dy = (cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]);
       const T g = adj[tp.M + t] * (T)2 * kappa * (fabs(dx) + fabs(dy));
       ax += g * sgn(dx);
       ay += g * sgn(dy);
@@ -143,18 +145,19 @@ __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restric
   for (int t = t0; t < t1; ++t) {  // this cell's input pins are sinks
     const int s = tp.snk_drv[t];
     const int dc = tp.drv_cell[s];
-    const T xs = (dc >= 0 ? (T)x[dc] : (T)0) + (T)tp.drv_ox[s], ys = (dc >= 0 ? (T)y[dc] : (T)0) + (T)tp.drv_oy[s];
-    const T dx = xs - ((T)x[cell] + (T)tp.snk_ox[t]), dy = ys - ((T)y[cell] + (T)tp.snk_oy[t]);
+    const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
+    const T dx = (cx - (T)x[cell]) + ((T)tp.drv_ox[s] - (T)tp.snk_ox[t]);
+    const T dy = (cy - (T)y[cell]) + ((T)tp.drv_oy[s] - (T)tp.snk_oy[t]);
     const T g = adj[tp.M + t] * (T)2 * kappa * (fabs(dx) + fabs(dy));
     ax -= g * sgn(dx);
     ay -= g * sgn(dy);
   }
-  const float go = *gout;
-  gx[cell] += go * (float)ax;
-  gy[cell] += go * (float)ay;
+  const T go = (T)*gout;
+  gx[cell] += (float)(go * ax);
+  gy[cell] += (float)(go * ay);
 }
 
-__global__ void __launch_bounds__(256) k_sum_parts2(int n, const double *__restrict__ part, float *__restrict__ out) {
+__global__ void __launch_bounds__(256) k_sum_parts2(int n, const double *__restrict__ part, double *__restrict__ out) {
   __shared__ double sh[256];
   double a = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) a += part[i];
@@ -164,13 +167,13 @@ __global__ void __launch_bounds__(256) k_sum_parts2(int n, const double *__restr
     if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = (float)sh[0];
+  if (threadIdx.x == 0) *out = sh[0];
 }
 
 constexpr int RED_BLOCKS = 512;
 
 template <typename T>
-void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, float *val, hipStream_t s) {
+void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, double *val, hipStream_t s) {
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_STNS, s);
   const T kappa = (T)g->scale * (T)g->r * (T)g->c;
@@ -197,7 +200,7 @@ void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, flo
 }
 
 template <typename T>
-void stns_bwd_impl(tdp_graph g, const float *gout, float *gx, float *gy, hipStream_t s) {
+void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStream_t s) {
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_STNS, s);
   const T kappa = (T)g->scale * (T)g->r * (T)g->c;
@@ -243,22 +246,22 @@ __device__ __forceinline__ float wa_lane(float c, float o, bool valid, int lane,
 }
 
 // chunked nets: value partials and the gradient of each pin (internal pin order)
-__global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
-                                                 float gam, float *__restrict__ gpin, double *__restrict__ part) {
+__global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float2 *__restrict__ xy, float gam,
+                                                 float *__restrict__ gpin, double *__restrict__ part) {
   __shared__ double sh[256];
   double acc = 0.0;
   const float ig = 1.0f / gam;
   const int lane = wave_lane();
   for (int chunk = blockIdx.x * 4 + (threadIdx.x >> 6); chunk < tp.n_nm_chunks; chunk += gridDim.x * 4) {
     const int k = chunk * CHUNK + lane;
-    const int p = tp.nm_pin[k];
-    const int sg = tp.nm_seg[k];
-    const int head = sg & 63, tail = (sg >> 8) & 63;
-    const int cell = tp.nm_cell[k];
+    const int4 rec = tp.nm_rec[k];
+    const int p = rec.x, cell = rec.y;
+    const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
     const bool valid = p >= 0;
     float gxp, gyp;
-    const float wx = wa_lane(cell >= 0 ? x[cell] : 0.f, tp.nm_ox[k], valid, lane, head, tail, ig, gxp);
-    const float wy = wa_lane(cell >= 0 ? y[cell] : 0.f, tp.nm_oy[k], valid, lane, head, tail, ig, gyp);
+    const float2 q = cell >= 0 ? xy[cell] : make_float2(0.f, 0.f);
+    const float wx = wa_lane(q.x, tp.nm_ox[k], valid, lane, head, tail, ig, gxp);
+    const float wy = wa_lane(q.y, tp.nm_oy[k], valid, lane, head, tail, ig, gyp);
     if (valid) {
       gpin[2 * p] = gxp;
       gpin[2 * p + 1] = gyp;
@@ -348,21 +351,22 @@ __global__ void __launch_bounds__(256) k_wa_cell(Topo tp, const float *__restric
   gy[cell] += ay;
 }
 
-void wa_impl(tdp_graph g, const float *x, const float *y, float gamma, float *wl, float *gx, float *gy,
+void wa_impl(tdp_graph g, const float *x, const float *y, float gamma, double *wl, float *gx, float *gy,
              hipStream_t s) {
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_WA, s);
   constexpr int WB = RED_BLOCKS * 4, BB = 64;  // partial slots: chunked nets, then big nets
-  hipLaunchKernelGGL(k_wa_net, dim3(WB), dim3(256), 0, s, tp, x, y, gamma, g->wa_gpin, g->red_wa);
+  pack_xy(x, y, g->xy, tp.N, s);
+  hipLaunchKernelGGL(k_wa_net, dim3(WB), dim3(256), 0, s, tp, g->xy, gamma, g->wa_gpin, g->red_wa);
   hipLaunchKernelGGL(k_wa_big, dim3(BB), dim3(64), 0, s, tp, x, y, gamma, g->wa_gpin, g->red_wa + WB);
   hipLaunchKernelGGL(k_sum_parts2, dim3(1), dim3(256), 0, s, WB + BB, g->red_wa, wl);
   hipLaunchKernelGGL(k_wa_cell, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->wa_gpin, gx, gy);
   prof_end(g, TDP_STAGE_WA, s);
 }
 
-template void stns_fwd_impl<float>(tdp_graph, const float *, const float *, float, float *, hipStream_t);
-template void stns_fwd_impl<double>(tdp_graph, const float *, const float *, float, float *, hipStream_t);
-template void stns_bwd_impl<float>(tdp_graph, const float *, float *, float *, hipStream_t);
-template void stns_bwd_impl<double>(tdp_graph, const float *, float *, float *, hipStream_t);
+template void stns_fwd_impl<float>(tdp_graph, const float *, const float *, float, double *, hipStream_t);
+template void stns_fwd_impl<double>(tdp_graph, const float *, const float *, float, double *, hipStream_t);
+template void stns_bwd_impl<float>(tdp_graph, const double *, float *, float *, hipStream_t);
+template void stns_bwd_impl<double>(tdp_graph, const double *, float *, float *, hipStream_t);
 
 }  // namespace tdp

@@ -23,6 +23,7 @@
 // Tables live in LDS for the forward sweep.  Nets with more than 63 sinks
 // take a one-thread-per-net path.
 #include "tdp_impl.h"
+#include "tdp_prims.h"
 #include "tdp_wave.h"
 
 namespace tdp {
@@ -63,23 +64,33 @@ __device__ __forceinline__ uint64_t pack2(float lo, float hi) {
   return (uint64_t)__float_as_uint(lo) | ((uint64_t)__float_as_uint(hi) << 32);
 }
 
-// Poll *p until it differs from `empty`.  The wait is bounded: after `limit`
-// polls (or once another wave has given up) it sets bit 2 of *err and returns
-// `empty`, so every wave always finishes.
+// Poll *p until it differs from `empty`, backing off from one to eight
+// sleeps between polls.  The wait is bounded: after `limit` polls (or once
+// another wave has given up) it sets bit 2 of *err and returns `empty`, so
+// every wave always finishes.
 template <typename U>
 __device__ __forceinline__ U wait_pub(const U *p, U empty, int32_t *err, int limit) {
   U v = pub_ld(p);
-  int it = 0;
+  int it = 0, nap = 1;
   while (v == empty) {
     if (++it > limit) {
       atomicOr(err, 2);
       break;
     }
     if ((it & 31) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-    __builtin_amdgcn_s_sleep(1);
+    for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
+    nap = nap < 8 ? 2 * nap : 8;
     v = pub_ld(p);
   }
   return v;
+}
+
+// A wave first waits on one representative word with its lane 0 alone (the
+// word its chunk is likely to see published last), so that a waiting wave
+// polls one address rather than 64; every lane then checks its own word.
+template <typename U>
+__device__ __forceinline__ void wait_rep(const U *p, U empty, int32_t *err, int limit) {
+  if (wave_lane() == 0) (void)wait_pub(p, empty, err, limit);
 }
 
 struct FlowInit {
@@ -119,8 +130,8 @@ __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, in
 
 // ------------------------------------------------------------- net pass
 template <typename T>
-__global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float *__restrict__ x,
-                                                  const float *__restrict__ y, T kappa, T cw, T in_slew,
+__global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, T kappa,
+                                                  T cw, T in_slew,
                                                   T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
                                                   T *__restrict__ at, T *__restrict__ slew,
                                                   int32_t *__restrict__ cdep, FlowInit fl) {
@@ -130,15 +141,19 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
   const int k = chunk * CHUNK + lane;
-  const int p = tp.nm_pin[k];
-  const int sg = tp.nm_seg[k];
-  const int head = sg & 63, tail = (sg >> 8) & 63;
-  const int cell = tp.nm_cell[k];
-  const T X = (cell >= 0 ? (T)x[cell] : (T)0) + (T)tp.nm_ox[k];
-  const T Y = (cell >= 0 ? (T)y[cell] : (T)0) + (T)tp.nm_oy[k];
-  const T Xd = __shfl(X, head, 64), Yd = __shfl(Y, head, 64);
+  const int4 rec = tp.nm_rec[k];
+  const int p = rec.x, cell = rec.y;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
+  // pin coordinate = cell coordinate + offset; differences are taken as
+  // (cell - cell) + (offset - offset), exact to the rounding of the result
+  // rather than of a die-scale sum
+  const float2 q = cell >= 0 ? xy[cell] : make_float2(0.f, 0.f);
+  const T cx = (T)q.x, cy = (T)q.y;
+  const T ox = (T)tp.nm_ox[k], oy = (T)tp.nm_oy[k];
+  const T cxd = __shfl(cx, head, 64), cyd = __shfl(cy, head, 64);
+  const T oxd = __shfl(ox, head, 64), oyd = __shfl(oy, head, 64);
   const bool sink = p >= 0 && lane != head;
-  const T len = sink ? fabs(Xd - X) + fabs(Yd - Y) : (T)0;
+  const T len = sink ? fabs((cxd - cx) + (oxd - ox)) + fabs((cyd - cy) + (oyd - oy)) : (T)0;
   if (sink) dnet[p - tp.M] = kappa * len * len;
   const T wl = seg_sum(len, lane, head, tail);
   if (p >= 0 && lane == head) {
@@ -157,13 +172,13 @@ __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, c
   if (i >= tp.n_big) return;
   const int v = tp.big_net[i];
   const int dc = tp.drv_cell[v];
-  const T xs = (dc >= 0 ? (T)x[dc] : (T)0) + (T)tp.drv_ox[v];
-  const T ys = (dc >= 0 ? (T)y[dc] : (T)0) + (T)tp.drv_oy[v];
+  const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
+  const T ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
   T wl = 0;
   for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
     const int t = tp.net_sink[k];
     const int sc = tp.snk_cell[t];
-    const T len = fabs(xs - ((T)x[sc] + (T)tp.snk_ox[t])) + fabs(ys - ((T)y[sc] + (T)tp.snk_oy[t]));
+    const T len = fabs((cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t])) + fabs((cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]));
     dnet[t] = kappa * len * len;
     wl += len;
   }
@@ -199,24 +214,23 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
                                                   int32_t *__restrict__ cdep, T *__restrict__ side_cost,
                                                   int32_t *__restrict__ side_pin) {
   extern __shared__ float s_lut[];
-  stage_lut(L, s_lut);
   const int lane = wave_lane();
   const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (chunk >= ch1) return;
   const int k = chunk * CHUNK + lane;
-  const int t = tp.fw_t[k];
-  const int sg = tp.fw_seg[k];
-  const int head = sg & 63, tail = (sg >> 8) & 63;
+  // the record load is issued before the tables are staged, so the two
+  // latencies overlap
+  const int4 rec = chunk < ch1 ? tp.fw_rec[k] : make_int4(-1, 0, 0, 0);
+  stage_lut(L, s_lut);
+  if (chunk >= ch1) return;
+  const int t = rec.x, s = rec.y, c = rec.z;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   const bool valid = t >= 0;
-  int c = 0, s = 0;
   T a = -pos_inf<T>(), o = 0;
   if (valid) {
-    c = tp.snk_comb[t];
-    s = tp.snk_drv[t];
     const T ld = load[tp.n_start + c];
     const T a_in = at[s] + dnet[t];
     T d;
-    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, tp.comb_type[c], slew[s], ld, d, o);
+    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, rec.w >> 16, slew[s], ld, d, o);
     at[tp.M + t] = a_in;
     darc[t] = d;
     a = a_in + d;
@@ -349,20 +363,25 @@ __global__ void k_ep_final(int num_inst, int chunks, const double *__restrict__ 
 }
 
 // ------------------------------------------------------------- backward
+// A net's pass gives each of its sinks its required time (a combinational
+// input: its cell output's minus the arc delay; a flip-flop D pin: set at the
+// endpoint) and slack, then its driver the minimum over the sinks of (sink
+// required time - net delay) and the driver's slack.
 template <typename T>
-__device__ __forceinline__ void give_inputs(const Topo &tp, int v, T r, const T *__restrict__ darc,
-                                            const T *__restrict__ at, T *__restrict__ rat, T *__restrict__ slack) {
-  const bool fin = r != pos_inf<T>();
+__device__ __forceinline__ T sink_required(int p, T r_out, T da, const T *__restrict__ at, T *__restrict__ rat,
+                                           T *__restrict__ slack) {
+  const bool fin = r_out != pos_inf<T>();
+  const T ri = fin ? r_out - da : pos_inf<T>();
+  rat[p] = ri;
+  slack[p] = fin ? ri - at[p] : pos_inf<T>();
+  return ri;
+}
+
+template <typename T>
+__device__ __forceinline__ void driver_required(int v, T r, const T *__restrict__ at, T *__restrict__ rat,
+                                                T *__restrict__ slack) {
   rat[v] = r;
-  slack[v] = fin ? r - at[v] : pos_inf<T>();
-  if (v < tp.n_start) return;
-  const int c = v - tp.n_start;
-  const int b = tp.comb_inptr[c], e = tp.comb_inptr[c + 1];
-  for (int t = b; t < e; ++t) {
-    const T ri = fin ? r - darc[t] : pos_inf<T>();
-    rat[tp.M + t] = ri;
-    slack[tp.M + t] = fin ? ri - at[tp.M + t] : pos_inf<T>();
-  }
+  slack[v] = r != pos_inf<T>() ? r - at[v] : pos_inf<T>();
 }
 
 template <typename T>
@@ -373,16 +392,17 @@ __global__ void __launch_bounds__(256) k_backward(Topo tp, int ch0, int ch1, con
   const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= ch1) return;
   const int k = chunk * CHUNK + lane;
-  const int p = tp.nm_pin[k];
-  const int sg = tp.nm_seg[k];
-  const int head = sg & 63, tail = (sg >> 8) & 63;
+  const int4 rec = tp.nm_rec[k];
+  const int p = rec.x, vo = rec.z;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   T r = pos_inf<T>();
   if (p >= 0 && lane != head) {
-    const T rt = rat[p];
-    if (rt != pos_inf<T>()) r = rt - dnet[p - tp.M];
+    const int t = p - tp.M;
+    const T rt = vo >= 0 ? sink_required<T>(p, rat[vo], darc[t], at, rat, slack) : rat[p];
+    if (rt != pos_inf<T>()) r = rt - dnet[t];
   }
   r = seg_min(r, lane, head, tail);
-  if (p >= 0 && lane == head) give_inputs<T>(tp, p, r, darc, at, rat, slack);
+  if (p >= 0 && lane == head) driver_required<T>(p, r, at, rat, slack);
 }
 
 template <typename T>
@@ -394,25 +414,40 @@ __global__ void k_backward_big(Topo tp, int i0, int i1, const T *__restrict__ dn
   T r = pos_inf<T>();
   for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
     const int t = tp.net_sink[k];
-    const T rt = rat[tp.M + t];
+    const int p = tp.M + t;
+    T rt;
+    if (t < tp.A) {
+      const int vo = tp.n_start + tp.snk_comb[t];
+      rt = sink_required<T>(p, rat[vo], darc[t], at, rat, slack);
+    } else {
+      rt = rat[p];
+    }
     if (rt == pos_inf<T>()) continue;
     const T q = rt - dnet[t];
     r = q < r ? q : r;
   }
-  give_inputs<T>(tp, v, r, darc, at, rat, slack);
+  driver_required<T>(v, r, at, rat, slack);
 }
 
 // ------------------------------------------------------ dataflow sweeps
-// One persistent launch per sweep.  Each wave takes the next 64-lane chunk
-// from a ticket counter (forward: level order; backward: reverse level
-// order), waits until the words it reads are published, computes exactly
-// what the per-level kernels compute, and publishes its own words.  A chunk
-// only waits on chunks with a smaller ticket, which running waves have
-// already taken, so the sweep always completes; every wait is also bounded.
+// One launch per sweep with one wave per 64-lane chunk, chunks in dependency
+// order by workgroup index (forward: level order; backward: reverse level
+// order).  A wave loads its chunk's static data, waits until the words it
+// reads are published, computes exactly what the per-level kernels compute,
+// and publishes its own words.  A chunk waits only on chunks with smaller
+// indices.  Workgroups are started in index order on each XCD, so the
+// smallest unfinished chunk is always resident and its inputs are complete:
+// the sweep completes.  (Handing chunks out from an atomic ticket counter
+// would not rely on the start order, but same-address atomics serialise at
+// about one per 16 ns, which costs more than the whole sweep.)  Every wait is
+// also bounded, so a broken assumption ends in a reported error, not a hang.
+// Waves waiting on the frontier overlap their static loads with its
+// progress, so the critical path is one publish-to-observe latency per level.
 //
 // Forward, phase 1: a lane polls its driver's {arrival, transition} word.
 // Phase 2 (head lanes, after the cell's word is out): the chain depth and the
-// deviation list follow the critical input, one polled word per entry.
+// deviation list follow the critical input, every entry its own word; all are
+// loaded at once and only the ones still empty are polled.
 template <int KM>
 __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const float *__restrict__ load,
                                                        const float *__restrict__ dnet, float *__restrict__ at,
@@ -424,26 +459,26 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
                                                        int32_t *__restrict__ ticket, int32_t *__restrict__ err,
                                                        int limit) {
   extern __shared__ float s_lut[];
-  stage_lut(L, s_lut);
   const int lane = wave_lane();
-  for (;;) {
-    int chunk = 0;
-    if (lane == 0) chunk = atomicAdd(ticket, 1);
-    chunk = __shfl(chunk, 0, 64);
-    if (chunk >= tp.n_fw_chunks) break;
-    const int k = chunk * CHUNK + lane;
-    const int t = tp.fw_t[k];
-    const int sg = tp.fw_seg[k];
-    const int head = sg & 63, tail = (sg >> 8) & 63;
+  const int chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int k = chunk * CHUNK + lane;
+  const int4 rec = chunk < tp.n_fw_chunks ? tp.fw_rec[k] : make_int4(-1, 0, 0, 0);
+  stage_lut(L, s_lut);
+  if (chunk >= tp.n_fw_chunks) return;
+  {
+    const int t = rec.x, s = rec.y, c = rec.z, ty = rec.w >> 16;
+    const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
     const bool valid = t >= 0;
-    int c = 0, s = 0;
     float a = -__builtin_huge_valf(), o = 0.f;
+    float ld = 0.f, dn = 0.f;
     if (valid) {
-      c = tp.snk_comb[t];
-      s = tp.snk_drv[t];
-      const float ld = load[tp.n_start + c];
-      const float dn = dnet[t];
-      const int ty = tp.comb_type[c];
+      ld = load[tp.n_start + c];
+      dn = dnet[t];
+    }
+    // drivers are numbered in production order: the highest one comes last
+    const int s_rep = wave_max_int(valid ? s : -1);
+    if (s_rep >= 0) wait_rep(&fw[s_rep], W_EMPTY, err, limit);
+    if (valid) {
       const uint64_t w = wait_pub(&fw[s], W_EMPTY, err, limit);
       const float a_in = __uint_as_float((uint32_t)w) + dn;
       float d;
@@ -455,8 +490,8 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
     const float best = seg_max(a, lane, head, tail);
     const float so = seg_max(o, lane, head, tail);
     // first input attaining the maximum (the head when none does, e.g. NaN)
-  const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
-  const int argl = arg0 <= tail ? arg0 : head;
+    const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
+    const int argl = arg0 <= tail ? arg0 : head;
     const int tc = __shfl(t, argl & 63, 64);
     const int pred = __shfl(s, argl & 63, 64);
     const bool is_head = valid && lane == head;
@@ -470,8 +505,18 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
     }
     // phase 2: chain depth (+1 in the published word) and deviation list
     uint32_t cdp = 0;
+    uint64_t pe[KM > 1 ? KM : 1];
+    const bool chain = is_head && pred >= tp.n_start;
+    const int p_rep = wave_max_int(chain ? pred : -1);
+    if (p_rep >= 0) wait_rep(&fcd[p_rep], 0u, err, limit);
     if (is_head) {
-      cdp = wait_pub(&fcd[pred], 0u, err, limit);
+      cdp = pub_ld(&fcd[pred]);
+      if constexpr (KM > 1) {
+        const size_t pb = (size_t)(pred - tp.n_start) * KM;
+#pragma unroll
+        for (int j = 0; j < KM; ++j) pe[j] = chain ? pub_ld(&fse[pb + j]) : W_EMPTY;
+      }
+      if (cdp == 0u) cdp = wait_pub(&fcd[pred], 0u, err, limit);
       cdep[v] = (int32_t)cdp;
     }
     if constexpr (KM > 1) {
@@ -484,11 +529,11 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
         kc[j] = __builtin_huge_valf();
         kp[j] = -1;
       }
-      if (is_head && pred >= tp.n_start) {
+      if (chain) {
         const size_t pb = (size_t)(pred - tp.n_start) * KM;
 #pragma unroll
         for (int j = 0; j < KM; ++j) {
-          const uint64_t e = wait_pub(&fse[pb + j], W_EMPTY, err, limit);
+          const uint64_t e = pe[j] != W_EMPTY ? pe[j] : wait_pub(&fse[pb + j], W_EMPTY, err, limit);
           kc[j] = __uint_as_float((uint32_t)e);
           kp[j] = (int32_t)(uint32_t)(e >> 32);
         }
@@ -522,30 +567,34 @@ __global__ void __launch_bounds__(256) k_backward_flow(Topo tp, float req, const
                                                         int32_t *__restrict__ err, int limit) {
   const int lane = wave_lane();
   const float inf = __builtin_huge_valf();
-  for (;;) {
-    int q = 0;
-    if (lane == 0) q = atomicAdd(ticket, 1);
-    q = __shfl(q, 0, 64);
-    if (q >= tp.n_nm_chunks) break;
+  const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (q >= tp.n_nm_chunks) return;
+  {
     const int chunk = tp.n_nm_chunks - 1 - q;
     const int k = chunk * CHUNK + lane;
-    const int p = tp.nm_pin[k];
-    const int sg = tp.nm_seg[k];
-    const int head = sg & 63, tail = (sg >> 8) & 63;
+    const int4 rec = tp.nm_rec[k];
+    const int p = rec.x, vo = rec.z;
+    const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
+    const bool sink = p >= 0 && lane != head;
+    const int t = p - tp.M;
+    const bool comb_in = sink && vo >= 0;
+    // static data first, then the wave's representative: outputs are numbered
+    // in production order of the forward sweep, so the backward sweep
+    // publishes the lowest one last
+    const float dn = sink ? dnet[t] : 0.f, da = comb_in ? darc[t] : 0.f;
+    const int v_rep = -wave_max_int(comb_in ? -vo : 1);
+    if (v_rep >= 0) wait_rep(&fr[v_rep], R_EMPTY, err, limit);
     float r = inf;
-    if (p >= 0 && lane != head) {
-      const int t = p - tp.M;
-      float rt = req;
-      if (t < tp.A) {
-        const uint32_t ro = wait_pub(&fr[tp.n_start + tp.snk_comb[t]], R_EMPTY, err, limit);
-        const float r_out = __uint_as_float(ro);
-        rt = r_out != inf ? r_out - darc[t] : inf;
-      }
-      if (rt != inf) r = rt - dnet[t];
+    if (sink) {
+      // a flip-flop D pin's required time was set at the endpoint
+      const float rt = comb_in ? sink_required<float>(p, __uint_as_float(wait_pub(&fr[vo], R_EMPTY, err, limit)),
+                                                      da, at, rat, slack)
+                               : req;
+      if (rt != inf) r = rt - dn;
     }
     r = seg_min(r, lane, head, tail);
     if (p >= 0 && lane == head) {
-      give_inputs<float>(tp, p, r, darc, at, rat, slack);
+      driver_required<float>(p, r, at, rat, slack);
       pub_st(&fr[p], __float_as_uint(r));
     }
   }
@@ -610,7 +659,8 @@ static void forward_level(tdp_graph g, int ch0, int ch1, hipStream_t s) {
 template <int KM>
 static void launch_forward_flow(tdp_graph g, hipStream_t s) {
   const Topo &tp = g->topo;
-  hipLaunchKernelGGL((k_forward_flow<KM>), dim3(g->flow_blocks), dim3(256), lut_bytes(g->lut), s, tp, g->lut,
+  const int w = g->flow_waves;
+  hipLaunchKernelGGL((k_forward_flow<KM>), dim3(nblk(tp.n_fw_chunks, w)), dim3(64 * w), lut_bytes(g->lut), s, tp, g->lut,
                      (const float *)g->load, (const float *)g->dnet, (float *)g->at, (float *)g->slew,
                      (float *)g->darc, g->crit, (int4 *)g->hop, g->cdep, (float *)g->side_cost, g->side_pin,
                      g->flow_w, g->flow_cd, g->flow_se, g->tickets, g->d_err, g->spin_limit);
@@ -644,7 +694,8 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
     fl.seed = g->sweep_mode == 2 ? 0 : 1;
   }
   prof_begin(g, TDP_STAGE_NETPASS, s);
-  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, x, y, kappa,
+  pack_xy(x, y, g->xy, tp.N, s);
+  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, kappa,
                      (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
                      (T *)g->slew, g->cdep, fl);
   if (tp.n_big > 0)
@@ -674,7 +725,9 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
   prof_end(g, TDP_STAGE_ENDPOINT, s);
   prof_begin(g, TDP_STAGE_BACKWARD, s);
   if (flow) {
-    hipLaunchKernelGGL(k_backward_flow, dim3(g->flow_blocks), dim3(256), 0, s, tp, (float)req, (const float *)g->dnet,
+    const int w = g->flow_waves;
+    hipLaunchKernelGGL(k_backward_flow, dim3(nblk(tp.n_nm_chunks, w)), dim3(64 * w), 0, s, tp, (float)req,
+                       (const float *)g->dnet,
                        (const float *)g->darc, (const float *)g->at, (float *)g->rat, (float *)g->slack, g->flow_r,
                        g->tickets + 1, g->d_err, g->spin_limit);
     prof_end(g, TDP_STAGE_BACKWARD, s);

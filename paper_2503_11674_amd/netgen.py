@@ -91,6 +91,27 @@ def batch_configs() -> List[NetlistConfig]:
     return out
 
 
+# the snapshot netlist of the batch: 500k cells, depth 50, 8 jittered copies
+SNAPSHOT_CONFIG = NetlistConfig("S500k", 500_000, depth=50, fanout_cap=32, die=5000.0, placement="gmm",
+                                seed=32, top_k_paths=5000)
+
+
+def batch_workload(num_snapshots: int = 8, sigma: float = 5.0,
+                   snapshot_cells: Optional[int] = None) -> List[Dict[str, np.ndarray]]:
+    """The batched workload: the 32 uneven netlists of batch_configs(), then
+    num_snapshots placement snapshots of one netlist (positions + N(0, sigma^2)
+    per snapshot; the snapshots share every other array with the first).
+    Clock periods are left to the caller."""
+    out = [make_netlist(c) for c in batch_configs()]
+    cfg = SNAPSHOT_CONFIG if snapshot_cells is None else scaled(SNAPSHOT_CONFIG, snapshot_cells)
+    base = make_netlist(cfg)
+    for i in range(num_snapshots):
+        snap = dict(base)
+        snap["x"], snap["y"] = jitter_positions(base, sigma, seed=1000 + i)
+        out.append(snap)
+    return out
+
+
 def scaled(cfg: NetlistConfig, num_cells: int, depth: Optional[int] = None,
            seed: Optional[int] = None) -> NetlistConfig:
     c = dataclasses.replace(cfg)

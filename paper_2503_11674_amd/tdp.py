@@ -91,6 +91,7 @@ tdp_wa_fwd_bwd = _sig("tdp_wa_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p)
 tdp_profile_enable = _sig("tdp_profile_enable", _p, _i32)
 tdp_profile_read = _sig("tdp_profile_read", _p, _p, _p)
 tdp_set_tuning = _sig("tdp_set_tuning", _p, _i32, _i32, _i32)
+tdp_autotune = _sig("tdp_autotune", _p, _p, _p, _i32, _i32, _i32, _i32, _p, _p)
 tdp_graph_info = _sig("tdp_graph_info", _p, _p)
 tdp_status_str = _lib.tdp_status_str
 tdp_status_str.restype = ctypes.c_char_p
@@ -104,7 +105,7 @@ EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destro
             "tdp_extract_paths", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd", "tdp_stns_fwd",
             "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
-            "tdp_graph_info", "tdp_status_str", "tdp_last_error"]
+            "tdp_autotune", "tdp_graph_info", "tdp_status_str", "tdp_last_error"]
 
 
 class TdpError(RuntimeError):
@@ -309,23 +310,24 @@ class TimingGraph:
 
     # ----------------------------------------------------------- losses
     def p2p_loss_fwd(self, x, y, out=None, stream=None) -> torch.Tensor:
-        out = torch.empty((), dtype=torch.float32, device=x.device) if out is None else out
+        out = _scalar_out(out, x.device)
         _check(tdp_p2p_loss_fwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _ptr(out), _stream(stream)), self.h)
         return out
 
     def p2p_loss_bwd(self, x, y, gout, gx, gy, stream=None):
-        _check(tdp_p2p_loss_bwd(self.h, _ptr(x), _ptr(y), _ptr(gout), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
+        _check(tdp_p2p_loss_bwd(self.h, _ptr(x), _ptr(y), _ptr(_f64_scalar(gout)), _ptr(gx), _ptr(gy),
+                                _stream(stream)), self.h)
 
     def stns_fwd(self, x, y, gamma: float = 10.0, out=None, stream=None) -> torch.Tensor:
-        out = torch.empty((), dtype=torch.float32, device=x.device) if out is None else out
+        out = _scalar_out(out, x.device)
         _check(tdp_stns_fwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _stream(stream)), self.h)
         return out
 
     def stns_bwd(self, gout, gx, gy, stream=None):
-        _check(tdp_stns_bwd(self.h, _ptr(gout), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
+        _check(tdp_stns_bwd(self.h, _ptr(_f64_scalar(gout)), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
 
     def wa_fwd_bwd(self, x, y, gamma: float, gx, gy, out=None, stream=None) -> torch.Tensor:
-        out = torch.empty((), dtype=torch.float32, device=x.device) if out is None else out
+        out = _scalar_out(out, x.device)
         _check(tdp_wa_fwd_bwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _ptr(gx), _ptr(gy),
                               _stream(stream)), self.h)
         return out
@@ -340,10 +342,38 @@ class TimingGraph:
         _check(tdp_profile_read(self.h, ms.ctypes.data, calls.ctypes.data), self.h)
         return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
 
-    def set_tuning(self, flow_blocks: int = 0, spin_log2: int = 0, sweep_mode: int = 1):
-        """sweep_mode 0: one launch per level; 1: persistent dataflow sweeps;
-        2: self-test of the dataflow sweeps' bounded waits."""
-        _check(tdp_set_tuning(self.h, flow_blocks, spin_log2, sweep_mode), self.h)
+    def set_tuning(self, flow_waves: int = 0, spin_log2: int = 0, sweep_mode: int = 1):
+        """sweep_mode 0: one launch per level; 1: dataflow sweeps; 2: self-test
+        of the dataflow sweeps' bounded waits.  flow_waves: waves per workgroup
+        of the dataflow sweeps (1, 2, 4; 0 keeps)."""
+        _check(tdp_set_tuning(self.h, flow_waves, spin_log2, sweep_mode), self.h)
+
+    def autotune(self, x, y, n: int = -1, k: int = 1, K: Optional[int] = None, reps: int = 3,
+                 stream=None) -> Dict[str, int]:
+        """Pick the fastest sweep configuration for update + extraction."""
+        K = self.max_paths if K is None else K
+        ch = np.zeros(3, np.int32)
+        _check(tdp_autotune(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), n, k, K, reps, ch.ctypes.data,
+                            _stream(stream)), self.h)
+        return {"sweep_mode": int(ch[0]), "flow_waves": int(ch[1]), "us_per_run": int(ch[2])}
+
+
+def _scalar_out(out, device) -> torch.Tensor:
+    """Loss values are single device doubles."""
+    if out is None:
+        return torch.empty((), dtype=torch.float64, device=device)
+    if out.dtype != torch.float64 or not out.is_cuda:
+        raise ValueError("loss output must be a float64 tensor on the GPU")
+    return out
+
+
+def _f64_scalar(t: torch.Tensor) -> torch.Tensor:
+    """Upstream gradients are single device doubles."""
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        t = t.to(torch.float64).contiguous()
+    if not t.is_cuda or t.numel() != 1:
+        raise ValueError("upstream gradient must be one value on the GPU")
+    return t
 
 
 def _copy_dev(dst: torch.Tensor, src_ptr: int, nbytes: int):
@@ -381,7 +411,7 @@ class P2PLoss(torch.autograd.Function):
         x, y = ctx.saved_tensors
         gx = torch.zeros_like(x)
         gy = torch.zeros_like(y)
-        ctx.graph.p2p_loss_bwd(x, y, gout.contiguous().float(), gx, gy)
+        ctx.graph.p2p_loss_bwd(x, y, gout, gx, gy)
         return gx, gy, None
 
 
@@ -399,5 +429,5 @@ class SmoothTNS(torch.autograd.Function):
         x, y = ctx.saved_tensors
         gx = torch.zeros_like(x)
         gy = torch.zeros_like(y)
-        ctx.graph.stns_bwd(gout.contiguous().float(), gx, gy)
+        ctx.graph.stns_bwd(gout, gx, gy)
         return gx, gy, None, None

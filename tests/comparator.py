@@ -95,3 +95,158 @@ def pairs_of(paths_dict, keys=None):
             continue
         out.update(pins[ptr[i] + 1:ptr[i + 1]:2].tolist())
     return out
+
+
+# ------------------------------------------------------------------
+# Vectorised forms for the full-size workloads (millions of path pins).
+def _segments(ptr):
+    """For a CSR pointer array: path index and position in the path of every
+    element."""
+    ptr = np.asarray(ptr, np.int64)
+    lens = np.diff(ptr)
+    pid = np.repeat(np.arange(lens.shape[0]), lens)
+    pos = np.arange(ptr[-1]) - ptr[pid]
+    return pid, pos, lens
+
+
+def arc_tables(nl):
+    """driver_of[sink pin], out_of[combinational input pin], is_start[pin],
+    is_end[pin] (-1 / False where not applicable)."""
+    P = int(nl["num_pins"])
+    net_ptr, net_pins = np.asarray(nl["net_ptr"]), np.asarray(nl["net_pins"])
+    driver_of = np.full(P, -1, np.int64)
+    nlen = np.diff(net_ptr)
+    drv = np.repeat(net_pins[net_ptr[:-1]], nlen)
+    first = np.zeros(net_pins.shape[0], bool)
+    first[net_ptr[:-1][nlen > 0]] = True
+    driver_of[net_pins[~first]] = drv[~first]
+    out_of = np.full(P, -1, np.int64)
+    ff = np.asarray(nl["cell_is_ff"]) != 0
+    cptr, cins = np.asarray(nl["cell_in_ptr"]), np.asarray(nl["cell_in_pins"])
+    clen = np.diff(cptr)
+    owner = np.repeat(np.arange(int(nl["num_cells"])), clen)
+    comb_in = ~ff[owner]
+    out_of[cins[comb_in]] = np.asarray(nl["cell_out_pin"])[owner[comb_in]]
+    is_start = np.asarray(nl["pin_cell"]) < 0
+    is_start[np.asarray(nl["cell_out_pin"])[ff]] = True
+    is_end = np.zeros(P, bool)
+    is_end[cins[ff[owner]]] = True
+    return driver_of, out_of, is_start, is_end
+
+
+def valid_paths(paths, tables):
+    """Per path: a start point, then alternately a net arc into a sink and a
+    cell arc to that cell's output, ending at its endpoint pin."""
+    driver_of, out_of, is_start, is_end = tables
+    pins = np.asarray(paths["path_pins"], np.int64)
+    ptr = np.asarray(paths["path_ptr"], np.int64)
+    m = int(paths["num_paths"])
+    if m == 0:
+        return np.zeros(0, bool)
+    pid, pos, lens = _segments(ptr)
+    ok = np.ones(pins.shape[0], bool)
+    odd = pos % 2 == 1
+    ok[odd] = driver_of[pins[odd]] == pins[np.nonzero(odd)[0] - 1]
+    ev = (pos % 2 == 0) & (pos > 0)
+    ok[ev] = out_of[pins[np.nonzero(ev)[0] - 1]] == pins[ev]
+    ok[pos == 0] = is_start[pins[pos == 0]]
+    good = np.ones(m, bool)
+    np.logical_and.at(good, pid, ok)
+    last = pins[ptr[1:] - 1]
+    good &= (lens % 2 == 0) & is_end[last] & (last == np.asarray(paths["path_ep"], np.int64))
+    return good
+
+
+def compare_paths_fast(gpu, ref, st, tables, k, fp32=True):
+    """compare_paths for large outputs.  Returns the same counts and the
+    boolean mask of pinned oracle paths that the GPU output also has (in the
+    oracle's output order)."""
+    m = int(ref["num_paths"])
+    at, rat = np.asarray(st["at"]), np.asarray(st["rat"])
+    r_ep = np.asarray(ref["path_ep"], np.int64)
+    r_rk = np.asarray(ref["path_rank"], np.int64)
+    r_sl = np.asarray(ref["path_slack"], np.float64)
+    r_ptr = np.asarray(ref["path_ptr"], np.int64)
+    r_pins = np.asarray(ref["path_pins"], np.int64)
+    key_r = r_ep * (k + 1) + r_rk
+    g_key = np.asarray(gpu["path_ep"], np.int64) * (k + 1) + np.asarray(gpu["path_rank"], np.int64)
+    # thresholds (module doc): rounding bound of each oracle path's slack
+    lens = np.diff(r_ptr)
+    if fp32:
+        d = np.abs(np.diff(at[r_pins])) if r_pins.shape[0] > 1 else np.zeros(0)
+        cs = np.concatenate([[0.0], np.cumsum(d)])
+        inner = cs[r_ptr[1:] - 1] - cs[r_ptr[:-1]]
+        terms = np.abs(at[r_pins[r_ptr[:-1]]]) + np.abs(rat[r_pins[r_ptr[1:] - 1]]) + inner
+        L = (lens - 1).astype(np.float64)
+        gam = L * U32 / (1 - L * U32)
+        thr = np.maximum(1e-3, 2.0 * gam * terms)
+    else:
+        thr = np.full(m, 1e-3)
+    # neighbours in (endpoint, rank) order
+    o = np.argsort(key_r, kind="stable")
+    ep_o, sl_o, rk_o = r_ep[o], r_sl[o], r_rk[o]
+    same_prev = np.zeros(m, bool)
+    same_prev[1:] = ep_o[1:] == ep_o[:-1]
+    same_next = np.zeros(m, bool)
+    same_next[:-1] = same_prev[1:]
+    nxt = dict(zip(np.asarray(ref["sel_ep"]).tolist(), np.asarray(ref["ep_next"]).tolist()))
+    cnt = np.bincount(np.searchsorted(np.unique(ep_o), ep_o))
+    count_of = np.repeat(cnt, cnt)
+    s_next = np.full(m, np.inf)
+    s_next[:-1] = np.where(same_next[:-1], sl_o[1:], np.inf)
+    tail = ~same_next & (count_of == k)
+    s_next[tail] = [nxt.get(int(e), np.inf) for e in ep_o[tail]]
+    s_prev = np.full(m, -np.inf)
+    s_prev[1:] = np.where(same_prev[1:], sl_o[:-1], -np.inf)
+    thr_o = thr[o]
+    lo = (rk_o == 0) | (sl_o - s_prev > thr_o)
+    hi = s_next - sl_o > thr_o
+    pinned_o = lo & hi
+    pinned = np.zeros(m, bool)
+    pinned[o] = pinned_o
+    # match GPU paths by key
+    g_sort = np.argsort(g_key, kind="stable")
+    pos = np.searchsorted(g_key[g_sort], key_r)
+    pos = np.minimum(pos, max(0, g_key.shape[0] - 1))
+    found = (g_key.shape[0] > 0) & (g_key[g_sort][pos] == key_r) if g_key.shape[0] else np.zeros(m, bool)
+    gi = g_sort[pos]
+    c = dict(missing=int((~found).sum()), extra=int((~np.isin(g_key, key_r)).sum()))
+    g_ptr = np.asarray(gpu["path_ptr"], np.int64)
+    g_pins = np.asarray(gpu["path_pins"], np.int64)
+    g_sl = np.asarray(gpu["path_slack"], np.float64)
+    last = r_pins[r_ptr[1:] - 1]
+    tol = 1e-4 * np.maximum(np.maximum(np.abs(at[last]), np.abs(rat[last])), 1.0)
+    slack_ok = found & (np.abs(g_sl[gi] - r_sl) <= tol)
+    # pin-for-pin equality for pinned paths of equal length
+    g_len = np.diff(g_ptr)[gi]
+    same_len = found & (g_len == lens)
+    cand = np.nonzero(pinned & same_len)[0]
+    eq = np.zeros(m, bool)
+    if cand.shape[0]:
+        ln = lens[cand]
+        seg = np.repeat(np.arange(cand.shape[0]), ln)
+        off = np.arange(ln.sum()) - np.repeat(np.cumsum(ln) - ln, ln)
+        a = r_pins[r_ptr[cand][seg] + off]
+        b = g_pins[g_ptr[gi[cand]][seg] + off]
+        bad = np.zeros(cand.shape[0], np.int64)
+        np.add.at(bad, seg, (a != b).astype(np.int64))
+        eq[cand] = bad == 0
+    gvalid = valid_paths(gpu, tables)
+    c["pinned"] = int((pinned & found).sum())
+    c["pinned_ok"] = int((pinned & eq & slack_ok).sum())
+    unp = ~pinned & found
+    c["unpinned"] = int(unp.sum())
+    c["unpinned_ok"] = int((unp & slack_ok & gvalid[gi]).sum())
+    c["gpu_valid"] = int(gvalid.sum())
+    return c, pinned & found
+
+
+def pair_sinks(paths, mask=None):
+    """Sink pins of the net arcs on the paths selected by mask (all if None),
+    one entry per occurrence."""
+    pid, pos, _ = _segments(paths["path_ptr"])
+    pins = np.asarray(paths["path_pins"], np.int64)
+    sel = pos % 2 == 1
+    if mask is not None:
+        sel &= np.asarray(mask)[pid]
+    return pins[sel]

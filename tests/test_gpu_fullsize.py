@@ -1,0 +1,285 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (single precision, persistent dataflow sweeps, one step =
+timing update, extraction, pair update, WA and p2p forward/backward).
+
+* 2M cells (depth 100, 12 % flip-flops, K = 100k paths): every pin's timing,
+  every path, the pair set and its weights, both losses and their gradients,
+  against the FP64 oracle on the same input (the oracle runs the whole size
+  in seconds).
+* 1M cells (depth 80, K = 50k, exponential pair weights): the two
+  differentiable objectives through torch.autograd against the oracle's
+  gradients and against central finite differences (h = 1e-3 um) of the
+  double-precision graph on 1,000 random cells.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ref  # noqa: E402
+from paper_2503_11674_amd import netgen  # noqa: E402
+from tests.comparator import arc_tables, compare_paths_fast, pair_sinks, timing_close  # noqa: E402
+from tests.conftest import with_clock  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _tdp():
+    from paper_2503_11674_amd import tdp
+    return tdp
+
+
+def _dev():
+    return torch.device("cuda", 0)
+
+
+def _log(msg):
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def _xy(nl):
+    return (torch.tensor(np.asarray(nl["x"], np.float32), device=_dev()),
+            torch.tensor(np.asarray(nl["y"], np.float32), device=_dev()))
+
+
+def _timing_checks(nl, st, o):
+    inf_ok, bad, worst = timing_close(o["at"], st["at"])
+    assert inf_ok and bad == 0, ("at", bad, worst)
+    scale = np.maximum(np.abs(np.where(np.isfinite(st["at"]), st["at"], 0)),
+                       np.abs(np.where(np.isfinite(st["rat"]), st["rat"], 0)))
+    scale = np.maximum(scale, abs(float(nl["clock_period"])))
+    for key in ("rat", "slack"):
+        inf_ok, bad, worst = timing_close(o[key], st[key], scale=scale)
+        _log(f"{key}: worst relative error {worst:.3g}")
+        assert inf_ok and bad == 0, (key, bad, worst)
+    for key in ("dnet", "load", "darc", "slew"):
+        inf_ok, bad, worst = timing_close(o[key], st[key], rtol=2e-5)
+        assert inf_ok and bad == 0, (key, bad, worst)
+
+
+def _pinned_pair_checks(nl, gp, rp, pinned_ref, w_gpu, in_gpu, w_ref, in_ref, rtol=1e-4):
+    """Pairs on pinned violating paths are in both sets; weights agree for
+    pairs that occur on pinned paths only."""
+    viol = rp["path_slack"] < 0
+    pinned_sinks = np.unique(pair_sinks(rp, pinned_ref & viol))
+    assert pinned_sinks.shape[0] > 0
+    assert in_gpu[pinned_sinks].all() and in_ref[pinned_sinks].all()
+    # occurrences on unpinned paths (either side) make a weight order-dependent
+    # in single precision: leave those pairs out
+    key_r = set(zip(rp["path_ep"][pinned_ref].tolist(), rp["path_rank"][pinned_ref].tolist()))
+    g_pinned = np.array([(int(e), int(r)) in key_r for e, r in zip(gp["path_ep"], gp["path_rank"])], bool)
+    loose = np.union1d(pair_sinks(rp, ~pinned_ref), pair_sinks(gp, ~g_pinned))
+    cmp = np.setdiff1d(pinned_sinks, loose)
+    assert cmp.shape[0] > 0.5 * pinned_sinks.shape[0]
+    np.testing.assert_allclose(w_gpu[cmp], w_ref[cmp], rtol=rtol)
+    return cmp
+
+
+def _p2p_abs_scale(nl, sinks, w):
+    """Per cell: sum of |dPP/dx| terms that reach it (vectorised)."""
+    driver_of = arc_tables(nl)[0]
+    pc = np.asarray(nl["pin_cell"])
+    px = np.where(pc >= 0, nl["x"][np.maximum(pc, 0)], 0) + nl["pin_off_x"]
+    py = np.where(pc >= 0, nl["y"][np.maximum(pc, 0)], 0) + nl["pin_off_y"]
+    s = driver_of[sinks]
+    m = 2 * np.asarray(w, np.float64) * (np.abs(px[s] - px[sinks]) + np.abs(py[s] - py[sinks]))
+    scale = np.zeros(int(nl["num_cells"]))
+    for q in (s, sinks):
+        ok = pc[q] >= 0
+        np.add.at(scale, pc[q][ok], m[ok])
+    return scale
+
+
+def test_full_size_step_2m_cells(library):
+    tdp = _tdp()
+    cfg = netgen.CONFIGS["C5"]
+    _log("generating the 2M-cell workload")
+    nl = with_clock(netgen.make_netlist(cfg), library)
+    st = ref.sta(nl, library)
+    K = cfg.top_k_paths
+    k = max(1, K // st["n_fail"])
+    _log(f"oracle timing done: n_fail={st['n_fail']} k={k}")
+    g = tdp.TimingGraph(nl, library, max_paths=K, max_k=k)
+    x, y = _xy(nl)
+    gx = torch.zeros_like(x)
+    gy = torch.zeros_like(y)
+    wl = torch.zeros((), dtype=torch.float64, device=_dev())
+    pp = torch.zeros((), dtype=torch.float64, device=_dev())
+    one = torch.ones((), dtype=torch.float64, device=_dev())
+
+    def step():
+        g.sta_update(x, y)
+        g.extract_paths(n=-1, k=k, K=K)
+        g.pairs_update(rule=0, w0=10.0, w1=0.2)
+        gx.zero_()
+        gy.zero_()
+        g.wa_fwd_bwd(x, y, 5.0, gx, gy, out=wl)
+        g.p2p_loss_fwd(x, y, out=pp)
+        g.p2p_loss_bwd(x, y, one, gx, gy)
+
+    step()
+    g.pairs_reset()
+    step()
+    torch.cuda.synchronize()
+    _log("GPU step done")
+    o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+    _timing_checks(nl, st, o)
+    wns, tns, nf = g.summary()
+    assert nf == st["n_fail"]
+    assert abs(wns - st["wns"]) <= 1e-4 * abs(st["wns"]) and abs(tns - st["tns"]) <= 1e-4 * abs(st["tns"])
+    # paths
+    gp = g.paths()
+    rp = ref.extract(nl, library, st, n=-1, k=k, K=K)
+    _log(f"oracle extraction done: {rp['num_paths']} paths")
+    assert gp["num_paths"] == rp["num_paths"] == min(K, st["n_fail"] * k)
+    c, pinned = compare_paths_fast(gp, rp, st, arc_tables(nl), k)
+    _log(f"paths: {c}")
+    assert c["missing"] == 0 and c["extra"] == 0 and c["gpu_valid"] == gp["num_paths"]
+    assert c["pinned_ok"] == c["pinned"] and c["unpinned_ok"] == c["unpinned"]
+    assert c["pinned"] > 0.9 * rp["num_paths"]
+    # at any size: the sorted path slacks agree element by element
+    tol = 1e-4 * max(abs(float(nl["clock_period"])), abs(st["wns"]))
+    assert np.all(np.abs(np.sort(gp["path_slack"]) - np.sort(rp["path_slack"])) <= tol)
+    # pairs (one Eq. 9 round)
+    w_gpu, in_gpu = g.pairs_export()
+    ps = ref.PairState(nl["num_pins"])
+    ref.pairs_update(ps, rp, st["wns"], rule=0)
+    _pinned_pair_checks(nl, gp, rp, pinned, w_gpu, in_gpu.astype(bool), ps.w, ps.in_p.astype(bool))
+    # losses on the GPU's own pair set
+    sinks = np.nonzero(in_gpu)[0]
+    l_ref, px_ref, py_ref = ref.p2p(nl, sinks, w_gpu[sinks].astype(np.float64))
+    assert abs(float(pp) - l_ref) <= 1e-4 * abs(l_ref)
+    v_wa, wx_ref, wy_ref, ax, ay = ref.wa(nl, 5.0, with_abs=True)
+    assert abs(float(wl) - v_wa) <= 1e-4 * abs(v_wa)
+    scale = _p2p_abs_scale(nl, sinks, w_gpu[sinks])
+    ex = np.abs(gx.cpu().numpy() - (wx_ref + px_ref))
+    ey = np.abs(gy.cpu().numpy() - (wy_ref + py_ref))
+    _log(f"gradient: worst scaled error {(ex / np.maximum(ax + scale, 1e-12)).max():.3g}")
+    assert np.all(ex <= 1e-4 * (ax + scale) + 1e-6)
+    assert np.all(ey <= 1e-4 * (ay + scale) + 1e-6)
+
+
+# ------------------------------------------------------------------ 1M cells
+_U64 = 2.0 ** -53
+
+
+def _central_fd(fwd, x, y, cells, axis, h=1e-3):
+    """Central differences of a scalar GPU objective at the given cells: the
+    perturbed coordinates are the single-precision values nearest to x +- h,
+    and the step is their exact difference."""
+    base = (x if axis == 0 else y)
+    v0 = base[cells].double().cpu().numpy()
+    plus = torch.tensor((v0 + h).astype(np.float32), device=_dev())
+    minus = torch.tensor((v0 - h).astype(np.float32), device=_dev())
+    out = torch.zeros((len(cells), 2), dtype=torch.float64, device=_dev())
+    work = base.clone()
+    xs = (work, y) if axis == 0 else (x, work)
+    for i, c in enumerate(cells.tolist()):
+        work[c] = plus[i]
+        fwd(*xs, out[i, 0])
+        work[c] = minus[i]
+        fwd(*xs, out[i, 1])
+        work[c] = base[c]
+    step = (plus.double() - minus.double()).cpu().numpy()
+    vals = out.cpu().numpy()
+    return (vals[:, 0] - vals[:, 1]) / step, np.abs(vals).max(), step
+
+
+def test_objectives_1m_cells_against_oracle_and_finite_differences(library):
+    tdp = _tdp()
+    cfg = netgen.CONFIGS["C3"]
+    _log("generating the 1M-cell workload")
+    nl = with_clock(netgen.make_netlist(cfg), library)
+    st = ref.sta(nl, library)
+    K = cfg.top_k_paths
+    k = max(1, K // st["n_fail"])
+    g = tdp.TimingGraph(nl, library, max_paths=K, max_k=k)
+    x, y = _xy(nl)
+    g.sta_update(x, y)
+    g.extract_paths(n=-1, k=k, K=K)
+    g.pairs_update(rule=1)
+    w_gpu, in_gpu = g.pairs_export()
+    in_gpu = in_gpu.astype(bool)
+    _log(f"GPU: {g.pairs_count()} pairs")
+    # exponential weights against the oracle on pinned paths
+    gp = g.paths()
+    rp = ref.extract(nl, library, st, n=-1, k=k, K=K)
+    c, pinned = compare_paths_fast(gp, rp, st, arc_tables(nl), k)
+    _log(f"paths: {c}")
+    assert c["missing"] == 0 and c["extra"] == 0
+    assert c["pinned_ok"] == c["pinned"] and c["unpinned_ok"] == c["unpinned"]
+    ps = ref.PairState(nl["num_pins"])
+    ref.pairs_update(ps, rp, st["wns"], rule=1)
+    _pinned_pair_checks(nl, gp, rp, pinned, w_gpu, in_gpu, ps.w, ps.in_p.astype(bool))
+    # autograd, single precision
+    xr = x.clone().requires_grad_(True)
+    yr = y.clone().requires_grad_(True)
+    pp = tdp.P2PLoss.apply(xr, yr, g)
+    stns = tdp.SmoothTNS.apply(xr, yr, g, 10.0)
+    (pp + stns).backward()
+    gx32 = xr.grad.cpu().numpy().astype(np.float64)
+    gy32 = yr.grad.cpu().numpy().astype(np.float64)
+    # oracle values and gradients (p2p on the GPU's own pair set)
+    sinks = np.nonzero(in_gpu)[0]
+    l_ref, px_ref, py_ref = ref.p2p(nl, sinks, w_gpu[sinks].astype(np.float64))
+    v_ref, sx_ref, sy_ref = ref.stns(nl, library, st, gamma=10.0)
+    assert abs(float(pp) - l_ref) <= 1e-4 * abs(l_ref)
+    assert abs(float(stns) - v_ref) <= 1e-4 * abs(v_ref)
+    # single-precision gradient of the sum against the oracle: p2p per-cell
+    # scale as at 2M cells; smoothed TNS with its largest entry as the scale
+    # (its log-sum-exp weights carry the arrival times' rounding)
+    p_scale = _p2p_abs_scale(nl, sinks, w_gpu[sinks])
+    s_scale = max(np.abs(sx_ref).max(), np.abs(sy_ref).max())
+    ex = np.abs(gx32 - (px_ref + sx_ref))
+    ey = np.abs(gy32 - (py_ref + sy_ref))
+    _log(f"autograd vs oracle: worst {max(ex.max(), ey.max()):.3g} (stns scale {s_scale:.3g})")
+    assert np.all(ex <= 1e-4 * p_scale + 1e-3 * s_scale)
+    assert np.all(ey <= 1e-4 * p_scale + 1e-3 * s_scale)
+    # central differences of the double-precision graph (same pair set and
+    # weights) on 1,000 random movable cells
+    g64 = tdp.TimingGraph(nl, library, precision="f64", max_paths=K, max_k=k)
+    g64.sta_update(x, y)
+    g64.pairs_import(w_gpu, in_gpu.astype(np.uint8))
+    rng = np.random.default_rng(2503)
+    movable = np.nonzero(np.asarray(nl["cell_fixed"]) == 0)[0]
+    cells = torch.tensor(np.sort(rng.choice(movable, 1000, replace=False)), device=_dev())
+    cn = cells.cpu().numpy()
+    for axis, gref, g32 in ((0, (px_ref, sx_ref), gx32), (1, (py_ref, sy_ref), gy32)):
+        fd_p, vmax_p, _ = _central_fd(lambda a, b, o: g64.p2p_loss_fwd(a, b, out=o), x, y, cells, axis)
+        fd_s, vmax_s, _ = _central_fd(lambda a, b, o: g64.stns_fwd(a, b, 10.0, out=o), x, y, cells, axis)
+        # rounding of two double-precision sums over the whole design,
+        # divided by the step (the objectives are smooth at this scale:
+        # cells with a pin within 2h of alignment with a net neighbour sit on
+        # an |dx| kink and are left out)
+        atol_p = 64 * _U64 * vmax_p / 1e-3
+        atol_s = 64 * _U64 * vmax_s / 1e-3
+        keep = ~_near_kink(nl, cn, axis, 2e-3)
+        _log(f"axis {axis}: {int(keep.sum())} cells; p2p fd atol {atol_p:.3g}, stns fd atol {atol_s:.3g}")
+        e_p = np.abs(fd_p - gref[0][cn])[keep]
+        e_s = np.abs(fd_s - gref[1][cn])[keep]
+        _log(f"fd vs oracle: p2p worst {e_p.max():.3g}, stns worst {e_s.max():.3g}")
+        assert np.all(e_p <= atol_p + 1e-6 * np.abs(gref[0][cn])[keep])
+        assert np.all(e_s <= atol_s + 1e-6 * np.abs(gref[1][cn])[keep])
+        # and the single-precision autograd gradient against the differences
+        e32 = np.abs(g32[cn] - (fd_p + fd_s))[keep]
+        assert np.all(e32 <= 1e-4 * p_scale[cn][keep] + 1e-3 * s_scale + atol_p + atol_s)
+        assert np.count_nonzero(np.abs(fd_p[keep]) > 0) > 10 and np.count_nonzero(np.abs(fd_s[keep]) > 0) > 10
+
+
+def _near_kink(nl, cells, axis, eps):
+    """Cells with a pin whose coordinate on the axis is within eps of the
+    other end of one of its net arcs."""
+    driver_of = arc_tables(nl)[0]
+    pc = np.asarray(nl["pin_cell"])
+    coord = np.asarray(nl["x"] if axis == 0 else nl["y"], np.float64)
+    off = np.asarray(nl["pin_off_x"] if axis == 0 else nl["pin_off_y"], np.float64)
+    pos = np.where(pc >= 0, coord[np.maximum(pc, 0)], 0) + off
+    sinks = np.nonzero(driver_of >= 0)[0]
+    close = np.abs(pos[sinks] - pos[driver_of[sinks]]) < eps
+    bad = np.zeros(int(nl["num_cells"]), bool)
+    for q in (sinks[close], driver_of[sinks[close]]):
+        ok = pc[q] >= 0
+        bad[pc[q][ok]] = True
+    return bad[cells]

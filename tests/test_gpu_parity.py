@@ -303,7 +303,7 @@ def test_wa_parity(name, library):
     gy = torch.zeros_like(c["y"])
     v = g.wa_fwd_bwd(c["x"], c["y"], 5.0, gx, gy)
     assert abs(float(v) - v_ref) <= 1e-4 * abs(v_ref)
-    # per cell: 1e-4 of the sum of the magnitudes of its pins' terms
+    # per cell: 1e-4 of the summed magnitudes of the summands of its pins' derivatives
     ex = np.abs(gx.cpu().numpy() - gx_ref)
     ey = np.abs(gy.cpu().numpy() - gy_ref)
     print("WA worst scaled error", (ex / np.maximum(ax, 1e-12)).max(), (ey / np.maximum(ay, 1e-12)).max())
@@ -344,7 +344,7 @@ def test_bitwise_determinism(library):
         gx = torch.zeros_like(x)
         gy = torch.zeros_like(y)
         loss = g.p2p_loss_fwd(x, y)
-        g.p2p_loss_bwd(x, y, torch.ones((), device=x.device), gx, gy)
+        g.p2p_loss_bwd(x, y, torch.ones((), dtype=torch.float64, device=x.device), gx, gy)
         p = g.paths()
         outs.append((g.export()["slack"].cpu().numpy(), p["path_pins"], p["path_slack"], g.pairs_export()[0],
                      float(loss), gx.cpu().numpy(), gy.cpu().numpy()))
@@ -461,3 +461,27 @@ def test_error_paths(library):
     assert g.pairs_count() == 0
     x, y = _xy(nl)
     assert float(g.p2p_loss_fwd(x, y)) == 0.0
+
+
+# -------------------------------------------------------------- autotuner
+def test_autotune_keeps_results(library):
+    """The autotuner picks a supported configuration and the results after it
+    are bitwise those of the default configuration."""
+    tdp = _tdp()
+    c = case("C2", library)
+    g = tdp.TimingGraph(c["nl"], library, max_paths=c["K"], max_k=c["k"])
+    ch = g.autotune(c["x"], c["y"], n=-1, k=c["k"], K=c["K"], reps=2)
+    print("autotune choice", ch)
+    assert ch["sweep_mode"] in (0, 1) and ch["flow_waves"] in (1, 2, 4) and ch["us_per_run"] > 0
+    o = {k: v.cpu().numpy() for k, v in g.export().items()}
+    for key in o:
+        assert np.array_equal(o[key], c["gpu"][key]), key
+    g.extract_paths(n=-1, k=c["k"], K=c["K"])
+    p = g.paths()
+    c["g"].extract_paths(n=-1, k=c["k"], K=c["K"])
+    p0 = c["g"].paths()
+    for key in ("path_ptr", "path_pins", "path_slack"):
+        assert np.array_equal(p[key], p0[key]), key
+    with pytest.raises(tdp.TdpError):
+        g.autotune(c["x"], c["y"], reps=0)
+    g.close()

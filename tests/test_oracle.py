@@ -431,6 +431,29 @@ def test_wa_tends_to_hpwl_and_fd(c1):
         assert abs((vp - vm) / (2 * h) - gx[c]) <= 1e-6 * max(1.0, abs(gx[c]))
 
 
+def test_wa_magnitudes_bound_the_gradient(c1):
+    """The per-cell magnitude sums (the rounding scale of the WA gradient) are
+    at least the gradient's magnitude, and for a lone two-pin net they are
+    the derivative's four summands, computable by hand."""
+    nl, _ = c1
+    v, gx, gy, ax, ay = ref.wa(nl, 5.0, with_abs=True)
+    assert np.all(ax >= np.abs(gx) * (1 - 1e-12)) and np.all(ay >= np.abs(gy) * (1 - 1e-12))
+    cells = [(0, 1), (7, 1)]
+    nets = [(1, [2]), (3, [0])]
+    g, d = 5.0, 7.0
+    nl2, _ = handnets.build(cells, 0, nets, [0.0, d], [0.0, 0.0])
+    _, gx2, _, ax2, _ = ref.wa(nl2, g, with_abs=True)
+    # two pins at 0 and d: weights a = (e^{-d/g}, 1) / (1 + e^{-d/g}); the
+    # mean fp = d / (1 + e^{-d/g}); pin 0's summands (both nets' pin on
+    # cell 0 count once per net: cell 0 has one pin on each net)
+    e = math.exp(-d / g)
+    a0, fp = e / (1 + e), d / (1 + e)
+    b0, fm = 1 / (1 + e), d * e / (1 + e)
+    mag0 = a0 * (1 + abs(0 - fp) / g) + b0 * (1 + abs(0 - fm) / g)
+    assert math.isclose(ax2[0], 2 * mag0, rel_tol=1e-12)
+    assert abs(gx2[0]) <= ax2[0]
+
+
 def test_zero_slack_endpoint_is_not_violated():
     # the chain's endpoint arrives at 40.25 ps: a clock of 40.25 gives slack 0
     nl, _ = handnets.chain_netlist()
