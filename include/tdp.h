@@ -134,8 +134,10 @@ tdp_status tdp_sta_build(const tdp_netlist *netlist, const tdp_library *lib, tdp
 /* Batched form: the graphs of `count` netlists become one disjoint union
  * (instance-major numbering, external ids offset by the preceding instances'
  * pin and cell counts); every later call runs all instances in the same
- * launches.  Per-instance quantities (WNS/TNS, endpoint selection, K) are
- * kept per instance.  max_paths_each bounds n*k per instance. */
+ * launches.  Per-instance quantities (clock period and setup, WNS/TNS,
+ * endpoint selection, K) are kept per instance; input and clock slews must
+ * agree (TDP_E_INVALID otherwise).  Single precision only.  max_paths_each
+ * bounds n*k per instance. */
 tdp_status tdp_batch_build(const tdp_netlist *const *netlists, int32_t count, const tdp_library *lib,
                            tdp_precision prec, int32_t max_paths_each, int32_t max_k, int device,
                            tdp_graph *out);
@@ -144,7 +146,8 @@ tdp_status tdp_batch_offsets(tdp_graph, int32_t *pin_base, int32_t *cell_base);
 
 void tdp_destroy(tdp_graph);
 
-/* Change the required time at every D pin (period - setup). */
+/* Change the required time at every D pin (period - setup), in every
+ * instance of a batched graph.  Synchronous (a small host-to-device copy). */
 tdp_status tdp_sta_set_clock(tdp_graph, float clock_period_ps, float setup_ps);
 
 /* ------------------------------------------------------------------ STA */
@@ -213,6 +216,18 @@ tdp_status tdp_p2p_loss_fwd(tdp_graph, const float *d_x, const float *d_y, doubl
  * ports get nothing.  Deterministic (fixed summation order per cell). */
 tdp_status tdp_p2p_loss_bwd(tdp_graph, const float *d_x, const float *d_y, const double *d_gout,
                             float *d_gx, float *d_gy, hipStream_t);
+
+/* The other pair distances Sec. III-C compares the quadratic one with, over
+ * the same pairs and weights: kind 1 = sum w (|X_s - X_t| + |Y_s - Y_t|)
+ * (the Manhattan distance, a two-pin pair's HPWL), kind 2 = sum w
+ * sqrt((X_s - X_t)^2 + (Y_s - Y_t)^2) (linear Euclidean); kind 0 is PP and
+ * equals tdp_p2p_loss_fwd / _bwd.  Gradients per axis: kind 1 w sgn(d)
+ * (sgn(0) = 0), kind 2 w d / L (0 at L = 0).  Same conventions as the p2p
+ * calls; TDP_E_INVALID for another kind. */
+tdp_status tdp_pair_loss_fwd(tdp_graph, int32_t kind, const float *d_x, const float *d_y, double *d_loss,
+                             hipStream_t);
+tdp_status tdp_pair_loss_bwd(tdp_graph, int32_t kind, const float *d_x, const float *d_y, const double *d_gout,
+                             float *d_gx, float *d_gy, hipStream_t);
 
 /* Smoothed TNS: cell-arc delays and start arrivals frozen from the last
  * update, net delays from d_x/d_y; log-sum-exp over fan-in with temperature

@@ -209,6 +209,27 @@ def p2p(nl, pair_sink, pair_w, x=None, y=None):
     return float(loss[0]), gx, gy
 
 
+def pair_loss(nl, kind, pair_sink, pair_w, x=None, y=None):
+    """Sec. III-C's other pair losses: kind 1 = sum w (|dX| + |dY|),
+    kind 2 = sum w sqrt(dX^2 + dY^2); value and cell gradient."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    N = int(nl["num_cells"])
+    gx, gy = np.empty(N, np.float64), np.empty(N, np.float64)
+    loss = np.zeros(1, np.float64)
+    ps, pw = _i32(pair_sink), _f64(pair_w)
+    if ps.shape[0] == 0:
+        ps, pw = np.zeros(1, np.int32), np.zeros(1, np.float64)
+    na, keep = _netlist_args(nl)
+    fixed = np.ascontiguousarray(nl["cell_fixed"], dtype=np.uint8)
+    rc = L.ora_pair_loss(*na, _p(fixed), _p(x), _p(y), ctypes.c_int(kind), ctypes.c_int(len(pair_sink)), _p(ps),
+                         _p(pw), _p(loss), _p(gx), _p(gy))
+    if rc != 0:
+        raise ValueError(f"pair loss kind {kind} failed ({rc})")
+    return float(loss[0]), gx, gy
+
+
 def stns(nl, lib, st, gamma: float = 10.0, x=None, y=None):
     """Smoothed TNS (frozen cell arcs and start-point arrivals from `st`)."""
     L = _load()

@@ -25,6 +25,9 @@
  *                  Eq. 9 (Sec. III-D), or the stateless exponential rule.
  *   ora_p2p      - PP = sum w * Q(i, j), Q the squared Euclidean pin distance
  *                  (Eqs. 8 and 10), with its gradient on cell positions.
+ *   ora_pair_loss - the two distance losses the paper compares PP with
+ *                  (Sec. III-C): the Manhattan distance (a two-pin pair's
+ *                  HPWL) and the linear Euclidean distance, with gradients.
  *   ora_stns     - a log-sum-exp smoothed TNS with its adjoint (not in the
  *                  paper; definition below).
  *   ora_wa       - weighted-average wirelength (the WL_e of Eq. 1, the
@@ -590,6 +593,44 @@ int ora_p2p(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float
     if (ct >= 0 && !cell_fixed[ct]) { grad_x[ct] += 2 * w * (xt - xs); grad_y[ct] += 2 * w * (yt - ys); }
   }
   *loss = pp;
+  conn_free(&c);
+  return 0;
+}
+
+/* Pair losses of Sec. III-C other than the quadratic one, over the same
+ * pairs: kind 1 = w (|X_s - X_t| + |Y_s - Y_t|), kind 2 = w sqrt((X_s - X_t)^2
+ * + (Y_s - Y_t)^2).  Gradient on cell positions: kind 1 gives w sgn(d) per
+ * axis (sgn(0) = 0), kind 2 gives w d / L (0 when L = 0). */
+int ora_pair_loss(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float *y, int kind,
+                  int num_pairs, const int32_t *pair_sink, const double *pair_w, double *loss,
+                  double *grad_x, double *grad_y) {
+  FILL_NETLIST(n);
+  if (kind != 1 && kind != 2) return -3;
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  for (int cell = 0; cell < num_cells; ++cell) { grad_x[cell] = 0; grad_y[cell] = 0; }
+  double total = 0.0;
+  for (int a = 0; a < num_pairs; ++a) {
+    int t = pair_sink[a], s = c.driver[t];
+    double xs, ys, xt, yt;
+    pin_xy(&n, x, y, s, &xs, &ys);
+    pin_xy(&n, x, y, t, &xt, &yt);
+    double w = pair_w[a], dx = xs - xt, dy = ys - yt, gxs, gys;
+    if (kind == 1) {
+      total += w * (fabs(dx) + fabs(dy));
+      gxs = w * (double)((dx > 0) - (dx < 0));
+      gys = w * (double)((dy > 0) - (dy < 0));
+    } else {
+      double len = sqrt(dx * dx + dy * dy);
+      total += w * len;
+      gxs = len > 0 ? w * dx / len : 0.0;
+      gys = len > 0 ? w * dy / len : 0.0;
+    }
+    int cs = pin_cell[s], ct = pin_cell[t];
+    if (cs >= 0 && !cell_fixed[cs]) { grad_x[cs] += gxs; grad_y[cs] += gys; }
+    if (ct >= 0 && !cell_fixed[ct]) { grad_x[ct] -= gxs; grad_y[ct] -= gys; }
+  }
+  *loss = total;
   conn_free(&c);
   return 0;
 }

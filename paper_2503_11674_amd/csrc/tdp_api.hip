@@ -74,6 +74,12 @@ void free_all(tdp_graph g) {
     if (e) { hipEventDestroy(e); e = nullptr; }
 }
 
+// required time at the D pins: period - setup as the graph's precision
+// computes it (so a batch of one equals the single-netlist graph bitwise)
+static double required_time(tdp_precision prec, float period, float setup) {
+  return prec == TDP_F32 ? (double)(period - setup) : (double)period - (double)setup;
+}
+
 // host-side copies kept for export / import
 struct HostSide {
   std::vector<int32_t> snk_ext;
@@ -112,10 +118,10 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   g->r = lib->r_per_um;
   g->c = lib->c_per_um;
   g->scale = lib->delay_scale;
-  g->clock_period = nls[0]->clock_period_ps;
-  g->setup = nls[0]->setup_ps;
   g->input_slew = nls[0]->input_slew_ps;
   g->clock_slew = nls[0]->clock_slew_ps;
+  g->h_inst_req.resize(count);
+  for (int i = 0; i < count; ++i) g->h_inst_req[i] = required_time(prec, nls[i]->clock_period_ps, nls[i]->setup_ps);
   g->max_paths = max_paths;
   g->max_k = max_k;
   g->side_k = 1;
@@ -153,18 +159,20 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        upload(g, T.ff_type, H.ff_type) && upload(g, T.ff_inst, H.ff_inst) &&
        upload(g, T.ext_pin_int, H.ext_pin_int) && upload(g, T.cell_int, H.cell_int) &&
        upload(g, T.cell_fixed, H.cell_fixed) && upload(g, g->d_ep_base, H.lv.ep_base) &&
-       upload(g, T.fw_rec, H.fw_rec) && upload(g, T.nm_rec, H.nm_rec) &&
+       upload(g, T.fw_rec, H.fw_rec) && upload(g, T.fw_ext, H.fw_ext) && upload(g, T.nm_rec, H.nm_rec) &&
        upload(g, T.nm_ox, H.nm_ox) && upload(g, T.nm_oy, H.nm_oy) && upload(g, T.big_net, H.big_net);
   g->h_snk_ext = H.snk_ext;
   // timing state
   const size_t es = g->esz;
   ok = ok && dalloc(g, g->load, T.M, es) && dalloc(g, g->dnet, T.S, es) && dalloc(g, g->at, T.P, es) &&
-       dalloc(g, g->slew, T.M, es) && dalloc(g, g->rat, T.P, es) && dalloc(g, g->slack, T.P, es) &&
+       dalloc(g, g->slew, T.M, es) && dalloc(g, g->rat, T.P, es) &&
+       dalloc(g, g->dnet_nm, (size_t)T.n_nm_chunks * CHUNK, es) && dalloc(g, g->drv_as, (size_t)2 * T.M, es) &&
        dalloc(g, g->darc, T.A, es) && dalloc(g, g->crit, T.n_comb) && dalloc(g, g->hop, (size_t)T.n_comb * 4) &&
        dalloc(g, g->cdep, T.M) && dalloc(g, g->ep_slack, T.E, es) &&
        dalloc(g, g->red_ep, (size_t)3 * T.num_inst * g->ep_chunks) && dalloc(g, g->red_loss, 4096) &&
        dalloc(g, g->red_wa, 4096) && dalloc(g, g->summary, (size_t)4 * T.num_inst) &&
-       dalloc(g, g->inst_nfail, T.num_inst) && dalloc(g, g->d_err, 4) && dalloc(g, g->consts, 4);
+       dalloc(g, g->inst_nfail, T.num_inst) && dalloc(g, g->d_err, 4) && dalloc(g, g->consts, 4) &&
+       upload(g, g->d_inst_req, g->h_inst_req);
   if (ok && g->side_k > 1)
     ok = dalloc(g, g->side_cost, (size_t)T.n_comb * g->side_k, es) &&
          dalloc(g, g->side_pin, (size_t)T.n_comb * g->side_k);
@@ -187,7 +195,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        dalloc(g, g->inst_seg, ni) && dalloc(g, g->inst_outb, ni) && dalloc(g, g->inst_kept, ni) &&
        dalloc(g, g->inst_selb, ni) && dalloc(g, g->sel_npop, T.E) &&
        dalloc(g, g->slot_key, sc, es) && dalloc(g, g->slot_dev, sc) && dalloc(g, g->slot_par, sc) &&
-       dalloc(g, g->slot_len, sc) && dalloc(g, g->slot_cells, sc) && dalloc(g, g->d_nslots, 1) &&
+       dalloc(g, g->slot_len, sc) && dalloc(g, g->slot_out, sc) && dalloc(g, g->slot_cells, sc) && dalloc(g, g->d_nslots, 1) &&
        dalloc(g, g->sort_k0, sc) && dalloc(g, g->sort_k1, sc) && dalloc(g, g->sort_v0, sc) &&
        dalloc(g, g->sort_v1, sc) && dalloc(g, g->sort_hist, sort_hist_size(sc)) &&
        dalloc(g, g->scan_tmp, scan_tmp_size(scan_cap)) && dalloc(g, g->out_slot, mo) &&
@@ -241,10 +249,9 @@ tdp_status tdp_batch_build(const tdp_netlist *const *netlists, int32_t count, co
                            tdp_precision prec, int32_t max_paths_each, int32_t max_k, int device, tdp_graph *out) {
   if (!netlists || count < 1) return fail(nullptr, TDP_E_INVALID, "no netlists");
   for (int i = 1; i < count; ++i)
-    if (!netlists[i] || !netlists[0] || netlists[i]->clock_period_ps != netlists[0]->clock_period_ps ||
-        netlists[i]->setup_ps != netlists[0]->setup_ps || netlists[i]->input_slew_ps != netlists[0]->input_slew_ps ||
+    if (!netlists[i] || !netlists[0] || netlists[i]->input_slew_ps != netlists[0]->input_slew_ps ||
         netlists[i]->clock_slew_ps != netlists[0]->clock_slew_ps)
-      return fail(nullptr, TDP_E_INVALID, "batched netlists must share clock period, setup and slews");
+      return fail(nullptr, TDP_E_INVALID, "batched netlists must share input and clock slews");
   int64_t cap = (int64_t)max_paths_each * count;
   if (max_paths_each < 1 || cap > (1 << 30)) return fail(nullptr, TDP_E_INVALID, "bad max_paths_each");
   return build_common(netlists, count, lib, prec, (int32_t)cap, max_paths_each, max_k, device, out);
@@ -270,8 +277,10 @@ void tdp_destroy(tdp_graph g) {
 tdp_status tdp_sta_set_clock(tdp_graph g, float period, float setup) {
   GUARD(g);
   if (!std::isfinite(period) || !std::isfinite(setup)) return fail(g, TDP_E_INVALID, "clock not finite");
-  g->clock_period = period;
-  g->setup = setup;
+  for (double &r : g->h_inst_req) r = required_time(g->prec, period, setup);
+  if (hipMemcpy(g->d_inst_req, g->h_inst_req.data(), sizeof(double) * g->h_inst_req.size(),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "clock upload failed");
   return TDP_OK;
 }
 
@@ -456,16 +465,34 @@ tdp_status tdp_pairs_count(tdp_graph g, int32_t *num_pairs, hipStream_t s) {
 tdp_status tdp_p2p_loss_fwd(tdp_graph g, const float *x, const float *y, double *loss, hipStream_t s) {
   GUARD(g);
   if (!x || !y || !loss) return fail(g, TDP_E_INVALID, "NULL argument");
-  dispatch(g, [&](auto z) { p2p_fwd_impl<decltype(z)>(g, x, y, loss, s); });
+  dispatch(g, [&](auto z) { p2p_fwd_impl<decltype(z)>(g, 0, x, y, loss, s); });
   return check_launch(g, "p2p_loss_fwd");
+}
+
+tdp_status tdp_pair_loss_fwd(tdp_graph g, int32_t kind, const float *x, const float *y, double *loss,
+                             hipStream_t s) {
+  GUARD(g);
+  if (kind < 0 || kind > 2) return fail(g, TDP_E_INVALID, "kind must be 0, 1 or 2");
+  if (!x || !y || !loss) return fail(g, TDP_E_INVALID, "NULL argument");
+  dispatch(g, [&](auto z) { p2p_fwd_impl<decltype(z)>(g, kind, x, y, loss, s); });
+  return check_launch(g, "pair_loss_fwd");
 }
 
 tdp_status tdp_p2p_loss_bwd(tdp_graph g, const float *x, const float *y, const double *gout, float *gx, float *gy,
                             hipStream_t s) {
   GUARD(g);
   if (!x || !y || !gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
-  dispatch(g, [&](auto z) { p2p_bwd_impl<decltype(z)>(g, x, y, gout ? gout : g->consts, gx, gy, s); });
+  dispatch(g, [&](auto z) { p2p_bwd_impl<decltype(z)>(g, 0, x, y, gout ? gout : g->consts, gx, gy, s); });
   return check_launch(g, "p2p_loss_bwd");
+}
+
+tdp_status tdp_pair_loss_bwd(tdp_graph g, int32_t kind, const float *x, const float *y, const double *gout,
+                             float *gx, float *gy, hipStream_t s) {
+  GUARD(g);
+  if (kind < 0 || kind > 2) return fail(g, TDP_E_INVALID, "kind must be 0, 1 or 2");
+  if (!x || !y || !gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
+  dispatch(g, [&](auto z) { p2p_bwd_impl<decltype(z)>(g, kind, x, y, gout ? gout : g->consts, gx, gy, s); });
+  return check_launch(g, "pair_loss_bwd");
 }
 
 tdp_status tdp_stns_fwd(tdp_graph g, const float *x, const float *y, float gamma, double *val, hipStream_t s) {

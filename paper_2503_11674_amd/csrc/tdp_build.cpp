@@ -367,6 +367,7 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
       while (lane % CHUNK) {
         const int l = (int)(lane % CHUNK);
         H.fw_rec.push_back(make_int4(-1, 0, 0, seg(l, l)));
+        H.fw_ext.push_back(make_int2(0, 0));
         ++lane;
       }
     };
@@ -379,6 +380,7 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
         const int head = (int)(lane % CHUNK);
         for (int t = H.comb_inptr[c]; t < H.comb_inptr[c + 1]; ++t) {
           H.fw_rec.push_back(make_int4(t, H.snk_drv[t], c, seg(head, head + n - 1) | (int)H.comb_type[c] << 16));
+          H.fw_ext.push_back(make_int2(H.snk_ext[t], H.drv_ext[H.snk_drv[t]]));
           ++lane;
         }
       }

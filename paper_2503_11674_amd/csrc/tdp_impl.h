@@ -33,9 +33,10 @@ template <typename T> void extract_impl(tdp_graph g, int n, int k, int K, float 
 template <typename T> void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s);
 void pairs_rebuild(tdp_graph g, hipStream_t s);
 void pairs_compact(tdp_graph g, hipStream_t s);
-template <typename T> void p2p_fwd_impl(tdp_graph g, const float *x, const float *y, double *loss, hipStream_t s);
 template <typename T>
-void p2p_bwd_impl(tdp_graph g, const float *x, const float *y, const double *gout, float *gx, float *gy,
+void p2p_fwd_impl(tdp_graph g, int kind, const float *x, const float *y, double *loss, hipStream_t s);
+template <typename T>
+void p2p_bwd_impl(tdp_graph g, int kind, const float *x, const float *y, const double *gout, float *gx, float *gy,
                   hipStream_t s);
 template <typename T>
 void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, double *val, hipStream_t s);

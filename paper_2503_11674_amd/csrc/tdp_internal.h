@@ -92,6 +92,7 @@ struct Topo {
   // cell type << 16}, so a lane finds everything static in one load.
   int32_t n_fw_chunks = 0;
   int4 *fw_rec = nullptr;
+  int2 *fw_ext = nullptr;  // per lane: external ids of its sink and of that sink's driver
   // 64-lane chunks of nets (driver lane first, then its sinks); a net never
   // straddles a chunk; chunks are level-pure by driver level.  Nets with more
   // than 63 sinks are "big" and handled one thread per net.
@@ -125,6 +126,7 @@ struct HostTopo {
   std::vector<float> drv_ox, drv_oy, snk_ox, snk_oy;
   std::vector<double> net_cpin;
   std::vector<int4> fw_rec, nm_rec;
+  std::vector<int2> fw_ext;
   std::vector<int32_t> big_net;
   std::vector<float> nm_ox, nm_oy;
   std::vector<uint8_t> comb_type, ff_type, cell_fixed;
@@ -153,7 +155,11 @@ struct tdp_graph_s {
   tdp::HostLevels lv;
   tdp::LutView lut{};
   float r = 0, c = 0, scale = 0;
-  float clock_period = 0, setup = 0, input_slew = 0, clock_slew = 0;
+  float input_slew = 0, clock_slew = 0;
+  // required time at the D pins of each instance (period - setup, rounded as
+  // the graph's precision rounds it); device copy in d_inst_req
+  std::vector<double> h_inst_req;
+  double *d_inst_req = nullptr;
   int32_t max_paths = 0, max_k = 1, side_k = 1, max_out = 0, max_out_inst = 0, slot_cap = 0, pin_cap = 0;
   int32_t key_bits32 = 40, ep_chunks = 1;
   int32_t tune_block = 256, tune_chunk = 1, sweep_mode = 0;
@@ -165,8 +171,12 @@ struct tdp_graph_s {
   double *consts = nullptr;    // [4] device constants: {1, 0, 0, 0}
 
   // timing state (element type per precision)
-  void *load = nullptr, *dnet = nullptr, *at = nullptr, *slew = nullptr, *rat = nullptr,
-       *slack = nullptr, *darc = nullptr;
+  // slack is not stored: export derives it as rat - at.  dnet_nm holds the
+  // net delays again in net-chunk slot order (the backward passes read them
+  // there); drv_as packs {arrival, transition} of each driver for the
+  // forward passes' gathers.
+  void *load = nullptr, *dnet = nullptr, *at = nullptr, *slew = nullptr, *rat = nullptr, *darc = nullptr,
+       *dnet_nm = nullptr, *drv_as = nullptr;
   int32_t *crit = nullptr;       // [n_comb] arc index of the critical input
   int32_t *hop = nullptr;        // [n_comb][4] {critical sink, its driver, their external ids}
   int32_t *cdep = nullptr;       // [M] combinational cells on the critical chain
@@ -196,6 +206,7 @@ struct tdp_graph_s {
   uint32_t *sort_v0 = nullptr, *sort_v1 = nullptr;
   int32_t *sort_hist = nullptr, *scan_tmp = nullptr;
   int32_t *out_slot = nullptr, *out_len = nullptr;
+  int32_t *slot_out = nullptr;  // [slot_cap] output index of a slot's path, -1 when cut
   int32_t *path_ptr = nullptr, *path_pins = nullptr, *path_int = nullptr, *path_ep = nullptr,
           *path_epi = nullptr, *path_rank = nullptr, *d_num_paths = nullptr;
   void *path_slack = nullptr;

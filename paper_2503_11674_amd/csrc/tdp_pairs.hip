@@ -62,15 +62,16 @@ __global__ void __launch_bounds__(256) k_pairs_acc(Topo tp, int rule, const int3
 }
 
 // Same sums, aggregated per block first: a block takes a run of consecutive
-// paths (which share most of their pins: they are adjacent in slack order),
+// slots, i.e. the k paths of a few endpoints, which share most of their pins,
 // merges its occurrences in an LDS hash table with integer atomics, and sends
-// one global atomic per distinct pin.  Pins shared by thousands of paths then
-// see one update per block instead of one per path.
+// one global atomic per distinct pin.  The first occurrence is still the
+// smallest output index, whatever order the paths are visited in.
 constexpr int HASH_SLOTS = 4096;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int per_block,
-                                                        const int32_t *__restrict__ d_num_paths,
+                                                        const int32_t *__restrict__ d_nslots,
+                                                        const int32_t *__restrict__ slot_out,
                                                         const int32_t *__restrict__ path_ptr,
                                                         const int32_t *__restrict__ path_int,
                                                         const int32_t *__restrict__ path_epi,
@@ -81,17 +82,20 @@ __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int pe
   __shared__ int32_t hkey[HASH_SLOTS];
   __shared__ unsigned long long hacc[HASH_SLOTS];
   __shared__ int32_t hfirst[HASH_SLOTS];
+  const int n = *d_nslots;
+  const int j0 = blockIdx.x * per_block;
+  if (j0 >= n) return;  // whole block: the grid is sized for the slot capacity
   for (int i = threadIdx.x; i < HASH_SLOTS; i += blockDim.x) {
     hkey[i] = -1;
     hacc[i] = 0ull;
     hfirst[i] = 0x7fffffff;
   }
   __syncthreads();
-  const int n = *d_num_paths;
-  const int q0 = blockIdx.x * per_block;
-  const int q1 = min(n, q0 + per_block);
+  const int j1 = min(n, j0 + per_block);
   const int lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
-  for (int q = q0 + (threadIdx.x >> 6); q < q1; q += nwv) {
+  for (int j = j0 + (threadIdx.x >> 6); j < j1; j += nwv) {
+    const int q = slot_out[j];
+    if (q < 0) continue;
     const double wns = summary[4 * tp.ff_inst[path_epi[q]]];
     unsigned long long v;
     if (!pair_contrib<T>(rule, path_slack[q], wns, v)) continue;
@@ -265,8 +269,38 @@ __global__ void k_inc_sort(const int32_t *__restrict__ d_ntouched, const int32_t
 // ------------------------------------------------------------------ loss
 constexpr int LOSS_BLOCKS = 512;
 
-// each pair's term in the graph's precision T, summed in double
+// Pair distance losses: KIND 0 is PP's quadratic term (Eqs. 8, 10); 1 and 2
+// are the Manhattan and linear Euclidean distances Sec. III-C compares it
+// with.  pair_term is w * f(dx, dy); pair_grad the derivative of that term
+// with respect to the first pin's coordinates (the second pin's is its
+// negative).
+template <typename T, int KIND>
+__device__ __forceinline__ T pair_term(T w, T dx, T dy) {
+  if constexpr (KIND == 0) return w * (dx * dx + dy * dy);
+  else if constexpr (KIND == 1) return w * (fabs(dx) + fabs(dy));
+  else return w * sqrt(dx * dx + dy * dy);
+}
 template <typename T>
+__device__ __forceinline__ T sgn_of(T v) {
+  return (T)((v > (T)0) - (v < (T)0));
+}
+template <typename T, int KIND>
+__device__ __forceinline__ void pair_grad(T w, T dx, T dy, T &gx, T &gy) {
+  if constexpr (KIND == 0) {
+    gx = (T)2 * w * dx;
+    gy = (T)2 * w * dy;
+  } else if constexpr (KIND == 1) {
+    gx = w * sgn_of(dx);
+    gy = w * sgn_of(dy);
+  } else {
+    const T len = sqrt(dx * dx + dy * dy);
+    gx = len > (T)0 ? w * dx / len : (T)0;
+    gy = len > (T)0 ? w * dy / len : (T)0;
+  }
+}
+
+// each pair's term in the graph's precision T, summed in double
+template <typename T, int KIND>
 __global__ void __launch_bounds__(256) k_p2p_fwd(const int32_t *__restrict__ d_npairs,
                                                   const int32_t *__restrict__ pair_cs,
                                                   const int32_t *__restrict__ pair_ct,
@@ -282,7 +316,7 @@ __global__ void __launch_bounds__(256) k_p2p_fwd(const int32_t *__restrict__ d_n
     const T xs = cs >= 0 ? (T)x[cs] : (T)0, ys = cs >= 0 ? (T)y[cs] : (T)0;
     const T dx = xs - (T)x[ct] + (T)pair_dox[q];
     const T dy = ys - (T)y[ct] + (T)pair_doy[q];
-    acc += (double)((T)pair_w[q] * (dx * dx + dy * dy));
+    acc += (double)pair_term<T, KIND>((T)pair_w[q], dx, dy);
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -306,7 +340,7 @@ __global__ void __launch_bounds__(256) k_sum_parts(int n, const double *__restri
   if (threadIdx.x == 0) *out = sh[0];
 }
 
-template <typename T>
+template <typename T, int KIND>
 __global__ void __launch_bounds__(256) k_p2p_bwd(const int32_t *__restrict__ d_ntouched,
                                                   const int32_t *__restrict__ touched,
                                                   const int32_t *__restrict__ cell_ptr,
@@ -324,9 +358,10 @@ __global__ void __launch_bounds__(256) k_p2p_bwd(const int32_t *__restrict__ d_n
     for (int a = cell_ptr[c]; a < cell_ptr[c + 1]; ++a) {
       const int o = inc_other[a];
       const T xo = o >= 0 ? (T)x[o] : (T)0, yo = o >= 0 ? (T)y[o] : (T)0;
-      const T w2 = (T)2 * (T)inc_w[a];
-      ax += w2 * (xc - xo + (T)inc_dx[a]);
-      ay += w2 * (yc - yo + (T)inc_dy[a]);
+      T gx1, gy1;
+      pair_grad<T, KIND>((T)inc_w[a], xc - xo + (T)inc_dx[a], yc - yo + (T)inc_dy[a], gx1, gy1);
+      ax += gx1;
+      ay += gy1;
     }
     gx[c] += (float)(g * ax);
     gy[c] += (float)(g * ay);
@@ -347,9 +382,9 @@ void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s)
   // 80 % of the hash table, otherwise fall back to plain global atomics
   const int per_block = (HASH_SLOTS * 4 / 5) / (tp.D + 1);
   if (per_block >= 1)
-    hipLaunchKernelGGL(k_pairs_acc_lds<T>, dim3(nb(g->max_out, per_block)), dim3(256), 0, s, tp, rule, per_block,
-                       g->d_num_paths, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack, g->summary,
-                       g->pacc, g->pfirst);
+    hipLaunchKernelGGL(k_pairs_acc_lds<T>, dim3(nb(g->slot_cap, per_block)), dim3(256), 0, s, tp, rule, per_block,
+                       g->d_nslots, g->slot_out, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack,
+                       g->summary, g->pacc, g->pfirst);
   else
     hipLaunchKernelGGL(k_pairs_acc<T>, dim3(std::min(2048, nb(g->max_out, 4))), dim3(256), 0, s, tp, rule,
                        g->d_num_paths, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack, g->summary,
@@ -387,31 +422,46 @@ void pairs_compact(tdp_graph g, hipStream_t s) {
   g->pairs_built = true;
 }
 
+template <typename T, int KIND>
+static void launch_pair_fwd(tdp_graph g, const float *x, const float *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_p2p_fwd<T, KIND>), dim3(LOSS_BLOCKS), dim3(256), 0, s, g->d_npairs, g->pair_cs, g->pair_ct,
+                     g->pair_dox, g->pair_doy, g->pair_w, x, y, g->red_loss);
+}
+
 template <typename T>
-void p2p_fwd_impl(tdp_graph g, const float *x, const float *y, double *loss, hipStream_t s) {
+void p2p_fwd_impl(tdp_graph g, int kind, const float *x, const float *y, double *loss, hipStream_t s) {
   prof_begin(g, TDP_STAGE_P2P_FWD, s);
-  hipLaunchKernelGGL(k_p2p_fwd<T>, dim3(LOSS_BLOCKS), dim3(256), 0, s, g->d_npairs, g->pair_cs, g->pair_ct, g->pair_dox,
-                     g->pair_doy, g->pair_w, x, y, g->red_loss);
+  if (kind == 1) launch_pair_fwd<T, 1>(g, x, y, s);
+  else if (kind == 2) launch_pair_fwd<T, 2>(g, x, y, s);
+  else launch_pair_fwd<T, 0>(g, x, y, s);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, LOSS_BLOCKS, g->red_loss, loss);
   prof_end(g, TDP_STAGE_P2P_FWD, s);
 }
 
+template <typename T, int KIND>
+static void launch_pair_bwd(tdp_graph g, const float *x, const float *y, const double *gout, float *gx, float *gy,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((k_p2p_bwd<T, KIND>), dim3(LOSS_BLOCKS * 2), dim3(256), 0, s, g->d_ntouched, g->touched,
+                     g->cell_ptr, g->inc_other, g->inc_dx, g->inc_dy, g->inc_w, x, y, gout, gx, gy);
+}
+
 template <typename T>
-void p2p_bwd_impl(tdp_graph g, const float *x, const float *y, const double *gout, float *gx, float *gy,
+void p2p_bwd_impl(tdp_graph g, int kind, const float *x, const float *y, const double *gout, float *gx, float *gy,
                   hipStream_t s) {
   prof_begin(g, TDP_STAGE_P2P_BWD, s);
-  hipLaunchKernelGGL(k_p2p_bwd<T>, dim3(LOSS_BLOCKS * 2), dim3(256), 0, s, g->d_ntouched, g->touched, g->cell_ptr,
-                     g->inc_other, g->inc_dx, g->inc_dy, g->inc_w, x, y, gout, gx, gy);
+  if (kind == 1) launch_pair_bwd<T, 1>(g, x, y, gout, gx, gy, s);
+  else if (kind == 2) launch_pair_bwd<T, 2>(g, x, y, gout, gx, gy, s);
+  else launch_pair_bwd<T, 0>(g, x, y, gout, gx, gy, s);
   prof_end(g, TDP_STAGE_P2P_BWD, s);
 }
 
 template void pairs_update_impl<float>(tdp_graph, int, float, float, hipStream_t);
 template void pairs_update_impl<double>(tdp_graph, int, float, float, hipStream_t);
-template void p2p_fwd_impl<float>(tdp_graph, const float *, const float *, double *, hipStream_t);
-template void p2p_fwd_impl<double>(tdp_graph, const float *, const float *, double *, hipStream_t);
-template void p2p_bwd_impl<float>(tdp_graph, const float *, const float *, const double *, float *, float *,
+template void p2p_fwd_impl<float>(tdp_graph, int, const float *, const float *, double *, hipStream_t);
+template void p2p_fwd_impl<double>(tdp_graph, int, const float *, const float *, double *, hipStream_t);
+template void p2p_bwd_impl<float>(tdp_graph, int, const float *, const float *, const double *, float *, float *,
                                   hipStream_t);
-template void p2p_bwd_impl<double>(tdp_graph, const float *, const float *, const double *, float *, float *,
+template void p2p_bwd_impl<double>(tdp_graph, int, const float *, const float *, const double *, float *, float *,
                                    hipStream_t);
 
 }  // namespace tdp

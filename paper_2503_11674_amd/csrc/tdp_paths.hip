@@ -233,7 +233,7 @@ __global__ void k_path_index(Topo tp, int k, const int32_t *__restrict__ d_nslot
                              const int32_t *__restrict__ sel, const int32_t *__restrict__ seg,
                              const int32_t *__restrict__ outb, const int32_t *__restrict__ kept,
                              const int32_t *__restrict__ slot_len, int32_t *__restrict__ out_slot,
-                             int32_t *__restrict__ out_len) {
+                             int32_t *__restrict__ out_len, int32_t *__restrict__ slot_out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= *d_nslots) return;
   const int slot = perm[j];
@@ -244,10 +244,55 @@ __global__ void k_path_index(Topo tp, int k, const int32_t *__restrict__ d_nslot
     const int q = outb[inst] + rho;
     out_slot[q] = slot;
     out_len[q] = slot_len[slot];
+    slot_out[slot] = q;
+  } else {
+    slot_out[slot] = -1;
   }
 }
 
 // ----------------------------------------------------------------- walk
+// Writes a path from its last position down to its first, two arrays at
+// once, in 16-byte stores where the positions are 16-byte aligned: values are
+// collected four at a time in registers (the hardware then writes whole
+// sectors instead of one word per lane and step).
+struct RevWriter {
+  int32_t *a, *b;
+  int pos;      // next position to write (descending)
+  int n = 0;    // values collected for the aligned group ending at top
+  int top = 0;  // highest position of the group being collected
+  int32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  __device__ void put(int32_t va, int32_t vb) {
+    if (n == 0 && (pos & 3) != 3) {  // not at the top of an aligned group yet
+      a[pos] = va;
+      b[pos] = vb;
+      --pos;
+      return;
+    }
+    if (n == 0) top = pos;
+    // position top - n takes slot 3 - n
+    a3 = n == 0 ? va : a3;
+    b3 = n == 0 ? vb : b3;
+    a2 = n == 1 ? va : a2;
+    b2 = n == 1 ? vb : b2;
+    a1 = n == 2 ? va : a1;
+    b1 = n == 2 ? vb : b1;
+    a0 = n == 3 ? va : a0;
+    b0 = n == 3 ? vb : b0;
+    --pos;
+    if (++n == 4) {
+      *(int4 *)(a + top - 3) = make_int4(a0, a1, a2, a3);
+      *(int4 *)(b + top - 3) = make_int4(b0, b1, b2, b3);
+      n = 0;
+    }
+  }
+  __device__ void flush() {  // a partial group: its values sit at top, top-1, ...
+    if (n > 0) { a[top] = a3; b[top] = b3; }
+    if (n > 1) { a[top - 1] = a2; b[top - 1] = b2; }
+    if (n > 2) { a[top - 2] = a1; b[top - 2] = b1; }
+    n = 0;
+  }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__restrict__ d_num_paths,
                                                const int32_t *__restrict__ out_slot, const int32_t *__restrict__ sel,
@@ -281,19 +326,15 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
     atomicOr(err, 1);
     return;
   }
-  int pos = hi - 1;
+  RevWriter w{path_pins, path_int, hi - 1};
   const int et = tp.A + f;
-  path_pins[pos] = tp.snk_ext[et];
-  path_int[pos] = tp.M + et;
-  --pos;
+  w.put(tp.snk_ext[et], tp.M + et);
   int v = tp.snk_drv[et];
   int vext = tp.drv_ext[v];
   int di = nd - 1;
   for (;;) {
-    if (pos < lo) break;
-    path_pins[pos] = vext;
-    path_int[pos] = v;
-    --pos;
+    if (w.pos < lo) break;
+    w.put(vext, v);
     if (v < tp.n_start) break;
     const int c = v - tp.n_start;
     int t, text, nv, nvext;
@@ -310,14 +351,13 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
       text = h.z;
       nvext = h.w;
     }
-    if (pos < lo) break;
-    path_pins[pos] = text;
-    path_int[pos] = tp.M + t;
-    --pos;
+    if (w.pos < lo) break;
+    w.put(text, tp.M + t);
     v = nv;
     vext = nvext;
   }
-  if (pos != lo - 1 || v >= tp.n_start || di >= 0) atomicOr(err, 1);
+  w.flush();
+  if (w.pos != lo - 1 || v >= tp.n_start || di >= 0) atomicOr(err, 1);
   path_ep[q] = tp.snk_ext[et];
   path_epi[q] = f;
   path_rank[q] = r;
@@ -388,7 +428,7 @@ void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream
   hipLaunchKernelGGL(k_path_bases, dim3(1), dim3(1), 0, s, tp.num_inst, k, K, g->inst_nsel, g->inst_nvalid,
                      g->inst_seg, g->inst_outb, g->inst_kept, g->d_num_paths);
   hipLaunchKernelGGL(k_path_index<T>, dim3(nb(cap, 256)), dim3(256), 0, s, tp, k, g->d_nslots, g->sort_v0,
-                     g->sel_list, g->inst_seg, g->inst_outb, g->inst_kept, g->slot_len, g->out_slot, g->out_len);
+                     g->sel_list, g->inst_seg, g->inst_outb, g->inst_kept, g->slot_len, g->out_slot, g->out_len, g->slot_out);
   scan_exclusive(g->out_len, g->path_ptr, g->max_out, g->d_num_paths, nullptr, g->scan_tmp, s);
   hipLaunchKernelGGL(k_ptr_tail, dim3(1), dim3(1), 0, s, g->d_num_paths, g->out_len, g->path_ptr);
   prof_end(g, TDP_STAGE_ORDER, s);

@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(256) k_st_fwd(Topo tp, int c0, int c1, T gam, 
 
 // endpoint values and adjoint seeds; per-block partial sums of the value
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_end(Topo tp, T req, T gam, const T *__restrict__ dnl,
+__global__ void __launch_bounds__(256) k_st_end(Topo tp, const double *__restrict__ inst_req, T gam,
+                                                 const T *__restrict__ dnl,
                                                  T *__restrict__ sa, T *__restrict__ adj,
                                                  double *__restrict__ part) {
   __shared__ double sh[256];
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(256) k_st_end(Topo tp, T req, T gam, const T *
     const int t = tp.A + f;
     const T a = sa[tp.snk_drv[t]] + dnl[t];
     sa[tp.M + t] = a;
-    const T z = (a - req) / gam;  // -slack / g
+    const T z = (a - (T)inst_req[tp.ff_inst[f]]) / gam;  // -slack / g
     const T sp = (z > 0 ? z : (T)0) + log1p(exp(-fabs(z)));
     acc += (double)(-gam * sp);
     adj[tp.M + t] = -(T)1 / ((T)1 + exp(-z));
@@ -188,8 +189,7 @@ void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, dou
       hipLaunchKernelGGL(k_st_fwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
                          (const T *)g->st_dnet, (const T *)g->darc, (T *)g->st_at);
   }
-  const T req = (T)g->clock_period - (T)g->setup;
-  hipLaunchKernelGGL(k_st_end<T>, dim3(RED_BLOCKS), dim3(256), 0, s, tp, req, gam, (const T *)g->st_dnet,
+  hipLaunchKernelGGL(k_st_end<T>, dim3(RED_BLOCKS), dim3(256), 0, s, tp, g->d_inst_req, gam, (const T *)g->st_dnet,
                      (T *)g->st_at, (T *)g->st_adj, g->red_loss);
   hipLaunchKernelGGL(k_sum_parts2, dim3(1), dim3(256), 0, s, RED_BLOCKS, g->red_loss, val);
   g->st_gamma = gamma;

@@ -28,6 +28,19 @@
 
 namespace tdp {
 
+// {arrival, transition} of a driver, one load in the forward gathers
+template <typename T> struct vec2_of;
+template <> struct vec2_of<float> { using type = float2; };
+template <> struct vec2_of<double> { using type = double2; };
+template <typename T> using V2 = typename vec2_of<T>::type;
+template <typename T>
+__device__ __forceinline__ V2<T> v2(T a, T b) {
+  V2<T> w;
+  w.x = a;
+  w.y = b;
+  return w;
+}
+
 template <typename T> __device__ __forceinline__ T pos_inf();
 template <> __device__ __forceinline__ float pos_inf<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double pos_inf<double>() { return __builtin_huge_val(); }
@@ -105,13 +118,14 @@ struct FlowInit {
 
 template <typename T>
 __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, int v, T ld, T in_slew, T clk_slew,
-                                            T *__restrict__ at, T *__restrict__ slew, int32_t *__restrict__ cdep,
-                                            const FlowInit &fl) {
+                                            T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
+                                            int32_t *__restrict__ cdep, const FlowInit &fl) {
   T a = 0, s = in_slew;
   if (v >= tp.n_pi && v < tp.n_start) lut_pair<T>(L, tp.ff_type[v - tp.n_pi], clk_slew, ld, a, s);
   if (v < tp.n_start) {
     at[v] = a;
     slew[v] = s;
+    as[v] = v2<T>(a, s);
     cdep[v] = 0;
   }
   if (fl.w) {  // reset (or seed) the words the dataflow sweeps poll
@@ -133,8 +147,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, T kappa,
                                                   T cw, T in_slew,
                                                   T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
-                                                  T *__restrict__ at, T *__restrict__ slew,
-                                                  int32_t *__restrict__ cdep, FlowInit fl) {
+                                                  T *__restrict__ dnet_nm, T *__restrict__ at, T *__restrict__ slew,
+                                                  V2<T> *__restrict__ as, int32_t *__restrict__ cdep, FlowInit fl) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && fl.err) *fl.err = 0;
   if (fl.tickets && blockIdx.x == 0 && threadIdx.x < 4) fl.tickets[threadIdx.x] = 0;
   const int lane = wave_lane();
@@ -154,12 +168,16 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
   const T oxd = __shfl(ox, head, 64), oyd = __shfl(oy, head, 64);
   const bool sink = p >= 0 && lane != head;
   const T len = sink ? fabs((cxd - cx) + (oxd - ox)) + fabs((cyd - cy) + (oyd - oy)) : (T)0;
-  if (sink) dnet[p - tp.M] = kappa * len * len;
+  if (sink) {
+    const T dn = kappa * len * len;
+    dnet[p - tp.M] = dn;
+    dnet_nm[k] = dn;
+  }
   const T wl = seg_sum(len, lane, head, tail);
   if (p >= 0 && lane == head) {
     const T ld = (T)tp.net_cpin[p] + cw * wl;
     load[p] = ld;
-    start_point<T>(tp, L, p, ld, in_slew, clk_slew, at, slew, cdep, fl);
+    start_point<T>(tp, L, p, ld, in_slew, clk_slew, at, slew, as, cdep, fl);
   }
 }
 
@@ -167,7 +185,8 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
 template <typename T>
 __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, const float *__restrict__ y, T kappa,
                               T cw, T in_slew, T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
-                              T *__restrict__ at, T *__restrict__ slew, int32_t *__restrict__ cdep) {
+                              T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
+                              int32_t *__restrict__ cdep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= tp.n_big) return;
   const int v = tp.big_net[i];
@@ -184,7 +203,7 @@ __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, c
   }
   const T ld = (T)tp.net_cpin[v] + cw * wl;
   load[v] = ld;
-  start_point<T>(tp, L, v, ld, in_slew, clk_slew, at, slew, cdep, FlowInit{});
+  start_point<T>(tp, L, v, ld, in_slew, clk_slew, at, slew, as, cdep, FlowInit{});
 }
 
 // insert (c, p) into the ascending list (kc, kp); an entry equal to existing
@@ -209,7 +228,7 @@ __device__ __forceinline__ void insert_front(T (&kc)[KM], int32_t (&kp)[KM], T c
 template <typename T, int KM>
 __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, int ch1, const T *__restrict__ load,
                                                   const T *__restrict__ dnet, T *__restrict__ at,
-                                                  T *__restrict__ slew, T *__restrict__ darc,
+                                                  T *__restrict__ slew, V2<T> *__restrict__ as, T *__restrict__ darc,
                                                   int32_t *__restrict__ crit, int4 *__restrict__ hop,
                                                   int32_t *__restrict__ cdep, T *__restrict__ side_cost,
                                                   int32_t *__restrict__ side_pin) {
@@ -225,12 +244,16 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
   const int t = rec.x, s = rec.y, c = rec.z;
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   const bool valid = t >= 0;
+  // the external ids of every lane's sink and driver come with the static
+  // data; the head takes the critical input's by shuffle
+  const int2 ex = valid ? tp.fw_ext[k] : make_int2(0, 0);
   T a = -pos_inf<T>(), o = 0;
   if (valid) {
     const T ld = load[tp.n_start + c];
-    const T a_in = at[s] + dnet[t];
+    const V2<T> w = as[s];
+    const T a_in = w.x + dnet[t];
     T d;
-    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, rec.w >> 16, slew[s], ld, d, o);
+    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, rec.w >> 16, w.y, ld, d, o);
     at[tp.M + t] = a_in;
     darc[t] = d;
     a = a_in + d;
@@ -242,15 +265,17 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
   const int argl = arg0 <= tail ? arg0 : head;
   const int tc = __shfl(t, argl & 63, 64);
   const int pred = __shfl(s, argl & 63, 64);
+  const int2 exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
   const bool is_head = valid && lane == head;
   if (is_head) {
     const int v = tp.n_start + c;
     at[v] = best;
     slew[v] = so;
+    as[v] = v2<T>(best, so);
     crit[c] = argl - head;
     // critical input, its driver and their external ids: one record per hop
     // of a path walk
-    hop[c] = make_int4(tc, pred, tp.snk_ext[tc], tp.drv_ext[pred]);
+    hop[c] = make_int4(tc, pred, exc.x, exc.y);
     cdep[v] = cdep[pred] + 1;
   }
   if constexpr (KM > 1) {
@@ -291,17 +316,17 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
 
 // ------------------------------------------------------------- endpoints
 template <typename T>
-__global__ void __launch_bounds__(256) k_endpoint(Topo tp, T req, const T *__restrict__ dnet, T *__restrict__ at,
-                                                   T *__restrict__ rat, T *__restrict__ slack,
-                                                   T *__restrict__ ep_slack) {
+__global__ void __launch_bounds__(256) k_endpoint(Topo tp, const double *__restrict__ inst_req,
+                                                   const T *__restrict__ dnet, T *__restrict__ at,
+                                                   T *__restrict__ rat, T *__restrict__ ep_slack) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= tp.E) return;
   const int t = tp.A + f;
+  const T req = (T)inst_req[tp.ff_inst[f]];
   const T a = at[tp.snk_drv[t]] + dnet[t];
   const T s = req - a;
   at[tp.M + t] = a;
   rat[tp.M + t] = req;
-  slack[tp.M + t] = s;
   ep_slack[f] = s;
 }
 
@@ -365,29 +390,19 @@ __global__ void k_ep_final(int num_inst, int chunks, const double *__restrict__ 
 // ------------------------------------------------------------- backward
 // A net's pass gives each of its sinks its required time (a combinational
 // input: its cell output's minus the arc delay; a flip-flop D pin: set at the
-// endpoint) and slack, then its driver the minimum over the sinks of (sink
-// required time - net delay) and the driver's slack.
+// endpoint), then its driver the minimum over the sinks of (sink required
+// time - net delay).  Slack is rat - at, formed where it is exported.  The
+// net delays are read in chunk-slot order (dnet_nm).
 template <typename T>
-__device__ __forceinline__ T sink_required(int p, T r_out, T da, const T *__restrict__ at, T *__restrict__ rat,
-                                           T *__restrict__ slack) {
-  const bool fin = r_out != pos_inf<T>();
-  const T ri = fin ? r_out - da : pos_inf<T>();
+__device__ __forceinline__ T sink_required(int p, T r_out, T da, T *__restrict__ rat) {
+  const T ri = r_out != pos_inf<T>() ? r_out - da : pos_inf<T>();
   rat[p] = ri;
-  slack[p] = fin ? ri - at[p] : pos_inf<T>();
   return ri;
 }
 
 template <typename T>
-__device__ __forceinline__ void driver_required(int v, T r, const T *__restrict__ at, T *__restrict__ rat,
-                                                T *__restrict__ slack) {
-  rat[v] = r;
-  slack[v] = r != pos_inf<T>() ? r - at[v] : pos_inf<T>();
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_backward(Topo tp, int ch0, int ch1, const T *__restrict__ dnet,
-                                                   const T *__restrict__ darc, const T *__restrict__ at,
-                                                   T *__restrict__ rat, T *__restrict__ slack) {
+__global__ void __launch_bounds__(256) k_backward(Topo tp, int ch0, int ch1, const T *__restrict__ dnet_nm,
+                                                   const T *__restrict__ darc, T *__restrict__ rat) {
   const int lane = wave_lane();
   const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= ch1) return;
@@ -397,17 +412,17 @@ __global__ void __launch_bounds__(256) k_backward(Topo tp, int ch0, int ch1, con
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   T r = pos_inf<T>();
   if (p >= 0 && lane != head) {
-    const int t = p - tp.M;
-    const T rt = vo >= 0 ? sink_required<T>(p, rat[vo], darc[t], at, rat, slack) : rat[p];
-    if (rt != pos_inf<T>()) r = rt - dnet[t];
+    const T dn = dnet_nm[k];
+    const T rt = vo >= 0 ? sink_required<T>(p, rat[vo], darc[p - tp.M], rat) : rat[p];
+    if (rt != pos_inf<T>()) r = rt - dn;
   }
   r = seg_min(r, lane, head, tail);
-  if (p >= 0 && lane == head) driver_required<T>(p, r, at, rat, slack);
+  if (p >= 0 && lane == head) rat[p] = r;
 }
 
 template <typename T>
 __global__ void k_backward_big(Topo tp, int i0, int i1, const T *__restrict__ dnet, const T *__restrict__ darc,
-                               const T *__restrict__ at, T *__restrict__ rat, T *__restrict__ slack) {
+                               T *__restrict__ rat) {
   const int i = i0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= i1) return;
   const int v = tp.big_net[i];
@@ -415,18 +430,12 @@ __global__ void k_backward_big(Topo tp, int i0, int i1, const T *__restrict__ dn
   for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
     const int t = tp.net_sink[k];
     const int p = tp.M + t;
-    T rt;
-    if (t < tp.A) {
-      const int vo = tp.n_start + tp.snk_comb[t];
-      rt = sink_required<T>(p, rat[vo], darc[t], at, rat, slack);
-    } else {
-      rt = rat[p];
-    }
+    const T rt = t < tp.A ? sink_required<T>(p, rat[tp.n_start + tp.snk_comb[t]], darc[t], rat) : rat[p];
     if (rt == pos_inf<T>()) continue;
     const T q = rt - dnet[t];
     r = q < r ? q : r;
   }
-  driver_required<T>(v, r, at, rat, slack);
+  rat[v] = r;
 }
 
 // ------------------------------------------------------ dataflow sweeps
@@ -560,11 +569,10 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
 
 // Backward: a sink lane polls the required time of its cell's output (the D
 // pin of a flip-flop needs nothing); the driver lane publishes its own.
-__global__ void __launch_bounds__(256) k_backward_flow(Topo tp, float req, const float *__restrict__ dnet,
-                                                        const float *__restrict__ darc, const float *__restrict__ at,
-                                                        float *__restrict__ rat, float *__restrict__ slack,
-                                                        uint32_t *__restrict__ fr, int32_t *__restrict__ ticket,
-                                                        int32_t *__restrict__ err, int limit) {
+__global__ void __launch_bounds__(256) k_backward_flow(Topo tp, const float *__restrict__ dnet_nm,
+                                                        const float *__restrict__ darc, float *__restrict__ rat,
+                                                        uint32_t *__restrict__ fr, int32_t *__restrict__ err,
+                                                        int limit) {
   const int lane = wave_lane();
   const float inf = __builtin_huge_valf();
   const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -581,20 +589,20 @@ __global__ void __launch_bounds__(256) k_backward_flow(Topo tp, float req, const
     // static data first, then the wave's representative: outputs are numbered
     // in production order of the forward sweep, so the backward sweep
     // publishes the lowest one last
-    const float dn = sink ? dnet[t] : 0.f, da = comb_in ? darc[t] : 0.f;
+    const float dn = sink ? dnet_nm[k] : 0.f, da = comb_in ? darc[t] : 0.f;
+    const float rq = sink && !comb_in ? rat[p] : 0.f;  // a D pin's, set at the endpoint
     const int v_rep = -wave_max_int(comb_in ? -vo : 1);
     if (v_rep >= 0) wait_rep(&fr[v_rep], R_EMPTY, err, limit);
     float r = inf;
     if (sink) {
       // a flip-flop D pin's required time was set at the endpoint
-      const float rt = comb_in ? sink_required<float>(p, __uint_as_float(wait_pub(&fr[vo], R_EMPTY, err, limit)),
-                                                      da, at, rat, slack)
-                               : req;
+      const float rt =
+          comb_in ? sink_required<float>(p, __uint_as_float(wait_pub(&fr[vo], R_EMPTY, err, limit)), da, rat) : rq;
       if (rt != inf) r = rt - dn;
     }
     r = seg_min(r, lane, head, tail);
     if (p >= 0 && lane == head) {
-      driver_required<float>(p, r, at, rat, slack);
+      rat[p] = r;
       pub_st(&fr[p], __float_as_uint(r));
     }
   }
@@ -603,7 +611,7 @@ __global__ void __launch_bounds__(256) k_backward_flow(Topo tp, float req, const
 // --------------------------------------------------------------- export
 template <typename T>
 __global__ void __launch_bounds__(256) k_export(Topo tp, const T *__restrict__ at, const T *__restrict__ rat,
-                                                 const T *__restrict__ slack, const T *__restrict__ slew,
+                                                 const T *__restrict__ slew,
                                                  const T *__restrict__ dnet, const T *__restrict__ load,
                                                  const T *__restrict__ darc, double *o_at, double *o_rat,
                                                  double *o_slack, double *o_slew, double *o_dnet,
@@ -615,7 +623,7 @@ __global__ void __launch_bounds__(256) k_export(Topo tp, const T *__restrict__ a
   const int t = i - tp.M;
   if (o_at) o_at[p] = (double)at[i];
   if (o_rat) o_rat[p] = (double)rat[i];
-  if (o_slack) o_slack[p] = (double)slack[i];
+  if (o_slack) o_slack[p] = (double)(rat[i] != pos_inf<T>() ? rat[i] - at[i] : pos_inf<T>());
   if (o_slew) o_slew[p] = (double)(sink ? slew[tp.snk_drv[t]] : slew[i]);
   if (o_dnet) o_dnet[p] = sink ? (double)dnet[t] : 0.0;
   if (o_load) o_load[p] = sink ? 0.0 : (double)load[i];
@@ -640,7 +648,8 @@ template <typename T, int KM>
 static void launch_forward(tdp_graph g, int ch0, int ch1, hipStream_t s) {
   const Topo &tp = g->topo;
   hipLaunchKernelGGL((k_forward<T, KM>), dim3(nblk(ch1 - ch0, 4)), dim3(256), lut_bytes(g->lut), s, tp, g->lut, ch0,
-                     ch1, (const T *)g->load, (const T *)g->dnet, (T *)g->at, (T *)g->slew, (T *)g->darc, g->crit,
+                     ch1, (const T *)g->load, (const T *)g->dnet, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as,
+                     (T *)g->darc, g->crit,
                      (int4 *)g->hop, g->cdep, (T *)g->side_cost, g->side_pin);
 }
 
@@ -696,12 +705,12 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
   prof_begin(g, TDP_STAGE_NETPASS, s);
   pack_xy(x, y, g->xy, tp.N, s);
   hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, kappa,
-                     (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
-                     (T *)g->slew, g->cdep, fl);
+                     (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
+                     (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
   if (tp.n_big > 0)
     hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, kappa,
                        (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
-                       (T *)g->slew, g->cdep);
+                       (T *)g->slew, (V2<T> *)g->drv_as, g->cdep);
   prof_end(g, TDP_STAGE_NETPASS, s);
   prof_begin(g, TDP_STAGE_FORWARD, s);
   if (flow) {
@@ -714,10 +723,9 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
   }
   prof_end(g, TDP_STAGE_FORWARD, s);
   prof_begin(g, TDP_STAGE_ENDPOINT, s);
-  const T req = (T)g->clock_period - (T)g->setup;
   if (tp.E > 0)
-    hipLaunchKernelGGL(k_endpoint<T>, dim3(nblk(tp.E, 256)), dim3(256), 0, s, tp, req, (const T *)g->dnet,
-                       (T *)g->at, (T *)g->rat, (T *)g->slack, (T *)g->ep_slack);
+    hipLaunchKernelGGL(k_endpoint<T>, dim3(nblk(tp.E, 256)), dim3(256), 0, s, tp, g->d_inst_req, (const T *)g->dnet,
+                       (T *)g->at, (T *)g->rat, (T *)g->ep_slack);
   hipLaunchKernelGGL(k_ep_partial<T>, dim3(tp.num_inst * g->ep_chunks), dim3(256), 0, s, g->d_ep_base,
                      g->ep_chunks, (const T *)g->ep_slack, g->red_ep);
   hipLaunchKernelGGL(k_ep_final, dim3(nblk(tp.num_inst, 64)), dim3(64), 0, s, tp.num_inst, g->ep_chunks, g->red_ep,
@@ -726,22 +734,21 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
   prof_begin(g, TDP_STAGE_BACKWARD, s);
   if (flow) {
     const int w = g->flow_waves;
-    hipLaunchKernelGGL(k_backward_flow, dim3(nblk(tp.n_nm_chunks, w)), dim3(64 * w), 0, s, tp, (float)req,
-                       (const float *)g->dnet,
-                       (const float *)g->darc, (const float *)g->at, (float *)g->rat, (float *)g->slack, g->flow_r,
-                       g->tickets + 1, g->d_err, g->spin_limit);
+    hipLaunchKernelGGL(k_backward_flow, dim3(nblk(tp.n_nm_chunks, w)), dim3(64 * w), 0, s, tp,
+                       (const float *)g->dnet_nm, (const float *)g->darc, (float *)g->rat, g->flow_r, g->d_err,
+                       g->spin_limit);
     prof_end(g, TDP_STAGE_BACKWARD, s);
     return;
   }
   for (int l = tp.D; l >= 0; --l) {
     const int ch0 = g->lv.nm_lvl[l], ch1 = g->lv.nm_lvl[l + 1];
     if (ch1 > ch0)
-      hipLaunchKernelGGL(k_backward<T>, dim3(nblk(ch1 - ch0, 4)), dim3(256), 0, s, tp, ch0, ch1, (const T *)g->dnet,
-                         (const T *)g->darc, (const T *)g->at, (T *)g->rat, (T *)g->slack);
+      hipLaunchKernelGGL(k_backward<T>, dim3(nblk(ch1 - ch0, 4)), dim3(256), 0, s, tp, ch0, ch1,
+                         (const T *)g->dnet_nm, (const T *)g->darc, (T *)g->rat);
     const int b0 = g->lv.big_lvl[l], b1 = g->lv.big_lvl[l + 1];
     if (b1 > b0)
       hipLaunchKernelGGL(k_backward_big<T>, dim3(nblk(b1 - b0, 64)), dim3(64), 0, s, tp, b0, b1, (const T *)g->dnet,
-                         (const T *)g->darc, (const T *)g->at, (T *)g->rat, (T *)g->slack);
+                         (const T *)g->darc, (T *)g->rat);
   }
   prof_end(g, TDP_STAGE_BACKWARD, s);
 }
@@ -751,7 +758,7 @@ void sta_export_impl(tdp_graph g, double *at, double *rat, double *slack, double
                      double *load, double *darc, hipStream_t s) {
   const Topo &tp = g->topo;
   hipLaunchKernelGGL(k_export<T>, dim3(nblk(tp.P, 256)), dim3(256), 0, s, tp, (const T *)g->at,
-                     (const T *)g->rat, (const T *)g->slack, (const T *)g->slew, (const T *)g->dnet,
+                     (const T *)g->rat, (const T *)g->slew, (const T *)g->dnet,
                      (const T *)g->load, (const T *)g->darc, at, rat, slack, slew, dnet, load, darc);
 }
 

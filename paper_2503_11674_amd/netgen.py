@@ -91,23 +91,27 @@ def batch_configs() -> List[NetlistConfig]:
     return out
 
 
-# the snapshot netlist of the batch: 500k cells, depth 50, 8 jittered copies
-SNAPSHOT_CONFIG = NetlistConfig("S500k", 500_000, depth=50, fanout_cap=32, die=5000.0, placement="gmm",
-                                seed=32, top_k_paths=5000)
+# the snapshot netlist of the batch: 500k cells, depth 60, 10 % flip-flops,
+# die side scaled with sqrt(N) like the uneven netlists
+SNAPSHOT_CONFIG = NetlistConfig("S500k", 500_000, depth=60, fanout_cap=32, die=1000.0 * math.sqrt(8.0),
+                                placement="gmm", seed=100, top_k_paths=5000)
 
 
 def batch_workload(num_snapshots: int = 8, sigma: float = 5.0,
                    snapshot_cells: Optional[int] = None) -> List[Dict[str, np.ndarray]]:
     """The batched workload: the 32 uneven netlists of batch_configs(), then
-    num_snapshots placement snapshots of one netlist (positions + N(0, sigma^2)
-    per snapshot; the snapshots share every other array with the first).
-    Clock periods are left to the caller."""
+    num_snapshots placement snapshots of one netlist (positions + N(0, sigma^2),
+    jitter seeds 1001, 1002, ...; the snapshots share every other array).  A
+    snapshot also carries the unperturbed positions as x_base / y_base: its
+    clock period is the one of the unperturbed placement.  Clock periods are
+    left to the caller."""
     out = [make_netlist(c) for c in batch_configs()]
     cfg = SNAPSHOT_CONFIG if snapshot_cells is None else scaled(SNAPSHOT_CONFIG, snapshot_cells)
     base = make_netlist(cfg)
     for i in range(num_snapshots):
         snap = dict(base)
-        snap["x"], snap["y"] = jitter_positions(base, sigma, seed=1000 + i)
+        snap["x"], snap["y"] = jitter_positions(base, sigma, seed=1001 + i)
+        snap["x_base"], snap["y_base"] = base["x"], base["y"]
         out.append(snap)
     return out
 

@@ -85,6 +85,8 @@ tdp_pairs_import = _sig("tdp_pairs_import", _p, _p, _p, _p)
 tdp_pairs_count = _sig("tdp_pairs_count", _p, _P(_i32), _p)
 tdp_p2p_loss_fwd = _sig("tdp_p2p_loss_fwd", _p, _p, _p, _p, _p)
 tdp_p2p_loss_bwd = _sig("tdp_p2p_loss_bwd", _p, _p, _p, _p, _p, _p, _p)
+tdp_pair_loss_fwd = _sig("tdp_pair_loss_fwd", _p, _i32, _p, _p, _p, _p)
+tdp_pair_loss_bwd = _sig("tdp_pair_loss_bwd", _p, _i32, _p, _p, _p, _p, _p, _p)
 tdp_stns_fwd = _sig("tdp_stns_fwd", _p, _p, _p, _f32, _p, _p)
 tdp_stns_bwd = _sig("tdp_stns_bwd", _p, _p, _p, _p, _p)
 tdp_wa_fwd_bwd = _sig("tdp_wa_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p)
@@ -103,7 +105,8 @@ tdp_last_error.argtypes = [_p]
 EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destroy", "tdp_sta_set_clock",
             "tdp_sta_update", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit",
             "tdp_extract_paths", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
-            "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd", "tdp_stns_fwd",
+            "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
+            "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
             "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
             "tdp_autotune", "tdp_graph_info", "tdp_status_str", "tdp_last_error"]
 
@@ -318,6 +321,17 @@ class TimingGraph:
         _check(tdp_p2p_loss_bwd(self.h, _ptr(x), _ptr(y), _ptr(_f64_scalar(gout)), _ptr(gx), _ptr(gy),
                                 _stream(stream)), self.h)
 
+    def pair_loss_fwd(self, kind: int, x, y, out=None, stream=None) -> torch.Tensor:
+        """kind 0: PP (quadratic); 1: Manhattan; 2: linear Euclidean."""
+        out = _scalar_out(out, x.device)
+        _check(tdp_pair_loss_fwd(self.h, kind, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _ptr(out), _stream(stream)),
+               self.h)
+        return out
+
+    def pair_loss_bwd(self, kind: int, x, y, gout, gx, gy, stream=None):
+        _check(tdp_pair_loss_bwd(self.h, kind, _ptr(x), _ptr(y), _ptr(_f64_scalar(gout)), _ptr(gx), _ptr(gy),
+                                 _stream(stream)), self.h)
+
     def stns_fwd(self, x, y, gamma: float = 10.0, out=None, stream=None) -> torch.Tensor:
         out = _scalar_out(out, x.device)
         _check(tdp_stns_fwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _stream(stream)), self.h)
@@ -413,6 +427,25 @@ class P2PLoss(torch.autograd.Function):
         gy = torch.zeros_like(y)
         ctx.graph.p2p_loss_bwd(x, y, gout, gx, gy)
         return gx, gy, None
+
+
+class PairLoss(torch.autograd.Function):
+    """A pair distance loss over the graph's pin-pair set: kind 0 quadratic
+    (PP), 1 Manhattan, 2 linear Euclidean (the comparison of Sec. III-C)."""
+
+    @staticmethod
+    def forward(ctx, x, y, graph: TimingGraph, kind: int = 0):
+        ctx.graph, ctx.kind = graph, kind
+        ctx.save_for_backward(x, y)
+        return graph.pair_loss_fwd(kind, x.contiguous(), y.contiguous())
+
+    @staticmethod
+    def backward(ctx, gout):
+        x, y = ctx.saved_tensors
+        gx = torch.zeros_like(x)
+        gy = torch.zeros_like(y)
+        ctx.graph.pair_loss_bwd(ctx.kind, x, y, gout, gx, gy)
+        return gx, gy, None, None
 
 
 class SmoothTNS(torch.autograd.Function):

@@ -485,3 +485,46 @@ def test_autotune_keeps_results(library):
     with pytest.raises(tdp.TdpError):
         g.autotune(c["x"], c["y"], reps=0)
     g.close()
+
+
+# ------------------------------------------------------ pair-loss variants
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_pair_loss_variants(library, kind):
+    """The three pair distances of Sec. III-C over the GPU's pair set, value
+    and gradient against the oracle (per cell: 1e-4 of the summed magnitudes
+    of the terms that reach it)."""
+    tdp = _tdp()
+    c = case("C2", library)
+    nl, g = c["nl"], c["g"]
+    g.pairs_reset()
+    g.extract_paths(n=-1, k=c["k"], K=c["K"])
+    g.pairs_update(rule=1)
+    w, in_p = g.pairs_export()
+    sinks = np.nonzero(in_p)[0]
+    ws = w[sinks].astype(np.float64)
+    if kind == 0:
+        v_ref, gx_ref, gy_ref = ref.p2p(nl, sinks, ws)
+        scale = _p2p_abs_scale(nl, sinks, w[sinks])
+    else:
+        v_ref, gx_ref, gy_ref = ref.pair_loss(nl, kind, sinks, ws)
+        # every term's gradient has magnitude at most w per axis
+        gr = Graph(nl)
+        pc = nl["pin_cell"]
+        scale = np.zeros(nl["num_cells"])
+        for t, wt in zip(sinks, ws):
+            for q in (gr.driver[t], t):
+                if pc[q] >= 0:
+                    scale[pc[q]] += wt
+    xr = c["x"].clone().requires_grad_(True)
+    yr = c["y"].clone().requires_grad_(True)
+    v = tdp.PairLoss.apply(xr, yr, g, kind)
+    v.backward()
+    assert abs(float(v) - v_ref) <= 1e-4 * abs(v_ref)
+    ex = np.abs(xr.grad.cpu().numpy() - gx_ref)
+    ey = np.abs(yr.grad.cpu().numpy() - gy_ref)
+    print("kind", kind, "worst scaled error", (ex / np.maximum(scale, 1e-12)).max())
+    assert np.all(ex <= 1e-4 * scale + 1e-6) and np.all(ey <= 1e-4 * scale + 1e-6)
+    if kind == 0:  # the variant entry equals the p2p entry bitwise
+        assert float(g.pair_loss_fwd(0, c["x"], c["y"])) == float(g.p2p_loss_fwd(c["x"], c["y"]))
+    with pytest.raises(tdp.TdpError):
+        g.pair_loss_fwd(3, c["x"], c["y"])
