@@ -161,7 +161,7 @@ def main():
         g.pairs_update(rule=0, w0=10.0, w1=0.2)
         gx.zero_()
         gy.zero_()
-        g.wa_fwd_bwd(x, y, WA_GAMMA, gx, gy, out=wl)
+        g.wa_fwd_bwd_at_update(WA_GAMMA, gx, gy, out=wl)  # positions of this step's update
         g.p2p_loss_fwd(x, y, out=pp)
         g.p2p_loss_bwd(x, y, beta, gx, gy)
 

@@ -244,6 +244,13 @@ tdp_status tdp_stns_bwd(tdp_graph, const double *d_gout, float *d_gx, float *d_g
  * d_gx/d_gy [num_cells] += gradient (movable cells only). */
 tdp_status tdp_wa_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float gamma_um, double *d_wl,
                           float *d_gx, float *d_gy, hipStream_t);
+/* The same at the positions of the last tdp_sta_update, reusing the cell
+ * coordinates that update gathered per pin (a coalesced read instead of a
+ * random one per pin).  The caller must not have changed those positions
+ * since; results are then bitwise those of tdp_wa_fwd_bwd.  TDP_E_STATE
+ * before the first update. */
+tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph, float gamma_um, double *d_wl, float *d_gx, float *d_gy,
+                                    hipStream_t);
 
 /* ------------------------------------------------------------ tooling */
 /* Stage timing: when enabled, every call records HIP events around its

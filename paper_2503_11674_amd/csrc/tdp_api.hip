@@ -167,6 +167,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   ok = ok && dalloc(g, g->load, T.M, es) && dalloc(g, g->dnet, T.S, es) && dalloc(g, g->at, T.P, es) &&
        dalloc(g, g->slew, T.M, es) && dalloc(g, g->rat, T.P, es) &&
        dalloc(g, g->dnet_nm, (size_t)T.n_nm_chunks * CHUNK, es) && dalloc(g, g->drv_as, (size_t)2 * T.M, es) &&
+       dalloc(g, g->fw_a, (size_t)T.n_fw_chunks * CHUNK, es) &&
        dalloc(g, g->darc, T.A, es) && dalloc(g, g->crit, T.n_comb) && dalloc(g, g->hop, (size_t)T.n_comb * 4) &&
        dalloc(g, g->cdep, T.M) && dalloc(g, g->ep_slack, T.E, es) &&
        dalloc(g, g->red_ep, (size_t)3 * T.num_inst * g->ep_chunks) && dalloc(g, g->red_loss, 4096) &&
@@ -214,7 +215,8 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        dalloc(g, g->inc_w, (size_t)2 * T.S);
   // smoothed TNS, WA
   ok = ok && dalloc(g, g->st_at, T.P, es) && dalloc(g, g->st_adj, T.P, es) && dalloc(g, g->st_dnet, T.S, es) &&
-       dalloc(g, g->wa_gpin, (size_t)2 * T.P) && dalloc(g, g->xy, T.N);
+       dalloc(g, g->wa_gpin, (size_t)2 * T.P) && dalloc(g, g->xy, T.N) &&
+       dalloc(g, g->xy_wa, T.N) && dalloc(g, g->cxy_nm, (size_t)T.n_nm_chunks * CHUNK);
   if (!ok || hipDeviceSynchronize() != hipSuccess) {
     free_all(g);
     delete g;
@@ -521,6 +523,15 @@ tdp_status tdp_wa_fwd_bwd(tdp_graph g, const float *x, const float *y, float gam
   if (!(gamma > 0) || !std::isfinite(gamma)) return fail(g, TDP_E_INVALID, "gamma must be > 0");
   wa_impl(g, x, y, gamma, wl, gx, gy, s);
   return check_launch(g, "wa_fwd_bwd");
+}
+
+tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph g, float gamma, double *wl, float *gx, float *gy, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (!wl || !gx || !gy) return fail(g, TDP_E_INVALID, "NULL argument");
+  if (!(gamma > 0) || !std::isfinite(gamma)) return fail(g, TDP_E_INVALID, "gamma must be > 0");
+  wa_impl(g, nullptr, nullptr, gamma, wl, gx, gy, s);
+  return check_launch(g, "wa_fwd_bwd_at_update");
 }
 
 tdp_status tdp_profile_enable(tdp_graph g, int32_t on) {

@@ -176,7 +176,7 @@ struct tdp_graph_s {
   // there); drv_as packs {arrival, transition} of each driver for the
   // forward passes' gathers.
   void *load = nullptr, *dnet = nullptr, *at = nullptr, *slew = nullptr, *rat = nullptr, *darc = nullptr,
-       *dnet_nm = nullptr, *drv_as = nullptr;
+       *dnet_nm = nullptr, *drv_as = nullptr, *fw_a = nullptr;
   int32_t *crit = nullptr;       // [n_comb] arc index of the critical input
   int32_t *hop = nullptr;        // [n_comb][4] {critical sink, its driver, their external ids}
   int32_t *cdep = nullptr;       // [M] combinational cells on the critical chain
@@ -233,7 +233,9 @@ struct tdp_graph_s {
 
   // weighted-average wirelength: per-pin gradient [2P]
   float *wa_gpin = nullptr;
-  float2 *xy = nullptr;        // [N] positions packed by the update and WA calls
+  float2 *xy = nullptr;        // [N] positions packed by the last timing update
+  float2 *xy_wa = nullptr;     // [N] positions packed by a WA call
+  float2 *cxy_nm = nullptr;    // [net-chunk slots] cell coordinates the last update gathered
 
   tdp::Profiler prof;
 };

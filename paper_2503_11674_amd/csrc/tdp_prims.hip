@@ -89,6 +89,40 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down(const int32_t *__restr
   }
 }
 
+// Second pass without a separate scan of the tile sums: every tile adds up
+// the sums of the tiles before it itself (a few thousand integers from L2),
+// which saves a launch; the last live tile writes the total.
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down_sum(const int32_t *__restrict__ in, int cap,
+                                                               const int32_t *d_n, const int32_t *__restrict__ part,
+                                                               int32_t *__restrict__ out, int32_t *d_total) {
+  __shared__ int sh[4];
+  __shared__ int offset;
+  const int n = live_count(cap, d_n);
+  const int tiles = n > 0 ? (n + SCAN_TILE - 1) / SCAN_TILE : 1;
+  if ((int)blockIdx.x >= tiles) return;
+  int acc = 0;
+  for (int i = threadIdx.x; i < (int)blockIdx.x; i += SCAN_BLOCK) acc += part[i];
+  acc = block_inclusive_scan(acc, sh);
+  if (threadIdx.x == SCAN_BLOCK - 1) offset = acc;
+  __syncthreads();
+  const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0;
+    s += v[i];
+  }
+  const int incl = block_inclusive_scan(s, sh);
+  int run = offset + incl - s;
+#pragma unroll
+  for (int i = 0; i < SCAN_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = run;
+    run += v[i];
+  }
+  if (d_total && (int)blockIdx.x == tiles - 1 && threadIdx.x == SCAN_BLOCK - 1) *d_total = offset + incl;
+}
+
 int scan_tmp_size(int cap) { return (cap + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
 void scan_exclusive(const int32_t *in, int32_t *out, int cap, const int32_t *d_n, int32_t *d_total,
@@ -99,6 +133,10 @@ void scan_exclusive(const int32_t *in, int32_t *out, int cap, const int32_t *d_n
   }
   int nb = (cap + SCAN_TILE - 1) / SCAN_TILE;
   hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_BLOCK), 0, s, in, cap, d_n, tmp);
+  if (nb <= 8192) {
+    hipLaunchKernelGGL(k_scan_down_sum, dim3(nb), dim3(SCAN_BLOCK), 0, s, in, cap, d_n, tmp, out, d_total);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_BLOCK), 0, s, tmp, nb, d_total);
   hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(SCAN_BLOCK), 0, s, in, cap, d_n, tmp, out);
 }

@@ -246,7 +246,10 @@ __device__ __forceinline__ float wa_lane(float c, float o, bool valid, int lane,
 }
 
 // chunked nets: value partials and the gradient of each pin (internal pin order)
-__global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float2 *__restrict__ xy, float gam,
+// cxy (optional): the cell coordinates of every slot, gathered by the last
+// timing update; otherwise they are gathered here from xy
+__global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float2 *__restrict__ xy,
+                                                 const float2 *__restrict__ cxy, float gam,
                                                  float *__restrict__ gpin, double *__restrict__ part) {
   __shared__ double sh[256];
   double acc = 0.0;
@@ -259,7 +262,7 @@ __global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float2 *__restric
     const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
     const bool valid = p >= 0;
     float gxp, gyp;
-    const float2 q = cell >= 0 ? xy[cell] : make_float2(0.f, 0.f);
+    const float2 q = cxy ? cxy[k] : (cell >= 0 ? xy[cell] : make_float2(0.f, 0.f));
     const float wx = wa_lane(q.x, tp.nm_ox[k], valid, lane, head, tail, ig, gxp);
     const float wy = wa_lane(q.y, tp.nm_oy[k], valid, lane, head, tail, ig, gyp);
     if (valid) {
@@ -278,8 +281,8 @@ __global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float2 *__restric
 }
 
 // nets wider than a chunk: one thread per net, same arithmetic
-__global__ void __launch_bounds__(64) k_wa_big(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
-                                                float gam, float *__restrict__ gpin, double *__restrict__ part) {
+__global__ void __launch_bounds__(64) k_wa_big(Topo tp, const float2 *__restrict__ xy, float gam,
+                                                float *__restrict__ gpin, double *__restrict__ part) {
   __shared__ double sh[64];
   double acc = 0.0;
   const float ig = 1.0f / gam;
@@ -288,19 +291,19 @@ __global__ void __launch_bounds__(64) k_wa_big(Topo tp, const float *__restrict_
     const int b = tp.net_ptr[v], e = tp.net_ptr[v + 1];
     const int dc = tp.drv_cell[v];
     for (int axis = 0; axis < 2; ++axis) {
-      const float *pc = axis ? y : x;
       const float *so = axis ? tp.snk_oy : tp.snk_ox;
-      const float pd = (dc >= 0 ? pc[dc] : 0.f) + (axis ? tp.drv_oy[v] : tp.drv_ox[v]);
+      auto pc = [&](int cell) { return axis ? xy[cell].y : xy[cell].x; };
+      const float pd = (dc >= 0 ? pc(dc) : 0.f) + (axis ? tp.drv_oy[v] : tp.drv_ox[v]);
       float mx = pd, mn = pd;
       for (int k = b; k < e; ++k) {
         const int t = tp.net_sink[k];
-        const float q = pc[tp.snk_cell[t]] + so[t];
+        const float q = pc(tp.snk_cell[t]) + so[t];
         mx = fmaxf(mx, q);
         mn = fminf(mn, q);
       }
       float sa = 0.f, sda = 0.f, sb = 0.f, seb = 0.f;
       for (int k = b - 1; k < e; ++k) {
-        const float q = k < b ? pd : pc[tp.snk_cell[tp.net_sink[k]]] + so[tp.net_sink[k]];
+        const float q = k < b ? pd : pc(tp.snk_cell[tp.net_sink[k]]) + so[tp.net_sink[k]];
         const float d = q - mx, ee = q - mn;
         const float a = expf(d * ig), bb = expf(-ee * ig);
         sa += a; sda += a * d; sb += bb; seb += bb * ee;
@@ -309,7 +312,7 @@ __global__ void __launch_bounds__(64) k_wa_big(Topo tp, const float *__restrict_
       acc += (double)((mx - mn) + fp - fm);
       for (int k = b - 1; k < e; ++k) {
         const int t = k < b ? -1 : tp.net_sink[k];
-        const float q = k < b ? pd : pc[tp.snk_cell[t]] + so[t];
+        const float q = k < b ? pd : pc(tp.snk_cell[t]) + so[t];
         const float d = q - mx, ee = q - mn;
         const float a = expf(d * ig), bb = expf(-ee * ig);
         const float gr = a / sa * (1.f + (d - fp) * ig) - bb / sb * (1.f - (ee - fm) * ig);
@@ -356,9 +359,16 @@ void wa_impl(tdp_graph g, const float *x, const float *y, float gamma, double *w
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_WA, s);
   constexpr int WB = RED_BLOCKS * 4, BB = 64;  // partial slots: chunked nets, then big nets
-  pack_xy(x, y, g->xy, tp.N, s);
-  hipLaunchKernelGGL(k_wa_net, dim3(WB), dim3(256), 0, s, tp, g->xy, gamma, g->wa_gpin, g->red_wa);
-  hipLaunchKernelGGL(k_wa_big, dim3(BB), dim3(64), 0, s, tp, x, y, gamma, g->wa_gpin, g->red_wa + WB);
+  // x == nullptr: the positions of the last timing update, whose cell
+  // coordinates per slot it already gathered
+  const float2 *xy = g->xy, *cxy = g->cxy_nm;
+  if (x) {
+    pack_xy(x, y, g->xy_wa, tp.N, s);
+    xy = g->xy_wa;
+    cxy = nullptr;
+  }
+  hipLaunchKernelGGL(k_wa_net, dim3(WB), dim3(256), 0, s, tp, xy, cxy, gamma, g->wa_gpin, g->red_wa);
+  hipLaunchKernelGGL(k_wa_big, dim3(BB), dim3(64), 0, s, tp, xy, gamma, g->wa_gpin, g->red_wa + WB);
   hipLaunchKernelGGL(k_sum_parts2, dim3(1), dim3(256), 0, s, WB + BB, g->red_wa, wl);
   hipLaunchKernelGGL(k_wa_cell, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->wa_gpin, gx, gy);
   prof_end(g, TDP_STAGE_WA, s);

@@ -147,7 +147,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, T kappa,
                                                   T cw, T in_slew,
                                                   T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
-                                                  T *__restrict__ dnet_nm, T *__restrict__ at, T *__restrict__ slew,
+                                                  T *__restrict__ dnet_nm, float2 *__restrict__ cxy_nm,
+                                                  T *__restrict__ at, T *__restrict__ slew,
                                                   V2<T> *__restrict__ as, int32_t *__restrict__ cdep, FlowInit fl) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && fl.err) *fl.err = 0;
   if (fl.tickets && blockIdx.x == 0 && threadIdx.x < 4) fl.tickets[threadIdx.x] = 0;
@@ -162,6 +163,7 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
   // (cell - cell) + (offset - offset), exact to the rounding of the result
   // rather than of a die-scale sum
   const float2 q = cell >= 0 ? xy[cell] : make_float2(0.f, 0.f);
+  cxy_nm[k] = q;  // kept for the weighted-average wirelength at these positions
   const T cx = (T)q.x, cy = (T)q.y;
   const T ox = (T)tp.nm_ox[k], oy = (T)tp.nm_oy[k];
   const T cxd = __shfl(cx, head, 64), cyd = __shfl(cy, head, 64);
@@ -225,16 +227,20 @@ __device__ __forceinline__ void insert_front(T (&kc)[KM], int32_t (&kp)[KM], T c
 }
 
 // -------------------------------------------------------------- forward
-template <typename T, int KM>
-__global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, int ch1, const T *__restrict__ load,
-                                                  const T *__restrict__ dnet, T *__restrict__ at,
-                                                  T *__restrict__ slew, V2<T> *__restrict__ as, T *__restrict__ darc,
-                                                  int32_t *__restrict__ crit, int4 *__restrict__ hop,
-                                                  int32_t *__restrict__ cdep, T *__restrict__ side_cost,
-                                                  int32_t *__restrict__ side_pin) {
-  extern __shared__ float s_lut[];
+// One launch per level l does two jobs in separate workgroups: the arrivals
+// of level l (the first n_arr workgroups) and, one level behind, the chain
+// depths and deviation lists of level l-1, whose critical inputs the previous
+// launch settled.  A cell's list extends its critical input's driver's list,
+// a dependent load; running it beside the next level's arrivals keeps that
+// round trip off the arrival chain.  fw_a keeps each input's arrival through
+// its arc (per chunk slot) for the list job.
+template <typename T>
+__device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, float *s_lut, int chunk, int ch1,
+                                            const T *__restrict__ load, const T *__restrict__ dnet,
+                                            T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
+                                            T *__restrict__ darc, int32_t *__restrict__ crit, int4 *__restrict__ hop,
+                                            T *__restrict__ fw_a) {
   const int lane = wave_lane();
-  const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
   const int k = chunk * CHUNK + lane;
   // the record load is issued before the tables are staged, so the two
   // latencies overlap
@@ -257,6 +263,7 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
     at[tp.M + t] = a_in;
     darc[t] = d;
     a = a_in + d;
+    fw_a[k] = a;
   }
   const T best = seg_max(a, lane, head, tail);
   const T so = seg_max(o, lane, head, tail);
@@ -266,8 +273,7 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
   const int tc = __shfl(t, argl & 63, 64);
   const int pred = __shfl(s, argl & 63, 64);
   const int2 exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
-  const bool is_head = valid && lane == head;
-  if (is_head) {
+  if (valid && lane == head) {
     const int v = tp.n_start + c;
     at[v] = best;
     slew[v] = so;
@@ -276,8 +282,28 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
     // critical input, its driver and their external ids: one record per hop
     // of a path walk
     hop[c] = make_int4(tc, pred, exc.x, exc.y);
-    cdep[v] = cdep[pred] + 1;
   }
+}
+
+template <typename T, int KM>
+__device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, const T *__restrict__ fw_a,
+                                         int32_t *__restrict__ cdep, T *__restrict__ side_cost,
+                                         int32_t *__restrict__ side_pin) {
+  if (chunk >= lc1) return;
+  const int lane = wave_lane();
+  const int k = chunk * CHUNK + lane;
+  const int4 rec = tp.fw_rec[k];
+  const int t = rec.x, s = rec.y, c = rec.z;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
+  const bool valid = t >= 0;
+  const T a = valid ? fw_a[k] : -pos_inf<T>();
+  // the same maximum and critical input as the arrival job found
+  const T best = seg_max(a, lane, head, tail);
+  const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
+  const int argl = arg0 <= tail ? arg0 : head;
+  const int pred = __shfl(s, argl & 63, 64);
+  const bool is_head = valid && lane == head;
+  if (is_head) cdep[tp.n_start + c] = cdep[pred] + 1;
   if constexpr (KM > 1) {
     const T dl = (valid && lane != argl) ? best - a : pos_inf<T>();
     const int width = wave_max_int(valid ? tail - head + 1 : 0);
@@ -312,6 +338,24 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
       }
     }
   }
+}
+
+// arrival chunks [ch0, ch1) in workgroups [0, n_arr); list chunks [lc0, lc1)
+// in the rest
+template <typename T, int KM>
+__global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, int ch1, int n_arr, int lc0, int lc1,
+                                                  const T *__restrict__ load, const T *__restrict__ dnet,
+                                                  T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
+                                                  T *__restrict__ darc, int32_t *__restrict__ crit,
+                                                  int4 *__restrict__ hop, int32_t *__restrict__ cdep,
+                                                  T *__restrict__ side_cost, int32_t *__restrict__ side_pin,
+                                                  T *__restrict__ fw_a) {
+  extern __shared__ float s_lut[];
+  const int wave = threadIdx.x >> 6;
+  if ((int)blockIdx.x < n_arr)
+    fw_arrivals<T>(tp, L, s_lut, ch0 + blockIdx.x * 4 + wave, ch1, load, dnet, at, slew, as, darc, crit, hop, fw_a);
+  else
+    fw_lists<T, KM>(tp, lc0 + (blockIdx.x - n_arr) * 4 + wave, lc1, fw_a, cdep, side_cost, side_pin);
 }
 
 // ------------------------------------------------------------- endpoints
@@ -645,23 +689,27 @@ static inline size_t lut_bytes(const LutView &L) {
 }
 
 template <typename T, int KM>
-static void launch_forward(tdp_graph g, int ch0, int ch1, hipStream_t s) {
+static void launch_forward(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipStream_t s) {
   const Topo &tp = g->topo;
-  hipLaunchKernelGGL((k_forward<T, KM>), dim3(nblk(ch1 - ch0, 4)), dim3(256), lut_bytes(g->lut), s, tp, g->lut, ch0,
-                     ch1, (const T *)g->load, (const T *)g->dnet, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as,
-                     (T *)g->darc, g->crit,
-                     (int4 *)g->hop, g->cdep, (T *)g->side_cost, g->side_pin);
+  const int n_arr = ch1 > ch0 ? nblk(ch1 - ch0, 4) : 0;
+  const int n_lst = lc1 > lc0 ? nblk(lc1 - lc0, 4) : 0;
+  if (n_arr + n_lst == 0) return;
+  hipLaunchKernelGGL((k_forward<T, KM>), dim3(n_arr + n_lst), dim3(256), n_arr ? lut_bytes(g->lut) : 0, s, tp,
+                     g->lut, ch0, ch1, n_arr, lc0, lc1, (const T *)g->load, (const T *)g->dnet, (T *)g->at,
+                     (T *)g->slew, (V2<T> *)g->drv_as, (T *)g->darc, g->crit, (int4 *)g->hop, g->cdep,
+                     (T *)g->side_cost, g->side_pin, (T *)g->fw_a);
 }
 
+// arrivals of chunks [ch0, ch1) and the lists of [lc0, lc1), the level before
 template <typename T>
-static void forward_level(tdp_graph g, int ch0, int ch1, hipStream_t s) {
+static void forward_level(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipStream_t s) {
   switch (g->side_k) {
-    case 1: launch_forward<T, 1>(g, ch0, ch1, s); break;
-    case 2: launch_forward<T, 2>(g, ch0, ch1, s); break;
-    case 4: launch_forward<T, 4>(g, ch0, ch1, s); break;
-    case 8: launch_forward<T, 8>(g, ch0, ch1, s); break;
-    case 16: launch_forward<T, 16>(g, ch0, ch1, s); break;
-    default: launch_forward<T, 32>(g, ch0, ch1, s); break;
+    case 1: launch_forward<T, 1>(g, ch0, ch1, lc0, lc1, s); break;
+    case 2: launch_forward<T, 2>(g, ch0, ch1, lc0, lc1, s); break;
+    case 4: launch_forward<T, 4>(g, ch0, ch1, lc0, lc1, s); break;
+    case 8: launch_forward<T, 8>(g, ch0, ch1, lc0, lc1, s); break;
+    case 16: launch_forward<T, 16>(g, ch0, ch1, lc0, lc1, s); break;
+    default: launch_forward<T, 32>(g, ch0, ch1, lc0, lc1, s); break;
   }
 }
 
@@ -706,7 +754,7 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
   pack_xy(x, y, g->xy, tp.N, s);
   hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, kappa,
                      (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
-                     (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
+                     g->cxy_nm, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
   if (tp.n_big > 0)
     hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, kappa,
                        (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
@@ -716,10 +764,15 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
   if (flow) {
     forward_flow(g, s);
   } else {
+    int lc0 = 0, lc1 = 0;  // the previous non-empty level, whose lists are due
     for (int l = 1; l <= tp.D; ++l) {
       const int ch0 = g->lv.fw_lvl[l - 1], ch1 = g->lv.fw_lvl[l];
-      if (ch1 > ch0) forward_level<T>(g, ch0, ch1, s);
+      if (ch1 <= ch0) continue;
+      forward_level<T>(g, ch0, ch1, lc0, lc1, s);
+      lc0 = ch0;
+      lc1 = ch1;
     }
+    forward_level<T>(g, 0, 0, lc0, lc1, s);
   }
   prof_end(g, TDP_STAGE_FORWARD, s);
   prof_begin(g, TDP_STAGE_ENDPOINT, s);

@@ -90,6 +90,7 @@ tdp_pair_loss_bwd = _sig("tdp_pair_loss_bwd", _p, _i32, _p, _p, _p, _p, _p, _p)
 tdp_stns_fwd = _sig("tdp_stns_fwd", _p, _p, _p, _f32, _p, _p)
 tdp_stns_bwd = _sig("tdp_stns_bwd", _p, _p, _p, _p, _p)
 tdp_wa_fwd_bwd = _sig("tdp_wa_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p)
+tdp_wa_fwd_bwd_at_update = _sig("tdp_wa_fwd_bwd_at_update", _p, _f32, _p, _p, _p, _p)
 tdp_profile_enable = _sig("tdp_profile_enable", _p, _i32)
 tdp_profile_read = _sig("tdp_profile_read", _p, _p, _p)
 tdp_set_tuning = _sig("tdp_set_tuning", _p, _i32, _i32, _i32)
@@ -107,7 +108,7 @@ EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destro
             "tdp_extract_paths", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
             "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
-            "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
+            "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_wa_fwd_bwd_at_update", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
             "tdp_autotune", "tdp_graph_info", "tdp_status_str", "tdp_last_error"]
 
 
@@ -344,6 +345,12 @@ class TimingGraph:
         out = _scalar_out(out, x.device)
         _check(tdp_wa_fwd_bwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _ptr(gx), _ptr(gy),
                               _stream(stream)), self.h)
+        return out
+
+    def wa_fwd_bwd_at_update(self, gamma: float, gx, gy, out=None, stream=None) -> torch.Tensor:
+        """WA at the positions of the last sta_update (unchanged since)."""
+        out = _scalar_out(out, gx.device)
+        _check(tdp_wa_fwd_bwd_at_update(self.h, gamma, _ptr(out), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
         return out
 
     # ----------------------------------------------------------- tooling

@@ -115,7 +115,7 @@ def test_full_size_step_2m_cells(library):
         g.pairs_update(rule=0, w0=10.0, w1=0.2)
         gx.zero_()
         gy.zero_()
-        g.wa_fwd_bwd(x, y, 5.0, gx, gy, out=wl)
+        g.wa_fwd_bwd_at_update(5.0, gx, gy, out=wl)
         g.p2p_loss_fwd(x, y, out=pp)
         g.p2p_loss_bwd(x, y, one, gx, gy)
 

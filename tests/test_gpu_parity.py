@@ -309,6 +309,12 @@ def test_wa_parity(name, library):
     print("WA worst scaled error", (ex / np.maximum(ax, 1e-12)).max(), (ey / np.maximum(ay, 1e-12)).max())
     assert np.all(ex <= 1e-4 * ax + 1e-7)
     assert np.all(ey <= 1e-4 * ay + 1e-7)
+    # at the last update's positions (the case's update used these): bitwise
+    gx2 = torch.zeros_like(c["x"])
+    gy2 = torch.zeros_like(c["y"])
+    g.sta_update(c["x"], c["y"])
+    v2 = g.wa_fwd_bwd_at_update(5.0, gx2, gy2)
+    assert float(v2) == float(v) and torch.equal(gx2, gx) and torch.equal(gy2, gy)
 
 
 # ------------------------------------------------------------ FP64 mode
