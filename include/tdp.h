@@ -156,6 +156,19 @@ tdp_status tdp_sta_set_clock(tdp_graph, float clock_period_ps, float setup_ps);
  * endpoint slacks and WNS / TNS / violated-endpoint count, required times and
  * slack backward.  Asynchronous. */
 tdp_status tdp_sta_update(tdp_graph, const float *d_x, const float *d_y, hipStream_t);
+/* The same update in two passes, for callers that overlap work on several
+ * streams:
+ *  tdp_sta_update_arrivals: net delays, loads, arrival times, transitions,
+ *    critical inputs, deviation lists, endpoint slacks, WNS / TNS (all that
+ *    extraction, pairs and the losses read);
+ *  tdp_sta_update_required: required times (Eq. 2) from the arrival pass's
+ *    delays; slack = required - arrival.
+ * The required pass may run on another stream concurrently with later
+ * extraction, pair and loss calls (they do not read required times), but it
+ * must be ordered after its arrival pass and before the next arrival pass
+ * and before any export or summary (event waits between the streams). */
+tdp_status tdp_sta_update_arrivals(tdp_graph, const float *d_x, const float *d_y, hipStream_t);
+tdp_status tdp_sta_update_required(tdp_graph, hipStream_t);
 
 /* WNS and TNS (Eqs. 3-4; both 0 without violations) and the number of
  * violated endpoints of the last update.  Synchronises the stream.  For a
@@ -262,7 +275,10 @@ enum {
   TDP_STAGE_SELECT, TDP_STAGE_SEARCH, TDP_STAGE_ORDER, TDP_STAGE_WALK, TDP_STAGE_PAIRS,
   TDP_STAGE_P2P_FWD, TDP_STAGE_P2P_BWD, TDP_STAGE_STNS, TDP_STAGE_WA, TDP_NUM_STAGES
 };
-tdp_status tdp_profile_enable(tdp_graph, int32_t on);
+/* stage_mask: bit TDP_STAGE_x times that stage (0 turns timing off; events
+ * are pooled and reused, so timing one stage adds two event records per
+ * call of it). */
+tdp_status tdp_profile_enable(tdp_graph, int32_t stage_mask);
 tdp_status tdp_profile_read(tdp_graph, double *ms, int32_t *calls);
 
 /* Launch tuning of the timing sweeps, used by the autotuner.

@@ -72,6 +72,8 @@ void free_all(tdp_graph g) {
   g->prof.marks.clear();
   for (auto &e : g->prof.open)
     if (e) { hipEventDestroy(e); e = nullptr; }
+  for (hipEvent_t e : g->prof.pool) hipEventDestroy(e);
+  g->prof.pool.clear();
 }
 
 // required time at the D pins: period - setup as the graph's precision
@@ -182,7 +184,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   g->sweep_mode = g->flow_ok ? 1 : 0;
   if (ok && g->flow_ok) {
     ok = dalloc(g, g->flow_w, T.M) && dalloc(g, g->flow_r, T.M) && dalloc(g, g->flow_cd, T.M) &&
-         dalloc(g, g->flow_se, (size_t)T.n_comb * g->side_k) && dalloc(g, g->tickets, 4);
+         dalloc(g, g->flow_se, (size_t)T.n_comb * g->side_k);
   }
   if (ok) {
     const double one[4] = {1.0, 0.0, 0.0, 0.0};
@@ -289,10 +291,29 @@ tdp_status tdp_sta_set_clock(tdp_graph g, float period, float setup) {
 tdp_status tdp_sta_update(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   GUARD(g);
   if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
-  dispatch(g, [&](auto z) { sta_update_impl<decltype(z)>(g, x, y, s); });
+  dispatch(g, [&](auto z) {
+    sta_arrivals_impl<decltype(z)>(g, x, y, s);
+    sta_required_impl<decltype(z)>(g, s);
+  });
   tdp_status st = check_launch(g, "sta_update");
   if (st == TDP_OK) g->updated = true;
   return st;
+}
+
+tdp_status tdp_sta_update_arrivals(tdp_graph g, const float *x, const float *y, hipStream_t s) {
+  GUARD(g);
+  if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
+  dispatch(g, [&](auto z) { sta_arrivals_impl<decltype(z)>(g, x, y, s); });
+  tdp_status st = check_launch(g, "sta_update_arrivals");
+  if (st == TDP_OK) g->updated = true;
+  return st;
+}
+
+tdp_status tdp_sta_update_required(tdp_graph g, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no arrival pass yet");
+  dispatch(g, [&](auto z) { sta_required_impl<decltype(z)>(g, s); });
+  return check_launch(g, "sta_update_required");
 }
 
 tdp_status tdp_sta_summary(tdp_graph g, double *wns, double *tns, int32_t *n_fail, hipStream_t s) {
@@ -534,9 +555,10 @@ tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph g, float gamma, double *wl, float 
   return check_launch(g, "wa_fwd_bwd_at_update");
 }
 
-tdp_status tdp_profile_enable(tdp_graph g, int32_t on) {
+tdp_status tdp_profile_enable(tdp_graph g, int32_t stage_mask) {
   GUARD(g);
-  g->prof.on = on != 0;
+  g->prof.mask = stage_mask;
+  g->prof.on = stage_mask != 0;
   return TDP_OK;
 }
 
@@ -548,8 +570,8 @@ tdp_status tdp_profile_read(tdp_graph g, double *ms, int32_t *calls) {
       g->prof.ms[m.stage] += e;
       g->prof.calls[m.stage] += 1;
     }
-    hipEventDestroy(m.a);
-    hipEventDestroy(m.b);
+    g->prof.pool.push_back(m.a);
+    g->prof.pool.push_back(m.b);
   }
   g->prof.marks.clear();
   for (int i = 0; i < TDP_NUM_STAGES; ++i) {

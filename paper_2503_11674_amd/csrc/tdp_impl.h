@@ -9,22 +9,23 @@ namespace tdp {
 
 // stage timing with HIP events on the caller's stream
 inline void prof_begin(tdp_graph g, int stage, hipStream_t s) {
-  if (!g->prof.on) return;
-  hipEvent_t a;
-  if (hipEventCreate(&a) != hipSuccess) return;
+  if (!g->prof.on || !((g->prof.mask >> stage) & 1)) return;
+  hipEvent_t a = g->prof.take();
+  if (!a) return;
   hipEventRecord(a, s);
   g->prof.open[stage] = a;
 }
 inline void prof_end(tdp_graph g, int stage, hipStream_t s) {
   if (!g->prof.on || !g->prof.open[stage]) return;
-  hipEvent_t b;
-  if (hipEventCreate(&b) != hipSuccess) return;
+  hipEvent_t b = g->prof.take();
+  if (!b) return;
   hipEventRecord(b, s);
   g->prof.marks.push_back({stage, g->prof.open[stage], b});
   g->prof.open[stage] = nullptr;
 }
 
-template <typename T> void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
+template <typename T> void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
+template <typename T> void sta_required_impl(tdp_graph g, hipStream_t s);
 template <typename T>
 void sta_export_impl(tdp_graph g, double *at, double *rat, double *slack, double *slew, double *dnet,
                      double *load, double *darc, hipStream_t s);

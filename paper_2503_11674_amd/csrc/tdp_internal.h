@@ -138,11 +138,22 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
 // ---------------------------------------------------------------- graph
 struct Profiler {
   bool on = false;
+  int32_t mask = 0;                       // stages being timed
   hipEvent_t open[TDP_NUM_STAGES] = {};
   struct Mark { int stage; hipEvent_t a, b; };
   std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;           // events reused between reads
   double ms[TDP_NUM_STAGES] = {0};
   int calls[TDP_NUM_STAGES] = {0};
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+  }
 };
 
 }  // namespace tdp
@@ -188,7 +199,6 @@ struct tdp_graph_s {
   uint32_t *flow_r = nullptr;    // [M] required time of a driver; all ones = not yet
   uint32_t *flow_cd = nullptr;   // [M] chain depth + 1 of a driver; 0 = not yet
   uint64_t *flow_se = nullptr;   // [n_comb][side_k] deviation entries {cost, sink}; all ones = not yet
-  int32_t *tickets = nullptr;    // [4] work counters of the persistent sweeps
   int32_t flow_waves = 4, spin_limit = 1 << 20;
   bool flow_ok = false;          // the graph can use the dataflow sweeps
   double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;

@@ -252,44 +252,36 @@ __global__ void k_path_index(Topo tp, int k, const int32_t *__restrict__ d_nslot
 
 // ----------------------------------------------------------------- walk
 // Writes a path from its last position down to its first, two arrays at
-// once, in 16-byte stores where the positions are 16-byte aligned: values are
-// collected four at a time in registers (the hardware then writes whole
-// sectors instead of one word per lane and step).
+// once.  Values are staged in LDS per aligned group of 32 positions (128
+// bytes) and a group goes out in one burst when its lowest position is
+// written (or the path starts inside it), so the L2 sees whole lines instead
+// of scattered words.  `sa` / `sb`: this thread's 33-word LDS rows (the odd
+// stride keeps the lanes of a wave on different banks).
 struct RevWriter {
   int32_t *a, *b;
-  int pos;      // next position to write (descending)
-  int n = 0;    // values collected for the aligned group ending at top
-  int top = 0;  // highest position of the group being collected
-  int32_t a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+  int32_t *sa, *sb;
+  int pos, lo, hi;  // next position (descending), path range [lo, hi)
   __device__ void put(int32_t va, int32_t vb) {
-    if (n == 0 && (pos & 3) != 3) {  // not at the top of an aligned group yet
-      a[pos] = va;
-      b[pos] = vb;
-      --pos;
+    const int j = pos & 31;
+    sa[j] = va;
+    sb[j] = vb;
+    if (j == 0 || pos == lo) flush(pos, j);
+    --pos;
+  }
+  __device__ void flush(int p0, int j0) {
+    const int top = min(hi - 1, p0 | 31);
+    if (j0 == 0 && top == p0 + 31) {
+#pragma unroll
+      for (int q = 0; q < 32; q += 4) {
+        *(int4 *)(a + p0 + q) = make_int4(sa[q], sa[q + 1], sa[q + 2], sa[q + 3]);
+        *(int4 *)(b + p0 + q) = make_int4(sb[q], sb[q + 1], sb[q + 2], sb[q + 3]);
+      }
       return;
     }
-    if (n == 0) top = pos;
-    // position top - n takes slot 3 - n
-    a3 = n == 0 ? va : a3;
-    b3 = n == 0 ? vb : b3;
-    a2 = n == 1 ? va : a2;
-    b2 = n == 1 ? vb : b2;
-    a1 = n == 2 ? va : a1;
-    b1 = n == 2 ? vb : b1;
-    a0 = n == 3 ? va : a0;
-    b0 = n == 3 ? vb : b0;
-    --pos;
-    if (++n == 4) {
-      *(int4 *)(a + top - 3) = make_int4(a0, a1, a2, a3);
-      *(int4 *)(b + top - 3) = make_int4(b0, b1, b2, b3);
-      n = 0;
+    for (int p = p0; p <= top; ++p) {
+      a[p] = sa[p & 31];
+      b[p] = sb[p & 31];
     }
-  }
-  __device__ void flush() {  // a partial group: its values sit at top, top-1, ...
-    if (n > 0) { a[top] = a3; b[top] = b3; }
-    if (n > 1) { a[top - 1] = a2; b[top - 1] = b2; }
-    if (n > 2) { a[top - 2] = a1; b[top - 2] = b1; }
-    n = 0;
   }
 };
 
@@ -302,6 +294,7 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
                                                int32_t *__restrict__ path_int, int32_t *__restrict__ path_ep,
                                                int32_t *__restrict__ path_epi, int32_t *__restrict__ path_rank,
                                                T *__restrict__ path_slack, int32_t *__restrict__ err, int pin_cap) {
+  __shared__ int32_t stage[2][128 * 33];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= *d_num_paths) return;
   const int slot = out_slot[q];
@@ -326,7 +319,7 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
     atomicOr(err, 1);
     return;
   }
-  RevWriter w{path_pins, path_int, hi - 1};
+  RevWriter w{path_pins, path_int, stage[0] + threadIdx.x * 33, stage[1] + threadIdx.x * 33, hi - 1, lo, hi};
   const int et = tp.A + f;
   w.put(tp.snk_ext[et], tp.M + et);
   int v = tp.snk_drv[et];
@@ -356,7 +349,6 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
     v = nv;
     vext = nvext;
   }
-  w.flush();
   if (w.pos != lo - 1 || v >= tp.n_start || di >= 0) atomicOr(err, 1);
   path_ep[q] = tp.snk_ext[et];
   path_epi[q] = f;

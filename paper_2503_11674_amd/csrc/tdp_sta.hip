@@ -110,7 +110,6 @@ struct FlowInit {
   uint64_t *w = nullptr;
   uint32_t *r = nullptr, *cd = nullptr;
   uint64_t *se = nullptr;
-  int32_t *tickets = nullptr;
   int32_t *err = nullptr;  // cleared at the start of every update
   int km = 0;
   int seed = 1;  // 0: start points are never published (self-test of the bounded waits)
@@ -151,7 +150,6 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
                                                   T *__restrict__ at, T *__restrict__ slew,
                                                   V2<T> *__restrict__ as, int32_t *__restrict__ cdep, FlowInit fl) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && fl.err) *fl.err = 0;
-  if (fl.tickets && blockIdx.x == 0 && threadIdx.x < 4) fl.tickets[threadIdx.x] = 0;
   const int lane = wave_lane();
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
@@ -509,7 +507,7 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
                                                        int32_t *__restrict__ cdep, float *__restrict__ side_cost,
                                                        int32_t *__restrict__ side_pin, uint64_t *__restrict__ fw,
                                                        uint32_t *__restrict__ fcd, uint64_t *__restrict__ fse,
-                                                       int32_t *__restrict__ ticket, int32_t *__restrict__ err,
+                                                       int32_t *__restrict__ err,
                                                        int limit) {
   extern __shared__ float s_lut[];
   const int lane = wave_lane();
@@ -720,7 +718,7 @@ static void launch_forward_flow(tdp_graph g, hipStream_t s) {
   hipLaunchKernelGGL((k_forward_flow<KM>), dim3(nblk(tp.n_fw_chunks, w)), dim3(64 * w), lut_bytes(g->lut), s, tp, g->lut,
                      (const float *)g->load, (const float *)g->dnet, (float *)g->at, (float *)g->slew,
                      (float *)g->darc, g->crit, (int4 *)g->hop, g->cdep, (float *)g->side_cost, g->side_pin,
-                     g->flow_w, g->flow_cd, g->flow_se, g->tickets, g->d_err, g->spin_limit);
+                     g->flow_w, g->flow_cd, g->flow_se, g->d_err, g->spin_limit);
 }
 
 static void forward_flow(tdp_graph g, hipStream_t s) {
@@ -734,8 +732,9 @@ static void forward_flow(tdp_graph g, hipStream_t s) {
   }
 }
 
+// arrivals: net pass, forward sweep, endpoint slacks and WNS / TNS
 template <typename T>
-void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
+void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   const Topo &tp = g->topo;
   const T kappa = (T)g->scale * (T)g->r * (T)g->c;
   const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;
@@ -746,7 +745,6 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
     fl.r = g->flow_r;
     fl.cd = g->flow_cd;
     fl.se = g->flow_se;
-    fl.tickets = g->tickets;
     fl.km = g->side_k > 1 ? g->side_k : 0;
     fl.seed = g->sweep_mode == 2 ? 0 : 1;
   }
@@ -784,6 +782,12 @@ void sta_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s)
   hipLaunchKernelGGL(k_ep_final, dim3(nblk(tp.num_inst, 64)), dim3(64), 0, s, tp.num_inst, g->ep_chunks, g->red_ep,
                      g->summary, g->inst_nfail);
   prof_end(g, TDP_STAGE_ENDPOINT, s);
+}
+
+template <typename T>
+void sta_required_impl(tdp_graph g, hipStream_t s) {
+  const Topo &tp = g->topo;
+  const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;
   prof_begin(g, TDP_STAGE_BACKWARD, s);
   if (flow) {
     const int w = g->flow_waves;
@@ -819,8 +823,10 @@ void sta_export_crit(tdp_graph g, int32_t *out, hipStream_t s) {
   hipLaunchKernelGGL(k_export_crit, dim3(nblk(g->topo.N, 256)), dim3(256), 0, s, g->topo, g->crit, out);
 }
 
-template void sta_update_impl<float>(tdp_graph, const float *, const float *, hipStream_t);
-template void sta_update_impl<double>(tdp_graph, const float *, const float *, hipStream_t);
+template void sta_arrivals_impl<float>(tdp_graph, const float *, const float *, hipStream_t);
+template void sta_arrivals_impl<double>(tdp_graph, const float *, const float *, hipStream_t);
+template void sta_required_impl<float>(tdp_graph, hipStream_t);
+template void sta_required_impl<double>(tdp_graph, hipStream_t);
 template void sta_export_impl<float>(tdp_graph, double *, double *, double *, double *, double *, double *,
                                      double *, hipStream_t);
 template void sta_export_impl<double>(tdp_graph, double *, double *, double *, double *, double *, double *,

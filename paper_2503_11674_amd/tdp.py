@@ -72,6 +72,8 @@ tdp_destroy.restype = None
 tdp_destroy.argtypes = [_p]
 tdp_sta_set_clock = _sig("tdp_sta_set_clock", _p, _f32, _f32)
 tdp_sta_update = _sig("tdp_sta_update", _p, _p, _p, _p)
+tdp_sta_update_arrivals = _sig("tdp_sta_update_arrivals", _p, _p, _p, _p)
+tdp_sta_update_required = _sig("tdp_sta_update_required", _p, _p)
 tdp_sta_summary = _sig("tdp_sta_summary", _p, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i32), _p)
 tdp_batch_summary = _sig("tdp_batch_summary", _p, _p, _p, _p, _p)
 tdp_sta_export = _sig("tdp_sta_export", _p, _p, _p, _p, _p, _p, _p, _p, _p)
@@ -104,7 +106,7 @@ tdp_last_error.restype = ctypes.c_char_p
 tdp_last_error.argtypes = [_p]
 
 EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destroy", "tdp_sta_set_clock",
-            "tdp_sta_update", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit",
+            "tdp_sta_update", "tdp_sta_update_arrivals", "tdp_sta_update_required", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit",
             "tdp_extract_paths", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
             "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
@@ -225,6 +227,12 @@ class TimingGraph:
 
     def sta_update(self, x: torch.Tensor, y: torch.Tensor, stream=None):
         _check(tdp_sta_update(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _stream(stream)), self.h)
+
+    def sta_update_arrivals(self, x: torch.Tensor, y: torch.Tensor, stream=None):
+        _check(tdp_sta_update_arrivals(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _stream(stream)), self.h)
+
+    def sta_update_required(self, stream=None):
+        _check(tdp_sta_update_required(self.h, _stream(stream)), self.h)
 
     def summary(self, stream=None):
         w, t, n = ctypes.c_double(), ctypes.c_double(), _i32()
@@ -354,8 +362,15 @@ class TimingGraph:
         return out
 
     # ----------------------------------------------------------- tooling
-    def profile(self, on: bool = True):
-        _check(tdp_profile_enable(self.h, 1 if on else 0), self.h)
+    def profile(self, on=True):
+        """on: True (every stage), False, or a collection of stage names."""
+        if on is True:
+            mask = (1 << len(STAGES)) - 1
+        elif not on:
+            mask = 0
+        else:
+            mask = sum(1 << STAGES.index(s) for s in on)
+        _check(tdp_profile_enable(self.h, mask), self.h)
 
     def profile_read(self) -> Dict[str, tuple]:
         ms = np.zeros(len(STAGES), np.float64)

@@ -109,16 +109,9 @@ def test_full_size_step_2m_cells(library):
     pp = torch.zeros((), dtype=torch.float64, device=_dev())
     one = torch.ones((), dtype=torch.float64, device=_dev())
 
-    def step():
-        g.sta_update(x, y)
-        g.extract_paths(n=-1, k=k, K=K)
-        g.pairs_update(rule=0, w0=10.0, w1=0.2)
-        gx.zero_()
-        gy.zero_()
-        g.wa_fwd_bwd_at_update(5.0, gx, gy, out=wl)
-        g.p2p_loss_fwd(x, y, out=pp)
-        g.p2p_loss_bwd(x, y, one, gx, gy)
-
+    # the benchmark's step, with its side streams (beta = 1 here)
+    import bench
+    step = bench.build_step(g, x, y, k, K, gx, gy, wl, pp, one, overlap=True)
     step()
     g.pairs_reset()
     step()

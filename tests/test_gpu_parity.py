@@ -534,3 +534,30 @@ def test_pair_loss_variants(library, kind):
         assert float(g.pair_loss_fwd(0, c["x"], c["y"])) == float(g.p2p_loss_fwd(c["x"], c["y"]))
     with pytest.raises(tdp.TdpError):
         g.pair_loss_fwd(3, c["x"], c["y"])
+
+
+def test_two_pass_update_on_two_streams(library):
+    """The arrival pass and the required-time pass, the second on another
+    stream ordered by events, give bitwise what the one-call update gives."""
+    tdp = _tdp()
+    c = case("C2", library)
+    g = tdp.TimingGraph(c["nl"], library, max_paths=c["K"], max_k=c["k"])
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    ev = torch.cuda.Event()
+    g.sta_update_arrivals(c["x"], c["y"])
+    ev.record(main)
+    side.wait_event(ev)
+    g.sta_update_required(stream=side)
+    ev2 = torch.cuda.Event()
+    ev2.record(side)
+    main.wait_event(ev2)
+    o = {k: v.cpu().numpy() for k, v in g.export().items()}
+    for key in o:
+        assert np.array_equal(o[key], c["gpu"][key]), key
+    g2 = tdp.TimingGraph(c["nl"], library, max_paths=8, max_k=1)
+    with pytest.raises(tdp.TdpError) as e:
+        g2.sta_update_required()
+    assert e.value.status == 6
+    g.close()
+    g2.close()
