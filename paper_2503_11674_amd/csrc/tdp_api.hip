@@ -171,6 +171,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        dalloc(g, g->dnet_nm, (size_t)T.n_nm_chunks * CHUNK, es) && dalloc(g, g->drv_as, (size_t)2 * T.M, es) &&
        dalloc(g, g->fw_a, (size_t)T.n_fw_chunks * CHUNK, es) &&
        dalloc(g, g->darc, T.A, es) && dalloc(g, g->crit, T.n_comb) && dalloc(g, g->hop, (size_t)T.n_comb * 4) &&
+       dalloc(g, g->hop4, (size_t)T.n_comb * 16) &&
        dalloc(g, g->cdep, T.M) && dalloc(g, g->ep_slack, T.E, es) &&
        dalloc(g, g->red_ep, (size_t)3 * T.num_inst * g->ep_chunks) && dalloc(g, g->red_loss, 4096) &&
        dalloc(g, g->red_wa, 4096) && dalloc(g, g->summary, (size_t)4 * T.num_inst) &&

@@ -190,6 +190,7 @@ struct tdp_graph_s {
        *dnet_nm = nullptr, *drv_as = nullptr, *fw_a = nullptr;
   int32_t *crit = nullptr;       // [n_comb] arc index of the critical input
   int32_t *hop = nullptr;        // [n_comb][4] {critical sink, its driver, their external ids}
+  int32_t *hop4 = nullptr;       // [n_comb][4][4] the hop records of a cell and of the next three up its chain
   int32_t *cdep = nullptr;       // [M] combinational cells on the critical chain
   void *side_cost = nullptr;     // [n_comb][side_k] cheapest deviations along the chain
   int32_t *side_pin = nullptr;   // [n_comb][side_k]

@@ -66,7 +66,8 @@ __global__ void __launch_bounds__(256) k_pairs_acc(Topo tp, int rule, const int3
 // merges its occurrences in an LDS hash table with integer atomics, and sends
 // one global atomic per distinct pin.  The first occurrence is still the
 // smallest output index, whatever order the paths are visited in.
-constexpr int HASH_SLOTS = 4096;
+constexpr int HASH_BITS = 11;
+constexpr int HASH_SLOTS = 1 << HASH_BITS;  // 24 KB of LDS: several workgroups per CU
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int per_block,
@@ -77,6 +78,7 @@ __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int pe
                                                         const int32_t *__restrict__ path_epi,
                                                         const T *__restrict__ path_slack,
                                                         const double *__restrict__ summary,
+                                                        const uint8_t *__restrict__ in_p,
                                                         unsigned long long *__restrict__ acc,
                                                         int32_t *__restrict__ first) {
   __shared__ int32_t hkey[HASH_SLOTS];
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int pe
     for (int i = b + 1 + 2 * lane; i < e; i += 128) {
       const int t = path_int[i] - tp.M;
       if (t < 0 || t >= tp.S) continue;
-      unsigned h = ((unsigned)t * 2654435761u) >> 20;
+      unsigned h = ((unsigned)t * 2654435761u) >> (32 - HASH_BITS);
       for (int probe = 0; probe < HASH_SLOTS; ++probe) {
         const int k = atomicCAS(&hkey[h], -1, t);
         if (k == -1 || k == t) {
@@ -120,7 +122,8 @@ __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int pe
     const int t = hkey[i];
     if (t >= 0) {
       atomicAdd(&acc[t], hacc[i]);
-      atomicMin(&first[t], hfirst[i]);
+      // the first occurrence matters only to a pair that Eq. 9 inserts
+      if (rule != 0 || !in_p[t]) atomicMin(&first[t], hfirst[i]);
     }
   }
 }
@@ -135,18 +138,19 @@ __global__ void k_pairs_apply(Topo tp, int rule, float w0, float w1, int max_out
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= tp.S) return;
   const int q = first[t];
-  if (q >= 0 && q < max_out) {
-    const unsigned long long sum = acc[t];
+  const unsigned long long sum = acc[t];
+  // a pair already in P (Eq. 9) only sums; its first occurrence is not kept
+  const bool member = rule == 0 && in_p[t];
+  if (member && sum != 0ull) {
+    w[t] = (float)((double)w[t] + (double)w1 * ((double)sum / FIX_ONE));
+    acc[t] = 0ull;
+  } else if (!member && q >= 0 && q < max_out) {
     const double wns = summary[4 * tp.ff_inst[path_epi[q]]];
     unsigned long long v = 0;
     pair_contrib<T>(rule, path_slack[q], wns, v);
-    if (rule == 0) {
-      if (in_p[t]) {
-        w[t] = (float)((double)w[t] + (double)w1 * ((double)sum / FIX_ONE));
-      } else {
-        w[t] = (float)((double)w0 + (double)w1 * ((double)(sum - v) / FIX_ONE));
-        in_p[t] = 1;
-      }
+    if (rule == 0) {  // inserted by its first occurrence, which adds no weight
+      w[t] = (float)((double)w0 + (double)w1 * ((double)(sum - v) / FIX_ONE));
+      in_p[t] = 1;
     } else {
       w[t] = (float)((double)sum / FIX_ONE);
       in_p[t] = 1;
@@ -384,7 +388,7 @@ void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s)
   if (per_block >= 1)
     hipLaunchKernelGGL(k_pairs_acc_lds<T>, dim3(nb(g->slot_cap, per_block)), dim3(256), 0, s, tp, rule, per_block,
                        g->d_nslots, g->slot_out, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack,
-                       g->summary, g->pacc, g->pfirst);
+                       g->summary, g->pin_p, g->pacc, g->pfirst);
   else
     hipLaunchKernelGGL(k_pairs_acc<T>, dim3(std::min(2048, nb(g->max_out, 4))), dim3(256), 0, s, tp, rule,
                        g->d_num_paths, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack, g->summary,

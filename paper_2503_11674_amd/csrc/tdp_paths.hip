@@ -289,7 +289,7 @@ template <typename T>
 __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__restrict__ d_num_paths,
                                                const int32_t *__restrict__ out_slot, const int32_t *__restrict__ sel,
                                                const int32_t *__restrict__ slot_dev, const int32_t *__restrict__ slot_par,
-                                               const T *__restrict__ slot_key, const int4 *__restrict__ hop,
+                                               const T *__restrict__ slot_key, const int4 *__restrict__ hop4,
                                                const int32_t *__restrict__ path_ptr, int32_t *__restrict__ path_pins,
                                                int32_t *__restrict__ path_int, int32_t *__restrict__ path_ep,
                                                int32_t *__restrict__ path_epi, int32_t *__restrict__ path_rank,
@@ -301,16 +301,13 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
   const int qs = slot / k, r = slot - qs * k;
   const int base = qs * k;
   const int f = sel[qs];
-  // deviations, upstream-most first
+  // deviations, upstream-most first (the walk meets them last to first)
   int devs[TDP_MAX_K];
-  int devc[TDP_MAX_K];
   int nd = 0;
   for (int a = r; a >= 0 && nd < TDP_MAX_K;) {
     const int d = slot_dev[base + a];
     if (d < 0) break;
-    devs[nd] = d;
-    devc[nd] = tp.snk_comb[d];
-    ++nd;
+    devs[nd++] = d;
     a = slot_par[base + a];
   }
   const int lo = path_ptr[q];
@@ -323,31 +320,63 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
   const int et = tp.A + f;
   w.put(tp.snk_ext[et], tp.M + et);
   int v = tp.snk_drv[et];
-  int vext = tp.drv_ext[v];
+  w.put(tp.drv_ext[v], v);
+  // the next deviation in registers: its sink, cell, external id and driver
   int di = nd - 1;
-  for (;;) {
-    if (w.pos < lo) break;
-    w.put(vext, v);
-    if (v < tp.n_start) break;
-    const int c = v - tp.n_start;
-    int t, text, nv, nvext;
-    if (di >= 0 && devc[di] == c) {
-      t = devs[di];
-      --di;
-      text = tp.snk_ext[t];
-      nv = tp.snk_drv[t];
-      nvext = tp.drv_ext[nv];
-    } else {
-      const int4 h = hop[c];
-      t = h.x;
-      nv = h.y;
-      text = h.z;
-      nvext = h.w;
+  int dt = -1, dc = -1;
+  if (di >= 0) {
+    dt = devs[di];
+    dc = tp.snk_comb[dt];
+  }
+  // Group-synchronous walk: every iteration all lanes load the four-hop
+  // record of their current cell together (one memory latency for the wave)
+  // and advance up to four cells along it; a deviation cell leaves the chain
+  // and ends the lane's group early.
+  bool done = v < tp.n_start;
+  while (!done && w.pos >= lo) {
+    const int4 *hp = hop4 + (size_t)(v - tp.n_start) * 4;
+    const int4 g0 = hp[0], g1 = hp[1], g2 = hp[2], g3 = hp[3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = v - tp.n_start;
+      int t, text, nv, nvext;
+      bool dev = c == dc;
+      if (dev) {
+        t = dt;
+        text = tp.snk_ext[t];
+        nv = tp.snk_drv[t];
+        nvext = tp.drv_ext[nv];
+        if (--di >= 0) {
+          dt = devs[di];
+          dc = tp.snk_comb[dt];
+        } else {
+          dt = -1;
+          dc = -1;
+        }
+      } else {
+        const int4 h = i == 0 ? g0 : (i == 1 ? g1 : (i == 2 ? g2 : g3));
+        t = h.x;
+        nv = h.y;
+        text = h.z;
+        nvext = h.w;
+      }
+      if (w.pos < lo) {
+        done = true;
+        break;
+      }
+      w.put(text, tp.M + t);
+      if (w.pos < lo) {
+        done = true;
+        break;
+      }
+      w.put(nvext, nv);
+      v = nv;
+      if (v < tp.n_start) {
+        done = true;
+        break;
+      }
+      if (dev) break;  // off the chain: reload at the new cell
     }
-    if (w.pos < lo) break;
-    w.put(text, tp.M + t);
-    v = nv;
-    vext = nvext;
   }
   if (w.pos != lo - 1 || v >= tp.n_start || di >= 0) atomicOr(err, 1);
   path_ep[q] = tp.snk_ext[et];
@@ -427,7 +456,7 @@ void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream
   // walk
   prof_begin(g, TDP_STAGE_WALK, s);
   hipLaunchKernelGGL(k_walk<T>, dim3(nb(g->max_out, 128)), dim3(128), 0, s, tp, k, g->d_num_paths, g->out_slot,
-                     g->sel_list, g->slot_dev, g->slot_par, (const T *)g->slot_key, (const int4 *)g->hop,
+                     g->sel_list, g->slot_dev, g->slot_par, (const T *)g->slot_key, (const int4 *)g->hop4,
                      g->path_ptr, g->path_pins, g->path_int, g->path_ep, g->path_epi, g->path_rank,
                      (T *)g->path_slack, g->d_err, g->pin_cap);
   prof_end(g, TDP_STAGE_WALK, s);

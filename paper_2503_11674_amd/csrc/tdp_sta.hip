@@ -236,8 +236,7 @@ template <typename T>
 __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, float *s_lut, int chunk, int ch1,
                                             const T *__restrict__ load, const T *__restrict__ dnet,
                                             T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
-                                            T *__restrict__ darc, int32_t *__restrict__ crit, int4 *__restrict__ hop,
-                                            T *__restrict__ fw_a) {
+                                            T *__restrict__ darc, int32_t *__restrict__ crit, T *__restrict__ fw_a) {
   const int lane = wave_lane();
   const int k = chunk * CHUNK + lane;
   // the record load is issued before the tables are staged, so the two
@@ -248,9 +247,6 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
   const int t = rec.x, s = rec.y, c = rec.z;
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   const bool valid = t >= 0;
-  // the external ids of every lane's sink and driver come with the static
-  // data; the head takes the critical input's by shuffle
-  const int2 ex = valid ? tp.fw_ext[k] : make_int2(0, 0);
   T a = -pos_inf<T>(), o = 0;
   if (valid) {
     const T ld = load[tp.n_start + c];
@@ -268,25 +264,22 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
   // first input attaining the maximum (the head when none does, e.g. NaN)
   const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
   const int argl = arg0 <= tail ? arg0 : head;
-  const int tc = __shfl(t, argl & 63, 64);
-  const int pred = __shfl(s, argl & 63, 64);
-  const int2 exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
-  if (valid && lane == head) {
+  if (valid && lane == head) {  // (the list job records the critical input's hop)
     const int v = tp.n_start + c;
     at[v] = best;
     slew[v] = so;
     as[v] = v2<T>(best, so);
     crit[c] = argl - head;
-    // critical input, its driver and their external ids: one record per hop
-    // of a path walk
-    hop[c] = make_int4(tc, pred, exc.x, exc.y);
   }
 }
 
+// hop4 of a cell: its own hop record followed by the first three of its
+// critical input's driver's hop4 (terminal records {-1, -1, 0, 0} past a
+// start point), so a path walk reads four hops per load
 template <typename T, int KM>
 __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, const T *__restrict__ fw_a,
                                          int32_t *__restrict__ cdep, T *__restrict__ side_cost,
-                                         int32_t *__restrict__ side_pin) {
+                                         int32_t *__restrict__ side_pin, int4 *__restrict__ hop4) {
   if (chunk >= lc1) return;
   const int lane = wave_lane();
   const int k = chunk * CHUNK + lane;
@@ -295,13 +288,31 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   const bool valid = t >= 0;
   const T a = valid ? fw_a[k] : -pos_inf<T>();
+  const int2 ex = valid ? tp.fw_ext[k] : make_int2(0, 0);
   // the same maximum and critical input as the arrival job found
   const T best = seg_max(a, lane, head, tail);
   const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
   const int argl = arg0 <= tail ? arg0 : head;
   const int pred = __shfl(s, argl & 63, 64);
+  const int tc = __shfl(t, argl & 63, 64);
+  const int2 exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
   const bool is_head = valid && lane == head;
-  if (is_head) cdep[tp.n_start + c] = cdep[pred] + 1;
+  if (is_head) {
+    cdep[tp.n_start + c] = cdep[pred] + 1;
+    const int4 none = make_int4(-1, -1, 0, 0);
+    int4 up0 = none, up1 = none, up2 = none;
+    if (pred >= tp.n_start) {
+      const int4 *ph = hop4 + (size_t)(pred - tp.n_start) * 4;
+      up0 = ph[0];
+      up1 = ph[1];
+      up2 = ph[2];
+    }
+    int4 *h = hop4 + (size_t)c * 4;
+    h[0] = make_int4(tc, pred, exc.x, exc.y);
+    h[1] = up0;
+    h[2] = up1;
+    h[3] = up2;
+  }
   if constexpr (KM > 1) {
     const T dl = (valid && lane != argl) ? best - a : pos_inf<T>();
     const int width = wave_max_int(valid ? tail - head + 1 : 0);
@@ -345,15 +356,15 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
                                                   const T *__restrict__ load, const T *__restrict__ dnet,
                                                   T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
                                                   T *__restrict__ darc, int32_t *__restrict__ crit,
-                                                  int4 *__restrict__ hop, int32_t *__restrict__ cdep,
+                                                  int32_t *__restrict__ cdep,
                                                   T *__restrict__ side_cost, int32_t *__restrict__ side_pin,
-                                                  T *__restrict__ fw_a) {
+                                                  T *__restrict__ fw_a, int4 *__restrict__ hop4) {
   extern __shared__ float s_lut[];
   const int wave = threadIdx.x >> 6;
   if ((int)blockIdx.x < n_arr)
-    fw_arrivals<T>(tp, L, s_lut, ch0 + blockIdx.x * 4 + wave, ch1, load, dnet, at, slew, as, darc, crit, hop, fw_a);
+    fw_arrivals<T>(tp, L, s_lut, ch0 + blockIdx.x * 4 + wave, ch1, load, dnet, at, slew, as, darc, crit, fw_a);
   else
-    fw_lists<T, KM>(tp, lc0 + (blockIdx.x - n_arr) * 4 + wave, lc1, fw_a, cdep, side_cost, side_pin);
+    fw_lists<T, KM>(tp, lc0 + (blockIdx.x - n_arr) * 4 + wave, lc1, fw_a, cdep, side_cost, side_pin, hop4);
 }
 
 // ------------------------------------------------------------- endpoints
@@ -650,6 +661,21 @@ __global__ void __launch_bounds__(256) k_backward_flow(Topo tp, const float *__r
   }
 }
 
+// hop4 from the hop records, for the dataflow forward sweep (the per-level
+// one builds it as it goes): three dependent gathers per cell
+__global__ void __launch_bounds__(256) k_hop4_fill(Topo tp, const int4 *__restrict__ hop, int4 *__restrict__ hop4) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= tp.n_comb) return;
+  int4 cur = hop[c];
+  int4 *h = hop4 + (size_t)c * 4;
+  h[0] = cur;
+  for (int j = 1; j < 4; ++j) {
+    if (cur.x >= 0 && cur.y >= tp.n_start) cur = hop[cur.y - tp.n_start];
+    else cur = make_int4(-1, -1, 0, 0);
+    h[j] = cur;
+  }
+}
+
 // --------------------------------------------------------------- export
 template <typename T>
 __global__ void __launch_bounds__(256) k_export(Topo tp, const T *__restrict__ at, const T *__restrict__ rat,
@@ -694,8 +720,8 @@ static void launch_forward(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipS
   if (n_arr + n_lst == 0) return;
   hipLaunchKernelGGL((k_forward<T, KM>), dim3(n_arr + n_lst), dim3(256), n_arr ? lut_bytes(g->lut) : 0, s, tp,
                      g->lut, ch0, ch1, n_arr, lc0, lc1, (const T *)g->load, (const T *)g->dnet, (T *)g->at,
-                     (T *)g->slew, (V2<T> *)g->drv_as, (T *)g->darc, g->crit, (int4 *)g->hop, g->cdep,
-                     (T *)g->side_cost, g->side_pin, (T *)g->fw_a);
+                     (T *)g->slew, (V2<T> *)g->drv_as, (T *)g->darc, g->crit, g->cdep,
+                     (T *)g->side_cost, g->side_pin, (T *)g->fw_a, (int4 *)g->hop4);
 }
 
 // arrivals of chunks [ch0, ch1) and the lists of [lc0, lc1), the level before
@@ -761,6 +787,9 @@ void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t 
   prof_begin(g, TDP_STAGE_FORWARD, s);
   if (flow) {
     forward_flow(g, s);
+    if (tp.n_comb > 0)
+      hipLaunchKernelGGL(k_hop4_fill, dim3(nblk(tp.n_comb, 256)), dim3(256), 0, s, tp, (const int4 *)g->hop,
+                         (int4 *)g->hop4);
   } else {
     int lc0 = 0, lc1 = 0;  // the previous non-empty level, whose lists are due
     for (int l = 1; l <= tp.D; ++l) {

@@ -561,3 +561,52 @@ def test_two_pass_update_on_two_streams(library):
     assert e.value.status == 6
     g.close()
     g2.close()
+
+
+# ------------------------------------------------------------- HIP graphs
+def test_step_replays_from_a_captured_graph(library):
+    """The benchmark's step (three streams) captured in a HIP graph: every
+    replay, with eager work and synchronisations between replays, gives
+    bitwise the eager step's paths, pair weights, losses and gradients."""
+    import bench
+    tdp = _tdp()
+    c = case("C2", library)
+    g = tdp.TimingGraph(c["nl"], library, max_paths=c["K"], max_k=c["k"])
+    x, y = c["x"], c["y"]
+    gx = torch.zeros_like(x)
+    gy = torch.zeros_like(y)
+    wl = torch.zeros((), dtype=torch.float64, device=_dev())
+    pp = torch.zeros((), dtype=torch.float64, device=_dev())
+    beta = torch.full((), 2.5e-5, dtype=torch.float64, device=_dev())
+    step = bench.build_step(g, x, y, c["k"], c["K"], gx, gy, wl, pp, beta, overlap=True)
+
+    def snapshot():
+        torch.cuda.synchronize()
+        p = g.paths()
+        w, _ = g.pairs_export()
+        return (p["path_pins"].copy(), p["path_slack"].copy(), w.copy(), float(wl), float(pp),
+                gx.cpu().numpy().copy(), gy.cpu().numpy().copy(), g.export()["slack"].cpu().numpy())
+
+    # eager reference: reset P, one step
+    g.pairs_reset()
+    step()
+    ref_out = snapshot()
+    # capture (the pair set then holds one round; reset before every replay)
+    step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.pairs_reset()
+        torch.cuda.synchronize()
+        graph.replay()
+        out = snapshot()
+        for a, b in zip(out, ref_out):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), rep
+        # eager work between replays
+        g.sta_update(x, y)
+        g.extract_paths(n=-1, k=1)
+        torch.cuda.synchronize()
+    g.close()
