@@ -157,6 +157,38 @@ def extract(nl, lib, st, n: int = -1, k: int = 1, K: int = 1 << 30,
             "sel_ep": sel_ep[:ns].copy(), "ep_next": ep_next[:ns].copy(), "k": k}
 
 
+def report_timing(nl, lib, st, K: int, slack_limit: float = float("inf")) -> Dict[str, np.ndarray]:
+    """report_timing(K): the K worst paths over all endpoints together,
+    ordered by (slack, endpoint pin, rank); ``next_slack`` is the slack key
+    of the next path after the K-th (+inf when there is none)."""
+    L = _load()
+    max_paths = max(1, int(K))
+    pin_cap = max(16, max_paths * (2 * int(nl.get("depth", 64)) + 8))
+    while True:
+        path_ptr = np.zeros(max_paths + 1, np.int32)
+        path_pins = np.zeros(pin_cap, np.int32)
+        path_ep = np.zeros(max_paths, np.int32)
+        path_rank = np.zeros(max_paths, np.int32)
+        path_slack = np.zeros(max_paths, np.float64)
+        nxt = np.zeros(1, np.float64)
+        na, k1 = _netlist_args(nl)
+        arrs = [_f64(st["at"]), _f64(st["rat"]), _f64(st["dnet"]), _f64(st["darc"]), _i32(st["crit"])]
+        rc = L.ora_report_timing(*na, *[_p(a) for a in arrs], ctypes.c_int(int(K)), ctypes.c_double(slack_limit),
+                                 _p(path_ptr), _p(path_pins), ctypes.c_int(pin_cap), _p(path_ep), _p(path_rank),
+                                 _p(path_slack), _p(nxt))
+        if rc == -2:
+            pin_cap *= 2
+            continue
+        if rc < 0:
+            raise ValueError("timing graph has a cycle")
+        break
+    m = rc
+    return {"num_paths": m, "path_ptr": path_ptr[:m + 1].copy(),
+            "path_pins": path_pins[:path_ptr[m]].copy(), "path_ep": path_ep[:m].copy(),
+            "path_rank": path_rank[:m].copy(), "path_slack": path_slack[:m].copy(),
+            "next_slack": float(nxt[0])}
+
+
 def path_list(paths) -> list:
     ptr, pins = paths["path_ptr"], paths["path_pins"]
     return [pins[ptr[i]:ptr[i + 1]].tolist() for i in range(paths["num_paths"])]

@@ -21,6 +21,9 @@
  *                  most critical endpoints, and the k worst paths at each.
  *                  Reached by deviation (sidetrack) enumeration from the
  *                  arrival-time tree, in order of path slack.
+ *   ora_report_timing - report_timing(K) (Sec. III-B, Table I): the K worst
+ *                  paths over the whole design, by one best-first deviation
+ *                  enumeration across all endpoints.
  *   ora_pairs    - the maintained pin-pair set P and the weight rule of
  *                  Eq. 9 (Sec. III-D), or the stateless exponential rule.
  *   ora_p2p      - PP = sum w * Q(i, j), Q the squared Euclidean pin distance
@@ -366,6 +369,59 @@ static ocand heap_pop(oheap *h) {
 
 typedef struct { double slack; int ep; int rank; int start; int len; } opath;
 
+/* Builds the path into endpoint e that follows the arrival-time tree except at
+ * the deviations devs[0..nd) (devs[nd-1] nearest the endpoint; a deviation is
+ * the non-critical input pin taken at its cell), appends its pins in
+ * start -> end order to the pool and records it with its slack recomputed
+ * from the arc delays along it. */
+static void add_path(const oconn *c, const int32_t *pin_cell, const int32_t *cell_in_ptr,
+                     const int32_t *cell_in_pins, const double *at, const double *rat, const double *dnet,
+                     const double *darc, const int32_t *crit, int e, int rank, const int *devs, int nd,
+                     int *chain_pins, int32_t **pool, long *pool_n, long *pool_cap, opath **paths, int *npaths,
+                     int *pcap) {
+  int len = 0, di = nd - 1;
+  chain_pins[len++] = e;
+  int v = c->driver[e];
+  for (;;) {
+    chain_pins[len++] = v;
+    if (c->role[v] != ROLE_COUT) break;
+    int cell = pin_cell[v];
+    int in;
+    if (di >= 0 && pin_cell[devs[di]] == cell) in = devs[di--];
+    else in = cell_in_pins[cell_in_ptr[cell] + crit[cell]];
+    chain_pins[len++] = in;
+    v = c->driver[in];
+  }
+  /* reverse into start -> end order and recompute the path slack */
+  if (*pool_n + len > *pool_cap) {
+    *pool_cap = (*pool_n + len) * 2 + 1024;
+    *pool = (int32_t *)realloc(*pool, sizeof(int32_t) * *pool_cap);
+  }
+  int32_t *dst = *pool + *pool_n;
+  int start = chain_pins[len - 1];
+  double arr = at[start];
+  for (int a = 0; a < len; ++a) {
+    int pin = chain_pins[len - 1 - a];
+    dst[a] = pin;
+    if (a == 0) continue;
+    int role = c->role[pin];
+    if (role == ROLE_CIN || role == ROLE_FFD) arr += dnet[pin];
+    else if (role == ROLE_COUT) arr += darc[chain_pins[len - a]];
+  }
+  if (*npaths == *pcap) {
+    *pcap = *pcap ? 2 * *pcap : 1024;
+    *paths = (opath *)realloc(*paths, sizeof(opath) * *pcap);
+  }
+  opath *o = *paths + *npaths;
+  o->slack = rat[e] - arr;
+  o->ep = e;
+  o->rank = rank;
+  o->start = (int)*pool_n;
+  o->len = len;
+  *npaths += 1;
+  *pool_n += len;
+}
+
 static int opath_cmp(const void *a, const void *b) {
   const opath *x = (const opath *)a, *y = (const opath *)b;
   if (x->slack != y->slack) return x->slack < y->slack ? -1 : 1;
@@ -463,43 +519,8 @@ int ora_extract(NETLIST_ARGS, const double *at, const double *rat, const double 
       int devs[4096];
       int nd = 0;
       for (int a = r; a >= 0 && popped[a].dev >= 0; a = popped[a].parent) devs[nd++] = popped[a].dev;
-      /* devs[nd-1] is the deviation nearest the endpoint */
-      int len = 0, di = nd - 1;
-      chain_pins[len++] = e;
-      int v = c.driver[e];
-      for (;;) {
-        chain_pins[len++] = v;
-        if (c.role[v] != ROLE_COUT) break;
-        int cell = pin_cell[v];
-        int in;
-        if (di >= 0 && pin_cell[devs[di]] == cell) in = devs[di--];
-        else in = cell_in_pins[cell_in_ptr[cell] + crit[cell]];
-        chain_pins[len++] = in;
-        v = c.driver[in];
-      }
-      /* reverse into start -> end order and recompute the path slack */
-      if (pool_n + len > pool_cap) {
-        pool_cap = (pool_n + len) * 2 + 1024;
-        pool = (int32_t *)realloc(pool, sizeof(int32_t) * pool_cap);
-      }
-      int start = chain_pins[len - 1];
-      double arr = at[start];
-      for (int a = 0; a < len; ++a) {
-        int pin = chain_pins[len - 1 - a];
-        pool[pool_n + a] = pin;
-        if (a == 0) continue;
-        int role = c.role[pin];
-        if (role == ROLE_CIN || role == ROLE_FFD) arr += dnet[pin];
-        else if (role == ROLE_COUT) arr += darc[chain_pins[len - a]];
-      }
-      if (npaths == pcap) { pcap = pcap ? 2 * pcap : 1024; paths = (opath *)realloc(paths, sizeof(opath) * pcap); }
-      paths[npaths].slack = rat[e] - arr;
-      paths[npaths].ep = e;
-      paths[npaths].rank = r;
-      paths[npaths].start = (int)pool_n;
-      paths[npaths].len = len;
-      npaths++;
-      pool_n += len;
+      add_path(&c, pin_cell, cell_in_ptr, cell_in_pins, at, rat, dnet, darc, crit, e, r, devs, nd, chain_pins,
+               &pool, &pool_n, &pool_cap, &paths, &npaths, &pcap);
     }
     free(popped);
     free(h.a);
@@ -522,6 +543,141 @@ int ora_extract(NETLIST_ARGS, const double *at, const double *rat, const double 
     }
   }
   free(paths); free(pool); free(chain_pins); free(eps);
+  conn_free(&c);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* K worst paths over the whole design                                       */
+/* ------------------------------------------------------------------------ */
+/* report_timing(K) (Sec. III-B, Table I): the K paths of smallest slack over
+ * all endpoints together, however many fall on one endpoint.  Every
+ * endpoint's deviation tree is searched by one best-first expansion: a
+ * candidate's key is its path slack, the endpoint's slack plus its deviation
+ * costs; the roots are the endpoints' critical paths, taken in (slack, pin)
+ * order so that equal keys pop in that order.  The first K pops are the
+ * answer.  Paths with key >= slack_limit are not reported.
+ * Outputs as ora_extract: paths ordered by (recomputed slack, endpoint pin,
+ * rank), rank counting the earlier pops at the same endpoint; *next_slack
+ * receives the key of the (K+1)-th pop (+inf if there is none).  Returns
+ * the number of paths, -1 on a cycle, -2 if pins_capacity is too small. */
+typedef struct { double key, cost; long seq; int parent, dev, u, ep; } gcand;
+typedef struct { gcand *a; int n, cap; } gheap;
+
+static int gcand_less(const gcand *x, const gcand *y) {
+  if (x->key != y->key) return x->key < y->key;
+  return x->seq < y->seq;
+}
+static void gheap_push(gheap *h, gcand v) {
+  if (h->n == h->cap) { h->cap = h->cap ? 2 * h->cap : 1024; h->a = (gcand *)realloc(h->a, sizeof(gcand) * h->cap); }
+  int i = h->n++;
+  h->a[i] = v;
+  while (i > 0) {
+    int par = (i - 1) / 2;
+    if (!gcand_less(&h->a[i], &h->a[par])) break;
+    gcand t = h->a[i]; h->a[i] = h->a[par]; h->a[par] = t;
+    i = par;
+  }
+}
+static gcand gheap_pop(gheap *h) {
+  gcand top = h->a[0];
+  h->a[0] = h->a[--h->n];
+  int i = 0;
+  for (;;) {
+    int l = 2 * i + 1, r = l + 1, m = i;
+    if (l < h->n && gcand_less(&h->a[l], &h->a[m])) m = l;
+    if (r < h->n && gcand_less(&h->a[r], &h->a[m])) m = r;
+    if (m == i) break;
+    gcand t = h->a[i]; h->a[i] = h->a[m]; h->a[m] = t;
+    i = m;
+  }
+  return top;
+}
+
+int ora_report_timing(NETLIST_ARGS, const double *at, const double *rat, const double *dnet,
+                      const double *darc, const int32_t *crit, int K, double slack_limit,
+                      int32_t *path_ptr, int32_t *path_pins, int pins_capacity, int32_t *path_ep,
+                      int32_t *path_rank, double *path_slack, double *next_slack) {
+  FILL_NETLIST(n);
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  int P = num_pins;
+  int E = 0;
+  for (int p = 0; p < P; ++p) if (c.role[p] == ROLE_FFD) E++;
+  oep *eps = (oep *)malloc(sizeof(oep) * (E > 0 ? E : 1));
+  E = 0;
+  for (int p = 0; p < P; ++p)
+    if (c.role[p] == ROLE_FFD) {
+      double s = (at[p] == -INFINITY) ? INFINITY : rat[p] - at[p];
+      eps[E].slack = s; eps[E].pin = p; E++;
+    }
+  qsort(eps, E, sizeof(oep), oep_cmp);
+  int *ep_count = (int *)calloc(P > 0 ? P : 1, sizeof(int));
+
+  gheap h = {0, 0, 0};
+  long seq = 0;
+  for (int q = 0; q < E; ++q) {
+    if (eps[q].slack == INFINITY) continue;
+    gcand root = {eps[q].slack, 0.0, seq++, -1, -1, c.driver[eps[q].pin], eps[q].pin};
+    gheap_push(&h, root);
+  }
+  gcand *popped = (gcand *)malloc(sizeof(gcand) * (K > 0 ? K : 1));
+  int *rank_of = (int *)malloc(sizeof(int) * (K > 0 ? K : 1));
+  int npop = 0;
+  *next_slack = INFINITY;
+  while (h.n > 0) {
+    gcand p = gheap_pop(&h);
+    if (p.key >= slack_limit) break;
+    if (npop == K) { *next_slack = p.key; break; }
+    popped[npop] = p;
+    rank_of[npop] = ep_count[p.ep]++;
+    int me = npop++;
+    double s_e = rat[p.ep] - at[p.ep];
+    /* children: one more deviation on the arrival-tree chain from p.u */
+    int v = p.u;
+    while (c.role[v] == ROLE_COUT) {
+      int cell = pin_cell[v];
+      int b = cell_in_ptr[cell];
+      for (int j = 0; b + j < cell_in_ptr[cell + 1]; ++j) {
+        if (j == crit[cell]) continue;
+        int i = cell_in_pins[b + j];
+        if (at[i] == -INFINITY) continue;
+        double delta = at[v] - (at[i] + darc[i]);
+        gcand ch = {s_e + (p.cost + delta), p.cost + delta, seq++, me, i, c.driver[i], p.ep};
+        gheap_push(&h, ch);
+      }
+      v = c.driver[cell_in_pins[b + crit[cell]]];
+    }
+  }
+  /* materialise: deviations of pop r, upstream-most first */
+  int *devs = (int *)malloc(sizeof(int) * (P > 0 ? P : 1));
+  int *chain_pins = (int *)malloc(sizeof(int) * (2 * P + 2));
+  opath *paths = NULL;
+  int npaths = 0, pcap = 0;
+  int32_t *pool = NULL;
+  long pool_n = 0, pool_cap = 0;
+  for (int r = 0; r < npop; ++r) {
+    int nd = 0;
+    for (int a = r; a >= 0 && popped[a].dev >= 0; a = popped[a].parent) devs[nd++] = popped[a].dev;
+    add_path(&c, pin_cell, cell_in_ptr, cell_in_pins, at, rat, dnet, darc, crit, popped[r].ep, rank_of[r], devs,
+             nd, chain_pins, &pool, &pool_n, &pool_cap, &paths, &npaths, &pcap);
+  }
+  qsort(paths, npaths, sizeof(opath), opath_cmp);
+  int rc = npaths;
+  if (pool_n > pins_capacity) {
+    rc = -2;
+  } else {
+    path_ptr[0] = 0;
+    for (int a = 0; a < npaths; ++a) {
+      memcpy(path_pins + path_ptr[a], pool + paths[a].start, sizeof(int32_t) * paths[a].len);
+      path_ptr[a + 1] = path_ptr[a] + paths[a].len;
+      path_ep[a] = paths[a].ep;
+      path_rank[a] = paths[a].rank;
+      path_slack[a] = paths[a].slack;
+    }
+  }
+  free(paths); free(pool); free(chain_pins); free(devs); free(popped); free(rank_of); free(h.a);
+  free(ep_count); free(eps);
   conn_free(&c);
   return rc;
 }

@@ -156,6 +156,74 @@ def test_k_paths_match_brute_force(seed, library):
                 assert any(pl == w[1] for w in want)
 
 
+def _all_paths(nl, st):
+    """Every path of the design with its slack, sorted by slack."""
+    out = []
+    for e in ref.endpoint_pins(nl):
+        out += [(s, int(e), pl) for s, pl in brute_endpoint_paths(nl, st, int(e))]
+    out.sort(key=lambda t: t[0])
+    return out
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("K", [1, 7, 40, 10 ** 6])
+def test_global_k_paths_match_brute_force(seed, K, library):
+    """report_timing(K): the K smallest slacks over every path of the design;
+    a path whose slack is separated from its neighbours is fixed pin for pin,
+    ranks count the earlier paths of the same endpoint."""
+    nl = with_clock(_tiny(seed), library, 0.3)
+    st = ref.sta(nl, library)
+    want = _all_paths(nl, st)
+    got = ref.report_timing(nl, library, st, K)
+    m = got["num_paths"]
+    assert m == min(K, len(want))
+    gl = ref.path_list(got)
+    assert np.all(np.diff(got["path_slack"]) >= 0)
+    assert len(set(map(tuple, gl))) == m
+    for r in range(m):
+        s = got["path_slack"][r]
+        assert abs(s - want[r][0]) <= 1e-9 * max(1.0, abs(want[r][0]))
+        lo = r == 0 or want[r][0] - want[r - 1][0] > 1e-9
+        hi = r + 1 >= len(want) or want[r + 1][0] - want[r][0] > 1e-9
+        if lo and hi:
+            assert gl[r] == want[r][2] and got["path_ep"][r] == want[r][1]
+        else:
+            assert any(gl[r] == w[2] for w in want)
+    nxt = want[m][0] if m < len(want) else math.inf
+    assert got["next_slack"] == nxt or abs(got["next_slack"] - nxt) <= 1e-9 * max(1.0, abs(nxt))
+    seen = {}
+    for r in range(m):
+        e = int(got["path_ep"][r])
+        assert got["path_rank"][r] == seen.get(e, 0)
+        seen[e] = seen.get(e, 0) + 1
+
+
+def test_global_k_agrees_with_per_endpoint_lists(library):
+    """On the 2k-cell workload: the paths report_timing(K) puts on an
+    endpoint are that endpoint's worst paths, and its K-th slack is no larger
+    than the K-th smallest of the per-endpoint top-k union (a subset of all
+    paths)."""
+    nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), library)
+    st = ref.sta(nl, library)
+    K = 100
+    g = ref.report_timing(nl, library, st, K)
+    assert g["num_paths"] == K
+    E = ref.endpoint_pins(nl)
+    per = ref.extract(nl, library, st, n=len(E), k=10)
+    assert g["path_slack"][-1] <= np.sort(per["path_slack"])[K - 1] + 1e-9
+    cnt = {}
+    for e in g["path_ep"].tolist():
+        cnt[e] = cnt.get(e, 0) + 1
+    for e, c in cnt.items():
+        one = ref.extract(nl, library, st, n=len(E), k=c)
+        s_ep = np.sort(one["path_slack"][one["path_ep"] == e])
+        s_gl = np.sort(g["path_slack"][g["path_ep"] == e])
+        assert np.allclose(s_ep, s_gl, rtol=0, atol=1e-9)
+    # every endpoint absent from the answer has slack >= the K-th path's
+    absent = np.setdiff1d(E, np.array(list(cnt.keys())))
+    assert np.all(st["slack"][absent] >= g["path_slack"][-1] - 1e-9)
+
+
 # ---------------------------------------------------------------------------
 # invariants on the smallest workload
 # ---------------------------------------------------------------------------
