@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch configuration)")
     ap.add_argument("--sweep-mode", type=int, default=-1, help="force a sweep form (0 per level, 1 dataflow)")
     ap.add_argument("--serial", action="store_true", help="run the whole step on one stream")
+    ap.add_argument("--table1", action="store_true",
+                    help="extraction statistics of report_timing(K) against report_timing_endpoint(n, k) "
+                         "(paths, endpoints, pin pairs, time) instead of the step benchmark")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy of MB MiB (counter calibration)")
     return ap.parse_args()
@@ -157,6 +160,64 @@ def build_step(g, x, y, k, K, gx, gy, wl, pp, beta, overlap=True):
     return step
 
 
+def bench_table1(a):
+    """Sec. III-B / Table I on a synthetic design: the K worst paths of the
+    whole design (report_timing(K), K = n_fail and 10 n_fail) against the
+    worst paths per failing endpoint (report_timing_endpoint(n_fail, 1) and
+    (n_fail, 10)): number of paths, of distinct endpoints and of distinct pin
+    pairs (net arcs) on them, and the GPU time of the call."""
+    import torch
+
+    from paper_2503_11674_amd import netgen
+    from paper_2503_11674_amd.tdp import TimingGraph
+
+    cfg = netgen.CONFIGS[a.workload]
+    nl = netgen.make_netlist(cfg)
+    lib = netgen.make_library()
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(nl["x"], device=dev)
+    y = torch.tensor(nl["y"], device=dev)
+    E = int(np.count_nonzero(nl["cell_is_ff"]))
+    nf = E // 20
+    g = TimingGraph(nl, lib, max_paths=10 * nf, max_k=10)
+    g.sta_update(x, y)
+    at = g.export()["at"].cpu().numpy()
+    ep = nl["cell_in_pins"][nl["cell_in_ptr"][np.nonzero(nl["cell_is_ff"])[0]]]
+    g.set_clock(netgen.clock_period_for_fail_fraction(at[ep], 0.05))
+    g.sta_update(x, y)
+    wns, tns, n_fail = g.summary()
+    cmds = [(f"report_timing({n_fail})", lambda: g.report_timing(n_fail)),
+            (f"report_timing({10 * n_fail})", lambda: g.report_timing(10 * n_fail)),
+            (f"report_timing_endpoint({n_fail},1)", lambda: g.extract_paths(n=-1, k=1, K=n_fail)),
+            (f"report_timing_endpoint({n_fail},10)", lambda: g.extract_paths(n=-1, k=10, K=10 * n_fail))]
+    rows = []
+    for name, call in cmds:
+        print(f"[table1] {name}", file=sys.stderr, flush=True)
+        call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(1, a.steps)):
+            t0 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        p = g.paths()
+        ptr, pins = p["path_ptr"], p["path_pins"]
+        lens = np.diff(ptr)
+        pos = np.arange(pins.shape[0]) - np.repeat(ptr[:-1], lens)
+        rows.append({"command": name, "paths": int(p["num_paths"]),
+                     "endpoints": int(np.unique(p["path_ep"]).shape[0]),
+                     "pin_pairs": int(np.unique(pins[pos % 2 == 1]).shape[0]),
+                     "ms": round(1e3 * float(np.median(ts)), 3),
+                     "worst_slack": float(p["path_slack"][0]) if p["num_paths"] else None,
+                     "last_slack": float(p["path_slack"][-1]) if p["num_paths"] else None})
+        print(f"[table1] {rows[-1]}", file=sys.stderr, flush=True)
+    print(json.dumps({"table": "extraction statistics (Sec. III-B, Table I analogue)",
+                      "workload": f"{a.workload}: {nl['num_cells']} cells, {nl['num_pins']} pins, "
+                                  f"{E} endpoints", "n_fail": n_fail, "wns": wns, "tns": tns,
+                      "runs": max(1, a.steps), "rows": rows}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -170,6 +231,8 @@ def main():
 
     if a.workload == "C4":
         return bench_batch(a)
+    if a.table1:
+        return bench_table1(a)
     cfg = netgen.CONFIGS[a.workload]
     t0 = time.time()
     nl = netgen.make_netlist(cfg)

@@ -199,6 +199,21 @@ tdp_status tdp_sta_export_crit(tdp_graph, int32_t *d_crit, hipStream_t);
  * before the first update. */
 tdp_status tdp_extract_paths(tdp_graph, int32_t n, int32_t k, int32_t K, float slack_limit,
                              hipStream_t, tdp_paths *out);
+/* report_timing(K) (Sec. III-B, Table I): the K paths of smallest slack over
+ * the whole design (each instance of a batched graph on its own), however
+ * many end at one endpoint; paths with slack >= slack_limit are dropped.
+ * K is capped at max_paths (max_paths_each for a batched graph).  Output as
+ * tdp_extract_paths (same views, replacing its paths), ordered by (slack,
+ * then a fixed order among equal slacks); path_rank counts the earlier paths
+ * of the same endpoint.  Exact: a bound on the K-th slack from the
+ * per-endpoint search, then every path within it by deviation expansion.
+ * Unlike the per-endpoint call it synchronises the stream (one counter read
+ * per expansion round) and allocates its node store on its first call.
+ * Errors: TDP_E_STATE before the first update, TDP_E_INVALID for K < 0 or a
+ * NaN limit, TDP_E_NOMEM if the node store cannot be allocated,
+ * TDP_E_CAPACITY if more paths tie at the K-th slack than the store holds
+ * (8 * max_paths nodes, at least E * max_k). */
+tdp_status tdp_report_timing(tdp_graph, int32_t K, float slack_limit, hipStream_t, tdp_paths *out);
 /* Number of paths and of path pins of the last extraction (synchronises). */
 tdp_status tdp_paths_count(tdp_graph, int32_t *num_paths, int32_t *num_pins, hipStream_t);
 

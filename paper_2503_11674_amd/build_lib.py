@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtdp.so")
-SOURCES = ["tdp_build.cpp", "tdp_prims.hip", "tdp_sta.hip", "tdp_paths.hip", "tdp_pairs.hip",
+SOURCES = ["tdp_build.cpp", "tdp_prims.hip", "tdp_sta.hip", "tdp_paths.hip", "tdp_global.hip", "tdp_pairs.hip",
            "tdp_smooth.hip", "tdp_api.hip"]
 ARCH = os.environ.get("TDP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -199,7 +199,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        dalloc(g, g->inst_seg, ni) && dalloc(g, g->inst_outb, ni) && dalloc(g, g->inst_kept, ni) &&
        dalloc(g, g->inst_selb, ni) && dalloc(g, g->sel_npop, T.E) &&
        dalloc(g, g->slot_key, sc, es) && dalloc(g, g->slot_dev, sc) && dalloc(g, g->slot_par, sc) &&
-       dalloc(g, g->slot_len, sc) && dalloc(g, g->slot_out, sc) && dalloc(g, g->slot_cells, sc) && dalloc(g, g->d_nslots, 1) &&
+       dalloc(g, g->slot_len, sc) && dalloc(g, g->slot_out, std::max(sc, mo)) && dalloc(g, g->slot_cells, sc) && dalloc(g, g->d_nslots, 1) &&
        dalloc(g, g->sort_k0, sc) && dalloc(g, g->sort_k1, sc) && dalloc(g, g->sort_v0, sc) &&
        dalloc(g, g->sort_v1, sc) && dalloc(g, g->sort_hist, sort_hist_size(sc)) &&
        dalloc(g, g->scan_tmp, scan_tmp_size(scan_cap)) && dalloc(g, g->out_slot, mo) &&
@@ -385,6 +385,52 @@ tdp_status tdp_extract_paths(tdp_graph g, int32_t n, int32_t k, int32_t K, float
   if (st != TDP_OK) return st;
   g->extracted = true;
   g->last_k = k;
+  if (out) {
+    out->max_paths = g->max_out;
+    out->d_num_paths = g->d_num_paths;
+    out->path_ptr = g->path_ptr;
+    out->path_pins = g->path_pins;
+    out->path_ep = g->path_ep;
+    out->path_rank = g->path_rank;
+    out->path_slack = g->path_slack;
+  }
+  return TDP_OK;
+}
+
+// the node store of report_timing(K), made on its first call
+static tdp_status ensure_global(tdp_graph g) {
+  if (g->gcap > 0) return TDP_OK;
+  const Topo &T = g->topo;
+  const int64_t want = std::max<int64_t>({(int64_t)8 * g->max_out, (int64_t)g->slot_cap, 4096});
+  const int cap = (int)std::min<int64_t>(want, (int64_t)1 << 27);
+  const size_t es = g->esz;
+  const int scan_cap = std::max(cap, sort_hist_size(cap));
+  const bool ok = dalloc(g, g->gt_cost, cap, es) && dalloc(g, g->gt_key, cap, es) &&
+                  dalloc(g, g->gt_theta, T.num_inst, es) && dalloc(g, g->gt_dev, cap) && dalloc(g, g->gt_par, cap) &&
+                  dalloc(g, g->gt_ep, cap) && dalloc(g, g->gt_cells, cap) && dalloc(g, g->gt_nd, cap) &&
+                  dalloc(g, g->gt_cnt, cap) && dalloc(g, g->gt_off, cap) && dalloc(g, g->gt_start, T.num_inst) &&
+                  dalloc(g, g->gt_end, T.num_inst) && dalloc(g, g->gt_misc, 4) && dalloc(g, g->gt_k0, cap) &&
+                  dalloc(g, g->gt_k1, cap) && dalloc(g, g->gt_v0, cap) && dalloc(g, g->gt_v1, cap) &&
+                  dalloc(g, g->gt_hist, sort_hist_size(cap)) && dalloc(g, g->gt_scan, scan_tmp_size(scan_cap));
+  if (!ok) return fail(g, TDP_E_NOMEM, "report_timing: device allocation failed");
+  g->gcap = cap;
+  return TDP_OK;
+}
+
+tdp_status tdp_report_timing(tdp_graph g, int32_t K, float slack_limit, hipStream_t s, tdp_paths *out) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (K < 0) return fail(g, TDP_E_INVALID, "K < 0");
+  if (std::isnan(slack_limit)) return fail(g, TDP_E_INVALID, "slack_limit is NaN");
+  tdp_status st = ensure_global(g);
+  if (st != TDP_OK) return st;
+  const int Keff = std::min(K, g->max_out_inst);
+  dispatch(g, [&](auto z) { st = report_impl<decltype(z)>(g, Keff, slack_limit, s); });
+  if (st != TDP_OK) return st;
+  st = check_launch(g, "report_timing");
+  if (st != TDP_OK) return st;
+  g->extracted = true;
+  g->last_k = 1;
   if (out) {
     out->max_paths = g->max_out;
     out->d_num_paths = g->d_num_paths;

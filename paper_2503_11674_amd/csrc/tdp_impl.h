@@ -31,6 +31,12 @@ void sta_export_impl(tdp_graph g, double *at, double *rat, double *slack, double
                      double *load, double *darc, hipStream_t s);
 void sta_export_crit(tdp_graph g, int32_t *out, hipStream_t s);
 template <typename T> void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream_t s);
+template <typename T> void select_stage(tdp_graph g, int n, hipStream_t s);
+template <typename T> void search_stage(tdp_graph g, int k, float slack_limit, hipStream_t s);
+template <typename T> void slot_sort_stage(tdp_graph g, int k, hipStream_t s);
+void ptr_tail(const int32_t *d_num_paths, const int32_t *len, int32_t *ptr, hipStream_t s);
+// report_timing(K); returns a status (it synchronises on s)
+template <typename T> tdp_status report_impl(tdp_graph g, int K, float slack_limit, hipStream_t s);
 template <typename T> void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s);
 void pairs_rebuild(tdp_graph g, hipStream_t s);
 void pairs_compact(tdp_graph g, hipStream_t s);

@@ -223,6 +223,17 @@ struct tdp_graph_s {
   void *path_slack = nullptr;
   int32_t last_k = 1;
 
+  // design-wide extraction, report_timing(K): a store of gcap search nodes
+  // and its sort / scan buffers, allocated by the first such call
+  int32_t gcap = 0;
+  void *gt_cost = nullptr, *gt_key = nullptr, *gt_theta = nullptr;
+  int32_t *gt_dev = nullptr, *gt_par = nullptr, *gt_ep = nullptr, *gt_cells = nullptr, *gt_nd = nullptr;
+  int32_t *gt_cnt = nullptr, *gt_off = nullptr, *gt_start = nullptr, *gt_end = nullptr;
+  int32_t *gt_misc = nullptr;  // [4] device counters read back per round
+  uint64_t *gt_k0 = nullptr, *gt_k1 = nullptr;
+  uint32_t *gt_v0 = nullptr, *gt_v1 = nullptr;
+  int32_t *gt_hist = nullptr, *gt_scan = nullptr;
+
   // pairs
   float *pw = nullptr;                 // [S] weight per sink pin
   uint8_t *pin_p = nullptr;            // [S] membership in P

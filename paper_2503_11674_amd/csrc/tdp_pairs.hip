@@ -386,7 +386,7 @@ void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s)
   // 80 % of the hash table, otherwise fall back to plain global atomics
   const int per_block = (HASH_SLOTS * 4 / 5) / (tp.D + 1);
   if (per_block >= 1)
-    hipLaunchKernelGGL(k_pairs_acc_lds<T>, dim3(nb(g->slot_cap, per_block)), dim3(256), 0, s, tp, rule, per_block,
+    hipLaunchKernelGGL(k_pairs_acc_lds<T>, dim3(nb(std::max(g->slot_cap, g->max_out), per_block)), dim3(256), 0, s, tp, rule, per_block,
                        g->d_nslots, g->slot_out, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack,
                        g->summary, g->pin_p, g->pacc, g->pfirst);
   else

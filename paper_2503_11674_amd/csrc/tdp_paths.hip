@@ -25,12 +25,9 @@
 //                  writing the pins in place from the end.
 #include "tdp_impl.h"
 #include "tdp_prims.h"
+#include "tdp_walk.h"
 
 namespace tdp {
-
-template <typename T> __device__ __forceinline__ T inf_of();
-template <> __device__ __forceinline__ float inf_of<float>() { return __builtin_huge_valf(); }
-template <> __device__ __forceinline__ double inf_of<double>() { return __builtin_huge_val(); }
 
 // ------------------------------------------------------------- selection
 template <typename T>
@@ -251,40 +248,6 @@ __global__ void k_path_index(Topo tp, int k, const int32_t *__restrict__ d_nslot
 }
 
 // ----------------------------------------------------------------- walk
-// Writes a path from its last position down to its first, two arrays at
-// once.  Values are staged in LDS per aligned group of 32 positions (128
-// bytes) and a group goes out in one burst when its lowest position is
-// written (or the path starts inside it), so the L2 sees whole lines instead
-// of scattered words.  `sa` / `sb`: this thread's 33-word LDS rows (the odd
-// stride keeps the lanes of a wave on different banks).
-struct RevWriter {
-  int32_t *a, *b;
-  int32_t *sa, *sb;
-  int pos, lo, hi;  // next position (descending), path range [lo, hi)
-  __device__ void put(int32_t va, int32_t vb) {
-    const int j = pos & 31;
-    sa[j] = va;
-    sb[j] = vb;
-    if (j == 0 || pos == lo) flush(pos, j);
-    --pos;
-  }
-  __device__ void flush(int p0, int j0) {
-    const int top = min(hi - 1, p0 | 31);
-    if (j0 == 0 && top == p0 + 31) {
-#pragma unroll
-      for (int q = 0; q < 32; q += 4) {
-        *(int4 *)(a + p0 + q) = make_int4(sa[q], sa[q + 1], sa[q + 2], sa[q + 3]);
-        *(int4 *)(b + p0 + q) = make_int4(sb[q], sb[q + 1], sb[q + 2], sb[q + 3]);
-      }
-      return;
-    }
-    for (int p = p0; p <= top; ++p) {
-      a[p] = sa[p & 31];
-      b[p] = sb[p & 31];
-    }
-  }
-};
-
 template <typename T>
 __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__restrict__ d_num_paths,
                                                const int32_t *__restrict__ out_slot, const int32_t *__restrict__ sel,
@@ -310,6 +273,7 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
     devs[nd++] = d;
     a = slot_par[base + a];
   }
+  int di = nd - 1;
   const int lo = path_ptr[q];
   const int hi = path_ptr[q + 1];
   if (lo < 0 || hi > pin_cap || hi - lo < 2) {  // only after a failed update
@@ -317,68 +281,8 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
     return;
   }
   RevWriter w{path_pins, path_int, stage[0] + threadIdx.x * 33, stage[1] + threadIdx.x * 33, hi - 1, lo, hi};
+  if (!walk_path(tp, hop4, w, f, [&]() { return di >= 0 ? devs[di--] : -1; })) atomicOr(err, 1);
   const int et = tp.A + f;
-  w.put(tp.snk_ext[et], tp.M + et);
-  int v = tp.snk_drv[et];
-  w.put(tp.drv_ext[v], v);
-  // the next deviation in registers: its sink, cell, external id and driver
-  int di = nd - 1;
-  int dt = -1, dc = -1;
-  if (di >= 0) {
-    dt = devs[di];
-    dc = tp.snk_comb[dt];
-  }
-  // Group-synchronous walk: every iteration all lanes load the four-hop
-  // record of their current cell together (one memory latency for the wave)
-  // and advance up to four cells along it; a deviation cell leaves the chain
-  // and ends the lane's group early.
-  bool done = v < tp.n_start;
-  while (!done && w.pos >= lo) {
-    const int4 *hp = hop4 + (size_t)(v - tp.n_start) * 4;
-    const int4 g0 = hp[0], g1 = hp[1], g2 = hp[2], g3 = hp[3];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int c = v - tp.n_start;
-      int t, text, nv, nvext;
-      bool dev = c == dc;
-      if (dev) {
-        t = dt;
-        text = tp.snk_ext[t];
-        nv = tp.snk_drv[t];
-        nvext = tp.drv_ext[nv];
-        if (--di >= 0) {
-          dt = devs[di];
-          dc = tp.snk_comb[dt];
-        } else {
-          dt = -1;
-          dc = -1;
-        }
-      } else {
-        const int4 h = i == 0 ? g0 : (i == 1 ? g1 : (i == 2 ? g2 : g3));
-        t = h.x;
-        nv = h.y;
-        text = h.z;
-        nvext = h.w;
-      }
-      if (w.pos < lo) {
-        done = true;
-        break;
-      }
-      w.put(text, tp.M + t);
-      if (w.pos < lo) {
-        done = true;
-        break;
-      }
-      w.put(nvext, nv);
-      v = nv;
-      if (v < tp.n_start) {
-        done = true;
-        break;
-      }
-      if (dev) break;  // off the chain: reload at the new cell
-    }
-  }
-  if (w.pos != lo - 1 || v >= tp.n_start || di >= 0) atomicOr(err, 1);
   path_ep[q] = tp.snk_ext[et];
   path_epi[q] = f;
   path_rank[q] = r;
@@ -403,12 +307,12 @@ static void launch_search(tdp_graph g, int k, T limit, hipStream_t s) {
                      g->slot_dev, g->slot_par, g->slot_len, g->slot_cells, g->sel_npop);
 }
 
+// endpoints of each instance: the first n in (slack, pin) order, or the
+// violated ones (n < 0); fills sel_list, d_nsel, inst_selb, inst_nsel
 template <typename T>
-void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream_t s) {
+void select_stage(tdp_graph g, int n, hipStream_t s) {
   const Topo &tp = g->topo;
   const int E = tp.E;
-  // selection
-  prof_begin(g, TDP_STAGE_SELECT, s);
   if (n < 0) {
     hipLaunchKernelGGL(k_sel_violated<T>, dim3(nb(E, 256)), dim3(256), 0, s, tp, (const T *)g->ep_slack,
                        g->sel_flag);
@@ -424,9 +328,12 @@ void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream
   hipLaunchKernelGGL(k_sel_compact, dim3(nb(E, 256)), dim3(256), 0, s, tp, g->sel_flag, g->sel_pos, g->sel_list);
   hipLaunchKernelGGL(k_sel_counts, dim3(nb(tp.num_inst, 64)), dim3(64), 0, s, tp.num_inst, E, g->d_ep_base,
                      g->sel_pos, g->d_nsel, g->inst_selb, g->inst_nsel);
-  prof_end(g, TDP_STAGE_SELECT, s);
-  // search
-  prof_begin(g, TDP_STAGE_SEARCH, s);
+}
+
+// up to k paths per selected endpoint, in slots q * k + r; per instance the
+// number found (inst_nvalid)
+template <typename T>
+void search_stage(tdp_graph g, int k, float slack_limit, hipStream_t s) {
   const T limit = (T)slack_limit;
   switch (g->side_k) {
     case 1: launch_search<T, 1>(g, k, limit, s); break;
@@ -436,22 +343,44 @@ void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream
     case 16: launch_search<T, 16>(g, k, limit, s); break;
     default: launch_search<T, 32>(g, k, limit, s); break;
   }
-  hipLaunchKernelGGL(k_valid_counts, dim3(tp.num_inst), dim3(256), 0, s, g->inst_selb, g->inst_nsel, g->sel_npop,
-                     g->inst_nvalid);
+  hipLaunchKernelGGL(k_valid_counts, dim3(g->topo.num_inst), dim3(256), 0, s, g->inst_selb, g->inst_nsel,
+                     g->sel_npop, g->inst_nvalid);
+}
+
+// slots sorted by (instance, path slack), stable: sort_v0 holds the slot
+// order, sort_k0 the keys
+template <typename T>
+void slot_sort_stage(tdp_graph g, int k, hipStream_t s) {
+  const int cap = g->slot_cap;
+  hipLaunchKernelGGL(k_slot_keys<T>, dim3(nb(cap, 256)), dim3(256), 0, s, g->topo, k, g->d_nsel, g->sel_list,
+                     (const T *)g->slot_key, g->d_nslots, g->sort_k0, g->sort_v0, (int64_t)cap);
+  radix_sort(g->sort_k0, g->sort_v0, g->sort_k1, g->sort_v1, cap, g->d_nslots,
+             sizeof(T) == 4 ? g->key_bits32 : 64, g->sort_hist, g->scan_tmp, s);
+}
+
+void ptr_tail(const int32_t *d_num_paths, const int32_t *len, int32_t *ptr, hipStream_t s) {
+  hipLaunchKernelGGL(k_ptr_tail, dim3(1), dim3(1), 0, s, d_num_paths, len, ptr);
+}
+
+template <typename T>
+void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream_t s) {
+  const Topo &tp = g->topo;
+  prof_begin(g, TDP_STAGE_SELECT, s);
+  select_stage<T>(g, n, s);
+  prof_end(g, TDP_STAGE_SELECT, s);
+  prof_begin(g, TDP_STAGE_SEARCH, s);
+  search_stage<T>(g, k, slack_limit, s);
   prof_end(g, TDP_STAGE_SEARCH, s);
   // ordering
   prof_begin(g, TDP_STAGE_ORDER, s);
   const int cap = g->slot_cap;
-  hipLaunchKernelGGL(k_slot_keys<T>, dim3(nb(cap, 256)), dim3(256), 0, s, tp, k, g->d_nsel, g->sel_list,
-                     (const T *)g->slot_key, g->d_nslots, g->sort_k0, g->sort_v0, (int64_t)cap);
-  radix_sort(g->sort_k0, g->sort_v0, g->sort_k1, g->sort_v1, cap, g->d_nslots,
-             sizeof(T) == 4 ? g->key_bits32 : 64, g->sort_hist, g->scan_tmp, s);
+  slot_sort_stage<T>(g, k, s);
   hipLaunchKernelGGL(k_path_bases, dim3(1), dim3(1), 0, s, tp.num_inst, k, K, g->inst_nsel, g->inst_nvalid,
                      g->inst_seg, g->inst_outb, g->inst_kept, g->d_num_paths);
   hipLaunchKernelGGL(k_path_index<T>, dim3(nb(cap, 256)), dim3(256), 0, s, tp, k, g->d_nslots, g->sort_v0,
                      g->sel_list, g->inst_seg, g->inst_outb, g->inst_kept, g->slot_len, g->out_slot, g->out_len, g->slot_out);
   scan_exclusive(g->out_len, g->path_ptr, g->max_out, g->d_num_paths, nullptr, g->scan_tmp, s);
-  hipLaunchKernelGGL(k_ptr_tail, dim3(1), dim3(1), 0, s, g->d_num_paths, g->out_len, g->path_ptr);
+  ptr_tail(g->d_num_paths, g->out_len, g->path_ptr, s);
   prof_end(g, TDP_STAGE_ORDER, s);
   // walk
   prof_begin(g, TDP_STAGE_WALK, s);
@@ -464,5 +393,11 @@ void extract_impl(tdp_graph g, int n, int k, int K, float slack_limit, hipStream
 
 template void extract_impl<float>(tdp_graph, int, int, int, float, hipStream_t);
 template void extract_impl<double>(tdp_graph, int, int, int, float, hipStream_t);
+template void select_stage<float>(tdp_graph, int, hipStream_t);
+template void select_stage<double>(tdp_graph, int, hipStream_t);
+template void search_stage<float>(tdp_graph, int, float, hipStream_t);
+template void search_stage<double>(tdp_graph, int, float, hipStream_t);
+template void slot_sort_stage<float>(tdp_graph, int, hipStream_t);
+template void slot_sort_stage<double>(tdp_graph, int, hipStream_t);
 
 }  // namespace tdp

@@ -250,3 +250,90 @@ def pair_sinks(paths, mask=None):
     if mask is not None:
         sel &= np.asarray(mask)[pid]
     return pins[sel]
+
+
+def path_slacks(paths, st):
+    """FP64 slack of every path from the oracle's arc delays:
+    RAT(end) - (AT(start) + net delays into its sinks + cell-arc delays)."""
+    m = int(paths["num_paths"])
+    if m == 0:
+        return np.zeros(0)
+    pid, pos, _ = _segments(paths["path_ptr"])
+    pins = np.asarray(paths["path_pins"], np.int64)
+    ptr = np.asarray(paths["path_ptr"], np.int64)
+    d = np.zeros(pins.shape[0])
+    odd = pos % 2 == 1
+    d[odd] = np.asarray(st["dnet"])[pins[odd]]
+    ev = (pos % 2 == 0) & (pos > 0)
+    d[ev] = np.asarray(st["darc"])[pins[np.nonzero(ev)[0] - 1]]
+    arr = np.zeros(m)
+    np.add.at(arr, pid, d)
+    arr += np.asarray(st["at"])[pins[ptr[:-1]]]
+    return np.asarray(st["rat"])[pins[ptr[1:] - 1]] - arr
+
+
+def _fp32_thresholds(paths, st):
+    """Per path: the single-precision rounding bound of the module doc."""
+    at, rat = np.asarray(st["at"]), np.asarray(st["rat"])
+    ptr = np.asarray(paths["path_ptr"], np.int64)
+    pins = np.asarray(paths["path_pins"], np.int64)
+    d = np.abs(np.diff(at[pins])) if pins.shape[0] > 1 else np.zeros(0)
+    cs = np.concatenate([[0.0], np.cumsum(d)])
+    inner = cs[ptr[1:] - 1] - cs[ptr[:-1]]
+    terms = np.abs(at[pins[ptr[:-1]]]) + np.abs(rat[pins[ptr[1:] - 1]]) + inner
+    L = (np.diff(ptr) - 1).astype(np.float64)
+    gam = L * U32 / (1 - L * U32)
+    return np.maximum(1e-3, 2.0 * gam * terms)
+
+
+def compare_global(gpu, ref, st, tables, fp32=True):
+    """report_timing(K): the GPU's paths against the oracle's.
+
+    Several answers are correct where slacks tie within rounding, so the
+    checks are: every GPU path is a valid, distinct path whose reported slack
+    matches its FP64 recomputation; the sorted FP64 slacks of the two answers
+    agree within the rounding bound (the K order statistics are unique); an
+    oracle path whose slack is separated by more than that bound from its
+    neighbours in the global order (and, for the last one, from the next path
+    after it) is in the GPU answer pin for pin; ranks count the earlier paths
+    of the same endpoint."""
+    m = int(ref["num_paths"])
+    n = int(gpu["num_paths"])
+    res = {"num": n, "count_ok": n == m}
+    at, rat = np.asarray(st["at"]), np.asarray(st["rat"])
+    g_ptr = np.asarray(gpu["path_ptr"], np.int64)
+    g_pins = np.asarray(gpu["path_pins"], np.int64)
+    g_sl = np.asarray(gpu["path_slack"], np.float64)
+    rec = path_slacks(gpu, st)
+    last = g_pins[g_ptr[1:] - 1] if n else np.zeros(0, np.int64)
+    tol = 1e-4 * np.maximum(np.maximum(np.abs(at[last]), np.abs(rat[last])), 1.0)
+    res["valid"] = int(valid_paths(gpu, tables).sum())
+    res["slack_ok"] = int((np.abs(g_sl - rec) <= tol).sum())
+    g_list = [tuple(g_pins[g_ptr[i]:g_ptr[i + 1]].tolist()) for i in range(n)]
+    res["distinct"] = len(set(g_list)) == n
+    res["sorted"] = bool(np.all(np.diff(g_sl) >= 0))
+    thr = _fp32_thresholds(ref, st) if fp32 else np.full(m, 1e-3)
+    thr_all = float(thr.max()) if m else 1e-3
+    r_sl = np.asarray(ref["path_slack"], np.float64)
+    k = min(n, m)
+    res["order_stat_ok"] = bool(np.all(np.abs(np.sort(rec)[:k] - np.sort(r_sl)[:k]) <= 2 * thr_all + tol[:k].max()
+                                       if k else True))
+    # pinned oracle paths
+    nxt = float(ref.get("next_slack", np.inf))
+    prev = np.concatenate([[-np.inf], r_sl[:-1]])
+    after = np.concatenate([r_sl[1:], [nxt]])
+    pinned = ((r_sl - prev) > thr) & ((after - r_sl) > thr)
+    r_ptr = np.asarray(ref["path_ptr"], np.int64)
+    r_pins = np.asarray(ref["path_pins"], np.int64)
+    gset = set(g_list)
+    found = [tuple(r_pins[r_ptr[i]:r_ptr[i + 1]].tolist()) in gset for i in np.nonzero(pinned)[0]]
+    res["pinned"] = int(pinned.sum())
+    res["pinned_found"] = int(sum(found))
+    seen = {}
+    ok = True
+    for i, e in enumerate(np.asarray(gpu["path_ep"]).tolist()):
+        ok &= int(gpu["path_rank"][i]) == seen.get(e, 0)
+        seen[e] = seen.get(e, 0) + 1
+    res["ranks_ok"] = bool(ok)
+    res["endpoints"] = len(seen)
+    return res

@@ -71,3 +71,45 @@ def test_pair_sinks_matches_pairs_of(library):
     mask = rp["path_slack"] < np.median(rp["path_slack"])
     keys = {(int(rp["path_ep"][i]), int(rp["path_rank"][i])) for i in np.nonzero(mask)[0]}
     assert set(pair_sinks(rp, mask).tolist()) == pairs_of(rp, keys)
+
+
+def test_compare_global_accepts_the_oracle_and_flags_mistakes(library):
+    from tests.comparator import compare_global, path_slacks
+    nl, st, _, _ = _case(library)
+    tables = arc_tables(nl)
+    rp = ref.report_timing(nl, library, st, 100)
+    assert np.allclose(path_slacks(rp, st), rp["path_slack"], rtol=0, atol=1e-9)
+
+    def ok(r):
+        return (r["count_ok"] and r["valid"] == r["num"] and r["slack_ok"] == r["num"] and r["distinct"]
+                and r["sorted"] and r["order_stat_ok"] and r["ranks_ok"] and r["pinned_found"] == r["pinned"])
+
+    gp = copy.deepcopy(rp)
+    gp["path_slack"] = gp["path_slack"].astype(np.float32).astype(np.float64)
+    res = compare_global(gp, rp, st, tables)
+    assert ok(res) and res["pinned"] > 50
+    # the (K+1)-th path in place of a pinned one: the order statistics move
+    more = ref.report_timing(nl, library, st, 101)
+    i = int(np.nonzero(np.diff(rp["path_slack"]) > 1.0)[0][0])
+    lists = ref.path_list(more)
+    keep = [j for j in range(101) if j != i]
+    bad = {"num_paths": 100, "path_ep": more["path_ep"][keep], "path_rank": more["path_rank"][keep],
+           "path_slack": more["path_slack"][keep]}
+    sel = [lists[j] for j in keep]
+    bad["path_ptr"] = np.concatenate([[0], np.cumsum([len(p) for p in sel])]).astype(np.int32)
+    bad["path_pins"] = np.concatenate(sel).astype(np.int32)
+    r = compare_global(bad, rp, st, tables)
+    assert not ok(r)
+    # a wrong rank, a corrupt pin, a duplicated path
+    g2 = copy.deepcopy(gp)
+    g2["path_rank"][0] += 1
+    assert not compare_global(g2, rp, st, tables)["ranks_ok"]
+    g3 = copy.deepcopy(gp)
+    g3["path_pins"][g3["path_ptr"][3] + 1] = g3["path_pins"][g3["path_ptr"][3] + 3]
+    assert compare_global(g3, rp, st, tables)["valid"] < 100
+    g4 = copy.deepcopy(gp)
+    a, b = g4["path_ptr"][0], g4["path_ptr"][1]
+    c_, d_ = g4["path_ptr"][1], g4["path_ptr"][2]
+    if b - a == d_ - c_:
+        g4["path_pins"][c_:d_] = g4["path_pins"][a:b]
+        assert not compare_global(g4, rp, st, tables)["distinct"]

@@ -5,7 +5,7 @@ timing update, extraction, pair update, WA and p2p forward/backward).
 * 2M cells (depth 100, 12 % flip-flops, K = 100k paths): every pin's timing,
   every path, the pair set and its weights, both losses and their gradients,
   against the FP64 oracle on the same input (the oracle runs the whole size
-  in seconds).
+  in seconds); then report_timing(K) on the same graph against the oracle's.
 * 1M cells (depth 80, K = 50k, exponential pair weights): the two
   differentiable objectives through torch.autograd against the oracle's
   gradients and against central finite differences (h = 1e-3 um) of the
@@ -20,7 +20,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import ref  # noqa: E402
 from paper_2503_11674_amd import netgen  # noqa: E402
-from tests.comparator import arc_tables, compare_paths_fast, pair_sinks, timing_close  # noqa: E402
+from tests.comparator import arc_tables, compare_global, compare_paths_fast, pair_sinks, timing_close  # noqa: E402
 from tests.conftest import with_clock  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -152,6 +152,18 @@ def test_full_size_step_2m_cells(library):
     _log(f"gradient: worst scaled error {(ex / np.maximum(ax + scale, 1e-12)).max():.3g}")
     assert np.all(ex <= 1e-4 * (ax + scale) + 1e-6)
     assert np.all(ey <= 1e-4 * (ay + scale) + 1e-6)
+
+    # report_timing(K) on the same graph: the K worst paths of the design
+    g.report_timing(K)
+    gk = g.paths()
+    _log(f"GPU report_timing({K}): {gk['num_paths']} paths")
+    rk = ref.report_timing(nl, library, st, K)
+    _log(f"oracle report_timing done: {rk['num_paths']} paths on {len(set(rk['path_ep'].tolist()))} endpoints")
+    res = compare_global(gk, rk, st, arc_tables(nl))
+    _log(f"report_timing: {res}")
+    assert res["count_ok"] and res["num"] == K
+    assert res["valid"] == K and res["slack_ok"] == K and res["distinct"] and res["sorted"] and res["ranks_ok"]
+    assert res["order_stat_ok"] and res["pinned_found"] == res["pinned"] and res["pinned"] > 0
 
 
 # ------------------------------------------------------------------ 1M cells

@@ -15,7 +15,7 @@ from oracle import ref  # noqa: E402
 from paper_2503_11674_amd import netgen  # noqa: E402
 from tests import handnets  # noqa: E402
 from tests.bruteforce import Graph  # noqa: E402
-from tests.comparator import compare_paths, pairs_of, timing_close  # noqa: E402
+from tests.comparator import arc_tables, compare_global, compare_paths, pairs_of, timing_close  # noqa: E402
 from tests.conftest import with_clock  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -199,6 +199,150 @@ def test_paths_on_small_random_dags(library):
         assert gp["num_paths"] == rp["num_paths"], seed
         assert res["missing"] == 0 and res["extra"] == 0, seed
         assert res["pinned_ok"] == res["pinned"] and res["unpinned_ok"] == res["unpinned"], (seed, res)
+
+
+# ------------------------------------------------------ report_timing(K)
+def _check_global(gp, rp, st, nl, fp32=True):
+    res = compare_global(gp, rp, st, arc_tables(nl), fp32=fp32)
+    print(res, flush=True)
+    assert res["count_ok"], (gp["num_paths"], rp["num_paths"])
+    assert res["valid"] == res["num"] and res["slack_ok"] == res["num"]
+    assert res["distinct"] and res["sorted"] and res["ranks_ok"]
+    assert res["order_stat_ok"]
+    assert res["pinned_found"] == res["pinned"]
+    return res
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_report_timing_parity(name, library):
+    c = case(name, library)
+    nl, st, g, K = c["nl"], c["st"], c["g"], c["K"]
+    for KK in (1, 37, K):
+        print(f"[report_timing] {name} K={KK}", flush=True)
+        g.report_timing(KK)
+        gp = g.paths()
+        rp = ref.report_timing(nl, library, st, KK)
+        res = _check_global(gp, rp, st, nl)
+        assert res["pinned"] > 0
+    # fewer distinct endpoints than report_timing_endpoint(n_fail, 1) covers
+    # whenever the worst endpoints hold several of the K worst paths
+    g.report_timing(K)
+    n_ep = len(set(g.paths()["path_ep"].tolist()))
+    assert n_ep <= K
+    # a slack limit keeps only the violating part
+    g.report_timing(K, slack_limit=0.0)
+    gp = g.paths()
+    rp = ref.report_timing(nl, library, st, K, slack_limit=0.0)
+    _check_global(gp, rp, st, nl)
+    assert np.all(gp["path_slack"] < 0)
+
+
+@pytest.mark.parametrize("max_k", [1, 2])
+def test_report_timing_short_lists_and_refinement(library, max_k):
+    """max_k = 1 keeps no deviation lists (every expansion walks the chain)
+    and gives a loose first bound, so the node store overflows and the bound
+    is refined; max_k = 2 cuts the lists short almost everywhere."""
+    tdp = _tdp()
+    nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), library)
+    st = ref.sta(nl, library)
+    E = len(ref.endpoint_pins(nl))
+    g = tdp.TimingGraph(nl, library, max_paths=E, max_k=max_k)
+    g.sta_update(*_xy(nl))
+    for KK in (E // 2, E):
+        print(f"[report_timing] max_k={max_k} K={KK}", flush=True)
+        g.report_timing(KK)
+        gp = g.paths()
+        rp = ref.report_timing(nl, library, st, KK)
+        _check_global(gp, rp, st, nl)
+
+
+def test_report_timing_small_random_dags(library):
+    tdp = _tdp()
+    for seed in range(6):
+        cfg = netgen.NetlistConfig("tiny", 60, ff_frac=0.25, depth=6, fanin_lo=1, fanin_hi=4, fanout_cap=8,
+                                   die=300.0, seed=100 + seed)
+        nl = with_clock(netgen.make_netlist(cfg), library, 0.3)
+        st = ref.sta(nl, library)
+        E = len(ref.endpoint_pins(nl))
+        g = tdp.TimingGraph(nl, library, max_paths=E * 8, max_k=4)
+        g.sta_update(*_xy(nl))
+        for KK in (5, E * 8):
+            g.report_timing(KK)
+            gp = g.paths()
+            rp = ref.report_timing(nl, library, st, KK)
+            _check_global(gp, rp, st, nl)
+        g.close()
+
+
+def test_report_timing_f64_and_determinism(library):
+    tdp = _tdp()
+    nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), library)
+    st = ref.sta(nl, library)
+    g = tdp.TimingGraph(nl, library, precision="f64", max_paths=200, max_k=10)
+    g.sta_update(*_xy(nl))
+    g.report_timing(100)
+    gp = g.paths()
+    rp = ref.report_timing(nl, library, st, 100)
+    _check_global(gp, rp, st, nl, fp32=False)
+    assert np.allclose(gp["path_slack"], rp["path_slack"], rtol=0, atol=1e-9)
+    g.close()
+    outs = []
+    for _ in range(2):
+        g = tdp.TimingGraph(nl, library, max_paths=200, max_k=10)
+        g.sta_update(*_xy(nl))
+        g.report_timing(200)
+        p = g.paths()
+        outs.append((p["path_pins"], p["path_slack"], p["path_rank"]))
+        g.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_report_timing_batch_matches_single_instances(library):
+    tdp = _tdp()
+    nls = []
+    for i, n in enumerate((3000, 800, 5000)):
+        cfg = netgen.NetlistConfig(f"b{i}", n, depth=10 + 5 * i, fanout_cap=16, die=600.0, seed=40 + i)
+        nls.append(with_clock(netgen.make_netlist(cfg), library))
+    gb = tdp.TimingGraph(nls, library, max_paths=2000, max_k=4)
+    pb, cb = gb.batch_offsets()
+    xb = torch.tensor(np.concatenate([nl["x"] for nl in nls]), device=_dev())
+    yb = torch.tensor(np.concatenate([nl["y"] for nl in nls]), device=_dev())
+    gb.sta_update(xb, yb)
+    gb.report_timing(300)
+    P = gb.paths()
+    for i, nl in enumerate(nls):
+        g = tdp.TimingGraph(nl, library, max_paths=2000, max_k=4)
+        g.sta_update(*_xy(nl))
+        g.report_timing(300)
+        p = g.paths()
+        sel = (P["path_ep"] >= pb[i]) & (P["path_ep"] < pb[i + 1])
+        idx = np.nonzero(sel)[0]
+        assert len(idx) == p["num_paths"] == 300
+        assert np.array_equal(P["path_slack"][idx], p["path_slack"])
+        assert np.array_equal(P["path_rank"][idx], p["path_rank"])
+        mine = np.concatenate([P["path_pins"][P["path_ptr"][j]:P["path_ptr"][j + 1]] for j in idx]) - pb[i]
+        assert np.array_equal(mine, p["path_pins"])
+        g.close()
+
+
+def test_pairs_from_report_timing(library):
+    """Eq. 9 weights over the paths of report_timing(K) match the oracle's
+    rule applied to the same paths."""
+    c = case("C1", library)
+    nl, st, g, K = c["nl"], c["st"], c["g"], c["K"]
+    g.pairs_reset()
+    g.report_timing(K)
+    gp = g.paths()
+    g.pairs_update(rule=0, w0=10.0, w1=0.2)
+    w_gpu, in_gpu = g.pairs_export()
+    ps = ref.PairState(nl["num_pins"])
+    ref.pairs_update(ps, gp, st["wns"], rule=0)
+    assert np.array_equal(in_gpu.astype(bool), ps.in_p.astype(bool))
+    sel = np.nonzero(ps.in_p)[0]
+    assert sel.shape[0] > 0
+    assert np.allclose(w_gpu[sel], ps.w[sel], rtol=1e-4)
+    g.pairs_reset()
 
 
 # ------------------------------------------------------------- pairs, loss
