@@ -388,6 +388,14 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
       H.lv.fw_lvl[l] = (int32_t)(lane / CHUNK);
     }
     T.n_fw_chunks = (int32_t)(lane / CHUNK);
+    // the widest cell of each chunk, in bits 24-30 of every lane's record:
+    // a wave-uniform bound for the segmented reductions
+    for (int64_t k0 = 0; k0 < lane; k0 += CHUNK) {
+      int w = 1;
+      for (int64_t k = k0; k < k0 + CHUNK; ++k)
+        if (H.fw_rec[k].x >= 0) w = std::max(w, ((H.fw_rec[k].w >> 8) & 63) - (H.fw_rec[k].w & 63) + 1);
+      for (int64_t k = k0; k < k0 + CHUNK; ++k) H.fw_rec[k].w |= w << 24;
+    }
   }
   // nets: driver lane then sinks, drivers level by level (start points first)
   {

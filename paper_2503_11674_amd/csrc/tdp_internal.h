@@ -89,7 +89,8 @@ struct Topo {
   // 64-lane chunks of combinational inputs: a cell's inputs never straddle a
   // chunk; chunks are level-pure.  One record per lane: {sink t (-1 =
   // padding), its driver, its combinational cell, head lane | tail lane << 8 |
-  // cell type << 16}, so a lane finds everything static in one load.
+  // cell type << 16 | widest cell of the chunk << 24}, so a lane finds
+  // everything static in one load.
   int32_t n_fw_chunks = 0;
   int4 *fw_rec = nullptr;
   int2 *fw_ext = nullptr;  // per lane: external ids of its sink and of that sink's driver

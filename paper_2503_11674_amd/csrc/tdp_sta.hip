@@ -253,17 +253,30 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
     const V2<T> w = as[s];
     const T a_in = w.x + dnet[t];
     T d;
-    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, rec.w >> 16, w.y, ld, d, o);
+    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, (rec.w >> 16) & 255, w.y, ld, d, o);
     at[tp.M + t] = a_in;
     darc[t] = d;
     a = a_in + d;
     fw_a[k] = a;
   }
-  const T best = seg_max(a, lane, head, tail);
-  const T so = seg_max(o, lane, head, tail);
-  // first input attaining the maximum (the head when none does, e.g. NaN)
-  const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
-  const int argl = arg0 <= tail ? arg0 : head;
+  // the cell's maximum arrival, worst transition and first input attaining
+  // the maximum (the head when none does, e.g. NaN)
+  T best, so;
+  int argl;
+  if (((rec.w >> 24) & 127) <= 4) {  // every cell of the chunk has <= 4 inputs
+    T ua[4], uo[4];
+    seg_fetch<4>(a, head, tail, ua);
+    seg_fetch<4>(o, head, tail, uo);
+    int aj, oj;
+    best = max_first<4>(ua, aj);
+    so = max_first<4>(uo, oj);
+    argl = head + aj;
+  } else {
+    best = seg_max(a, lane, head, tail);
+    so = seg_max(o, lane, head, tail);
+    const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
+    argl = arg0 <= tail ? arg0 : head;
+  }
   if (valid && lane == head) {  // (the list job records the critical input's hop)
     const int v = tp.n_start + c;
     at[v] = best;
@@ -290,12 +303,25 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
   const T a = valid ? fw_a[k] : -pos_inf<T>();
   const int2 ex = valid ? tp.fw_ext[k] : make_int2(0, 0);
   // the same maximum and critical input as the arrival job found
-  const T best = seg_max(a, lane, head, tail);
-  const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
-  const int argl = arg0 <= tail ? arg0 : head;
-  const int pred = __shfl(s, argl & 63, 64);
-  const int tc = __shfl(t, argl & 63, 64);
-  const int2 exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
+  const bool narrow = ((rec.w >> 24) & 127) <= 4;  // wave-uniform
+  T ua[4];
+  int ut[4], aj = 0;
+  T best;
+  int argl, pred, tc;
+  int2 exc;
+  if (narrow) {
+    seg_fetch<4>(a, head, tail, ua);
+    seg_fetch<4>(t, head, tail, ut);
+    best = max_first<4>(ua, aj);
+    argl = head + aj;
+  } else {
+    best = seg_max(a, lane, head, tail);
+    const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
+    argl = arg0 <= tail ? arg0 : head;
+  }
+  pred = __shfl(s, argl & 63, 64);
+  tc = __shfl(t, argl & 63, 64);
+  exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
   const bool is_head = valid && lane == head;
   if (is_head) {
     cdep[tp.n_start + c] = cdep[pred] + 1;
@@ -314,8 +340,6 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
     h[3] = up2;
   }
   if constexpr (KM > 1) {
-    const T dl = (valid && lane != argl) ? best - a : pos_inf<T>();
-    const int width = wave_max_int(valid ? tail - head + 1 : 0);
     T kc[KM];
     int32_t kp[KM];
 #pragma unroll
@@ -332,11 +356,23 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
       }
     }
     // own deviations, last arc first so that equal costs keep arc order
-    for (int r = 0; r < width; ++r) {
-      const int j = tail - r;
-      const T dj = __shfl(dl, j & 63, 64);
-      const int tj = __shfl(t, j & 63, 64);
-      if (is_head && j >= head && dj < pos_inf<T>()) insert_front<T, KM>(kc, kp, dj, tj);
+    if (narrow) {
+      if (is_head) {
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+          const T dj = best - ua[j];
+          if (j <= tail - head && j != aj && dj < pos_inf<T>()) insert_front<T, KM>(kc, kp, dj, ut[j]);
+        }
+      }
+    } else {
+      const T dl = (valid && lane != argl) ? best - a : pos_inf<T>();
+      const int width = wave_max_int(valid ? tail - head + 1 : 0);
+      for (int r = 0; r < width; ++r) {
+        const int j = tail - r;
+        const T dj = __shfl(dl, j & 63, 64);
+        const int tj = __shfl(t, j & 63, 64);
+        if (is_head && j >= head && dj < pos_inf<T>()) insert_front<T, KM>(kc, kp, dj, tj);
+      }
     }
     if (is_head) {
       const size_t cb = (size_t)c * KM;
@@ -528,7 +564,7 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
   stage_lut(L, s_lut);
   if (chunk >= tp.n_fw_chunks) return;
   {
-    const int t = rec.x, s = rec.y, c = rec.z, ty = rec.w >> 16;
+    const int t = rec.x, s = rec.y, c = rec.z, ty = (rec.w >> 16) & 255;
     const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
     const bool valid = t >= 0;
     float a = -__builtin_huge_valf(), o = 0.f;

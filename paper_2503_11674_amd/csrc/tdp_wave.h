@@ -39,6 +39,29 @@ __device__ __forceinline__ T seg_min(T v, int lane, int head, int tail) {
   return __shfl(v, tail, 64);
 }
 
+// For segments of at most WM lanes: every lane fetches the values of lanes
+// head .. head + WM - 1 of its own segment (clamped to the tail, so a short
+// segment repeats its last value) with independent shuffles, which the
+// hardware overlaps: one cross-lane latency instead of a dependent chain of
+// log2(64) steps.  Every lane of the wave must call it.
+template <int WM, typename T>
+__device__ __forceinline__ void seg_fetch(T v, int head, int tail, T (&u)[WM]) {
+#pragma unroll
+  for (int j = 0; j < WM; ++j) u[j] = __shfl(v, min(head + j, tail), 64);
+}
+
+// maximum of u[] and the first index that attains it (0 when none does)
+template <int WM, typename T>
+__device__ __forceinline__ T max_first(const T (&u)[WM], int &arg) {
+  T m = u[0];
+#pragma unroll
+  for (int j = 1; j < WM; ++j) m = u[j] > m ? u[j] : m;
+  arg = 0;
+#pragma unroll
+  for (int j = WM - 1; j >= 0; --j) arg = u[j] == m ? j : arg;
+  return m;
+}
+
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {

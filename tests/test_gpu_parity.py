@@ -569,6 +569,44 @@ def test_level_and_dataflow_sweeps_agree_bitwise(library):
     assert s0 == s1
 
 
+def test_wide_cells_match_oracle_and_dataflow(library):
+    """Fan-in up to 8: chunks whose cells all have <= 4 inputs take the
+    gathered reductions, wider ones the shuffle scan; both against the
+    oracle and bitwise against the dataflow sweep (scan only)."""
+    tdp = _tdp()
+    cfg = netgen.NetlistConfig("wide", 20000, ff_frac=0.1, depth=30, fanin_lo=1, fanin_hi=8, fanout_cap=16,
+                               die=2000.0, seed=7)
+    nl = with_clock(netgen.make_netlist(cfg), library)
+    st = ref.sta(nl, library)
+    widths = np.diff(nl["cell_in_ptr"])[np.asarray(nl["cell_is_ff"]) == 0]
+    assert widths.max() > 4 and (widths <= 4).mean() > 0.3
+    k, K = 4, 2000
+    outs = []
+    for mode in (0, 1):
+        g = tdp.TimingGraph(nl, library, max_paths=K, max_k=k)
+        g.set_tuning(sweep_mode=mode)
+        g.sta_update(*_xy(nl))
+        o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+        g.extract_paths(n=-1, k=k, K=K)
+        outs.append((o, g.paths()))
+        g.close()
+    (o0, p0), (o1, p1) = outs
+    for key in o0:
+        assert np.array_equal(o0[key], o1[key]), key
+    for key in ("path_ptr", "path_pins", "path_slack"):
+        assert np.array_equal(p0[key], p1[key]), key
+    for key in ("at", "rat"):
+        inf_ok, bad, worst = timing_close(o0[key], st[key],
+                                          scale=np.maximum(np.abs(np.nan_to_num(st["at"], posinf=0, neginf=0)),
+                                                           abs(float(nl["clock_period"]))))
+        assert inf_ok and bad == 0, (key, bad, worst)
+    rp = ref.extract(nl, library, st, n=-1, k=k, K=K)
+    res = compare_paths(p0, rp, st, Graph(nl), k)
+    assert p0["num_paths"] == rp["num_paths"]
+    assert res["missing"] == 0 and res["extra"] == 0
+    assert res["pinned_ok"] == res["pinned"] and res["unpinned_ok"] == res["unpinned"]
+
+
 def test_dataflow_wait_gives_up_cleanly(library):
     """Self-test of the bounded waits: with the start points withheld every
     wait runs out of polls, the kernels still finish and the summary reports
