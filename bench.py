@@ -139,12 +139,12 @@ def build_step(g, x, y, k, K, gx, gy, wl, pp, beta, overlap=True):
             g.p2p_loss_fwd(x, y, out=pp)
             g.p2p_loss_bwd(x, y, beta, gx, gy)
             return
+        # submission order matters as much as the streams: the host enqueues
+        # the main stream's extraction before the 101 launches of the
+        # required-time pass, so the main stream never waits for the host
         g.sta_update_arrivals(x, y)
         ev_arr.record(main)
-        side_req.wait_event(ev_arr)
         side_wa.wait_event(ev_arr)
-        g.sta_update_required(stream=side_req)
-        ev_req.record(side_req)
         with torch.cuda.stream(side_wa):
             gx.zero_()
             gy.zero_()
@@ -153,6 +153,9 @@ def build_step(g, x, y, k, K, gx, gy, wl, pp, beta, overlap=True):
         g.extract_paths(n=-1, k=k, K=K)
         g.pairs_update(rule=0, w0=10.0, w1=0.2)
         g.p2p_loss_fwd(x, y, out=pp)
+        side_req.wait_event(ev_arr)
+        g.sta_update_required(stream=side_req)
+        ev_req.record(side_req)
         main.wait_event(ev_wa)  # the p2p gradient adds to WA's
         g.p2p_loss_bwd(x, y, beta, gx, gy)
         main.wait_event(ev_req)

@@ -141,16 +141,22 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   bool ok = true;
   // library
   const int nt = lib->num_types, ns = lib->n_slew, nl = lib->n_load;
-  float *sa = nullptr, *la = nullptr, *dl = nullptr, *sl = nullptr;
-  ok = ok && dalloc(g, sa, (size_t)nt * ns) && dalloc(g, la, (size_t)nt * nl) &&
-       dalloc(g, dl, (size_t)nt * ns * nl) && dalloc(g, sl, (size_t)nt * ns * nl);
+  // one buffer [slew axes | load axes | delay tables | slew tables], padded
+  // to whole float4s (the layout kernels stage in LDS)
+  const size_t n_sa = (size_t)nt * ns, n_la = (size_t)nt * nl, n_tab = (size_t)nt * ns * nl;
+  const size_t n_all = n_sa + n_la + 2 * n_tab, n4 = (n_all + 3) / 4;
+  float4 *flat = nullptr;
+  ok = ok && dalloc(g, flat, n4);
+  float *sa = (float *)flat, *la = sa + n_sa, *dl = la + n_la, *sl = dl + n_tab;
   if (ok) {
-    ok = hipMemcpy(sa, lib->slew_axis, sizeof(float) * nt * ns, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(la, lib->load_axis, sizeof(float) * nt * nl, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(dl, lib->delay_lut, sizeof(float) * nt * ns * nl, hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(sl, lib->slew_lut, sizeof(float) * nt * ns * nl, hipMemcpyHostToDevice) == hipSuccess;
+    std::vector<float> img(4 * n4, 0.f);
+    std::copy(lib->slew_axis, lib->slew_axis + n_sa, img.begin());
+    std::copy(lib->load_axis, lib->load_axis + n_la, img.begin() + n_sa);
+    std::copy(lib->delay_lut, lib->delay_lut + n_tab, img.begin() + n_sa + n_la);
+    std::copy(lib->slew_lut, lib->slew_lut + n_tab, img.begin() + n_sa + n_la + n_tab);
+    ok = hipMemcpy(flat, img.data(), sizeof(float) * img.size(), hipMemcpyHostToDevice) == hipSuccess;
   }
-  g->lut = LutView{nt, ns, nl, sa, la, dl, sl};
+  g->lut = LutView{nt, ns, nl, sa, la, dl, sl, flat, (int)n4};
   // topology
   ok = ok && upload(g, T.drv_cell, H.drv_cell) && upload(g, T.drv_ox, H.drv_ox) && upload(g, T.drv_oy, H.drv_oy) &&
        upload(g, T.drv_ext, H.drv_ext) && upload(g, T.net_ptr, H.net_ptr) && upload(g, T.net_sink, H.net_sink) &&

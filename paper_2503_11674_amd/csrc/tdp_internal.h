@@ -29,6 +29,10 @@ struct LutView {
   const float *load_axis;   // [nt][nl]
   const float *delay;       // [nt][ns][nl]
   const float *slew;        // [nt][ns][nl]
+  // the four arrays above are consecutive in one buffer, padded to whole
+  // float4s: the image a kernel stages in LDS
+  const float4 *flat4;
+  int n4;
 };
 
 // Bilinear lookup with clamping: the breakpoint interval is the last one whose

@@ -10,8 +10,39 @@
 namespace tdp {
 
 constexpr int SCAN_BLOCK = 256;
-constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_ITEMS = 16;  // four int4 per thread
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
+
+// a thread's SCAN_ITEMS consecutive values starting at base (16-byte
+// aligned): vector loads for a full run, element loads in the ragged tail
+__device__ __forceinline__ void load_items(const int32_t *in, int base, int n, int (&v)[SCAN_ITEMS]) {
+  if (base + SCAN_ITEMS <= n) {
+    const int4 *p = (const int4 *)(in + base);
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS / 4; ++q) {
+      const int4 x = p[q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) v[i] = base + i < n ? in[base + i] : 0;
+  }
+}
+
+__device__ __forceinline__ void store_items(int32_t *out, int base, int n, const int (&v)[SCAN_ITEMS]) {
+  if (base + SCAN_ITEMS <= n) {
+    int4 *p = (int4 *)(out + base);
+#pragma unroll
+    for (int q = 0; q < SCAN_ITEMS / 4; ++q) p[q] = make_int4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+      if (base + i < n) out[base + i] = v[i];
+  }
+}
 
 __device__ __forceinline__ int live_count(int cap, const int32_t *d_n) {
   if (!d_n) return cap;
@@ -40,10 +71,11 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_reduce(const int32_t *__res
   __shared__ int sh[4];
   const int n = live_count(cap, d_n);
   const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  load_items(in, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i)
-    if (base + i < n) s += in[base + i];
+  for (int i = 0; i < SCAN_ITEMS; ++i) s += v[i];
   int incl = block_inclusive_scan(s, sh);
   if (threadIdx.x == SCAN_BLOCK - 1) part[blockIdx.x] = incl;
 }
@@ -67,34 +99,35 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_partials(int32_t *__restric
   if (threadIdx.x == 0 && d_total) *d_total = carry;
 }
 
-__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down(const int32_t *__restrict__ in, int cap,
-                                                           const int32_t *d_n, const int32_t *__restrict__ part,
-                                                           int32_t *__restrict__ out) {
+// (in and out may be the same array: a thread reads its items before it
+// writes them and no other thread touches them)
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down(const int32_t *in, int cap, const int32_t *d_n,
+                                                           const int32_t *__restrict__ part, int32_t *out) {
   __shared__ int sh[4];
   const int n = live_count(cap, d_n);
   const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
+  load_items(in, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0;
-    s += v[i];
-  }
+  for (int i = 0; i < SCAN_ITEMS; ++i) s += v[i];
   int incl = block_inclusive_scan(s, sh);
   int run = part[blockIdx.x] + incl - s;
 #pragma unroll
   for (int i = 0; i < SCAN_ITEMS; ++i) {
-    if (base + i < n) out[base + i] = run;
-    run += v[i];
+    const int x = v[i];
+    v[i] = run;
+    run += x;
   }
+  store_items(out, base, n, v);
 }
 
 // Second pass without a separate scan of the tile sums: every tile adds up
 // the sums of the tiles before it itself (a few thousand integers from L2),
 // which saves a launch; the last live tile writes the total.
-__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down_sum(const int32_t *__restrict__ in, int cap,
-                                                               const int32_t *d_n, const int32_t *__restrict__ part,
-                                                               int32_t *__restrict__ out, int32_t *d_total) {
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down_sum(const int32_t *in, int cap, const int32_t *d_n,
+                                                               const int32_t *__restrict__ part, int32_t *out,
+                                                               int32_t *d_total) {
   __shared__ int sh[4];
   __shared__ int offset;
   const int n = live_count(cap, d_n);
@@ -107,19 +140,19 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_down_sum(const int32_t *__r
   __syncthreads();
   const int base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
+  load_items(in, base, n, v);
   int s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_ITEMS; ++i) {
-    v[i] = base + i < n ? in[base + i] : 0;
-    s += v[i];
-  }
+  for (int i = 0; i < SCAN_ITEMS; ++i) s += v[i];
   const int incl = block_inclusive_scan(s, sh);
   int run = offset + incl - s;
 #pragma unroll
   for (int i = 0; i < SCAN_ITEMS; ++i) {
-    if (base + i < n) out[base + i] = run;
-    run += v[i];
+    const int x = v[i];
+    v[i] = run;
+    run += x;
   }
+  store_items(out, base, n, v);
   if (d_total && (int)blockIdx.x == tiles - 1 && threadIdx.x == SCAN_BLOCK - 1) *d_total = offset + incl;
 }
 

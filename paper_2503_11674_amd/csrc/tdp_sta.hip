@@ -46,12 +46,16 @@ template <> __device__ __forceinline__ float pos_inf<float>() { return __builtin
 template <> __device__ __forceinline__ double pos_inf<double>() { return __builtin_huge_val(); }
 
 __device__ __forceinline__ void stage_lut(const LutView &L, float *s_lut) {
-  const int nsl = L.nt * L.ns, nld = L.nt * L.nl, ntab = L.nt * L.ns * L.nl;
-  for (int i = threadIdx.x; i < nsl; i += blockDim.x) s_lut[i] = L.slew_axis[i];
-  for (int i = threadIdx.x; i < nld; i += blockDim.x) s_lut[nsl + i] = L.load_axis[i];
-  for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
-    s_lut[nsl + nld + i] = L.delay[i];
-    s_lut[nsl + nld + ntab + i] = L.slew[i];
+  // two float4 loads in flight per thread before their LDS writes (one
+  // memory latency for the usual table sizes)
+  float4 *dst = (float4 *)s_lut;
+  const int n4 = L.n4, bd = blockDim.x;
+  for (int i = threadIdx.x; i < n4; i += 2 * bd) {
+    const int i1 = i + bd;
+    const float4 v0 = L.flat4[i];
+    const float4 v1 = i1 < n4 ? L.flat4[i1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    dst[i] = v0;
+    if (i1 < n4) dst[i1] = v1;
   }
   __syncthreads();
 }
@@ -240,8 +244,9 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
   const int lane = wave_lane();
   const int k = chunk * CHUNK + lane;
   // the record load is issued before the tables are staged, so the two
-  // latencies overlap
-  const int4 rec = chunk < ch1 ? tp.fw_rec[k] : make_int4(-1, 0, 0, 0);
+  // latencies overlap (unconditionally: a wave past the level's last chunk
+  // reads that chunk again and then leaves)
+  const int4 rec = tp.fw_rec[(chunk < ch1 ? chunk : ch1 - 1) * CHUNK + lane];
   stage_lut(L, s_lut);
   if (chunk >= ch1) return;
   const int t = rec.x, s = rec.y, c = rec.z;
@@ -395,7 +400,8 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
                                                   int32_t *__restrict__ cdep,
                                                   T *__restrict__ side_cost, int32_t *__restrict__ side_pin,
                                                   T *__restrict__ fw_a, int4 *__restrict__ hop4) {
-  extern __shared__ float s_lut[];
+  extern __shared__ float4 s_lut4[];
+  float *s_lut = (float *)s_lut4;
   const int wave = threadIdx.x >> 6;
   if ((int)blockIdx.x < n_arr)
     fw_arrivals<T>(tp, L, s_lut, ch0 + blockIdx.x * 4 + wave, ch1, load, dnet, at, slew, as, darc, crit, fw_a);
@@ -556,7 +562,8 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
                                                        uint32_t *__restrict__ fcd, uint64_t *__restrict__ fse,
                                                        int32_t *__restrict__ err,
                                                        int limit) {
-  extern __shared__ float s_lut[];
+  extern __shared__ float4 s_lut4[];
+  float *s_lut = (float *)s_lut4;
   const int lane = wave_lane();
   const int chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int k = chunk * CHUNK + lane;
@@ -744,9 +751,7 @@ __global__ void k_export_crit(Topo tp, const int32_t *__restrict__ crit, int32_t
 // --------------------------------------------------------------- launchers
 static inline int nblk(long long n, int b) { return n > 0 ? (int)((n + b - 1) / b) : 1; }
 
-static inline size_t lut_bytes(const LutView &L) {
-  return sizeof(float) * (size_t)(L.nt * (L.ns + L.nl) + 2 * L.nt * L.ns * L.nl);
-}
+static inline size_t lut_bytes(const LutView &L) { return sizeof(float4) * (size_t)L.n4; }
 
 template <typename T, int KM>
 static void launch_forward(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipStream_t s) {
