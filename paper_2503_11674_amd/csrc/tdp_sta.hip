@@ -328,30 +328,19 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
   tc = __shfl(t, argl & 63, 64);
   exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
   const bool is_head = valid && lane == head;
-  if (is_head) {
-    cdep[tp.n_start + c] = cdep[pred] + 1;
-    const int4 none = make_int4(-1, -1, 0, 0);
-    int4 up0 = none, up1 = none, up2 = none;
-    if (pred >= tp.n_start) {
-      const int4 *ph = hop4 + (size_t)(pred - tp.n_start) * 4;
-      up0 = ph[0];
-      up1 = ph[1];
-      up2 = ph[2];
-    }
-    int4 *h = hop4 + (size_t)c * 4;
-    h[0] = make_int4(tc, pred, exc.x, exc.y);
-    h[1] = up0;
-    h[2] = up1;
-    h[3] = up2;
+  // Every load from the critical input's driver (its deviation list, hop
+  // records and chain depth) comes before the first store in program order,
+  // so the three share one memory latency (loads are not moved above the
+  // stores).
+  constexpr int KL = KM > 1 ? KM : 1;
+  T kc[KL];
+  int32_t kp[KL];
+#pragma unroll
+  for (int j = 0; j < KL; ++j) {
+    kc[j] = pos_inf<T>();
+    kp[j] = -1;
   }
   if constexpr (KM > 1) {
-    T kc[KM];
-    int32_t kp[KM];
-#pragma unroll
-    for (int j = 0; j < KM; ++j) {
-      kc[j] = pos_inf<T>();
-      kp[j] = -1;
-    }
     if (is_head && pred >= tp.n_start) {
       const size_t pb = (size_t)(pred - tp.n_start) * KM;
 #pragma unroll
@@ -360,6 +349,25 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
         kp[j] = side_pin[pb + j];
       }
     }
+  }
+  if (is_head) {
+    const int4 none = make_int4(-1, -1, 0, 0);
+    int4 up0 = none, up1 = none, up2 = none;
+    if (pred >= tp.n_start) {
+      const int4 *ph = hop4 + (size_t)(pred - tp.n_start) * 4;
+      up0 = ph[0];
+      up1 = ph[1];
+      up2 = ph[2];
+    }
+    const int32_t cd = cdep[pred];
+    cdep[tp.n_start + c] = cd + 1;
+    int4 *h = hop4 + (size_t)c * 4;
+    h[0] = make_int4(tc, pred, exc.x, exc.y);
+    h[1] = up0;
+    h[2] = up1;
+    h[3] = up2;
+  }
+  if constexpr (KM > 1) {
     // own deviations, last arc first so that equal costs keep arc order
     if (narrow) {
       if (is_head) {
