@@ -176,7 +176,7 @@ void scan_exclusive(const int32_t *in, int32_t *out, int cap, const int32_t *d_n
 
 // ------------------------------------------------------------------ sort
 constexpr int RS_BLOCK = 256;
-constexpr int RS_ITEMS = 16;
+constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_BLOCK * RS_ITEMS;
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) { return (uint32_t)(k >> shift) & 0xFFu; }
@@ -197,10 +197,16 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_hist(const uint64_t *__restrict
   cnt[threadIdx.x] = 0;
   __syncthreads();
   const int base = blockIdx.x * RS_TILE;
+  // every key of the thread is requested before the first count
+  uint32_t dg[RS_ITEMS];
+#pragma unroll
   for (int j = 0; j < RS_ITEMS; ++j) {
-    int i = base + j * RS_BLOCK + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[digit_of(keys[i], shift)], 1);
+    const int i = base + j * RS_BLOCK + threadIdx.x;
+    dg[j] = i < n ? digit_of(keys[i], shift) : 256u;
   }
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j)
+    if (dg[j] < 256u) atomicAdd(&cnt[dg[j]], 1);
   __syncthreads();
   hist[threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
 }
@@ -221,11 +227,21 @@ __global__ void __launch_bounds__(RS_BLOCK) k_rs_scatter(const uint64_t *__restr
   __syncthreads();
   const int base = blockIdx.x * RS_TILE;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // every key and value of the thread is requested before the ranking
+  uint64_t kk[RS_ITEMS];
+  uint32_t vv[RS_ITEMS];
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; ++j) {
+    const int i = base + j * RS_BLOCK + tid;
+    kk[j] = i < n ? kin[i] : 0ull;
+    vv[j] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
   for (int j = 0; j < RS_ITEMS; ++j) {
     const int i = base + j * RS_BLOCK + tid;
     const bool valid = i < n;
-    uint64_t k = valid ? kin[i] : 0ull;
-    uint32_t v = valid ? vin[i] : 0u;
+    const uint64_t k = kk[j];
+    const uint32_t v = vv[j];
     uint32_t d = digit_of(k, shift);
     uint64_t m = __ballot(valid);
 #pragma unroll
