@@ -262,8 +262,8 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
     at[tp.M + t] = a_in;
     darc[t] = d;
     a = a_in + d;
-    fw_a[k] = a;
   }
+  fw_a[k] = a;  // -inf in padding slots
   // the cell's maximum arrival, worst transition and first input attaining
   // the maximum (the head when none does, e.g. NaN)
   T best, so;
@@ -302,11 +302,11 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
   const int lane = wave_lane();
   const int k = chunk * CHUNK + lane;
   const int4 rec = tp.fw_rec[k];
+  const T a = fw_a[k];
+  const int2 ex = tp.fw_ext[k];
   const int t = rec.x, s = rec.y, c = rec.z;
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   const bool valid = t >= 0;
-  const T a = valid ? fw_a[k] : -pos_inf<T>();
-  const int2 ex = valid ? tp.fw_ext[k] : make_int2(0, 0);
   // the same maximum and critical input as the arrival job found
   const bool narrow = ((rec.w >> 24) & 127) <= 4;  // wave-uniform
   T ua[4];
