@@ -651,6 +651,60 @@ def test_error_paths(library):
     assert float(g.p2p_loss_fwd(x, y)) == 0.0
 
 
+def test_empty_requests_and_a_design_without_logic(library):
+    """K = 0, n = 0 and a slack limit below WNS give no paths from either
+    extraction; a design of flip-flops and ports only (no combinational
+    cell, depth 0) times, extracts and scores exactly."""
+    tdp = _tdp()
+    c = case("C1", library)
+    st, g = c["st"], c["g"]
+    lim = float(st["wns"]) - 1.0
+    for call in (lambda: g.extract_paths(n=-1, k=2, K=0), lambda: g.extract_paths(n=0, k=2),
+                 lambda: g.report_timing(0), lambda: g.report_timing(50, slack_limit=lim),
+                 lambda: g.extract_paths(n=-1, k=2, slack_limit=lim)):
+        call()
+        p = g.paths()
+        assert p["num_paths"] == 0 and p["path_ptr"].tolist() == [0]
+    # ports 6, 7 and flip-flops 0, 1, 2 (D pins 0, 2, 4; Q pins 1, 3, 5); Q 3
+    # and Q 5 drive nothing.  Distances 10, 130 and 120 um give the exact
+    # arrivals 1.5625, 264.0625 and 26 + 225 = 251 under the dyadic library.
+    nl0, _ = handnets.build([(netgen.FF_TYPE, 1)] * 3, 2, [(6, [0]), (7, [2]), (1, [4]), (3, []), (5, [])],
+                            x=[10.0, 50.0, 90.0], y=[0.0, 20.0, 40.0], port_xy=[(0.0, 0.0), (100.0, 100.0)],
+                            clock_period=200.0)
+    lib = handnets.dyadic_library()
+    st0 = ref.sta(nl0, lib)
+    assert st0["at"][[0, 2, 4]].tolist() == [1.5625, 264.0625, 251.0]
+    g0 = tdp.TimingGraph(nl0, lib, max_paths=8, max_k=2)
+    x0, y0 = _xy(nl0)
+    g0.sta_update(x0, y0)
+    o = {k: v.cpu().numpy() for k, v in g0.export().items()}
+    fin = np.isfinite(st0["rat"])
+    assert np.array_equal(o["at"], st0["at"]) and np.array_equal(o["rat"][fin], st0["rat"][fin])
+    assert g0.summary() == (-64.0625, -115.0625, 2)
+    g0.extract_paths(n=-1, k=2)
+    gp = g0.paths()
+    rp = ref.extract(nl0, lib, st0, n=-1, k=2)
+    assert gp["num_paths"] == rp["num_paths"] == 2
+    assert np.array_equal(gp["path_pins"], rp["path_pins"]) and np.array_equal(gp["path_slack"], rp["path_slack"])
+    g0.report_timing(5)
+    gk = g0.paths()
+    rk = ref.report_timing(nl0, lib, st0, 5)
+    assert gk["num_paths"] == rk["num_paths"] == 3
+    assert np.array_equal(gk["path_pins"], rk["path_pins"]) and np.array_equal(gk["path_slack"], rk["path_slack"])
+    g0.pairs_reset()
+    g0.extract_paths(n=-1, k=2)
+    g0.pairs_update()
+    w, inp = g0.pairs_export()
+    assert sorted(np.nonzero(inp)[0].tolist()) == [2, 4]
+    gx = torch.zeros_like(x0)
+    gy = torch.zeros_like(y0)
+    wl = g0.wa_fwd_bwd(x0, y0, 5.0, gx, gy)
+    v_wa, wx, wy = ref.wa(nl0, 5.0)
+    assert abs(float(wl) - v_wa) <= 1e-5 * max(1.0, abs(v_wa))
+    assert np.allclose(gx.cpu().numpy(), wx, rtol=1e-4, atol=1e-6)
+    g0.close()
+
+
 # -------------------------------------------------------------- autotuner
 def test_autotune_keeps_results(library):
     """The autotuner picks a supported configuration and the results after it
