@@ -341,6 +341,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    # the three pair distances of Sec. III-C on the step's pair set, forward
+    # and backward, after the timed region (events on the current stream)
+    pair_ms = {}
+    one = torch.ones((), dtype=torch.float64, device=dev)
+    for kind, name in ((0, "quadratic"), (1, "manhattan"), (2, "euclidean")):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g.pair_loss_fwd(kind, x, y, out=pp)
+        g.pair_loss_bwd(kind, x, y, one, gx, gy)
+        e0.record()
+        for _ in range(20):
+            g.pair_loss_fwd(kind, x, y, out=pp)
+            g.pair_loss_bwd(kind, x, y, one, gx, gy)
+        e1.record()
+        e1.synchronize()
+        pair_ms[name] = round(e0.elapsed_time(e1) / 20, 4)
+
     sta_ms = sum(stages[s]["ms"] for s in ("netpass", "forward", "endpoint", "backward") if s in stages)
     ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
     loss_ms = sum(stages[s]["ms"] for s in ("p2p_fwd", "p2p_bwd") if s in stages)
@@ -376,6 +392,7 @@ def main():
         "sta_extract_pins_per_s": round(pins / ((sta_ms + ext_ms) * 1e-3), 1) if sta_ms else None,
         "p2p_fwd_bwd_GBps": round((sb["p2p_fwd"] + sb["p2p_bwd"]) / (loss_ms * 1e-3) / 1e9, 2) if loss_ms else None,
         "stages": stages,
+        "pair_losses_ms": pair_ms,
         "roofline": roof,
         "graph_replay": bool(graph is not None),
         "streams": 1 if a.serial else 3,

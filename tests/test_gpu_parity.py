@@ -772,6 +772,40 @@ def test_pair_loss_variants(library, kind):
         g.pair_loss_fwd(3, c["x"], c["y"])
 
 
+def test_quadratic_pair_loss_spaces_a_chain_on_the_gpu(library):
+    """Sec. III-C / Fig. 3 on the GPU path: gradient descent on the pair loss
+    of a chain of movable buffers between a fixed port and a fixed flip-flop.
+    The quadratic loss moves the buffers to equal spacing; the Manhattan and
+    linear Euclidean losses give every interior buffer a zero gradient, so a
+    skewed chain stays where it is."""
+    from tests.test_pair_losses import _chain
+    tdp = _tdp()
+    skew = [0.0, 0.5, 1.0, 1.5, 2.0, 9.0, 10.0]
+    nl, sinks = _chain(skew)
+    n = len(skew) - 2
+    for kind in (0, 1, 2):
+        g = tdp.TimingGraph(nl, library, max_paths=4, max_k=1)
+        x, y = _xy(nl)
+        g.sta_update(x, y)
+        w = np.zeros(nl["num_pins"], np.float32)
+        inp = np.zeros(nl["num_pins"], np.uint8)
+        w[sinks], inp[sinks] = 1.0, 1
+        g.pairs_import(w, inp)
+        x = x.clone()
+        for _ in range(400):
+            xr = x.clone().requires_grad_(True)
+            tdp.PairLoss.apply(xr, y, g, kind).backward()
+            if kind != 0:
+                # the interior buffers feel no pull at all
+                assert torch.count_nonzero(xr.grad[:n]) == 0
+                break
+            x = x - 0.1 * xr.grad
+        if kind == 0:
+            pos = [0.0] + x.cpu().numpy()[:n].tolist() + [10.0]
+            assert np.allclose(np.diff(pos), 10.0 / (n + 1), atol=1e-3), pos
+        g.close()
+
+
 def test_two_pass_update_on_two_streams(library):
     """The arrival pass and the required-time pass, the second on another
     stream ordered by events, give bitwise what the one-call update gives."""
