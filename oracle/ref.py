@@ -71,7 +71,8 @@ def _lib_args(lib) -> list:
     args = [ctypes.c_int(nt), ctypes.c_int(n_slew), ctypes.c_int(n_load)] + [_p(a) for a in keep] + [
         ctypes.c_double(float(np.float32(lib["r_per_um"]))),
         ctypes.c_double(float(np.float32(lib["c_per_um"]))),
-        ctypes.c_double(float(np.float32(lib["delay_scale"])))]
+        ctypes.c_double(float(np.float32(lib["delay_scale"]))),
+        ctypes.c_int(int(lib.get("net_model", 0)))]
     return args, keep
 
 

@@ -16,7 +16,10 @@
  *                  violated endpoints, both 0 when none violates (Eqs. 3-4).
  *                  Net delay is R*C, with R and C linear in wire length
  *                  (Sec. III-C, Eq. 7), i.e. r*c*L^2 with L the Manhattan
- *                  distance; cell arcs come from slew x load tables.
+ *                  distance, or, as a fuller model of the same wires, the
+ *                  Elmore delay of a star RC net with degraded sink
+ *                  transitions (net model section below); cell arcs come
+ *                  from slew x load tables.
  *   ora_extract  - report_timing_endpoint(n, k) (Sec. III-B, Table I): the n
  *                  most critical endpoints, and the k worst paths at each.
  *                  Reached by deviation (sidetrack) enumeration from the
@@ -66,6 +69,7 @@ typedef struct {
   int num_types, n_slew, n_load;
   const float *slew_axis, *load_axis, *delay_lut, *slew_lut, *pin_cap;
   double r, c, scale;
+  int model; /* net model: 0 lumped (Eq. 7), 1 Elmore star with slew degradation */
 } olib;
 
 /* ------------------------------------------------------------------------ */
@@ -181,6 +185,43 @@ static void pin_xy(const onl *n, const float *x, const float *y, int p, double *
   *py = by + (double)n->pin_off_y[p];
 }
 
+/* ------------------------------------------------------------------------ */
+/* net model                                                                 */
+/* ------------------------------------------------------------------------ */
+/* Each sink hangs off the driver on a wire of its own whose length L is the
+ * Manhattan driver-to-sink distance, with resistance r*L and capacitance c*L
+ * (Eq. 7: both linear in length).  The driver's load is the total capacitance
+ * of the net, sum over sinks of (pin cap + c*L), in either model.
+ *   model 0 (Eq. 7 as written): the wire's lumped R times C, scale*r*c*L^2.
+ *   model 1: the Elmore delay of that star RC net.  The first moment of the
+ *     impulse response at a sink is the sum, over the resistances between the
+ *     driver and the sink, of resistance times the capacitance downstream of
+ *     it.  The sink's branch is a uniform line, so that sum is
+ *     r*L*(c*L/2 + C_sink), the other branches having no resistance in common
+ *     with it; scale converts to the time unit.
+ * Sink transition: model 0 passes the driver's transition through unchanged;
+ * model 1 degrades it by the wire with the PERI rule (Kashyap, Alpert, Liu
+ * and Devgan, IEEE TCAD 2004): the root sum of squares of the input
+ * transition and the wire's own step-response transition, the latter taken
+ * as ln(9) times the Elmore delay (the 10-90% time of a single-pole
+ * response with that time constant). */
+static double net_delay(const olib *L, double len, double sink_cap) {
+  if (L->model == 1) return L->scale * L->r * len * (0.5 * L->c * len + sink_cap);
+  return L->scale * L->r * L->c * len * len;
+}
+
+/* d net_delay / d len */
+static double net_delay_dlen(const olib *L, double len, double sink_cap) {
+  if (L->model == 1) return L->scale * L->r * (L->c * len + sink_cap);
+  return 2.0 * L->scale * L->r * L->c * len;
+}
+
+static double sink_slew(const olib *L, double drv_slew, double dnet) {
+  if (L->model != 1) return drv_slew;
+  double w = log(9.0) * dnet;
+  return sqrt(drv_slew * drv_slew + w * w);
+}
+
 #define NETLIST_ARGS                                                                             \
   int num_cells, int num_pins, int num_nets, const int32_t *pin_cell, const float *pin_off_x,    \
       const float *pin_off_y, const int32_t *net_ptr, const int32_t *net_pins,                   \
@@ -189,7 +230,7 @@ static void pin_xy(const onl *n, const float *x, const float *y, int p, double *
 #define LIB_ARGS                                                                                 \
   int num_types, int n_slew, int n_load, const float *slew_axis, const float *load_axis,         \
       const float *delay_lut, const float *slew_lut, const float *pin_cap, double r_per_um,      \
-      double c_per_um, double delay_scale
+      double c_per_um, double delay_scale, int net_model
 
 #define FILL_NETLIST(nn)                                                                         \
   onl nn;                                                                                        \
@@ -202,7 +243,8 @@ static void pin_xy(const onl *n, const float *x, const float *y, int p, double *
   olib ll;                                                                                       \
   ll.num_types = num_types; ll.n_slew = n_slew; ll.n_load = n_load; ll.slew_axis = slew_axis;    \
   ll.load_axis = load_axis; ll.delay_lut = delay_lut; ll.slew_lut = slew_lut;                    \
-  ll.pin_cap = pin_cap; ll.r = r_per_um; ll.c = c_per_um; ll.scale = delay_scale
+  ll.pin_cap = pin_cap; ll.r = r_per_um; ll.c = c_per_um; ll.scale = delay_scale;            \
+  ll.model = net_model
 
 /* ------------------------------------------------------------------------ */
 /* STA                                                                       */
@@ -225,14 +267,13 @@ int ora_sta(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double clock
   oconn c;
   if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
   int P = num_pins, N = num_cells, M = num_nets;
-  const double kappa = L.scale * L.r * L.c;
   for (int p = 0; p < P; ++p) {
     at[p] = -INFINITY; slew[p] = 0; rat[p] = INFINITY; slack[p] = INFINITY;
     dnet[p] = 0; load[p] = 0; darc[p] = 0;
   }
   for (int cell = 0; cell < N; ++cell) crit[cell] = -1;
 
-  /* net pass: Manhattan length, RC net delay, star-model driver load */
+  /* net pass: Manhattan length, net delay, star-model driver load */
   for (int net = 0; net < M; ++net) {
     int s = net_pins[net_ptr[net]];
     double xs, ys;
@@ -243,8 +284,9 @@ int ora_sta(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double clock
       double xt, yt;
       pin_xy(&n, x, y, t, &xt, &yt);
       double len = fabs(xs - xt) + fabs(ys - yt);
-      dnet[t] = kappa * len * len;
-      ld += (double)pin_cap[cell_type[pin_cell[t]]] + L.c * len;
+      double cap = (double)pin_cap[cell_type[pin_cell[t]]];
+      dnet[t] = net_delay(&L, len, cap);
+      ld += cap + L.c * len;
     }
     load[s] = ld;
   }
@@ -267,7 +309,7 @@ int ora_sta(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double clock
       case ROLE_FFD:
         if (c.driver[p] >= 0) {
           at[p] = at[c.driver[p]] + dnet[p];
-          slew[p] = slew[c.driver[p]];
+          slew[p] = sink_slew(&L, slew[c.driver[p]], dnet[p]);
         }
         break;
       case ROLE_COUT: {
@@ -801,8 +843,9 @@ int ora_pair_loss(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const
  *   comb output o:  A(o) = m + g*ln sum_j exp((a_j - m)/g), a_j = A(i_j) + darc(i_j)
  *   endpoint e:     s(e) = (T - setup) - A(e)
  *   value:          -g * sum_e softplus(-s(e)/g)
- * The gradient on cell positions goes through dnet = kappa * L^2,
- * L = |dx| + |dy| (sign(0) = 0).  grad_x/grad_y [N] are overwritten. */
+ * The gradient on cell positions goes through the net delay of the library's
+ * net model as a function of L = |dx| + |dy| (sign(0) = 0).  grad_x/grad_y
+ * [N] are overwritten. */
 int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, const float *y,
              const double *at0, const double *darc, double clock_period, double setup,
              double gamma, double *value, double *grad_x, double *grad_y) {
@@ -811,7 +854,6 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
   oconn c;
   if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
   int P = num_pins;
-  const double kappa = L.scale * L.r * L.c;
   double *A = (double *)malloc(sizeof(double) * P);
   double *Ab = (double *)calloc(P, sizeof(double));
   double *dn = (double *)calloc(P, sizeof(double));
@@ -825,7 +867,7 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
       double xt, yt;
       pin_xy(&n, x, y, t, &xt, &yt);
       double len = fabs(xs - xt) + fabs(ys - yt);
-      dn[t] = kappa * len * len;
+      dn[t] = net_delay(&L, len, (double)pin_cap[cell_type[pin_cell[t]]]);
     }
   }
   for (int q = 0; q < P; ++q) {
@@ -885,8 +927,9 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
       double len = fabs(xs - xt) + fabs(ys - yt);
       double dx = xs - xt, dy = ys - yt;
       double sx = (dx > 0) - (dx < 0), sy = (dy > 0) - (dy < 0);
-      double gx = Ab[t] * 2.0 * kappa * len * sx;   /* d value / d X_s */
-      double gy = Ab[t] * 2.0 * kappa * len * sy;
+      double dd = net_delay_dlen(&L, len, (double)pin_cap[cell_type[pin_cell[t]]]);
+      double gx = Ab[t] * dd * sx;   /* d value / d X_s */
+      double gy = Ab[t] * dd * sy;
       int ct = pin_cell[t];
       if (cs >= 0 && !cell_fixed[cs]) { grad_x[cs] += gx; grad_y[cs] += gy; }
       if (ct >= 0 && !cell_fixed[ct]) { grad_x[ct] -= gx; grad_y[ct] -= gy; }
