@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--table1", action="store_true",
                     help="extraction statistics of report_timing(K) against report_timing_endpoint(n, k) "
                          "(paths, endpoints, pin pairs, time) instead of the step benchmark")
+    ap.add_argument("--net-model", type=int, default=0, choices=(0, 1),
+                    help="0: lumped RC wires (Eq. 7); 1: Elmore star nets with degraded sink transitions")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy of MB MiB (counter calibration)")
     return ap.parse_args()
@@ -239,7 +241,7 @@ def main():
     cfg = netgen.CONFIGS[a.workload]
     t0 = time.time()
     nl = netgen.make_netlist(cfg)
-    lib = netgen.make_library()
+    lib = dict(netgen.make_library(), net_model=a.net_model)
     print(f"[bench] generated {a.workload}: {nl['num_cells']} cells {nl['num_pins']} pins "
           f"({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     dev = torch.device("cuda", 0)
@@ -388,7 +390,8 @@ def main():
         "config": {"workload": f"{a.workload}: {nl['num_cells']} cells, {pins} pins, depth {g.depth}, "
                                f"{E} endpoints, (n_fail, k, K) = ({nfail}, {k}, {K}), clustered placement "
                                f"in {cfg.die:.0f} um die; step = STA + extraction + Eq. 9 pairs + WA + p2p "
-                               f"fwd/bwd", "parallelism": "none"},
+                               f"fwd/bwd" + ("; Elmore net model" if a.net_model else ""),
+                   "parallelism": "none"},
         "sta_extract_pins_per_s": round(pins / ((sta_ms + ext_ms) * 1e-3), 1) if sta_ms else None,
         "p2p_fwd_bwd_GBps": round((sb["p2p_fwd"] + sb["p2p_bwd"]) / (loss_ms * 1e-3) / 1e9, 2) if loss_ms else None,
         "stages": stages,

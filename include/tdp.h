@@ -85,22 +85,32 @@ typedef struct {
   float clock_period_ps, setup_ps, input_slew_ps, clock_slew_ps;
 } tdp_netlist;
 
-/* Cell library (host arrays, copied at build).
+/* Cell library (host arrays, copied at build); 1..256 cell types.
  *  slew_axis[num_types][n_slew], load_axis[num_types][n_load]: strictly
  *    increasing breakpoints; lookups clamp to the axis range and interpolate
  *    bilinearly between breakpoints.
  *  delay_lut, slew_lut [num_types][n_slew][n_load]: arc delay and output
  *    transition (slew_lut may equal delay_lut).
  *  pin_cap[num_types]: input-pin capacitance.
- *  Net delay into a sink = delay_scale * r_per_um * c_per_um * L^2, with L the
- *  Manhattan driver-to-sink distance (Eq. 7: R and C both linear in length);
- *  a driver's load = sum over its sinks of (pin_cap + c_per_um * L). */
+ *  Every sink sits on a wire of its own from the driver, of length L, the
+ *  Manhattan driver-to-sink distance, with resistance r_per_um * L and
+ *  capacitance c_per_um * L (Eq. 7: R and C both linear in length).  A
+ *  driver's load = sum over its sinks of (pin_cap + c_per_um * L).
+ *  net_model selects the net delay into a sink and the transition it sees:
+ *    0  lumped (Eq. 7): delay_scale * r_per_um * c_per_um * L^2; the sink
+ *       sees its driver's transition.
+ *    1  Elmore delay of that star RC net: delay_scale * r_per_um * L *
+ *       (c_per_um * L / 2 + pin_cap of the sink); the sink's transition is
+ *       the driver's degraded by the wire (PERI, Kashyap et al., TCAD 2004):
+ *       sqrt(s_drv^2 + (ln 9 * delay)^2).
+ *  Any other value fails the build with TDP_E_INVALID. */
 typedef struct {
   int32_t num_types, n_slew, n_load;
   const float *slew_axis, *load_axis;
   const float *delay_lut, *slew_lut;
   const float *pin_cap;
   float r_per_um, c_per_um, delay_scale;
+  int32_t net_model;
 } tdp_library;
 
 /* Extracted paths (device views owned by the graph; valid until the next
@@ -178,7 +188,9 @@ tdp_status tdp_batch_summary(tdp_graph, double *wns, double *tns, int32_t *n_fai
 
 /* Per-pin results of the last update in external pin order, as double device
  * arrays [num_pins] (any pointer may be NULL):
- *   at, rat, slack, slew; dnet (net delay into a sink pin, 0 elsewhere),
+ *   at, rat, slack, slew (at a sink pin, the transition its cell arc or
+ *   setup check sees: degraded by the wire under net model 1);
+ *   dnet (net delay into a sink pin, 0 elsewhere),
  *   load (at a driver pin, 0 elsewhere), darc (cell-arc delay from a
  *   combinational input pin to its output, 0 elsewhere).
  * Unconstrained pins (no endpoint downstream) have rat = slack = +inf. */

@@ -156,13 +156,14 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
     std::copy(lib->slew_lut, lib->slew_lut + n_tab, img.begin() + n_sa + n_la + n_tab);
     ok = hipMemcpy(flat, img.data(), sizeof(float) * img.size(), hipMemcpyHostToDevice) == hipSuccess;
   }
-  g->lut = LutView{nt, ns, nl, sa, la, dl, sl, flat, (int)n4};
+  g->lut = LutView{nt, ns, nl, sa, la, dl, sl, flat, (int)n4, lib->net_model};
   // topology
   ok = ok && upload(g, T.drv_cell, H.drv_cell) && upload(g, T.drv_ox, H.drv_ox) && upload(g, T.drv_oy, H.drv_oy) &&
        upload(g, T.drv_ext, H.drv_ext) && upload(g, T.net_ptr, H.net_ptr) && upload(g, T.net_sink, H.net_sink) &&
-       upload(g, T.net_cpin, H.net_cpin) && upload(g, T.snk_cell, H.snk_cell) && upload(g, T.snk_ox, H.snk_ox) &&
-       upload(g, T.snk_oy, H.snk_oy) && upload(g, T.snk_drv, H.snk_drv) && upload(g, T.snk_ext, H.snk_ext) &&
-       upload(g, T.snk_comb, H.snk_comb) && upload(g, T.comb_type, H.comb_type) &&
+       upload(g, T.net_cpin, H.net_cpin) && upload(g, T.snk_cap, H.snk_cap) && upload(g, T.type_cap, H.type_cap) &&
+       upload(g, T.snk_cell, H.snk_cell) && upload(g, T.snk_ox, H.snk_ox) && upload(g, T.snk_oy, H.snk_oy) &&
+       upload(g, T.snk_drv, H.snk_drv) && upload(g, T.snk_ext, H.snk_ext) && upload(g, T.snk_comb, H.snk_comb) &&
+       upload(g, T.comb_type, H.comb_type) &&
        upload(g, T.comb_inptr, H.comb_inptr) && upload(g, T.comb_ext, H.comb_ext) && upload(g, T.ff_ext, H.ff_ext) &&
        upload(g, T.ff_type, H.ff_type) && upload(g, T.ff_inst, H.ff_inst) &&
        upload(g, T.ext_pin_int, H.ext_pin_int) && upload(g, T.cell_int, H.cell_int) &&

@@ -26,6 +26,8 @@ bool check_library(const tdp_library *lib, std::string &err) {
   if (!lib) return fail(err, "library is NULL");
   if (lib->num_types < 1 || lib->n_slew < 2 || lib->n_load < 2 || lib->n_slew > 16 || lib->n_load > 16)
     return fail(err, "library: need >= 1 type and 2..16 breakpoints per axis");
+  // cell types travel in 8-bit fields of the lane records
+  if (lib->num_types > 256) return fail(err, "library: at most 256 cell types");
   if (!lib->slew_axis || !lib->load_axis || !lib->delay_lut || !lib->slew_lut || !lib->pin_cap)
     return fail(err, "library: NULL array");
   for (int t = 0; t < lib->num_types; ++t) {
@@ -43,6 +45,7 @@ bool check_library(const tdp_library *lib, std::string &err) {
       return fail(err, "library: table entry not finite");
   if (!std::isfinite(lib->r_per_um) || !std::isfinite(lib->c_per_um) || !std::isfinite(lib->delay_scale))
     return fail(err, "library: wire parameters not finite");
+  if (lib->net_model != 0 && lib->net_model != 1) return fail(err, "library: net_model must be 0 or 1");
   return true;
 }
 
@@ -339,6 +342,8 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
   H.net_sink.clear();
   H.net_sink.reserve(T.S);
   H.net_cpin.assign(T.M, 0.0);
+  H.snk_cap.assign(T.S, 0.f);
+  H.type_cap.assign(lib->pin_cap, lib->pin_cap + lib->num_types);
   for (int v = 0; v < T.M; ++v) {
     int inst, local;
     const tdp_netlist *nl = get_nl(drv_pin[v], inst, local);
@@ -348,6 +353,7 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
       int tl = nl->net_pins[k];
       int t = H.ext_pin_int[H.lv.pin_base[inst] + tl] - T.M;
       H.net_sink.push_back(t);
+      H.snk_cap[t] = lib->pin_cap[nl->cell_type[nl->pin_cell[tl]]];
       cp += lib->pin_cap[nl->cell_type[nl->pin_cell[tl]]];
     }
     H.net_cpin[v] = cp;
@@ -429,7 +435,8 @@ tdp_status build_host_topology(const tdp_netlist *const *nls, int32_t count, con
         for (int k = H.net_ptr[v]; k < H.net_ptr[v + 1]; ++k) {
           const int t = H.net_sink[k];
           const int vo = t < T.A ? T.n_start + H.snk_comb[t] : -1;
-          H.nm_rec.push_back(make_int4(T.M + t, H.snk_cell[t], vo, seg(head, head + n - 1)));
+          const int ty = t < T.A ? H.comb_type[H.snk_comb[t]] : H.ff_type[t - T.A];
+          H.nm_rec.push_back(make_int4(T.M + t, H.snk_cell[t], vo, seg(head, head + n - 1) | ty << 16));
           H.nm_ox.push_back(H.snk_ox[t]);
           H.nm_oy.push_back(H.snk_oy[t]);
           ++lane;

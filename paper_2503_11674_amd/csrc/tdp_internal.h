@@ -33,7 +33,43 @@ struct LutView {
   // float4s: the image a kernel stages in LDS
   const float4 *flat4;
   int n4;
+  int net_model;  // 0: lumped wires; 1: Elmore star nets with degraded sink transitions
 };
+
+// Net delay into a sink at Manhattan distance len (Eq. 7: wire R and C both
+// linear in length).  Lumped: the wire's R times its C, kappa * len^2 with
+// kappa = scale * r * c.  Elmore: each sink on a branch of its own from the
+// driver, a uniform RC line loaded by the sink's pin capacitance; the first
+// moment of its response is scale * r * len * (c * len / 2 + cap).
+template <typename T>
+struct NetModel {
+  int elmore;
+  T kappa;  // scale * r * c
+  T rs;     // scale * r
+  T hc;     // c / 2
+  __device__ __forceinline__ T delay(T len, T cap) const {
+    return elmore ? rs * len * (hc * len + cap) : kappa * len * len;
+  }
+  // d delay / d len
+  __device__ __forceinline__ T slope(T len, T cap) const {
+    return elmore ? rs * ((T)2 * hc * len + cap) : (T)2 * kappa * len;
+  }
+};
+
+// Transition at a sink: the driver's, or under the Elmore model that one
+// degraded by the wire (PERI: root sum of squares of the input transition and
+// the wire's step-response transition, ln 9 times its Elmore delay, the 10-90%
+// time of a single pole).
+// The fused multiply-add is written out: left to the compiler, the sum of
+// squares may be contracted one way in one kernel and another way in the
+// next, and the sweeps that compute the same arrivals would then differ in
+// the last bit.
+template <typename T>
+__device__ __forceinline__ T sink_slew(int net_model, T s, T dn) {
+  if (!net_model) return s;
+  const T w = (T)2.1972245773362196 * dn;  // ln 9
+  return sqrt(fma(s, s, w * w));
+}
 
 // Bilinear lookup with clamping: the breakpoint interval is the last one whose
 // left end is <= the value (the top interval for values at or past the end).
@@ -72,6 +108,8 @@ struct Topo {
   int32_t *net_ptr = nullptr;   // [M+1] into net_sink
   int32_t *net_sink = nullptr;  // [S] sinks of each net
   double *net_cpin = nullptr;   // [M] sum of sink pin capacitances
+  float *snk_cap = nullptr;     // [S] input-pin capacitance of each sink
+  float *type_cap = nullptr;    // [num_types] input-pin capacitance of each cell type
   // sinks [S]
   int32_t *snk_cell = nullptr;
   float *snk_ox = nullptr, *snk_oy = nullptr;
@@ -103,7 +141,8 @@ struct Topo {
   // than 63 sinks are "big" and handled one thread per net.
   // One record per lane: {internal pin (driver v or M + t; -1 = padding),
   // external cell (-1 for a port or padding), for a combinational-input sink
-  // the output driver of its cell (else -1), head lane | tail lane << 8}.
+  // the output driver of its cell (else -1), head lane | tail lane << 8 |
+  // for a sink, its cell's type << 16}.
   int32_t n_nm_chunks = 0, n_big = 0;
   int4 *nm_rec = nullptr;
   float *nm_ox = nullptr, *nm_oy = nullptr;
@@ -128,7 +167,7 @@ struct HostTopo {
   HostLevels lv;
   std::vector<int32_t> drv_cell, drv_ext, net_ptr, net_sink, snk_cell, snk_drv, snk_ext, snk_comb,
       comb_inptr, comb_ext, ff_ext, ff_inst, ext_pin_int, cell_int;
-  std::vector<float> drv_ox, drv_oy, snk_ox, snk_oy;
+  std::vector<float> drv_ox, drv_oy, snk_ox, snk_oy, snk_cap, type_cap;
   std::vector<double> net_cpin;
   std::vector<int4> fw_rec, nm_rec;
   std::vector<int2> fw_ext;
@@ -266,3 +305,11 @@ struct tdp_graph_s {
 
   tdp::Profiler prof;
 };
+
+namespace tdp {
+// the graph's net model in the precision T of its timing values
+template <typename T>
+inline NetModel<T> net_model(const tdp_graph_s *g) {
+  return NetModel<T>{g->lut.net_model, (T)g->scale * (T)g->r * (T)g->c, (T)g->scale * (T)g->r, (T)0.5 * (T)g->c};
+}
+}  // namespace tdp

@@ -5,7 +5,8 @@
 //
 // Smoothed TNS (not in the paper; this is its definition here): cell-arc
 // delays and start-point arrivals are frozen from the last timing update, net
-// delays follow the positions (kappa * L^2, L Manhattan).
+// delays follow the positions (the library's net model as a function of L,
+// the Manhattan length).
 //   sink t:          A(t) = A(drv) + dnet(t)
 //   comb output o:   A(o) = m + g ln sum_j exp((a_j - m)/g), a_j = A(in_j) + d_arc(in_j)
 //   endpoint e:      s(e) = (period - setup) - A(e)
@@ -13,7 +14,7 @@
 // The adjoint runs the levels top-down: dv/dA(e) = -sigmoid(-s(e)/g); an
 // output passes its adjoint to input j in proportion to softmax_j(a/g); a
 // driver collects the adjoints of its sinks.  dv/d dnet(t) is the adjoint at
-// t, and d dnet/dX_s = 2 kappa L sign(X_s - X_t) = -d dnet/dX_t.
+// t, and d dnet/dX_s = dnet'(L) sign(X_s - X_t) = -d dnet/dX_t.
 //
 // Weighted-average wirelength (the smoothed WL of Eq. 1): per net and axis,
 // sum x e^{x/g} / sum e^{x/g} - sum x e^{-x/g} / sum e^{-x/g}, with the
@@ -32,7 +33,7 @@ __device__ __forceinline__ T sgn(T v) {
 }
 
 template <typename T>
-__global__ void k_st_net(Topo tp, const float *__restrict__ x, const float *__restrict__ y, T kappa,
+__global__ void k_st_net(Topo tp, const float *__restrict__ x, const float *__restrict__ y, NetModel<T> nm,
                          T *__restrict__ dnl) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= tp.M) return;
@@ -44,7 +45,7 @@ __global__ void k_st_net(Topo tp, const float *__restrict__ x, const float *__re
     const int t = tp.net_sink[k];
     const int sc = tp.snk_cell[t];
     const T len = fabs((cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t])) + fabs((cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]));
-    dnl[t] = kappa * len * len;
+    dnl[t] = nm.delay(len, nm.elmore ? (T)tp.snk_cap[t] : (T)0);
   }
 }
 
@@ -115,7 +116,8 @@ __global__ void __launch_bounds__(256) k_st_bwd(Topo tp, int c0, int c1, T gam, 
 // gradient per cell: its output pin's net arcs and its input pins' net arcs
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
-                                                  T kappa, const T *__restrict__ adj, const double *__restrict__ gout,
+                                                  NetModel<T> nm, const T *__restrict__ adj,
+                                                  const double *__restrict__ gout,
                                                   float *__restrict__ gx, float *__restrict__ gy) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= tp.N || tp.cell_fixed[cell]) return;
@@ -138,7 +140,7 @@ __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restric
       const int t = tp.net_sink[k];
       const int sc = tp.snk_cell[t];
       const T dx = (cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t]), dy = (cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]);
-      const T g = adj[tp.M + t] * (T)2 * kappa * (fabs(dx) + fabs(dy));
+      const T g = adj[tp.M + t] * nm.slope(fabs(dx) + fabs(dy), nm.elmore ? (T)tp.snk_cap[t] : (T)0);
       ax += g * sgn(dx);
       ay += g * sgn(dy);
     }
@@ -149,7 +151,7 @@ __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restric
     const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
     const T dx = (cx - (T)x[cell]) + ((T)tp.drv_ox[s] - (T)tp.snk_ox[t]);
     const T dy = (cy - (T)y[cell]) + ((T)tp.drv_oy[s] - (T)tp.snk_oy[t]);
-    const T g = adj[tp.M + t] * (T)2 * kappa * (fabs(dx) + fabs(dy));
+    const T g = adj[tp.M + t] * nm.slope(fabs(dx) + fabs(dy), nm.elmore ? (T)tp.snk_cap[t] : (T)0);
     ax -= g * sgn(dx);
     ay -= g * sgn(dy);
   }
@@ -177,9 +179,9 @@ template <typename T>
 void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, double *val, hipStream_t s) {
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_STNS, s);
-  const T kappa = (T)g->scale * (T)g->r * (T)g->c;
   const T gam = (T)gamma;
-  hipLaunchKernelGGL(k_st_net<T>, dim3(nb(tp.M, 256)), dim3(256), 0, s, tp, x, y, kappa, (T *)g->st_dnet);
+  hipLaunchKernelGGL(k_st_net<T>, dim3(nb(tp.M, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
+                     (T *)g->st_dnet);
   if (tp.n_start > 0)
     hipLaunchKernelGGL(k_st_start<T>, dim3(nb(tp.n_start, 256)), dim3(256), 0, s, tp, (const T *)g->at,
                        (T *)g->st_at);
@@ -203,7 +205,6 @@ template <typename T>
 void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStream_t s) {
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_STNS, s);
-  const T kappa = (T)g->scale * (T)g->r * (T)g->c;
   const T gam = (T)g->st_gamma;
   for (int l = tp.D; l >= 1; --l) {
     const int c0 = g->lv.lvl[l - 1], c1 = g->lv.lvl[l];
@@ -211,7 +212,7 @@ void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStr
       hipLaunchKernelGGL(k_st_bwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
                          (const T *)g->darc, (const T *)g->st_at, (T *)g->st_adj);
   }
-  hipLaunchKernelGGL(k_st_grad<T>, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->st_x, g->st_y, kappa,
+  hipLaunchKernelGGL(k_st_grad<T>, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->st_x, g->st_y, net_model<T>(g),
                      (const T *)g->st_adj, gout, gx, gy);
   prof_end(g, TDP_STAGE_STNS, s);
 }

@@ -3,12 +3,14 @@
 // One update is:
 //   net pass   every net as a segment of a 64-lane chunk (driver lane, then
 //              its sinks): pin positions, the RC delay into each sink
-//              (kappa * L^2, L Manhattan), the driver's load (star model,
-//              a segmented sum); start points get arrival and transition.
+//              (kappa * L^2 with L Manhattan, or the sink's Elmore delay),
+//              the driver's load (star model, a segmented sum); start points
+//              get arrival and transition.
 //   forward    one launch per level; one lane per combinational input pin,
 //              a cell's inputs adjacent: arrival = segmented max over inputs of
 //              (driver arrival + net delay + table delay at the input's
-//              transition and the output load), output transition =
+//              transition, under the Elmore model the driver's degraded by the
+//              wire, and the output load), output transition =
 //              segmented max of the table transitions, the critical input =
 //              lowest lane attaining the max; the cell's head lane writes the
 //              output and, with deviation lists on, merges the cell's own
@@ -147,7 +149,7 @@ __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, in
 
 // ------------------------------------------------------------- net pass
 template <typename T>
-__global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, T kappa,
+__global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, NetModel<T> nm,
                                                   T cw, T in_slew,
                                                   T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
                                                   T *__restrict__ dnet_nm, float2 *__restrict__ cxy_nm,
@@ -173,7 +175,7 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
   const bool sink = p >= 0 && lane != head;
   const T len = sink ? fabs((cxd - cx) + (oxd - ox)) + fabs((cyd - cy) + (oyd - oy)) : (T)0;
   if (sink) {
-    const T dn = kappa * len * len;
+    const T dn = nm.delay(len, nm.elmore ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0);
     dnet[p - tp.M] = dn;
     dnet_nm[k] = dn;
   }
@@ -187,7 +189,7 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
 
 // nets too wide for one chunk: one thread per net
 template <typename T>
-__global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, const float *__restrict__ y, T kappa,
+__global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, const float *__restrict__ y, NetModel<T> nm,
                               T cw, T in_slew, T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
                               T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
                               int32_t *__restrict__ cdep) {
@@ -202,7 +204,7 @@ __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, c
     const int t = tp.net_sink[k];
     const int sc = tp.snk_cell[t];
     const T len = fabs((cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t])) + fabs((cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]));
-    dnet[t] = kappa * len * len;
+    dnet[t] = nm.delay(len, nm.elmore ? (T)tp.snk_cap[t] : (T)0);
     wl += len;
   }
   const T ld = (T)tp.net_cpin[v] + cw * wl;
@@ -256,9 +258,10 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
   if (valid) {
     const T ld = load[tp.n_start + c];
     const V2<T> w = as[s];
-    const T a_in = w.x + dnet[t];
+    const T dn = dnet[t];
+    const T a_in = w.x + dn;
     T d;
-    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, (rec.w >> 16) & 255, w.y, ld, d, o);
+    lut_lds<T>(s_lut, L.nt, L.ns, L.nl, (rec.w >> 16) & 255, sink_slew<T>(L.net_model, w.y, dn), ld, d, o);
     at[tp.M + t] = a_in;
     darc[t] = d;
     a = a_in + d;
@@ -595,7 +598,8 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
       const uint64_t w = wait_pub(&fw[s], W_EMPTY, err, limit);
       const float a_in = __uint_as_float((uint32_t)w) + dn;
       float d;
-      lut_lds<float>(s_lut, L.nt, L.ns, L.nl, ty, __uint_as_float((uint32_t)(w >> 32)), ld, d, o);
+      lut_lds<float>(s_lut, L.nt, L.ns, L.nl, ty, sink_slew<float>(L.net_model, __uint_as_float((uint32_t)(w >> 32)), dn),
+                     ld, d, o);
       at[tp.M + t] = a_in;
       darc[t] = d;
       a = a_in + d;
@@ -734,7 +738,7 @@ __global__ void __launch_bounds__(256) k_export(Topo tp, const T *__restrict__ a
                                                  const T *__restrict__ dnet, const T *__restrict__ load,
                                                  const T *__restrict__ darc, double *o_at, double *o_rat,
                                                  double *o_slack, double *o_slew, double *o_dnet,
-                                                 double *o_load, double *o_darc) {
+                                                 double *o_load, double *o_darc, int net_model) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= tp.P) return;
   const int i = tp.ext_pin_int[p];
@@ -743,7 +747,7 @@ __global__ void __launch_bounds__(256) k_export(Topo tp, const T *__restrict__ a
   if (o_at) o_at[p] = (double)at[i];
   if (o_rat) o_rat[p] = (double)rat[i];
   if (o_slack) o_slack[p] = (double)(rat[i] != pos_inf<T>() ? rat[i] - at[i] : pos_inf<T>());
-  if (o_slew) o_slew[p] = (double)(sink ? slew[tp.snk_drv[t]] : slew[i]);
+  if (o_slew) o_slew[p] = (double)(sink ? sink_slew<T>(net_model, slew[tp.snk_drv[t]], dnet[t]) : slew[i]);
   if (o_dnet) o_dnet[p] = sink ? (double)dnet[t] : 0.0;
   if (o_load) o_load[p] = sink ? 0.0 : (double)load[i];
   if (o_darc) o_darc[p] = (sink && t < tp.A) ? (double)darc[t] : 0.0;
@@ -811,7 +815,7 @@ static void forward_flow(tdp_graph g, hipStream_t s) {
 template <typename T>
 void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   const Topo &tp = g->topo;
-  const T kappa = (T)g->scale * (T)g->r * (T)g->c;
+  const NetModel<T> nm = net_model<T>(g);
   const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;
   FlowInit fl;
   fl.err = g->d_err;
@@ -825,11 +829,11 @@ void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t 
   }
   prof_begin(g, TDP_STAGE_NETPASS, s);
   pack_xy(x, y, g->xy, tp.N, s);
-  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, kappa,
+  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, nm,
                      (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
                      g->cxy_nm, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
   if (tp.n_big > 0)
-    hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, kappa,
+    hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, nm,
                        (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
                        (T *)g->slew, (V2<T> *)g->drv_as, g->cdep);
   prof_end(g, TDP_STAGE_NETPASS, s);
@@ -894,7 +898,8 @@ void sta_export_impl(tdp_graph g, double *at, double *rat, double *slack, double
   const Topo &tp = g->topo;
   hipLaunchKernelGGL(k_export<T>, dim3(nblk(tp.P, 256)), dim3(256), 0, s, tp, (const T *)g->at,
                      (const T *)g->rat, (const T *)g->slew, (const T *)g->dnet,
-                     (const T *)g->load, (const T *)g->darc, at, rat, slack, slew, dnet, load, darc);
+                     (const T *)g->load, (const T *)g->darc, at, rat, slack, slew, dnet, load, darc,
+                     g->lut.net_model);
 }
 
 void sta_export_crit(tdp_graph g, int32_t *out, hipStream_t s) {

@@ -46,7 +46,7 @@ class tdp_netlist(ctypes.Structure):
 class tdp_library(ctypes.Structure):
     _fields_ = [("num_types", _i32), ("n_slew", _i32), ("n_load", _i32), ("slew_axis", _p), ("load_axis", _p),
                 ("delay_lut", _p), ("slew_lut", _p), ("pin_cap", _p), ("r_per_um", _f32), ("c_per_um", _f32),
-                ("delay_scale", _f32)]
+                ("delay_scale", _f32), ("net_model", _i32)]
 
 
 class tdp_paths(ctypes.Structure):
@@ -178,7 +178,7 @@ class _LibraryHolder:
         ns = self.keep[0].reshape(nt, -1).shape[1]
         nl = self.keep[1].reshape(nt, -1).shape[1]
         self.s = tdp_library(nt, ns, nl, *[a.ctypes.data for a in self.keep], float(lib["r_per_um"]),
-                             float(lib["c_per_um"]), float(lib["delay_scale"]))
+                             float(lib["c_per_um"]), float(lib["delay_scale"]), int(lib.get("net_model", 0)))
 
 
 class TimingGraph:

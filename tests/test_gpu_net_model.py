@@ -1,0 +1,217 @@
+"""Parity of the HIP path with the FP64 oracle under the Elmore net model
+(net_model 1: Elmore delay of a star RC net, PERI-degraded sink transitions),
+and of the one-thread-per-net path for nets wider than a 64-lane chunk in both
+models.  Tolerances as in test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import ref  # noqa: E402
+from paper_2503_11674_amd import netgen  # noqa: E402
+from tests import handnets  # noqa: E402
+from tests.bruteforce import Graph  # noqa: E402
+from tests.comparator import arc_tables, compare_global, compare_paths, timing_close  # noqa: E402
+from tests.conftest import with_clock  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _tdp():
+    from paper_2503_11674_amd import tdp
+    return tdp
+
+
+def _xy(nl):
+    d = torch.device("cuda", 0)
+    return (torch.tensor(np.asarray(nl["x"], np.float32), device=d),
+            torch.tensor(np.asarray(nl["y"], np.float32), device=d))
+
+
+def _elmore(library):
+    lib = dict(library)
+    lib["net_model"] = 1
+    return lib
+
+
+_CASES = {}
+
+
+def _case(name, library):
+    if name in _CASES:
+        return _CASES[name]
+    print(f"[elmore case] building {name}", flush=True)
+    lib = _elmore(library)
+    # the clock is set from the model's own arrivals
+    nl = with_clock(netgen.make_netlist(netgen.CONFIGS[name]), lib)
+    st = ref.sta(nl, lib)
+    E = len(ref.endpoint_pins(nl))
+    K = netgen.CONFIGS[name].top_k_paths
+    k = max(1, K // max(1, st["n_fail"]))
+    g = _tdp().TimingGraph(nl, lib, max_paths=max(K, E), max_k=max(k, 4))
+    x, y = _xy(nl)
+    g.sta_update(x, y)
+    out = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+    _CASES[name] = dict(nl=nl, lib=lib, st=st, g=g, x=x, y=y, gpu=out, K=K, k=k)
+    return _CASES[name]
+
+
+def _check_sta(o, st, nl, rtol_local=2e-5):
+    inf_ok, bad, worst = timing_close(o["at"], st["at"])
+    assert inf_ok and bad == 0, ("at", bad, worst)
+    scale = np.maximum(np.abs(np.where(np.isfinite(st["at"]), st["at"], 0)),
+                       np.abs(np.where(np.isfinite(st["rat"]), st["rat"], 0)))
+    scale = np.maximum(scale, abs(float(nl["clock_period"])))
+    for key in ("rat", "slack"):
+        inf_ok, bad, worst = timing_close(o[key], st[key], scale=scale)
+        assert inf_ok and bad == 0, (key, bad, worst)
+    for key in ("dnet", "load", "darc", "slew"):
+        inf_ok, bad, worst = timing_close(o[key], st[key], rtol=rtol_local)
+        assert inf_ok and bad == 0, (key, bad, worst)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_elmore_sta_parity(name, library):
+    c = _case(name, library)
+    nl, st, o = c["nl"], c["st"], c["gpu"]
+    _check_sta(o, st, nl)
+    wns, tns, nf = c["g"].summary()
+    assert nf == st["n_fail"] == len(ref.endpoint_pins(nl)) // 20
+    assert abs(wns - st["wns"]) <= 1e-4 * abs(st["wns"])
+    assert abs(tns - st["tns"]) <= 1e-4 * abs(st["tns"])
+    # the model is in effect: sinks see degraded transitions
+    sinks = np.nonzero(o["dnet"] > 0)[0]
+    g = Graph(nl)
+    drv = np.array([g.driver[t] for t in sinks])
+    assert np.mean(o["slew"][sinks] > o["slew"][drv]) > 0.9
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_elmore_paths_and_report_timing(name, library):
+    c = _case(name, library)
+    nl, lib, st, g, k, K = c["nl"], c["lib"], c["st"], c["g"], c["k"], c["K"]
+    print(f"[elmore] {name} extract n_fail k={k} K={K}", flush=True)
+    g.extract_paths(n=-1, k=k, K=K)
+    gp = g.paths()
+    rp = ref.extract(nl, lib, st, n=-1, k=k, K=K)
+    assert gp["num_paths"] == rp["num_paths"]
+    res = compare_paths(gp, rp, st, Graph(nl), k)
+    assert res["missing"] == 0 and res["extra"] == 0
+    assert res["pinned_ok"] == res["pinned"] and res["unpinned_ok"] == res["unpinned"]
+    print(f"[elmore] {name} report_timing K={K}", flush=True)
+    g.report_timing(K)
+    gp = g.paths()
+    rp = ref.report_timing(nl, lib, st, K)
+    r = compare_global(gp, rp, st, arc_tables(nl), fp32=True)
+    assert r["count_ok"] and r["valid"] == r["num"] and r["slack_ok"] == r["num"]
+    assert r["distinct"] and r["sorted"] and r["ranks_ok"] and r["order_stat_ok"]
+    assert r["pinned_found"] == r["pinned"]
+
+
+def test_elmore_smoothed_tns_parity(library):
+    tdp = _tdp()
+    c = _case("C1", library)
+    nl, lib, st, g = c["nl"], c["lib"], c["st"], c["g"]
+    v_ref, gx_ref, gy_ref = ref.stns(nl, lib, st, gamma=10.0)
+    xr = c["x"].clone().requires_grad_(True)
+    yr = c["y"].clone().requires_grad_(True)
+    v = tdp.SmoothTNS.apply(xr, yr, g, 10.0)
+    v.backward()
+    assert abs(float(v) - v_ref) <= 1e-4 * abs(v_ref)
+    sc = max(np.abs(gx_ref).max(), np.abs(gy_ref).max())
+    assert np.allclose(xr.grad.cpu().numpy(), gx_ref, atol=1e-4 * sc, rtol=1e-3)
+    assert np.allclose(yr.grad.cpu().numpy(), gy_ref, atol=1e-4 * sc, rtol=1e-3)
+
+
+def test_elmore_f64_and_sweeps_agree(library):
+    """FP64 graphs meet the oracle to 1e-12; the dataflow sweep computes
+    bitwise what the per-level sweep computes under this model too."""
+    tdp = _tdp()
+    c = _case("C2", library)
+    nl, lib, st = c["nl"], c["lib"], c["st"]
+    g = tdp.TimingGraph(nl, lib, precision="f64", max_paths=200, max_k=4)
+    g.sta_update(c["x"], c["y"])
+    o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+    for key in ("at", "rat", "slew", "dnet"):
+        inf_ok, bad, worst = timing_close(o[key], st[key], rtol=1e-12)
+        assert inf_ok and bad == 0, (key, bad, worst)
+    g.close()
+    outs = []
+    for mode in (0, 1):
+        g = tdp.TimingGraph(nl, lib, max_paths=c["K"], max_k=c["k"])
+        g.set_tuning(sweep_mode=mode)
+        g.sta_update(c["x"], c["y"])
+        outs.append({kk: v.cpu().numpy() for kk, v in g.export().items()})
+        g.close()
+    for key in outs[0]:
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+def _fanout_design(n_wide=80, seed=0):
+    """A port drives n_wide buffers; the first buffer drives n_wide more; every
+    buffer but the first drives a flip-flop.  Two nets wider than a 64-lane
+    chunk: one from a start point, one from a combinational output."""
+    rng = np.random.default_rng(seed)
+    cells = [(0, 1)]  # cell 0: the buffer that fans out again
+    nets = []
+    n_buf = 2 * n_wide - 1
+    for i in range(1, n_buf + 1):
+        cells.append((int(rng.integers(0, 7)), 1))
+    for i in range(1, n_buf + 1):
+        cells.append((7, 1))
+    # pins: cell c < 1 + n_buf: in 2c, out 2c+1; flip-flop j (cell 1 + n_buf + j): D, Q after
+    ff0 = 2 * (1 + n_buf)
+    port = ff0 + 2 * n_buf
+    first = [0] + [2 * c for c in range(1, n_wide)]
+    second = [2 * c for c in range(n_wide, n_buf + 1)]
+    nets.append((port, first))
+    nets.append((1, second))
+    for j, c in enumerate(range(1, n_buf + 1)):
+        nets.append((2 * c + 1, [ff0 + 2 * j]))
+        nets.append((ff0 + 2 * j + 1, []))
+    N = len(cells)
+    x = rng.uniform(0, 300, N).astype(np.float32)
+    y = rng.uniform(0, 300, N).astype(np.float32)
+    x[0], y[0] = 150.0, 150.0
+    nl, _ = handnets.build(cells, 1, nets, x, y, port_xy=[(0.0, 0.0)], clock_period=0.0)
+    return nl
+
+
+@pytest.mark.parametrize("net_model", [0, 1])
+def test_nets_wider_than_a_chunk(library, net_model):
+    tdp = _tdp()
+    lib = dict(library, net_model=net_model)
+    nl = _fanout_design()
+    fo = np.diff(nl["net_ptr"]) - 1
+    assert (fo > 63).sum() == 2
+    nl = with_clock(nl, lib, 0.3)
+    st = ref.sta(nl, lib)
+    E = len(ref.endpoint_pins(nl))
+    g = tdp.TimingGraph(nl, lib, max_paths=4 * E, max_k=4)
+    g.sta_update(*_xy(nl))
+    o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+    _check_sta(o, st, nl)
+    g.extract_paths(n=-1, k=4)
+    gp = g.paths()
+    rp = ref.extract(nl, lib, st, n=-1, k=4)
+    assert gp["num_paths"] == rp["num_paths"]
+    res = compare_paths(gp, rp, st, Graph(nl), 4)
+    assert res["missing"] == 0 and res["extra"] == 0
+    assert res["pinned_ok"] == res["pinned"] and res["unpinned_ok"] == res["unpinned"]
+    g.close()
+
+
+def test_net_model_is_validated(library):
+    tdp = _tdp()
+    nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), library)
+    with pytest.raises(Exception, match="net_model"):
+        tdp.TimingGraph(nl, dict(library, net_model=2), max_paths=10, max_k=1)
+    # cell types travel in 8-bit fields: a library with more is refused
+    nt = 300
+    wide = {"num_types": nt,
+            "slew_axis": np.tile(np.float32([5, 80]), (nt, 1)), "load_axis": np.tile(np.float32([2, 8192]), (nt, 1)),
+            "delay_lut": np.full((nt, 2, 2), 10, np.float32), "slew_lut": np.full((nt, 2, 2), 10, np.float32),
+            "pin_cap": np.ones(nt, np.float32), "r_per_um": library["r_per_um"], "c_per_um": library["c_per_um"],
+            "delay_scale": library["delay_scale"]}
+    with pytest.raises(Exception, match="256 cell types"):
+        tdp.TimingGraph(nl, wide, max_paths=10, max_k=1)
