@@ -300,3 +300,42 @@ def wa(nl, gamma: float = 5.0, x=None, y=None, with_abs: bool = False):
     if with_abs:
         return float(val[0]), gx, gy, ax, ay
     return float(val[0]), gx, gy
+
+
+def density(x, y, area, fixed, grid, target: float = 1.0):
+    """Bin density, squared-overflow penalty, overflow and gradient.
+    grid = dict(x0, y0, bw, bh, gx, gy, R).  Returns a dict with dens
+    [gy, gx] (area per bin), value, overflow, grad_x, grad_y."""
+    L = _load()
+    x, y, area = _f32(x), _f32(y), _f32(area)
+    n = int(x.shape[0])
+    fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
+    gx_, gy_ = int(grid["gx"]), int(grid["gy"])
+    dens = np.empty(gx_ * gy_, np.float64)
+    val, ovf = np.zeros(1, np.float64), np.zeros(1, np.float64)
+    grx, gry = np.empty(n, np.float64), np.empty(n, np.float64)
+    d = ctypes.c_double
+    L.ora_density(ctypes.c_int(n), _p(x), _p(y), _p(area), _p(fixed), d(float(grid["x0"])), d(float(grid["y0"])),
+                  d(float(grid["bw"])), d(float(grid["bh"])), ctypes.c_int(gx_), ctypes.c_int(gy_),
+                  ctypes.c_int(int(grid["R"])), d(float(target)), _p(dens), _p(val), _p(ovf), _p(grx), _p(gry))
+    return {"dens": dens.reshape(gy_, gx_), "value": float(val[0]), "overflow": float(ovf[0]),
+            "grad_x": grx, "grad_y": gry}
+
+
+def nesterov(state, gx, gy, pdiv, frozen, coef: float, alpha0: float, first: bool, bounds):
+    """One Nesterov step.  state: dict of float64 arrays vx, vy, ux, uy, vpx,
+    vpy, gpx, gpy (updated in place); bounds = (xlo, xhi, ylo, yhi).
+    Returns the step length used."""
+    L = _load()
+    n = int(state["vx"].shape[0])
+    for k in ("vx", "vy", "ux", "uy", "vpx", "vpy", "gpx", "gpy"):
+        assert state[k].dtype == np.float64 and state[k].flags.c_contiguous
+    gx, gy, pdiv = _f64(gx), _f64(gy), _f64(pdiv)
+    frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
+    alpha = np.zeros(1, np.float64)
+    d = ctypes.c_double
+    L.ora_nesterov(ctypes.c_int(n), _p(frozen), _p(pdiv), _p(gx), _p(gy), _p(state["vx"]), _p(state["vy"]),
+                   _p(state["ux"]), _p(state["uy"]), _p(state["vpx"]), _p(state["vpy"]), _p(state["gpx"]),
+                   _p(state["gpy"]), d(coef), d(alpha0), ctypes.c_int(1 if first else 0),
+                   *[d(float(b)) for b in bounds], _p(alpha))
+    return float(alpha[0])

@@ -38,6 +38,11 @@
  *                  paper; definition below).
  *   ora_wa       - weighted-average wirelength (the WL_e of Eq. 1, the
  *                  published weighted-average model) with its gradient.
+ *   ora_density  - a bin-density penalty and overflow for the placement loop
+ *                  around the hot path (the density term of Eq. 1; its
+ *                  definition is below), with its gradient.
+ *   ora_nesterov - one Nesterov step with the Lipschitz step prediction
+ *                  ePlace uses (the optimiser of the paper's placer).
  *
  * Pin roles: a port (pin_cell == -1) is a primary input and drives a net;
  * a combinational cell has input pins (net sinks) and one output pin (a net
@@ -1006,5 +1011,135 @@ int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float 
   }
   *value = total;
   free(vx); free(vy); free(gx); free(gy); free(ax); free(ay);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* placement loop: bin density and one Nesterov step                        */
+/* ------------------------------------------------------------------------ */
+/* The paper's loop (Sec. IV) is DREAMPlace's: wirelength plus lambda times a
+ * density term (Eq. 1) plus beta * PP (Eq. 6), minimised with Nesterov's
+ * method.  The density term is not restated in the paper; this is the
+ * definition used here.
+ *
+ * The die [x0, x0 + gx*bw) x [y0, y0 + gy*bh) is cut into gx x gy bins, bin
+ * (i, j) stored at j*gx + i.  Cell c spreads its area a_c as a Gaussian
+ * centred on its position with standard deviations bw and bh, integrated
+ * over each bin and cut to the (2R+1) x (2R+1) bins around the bin holding
+ * the cell (its indices clamped into the grid); bins off the die get nothing:
+ *   D(i, j) = sum_c a_c Wx_c(i) Wy_c(j),
+ *   Wx_c(i) = Phi((x0 + (i+1) bw - x_c) / bw) - Phi((x0 + i bw - x_c) / bw),
+ * Phi the standard normal distribution function.  With cap = target*bw*bh:
+ *   value    = sum_b max(0, D_b - cap)^2
+ *   overflow = sum_b max(0, D_b - cap) / sum_c a_c
+ *   d value / d x_c = sum_b 2 max(0, D_b - cap) a_c Wx_c'(i) Wy_c(j)
+ * (likewise in y), Wx_c'(i) = (phi(lower) - phi(upper)) / bw with phi the
+ * standard normal density at the bin's two standardised edges; the window
+ * stays put while the cell stays in its bin.  Fixed cells count in D and get
+ * no gradient.  grad_x / grad_y [num_cells] are overwritten. */
+static double std_cdf(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+static double std_pdf(double z) { return exp(-0.5 * z * z) / sqrt(2.0 * acos(-1.0)); }
+
+static int bin_of(double v, double v0, double w, int g) {
+  double q = floor((v - v0) / w);
+  if (q < 0) q = 0;
+  if (q > g - 1) q = g - 1;
+  return (int)q;
+}
+
+int ora_density(int num_cells, const float *x, const float *y, const float *area, const uint8_t *cell_fixed,
+                double x0, double y0, double bw, double bh, int gx, int gy, int R, double target,
+                double *dens, double *value, double *overflow, double *grad_x, double *grad_y) {
+  double cap = target * bw * bh, total_area = 0.0;
+  for (int b = 0; b < gx * gy; ++b) dens[b] = 0.0;
+  for (int c = 0; c < num_cells; ++c) {
+    double xc = x[c], yc = y[c];
+    int bx = bin_of(xc, x0, bw, gx), by = bin_of(yc, y0, bh, gy);
+    total_area += area[c];
+    for (int j = by - R; j <= by + R; ++j) {
+      if (j < 0 || j >= gy) continue;
+      double wy = std_cdf((y0 + (j + 1) * bh - yc) / bh) - std_cdf((y0 + j * bh - yc) / bh);
+      for (int i = bx - R; i <= bx + R; ++i) {
+        if (i < 0 || i >= gx) continue;
+        double wx = std_cdf((x0 + (i + 1) * bw - xc) / bw) - std_cdf((x0 + i * bw - xc) / bw);
+        dens[j * gx + i] += area[c] * wx * wy;
+      }
+    }
+  }
+  double val = 0.0, ovf = 0.0;
+  for (int b = 0; b < gx * gy; ++b) {
+    double o = dens[b] > cap ? dens[b] - cap : 0.0;
+    val += o * o;
+    ovf += o;
+  }
+  *value = val;
+  *overflow = total_area > 0 ? ovf / total_area : 0.0;
+  for (int c = 0; c < num_cells; ++c) {
+    grad_x[c] = 0.0; grad_y[c] = 0.0;
+    if (cell_fixed && cell_fixed[c]) continue;
+    double xc = x[c], yc = y[c];
+    int bx = bin_of(xc, x0, bw, gx), by = bin_of(yc, y0, bh, gy);
+    for (int j = by - R; j <= by + R; ++j) {
+      if (j < 0 || j >= gy) continue;
+      double lo = (y0 + j * bh - yc) / bh, hi = (y0 + (j + 1) * bh - yc) / bh;
+      double wy = std_cdf(hi) - std_cdf(lo), dy = (std_pdf(lo) - std_pdf(hi)) / bh;
+      for (int i = bx - R; i <= bx + R; ++i) {
+        if (i < 0 || i >= gx) continue;
+        double o = dens[j * gx + i] - cap;
+        if (o <= 0) continue;
+        double lx = (x0 + i * bw - xc) / bw, hx = (x0 + (i + 1) * bw - xc) / bw;
+        double wx = std_cdf(hx) - std_cdf(lx), dx = (std_pdf(lx) - std_pdf(hx)) / bw;
+        grad_x[c] += 2.0 * o * area[c] * dx * wy;
+        grad_y[c] += 2.0 * o * area[c] * wx * dy;
+      }
+    }
+  }
+  return 0;
+}
+
+/* One step of Nesterov's method as ePlace applies it to placement (Lu et
+ * al., TODAES 2015), on the 2n coordinates (x then y) of n cells:
+ *   g      = the gradient at v_k divided per cell by max(1, pdiv_c)
+ *            (a diagonal preconditioner; frozen cells: 0),
+ *   alpha  = |v_k - v_{k-1}| / |g - g_{k-1}| (the Lipschitz prediction),
+ *            or alpha0 when first != 0 or that ratio is not a positive number,
+ *   u_{k+1} = clamp(v_k - alpha g),
+ *   v_{k+1} = clamp(u_{k+1} + coef (u_{k+1} - u_k)),
+ * clamp into [xlo, xhi] x [ylo, yhi].  Frozen cells keep v and u.  The
+ * arrays v, u, vp (v_{k-1}), gp (g_{k-1}) are updated in place: afterwards
+ * v = v_{k+1}, u = u_{k+1}, vp = v_k, gp = g.  Returns alpha in *alpha_out. */
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+int ora_nesterov(int n, const uint8_t *frozen, const double *pdiv, const double *gx, const double *gy,
+                 double *vx, double *vy, double *ux, double *uy, double *vpx, double *vpy, double *gpx,
+                 double *gpy, double coef, double alpha0, int first, double xlo, double xhi, double ylo,
+                 double yhi, double *alpha_out) {
+  double *qx = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  double *qy = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+  double dv = 0.0, dg = 0.0;
+  for (int c = 0; c < n; ++c) {
+    double s = pdiv[c] > 1.0 ? pdiv[c] : 1.0;
+    qx[c] = frozen[c] ? 0.0 : gx[c] / s;
+    qy[c] = frozen[c] ? 0.0 : gy[c] / s;
+    if (frozen[c]) continue;
+    dv += (vx[c] - vpx[c]) * (vx[c] - vpx[c]) + (vy[c] - vpy[c]) * (vy[c] - vpy[c]);
+    dg += (qx[c] - gpx[c]) * (qx[c] - gpx[c]) + (qy[c] - gpy[c]) * (qy[c] - gpy[c]);
+  }
+  double alpha = alpha0;
+  if (!first && dg > 0.0) {
+    double a = sqrt(dv) / sqrt(dg);
+    if (a > 0.0 && isfinite(a)) alpha = a;
+  }
+  for (int c = 0; c < n; ++c) {
+    if (frozen[c]) { vpx[c] = vx[c]; vpy[c] = vy[c]; gpx[c] = 0.0; gpy[c] = 0.0; continue; }
+    double nux = clampd(vx[c] - alpha * qx[c], xlo, xhi), nuy = clampd(vy[c] - alpha * qy[c], ylo, yhi);
+    double nvx = clampd(nux + coef * (nux - ux[c]), xlo, xhi), nvy = clampd(nuy + coef * (nuy - uy[c]), ylo, yhi);
+    vpx[c] = vx[c]; vpy[c] = vy[c];
+    gpx[c] = qx[c]; gpy[c] = qy[c];
+    ux[c] = nux; uy[c] = nuy;
+    vx[c] = nvx; vy[c] = nvy;
+  }
+  *alpha_out = alpha;
+  free(qx); free(qy);
   return 0;
 }
