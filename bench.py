@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--table1", action="store_true",
                     help="extraction statistics of report_timing(K) against report_timing_endpoint(n, k) "
                          "(paths, endpoints, pin pairs, time) instead of the step benchmark")
+    ap.add_argument("--loop", action="store_true",
+                    help="the placement loop around the step (Sec. IV, Fig. 5 analogue): wirelength-driven "
+                         "against timing-driven runs, and the time per iteration")
     ap.add_argument("--net-model", type=int, default=0, choices=(0, 1),
                     help="0: lumped RC wires (Eq. 7); 1: Elmore star nets with degraded sink transitions")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
@@ -223,6 +226,88 @@ def bench_table1(a):
                       "runs": max(1, a.steps), "rows": rows}), flush=True)
 
 
+def bench_loop(a):
+    """The placement loop (Sec. IV) from the generated placement, the same
+    schedule with beta = 0 (wirelength-driven) and with timing from the start
+    iteration every 15 (report_timing_endpoint(n_fail, 1), Eq. 9, PP).  The
+    clock period is the one at which 5 % of the endpoints fail at the end of
+    the wirelength-driven run (the design's constraint is set where the plain
+    placer lands), the same for both runs.  Prints the histories (HPWL,
+    overflow, WNS, TNS every 20 iterations) and the GPU time per iteration
+    with and without a timing refresh."""
+    import torch
+
+    from paper_2503_11674_amd import netgen
+    from paper_2503_11674_amd.placer import GlobalPlacer, LoopConfig
+
+    cfg_n = netgen.CONFIGS[a.workload]
+    nl = netgen.make_netlist(cfg_n)
+    lib = dict(netgen.make_library(), net_model=a.net_model)
+    N = int(nl["num_cells"])
+    bins = 1
+    while bins * bins < N // 2:
+        bins *= 2
+
+    def log(beta):
+        return lambda r: print(f"[loop] beta={beta} it={r.it} hpwl={r.hpwl:.4g} ovf={r.overflow:.3f} "
+                               f"wns={r.wns:.1f} tns={r.tns:.4g} pairs={r.pairs}", file=sys.stderr, flush=True)
+
+    # the wirelength-driven placement sets the clock
+    nl["clock_period"] = np.float32(1e9)
+    p = GlobalPlacer(nl, lib, LoopConfig(die=float(cfg_n.die), bins=bins, beta=0.0, record_every=20))
+    p.run()
+    ux, uy = p.positions()
+    p.g.sta_update(ux, uy)
+    at = p.g.export()["at"].cpu().numpy()
+    ff = np.nonzero(np.asarray(nl["cell_is_ff"]))[0]
+    ep = np.asarray(nl["cell_in_pins"])[np.asarray(nl["cell_in_ptr"])[ff]]
+    T = netgen.clock_period_for_fail_fraction(at[ep], 0.05)
+    p.g.close()
+    nl["clock_period"] = np.float32(T)
+    print(f"[loop] clock period {T:.1f} ps", file=sys.stderr, flush=True)
+    runs = []
+    for beta in (0.0, 1e-3):
+        cfg = LoopConfig(die=float(cfg_n.die), bins=bins, beta=beta, record_every=20)
+        p = GlobalPlacer(nl, lib, cfg)
+        t0 = time.perf_counter()
+        hist = p.run(log=log(beta))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs.append({"beta": beta, "iterations": p.it, "wall_s": round(wall, 3),
+                     "final": {"hpwl_um": round(hist[-1].hpwl, 1), "overflow": round(hist[-1].overflow, 4),
+                               "wns_ps": round(hist[-1].wns, 1), "tns_ps": round(hist[-1].tns, 1),
+                               "n_fail": hist[-1].n_fail},
+                     "history": [[r.it, round(r.hpwl, 1), round(r.overflow, 4), round(r.wns, 1), round(r.tns, 1),
+                                  r.n_fail, r.pairs] for r in hist]})
+        if beta > 0:
+            # GPU time per iteration (HIP events on the default stream): plain
+            # iterations, and a timing refresh (every 15th iteration)
+            n_it = max(10, a.steps)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            p.cfg.timing_start = 1 << 30  # no refresh inside this segment
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(n_it):
+                p.step()
+            e1.record()
+            torch.cuda.synchronize()
+            it_ms = e0.elapsed_time(e1) / n_it
+            e0.record()
+            for _ in range(3):
+                p.timing_refresh()
+            e1.record()
+            torch.cuda.synchronize()
+            runs[-1]["ms_per_iteration"] = round(it_ms, 4)
+            runs[-1]["ms_per_timing_refresh"] = round(e0.elapsed_time(e1) / 3, 4)
+        p.g.close()
+    out = {"table": "placement loop (Sec. IV, Fig. 5 analogue)",
+           "workload": f"{a.workload}: {N} cells, {int(nl['num_pins'])} pins, die {cfg_n.die:.0f} um, "
+                       f"{bins}x{bins} bins, utilisation 0.5, clock {T:.1f} ps",
+           "columns": ["iteration", "hpwl_um", "overflow", "wns_ps", "tns_ps", "n_fail", "pairs"],
+           "runs": runs}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -238,6 +323,8 @@ def main():
         return bench_batch(a)
     if a.table1:
         return bench_table1(a)
+    if a.loop:
+        return bench_loop(a)
     cfg = netgen.CONFIGS[a.workload]
     t0 = time.time()
     nl = netgen.make_netlist(cfg)

@@ -292,6 +292,61 @@ tdp_status tdp_wa_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float g
 tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph, float gamma_um, double *d_wl, float *d_gx, float *d_gy,
                                     hipStream_t);
 
+/* ------------------------------------------------ placement loop pieces */
+/* The placer around the hot path (Sec. IV) minimises wirelength + lambda *
+ * density (Eq. 1) + beta * PP (Eq. 6) with Nesterov's method.  The paper does
+ * not restate its density term; this library's is a bin density:
+ *   the die [x0, x0 + bins_x*bin_w) x [y0, y0 + bins_y*bin_h) is cut into
+ *   bins, bin (i, j) stored at j*bins_x + i; cell c spreads its area a_c as a
+ *   Gaussian centred on its position with standard deviations (bin_w, bin_h),
+ *   integrated over each bin and cut to the (2*radius+1)^2 bins around the
+ *   bin holding the cell (indices clamped into the grid); window mass off
+ *   the die is reflected back in at its edges (mirror images, as a Neumann
+ *   boundary): D(i, j) = sum_c a_c Wx_c(i) Wy_c(j).
+ *   value    = sum_b max(0, D_b - cap)^2, cap = target * bin_w * bin_h;
+ *   overflow = sum_b max(0, D_b - cap) / sum_c a_c. */
+typedef struct {
+  float x0, y0, bin_w, bin_h;
+  int32_t bins_x, bins_y; /* 1..4096 each */
+  int32_t radius;         /* 0..8 */
+  float target;           /* > 0 */
+} tdp_density_grid;
+
+/* Sets the grid and the cell areas (host [num_cells], finite, >= 0) and
+ * allocates the scratch of the density and Nesterov calls (synchronous; a
+ * later call with a grid no larger and a radius no larger reuses it).
+ * TDP_E_INVALID on a bad grid or area. */
+tdp_status tdp_density_setup(tdp_graph, const tdp_density_grid *grid, const float *h_area);
+
+/* Density value and overflow (single device doubles, overwritten; either
+ * may be NULL) at cell positions d_x, d_y [num_cells]; with d_gx and d_gy
+ * (both or neither) adds scale * d value / d position on movable cells;
+ * d_map (optional, [bins]) receives D.  Results are bitwise reproducible (no
+ * floating-point atomics).  TDP_E_STATE before tdp_density_setup. */
+tdp_status tdp_density_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float scale, double *d_value,
+                               double *d_overflow, float *d_gx, float *d_gy, float *d_map, hipStream_t);
+
+/* One step of Nesterov's method as ePlace applies it (Lu et al., TODAES
+ * 2015) on the cells' 2*num_cells coordinates, all device float arrays
+ * [num_cells]:
+ *   q = (d_gx, d_gy) / max(1, d_pdiv) per cell (fixed cells: 0);
+ *   alpha = |v - vp| / |q - gp|, or alpha0 when first != 0 or that ratio is
+ *           not a positive number (written to *d_alpha when not NULL);
+ *   u' = clamp(v - alpha q), v' = clamp(u' + coef (u' - u)) into
+ *   [xlo, xhi] x [ylo, yhi]; then vp = v, gp = q, u = u', v = v' in place.
+ * Fixed cells keep v and u.  Uses the scratch of tdp_density_setup
+ * (TDP_E_STATE before it); asynchronous, allocates nothing. */
+tdp_status tdp_nesterov_step(tdp_graph, const float *d_gx, const float *d_gy, const float *d_pdiv, float *d_vx,
+                             float *d_vy, float *d_ux, float *d_uy, float *d_vpx, float *d_vpy, float *d_gpx,
+                             float *d_gpy, double coef, double alpha0, int32_t first, float xlo, float xhi,
+                             float ylo, float yhi, double *d_alpha, hipStream_t);
+
+/* *d_out (one device double, overwritten) = sum over cells of |d_a[c]| +
+ * |d_b[c]| (an L1 norm of a gradient pair, e.g. to set lambda from the ratio
+ * of the wirelength and density gradients), in a fixed order.  Uses the
+ * scratch of tdp_density_setup (TDP_E_STATE before it). */
+tdp_status tdp_abs_sum(tdp_graph, const float *d_a, const float *d_b, double *d_out, hipStream_t);
+
 /* ------------------------------------------------------------ tooling */
 /* Stage timing: when enabled, every call records HIP events around its
  * stages on its stream.  tdp_profile_read synchronises and returns the
@@ -300,7 +355,7 @@ tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph, float gamma_um, double *d_wl, flo
 enum {
   TDP_STAGE_NETPASS = 0, TDP_STAGE_FORWARD, TDP_STAGE_ENDPOINT, TDP_STAGE_BACKWARD,
   TDP_STAGE_SELECT, TDP_STAGE_SEARCH, TDP_STAGE_ORDER, TDP_STAGE_WALK, TDP_STAGE_PAIRS,
-  TDP_STAGE_P2P_FWD, TDP_STAGE_P2P_BWD, TDP_STAGE_STNS, TDP_STAGE_WA, TDP_NUM_STAGES
+  TDP_STAGE_P2P_FWD, TDP_STAGE_P2P_BWD, TDP_STAGE_STNS, TDP_STAGE_WA, TDP_STAGE_DENSITY, TDP_NUM_STAGES
 };
 /* stage_mask: bit TDP_STAGE_x times that stage (0 turns timing off; events
  * are pooled and reused, so timing one stage adds two event records per

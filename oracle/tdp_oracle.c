@@ -1026,19 +1026,45 @@ int ora_wa(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const float 
  * (i, j) stored at j*gx + i.  Cell c spreads its area a_c as a Gaussian
  * centred on its position with standard deviations bw and bh, integrated
  * over each bin and cut to the (2R+1) x (2R+1) bins around the bin holding
- * the cell (its indices clamped into the grid); bins off the die get nothing:
+ * the cell (its indices clamped into the grid).  Mass the window puts off the
+ * die is reflected back in at the die's edges (mirror images of the Gaussian,
+ * as the Neumann boundary of DREAMPlace's electrostatic density does), so
+ * that an edge does not look emptier than the interior:
  *   D(i, j) = sum_c a_c Wx_c(i) Wy_c(j),
- *   Wx_c(i) = Phi((x0 + (i+1) bw - x_c) / bw) - Phi((x0 + i bw - x_c) / bw),
- * Phi the standard normal distribution function.  With cap = target*bw*bh:
+ *   Wx_c(i) = sum over window bins v that fold onto i of
+ *             Phi((x0 + (v+1) bw - x_c) / bw) - Phi((x0 + v bw - x_c) / bw),
+ * Phi the standard normal distribution function, a bin v < 0 folding onto
+ * -1 - v and a bin v >= gx onto 2 gx - 1 - v (repeatedly, for grids narrower
+ * than the window).  With cap = target*bw*bh:
  *   value    = sum_b max(0, D_b - cap)^2
  *   overflow = sum_b max(0, D_b - cap) / sum_c a_c
  *   d value / d x_c = sum_b 2 max(0, D_b - cap) a_c Wx_c'(i) Wy_c(j)
- * (likewise in y), Wx_c'(i) = (phi(lower) - phi(upper)) / bw with phi the
- * standard normal density at the bin's two standardised edges; the window
- * stays put while the cell stays in its bin.  Fixed cells count in D and get
+ * (likewise in y), Wx_c'(i) the same fold of (phi(lower) - phi(upper)) / bw,
+ * phi the standard normal density at a window bin's standardised edges; the
+ * window stays put while the cell stays in its bin.  Fixed cells count in D and get
  * no gradient.  grad_x / grad_y [num_cells] are overwritten. */
 static double std_cdf(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
 static double std_pdf(double z) { return exp(-0.5 * z * z) / sqrt(2.0 * acos(-1.0)); }
+
+static int fold_bin(int v, int g) {
+  while (v < 0 || v >= g) v = v < 0 ? -1 - v : 2 * g - 1 - v;
+  return v;
+}
+
+/* folded window weights of one axis: wt[k] and dt[k] for grid bin
+ * b - R + k (0 when off the grid), from a cell at standardised position
+ * (v - v0) / w relative to its window bin b */
+static void axis_weights(double v, double v0, double w, int g, int b, int R, double *wt, double *dt) {
+  for (int k = 0; k < 2 * R + 1; ++k) { wt[k] = 0.0; dt[k] = 0.0; }
+  for (int k = 0; k < 2 * R + 1; ++k) {
+    int u = b - R + k;
+    double lo = (v0 + u * w - v) / w, hi = (v0 + (u + 1) * w - v) / w;
+    int f = fold_bin(u, g);
+    int kf = f - (b - R);
+    wt[kf] += std_cdf(hi) - std_cdf(lo);
+    dt[kf] += (std_pdf(lo) - std_pdf(hi)) / w;
+  }
+}
 
 static int bin_of(double v, double v0, double w, int g) {
   double q = floor((v - v0) / w);
@@ -1051,18 +1077,22 @@ int ora_density(int num_cells, const float *x, const float *y, const float *area
                 double x0, double y0, double bw, double bh, int gx, int gy, int R, double target,
                 double *dens, double *value, double *overflow, double *grad_x, double *grad_y) {
   double cap = target * bw * bh, total_area = 0.0;
+  int K = 2 * R + 1;
+  double *wx = (double *)malloc(sizeof(double) * K), *dx = (double *)malloc(sizeof(double) * K);
+  double *wy = (double *)malloc(sizeof(double) * K), *dy = (double *)malloc(sizeof(double) * K);
   for (int b = 0; b < gx * gy; ++b) dens[b] = 0.0;
   for (int c = 0; c < num_cells; ++c) {
-    double xc = x[c], yc = y[c];
-    int bx = bin_of(xc, x0, bw, gx), by = bin_of(yc, y0, bh, gy);
+    int bx = bin_of(x[c], x0, bw, gx), by = bin_of(y[c], y0, bh, gy);
     total_area += area[c];
-    for (int j = by - R; j <= by + R; ++j) {
+    axis_weights(x[c], x0, bw, gx, bx, R, wx, dx);
+    axis_weights(y[c], y0, bh, gy, by, R, wy, dy);
+    for (int kj = 0; kj < K; ++kj) {
+      int j = by - R + kj;
       if (j < 0 || j >= gy) continue;
-      double wy = std_cdf((y0 + (j + 1) * bh - yc) / bh) - std_cdf((y0 + j * bh - yc) / bh);
-      for (int i = bx - R; i <= bx + R; ++i) {
+      for (int ki = 0; ki < K; ++ki) {
+        int i = bx - R + ki;
         if (i < 0 || i >= gx) continue;
-        double wx = std_cdf((x0 + (i + 1) * bw - xc) / bw) - std_cdf((x0 + i * bw - xc) / bw);
-        dens[j * gx + i] += area[c] * wx * wy;
+        dens[j * gx + i] += area[c] * wx[ki] * wy[kj];
       }
     }
   }
@@ -1077,23 +1107,23 @@ int ora_density(int num_cells, const float *x, const float *y, const float *area
   for (int c = 0; c < num_cells; ++c) {
     grad_x[c] = 0.0; grad_y[c] = 0.0;
     if (cell_fixed && cell_fixed[c]) continue;
-    double xc = x[c], yc = y[c];
-    int bx = bin_of(xc, x0, bw, gx), by = bin_of(yc, y0, bh, gy);
-    for (int j = by - R; j <= by + R; ++j) {
+    int bx = bin_of(x[c], x0, bw, gx), by = bin_of(y[c], y0, bh, gy);
+    axis_weights(x[c], x0, bw, gx, bx, R, wx, dx);
+    axis_weights(y[c], y0, bh, gy, by, R, wy, dy);
+    for (int kj = 0; kj < K; ++kj) {
+      int j = by - R + kj;
       if (j < 0 || j >= gy) continue;
-      double lo = (y0 + j * bh - yc) / bh, hi = (y0 + (j + 1) * bh - yc) / bh;
-      double wy = std_cdf(hi) - std_cdf(lo), dy = (std_pdf(lo) - std_pdf(hi)) / bh;
-      for (int i = bx - R; i <= bx + R; ++i) {
+      for (int ki = 0; ki < K; ++ki) {
+        int i = bx - R + ki;
         if (i < 0 || i >= gx) continue;
         double o = dens[j * gx + i] - cap;
         if (o <= 0) continue;
-        double lx = (x0 + i * bw - xc) / bw, hx = (x0 + (i + 1) * bw - xc) / bw;
-        double wx = std_cdf(hx) - std_cdf(lx), dx = (std_pdf(lx) - std_pdf(hx)) / bw;
-        grad_x[c] += 2.0 * o * area[c] * dx * wy;
-        grad_y[c] += 2.0 * o * area[c] * wx * dy;
+        grad_x[c] += 2.0 * o * area[c] * dx[ki] * wy[kj];
+        grad_y[c] += 2.0 * o * area[c] * wx[ki] * dy[kj];
       }
     }
   }
+  free(wx); free(dx); free(wy); free(dy);
   return 0;
 }
 

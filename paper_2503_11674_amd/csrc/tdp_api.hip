@@ -609,6 +609,89 @@ tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph g, float gamma, double *wl, float 
   return check_launch(g, "wa_fwd_bwd_at_update");
 }
 
+tdp_status tdp_density_setup(tdp_graph g, const tdp_density_grid *grid, const float *h_area) {
+  GUARD(g);
+  if (!grid || !h_area) return fail(g, TDP_E_INVALID, "NULL argument");
+  const tdp_density_grid &q = *grid;
+  if (q.bins_x < 1 || q.bins_y < 1 || q.bins_x > 4096 || q.bins_y > 4096)
+    return fail(g, TDP_E_INVALID, "density grid: bins_x and bins_y must be in 1..4096");
+  if (q.radius < 0 || q.radius > 8) return fail(g, TDP_E_INVALID, "density grid: radius must be in 0..8");
+  if (!(q.bin_w > 0) || !(q.bin_h > 0) || !std::isfinite(q.bin_w) || !std::isfinite(q.bin_h) ||
+      !std::isfinite(q.x0) || !std::isfinite(q.y0))
+    return fail(g, TDP_E_INVALID, "density grid: origin and bin sizes must be finite, sizes > 0");
+  if (!(q.target > 0) || !std::isfinite(q.target)) return fail(g, TDP_E_INVALID, "density grid: target must be > 0");
+  const int N = g->topo.N;
+  double total = 0.0;
+  for (int c = 0; c < N; ++c) {
+    if (!std::isfinite(h_area[c]) || h_area[c] < 0) return fail(g, TDP_E_INVALID, "cell areas must be finite, >= 0");
+    total += h_area[c];
+  }
+  const int bins = q.bins_x * q.bins_y, K = 2 * q.radius + 1;
+  bool ok = true;
+  if (!g->dn_area) {
+    const int scan_cap = std::max(std::max(N, 1), sort_hist_size(std::max(N, 1)));
+    ok = dalloc(g, g->dn_area, N) && dalloc(g, g->dn_k0, N) && dalloc(g, g->dn_k1, N) && dalloc(g, g->dn_v0, N) &&
+         dalloc(g, g->dn_v1, N) && dalloc(g, g->dn_hist, sort_hist_size(std::max(N, 1))) &&
+         dalloc(g, g->dn_scan, scan_tmp_size(scan_cap)) && dalloc(g, g->dn_part, 2 * density_parts()) &&
+         dalloc(g, g->nest_part, 2 * density_parts()) && dalloc(g, g->nest_alpha, 1) && dalloc(g, g->dn_nheavy, 1);
+  }
+  if (ok && bins > g->dn_alloc_bins) {  // a smaller grid reuses the buffers
+    ok = dalloc(g, g->dn_start, (size_t)bins + 1) && dalloc(g, g->dn_map, bins) && dalloc(g, g->dn_heavy, bins);
+    if (ok) g->dn_alloc_bins = bins;
+  }
+  if (ok && q.radius > g->dn_alloc_R) {
+    ok = dalloc(g, g->dn_w, (size_t)2 * K * std::max(N, 1));
+    if (ok) g->dn_alloc_R = q.radius;
+  }
+  if (!ok) return fail(g, TDP_E_NOMEM, "density: device allocation failed");
+  if (N > 0 && hipMemcpy(g->dn_area, h_area, sizeof(float) * N, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "density: area upload failed");
+  int bits = 0;
+  while (bits < 62 && ((int64_t)1 << bits) < (int64_t)bins) ++bits;
+  g->dn_key_bits = std::max(8, (bits + 7) / 8 * 8);
+  g->dn = DensityGrid{q.x0, q.y0, q.bin_w, q.bin_h, q.target, q.bins_x, q.bins_y, q.radius};
+  g->dn_total_area = total;
+  g->dn_ready = true;
+  return TDP_OK;
+}
+
+tdp_status tdp_density_fwd_bwd(tdp_graph g, const float *x, const float *y, float scale, double *d_value,
+                               double *d_overflow, float *d_gx, float *d_gy, float *d_map, hipStream_t s) {
+  GUARD(g);
+  if (!g->dn_ready) return fail(g, TDP_E_STATE, "density: no tdp_density_setup yet");
+  if (!x || !y) return fail(g, TDP_E_INVALID, "NULL positions");
+  if ((d_gx == nullptr) != (d_gy == nullptr)) return fail(g, TDP_E_INVALID, "d_gx and d_gy: both or neither");
+  if (!std::isfinite(scale)) return fail(g, TDP_E_INVALID, "scale not finite");
+  density_impl(g, x, y, scale, d_value, d_overflow, d_gx, d_gy, d_map, s);
+  return check_launch(g, "density_fwd_bwd");
+}
+
+tdp_status tdp_nesterov_step(tdp_graph g, const float *d_gx, const float *d_gy, const float *d_pdiv, float *d_vx,
+                             float *d_vy, float *d_ux, float *d_uy, float *d_vpx, float *d_vpy, float *d_gpx,
+                             float *d_gpy, double coef, double alpha0, int32_t first, float xlo, float xhi, float ylo,
+                             float yhi, double *d_alpha, hipStream_t s) {
+  GUARD(g);
+  if (!g->dn_ready) return fail(g, TDP_E_STATE, "nesterov: no tdp_density_setup yet");
+  if (!d_gx || !d_gy || !d_pdiv || !d_vx || !d_vy || !d_ux || !d_uy || !d_vpx || !d_vpy || !d_gpx || !d_gpy)
+    return fail(g, TDP_E_INVALID, "NULL argument");
+  if (!std::isfinite(coef) || !(alpha0 > 0) || !std::isfinite(alpha0))
+    return fail(g, TDP_E_INVALID, "coef must be finite and alpha0 > 0");
+  if (!(xlo <= xhi) || !(ylo <= yhi) || !std::isfinite(xlo) || !std::isfinite(xhi) || !std::isfinite(ylo) ||
+      !std::isfinite(yhi))
+    return fail(g, TDP_E_INVALID, "bounds must be finite with lo <= hi");
+  nesterov_impl(g, d_gx, d_gy, d_pdiv, d_vx, d_vy, d_ux, d_uy, d_vpx, d_vpy, d_gpx, d_gpy, coef, alpha0, first ? 1 : 0,
+                xlo, xhi, ylo, yhi, d_alpha, s);
+  return check_launch(g, "nesterov_step");
+}
+
+tdp_status tdp_abs_sum(tdp_graph g, const float *d_a, const float *d_b, double *d_out, hipStream_t s) {
+  GUARD(g);
+  if (!g->dn_ready) return fail(g, TDP_E_STATE, "abs_sum: no tdp_density_setup yet");
+  if (!d_a || !d_b || !d_out) return fail(g, TDP_E_INVALID, "NULL argument");
+  abs_sum_impl(g, d_a, d_b, d_out, s);
+  return check_launch(g, "abs_sum");
+}
+
 tdp_status tdp_profile_enable(tdp_graph g, int32_t stage_mask) {
   GUARD(g);
   g->prof.mask = stage_mask;

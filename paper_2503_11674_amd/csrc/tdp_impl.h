@@ -50,5 +50,12 @@ void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, dou
 template <typename T> void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStream_t s);
 void wa_impl(tdp_graph g, const float *x, const float *y, float gamma, double *wl, float *gx, float *gy,
              hipStream_t s);
+void density_impl(tdp_graph g, const float *x, const float *y, float scale, double *value, double *overflow,
+                  float *gx, float *gy, float *map_out, hipStream_t s);
+void nesterov_impl(tdp_graph g, const float *gx, const float *gy, const float *pdiv, float *vx, float *vy, float *ux,
+                   float *uy, float *vpx, float *vpy, float *gpx, float *gpy, double coef, double alpha0, int first,
+                   float xlo, float xhi, float ylo, float yhi, double *alpha_out, hipStream_t s);
+void abs_sum_impl(tdp_graph g, const float *a, const float *b, double *out, hipStream_t s);
+int density_parts();
 
 }  // namespace tdp

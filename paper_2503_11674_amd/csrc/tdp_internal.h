@@ -95,6 +95,13 @@ __device__ __forceinline__ void lut_pair(const LutView &L, int type, T s, T l, T
           w11 * (T)L.slew[base + L.nl + 1];
 }
 
+// bin grid of the density term: bin (i, j) covers [x0 + i bw, x0 + (i+1) bw)
+// x [y0 + j bh, y0 + (j+1) bh), stored at j * gx + i; window radius R bins
+struct DensityGrid {
+  float x0, y0, bw, bh, target;
+  int gx, gy, R;
+};
+
 // ---------------------------------------------------------------- topology
 // Device topology; plain data so kernels take it by value.
 struct Topo {
@@ -296,6 +303,20 @@ struct tdp_graph_s {
   void *st_at = nullptr, *st_adj = nullptr, *st_dnet = nullptr;
   float st_gamma = 0;
   const float *st_x = nullptr, *st_y = nullptr;
+
+  // density term and Nesterov steps (tdp_density_setup)
+  bool dn_ready = false;
+  tdp::DensityGrid dn{};
+  int dn_key_bits = 8, dn_alloc_bins = 0, dn_alloc_R = -1;
+  double dn_total_area = 0;
+  float *dn_area = nullptr;                    // [N]
+  uint64_t *dn_k0 = nullptr, *dn_k1 = nullptr;  // [N] bin keys (sort ping-pong)
+  uint32_t *dn_v0 = nullptr, *dn_v1 = nullptr;  // [N] cell ids
+  int32_t *dn_hist = nullptr, *dn_scan = nullptr, *dn_start = nullptr;  // start [bins + 1]
+  int32_t *dn_heavy = nullptr, *dn_nheavy = nullptr;  // crowded bins [bins] and their count
+  float *dn_w = nullptr;                       // [2 (2R+1)][N] window weights of the sorted cells
+  float *dn_map = nullptr;                     // [bins]
+  double *dn_part = nullptr, *nest_part = nullptr, *nest_alpha = nullptr;
 
   // weighted-average wirelength: per-pin gradient [2P]
   float *wa_gpin = nullptr;

@@ -26,7 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 TDP_F32, TDP_F64 = 0, 1
 STAGES = ["netpass", "forward", "endpoint", "backward", "select", "search", "order", "walk", "pairs",
-          "p2p_fwd", "p2p_bwd", "stns", "wa"]
+          "p2p_fwd", "p2p_bwd", "stns", "wa", "density"]
 _STATUS = {0: "ok", 1: "invalid argument", 2: "combinational cycle", 3: "out of memory", 4: "device error",
            5: "capacity exceeded", 6: "call out of order", 7: "unsupported"}
 
@@ -47,6 +47,11 @@ class tdp_library(ctypes.Structure):
     _fields_ = [("num_types", _i32), ("n_slew", _i32), ("n_load", _i32), ("slew_axis", _p), ("load_axis", _p),
                 ("delay_lut", _p), ("slew_lut", _p), ("pin_cap", _p), ("r_per_um", _f32), ("c_per_um", _f32),
                 ("delay_scale", _f32), ("net_model", _i32)]
+
+
+class tdp_density_grid(ctypes.Structure):
+    _fields_ = [("x0", _f32), ("y0", _f32), ("bin_w", _f32), ("bin_h", _f32), ("bins_x", _i32), ("bins_y", _i32),
+                ("radius", _i32), ("target", _f32)]
 
 
 class tdp_paths(ctypes.Structure):
@@ -94,6 +99,11 @@ tdp_stns_fwd = _sig("tdp_stns_fwd", _p, _p, _p, _f32, _p, _p)
 tdp_stns_bwd = _sig("tdp_stns_bwd", _p, _p, _p, _p, _p)
 tdp_wa_fwd_bwd = _sig("tdp_wa_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p)
 tdp_wa_fwd_bwd_at_update = _sig("tdp_wa_fwd_bwd_at_update", _p, _f32, _p, _p, _p, _p)
+tdp_density_setup = _sig("tdp_density_setup", _p, _P(tdp_density_grid), _p)
+tdp_density_fwd_bwd = _sig("tdp_density_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p, _p, _p)
+tdp_nesterov_step = _sig("tdp_nesterov_step", _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, ctypes.c_double,
+                         ctypes.c_double, _i32, _f32, _f32, _f32, _f32, _p, _p)
+tdp_abs_sum = _sig("tdp_abs_sum", _p, _p, _p, _p, _p)
 tdp_profile_enable = _sig("tdp_profile_enable", _p, _i32)
 tdp_profile_read = _sig("tdp_profile_read", _p, _p, _p)
 tdp_set_tuning = _sig("tdp_set_tuning", _p, _i32, _i32, _i32)
@@ -111,7 +121,8 @@ EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destro
             "tdp_extract_paths", "tdp_report_timing", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
             "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
-            "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_wa_fwd_bwd_at_update", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
+            "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_wa_fwd_bwd_at_update", "tdp_density_setup",
+            "tdp_density_fwd_bwd", "tdp_nesterov_step", "tdp_abs_sum", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
             "tdp_autotune", "tdp_graph_info", "tdp_status_str", "tdp_last_error"]
 
 
@@ -210,6 +221,7 @@ class TimingGraph:
         self.max_paths = max_paths
         self.max_k = max_k
         self._paths = None
+        self._dn_grid = None
 
     def close(self):
         if getattr(self, "h", None):
@@ -370,6 +382,50 @@ class TimingGraph:
         out = _scalar_out(out, gx.device)
         _check(tdp_wa_fwd_bwd_at_update(self.h, gamma, _ptr(out), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
         return out
+
+    # ------------------------------------------------ placement loop pieces
+    def density_setup(self, grid: Dict, area):
+        """grid: x0, y0, bw, bh, gx, gy, R, target; area: [num_cells] host."""
+        a = np.ascontiguousarray(area, dtype=np.float32)
+        if a.shape[0] != self.num_cells:
+            raise ValueError("one area per cell")
+        q = tdp_density_grid(float(grid["x0"]), float(grid["y0"]), float(grid["bw"]), float(grid["bh"]),
+                             int(grid["gx"]), int(grid["gy"]), int(grid["R"]), float(grid.get("target", 1.0)))
+        _check(tdp_density_setup(self.h, ctypes.byref(q), a.ctypes.data), self.h)
+        self._dn_grid = int(grid["gx"]) * int(grid["gy"])
+
+    def density(self, x, y, scale: float = 1.0, gx=None, gy=None, want_map: bool = False, stream=None):
+        """(value, overflow[, map]) as device tensors; adds scale * gradient
+        to gx, gy when given."""
+        val = torch.zeros(2, dtype=torch.float64, device=x.device)
+        mp = None
+        if want_map:
+            mp = torch.empty(int(self._grid_bins()), dtype=torch.float32, device=x.device)
+        _check(tdp_density_fwd_bwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), float(scale), _ptr(val),
+                                   val.data_ptr() + 8, _ptr(gx), _ptr(gy), _ptr(mp), _stream(stream)), self.h)
+        return (val[0], val[1], mp) if want_map else (val[0], val[1])
+
+    def abs_sum(self, a, b, out=None, stream=None) -> torch.Tensor:
+        """sum |a| + |b| over cells (device double)."""
+        out = _scalar_out(out, a.device)
+        _check(tdp_abs_sum(self.h, _ptr(_cuda_f32(a)), _ptr(_cuda_f32(b)), _ptr(out), _stream(stream)), self.h)
+        return out
+
+    def _grid_bins(self):
+        if self._dn_grid is None:
+            raise RuntimeError("density_setup first")
+        return self._dn_grid
+
+    def nesterov_step(self, st: Dict, gx, gy, pdiv, coef: float, alpha0: float, first: bool, bounds,
+                      alpha_out=None, stream=None):
+        """One Nesterov step on the state tensors st (vx, vy, ux, uy, vpx, vpy,
+        gpx, gpy; updated in place); bounds = (xlo, xhi, ylo, yhi)."""
+        for k in ("vx", "vy", "ux", "uy", "vpx", "vpy", "gpx", "gpy"):
+            _cuda_f32(st[k])
+        _check(tdp_nesterov_step(self.h, _ptr(_cuda_f32(gx)), _ptr(_cuda_f32(gy)), _ptr(_cuda_f32(pdiv)),
+                                 *[_ptr(st[k]) for k in ("vx", "vy", "ux", "uy", "vpx", "vpy", "gpx", "gpy")],
+                                 float(coef), float(alpha0), 1 if first else 0, *[float(b) for b in bounds],
+                                 _ptr(alpha_out), _stream(stream)), self.h)
 
     # ----------------------------------------------------------- tooling
     def profile(self, on=True):

@@ -39,19 +39,42 @@ def test_density_of_one_cell_is_its_gaussian_integrated_over_each_bin():
 
 @pytest.mark.parametrize("pos", [(60.0, 70.0), (3.0, 2.0), (119.5, 139.0)])
 def test_density_mass_is_the_window_mass(pos):
-    # the cell's area times the normal mass over its window, clipped to the die
+    # the cell's area times the normal mass over its whole window: what falls
+    # off the die is reflected back in, none is lost
     g = _grid()
     xc, yc = pos
     a = 1.75
     r = ref.density([xc], [yc], [a], [0], g)
     bx = min(max(int(xc // g["bw"]), 0), g["gx"] - 1)
     by = min(max(int(yc // g["bh"]), 0), g["gy"] - 1)
-    lo_x, hi_x = max(bx - g["R"], 0) * g["bw"], min(bx + g["R"] + 1, g["gx"]) * g["bw"]
-    lo_y, hi_y = max(by - g["R"], 0) * g["bh"], min(by + g["R"] + 1, g["gy"]) * g["bh"]
+    lo_x, hi_x = (bx - g["R"]) * g["bw"], (bx + g["R"] + 1) * g["bw"]
+    lo_y, hi_y = (by - g["R"]) * g["bh"], (by + g["R"] + 1) * g["bh"]
     mx = norm.cdf(hi_x, xc, g["bw"]) - norm.cdf(lo_x, xc, g["bw"])
     my = norm.cdf(hi_y, yc, g["bh"]) - norm.cdf(lo_y, yc, g["bh"])
     assert math.isclose(r["dens"].sum(), a * mx * my, rel_tol=1e-12)
     assert r["overflow"] == 0.0 and r["value"] == 0.0  # one cell never fills a bin of capacity 70
+
+
+def test_density_reflects_at_the_die_edges():
+    # near a corner each bin holds the Gaussian plus its mirror image in the
+    # edge (integrated over the bin), the image counting where its source bin
+    # lies inside the window
+    g = _grid()
+    xc, yc, a = 4.25, 9.5, 3.0
+    r = ref.density([xc], [yc], [a], [0], g)
+    bx, by, R = int(xc // g["bw"]), int(yc // g["bh"]), g["R"]
+
+    def axis(i, c, w, b):
+        m = integrate.quad(lambda t: norm.pdf(t, c, w), i * w, (i + 1) * w, epsabs=1e-14)[0]
+        if -1 - i >= b - R:  # the mirrored bin -1 - i is in the window
+            m += integrate.quad(lambda t: norm.pdf(t, -c, w), i * w, (i + 1) * w, epsabs=1e-14)[0]
+        return m if abs(i - b) <= R else 0.0
+
+    for j in range(g["gy"]):
+        for i in range(g["gx"]):
+            want = a * axis(i, xc, g["bw"], bx) * axis(j, yc, g["bh"], by)
+            assert math.isclose(r["dens"][j, i], want, rel_tol=1e-9, abs_tol=1e-14), (i, j, r["dens"][j, i], want)
+    assert r["dens"][0, 0] > r["dens"][0, 1]  # the corner bin gains the most
 
 
 def _cluster(n, seed, g, spread=12.0):
