@@ -231,8 +231,8 @@ def bench_loop(a):
     schedule with beta = 0 (wirelength-driven) and with timing from the start
     iteration every 15 (report_timing_endpoint(n_fail, 1), Eq. 9, PP).  The
     clock period is the one at which 5 % of the endpoints fail at the end of
-    the wirelength-driven run (the design's constraint is set where the plain
-    placer lands), the same for both runs.  Prints the histories (HPWL,
+    the wirelength-driven run (the constraint is set where the plain placer
+    lands), the same for both runs.  Prints the histories (HPWL,
     overflow, WNS, TNS every 20 iterations) and the GPU time per iteration
     with and without a timing refresh."""
     import torch
@@ -252,7 +252,7 @@ def bench_loop(a):
         return lambda r: print(f"[loop] beta={beta} it={r.it} hpwl={r.hpwl:.4g} ovf={r.overflow:.3f} "
                                f"wns={r.wns:.1f} tns={r.tns:.4g} pairs={r.pairs}", file=sys.stderr, flush=True)
 
-    # the wirelength-driven placement sets the clock
+    # the clock: 5 % of the endpoints fail where the wirelength-driven run ends
     nl["clock_period"] = np.float32(1e9)
     p = GlobalPlacer(nl, lib, LoopConfig(die=float(cfg_n.die), bins=bins, beta=0.0, record_every=20))
     p.run()

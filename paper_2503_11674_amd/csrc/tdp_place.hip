@@ -88,15 +88,19 @@ __global__ void __launch_bounds__(DN_BLOCK) k_dn_keys(int n, const float *__rest
   val[c] = (uint32_t)c;
 }
 
-// start[b] = first sorted position with key >= b, for b in [0, G]
+// start[b] = first sorted position with key >= b, for b in [0, G]: a binary
+// search per bin (balanced however crowded the bins are)
 __global__ void __launch_bounds__(DN_BLOCK) k_dn_starts(int n, int G, const uint64_t *__restrict__ key,
                                                          int32_t *__restrict__ start) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s > n) return;
-  const int lo = s == 0 ? -1 : (int)key[s - 1];
-  const int hi = s == n ? G - 1 : (int)key[s];
-  for (int b = lo + 1; b <= hi; ++b) start[b] = s;
-  if (s == n) start[G] = n;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > G) return;
+  int lo = 0, hi = n;  // the answer lies in [lo, hi]
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo) >> 1);
+    if (key[mid] < (uint64_t)b) lo = mid + 1;
+    else hi = mid;
+  }
+  start[b] = lo;
 }
 
 // weights of sorted cell s: w[k * n + s] = a_c Wx(k - R), w[(K + k) * n + s] = Wy(k - R), K = 2R + 1
@@ -258,38 +262,59 @@ __global__ void __launch_bounds__(DN_BLOCK) k_dn_final(const double *__restrict_
   }
 }
 
-// gradient of the penalty on movable cells: += scale * d value / d (x, y)
+// gradient of the penalty on movable cells: += scale * d value / d (x, y).
+// The window's weights and derivatives are evaluated once per axis (2R+1
+// each, in registers: R is a template parameter); the window sum is then
+//   d/dx = 2 a sum_j Wy(j) sum_i Wx'(i) o(i, j),  d/dy likewise.
+template <int R>
 __global__ void __launch_bounds__(DN_BLOCK) k_dn_grad(int n, const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ area,
                                                        const uint8_t *__restrict__ fixed, DensityGrid gr,
                                                        const float *__restrict__ map, float scale,
                                                        float *__restrict__ gx, float *__restrict__ gy) {
+  constexpr int K = 2 * R + 1;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n || fixed[c]) return;
   float fx, fy;
   const int bx = dn_bin(x[c], gr.x0, gr.bw, gr.gx, fx);
   const int by = dn_bin(y[c], gr.y0, gr.bh, gr.gy, fy);
   const float cap = gr.target * gr.bw * gr.bh;
+  float wx[K], dx[K], wy[K], dy[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = bx - R + k, j = by - R + k;
+    wx[k] = dx[k] = wy[k] = dy[k] = 0.f;
+    if (i >= 0 && i < gr.gx) axis_weight(bx, fx, gr.gx, R, i, 1.f / gr.bw, wx[k], dx[k]);
+    if (j >= 0 && j < gr.gy) axis_weight(by, fy, gr.gy, R, j, 1.f / gr.bh, wy[k], dy[k]);
+  }
   float ax = 0.f, ay = 0.f;
-  for (int dj = -gr.R; dj <= gr.R; ++dj) {
-    const int j = by + dj;
+#pragma unroll
+  for (int kj = 0; kj < K; ++kj) {
+    const int j = by - R + kj;
     if (j < 0 || j >= gr.gy) continue;
-    float wy, dy;
-    axis_weight(by, fy, gr.gy, gr.R, j, 1.f / gr.bh, wy, dy);
-    for (int di = -gr.R; di <= gr.R; ++di) {
-      const int i = bx + di;
+    float sx = 0.f, sy = 0.f;
+#pragma unroll
+    for (int ki = 0; ki < K; ++ki) {
+      const int i = bx - R + ki;
       if (i < 0 || i >= gr.gx) continue;
       const float o = map[j * gr.gx + i] - cap;
       if (o <= 0.f) continue;
-      float wx, dx;
-      axis_weight(bx, fx, gr.gx, gr.R, i, 1.f / gr.bw, wx, dx);
-      ax += o * dx * wy;
-      ay += o * wx * dy;
+      sx += o * dx[ki];
+      sy += o * wx[ki];
     }
+    ax += sx * wy[kj];
+    ay += sy * dy[kj];
   }
-  const float k = 2.f * area[c] * scale;
-  gx[c] += k * ax;
-  gy[c] += k * ay;
+  const float k2 = 2.f * area[c] * scale;
+  gx[c] += k2 * ax;
+  gy[c] += k2 * ay;
+}
+
+template <int R>
+static void launch_grad(int n, const float *x, const float *y, const float *area, const uint8_t *fixed,
+                        const DensityGrid &gr, const float *map, float scale, float *gx, float *gy, hipStream_t s) {
+  hipLaunchKernelGGL(k_dn_grad<R>, dim3(nbk(n, DN_BLOCK)), dim3(DN_BLOCK), 0, s, n, x, y, area, fixed, gr, map, scale,
+                     gx, gy);
 }
 
 void density_impl(tdp_graph g, const float *x, const float *y, float scale, double *value, double *overflow,
@@ -304,7 +329,7 @@ void density_impl(tdp_graph g, const float *x, const float *y, float scale, doub
     hipLaunchKernelGGL(k_dn_weights, dim3(nbk(n, DN_BLOCK)), dim3(DN_BLOCK), 0, s, n, (const uint32_t *)g->dn_v0,
                        x, y, (const float *)g->dn_area, gr, g->dn_w);
   }
-  hipLaunchKernelGGL(k_dn_starts, dim3(nbk((long long)n + 1, DN_BLOCK)), dim3(DN_BLOCK), 0, s, n, G,
+  hipLaunchKernelGGL(k_dn_starts, dim3(nbk((long long)G + 1, DN_BLOCK)), dim3(DN_BLOCK), 0, s, n, G,
                      (const uint64_t *)g->dn_k0, g->dn_start);
   float *map = map_out ? map_out : g->dn_map;
   fill_i32(g->dn_nheavy, 1, 0, s);
@@ -316,9 +341,21 @@ void density_impl(tdp_graph g, const float *x, const float *y, float scale, doub
   hipLaunchKernelGGL(k_dn_reduce, dim3(DN_PARTS), dim3(DN_BLOCK), 0, s, gr, (const float *)map, g->dn_part);
   hipLaunchKernelGGL(k_dn_final, dim3(1), dim3(DN_BLOCK), 0, s, (const double *)g->dn_part,
                      g->dn_total_area > 0 ? 1.0 / g->dn_total_area : 0.0, value, overflow);
-  if (gx && gy && n > 0)
-    hipLaunchKernelGGL(k_dn_grad, dim3(nbk(n, DN_BLOCK)), dim3(DN_BLOCK), 0, s, n, x, y, (const float *)g->dn_area,
-                       (const uint8_t *)g->topo.cell_fixed, gr, (const float *)map, scale, gx, gy);
+  if (gx && gy && n > 0) {
+    const float *area = g->dn_area;
+    const uint8_t *fixed = g->topo.cell_fixed;
+    switch (gr.R) {
+      case 0: launch_grad<0>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 1: launch_grad<1>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 2: launch_grad<2>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 3: launch_grad<3>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 4: launch_grad<4>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 5: launch_grad<5>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 6: launch_grad<6>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 7: launch_grad<7>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      default: launch_grad<8>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+    }
+  }
   prof_end(g, TDP_STAGE_DENSITY, s);
 }
 

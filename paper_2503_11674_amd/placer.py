@@ -33,7 +33,12 @@ class LoopConfig:
     utilisation: float = 0.5        # total cell area / die area (equal cell areas)
     wa_gamma: float = 5.0           # um
     lambda_init: float = 0.01       # times |grad WL|_1 / |grad D|_1 at the start
-    lambda_growth: float = 1.025    # per iteration
+    # lambda grows by mu = mu_max ** (1 - dWL / dWL_ref) per iteration, clamped
+    # to [mu_min, mu_max] (ePlace's penalty-factor rule): slower while the
+    # wirelength climbs fast; dWL_ref = wl_ref_frac * the starting wirelength
+    mu_max: float = 1.05
+    mu_min: float = 0.95
+    wl_ref_frac: float = 0.01
     max_iters: int = 600
     stop_overflow: float = 0.1
     # the paper starts timing at iteration 500 of a run of about a thousand;
@@ -100,6 +105,8 @@ class GlobalPlacer:
         self.beta_dev = torch.tensor([cfg.beta], dtype=torch.float64, device=dev)
         self.alpha = torch.zeros(1, dtype=torch.float64, device=dev)
         self.lam = None
+        self.wl_prev = None
+        self.wl_ref = None
         self.a_k = 1.0
         self.it = 0
         self.timing_on = False
@@ -148,7 +155,7 @@ class GlobalPlacer:
             self.timing_refresh()
         self.gx.zero_()
         self.gy.zero_()
-        self.g.wa_fwd_bwd(st["vx"], st["vy"], cfg.wa_gamma, self.gx, self.gy)
+        wl = self.g.wa_fwd_bwd(st["vx"], st["vy"], cfg.wa_gamma, self.gx, self.gy)
         self.g.density(st["vx"], st["vy"], self.lam, self.gx, self.gy)
         if self.timing_on and cfg.beta > 0:
             self.g.p2p_loss_bwd(st["vx"], st["vy"], self.beta_dev, self.gx, self.gy)
@@ -157,7 +164,14 @@ class GlobalPlacer:
         self.g.nesterov_step(st, self.gx, self.gy, self.pdiv, coef, cfg.alpha0, self.it == 0, self.bounds,
                              alpha_out=self.alpha)
         self.a_k = a_n
-        self.lam *= cfg.lambda_growth
+        wl = float(wl)
+        if self.wl_prev is None:
+            mu, self.wl_ref = cfg.mu_max, cfg.wl_ref_frac * abs(wl)
+        else:
+            mu = cfg.mu_max ** (1.0 - (wl - self.wl_prev) / self.wl_ref) if self.wl_ref > 0 else cfg.mu_max
+            mu = min(cfg.mu_max, max(cfg.mu_min, mu))
+        self.wl_prev = wl
+        self.lam *= mu
         self.it += 1
 
     def run(self, iters: Optional[int] = None, log=None) -> List[LoopRecord]:

@@ -176,7 +176,7 @@ def test_placement_loop_spreads_and_is_deterministic(library):
     nl["y"] = (500 + 40 * rng.standard_normal(nl["num_cells"])).astype(np.float32)
     nl["clock_period"] = np.float32(0.0)  # the placer sets 5 % failing at this start
     cfg = LoopConfig(die=1000.0, bins=64, max_iters=120, timing_start=40, timing_every=15, beta=1e-3,
-                     lambda_init=0.1, lambda_growth=1.05, record_every=20, stop_overflow=0.0)
+                     lambda_init=1.0, record_every=20, stop_overflow=0.0)
     runs = []
     for rep in range(2):
         print(f"[loop] run {rep}", flush=True)
