@@ -55,6 +55,7 @@ class LoopConfig:
     record_every: int = 10
     hpwl_gamma: float = 1e-3        # WA at this temperature is the HPWL (um)
     fail_frac: float = 0.05         # clock: this share of endpoints fails at the start
+    lambda_fixed: Optional[float] = None  # a fixed density weight (no growth) instead of the schedule
 
 
 @dataclass
@@ -150,7 +151,7 @@ class GlobalPlacer:
         """One iteration: gradient at the look-ahead point v, Nesterov step."""
         cfg, st = self.cfg, self.st
         if self.lam is None:
-            self.lam = self._lambda0()
+            self.lam = cfg.lambda_fixed if cfg.lambda_fixed is not None else self._lambda0()
         if cfg.beta > 0 and self.it >= cfg.timing_start and (self.it - cfg.timing_start) % cfg.timing_every == 0:
             self.timing_refresh()
         self.gx.zero_()
@@ -171,7 +172,8 @@ class GlobalPlacer:
             mu = cfg.mu_max ** (1.0 - (wl - self.wl_prev) / self.wl_ref) if self.wl_ref > 0 else cfg.mu_max
             mu = min(cfg.mu_max, max(cfg.mu_min, mu))
         self.wl_prev = wl
-        self.lam *= mu
+        if cfg.lambda_fixed is None:
+            self.lam *= mu
         self.it += 1
 
     def run(self, iters: Optional[int] = None, log=None) -> List[LoopRecord]:

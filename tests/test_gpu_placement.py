@@ -192,3 +192,59 @@ def test_placement_loop_spreads_and_is_deterministic(library):
     assert all(np.isfinite(r.hpwl) and np.isfinite(r.tns) for r in h0)
     assert h0[0].pairs == 0 and h0[-1].pairs > 0
     assert np.all((x0 >= 0) & (x0 <= 1000) & (y0 >= 0) & (y0 <= 1000))
+
+
+def test_loop_trajectory_matches_the_oracle_composition(library):
+    """Three iterations of the placer (timing off) against the same loop
+    composed from the oracle's WA, density and Nesterov step: lambda_0 from
+    the gradients' L1 norms, the growth rule, the preconditioner and the
+    Nesterov coefficients all enter."""
+    import math
+
+    from paper_2503_11674_amd.placer import GlobalPlacer, LoopConfig
+    nl = netgen.make_netlist(netgen.CONFIGS["C1"])
+    nl["clock_period"] = np.float32(1e9)
+    cfg = LoopConfig(die=1000.0, bins=32, beta=0.0, record_every=1 << 30)
+    p = GlobalPlacer(nl, library, cfg)
+    p.run(iters=3)
+    gpu_x, gpu_y = (t.cpu().numpy().astype(np.float64) for t in p.positions())
+    alpha_gpu = float(p.alpha)
+    p.g.close()
+    # the oracle composition
+    N = nl["num_cells"]
+    grid = dict(x0=0.0, y0=0.0, bw=1000.0 / 32, bh=1000.0 / 32, gx=32, gy=32, R=3)
+    area = np.full(N, np.float32(0.5 * 1000.0 * 1000.0 / N), np.float32)
+    fixed = np.asarray(nl["cell_fixed"], np.uint8)
+    pins = np.bincount(np.asarray(nl["pin_cell"])[np.asarray(nl["pin_cell"]) >= 0], minlength=N)
+    pdiv = np.maximum(pins, 1).astype(np.float32).astype(np.float64)
+    x0, y0 = np.asarray(nl["x"], np.float64), np.asarray(nl["y"], np.float64)
+    st = {"vx": x0.copy(), "vy": y0.copy(), "ux": x0.copy(), "uy": y0.copy(), "vpx": x0.copy(), "vpy": y0.copy(),
+          "gpx": np.zeros(N), "gpy": np.zeros(N)}
+    _, wgx, wgy = ref.wa(nl, cfg.wa_gamma, st["vx"], st["vy"])
+    d = ref.density(st["vx"], st["vy"], area, fixed, grid, cfg.target)
+    lam = cfg.lambda_init * (np.abs(wgx).sum() + np.abs(wgy).sum()) / (np.abs(d["grad_x"]).sum() + np.abs(d["grad_y"]).sum())
+    a_k, wl_prev, wl_ref = 1.0, None, None
+    for it in range(3):
+        wl, wgx, wgy = ref.wa(nl, cfg.wa_gamma, st["vx"], st["vy"])
+        d = ref.density(st["vx"], st["vy"], area, fixed, grid, cfg.target)
+        gx, gy = wgx + lam * d["grad_x"], wgy + lam * d["grad_y"]
+        a_n = (1 + math.sqrt(4 * a_k * a_k + 1)) / 2
+        alpha = ref.nesterov(st, gx, gy, pdiv, fixed, (a_k - 1) / a_n, cfg.alpha0, it == 0,
+                             (0.0, 1000.0, 0.0, 1000.0))
+        a_k = a_n
+        if wl_prev is None:
+            mu, wl_ref = cfg.mu_max, cfg.wl_ref_frac * abs(wl)
+        else:
+            mu = min(cfg.mu_max, max(cfg.mu_min, cfg.mu_max ** (1 - (wl - wl_prev) / wl_ref)))
+        wl_prev = wl
+        lam *= mu
+    # the step length divides by the change of the gradient between two
+    # nearby points, about 1 % of the gradient here: FP32 rounding of the
+    # two gradients reaches it amplified a hundredfold
+    assert abs(alpha_gpu - alpha) <= 1e-2 * alpha, (alpha_gpu, alpha)
+    # positions: within 1 % of each cell's own move (the step length's
+    # relative error carries into the move) plus FP32 rounding of the position
+    moved = np.abs(st["ux"] - x0) + np.abs(st["uy"] - y0)
+    assert np.median(moved) > 0.1  # the cells did move
+    err = np.abs(gpu_x - st["ux"]) + np.abs(gpu_y - st["uy"])
+    assert np.all(err <= 1e-2 * moved + 1e-3), (err.max(), moved[err.argmax()])
