@@ -235,8 +235,8 @@ def bench_loop(a):
 
     Timing phase (the part of the paper's flow after timing starts): from that
     converged placement, with the clock at which 5 % of its endpoints fail and
-    lambda frozen at its final value, 150 more iterations with beta = 0 and
-    with timing every 15 iterations (report_timing_endpoint(n_fail, 1),
+    lambda frozen at its final value, 150 more iterations of the same
+    optimiser state with beta = 0 and with timing every 15 iterations (report_timing_endpoint(n_fail, 1),
     Eq. 9, PP); HPWL, overflow, WNS, TNS every 15 iterations (a Fig. 5
     analogue).  Also the GPU time per iteration with and without a timing
     refresh."""
@@ -264,7 +264,7 @@ def bench_loop(a):
 
     # global placement, wirelength-driven, to convergence
     nl["clock_period"] = np.float32(1e9)
-    p = GlobalPlacer(nl, lib, LoopConfig(die=die, bins=bins, beta=0.0, record_every=20))
+    p = GlobalPlacer(nl, lib, LoopConfig(die=die, bins=bins, beta=0.0, record_every=15))
     t0 = time.perf_counter()
     hist = p.run(log=log("global"))
     torch.cuda.synchronize()
@@ -272,6 +272,7 @@ def bench_loop(a):
             "history": [[r.it, round(r.hpwl, 1), round(r.overflow, 4)] for r in hist]}
     ux, uy = (t.cpu().numpy().copy() for t in p.positions())
     lam = float(p.lam)
+    snap = p.snapshot()
     p.g.sta_update(*p.positions())
     at = p.g.export()["at"].cpu().numpy()
     ff = np.nonzero(np.asarray(nl["cell_is_ff"]))[0]
@@ -281,13 +282,17 @@ def bench_loop(a):
     print(f"[loop] converged after {glob['iterations']} iterations; clock {T:.1f} ps; lambda {lam:.4g}",
           file=sys.stderr, flush=True)
 
-    # the timing phase from the converged placement
+    # the timing phase: both runs continue the converged run's optimiser state
+    # (positions, previous point and gradient) with lambda frozen and the
+    # momentum sequence restarted
     nl2 = dict(nl, x=ux.astype(np.float32), y=uy.astype(np.float32), clock_period=np.float32(T))
     runs = []
     for beta in (0.0, 1e-3):
-        cfg = LoopConfig(die=die, bins=bins, beta=beta, lambda_fixed=lam, timing_start=0, max_iters=150,
+        cfg = LoopConfig(die=die, bins=bins, beta=beta, lambda_fixed=lam, timing_start=snap["it"], max_iters=150,
                          record_every=15, stop_overflow=-1.0)
         p = GlobalPlacer(nl2, lib, cfg)
+        p.resume(snap)
+        p.a_k = 1.0  # momentum restart: the sequence's coefficient tends to 1 late in a run
         start = p.metrics()
         t0 = time.perf_counter()
         hist = p.run(log=log(f"beta={beta}"))

@@ -192,3 +192,15 @@ class GlobalPlacer:
 
     def positions(self):
         return self.st["ux"], self.st["uy"]
+
+    def snapshot(self) -> Dict:
+        """The optimiser state, to continue from it in another placer."""
+        return {"st": {k: v.clone() for k, v in self.st.items()}, "a_k": self.a_k, "lam": self.lam,
+                "wl_prev": self.wl_prev, "wl_ref": self.wl_ref, "it": self.it}
+
+    def resume(self, snap: Dict):
+        """Continue from a snapshot of a placer over the same design."""
+        for k, v in snap["st"].items():
+            self.st[k].copy_(v)
+        self.a_k, self.lam, self.wl_prev, self.wl_ref, self.it = (snap["a_k"], snap["lam"], snap["wl_prev"],
+                                                                  snap["wl_ref"], snap["it"])
