@@ -283,16 +283,16 @@ def bench_loop(a):
           file=sys.stderr, flush=True)
 
     # the timing phase: both runs continue the converged run's optimiser state
-    # (positions, previous point and gradient) with lambda frozen and the
-    # momentum sequence restarted
+    # (positions, previous point and gradient) with lambda frozen and without
+    # momentum (the predicted step alone: past convergence the momentum
+    # coefficient, near 1, carries the placement away)
     nl2 = dict(nl, x=ux.astype(np.float32), y=uy.astype(np.float32), clock_period=np.float32(T))
     runs = []
     for beta in (0.0, 1e-3):
         cfg = LoopConfig(die=die, bins=bins, beta=beta, lambda_fixed=lam, timing_start=snap["it"], max_iters=150,
-                         record_every=15, stop_overflow=-1.0)
+                         record_every=15, stop_overflow=-1.0, momentum=False)
         p = GlobalPlacer(nl2, lib, cfg)
         p.resume(snap)
-        p.a_k = 1.0  # momentum restart: the sequence's coefficient tends to 1 late in a run
         start = p.metrics()
         t0 = time.perf_counter()
         hist = p.run(log=log(f"beta={beta}"))

@@ -56,6 +56,7 @@ class LoopConfig:
     hpwl_gamma: float = 1e-3        # WA at this temperature is the HPWL (um)
     fail_frac: float = 0.05         # clock: this share of endpoints fails at the start
     lambda_fixed: Optional[float] = None  # a fixed density weight (no growth) instead of the schedule
+    momentum: bool = True           # False: the same predicted step without Nesterov's momentum
 
 
 @dataclass
@@ -161,7 +162,7 @@ class GlobalPlacer:
         if self.timing_on and cfg.beta > 0:
             self.g.p2p_loss_bwd(st["vx"], st["vy"], self.beta_dev, self.gx, self.gy)
         a_n = (1.0 + math.sqrt(4.0 * self.a_k * self.a_k + 1.0)) / 2.0
-        coef = (self.a_k - 1.0) / a_n
+        coef = (self.a_k - 1.0) / a_n if cfg.momentum else 0.0
         self.g.nesterov_step(st, self.gx, self.gy, self.pdiv, coef, cfg.alpha0, self.it == 0, self.bounds,
                              alpha_out=self.alpha)
         self.a_k = a_n
