@@ -339,3 +339,23 @@ def nesterov(state, gx, gy, pdiv, frozen, coef: float, alpha0: float, first: boo
                    _p(state["gpy"]), d(coef), d(alpha0), ctypes.c_int(1 if first else 0),
                    *[d(float(b)) for b in bounds], _p(alpha))
     return float(alpha[0])
+
+
+def sta_early(nl, lib, hold: float = 0.0, x=None, y=None) -> Dict[str, np.ndarray]:
+    """Early arrivals, transitions and arc delays, hold slack at D pins, and
+    {whs, ths, n_hold_fail}."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    P = int(nl["num_pins"])
+    out = {k: np.empty(P, np.float64) for k in ("at", "slew", "darc", "hold_slack")}
+    summ = np.zeros(3, np.float64)
+    na, k1 = _netlist_args(nl)
+    la, k2 = _lib_args(lib)
+    rc = L.ora_sta_early(*na, *la, _p(x), _p(y), ctypes.c_double(float(hold)),
+                         ctypes.c_double(float(nl["input_slew"])), ctypes.c_double(float(nl["clock_slew"])),
+                         _p(out["at"]), _p(out["slew"]), _p(out["darc"]), _p(out["hold_slack"]), _p(summ))
+    if rc != 0:
+        raise ValueError("timing graph has a cycle")
+    out["whs"], out["ths"], out["n_hold_fail"] = float(summ[0]), float(summ[1]), int(summ[2])
+    return out

@@ -20,6 +20,10 @@
  *                  Elmore delay of a star RC net with degraded sink
  *                  transitions (net model section below); cell arcs come
  *                  from slew x load tables.
+ *   ora_sta_early - the early half of an early/late timer: earliest
+ *                  arrivals at best-case transitions and the hold check at
+ *                  the D pins (not used by the paper's objective, which is
+ *                  setup TNS / WNS; a fuller timing model around it).
  *   ora_extract  - report_timing_endpoint(n, k) (Sec. III-B, Table I): the n
  *                  most critical endpoints, and the k worst paths at each.
  *                  Reached by deviation (sidetrack) enumeration from the
@@ -373,6 +377,97 @@ int ora_sta(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double clock
   }
   for (int p = 0; p < P; ++p)
     slack[p] = (rat[p] == INFINITY || at[p] == -INFINITY) ? INFINITY : rat[p] - at[p];
+  conn_free(&c);
+  return 0;
+}
+
+/* Early (hold) analysis on the same timing graph: the other half of an
+ * early/late timer.  Net delays and loads are those of the net model; start
+ * points arrive as in ora_sta; every other pin takes the earliest arrival:
+ *   sink t:         AT_e(t) = AT_e(drv) + dnet(t), transition as ora_sta
+ *                   gives a sink from its driver's (early) transition;
+ *   comb output o:  AT_e(o) = min_j (AT_e(i_j) + d_e(i_j)), d_e(i_j) the
+ *                   delay table at i_j's early transition and o's load;
+ *                   transition = min_j of the transition table (best case).
+ * Hold check at a D pin (ideal clock): hold slack = AT_e - hold.  Outputs
+ * [P]: at_e, slew_e, darc_e (0 off comb inputs), hold_slack (+inf off D pins
+ * and at unreachable D pins); summary = {WHS, THS, number of D pins with
+ * hold slack < 0}, the first two 0 when none violates.  Returns 0, or -1 on
+ * a cycle. */
+int ora_sta_early(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double hold, double input_slew,
+                  double clock_slew, double *at_e, double *slew_e, double *darc_e, double *hold_slack,
+                  double *summary) {
+  FILL_NETLIST(n);
+  FILL_LIB(L);
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  int P = num_pins;
+  double *dnet = (double *)calloc(P, sizeof(double)), *load = (double *)calloc(P, sizeof(double));
+  for (int p = 0; p < P; ++p) { at_e[p] = INFINITY; slew_e[p] = 0; darc_e[p] = 0; hold_slack[p] = INFINITY; }
+  for (int net = 0; net < num_nets; ++net) {
+    int s = net_pins[net_ptr[net]];
+    double xs, ys;
+    pin_xy(&n, x, y, s, &xs, &ys);
+    double ld = 0.0;
+    for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
+      int t = net_pins[k];
+      double xt, yt;
+      pin_xy(&n, x, y, t, &xt, &yt);
+      double len = fabs(xs - xt) + fabs(ys - yt);
+      double cap = (double)pin_cap[cell_type[pin_cell[t]]];
+      dnet[t] = net_delay(&L, len, cap);
+      ld += cap + L.c * len;
+    }
+    load[s] = ld;
+  }
+  for (int q = 0; q < P; ++q) {
+    int p = c.topo[q];
+    switch (c.role[p]) {
+      case ROLE_PORT:
+        at_e[p] = 0.0;
+        slew_e[p] = input_slew;
+        break;
+      case ROLE_FFQ: {
+        int type = cell_type[pin_cell[p]];
+        at_e[p] = lut_eval(&L, delay_lut, type, clock_slew, load[p]);
+        slew_e[p] = lut_eval(&L, slew_lut, type, clock_slew, load[p]);
+        break;
+      }
+      case ROLE_CIN:
+      case ROLE_FFD:
+        if (c.driver[p] >= 0 && at_e[c.driver[p]] != INFINITY) {
+          at_e[p] = at_e[c.driver[p]] + dnet[p];
+          slew_e[p] = sink_slew(&L, slew_e[c.driver[p]], dnet[p]);
+        }
+        break;
+      case ROLE_COUT: {
+        int cell = pin_cell[p], type = cell_type[cell];
+        double best = INFINITY, sl = INFINITY;
+        for (int k = cell_in_ptr[cell]; k < cell_in_ptr[cell + 1]; ++k) {
+          int i = cell_in_pins[k];
+          if (at_e[i] == INFINITY) continue;
+          double d = lut_eval(&L, delay_lut, type, slew_e[i], load[p]);
+          double so = lut_eval(&L, slew_lut, type, slew_e[i], load[p]);
+          darc_e[i] = d;
+          if (at_e[i] + d < best) best = at_e[i] + d;
+          if (so < sl) sl = so;
+        }
+        at_e[p] = best;
+        slew_e[p] = best == INFINITY ? 0.0 : sl;
+        break;
+      }
+    }
+  }
+  double whs = 0.0, ths = 0.0;
+  long nfail = 0;
+  for (int p = 0; p < P; ++p)
+    if (c.role[p] == ROLE_FFD && at_e[p] != INFINITY) {
+      double h = at_e[p] - hold;
+      hold_slack[p] = h;
+      if (h < 0) { nfail++; ths += h; if (h < whs) whs = h; }
+    }
+  summary[0] = whs; summary[1] = ths; summary[2] = (double)nfail;
+  free(dnet); free(load);
   conn_free(&c);
   return 0;
 }
