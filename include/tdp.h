@@ -292,6 +292,29 @@ tdp_status tdp_wa_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float g
 tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph, float gamma_um, double *d_wl, float *d_gx, float *d_gy,
                                     hipStream_t);
 
+/* ------------------------------------------------ early (hold) analysis */
+/* The early half of an early/late timer, on the net delays and loads of the
+ * last tdp_sta_update (TDP_E_STATE before one).  Start points arrive as in
+ * the late analysis; a sink at its driver's early arrival plus the net delay
+ * (transition from the driver's early transition as the net model gives
+ * it); a combinational output at the minimum over its inputs of (arrival +
+ * table delay at the input's early transition and the output's load), with
+ * the minimum of the table transitions.  Hold check at a D pin (ideal
+ * clock): hold slack = early arrival - hold_ps.  Not part of the paper's
+ * objective (setup TNS / WNS).  Asynchronous; the first call allocates its
+ * arrays. */
+tdp_status tdp_sta_update_early(tdp_graph, float hold_ps, hipStream_t);
+/* WHS (minimum hold slack over D pins, 0 if none is negative), THS (sum of
+ * the negative ones) and their count, over every D pin of the graph;
+ * synchronises.  TDP_E_STATE before tdp_sta_update_early. */
+tdp_status tdp_sta_early_summary(tdp_graph, double *whs, double *ths, int32_t *n_fail, hipStream_t);
+/* Device double arrays [num_pins], any may be NULL: early arrival and
+ * transition (at a sink, the one its cell arc or hold check sees), early
+ * arc delay at combinational inputs (0 elsewhere), hold slack at D pins
+ * (+inf elsewhere). */
+tdp_status tdp_sta_early_export(tdp_graph, double *d_at, double *d_slew, double *d_darc, double *d_hold_slack,
+                                hipStream_t);
+
 /* ------------------------------------------------ placement loop pieces */
 /* The placer around the hot path (Sec. IV) minimises wirelength + lambda *
  * density (Eq. 1) + beta * PP (Eq. 6) with Nesterov's method.  The paper does

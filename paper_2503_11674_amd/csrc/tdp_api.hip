@@ -609,6 +609,45 @@ tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph g, float gamma, double *wl, float 
   return check_launch(g, "wa_fwd_bwd_at_update");
 }
 
+tdp_status tdp_sta_update_early(tdp_graph g, float hold_ps, hipStream_t s) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (!std::isfinite(hold_ps)) return fail(g, TDP_E_INVALID, "hold time not finite");
+  if (!g->ea_as) {
+    const Topo &T = g->topo;
+    const size_t es = g->esz;
+    const bool ok = dalloc(g, g->ea_as, std::max(T.M, 1), 2 * es) && dalloc(g, g->ea_at, std::max(T.S, 1), es) &&
+                    dalloc(g, g->ea_darc, std::max(T.A, 1), es) && dalloc(g, g->ea_part, 3 * early_parts()) &&
+                    dalloc(g, g->ea_summary, 3);
+    if (!ok) return fail(g, TDP_E_NOMEM, "early analysis: device allocation failed");
+  }
+  g->ea_hold = hold_ps;
+  dispatch(g, [&](auto z) { early_impl<decltype(z)>(g, hold_ps, s); });
+  g->ea_ready = true;
+  return check_launch(g, "sta_update_early");
+}
+
+tdp_status tdp_sta_early_summary(tdp_graph g, double *whs, double *ths, int32_t *n_fail, hipStream_t s) {
+  GUARD(g);
+  if (!g->ea_ready) return fail(g, TDP_E_STATE, "no early update yet");
+  double h[3];
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(h, g->ea_summary, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "early summary copy failed");
+  if (whs) *whs = h[0];
+  if (ths) *ths = h[1];
+  if (n_fail) *n_fail = (int32_t)h[2];
+  return TDP_OK;
+}
+
+tdp_status tdp_sta_early_export(tdp_graph g, double *d_at, double *d_slew, double *d_darc, double *d_hold_slack,
+                                hipStream_t s) {
+  GUARD(g);
+  if (!g->ea_ready) return fail(g, TDP_E_STATE, "no early update yet");
+  dispatch(g, [&](auto z) { early_export_impl<decltype(z)>(g, d_at, d_slew, d_darc, d_hold_slack, s); });
+  return check_launch(g, "sta_early_export");
+}
+
 tdp_status tdp_density_setup(tdp_graph g, const tdp_density_grid *grid, const float *h_area) {
   GUARD(g);
   if (!grid || !h_area) return fail(g, TDP_E_INVALID, "NULL argument");

@@ -57,5 +57,9 @@ void nesterov_impl(tdp_graph g, const float *gx, const float *gy, const float *p
                    float xlo, float xhi, float ylo, float yhi, double *alpha_out, hipStream_t s);
 void abs_sum_impl(tdp_graph g, const float *a, const float *b, double *out, hipStream_t s);
 int density_parts();
+template <typename T> void early_impl(tdp_graph g, float hold, hipStream_t s);
+template <typename T>
+void early_export_impl(tdp_graph g, double *at, double *slew, double *darc, double *hold_slack, hipStream_t s);
+int early_parts();
 
 }  // namespace tdp

@@ -304,6 +304,13 @@ struct tdp_graph_s {
   float st_gamma = 0;
   const float *st_x = nullptr, *st_y = nullptr;
 
+  // early (hold) analysis, allocated by its first call: packed {arrival,
+  // transition} per driver, arrival per sink, arc delay per comb input
+  void *ea_as = nullptr, *ea_at = nullptr, *ea_darc = nullptr;
+  double *ea_part = nullptr, *ea_summary = nullptr;
+  float ea_hold = 0;
+  bool ea_ready = false;
+
   // density term and Nesterov steps (tdp_density_setup)
   bool dn_ready = false;
   tdp::DensityGrid dn{};

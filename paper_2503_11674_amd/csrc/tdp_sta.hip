@@ -30,23 +30,6 @@
 
 namespace tdp {
 
-// {arrival, transition} of a driver, one load in the forward gathers
-template <typename T> struct vec2_of;
-template <> struct vec2_of<float> { using type = float2; };
-template <> struct vec2_of<double> { using type = double2; };
-template <typename T> using V2 = typename vec2_of<T>::type;
-template <typename T>
-__device__ __forceinline__ V2<T> v2(T a, T b) {
-  V2<T> w;
-  w.x = a;
-  w.y = b;
-  return w;
-}
-
-template <typename T> __device__ __forceinline__ T pos_inf();
-template <> __device__ __forceinline__ float pos_inf<float>() { return __builtin_huge_valf(); }
-template <> __device__ __forceinline__ double pos_inf<double>() { return __builtin_huge_val(); }
-
 __device__ __forceinline__ void stage_lut(const LutView &L, float *s_lut) {
   // two float4 loads in flight per thread before their LDS writes (one
   // memory latency for the usual table sizes)

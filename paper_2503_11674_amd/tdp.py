@@ -99,6 +99,9 @@ tdp_stns_fwd = _sig("tdp_stns_fwd", _p, _p, _p, _f32, _p, _p)
 tdp_stns_bwd = _sig("tdp_stns_bwd", _p, _p, _p, _p, _p)
 tdp_wa_fwd_bwd = _sig("tdp_wa_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p)
 tdp_wa_fwd_bwd_at_update = _sig("tdp_wa_fwd_bwd_at_update", _p, _f32, _p, _p, _p, _p)
+tdp_sta_update_early = _sig("tdp_sta_update_early", _p, _f32, _p)
+tdp_sta_early_summary = _sig("tdp_sta_early_summary", _p, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i32), _p)
+tdp_sta_early_export = _sig("tdp_sta_early_export", _p, _p, _p, _p, _p, _p)
 tdp_density_setup = _sig("tdp_density_setup", _p, _P(tdp_density_grid), _p)
 tdp_density_fwd_bwd = _sig("tdp_density_fwd_bwd", _p, _p, _p, _f32, _p, _p, _p, _p, _p, _p)
 tdp_nesterov_step = _sig("tdp_nesterov_step", _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, ctypes.c_double,
@@ -121,7 +124,8 @@ EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destro
             "tdp_extract_paths", "tdp_report_timing", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
             "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
-            "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_wa_fwd_bwd_at_update", "tdp_density_setup",
+            "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_wa_fwd_bwd_at_update", "tdp_sta_update_early",
+            "tdp_sta_early_summary", "tdp_sta_early_export", "tdp_density_setup",
             "tdp_density_fwd_bwd", "tdp_nesterov_step", "tdp_abs_sum", "tdp_profile_enable", "tdp_profile_read", "tdp_set_tuning",
             "tdp_autotune", "tdp_graph_info", "tdp_status_str", "tdp_last_error"]
 
@@ -381,6 +385,26 @@ class TimingGraph:
         """WA at the positions of the last sta_update (unchanged since)."""
         out = _scalar_out(out, gx.device)
         _check(tdp_wa_fwd_bwd_at_update(self.h, gamma, _ptr(out), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
+        return out
+
+    # ------------------------------------------------ early (hold) analysis
+    def sta_update_early(self, hold: float = 0.0, stream=None):
+        """Early arrivals and hold slacks from the last sta_update's net delays."""
+        _check(tdp_sta_update_early(self.h, float(hold), _stream(stream)), self.h)
+
+    def early_summary(self, stream=None):
+        """(WHS, THS, number of D pins with negative hold slack)."""
+        w, t, n = ctypes.c_double(), ctypes.c_double(), _i32()
+        _check(tdp_sta_early_summary(self.h, ctypes.byref(w), ctypes.byref(t), ctypes.byref(n), _stream(stream)),
+               self.h)
+        return w.value, t.value, n.value
+
+    def early_export(self, stream=None) -> Dict[str, torch.Tensor]:
+        dev = torch.device("cuda", self.device)
+        out = {k: torch.empty(self.num_pins, dtype=torch.float64, device=dev)
+               for k in ("at", "slew", "darc", "hold_slack")}
+        _check(tdp_sta_early_export(self.h, *[_ptr(out[k]) for k in ("at", "slew", "darc", "hold_slack")],
+                                    _stream(stream)), self.h)
         return out
 
     # ------------------------------------------------ placement loop pieces
