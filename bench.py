@@ -332,8 +332,8 @@ def bench_loop(a):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU layout is described in "
-              f"DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}): independent designs or placement snapshots would "
+              f"shard one per GPU, and that layout is not built.", file=sys.stderr)
         sys.exit(2)
     import torch
 
