@@ -187,13 +187,21 @@ __global__ void __launch_bounds__(DN_BLOCK) k_dn_bins(int n, DensityGrid gr, con
     heavy[atomicAdd(n_heavy, 1)] = b;  // summed by k_dn_heavy
     return;
   }
+  // rows in order; within a row, source bins (and so cells) in sorted
+  // order, each bin's x-weight column fixed by its offset from bin i
   double d = 0.0;
   for (int dj = -R; dj <= R; ++dj) {
     const int sj = j - dj;
     if (sj < 0 || sj >= gr.gy) continue;
-    int s0, s1;
-    window_row(gr, start, i, sj, s0, s1);
-    for (int s = s0; s < s1; ++s) d += dn_term(gr, key, w, n, K, i, sj, dj, s);
+    const float *wy = w + (size_t)(K + dj + R) * n;
+    const int lo = i - R > 0 ? i - R : 0, hi = i + R < gr.gx - 1 ? i + R : gr.gx - 1;
+    int s0 = start[sj * gr.gx + lo];
+    for (int si = lo; si <= hi; ++si) {
+      const int s1 = start[sj * gr.gx + si + 1];
+      const float *wx = w + (size_t)(i - si + R) * n;
+      for (int s = s0; s < s1; ++s) d += (double)(wx[s] * wy[s]);
+      s0 = s1;
+    }
   }
   map[b] = (float)d;
 }
