@@ -11,7 +11,9 @@ loop.
 Every vector operation runs in the library's kernels (wirelength, density,
 pair loss, the Nesterov step, timing); this module sequences the calls and
 keeps the host-side scalars (lambda, the Nesterov coefficients, the
-iteration count).
+iteration count).  Lambda's growth rule reads the wirelength back every
+iteration (one synchronisation per iteration; the step length itself stays
+on the device).
 """
 import math
 from dataclasses import dataclass, field
