@@ -274,15 +274,20 @@ __global__ void __launch_bounds__(DN_BLOCK) k_dn_final(const double *__restrict_
 // The window's weights and derivatives are evaluated once per axis (2R+1
 // each, in registers: R is a template parameter); the window sum is then
 //   d/dx = 2 a sum_j Wy(j) sum_i Wx'(i) o(i, j),  d/dy likewise.
+// Threads take the cells in bin order, so that a wave's windows overlap and
+// share the map's cache lines.
 template <int R>
-__global__ void __launch_bounds__(DN_BLOCK) k_dn_grad(int n, const float *__restrict__ x, const float *__restrict__ y,
+__global__ void __launch_bounds__(DN_BLOCK) k_dn_grad(int n, const uint32_t *__restrict__ order,
+                                                       const float *__restrict__ x, const float *__restrict__ y,
                                                        const float *__restrict__ area,
                                                        const uint8_t *__restrict__ fixed, DensityGrid gr,
                                                        const float *__restrict__ map, float scale,
                                                        float *__restrict__ gx, float *__restrict__ gy) {
   constexpr int K = 2 * R + 1;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n || fixed[c]) return;
+  const int si = blockIdx.x * blockDim.x + threadIdx.x;
+  if (si >= n) return;
+  const int c = (int)order[si];
+  if (fixed[c]) return;
   float fx, fy;
   const int bx = dn_bin(x[c], gr.x0, gr.bw, gr.gx, fx);
   const int by = dn_bin(y[c], gr.y0, gr.bh, gr.gy, fy);
@@ -319,10 +324,11 @@ __global__ void __launch_bounds__(DN_BLOCK) k_dn_grad(int n, const float *__rest
 }
 
 template <int R>
-static void launch_grad(int n, const float *x, const float *y, const float *area, const uint8_t *fixed,
-                        const DensityGrid &gr, const float *map, float scale, float *gx, float *gy, hipStream_t s) {
-  hipLaunchKernelGGL(k_dn_grad<R>, dim3(nbk(n, DN_BLOCK)), dim3(DN_BLOCK), 0, s, n, x, y, area, fixed, gr, map, scale,
-                     gx, gy);
+static void launch_grad(int n, const uint32_t *order, const float *x, const float *y, const float *area,
+                        const uint8_t *fixed, const DensityGrid &gr, const float *map, float scale, float *gx,
+                        float *gy, hipStream_t s) {
+  hipLaunchKernelGGL(k_dn_grad<R>, dim3(nbk(n, DN_BLOCK)), dim3(DN_BLOCK), 0, s, n, order, x, y, area, fixed, gr, map,
+                     scale, gx, gy);
 }
 
 void density_impl(tdp_graph g, const float *x, const float *y, float scale, double *value, double *overflow,
@@ -352,16 +358,17 @@ void density_impl(tdp_graph g, const float *x, const float *y, float scale, doub
   if (gx && gy && n > 0) {
     const float *area = g->dn_area;
     const uint8_t *fixed = g->topo.cell_fixed;
+    const uint32_t *order = g->dn_v0;  // cell ids in bin order (this call's sort)
     switch (gr.R) {
-      case 0: launch_grad<0>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      case 1: launch_grad<1>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      case 2: launch_grad<2>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      case 3: launch_grad<3>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      case 4: launch_grad<4>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      case 5: launch_grad<5>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      case 6: launch_grad<6>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      case 7: launch_grad<7>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
-      default: launch_grad<8>(n, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 0: launch_grad<0>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 1: launch_grad<1>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 2: launch_grad<2>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 3: launch_grad<3>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 4: launch_grad<4>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 5: launch_grad<5>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 6: launch_grad<6>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      case 7: launch_grad<7>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
+      default: launch_grad<8>(n, order, x, y, area, fixed, gr, map, scale, gx, gy, s); break;
     }
   }
   prof_end(g, TDP_STAGE_DENSITY, s);
