@@ -466,6 +466,21 @@ def main():
         e1.record()
         e1.synchronize()
         pair_ms[name] = round(e0.elapsed_time(e1) / 20, 4)
+    # the early (hold) analysis on the same update, outside the step: the hold
+    # time at which 5 % of the D pins fail
+    g.sta_update_early(0.0)
+    at_e = g.early_export()["at"].cpu().numpy()
+    hold = float(np.quantile(at_e[ep], 0.05))
+    g.sta_update_early(hold)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        g.sta_update_early(hold)
+    e1.record()
+    e1.synchronize()
+    whs, ths, n_hold = g.early_summary()
+    early = {"ms": round(e0.elapsed_time(e1) / 10, 4), "hold_ps": round(hold, 1), "whs": round(whs, 1),
+             "ths": round(ths, 1), "n_hold_fail": n_hold}
 
     sta_ms = sum(stages[s]["ms"] for s in ("netpass", "forward", "endpoint", "backward") if s in stages)
     ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
@@ -504,6 +519,7 @@ def main():
         "p2p_fwd_bwd_GBps": round((sb["p2p_fwd"] + sb["p2p_bwd"]) / (loss_ms * 1e-3) / 1e9, 2) if loss_ms else None,
         "stages": stages,
         "pair_losses_ms": pair_ms,
+        "early_analysis": early,
         "roofline": roof,
         "graph_replay": bool(graph is not None),
         "streams": 1 if a.serial else 3,
