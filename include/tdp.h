@@ -13,7 +13,13 @@
  *      (Sec. III-D), and the pin-to-pin loss PP = sum w * Q (Eqs. 8, 10) with
  *      its gradient on cell positions;
  * plus a log-sum-exp smoothed TNS with its adjoint, weighted-average
- * wirelength (the WL term of Eq. 1) and a batched form over many designs.
+ * wirelength (the WL term of Eq. 1), the Manhattan and Euclidean pair losses
+ * that Sec. III-C compares PP with, report_timing(K) (the K worst paths of the
+ * design, Table I), a batched form over many designs, and a fuller timing
+ * model around the paper's (an Elmore net model with degraded transitions,
+ * the early / hold half of an early/late timer); and, for the placement loop
+ * around all of it (Sec. IV), a bin-density term with its gradient and a
+ * Nesterov step.
  *
  * Conventions (every entry point):
  *  - Return a tdp_status; nothing throws across the ABI.  A failed call leaves
