@@ -101,6 +101,12 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   std::string err;
   tdp_status st = build_host_topology(nls, count, lib, H, err);
   if (st != TDP_OK) return fail(nullptr, st, err);
+  // path storage is indexed with 32-bit offsets: up to 2 D + 2 pins per path
+  // and max_k path slots per endpoint
+  if ((int64_t)max_paths * (2 * (int64_t)H.dims.D + 2) > INT32_MAX)
+    return fail(nullptr, TDP_E_INVALID, "max_paths * (2 depth + 2) exceeds 2^31 - 1 path pins");
+  if ((int64_t)H.dims.E * max_k > INT32_MAX)
+    return fail(nullptr, TDP_E_INVALID, "endpoints * max_k exceeds 2^31 - 1 path slots");
   // the tables are staged in LDS by the forward sweep
   if ((size_t)lib->num_types * (lib->n_slew + lib->n_load + 2 * lib->n_slew * lib->n_load) > 8192)
     return fail(nullptr, TDP_E_UNSUPPORTED, "library tables exceed 32 KB");
@@ -132,7 +138,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   g->max_out = max_paths;
   g->max_out_inst = per_inst_paths;
   g->slot_cap = std::max(1, T.E * max_k);
-  g->pin_cap = max_paths * (2 * T.D + 2);
+  g->pin_cap = (int32_t)((int64_t)max_paths * (2 * T.D + 2));
   g->key_bits32 = T.num_inst <= 1 ? 32 : (T.num_inst <= 256 ? 40 : 48);
   int max_inst_e = 1;
   for (int i = 0; i < T.num_inst; ++i) max_inst_e = std::max(max_inst_e, H.lv.ep_base[i + 1] - H.lv.ep_base[i]);
@@ -299,6 +305,7 @@ tdp_status tdp_sta_set_clock(tdp_graph g, float period, float setup) {
 tdp_status tdp_sta_update(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   GUARD(g);
   if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
+  g->ea_ready = false;  // the hold results belong to the previous placement
   dispatch(g, [&](auto z) {
     sta_arrivals_impl<decltype(z)>(g, x, y, s);
     sta_required_impl<decltype(z)>(g, s);
@@ -311,6 +318,7 @@ tdp_status tdp_sta_update(tdp_graph g, const float *x, const float *y, hipStream
 tdp_status tdp_sta_update_arrivals(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   GUARD(g);
   if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
+  g->ea_ready = false;
   dispatch(g, [&](auto z) { sta_arrivals_impl<decltype(z)>(g, x, y, s); });
   tdp_status st = check_launch(g, "sta_update_arrivals");
   if (st == TDP_OK) g->updated = true;

@@ -156,9 +156,13 @@ def _stream(stream=None) -> int:
     return stream.cuda_stream
 
 
-def _cuda_f32(t: torch.Tensor) -> torch.Tensor:
-    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+def _cuda_f32(t: torch.Tensor, n: Optional[int] = None) -> torch.Tensor:
+    """A contiguous float32 CUDA tensor, of n elements when n is given (the
+    kernels index it by cell and would otherwise read or write past its end)."""
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
         raise ValueError("expected a contiguous float32 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements (one per cell), got {t.numel()}")
     return t
 
 
@@ -238,15 +242,21 @@ class TimingGraph:
         except Exception:
             pass
 
+    def _cells(self, t, optional: bool = False):
+        """A per-cell float32 device tensor of this graph (positions, gradients)."""
+        if t is None and optional:
+            return None
+        return _cuda_f32(t, self.num_cells)
+
     # ------------------------------------------------------------- STA
     def set_clock(self, period: float, setup: float = 0.0):
         _check(tdp_sta_set_clock(self.h, period, setup), self.h)
 
     def sta_update(self, x: torch.Tensor, y: torch.Tensor, stream=None):
-        _check(tdp_sta_update(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _stream(stream)), self.h)
+        _check(tdp_sta_update(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), _stream(stream)), self.h)
 
     def sta_update_arrivals(self, x: torch.Tensor, y: torch.Tensor, stream=None):
-        _check(tdp_sta_update_arrivals(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _stream(stream)), self.h)
+        _check(tdp_sta_update_arrivals(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), _stream(stream)), self.h)
 
     def sta_update_required(self, stream=None):
         _check(tdp_sta_update_required(self.h, _stream(stream)), self.h)
@@ -349,42 +359,45 @@ class TimingGraph:
     # ----------------------------------------------------------- losses
     def p2p_loss_fwd(self, x, y, out=None, stream=None) -> torch.Tensor:
         out = _scalar_out(out, x.device)
-        _check(tdp_p2p_loss_fwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _ptr(out), _stream(stream)), self.h)
+        _check(tdp_p2p_loss_fwd(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), _ptr(out), _stream(stream)), self.h)
         return out
 
     def p2p_loss_bwd(self, x, y, gout, gx, gy, stream=None):
-        _check(tdp_p2p_loss_bwd(self.h, _ptr(x), _ptr(y), _ptr(_f64_scalar(gout)), _ptr(gx), _ptr(gy),
-                                _stream(stream)), self.h)
+        _check(tdp_p2p_loss_bwd(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), _ptr(_f64_scalar(gout)),
+                                _ptr(self._cells(gx)), _ptr(self._cells(gy)), _stream(stream)), self.h)
 
     def pair_loss_fwd(self, kind: int, x, y, out=None, stream=None) -> torch.Tensor:
         """kind 0: PP (quadratic); 1: Manhattan; 2: linear Euclidean."""
         out = _scalar_out(out, x.device)
-        _check(tdp_pair_loss_fwd(self.h, kind, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), _ptr(out), _stream(stream)),
-               self.h)
+        _check(tdp_pair_loss_fwd(self.h, kind, _ptr(self._cells(x)), _ptr(self._cells(y)), _ptr(out),
+                                 _stream(stream)), self.h)
         return out
 
     def pair_loss_bwd(self, kind: int, x, y, gout, gx, gy, stream=None):
-        _check(tdp_pair_loss_bwd(self.h, kind, _ptr(x), _ptr(y), _ptr(_f64_scalar(gout)), _ptr(gx), _ptr(gy),
-                                 _stream(stream)), self.h)
+        _check(tdp_pair_loss_bwd(self.h, kind, _ptr(self._cells(x)), _ptr(self._cells(y)), _ptr(_f64_scalar(gout)),
+                                 _ptr(self._cells(gx)), _ptr(self._cells(gy)), _stream(stream)), self.h)
 
     def stns_fwd(self, x, y, gamma: float = 10.0, out=None, stream=None) -> torch.Tensor:
         out = _scalar_out(out, x.device)
-        _check(tdp_stns_fwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _stream(stream)), self.h)
+        _check(tdp_stns_fwd(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), gamma, _ptr(out), _stream(stream)),
+               self.h)
         return out
 
     def stns_bwd(self, gout, gx, gy, stream=None):
-        _check(tdp_stns_bwd(self.h, _ptr(_f64_scalar(gout)), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
+        _check(tdp_stns_bwd(self.h, _ptr(_f64_scalar(gout)), _ptr(self._cells(gx)), _ptr(self._cells(gy)),
+                            _stream(stream)), self.h)
 
     def wa_fwd_bwd(self, x, y, gamma: float, gx, gy, out=None, stream=None) -> torch.Tensor:
         out = _scalar_out(out, x.device)
-        _check(tdp_wa_fwd_bwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), gamma, _ptr(out), _ptr(gx), _ptr(gy),
-                              _stream(stream)), self.h)
+        _check(tdp_wa_fwd_bwd(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), gamma, _ptr(out),
+                              _ptr(self._cells(gx)), _ptr(self._cells(gy)), _stream(stream)), self.h)
         return out
 
     def wa_fwd_bwd_at_update(self, gamma: float, gx, gy, out=None, stream=None) -> torch.Tensor:
         """WA at the positions of the last sta_update (unchanged since)."""
         out = _scalar_out(out, gx.device)
-        _check(tdp_wa_fwd_bwd_at_update(self.h, gamma, _ptr(out), _ptr(gx), _ptr(gy), _stream(stream)), self.h)
+        _check(tdp_wa_fwd_bwd_at_update(self.h, gamma, _ptr(out), _ptr(self._cells(gx)), _ptr(self._cells(gy)),
+                                        _stream(stream)), self.h)
         return out
 
     # ------------------------------------------------ early (hold) analysis
@@ -425,14 +438,15 @@ class TimingGraph:
         mp = None
         if want_map:
             mp = torch.empty(int(self._grid_bins()), dtype=torch.float32, device=x.device)
-        _check(tdp_density_fwd_bwd(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), float(scale), _ptr(val),
-                                   val.data_ptr() + 8, _ptr(gx), _ptr(gy), _ptr(mp), _stream(stream)), self.h)
+        _check(tdp_density_fwd_bwd(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), float(scale), _ptr(val),
+                                   val.data_ptr() + 8, _ptr(self._cells(gx, True)), _ptr(self._cells(gy, True)),
+                                   _ptr(mp), _stream(stream)), self.h)
         return (val[0], val[1], mp) if want_map else (val[0], val[1])
 
     def abs_sum(self, a, b, out=None, stream=None) -> torch.Tensor:
         """sum |a| + |b| over cells (device double)."""
         out = _scalar_out(out, a.device)
-        _check(tdp_abs_sum(self.h, _ptr(_cuda_f32(a)), _ptr(_cuda_f32(b)), _ptr(out), _stream(stream)), self.h)
+        _check(tdp_abs_sum(self.h, _ptr(self._cells(a)), _ptr(self._cells(b)), _ptr(out), _stream(stream)), self.h)
         return out
 
     def _grid_bins(self):
@@ -445,8 +459,8 @@ class TimingGraph:
         """One Nesterov step on the state tensors st (vx, vy, ux, uy, vpx, vpy,
         gpx, gpy; updated in place); bounds = (xlo, xhi, ylo, yhi)."""
         for k in ("vx", "vy", "ux", "uy", "vpx", "vpy", "gpx", "gpy"):
-            _cuda_f32(st[k])
-        _check(tdp_nesterov_step(self.h, _ptr(_cuda_f32(gx)), _ptr(_cuda_f32(gy)), _ptr(_cuda_f32(pdiv)),
+            self._cells(st[k])
+        _check(tdp_nesterov_step(self.h, _ptr(self._cells(gx)), _ptr(self._cells(gy)), _ptr(self._cells(pdiv)),
                                  *[_ptr(st[k]) for k in ("vx", "vy", "ux", "uy", "vpx", "vpy", "gpx", "gpy")],
                                  float(coef), float(alpha0), 1 if first else 0, *[float(b) for b in bounds],
                                  _ptr(alpha_out), _stream(stream)), self.h)
@@ -479,7 +493,7 @@ class TimingGraph:
         """Pick the fastest sweep configuration for update + extraction."""
         K = self.max_paths if K is None else K
         ch = np.zeros(3, np.int32)
-        _check(tdp_autotune(self.h, _ptr(_cuda_f32(x)), _ptr(_cuda_f32(y)), n, k, K, reps, ch.ctypes.data,
+        _check(tdp_autotune(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), n, k, K, reps, ch.ctypes.data,
                             _stream(stream)), self.h)
         return {"sweep_mode": int(ch[0]), "flow_waves": int(ch[1]), "us_per_run": int(ch[2])}
 
@@ -523,20 +537,26 @@ def _hip():
     return _hip_lib
 
 
+def _zero_grads(x: torch.Tensor, y: torch.Tensor):
+    """Fresh contiguous gradient buffers (the kernels accumulate into them)."""
+    return (torch.zeros(x.shape, dtype=torch.float32, device=x.device),
+            torch.zeros(y.shape, dtype=torch.float32, device=y.device))
+
+
 class P2PLoss(torch.autograd.Function):
     """PP(x, y) over the graph's current pin-pair set (Eqs. 8, 10)."""
 
     @staticmethod
     def forward(ctx, x, y, graph: TimingGraph):
         ctx.graph = graph
+        x, y = x.contiguous(), y.contiguous()
         ctx.save_for_backward(x, y)
-        return graph.p2p_loss_fwd(x.contiguous(), y.contiguous())
+        return graph.p2p_loss_fwd(x, y)
 
     @staticmethod
     def backward(ctx, gout):
         x, y = ctx.saved_tensors
-        gx = torch.zeros_like(x)
-        gy = torch.zeros_like(y)
+        gx, gy = _zero_grads(x, y)
         ctx.graph.p2p_loss_bwd(x, y, gout, gx, gy)
         return gx, gy, None
 
@@ -548,14 +568,14 @@ class PairLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, y, graph: TimingGraph, kind: int = 0):
         ctx.graph, ctx.kind = graph, kind
+        x, y = x.contiguous(), y.contiguous()
         ctx.save_for_backward(x, y)
-        return graph.pair_loss_fwd(kind, x.contiguous(), y.contiguous())
+        return graph.pair_loss_fwd(kind, x, y)
 
     @staticmethod
     def backward(ctx, gout):
         x, y = ctx.saved_tensors
-        gx = torch.zeros_like(x)
-        gy = torch.zeros_like(y)
+        gx, gy = _zero_grads(x, y)
         ctx.graph.pair_loss_bwd(ctx.kind, x, y, gout, gx, gy)
         return gx, gy, None, None
 
@@ -566,13 +586,13 @@ class SmoothTNS(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, y, graph: TimingGraph, gamma: float = 10.0):
         ctx.graph = graph
+        x, y = x.contiguous(), y.contiguous()
         ctx.save_for_backward(x, y)
-        return graph.stns_fwd(x.contiguous(), y.contiguous(), gamma)
+        return graph.stns_fwd(x, y, gamma)
 
     @staticmethod
     def backward(ctx, gout):
         x, y = ctx.saved_tensors
-        gx = torch.zeros_like(x)
-        gy = torch.zeros_like(y)
+        gx, gy = _zero_grads(x, y)
         ctx.graph.stns_bwd(gout, gx, gy)
         return gx, gy, None, None

@@ -106,3 +106,16 @@ def test_valid_netlist_reaches_the_device_check():
     nl = netgen.make_netlist(netgen.CONFIGS["C1"])
     st, msg = _build_status(nl, netgen.make_library())
     assert st == 4 and "device" in msg
+
+
+def test_path_capacity_that_overflows_32_bits_is_rejected():
+    # path pins are addressed with 32-bit offsets: max_paths * (2 D + 2) must fit
+    from paper_2503_11674_amd import tdp
+    nl, _ = handnets.chain_netlist()
+    nh = tdp._NetlistHolder(nl)
+    lh = tdp._LibraryHolder(handnets.dyadic_library())
+    h = ctypes.c_void_p()
+    st = tdp.tdp_sta_build(ctypes.byref(nh.s), ctypes.byref(lh.s), 0, 1 << 30, 1, 0, ctypes.byref(h))
+    msg = tdp.tdp_last_error(None).decode()
+    assert st == 1 and "max_paths" in msg, (st, msg)
+    assert h.value is None

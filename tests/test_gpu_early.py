@@ -104,4 +104,15 @@ def test_early_needs_an_update(library):
         g.sta_update_early(float("nan"))
     g.sta_update_early(0.0)
     assert g.early_summary() == (0.0, 0.0, 0)  # arrivals are positive: nothing fails a zero hold
+    # a new timing update makes the hold results stale until the next early update
+    g.sta_update(*_xy(nl))
+    with pytest.raises(tdp.TdpError):
+        g.early_summary()
+    with pytest.raises(tdp.TdpError):
+        g.early_export()
+    g.sta_update_arrivals(*_xy(nl))
+    with pytest.raises(tdp.TdpError):
+        g.early_summary()
+    g.sta_update_early(0.0)
+    assert g.early_summary() == (0.0, 0.0, 0)
     g.close()

@@ -407,6 +407,57 @@ def test_pairs_and_p2p(name, library):
     assert float(g.p2p_loss_fwd(c["x"], c["y"])) == l1
 
 
+def test_autograd_on_column_views_of_a_position_matrix(library):
+    # placers keep positions as one [N, 2] tensor; its columns are strided
+    # views, which the autograd Functions must hand to the kernels as
+    # contiguous arrays in both directions
+    tdp = _tdp()
+    c = case("C1", library)
+    nl, st, g, k, K = c["nl"], c["st"], c["g"], c["k"], c["K"]
+    g.pairs_reset()
+    g.extract_paths(n=-1, k=k, K=K)
+    g.pairs_update(rule=0, w0=10.0, w1=0.2)
+    w_gpu, in_gpu = g.pairs_export()
+    sinks = np.nonzero(in_gpu)[0]
+    l_ref, gx_ref, gy_ref = ref.p2p(nl, sinks, w_gpu[sinks].astype(np.float64))
+    scale = _p2p_abs_scale(nl, sinks, w_gpu[sinks])
+    pos = torch.stack([c["x"], c["y"]], dim=1).clone().requires_grad_(True)
+    assert not pos[:, 0].is_contiguous()
+    for fn in (lambda a, b: tdp.P2PLoss.apply(a, b, g), lambda a, b: tdp.PairLoss.apply(a, b, g, 0)):
+        pos.grad = None
+        loss = fn(pos[:, 0], pos[:, 1])
+        loss.backward()
+        assert abs(float(loss) - l_ref) <= 1e-4 * abs(l_ref)
+        gr = pos.grad.cpu().numpy()
+        assert np.all(np.abs(gr[:, 0] - gx_ref) <= 1e-4 * scale + 1e-6)
+        assert np.all(np.abs(gr[:, 1] - gy_ref) <= 1e-4 * scale + 1e-6)
+    # the smoothed TNS through the same views
+    v_ref, sx_ref, sy_ref = ref.stns(nl, library, st, gamma=10.0)
+    pos.grad = None
+    v = tdp.SmoothTNS.apply(pos[:, 0], pos[:, 1], g, 10.0)
+    v.backward()
+    gr = pos.grad.cpu().numpy()
+    sc = np.abs(sx_ref).max()
+    assert np.allclose(gr[:, 0], sx_ref, atol=1e-4 * sc, rtol=1e-3)
+    assert np.allclose(gr[:, 1], sy_ref, atol=1e-4 * sc, rtol=1e-3)
+
+
+def test_per_cell_tensors_are_checked(library):
+    tdp = _tdp()
+    c = case("C1", library)
+    g = c["g"]
+    short = c["x"][:-1].clone()
+    with pytest.raises(ValueError):
+        g.sta_update(short, c["y"])
+    with pytest.raises(ValueError):
+        g.p2p_loss_fwd(c["x"], c["y"].double())
+    gx = torch.zeros_like(c["x"])
+    with pytest.raises(ValueError):
+        g.p2p_loss_bwd(c["x"], c["y"], torch.ones((), dtype=torch.float64, device=_dev()), gx, gx[:-1])
+    with pytest.raises(ValueError):
+        g.wa_fwd_bwd(c["x"], c["y"], 5.0, gx, torch.zeros(2 * g.num_cells, device=_dev())[::2])
+
+
 def _p2p_abs_scale(nl, sinks, w):
     gr = Graph(nl)
     scale = np.zeros(nl["num_cells"])

@@ -414,6 +414,67 @@ def test_stns_chain_equals_hard_tns():
     assert math.isclose(v, -g * math.log1p(math.exp(-s / g)), rel_tol=1e-15)
 
 
+def _lse_diamond(flip):
+    """Port A (0, 0) -> BUF (cell 0, x = 16) -> AND.in0 and A -> AND.in1
+    (AND = cell 1, type 2, x = 48) -> FF (cell 2, x = 80).D; clock 56 ps.
+    Pins: BUF in 0 out 1; AND in0 2 in1 3 out 4; FF D 5 Q 6; port 7.  With
+    flip the AND's two inputs swap nets, so the critical one is in0."""
+    cells = [(0, 1), (2, 2), (7, 1)]
+    a_direct, a_buf = (2, 3) if flip else (3, 2)
+    nets = [(7, [0, a_direct]), (1, [a_buf]), (4, [5]), (6, [])]
+    return handnets.build(cells, 1, nets, [16.0, 48.0, 80.0], [0.0, 0.0, 0.0], port_xy=[(0.0, 0.0)],
+                          clock_period=56.0)[0], a_direct, a_buf
+
+
+@pytest.mark.parametrize("flip", [False, True])
+@pytest.mark.parametrize("g", [10.0, 3.0])
+def test_stns_two_input_closed_form(flip, g):
+    # The smoothed arrival at a two-input cell is m + g ln(1 + exp(-D / g))
+    # (D the gap between the two arrivals through the arcs), and its adjoint
+    # splits the output's sensitivity over the inputs by the softmax weights.
+    # Every value below is worked out by hand from the dyadic library:
+    #   wires: A->BUF 16 um (4 ps), BUF->AND 32 um (16 ps), A->AND 48 um
+    #   (36 ps), AND->FF 32 um (16 ps); loads 2 + 32/4 = 10 fF;
+    #   BUF arc 4 + 10/4 + 10/64 = 6.65625 ps, AND arcs 6 + 2.5 + 10/64.
+    nl, a_direct, a_buf = _lse_diamond(flip)
+    lib = handnets.dyadic_library()
+    st = ref.sta(nl, lib)
+    a_via_buf = 4.0 + 6.65625 + 16.0 + 8.65625   # 35.3125
+    a_dir = 36.0 + 8.65625                        # 44.65625
+    assert st["at"][4] == a_dir and st["crit"][1] == (0 if flip else 1)
+    D = a_dir - a_via_buf
+    at_out = a_dir + g * math.log(1.0 + math.exp(-D / g))
+    s_end = 56.0 - (at_out + 16.0)
+    z = -s_end / g
+    value = -g * (max(z, 0.0) + math.log1p(math.exp(-abs(z))))
+    v, gx, gy = ref.stns(nl, lib, st, gamma=g)
+    assert math.isclose(v, value, rel_tol=4e-15), (v, value)
+    # adjoint: d value / d AT~(FF.D) = -sigmoid(z); softmax split at the AND
+    ab_end = -1.0 / (1.0 + math.exp(-z))
+    w_buf = math.exp((a_via_buf - at_out) / g)
+    w_dir = math.exp((a_dir - at_out) / g)
+    assert math.isclose(w_buf + w_dir, 1.0, rel_tol=1e-14)
+    # d delay / d L = 2 kappa L = L / 32 (kappa = 1/64); every wire runs in
+    # +x from driver to sink, so d L / d x_driver = -1 and d L / d x_sink = +1
+    gx0 = ab_end * w_buf * (16.0 / 32) - ab_end * w_buf * (32.0 / 32)
+    gx1 = ab_end * w_dir * (48.0 / 32) + ab_end * w_buf * (32.0 / 32) - ab_end * (32.0 / 32)
+    gx2 = ab_end * (32.0 / 32)
+    for got, want in zip(gx, (gx0, gx1, gx2)):
+        assert math.isclose(got, want, rel_tol=1e-14, abs_tol=1e-16), (gx, (gx0, gx1, gx2))
+    assert np.all(gy == 0.0)  # every wire is horizontal: sign(0) = 0
+
+
+def test_stns_tends_to_hard_tns_as_gamma_vanishes(c1, library):
+    # g -> 0: the log-sum-exp becomes the maximum and softplus the ramp, so
+    # the smoothed TNS becomes the TNS of Eq. 4
+    nl, st = c1
+    v, _, _ = ref.stns(nl, library, st, gamma=1e-6)
+    assert st["tns"] < 0
+    assert abs(v - st["tns"]) <= 1e-9 * abs(st["tns"]), (v, st["tns"])
+    v1, _, _ = ref.stns(nl, library, st, gamma=1.0)
+    assert v1 < v  # a larger temperature only lowers it (both terms add)
+
+
 def test_stns_bounds_and_fd(c1, library):
     nl, st = c1
     g = 10.0
