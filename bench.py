@@ -66,6 +66,29 @@ def measured_traffic(kernel: str):
         if len(cells) == 5 and cells[0] == kernel:
             return int(float(cells[4]) * 1e6)
     return None
+STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_2m_cells.md")
+
+
+def rocprof_avg_us(kernel: str):
+    """Average dispatch duration of `kernel` in the committed rocprofv3
+    statistics of the 2M-cell step, or None when missing or taken from other
+    sources."""
+    try:
+        text = open(STATS_FILE).read()
+    except OSError:
+        return None
+    if f"Source digest: {source_digest()}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == kernel:
+            try:
+                return float(cells[2])
+            except ValueError:
+                return None
+    return None
+
+
 BETA = 2.5e-5          # weight of the pin-to-pin term in the objective (Sec. IV)
 WA_GAMMA = 5.0
 
@@ -77,6 +100,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C5")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched (40-instance) leg of the default run")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch configuration)")
     ap.add_argument("--sweep-mode", type=int, default=-1, help="force a sweep form (0 per level, 1 dataflow)")
@@ -94,28 +118,53 @@ def parse():
     return ap.parse_args()
 
 
-def stage_bytes(info, counts, side_k):
-    """Algorithmic bytes per stage of one step (float32 values, int32 ids; an
-    array element counts once per pass, a gather counts its element size)."""
+def algo_bytes(info, counts):
+    """Algorithmic bytes per stage of one step: what the method itself must
+    move (float32 values, int32 ids; an array element counts once per pass, a
+    gather counts its element size).  S sink arcs, M nets (drivers), A
+    combinational input pins, N_c combinational cells, E endpoints (= flip-
+    flops), PI primary inputs, K_out paths of Lbar cells (Lbar measured: half
+    the pins per path), Q unique pairs, T touched cells.
+      net pass 28 S + 28 M; forward 24 A + 18 N_c + 16 (E + FF + PI);
+      endpoint / select 12 E; backward 28 S + 16 M;
+      extraction 13 K_out Lbar + 12 K_out; p2p forward + backward 36 Q + 8 T;
+      WA forward + backward 16 P + 4 M + 8 N.
+    The pair update has no such figure; its bytes follow the kernels' reads
+    and writes of the occurrences and of the pair tables."""
+    N, P, M, D, E, n_start, n_comb, S = info
+    A = S - E
+    PI = n_start - E
+    npaths, npins = counts["paths"], counts["path_pins"]
+    lbar = npins / (2.0 * npaths) if npaths else 0.0
+    b = {}
+    b["netpass"] = 28 * S + 28 * M
+    b["forward"] = 24 * A + 18 * n_comb + 16 * (E + E + PI)
+    b["endpoint"] = 12 * E
+    b["backward"] = 28 * S + 16 * M
+    ext = 13 * npaths * lbar + 12 * npaths
+    # extraction as one figure, spread over its kernels by what each touches
+    b["select"] = 0
+    b["search"] = 0
+    b["order"] = 12 * npaths
+    b["walk"] = int(13 * npaths * lbar)
+    occ = npins // 2
+    b["pairs"] = 2 * (12 * occ + 8 * npaths) + 9 * S + 76 * counts["pairs"]
+    b["p2p_fwd"] = 36 * counts["pairs"]
+    b["p2p_bwd"] = 8 * counts["touched"]
+    b["wa"] = 16 * P + 4 * M + 8 * N
+    b["_extraction"] = int(ext)
+    return b
+
+
+def design_overhead(info, side_k):
+    """Bytes per step that this design moves beyond the method's own: the
+    forward sweep's per-cell deviation lists (cost and sink per entry) and
+    four-hop walk records and the per-input arrivals it keeps for them; the
+    backward sweep's second copy of the net delays in net-chunk order."""
     N, P, M, D, E, n_start, n_comb, S = info
     A = S - E
     km = side_k if side_k > 1 else 0
-    b = {}
-    b["netpass"] = 28 * M + 28 * S + 12 * n_start
-    b["forward"] = n_comb * (37 + 16 * km) + 24 * A
-    b["endpoint"] = 32 * E
-    b["backward"] = 20 * M + 12 * S + 16 * A
-    nsel, nslots, npaths, npins = counts["nsel"], counts["nslots"], counts["paths"], counts["path_pins"]
-    b["select"] = 16 * E
-    b["search"] = nsel * (16 + counts["k"] * (8 * km + 40))
-    b["order"] = 4 * (24 * nslots) + 28 * nslots + 16 * npaths
-    b["walk"] = 20 * npins + 24 * npaths
-    occ = npins // 2
-    b["pairs"] = 2 * (12 * occ + 8 * npaths) + 9 * S + 36 * counts["pairs"] + 40 * counts["pairs"]
-    b["p2p_fwd"] = 36 * counts["pairs"]
-    b["p2p_bwd"] = 2 * 24 * counts["pairs"] + 36 * counts["touched"]
-    b["wa"] = 36 * P + 8 * M + 28 * N
-    return b
+    return {"forward": n_comb * (8 * km + 64 + 4) + 4 * A, "backward": 4 * S}
 
 
 def build_step(g, x, y, k, K, gx, gy, wl, pp, beta, overlap=True):
@@ -338,7 +387,7 @@ def main():
     import torch
 
     from paper_2503_11674_amd import netgen
-    from paper_2503_11674_amd.tdp import TimingGraph, STAGES
+    from paper_2503_11674_amd.tdp import TimingGraph, STAGES, TdpError
 
     if a.workload == "C4":
         return bench_batch(a)
@@ -385,6 +434,31 @@ def main():
         tune = {"forced_sweep_mode": a.sweep_mode}
     elif not a.no_tune:
         tune = g.autotune(x, y, n=-1, k=k, K=K, reps=3)
+        # the library's autotuner times the update and extraction on one
+        # stream; the step overlaps the required-time pass and WA with them,
+        # so the sweep form is settled on the step itself among the
+        # autotuner's pick and two that leave more of the GPU to the main
+        # stream
+        cands = [(tune["sweep_mode"], tune["flow_waves"], tune["flow_per_cu"]), (3, 1, 1), (0, 4, 1)]
+        step_ms = {}
+        for c in dict.fromkeys(cands):
+            try:
+                g.set_tuning(sweep_mode=c[0], flow_waves=c[1], flow_per_cu=c[2])
+            except TdpError:  # no resident grids for this graph
+                continue
+            for _ in range(2):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                step()
+            torch.cuda.synchronize()
+            step_ms[c] = (time.perf_counter() - t0) / 5 * 1e3
+        best = min(step_ms, key=step_ms.get)
+        g.set_tuning(sweep_mode=best[0], flow_waves=best[1], flow_per_cu=best[2])
+        tune = dict(tune, step_choice={"sweep_mode": best[0], "flow_waves": best[1], "flow_per_cu": best[2]},
+                    step_ms={f"{c[0]}/{c[1]}/{c[2]}": round(v, 4) for c, v in step_ms.items()})
+        tune["sweep_mode"] = best[0]
     if tune:
         print(f"[bench] autotuner: {tune}", file=sys.stderr, flush=True)
     for _ in range(a.warmup):
@@ -408,13 +482,17 @@ def main():
     counts = {"paths": npaths, "path_pins": npins, "pairs": g.pairs_count(), "k": k,
               "nsel": nfail, "nslots": nfail * k, "touched": 0}
     counts["touched"] = 2 * counts["pairs"]
-    sb = stage_bytes(info, counts, g.max_k if g.max_k == 1 else 1 << (g.max_k - 1).bit_length())
+    side_k = g.max_k if g.max_k == 1 else 1 << (g.max_k - 1).bit_length()
+    sb = algo_bytes(info, counts)
+    ov = design_overhead(info, side_k)
     stages = {}
     for s_ in STAGES:
         ms, calls = prof_all.get(s_, (0.0, 0))
         if calls:
             per = ms / calls
-            stages[s_] = {"ms": round(per, 4), "GBps": round(sb.get(s_, 0) / (per * 1e-3) / 1e9, 1)}
+            stages[s_] = {"ms": round(per, 4)}
+            if sb.get(s_):
+                stages[s_]["GBps"] = round(sb[s_] / (per * 1e-3) / 1e9, 1)
     # the dominant kernel: the longest stage on the step's critical path (the
     # calling stream; with overlap the required-time pass and WA run beside it)
     side = () if a.serial else ("backward", "wa")
@@ -486,23 +564,32 @@ def main():
     ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
     loss_ms = sum(stages[s]["ms"] for s in ("p2p_fwd", "p2p_bwd") if s in stages)
     pins = g.num_pins
+    step_gb = sum(v for k_, v in sb.items() if k_ not in ("select", "search", "order", "walk")) / 1e9
     roof = None
     if dom and prof.get(dom, (0.0, 0))[1]:
-        # per-level sweeps launch their kernel once per non-empty level; the
-        # stage time over the launches is the average launch duration
+        # the sweeps launch their kernel once per non-empty level in the
+        # per-level form, once in the resident form; the stage time over its
+        # launches is the average launch duration (with the gaps between the
+        # launches of a per-level sweep)
         mode = (tune or {}).get("sweep_mode", (tune or {}).get("forced_sweep_mode", 0))
-        per_level = dom in ("forward", "backward") and mode == 0
+        flow_dom = (dom == "forward" and mode in (1, 2)) or (dom == "backward" and mode >= 1)
+        per_level = dom in ("forward", "backward") and not flow_dom
         launches = g.depth + 1 if per_level else 1  # forward: D levels + the last level's lists
         names = STAGE_KERNEL.get(dom, (dom,))
-        kname = names[0] if per_level or len(names) == 1 else names[1]
+        kname = names[1] if flow_dom and len(names) > 1 else names[0]
         per_launch = sb[dom] / launches
         ms_dom, calls_dom = prof[dom]
         dur = ms_dom / calls_dom * 1e-3 / launches
         ach = per_launch / dur / 1e9
+        rp_us = rocprof_avg_us(kname)
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(kname),
                 "kernel": kname, "stage": dom, "launches_per_step": launches,
-                "avg_launch_us": round(dur * 1e6, 3), "algorithmic_bytes_per_launch": int(per_launch)}
+                "avg_launch_us": round(dur * 1e6, 3), "algorithmic_bytes_per_launch": int(per_launch),
+                "design_overhead_bytes_per_launch": int(ov.get(dom, 0) / launches),
+                "rocprof_avg_us": rp_us,
+                "frac_at_rocprof_duration": (round(per_launch / (rp_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)
+                                             if rp_us else None)}
     out = {
         "metric": "timing-graph pins/s for STA+top-K extraction; p2p loss fwd+bwd GB/s",
         "value": round(pins / (ms_step * 1e-3), 1),
@@ -517,6 +604,8 @@ def main():
                    "parallelism": "none"},
         "sta_extract_pins_per_s": round(pins / ((sta_ms + ext_ms) * 1e-3), 1) if sta_ms else None,
         "p2p_fwd_bwd_GBps": round((sb["p2p_fwd"] + sb["p2p_bwd"]) / (loss_ms * 1e-3) / 1e9, 2) if loss_ms else None,
+        "step_algorithmic_GB": round(step_gb, 4),
+        "step_hbm_frac": round(step_gb / (ms_step * 1e-3) / HBM_PEAK_GBPS, 4),
         "stages": stages,
         "pair_losses_ms": pair_ms,
         "early_analysis": early,
@@ -527,6 +616,16 @@ def main():
         "timing": {"wns": wns, "tns": tns, "n_fail": nfail, "paths": npaths, "path_pins": npins,
                    "pairs": counts["pairs"]},
     }
+    if not a.no_batch:
+        # the batched workload on the same GPU, after the headline's timed
+        # region: the union against per-instance launches
+        b = measure_batch(a, 10, 2, a.no_tune)
+        out["batched_C4"] = {key: b[key] for key in (
+            "value", "ms_per_step", "batched_graph_ms", "batched_eager_ms", "per_instance_graph_ms",
+            "per_instance_eager_ms", "speedup_vs_per_instance_eager", "speedup_vs_per_instance_graph", "paths",
+            "n_fail")}
+        out["batched_C4"]["workload"] = b["config"]["workload"]
+        out["batched_C4"]["unit"] = "pins/s"
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nl, lib, k, K, pins)
     print(json.dumps(out))
@@ -534,6 +633,12 @@ def main():
 
 def bench_batch(a):
     """Batched timing update + extraction against per-instance launches."""
+    print(json.dumps(measure_batch(a, a.steps, a.warmup, a.no_tune)))
+
+
+def measure_batch(a, steps, warmup, no_tune):
+    """The 40-instance batched workload: one union graph replayed from a
+    captured HIP graph against the same instances one graph at a time."""
     import torch
 
     from paper_2503_11674_amd import netgen
@@ -565,8 +670,8 @@ def bench_batch(a):
     yb = torch.cat([s[2] for s in singles])
     pins = gb.num_pins
     print(f"[bench] union graph: {gb.num_cells} cells, {pins} pins", file=sys.stderr, flush=True)
-    tune_b = None if a.no_tune else gb.autotune(xb, yb, n=-1, k=k, K=K, reps=3)
-    tune_s = None if a.no_tune else [g.autotune(x, y, n=-1, k=k, K=K, reps=2) for g, x, y in singles]
+    tune_b = None if no_tune else gb.autotune(xb, yb, n=-1, k=k, K=K, reps=3)
+    tune_s = None if no_tune else [g.autotune(x, y, n=-1, k=k, K=K, reps=2) for g, x, y in singles]
 
     def batched():
         gb.sta_update(xb, yb)
@@ -594,16 +699,16 @@ def bench_batch(a):
         torch.cuda.synchronize()
         return gr
 
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         batched()
         per_instance()
     gr_b = captured(batched)
     gr_s = captured(per_instance)
-    print(f"[bench] timing {a.steps} steps of each form", file=sys.stderr, flush=True)
-    t_b = timed(gr_b.replay, a.steps)
-    t_s_graph = timed(gr_s.replay, a.steps)
-    t_s_eager = timed(per_instance, a.steps)
-    t_b_eager = timed(batched, a.steps)
+    print(f"[bench] timing {steps} steps of each form", file=sys.stderr, flush=True)
+    t_b = timed(gr_b.replay, steps)
+    t_s_graph = timed(gr_s.replay, steps)
+    t_s_eager = timed(per_instance, steps)
+    t_b_eager = timed(batched, steps)
     # the union's selections are the instances' own: same path counts
     nb = gb.paths_count()
     ns = [g.paths_count() for g, _, _ in singles]
@@ -611,7 +716,7 @@ def bench_batch(a):
     out = {
         "metric": "timing-graph pins/s for STA+top-K extraction; p2p loss fwd+bwd GB/s",
         "value": round(pins / t_b, 1), "unit": "pins/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(1000 * t_b, 4),
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(1000 * t_b, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"C4: {len(nls)} instances (32 netlists of 10k-300k cells, depth 20-80, and 8 "
                                f"jittered snapshots of a 500k-cell netlist), {gb.num_cells} cells, {pins} pins; "
@@ -627,27 +732,51 @@ def bench_batch(a):
         "n_fail": {"batched": int(fb.sum()), "min_instance": int(fb.min())},
         "tuning": {"batched": tune_b, "per_instance": tune_s[:3] if tune_s else None},
     }
-    print(json.dumps(out))
+    gr_b = gr_s = None
+    for g, _, _ in singles:
+        g.close()
+    gb.close()
+    return out
 
 
-def cpu_baseline(nl, lib, k, K, pins):
+def host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(nl, lib, k, K, pins, runs=3):
     """The FP64 CPU oracle, single threaded, on the same workload: one step
-    (STA, extraction, pairs, WA and p2p forward+backward)."""
+    (STA, extraction, pairs, WA and p2p forward+backward), once to warm up,
+    then the median of `runs` timed steps."""
     from oracle import ref
 
-    t0 = time.perf_counter()
-    st = ref.sta(nl, lib)
-    pa = ref.extract(nl, lib, st, n=-1, k=k, K=K)
-    t1 = time.perf_counter()
-    ps = ref.PairState(nl["num_pins"])
-    ref.pairs_update(ps, pa, st["wns"])
-    s, w = ps.pairs()
-    ref.wa(nl, WA_GAMMA)
-    ref.p2p(nl, s, w)
-    t2 = time.perf_counter()
-    return {"value": round(pins / (t2 - t0), 1), "unit": "pins/s", "cores": 1, "kind": "oracle",
-            "sample": "one full step of the same workload (STA + extraction + pairs + WA + p2p fwd/bwd), FP64",
-            "seconds": round(t2 - t0, 3), "sta_extract_pins_per_s": round(pins / (t1 - t0), 1)}
+    def one():
+        t0 = time.perf_counter()
+        st = ref.sta(nl, lib)
+        pa = ref.extract(nl, lib, st, n=-1, k=k, K=K)
+        t1 = time.perf_counter()
+        ps = ref.PairState(nl["num_pins"])
+        ref.pairs_update(ps, pa, st["wns"])
+        s, w = ps.pairs()
+        ref.wa(nl, WA_GAMMA)
+        ref.p2p(nl, s, w)
+        t2 = time.perf_counter()
+        return t2 - t0, t1 - t0
+
+    one()
+    times = sorted(one() for _ in range(runs))
+    t_step, t_sta = times[len(times) // 2]
+    return {"value": round(pins / t_step, 1), "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full step of the same workload (STA + extraction + pairs + WA + p2p fwd/bwd), FP64; "
+                      f"one warm-up, median of {runs}",
+            "seconds": round(t_step, 3), "seconds_all": [round(t[0], 3) for t in times],
+            "sta_extract_pins_per_s": round(pins / t_sta, 1),
+            "host_cpu": host_cpu(), "host_threads_available": os.cpu_count()}
 
 
 if __name__ == "__main__":

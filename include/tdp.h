@@ -392,30 +392,40 @@ enum {
 tdp_status tdp_profile_enable(tdp_graph, int32_t stage_mask);
 tdp_status tdp_profile_read(tdp_graph, double *ms, int32_t *calls);
 
-/* Launch tuning of the timing sweeps, used by the autotuner.
+/* Launch tuning of the timing sweeps (Sec. II-B's arrival and required-time
+ * propagation), used by the autotuner.
  *  sweep_mode 0: one launch per level (any graph);
- *  sweep_mode 1: one persistent launch per sweep in which each 64-lane chunk
- *    of pins waits for the values it reads (single precision, every net with
- *    at most 63 sinks; the default where possible); TDP_E_UNSUPPORTED
+ *  sweep_mode 1: one launch per sweep on a resident grid: every workgroup of
+ *    it is on the GPU at once, each 64-lane wave owns a fixed set of chunks
+ *    of pins in dependency order and waits for the values each chunk reads
+ *    (single precision, every net with at most 63 sinks); TDP_E_UNSUPPORTED
  *    otherwise.  Every wait is bounded: a wait that runs out of polls makes
  *    all waves stop waiting, and tdp_sta_summary then returns TDP_E_DEVICE.
  *  sweep_mode 2: self-test of those bounded waits: as 1, but the start
  *    points are never published, so every wait gives up.
- *  flow_waves: 64-lane waves per workgroup of the dataflow sweeps (1, 2 or
+ *  sweep_mode 3: arrivals one launch per level, required times on a
+ *    resident grid (the default where the resident grid is possible).
+ *  flow_waves: 64-lane waves per workgroup of the resident grids (1, 2 or
  *    4; 0 keeps; default 4);
+ *  flow_per_cu: workgroups per compute unit of the resident grids (1..4,
+ *    capped by the kernel's occupancy; 0 keeps; default 1).  The grids must
+ *    fit on the GPU beside whatever runs concurrently on other streams; two
+ *    such sweeps from different graphs may run at once within 4 per CU.
  *  spin_log2: log2 of the poll budget per wait (0 keeps, 1..30).
  * Results do not depend on the tuning: both sweep forms compute every value
  * with the same operations in the same order. */
-tdp_status tdp_set_tuning(tdp_graph, int32_t flow_waves, int32_t spin_log2, int32_t sweep_mode);
+tdp_status tdp_set_tuning(tdp_graph, int32_t flow_waves, int32_t flow_per_cu, int32_t spin_log2,
+                          int32_t sweep_mode);
 
 /* Autotuner: on the caller's positions, times the timing update followed by
  * extract_paths(n, k, K) (k = 0: the update alone) under every sweep
- * configuration the graph supports (per-level launches; dataflow sweeps with
- * 1, 2 or 4 waves per workgroup), one warm-up and `reps` timed runs each
- * (1..1000), and keeps the fastest.  h_choice (3 int32, host, may be NULL)
- * receives {sweep_mode, flow_waves, microseconds per run}.  Synchronises;
- * on return the graph holds the chosen configuration's results for these
- * positions.  Errors as tdp_sta_update / tdp_extract_paths. */
+ * configuration the graph supports (per-level launches; resident dataflow
+ * grids for both sweeps or for the required times only, with 1, 2 or 4
+ * waves per workgroup and 1, 2 or 4 workgroups per compute unit), one warm-up and `reps` timed runs each (1..1000), and keeps
+ * the fastest.  h_choice (4 int32, host, may be NULL) receives {sweep_mode,
+ * flow_waves, flow_per_cu, microseconds per run}.  Synchronises; on return
+ * the graph holds the chosen configuration's results for these positions.
+ * Errors as tdp_sta_update / tdp_extract_paths. */
 tdp_status tdp_autotune(tdp_graph, const float *d_x, const float *d_y, int32_t n, int32_t k, int32_t K,
                         int32_t reps, int32_t *h_choice, hipStream_t);
 

@@ -263,13 +263,16 @@ def pair_loss(nl, kind, pair_sink, pair_w, x=None, y=None):
     return float(loss[0]), gx, gy
 
 
-def stns(nl, lib, st, gamma: float = 10.0, x=None, y=None):
-    """Smoothed TNS (frozen cell arcs and start-point arrivals from `st`)."""
+def stns(nl, lib, st, gamma: float = 10.0, x=None, y=None, with_abs: bool = False):
+    """Smoothed TNS (frozen cell arcs and start-point arrivals from `st`)
+    (with_abs: also, per cell, the summed magnitudes of the net-arc terms of
+    its gradient, the scale of the rounding error)."""
     L = _load()
     x = _f32(nl["x"] if x is None else x)
     y = _f32(nl["y"] if y is None else y)
     N = int(nl["num_cells"])
     gx, gy = np.empty(N, np.float64), np.empty(N, np.float64)
+    ax, ay = np.empty(N, np.float64), np.empty(N, np.float64)
     val = np.zeros(1, np.float64)
     na, k1 = _netlist_args(nl)
     la, k2 = _lib_args(lib)
@@ -277,9 +280,11 @@ def stns(nl, lib, st, gamma: float = 10.0, x=None, y=None):
     at0, darc = _f64(st["at"]), _f64(st["darc"])
     rc = L.ora_stns(*na, *la, _p(fixed), _p(x), _p(y), _p(at0), _p(darc),
                     ctypes.c_double(float(st["clock_period"])), ctypes.c_double(float(nl["setup"])),
-                    ctypes.c_double(gamma), _p(val), _p(gx), _p(gy))
+                    ctypes.c_double(gamma), _p(val), _p(gx), _p(gy), _p(ax), _p(ay))
     if rc != 0:
         raise ValueError("timing graph has a cycle")
+    if with_abs:
+        return float(val[0]), gx, gy, ax, ay
     return float(val[0]), gx, gy
 
 

@@ -945,10 +945,13 @@ int ora_pair_loss(NETLIST_ARGS, const uint8_t *cell_fixed, const float *x, const
  *   value:          -g * sum_e softplus(-s(e)/g)
  * The gradient on cell positions goes through the net delay of the library's
  * net model as a function of L = |dx| + |dy| (sign(0) = 0).  grad_x/grad_y
- * [N] are overwritten. */
+ * [N] are overwritten.  gabs_x/gabs_y (optional, [N]) receive, per cell, the
+ * sum of the magnitudes of the net-arc terms added into its gradient: the
+ * terms of a cell's pins can cancel, so their magnitudes, not the sum, set
+ * the scale of rounding error. */
 int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, const float *y,
              const double *at0, const double *darc, double clock_period, double setup,
-             double gamma, double *value, double *grad_x, double *grad_y) {
+             double gamma, double *value, double *grad_x, double *grad_y, double *gabs_x, double *gabs_y) {
   FILL_NETLIST(n);
   FILL_LIB(L);
   oconn c;
@@ -1015,6 +1018,8 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
     }
   }
   for (int cell = 0; cell < num_cells; ++cell) { grad_x[cell] = 0; grad_y[cell] = 0; }
+  if (gabs_x && gabs_y)
+    for (int cell = 0; cell < num_cells; ++cell) { gabs_x[cell] = 0; gabs_y[cell] = 0; }
   for (int net = 0; net < num_nets; ++net) {
     int s = net_pins[net_ptr[net]];
     double xs, ys;
@@ -1033,6 +1038,10 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
       int ct = pin_cell[t];
       if (cs >= 0 && !cell_fixed[cs]) { grad_x[cs] += gx; grad_y[cs] += gy; }
       if (ct >= 0 && !cell_fixed[ct]) { grad_x[ct] -= gx; grad_y[ct] -= gy; }
+      if (gabs_x && gabs_y) {
+        if (cs >= 0 && !cell_fixed[cs]) { gabs_x[cs] += fabs(gx); gabs_y[cs] += fabs(gy); }
+        if (ct >= 0 && !cell_fixed[ct]) { gabs_x[ct] += fabs(gx); gabs_y[ct] += fabs(gy); }
+      }
     }
   }
   free(A); free(Ab); free(dn);

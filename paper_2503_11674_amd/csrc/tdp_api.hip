@@ -118,6 +118,9 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   if (!g) return fail(nullptr, TDP_E_NOMEM, "host allocation failed");
   DeviceGuard dg(device);
   g->device = device;
+  if (hipDeviceGetAttribute(&g->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      g->num_cu < 1)
+    g->num_cu = 1;
   g->prec = prec;
   g->esz = prec == TDP_F64 ? 8 : 4;
   g->lv = H.lv;
@@ -195,7 +198,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
          dalloc(g, g->side_pin, (size_t)T.n_comb * g->side_k);
   // dataflow sweeps: single precision, every net fits one 64-lane chunk
   g->flow_ok = prec == TDP_F32 && T.n_big == 0;
-  g->sweep_mode = g->flow_ok ? 1 : 0;
+  g->sweep_mode = g->flow_ok ? 3 : 0;
   if (ok && g->flow_ok) {
     ok = dalloc(g, g->flow_w, T.M) && dalloc(g, g->flow_r, T.M) && dalloc(g, g->flow_cd, T.M) &&
          dalloc(g, g->flow_se, (size_t)T.n_comb * g->side_k);
@@ -767,15 +770,18 @@ tdp_status tdp_profile_read(tdp_graph g, double *ms, int32_t *calls) {
   return TDP_OK;
 }
 
-tdp_status tdp_set_tuning(tdp_graph g, int32_t flow_waves, int32_t spin_log2, int32_t sweep_mode) {
+tdp_status tdp_set_tuning(tdp_graph g, int32_t flow_waves, int32_t flow_per_cu, int32_t spin_log2,
+                          int32_t sweep_mode) {
   GUARD(g);
   if (flow_waves != 0 && flow_waves != 1 && flow_waves != 2 && flow_waves != 4)
     return fail(g, TDP_E_INVALID, "flow_waves must be 0, 1, 2 or 4");
+  if (flow_per_cu < 0 || flow_per_cu > 4) return fail(g, TDP_E_INVALID, "flow_per_cu must be 0..4");
   if (spin_log2 != 0 && (spin_log2 < 1 || spin_log2 > 30)) return fail(g, TDP_E_INVALID, "spin_log2 out of range");
-  if (sweep_mode < 0 || sweep_mode > 2) return fail(g, TDP_E_INVALID, "sweep_mode must be 0, 1 or 2");
+  if (sweep_mode < 0 || sweep_mode > 3) return fail(g, TDP_E_INVALID, "sweep_mode must be 0..3");
   if (sweep_mode >= 1 && !g->flow_ok)
     return fail(g, TDP_E_UNSUPPORTED, "dataflow sweeps need single precision and nets of at most 63 sinks");
   if (flow_waves) g->flow_waves = flow_waves;
+  if (flow_per_cu) g->flow_per_cu = flow_per_cu;
   if (spin_log2) g->spin_limit = 1 << spin_log2;
   g->sweep_mode = sweep_mode;
   return TDP_OK;
@@ -788,11 +794,13 @@ tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, 
   if (reps < 1 || reps > 1000) return fail(g, TDP_E_INVALID, "reps must be 1..1000");
   if (k < 0 || k > g->max_k) return fail(g, TDP_E_CAPACITY, "k outside 0..max_k");
   struct Cand {
-    int mode, waves;
+    int mode, waves, per_cu;
   };
-  std::vector<Cand> cands = {{0, g->flow_waves}};
+  std::vector<Cand> cands = {{0, g->flow_waves, g->flow_per_cu}};
   if (g->flow_ok)
-    for (int w : {1, 2, 4}) cands.push_back({1, w});
+    for (int w : {1, 2, 4})
+      for (int pc : {1, 2, 4})
+        for (int m : {1, 3}) cands.push_back({m, w, pc});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) hipEventDestroy(e0);
@@ -801,7 +809,7 @@ tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, 
   const bool prof = g->prof.on;
   g->prof.on = false;
   const float no_limit = std::numeric_limits<float>::infinity();
-  Cand best_c = {g->sweep_mode, g->flow_waves};
+  Cand best_c = {g->sweep_mode, g->flow_waves, g->flow_per_cu};
   float best = std::numeric_limits<float>::infinity();
   tdp_status st = TDP_OK;
   auto run = [&]() {
@@ -812,6 +820,7 @@ tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, 
   for (const Cand &c : cands) {
     g->sweep_mode = c.mode;
     g->flow_waves = c.waves;
+    g->flow_per_cu = c.per_cu;
     st = run();  // warm-up
     if (st == TDP_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(g, TDP_E_DEVICE, "event record failed");
     for (int r = 0; r < reps && st == TDP_OK; ++r) st = run();
@@ -835,6 +844,7 @@ tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, 
   hipEventDestroy(e1);
   g->sweep_mode = best_c.mode;
   g->flow_waves = best_c.waves;
+  g->flow_per_cu = best_c.per_cu;
   g->prof.on = prof;
   if (st != TDP_OK) return st;
   // leave the results of the chosen configuration behind
@@ -843,7 +853,8 @@ tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, 
   if (choice) {
     choice[0] = best_c.mode;
     choice[1] = best_c.waves;
-    choice[2] = std::isfinite(best) ? (int32_t)std::lround(best * 1000.0f) : -1;
+    choice[2] = best_c.per_cu;
+    choice[3] = std::isfinite(best) ? (int32_t)std::lround(best * 1000.0f) : -1;
   }
   return TDP_OK;
 }

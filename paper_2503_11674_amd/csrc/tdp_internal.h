@@ -252,6 +252,9 @@ struct tdp_graph_s {
   uint32_t *flow_cd = nullptr;   // [M] chain depth + 1 of a driver; 0 = not yet
   uint64_t *flow_se = nullptr;   // [n_comb][side_k] deviation entries {cost, sink}; all ones = not yet
   int32_t flow_waves = 4, spin_limit = 1 << 20;
+  int32_t flow_per_cu = 1;       // workgroups per compute unit of the resident dataflow grids
+  int32_t num_cu = 0;            // compute units of the device
+  int32_t occ_fw[3] = {-1, -1, -1}, occ_bw[3] = {-1, -1, -1};  // occupancy per 1 / 2 / 4 waves, -1 = not yet
   bool flow_ok = false;          // the graph can use the dataflow sweeps
   double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;
   double *summary = nullptr;     // [4 * num_inst]: wns, tns, n_fail, 0

@@ -66,22 +66,21 @@ __device__ __forceinline__ uint64_t pack2(float lo, float hi) {
   return (uint64_t)__float_as_uint(lo) | ((uint64_t)__float_as_uint(hi) << 32);
 }
 
-// Poll *p until it differs from `empty`, backing off from one to eight
-// sleeps between polls.  The wait is bounded: after `limit` polls (or once
-// another wave has given up) it sets bit 2 of *err and returns `empty`, so
-// every wave always finishes.
+// Poll *p until it differs from `empty`, with one short sleep between polls
+// (a longer back-off delays the frontier by the sleep).  The wait is
+// bounded: after `limit` polls (or once another wave has given up) it sets
+// bit 2 of *err and returns `empty`, so every wave always finishes.
 template <typename U>
 __device__ __forceinline__ U wait_pub(const U *p, U empty, int32_t *err, int limit) {
   U v = pub_ld(p);
-  int it = 0, nap = 1;
+  int it = 0;
   while (v == empty) {
     if (++it > limit) {
       atomicOr(err, 2);
       break;
     }
     if ((it & 31) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-    for (int z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(1);
-    nap = nap < 8 ? 2 * nap : 8;
+    __builtin_amdgcn_s_sleep(1);
     v = pub_ld(p);
   }
   return v;
@@ -95,6 +94,24 @@ __device__ __forceinline__ void wait_rep(const U *p, U empty, int32_t *err, int 
   if (wave_lane() == 0) (void)wait_pub(p, empty, err, limit);
 }
 
+// Every lane that wants one loads its word; only if some wanted word is not
+// yet published does the wave wait: one lane polls the missing word that is
+// published last (the highest-numbered one when producers go up the index
+// order, the lowest with LOW_LAST), then the missing lanes wait for theirs.
+// A wave behind the frontier pays one memory round trip.  Lanes that want
+// nothing get `empty`.
+template <bool LOW_LAST = false, typename U>
+__device__ __forceinline__ U load_or_wait(const U *base, int idx, bool want, U empty, int32_t *err, int limit) {
+  U v = want ? pub_ld(base + idx) : empty;
+  const bool miss = want && v == empty;
+  if (__ballot(miss)) {
+    const int rep = LOW_LAST ? -wave_max_int(miss ? -idx : INT32_MIN + 1) : wave_max_int(miss ? idx : -1);
+    if (wave_lane() == 0) (void)wait_pub(base + rep, empty, err, limit);
+    if (miss) v = wait_pub(base + idx, empty, err, limit);
+  }
+  return v;
+}
+
 struct FlowInit {
   uint64_t *w = nullptr;
   uint32_t *r = nullptr, *cd = nullptr;
@@ -102,7 +119,36 @@ struct FlowInit {
   int32_t *err = nullptr;  // cleared at the start of every update
   int km = 0;
   int seed = 1;  // 0: start points are never published (self-test of the bounded waits)
+  int reset_blocks = 0;  // trailing workgroups of the net pass that reset the words
 };
+
+// v[0, n) = x, 16-byte stores where the alignment allows
+__device__ __forceinline__ void fill_u32(uint32_t *p, size_t n, uint32_t x, size_t tid, size_t nth) {
+  size_t h = ((16 - ((uintptr_t)p & 15)) & 15) / 4;
+  h = h < n ? h : n;
+  if (tid < h) p[tid] = x;
+  uint4 *q = (uint4 *)(p + h);
+  const size_t n4 = (n - h) / 4;
+  const uint4 xx = make_uint4(x, x, x, x);
+  for (size_t i = tid; i < n4; i += nth) q[i] = xx;
+  const size_t t0 = h + n4 * 4;
+  if (tid < n - t0) p[t0 + tid] = x;
+}
+
+// The words the dataflow sweeps poll return to "not yet published" at the
+// start of every update (the start points' words are seeded by the net pass
+// itself, so they are left out here): streaming stores in workgroups of their
+// own beside the net pass's gathers.
+__device__ __forceinline__ void flow_reset(const FlowInit &fl, const Topo &tp, int b) {
+  const size_t nth = (size_t)fl.reset_blocks * blockDim.x, tid = (size_t)b * blockDim.x + threadIdx.x;
+  const size_t nc = (size_t)(tp.M - tp.n_start);
+  if (fl.w) {
+    fill_u32((uint32_t *)(fl.w + tp.n_start), 2 * nc, ~0u, tid, nth);
+    fill_u32(fl.cd + tp.n_start, nc, 0u, tid, nth);
+    if (fl.km) fill_u32((uint32_t *)fl.se, 2 * (size_t)tp.n_comb * fl.km, ~0u, tid, nth);
+  }
+  if (fl.r) fill_u32(fl.r, (size_t)tp.M, R_EMPTY, tid, nth);
+}
 
 template <typename T>
 __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, int v, T ld, T in_slew, T clk_slew,
@@ -115,17 +161,9 @@ __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, in
     slew[v] = s;
     as[v] = v2<T>(a, s);
     cdep[v] = 0;
-  }
-  if (fl.w) {  // reset (or seed) the words the dataflow sweeps poll
-    fl.r[v] = R_EMPTY;
-    if (v < tp.n_start) {
+    if (fl.w) {  // seed the start points' words of the dataflow sweeps
       fl.w[v] = fl.seed ? pack2((float)a, (float)s) : W_EMPTY;
       fl.cd[v] = fl.seed ? 1 : 0;
-    } else {
-      fl.w[v] = W_EMPTY;
-      fl.cd[v] = 0;
-      const size_t b = (size_t)(v - tp.n_start) * fl.km;
-      for (int j = 0; j < fl.km; ++j) fl.se[b + j] = W_EMPTY;
     }
   }
 }
@@ -139,6 +177,11 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
                                                   T *__restrict__ at, T *__restrict__ slew,
                                                   V2<T> *__restrict__ as, int32_t *__restrict__ cdep, FlowInit fl) {
   if (blockIdx.x == 0 && threadIdx.x == 0 && fl.err) *fl.err = 0;
+  const int main_blocks = (int)gridDim.x - fl.reset_blocks;
+  if ((int)blockIdx.x >= main_blocks) {
+    flow_reset(fl, tp, (int)blockIdx.x - main_blocks);
+    return;
+  }
   const int lane = wave_lane();
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
@@ -528,24 +571,126 @@ __global__ void k_backward_big(Topo tp, int i0, int i1, const T *__restrict__ dn
 }
 
 // ------------------------------------------------------ dataflow sweeps
-// One launch per sweep with one wave per 64-lane chunk, chunks in dependency
-// order by workgroup index (forward: level order; backward: reverse level
-// order).  A wave loads its chunk's static data, waits until the words it
-// reads are published, computes exactly what the per-level kernels compute,
-// and publishes its own words.  A chunk waits only on chunks with smaller
-// indices.  Workgroups are started in index order on each XCD, so the
-// smallest unfinished chunk is always resident and its inputs are complete:
-// the sweep completes.  (Handing chunks out from an atomic ticket counter
-// would not rely on the start order, but same-address atomics serialise at
-// about one per 16 ns, which costs more than the whole sweep.)  Every wait is
-// also bounded, so a broken assumption ends in a reported error, not a hang.
-// Waves waiting on the frontier overlap their static loads with its
-// progress, so the critical path is one publish-to-observe latency per level.
+// One launch per sweep on a resident grid: every workgroup of the launch is
+// on the GPU at once (the grid is sized from the occupancy of the kernel, at
+// most a few workgroups per compute unit, so a concurrent kernel on another
+// stream cannot keep part of it waiting), and wave w of the W waves owns
+// chunks w, w + W, w + 2W, ... in dependency order (forward: level order;
+// backward: reverse level order).  For each chunk a wave loads its static
+// data (the next chunk's record is already in flight), waits until the words
+// it reads are published, computes exactly what the per-level kernels
+// compute, and publishes its own words.  A chunk waits only on chunks with
+// smaller indices, and every wave takes its chunks in increasing order, so
+// the smallest unfinished chunk always has its inputs and its owner at it:
+// the sweep completes.  The tables are staged in LDS once per workgroup, not
+// once per chunk, and no workgroup is dispatched while the sweep runs.
+// Every wait is also bounded, so a broken assumption ends in a reported
+// error, not a hang.  One lane per wave polls (the word its chunk is likely
+// to see published last) before the others load theirs, which keeps the
+// polling traffic of the waiting waves off the frontier's way.
 //
-// Forward, phase 1: a lane polls its driver's {arrival, transition} word.
-// Phase 2 (head lanes, after the cell's word is out): the chain depth and the
-// deviation list follow the critical input, every entry its own word; all are
-// loaded at once and only the ones still empty are polled.
+// Forward.  Arrival phase of a chunk: a lane loads its driver's {arrival,
+// transition} word, waiting only if it is not out yet, and the cell's head
+// lane publishes the output's word before anything else.  List phase (head
+// lanes): the chain depth and the deviation list follow the critical input,
+// every entry its own word, loaded at once and waited for only where still
+// empty.  A wave runs the list phase of a chunk after the arrival phase of
+// its next chunk: the list chain trails the arrival chain, and a list phase
+// run at once would hold the wave (and its next arrivals) until the lists
+// below it are out.  Deferral keeps the sweep deadlock-free: give the
+// arrival phase of chunk c the key c and its list phase the key c + W; a
+// phase waits only on phases of smaller keys, and every wave runs its phases
+// in increasing key order (the arrival phase of chunk c, then the list phase
+// of chunk c - W, whose key is also c), so the phase of smallest key not yet
+// done always has its inputs and its wave at it.
+struct FwPend {
+  int4 rec;   // the chunk's record (rec.x = -1: nothing pending)
+  float a;    // arrival through the lane's arc
+  float best; // the cell's arrival
+  int argl;   // lane of the critical input
+  int pred;   // driver of the critical input
+};
+
+template <int KM>
+__device__ __forceinline__ void fw_flow_lists(const Topo &tp, const FwPend &q, int32_t *__restrict__ cdep,
+                                              float *__restrict__ side_cost, int32_t *__restrict__ side_pin,
+                                              uint32_t *__restrict__ fcd, uint64_t *__restrict__ fse,
+                                              int32_t *__restrict__ err, int limit) {
+  const int lane = wave_lane();
+  const int t = q.rec.x, c = q.rec.z;
+  const int head = q.rec.w & 63, tail = (q.rec.w >> 8) & 63;
+  const bool valid = t >= 0;
+  const bool is_head = valid && lane == head;
+  const int pred = q.pred;
+  const int v = tp.n_start + c;
+  // chain depth (+1 in the published word) and deviation list of the
+  // critical input's driver
+  constexpr int KL = KM > 1 ? KM : 1;
+  const bool chain = is_head && pred >= tp.n_start;
+  const size_t pb = chain ? (size_t)(pred - tp.n_start) * KM : 0;
+  uint32_t cdp = is_head ? pub_ld(&fcd[pred]) : 1u;
+  uint64_t pe[KL];
+  bool miss = cdp == 0u;
+#pragma unroll
+  for (int j = 0; j < KL; ++j) {
+    pe[j] = (KM > 1 && chain) ? pub_ld(&fse[pb + j]) : 0ull;
+    miss = miss || pe[j] == W_EMPTY;
+  }
+  if (__ballot(miss)) {
+    const int p_rep = wave_max_int(miss ? pred : -1);
+    if (lane == 0) (void)wait_pub(&fcd[p_rep], 0u, err, limit);
+    // then every word still missing is loaded again, all at once (one round
+    // trip per poll, not one per word)
+    int it = 0;
+    while (__ballot(miss)) {
+      if (miss) {
+        if (cdp == 0u) cdp = pub_ld(&fcd[pred]);
+#pragma unroll
+        for (int j = 0; j < KL; ++j)
+          if (pe[j] == W_EMPTY) pe[j] = pub_ld(&fse[pb + j]);
+        miss = cdp == 0u;
+#pragma unroll
+        for (int j = 0; j < KL; ++j) miss = miss || pe[j] == W_EMPTY;
+      }
+      if (++it > limit) {
+        if (lane == 0) atomicOr(err, 2);
+        break;
+      }
+      if ((it & 31) == 0 && __ballot(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) break;
+      if (__ballot(miss)) __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  if (is_head) cdep[v] = (int32_t)cdp;
+  if constexpr (KM > 1) {
+    const float dl = (valid && lane != q.argl) ? q.best - q.a : __builtin_huge_valf();
+    const int width = wave_max_int(valid ? tail - head + 1 : 0);
+    float kc[KM];
+    int32_t kp[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+      kc[j] = chain ? __uint_as_float((uint32_t)pe[j]) : __builtin_huge_valf();
+      kp[j] = chain ? (int32_t)(uint32_t)(pe[j] >> 32) : -1;
+    }
+    // own deviations, last arc first so that equal costs keep arc order
+    for (int r = 0; r < width; ++r) {
+      const int j = tail - r;
+      const float dj = __shfl(dl, j & 63, 64);
+      const int tj = __shfl(t, j & 63, 64);
+      if (is_head && j >= head && dj < __builtin_huge_valf()) insert_front<float, KM>(kc, kp, dj, tj);
+    }
+    if (is_head) {
+      const size_t cb = (size_t)c * KM;
+#pragma unroll
+      for (int j = 0; j < KM; ++j) {
+        pub_st(&fse[cb + j], (uint64_t)__float_as_uint(kc[j]) | ((uint64_t)(uint32_t)kp[j] << 32));
+        side_cost[cb + j] = kc[j];
+        side_pin[cb + j] = kp[j];
+      }
+    }
+  }
+  if (is_head) pub_st(&fcd[v], cdp + 1);
+}
+
 template <int KM>
 __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const float *__restrict__ load,
                                                        const float *__restrict__ dnet, float *__restrict__ at,
@@ -559,12 +704,26 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
   extern __shared__ float4 s_lut4[];
   float *s_lut = (float *)s_lut4;
   const int lane = wave_lane();
-  const int chunk = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int k = chunk * CHUNK + lane;
-  const int4 rec = chunk < tp.n_fw_chunks ? tp.fw_rec[k] : make_int4(-1, 0, 0, 0);
+  const int wpb = blockDim.x >> 6;
+  const int W = gridDim.x * wpb;
+  const int nch = tp.n_fw_chunks;
+  int chunk = blockIdx.x * wpb + (threadIdx.x >> 6);
+  int4 nrec = make_int4(-1, 0, 0, 0);
+  int2 nex = make_int2(0, 0);
+  if (chunk < nch) {
+    nrec = tp.fw_rec[chunk * CHUNK + lane];
+    nex = tp.fw_ext[chunk * CHUNK + lane];
+  }
   stage_lut(L, s_lut);
-  if (chunk >= tp.n_fw_chunks) return;
-  {
+  FwPend pend;
+  bool pending = false;
+  for (; chunk < nch; chunk += W) {
+    const int4 rec = nrec;
+    const int2 ex = nex;
+    if (chunk + W < nch) {  // the next chunk's static data, in flight while this one waits
+      nrec = tp.fw_rec[(chunk + W) * CHUNK + lane];
+      nex = tp.fw_ext[(chunk + W) * CHUNK + lane];
+    }
     const int t = rec.x, s = rec.y, c = rec.z, ty = (rec.w >> 16) & 255;
     const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
     const bool valid = t >= 0;
@@ -574,11 +733,8 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
       ld = load[tp.n_start + c];
       dn = dnet[t];
     }
-    // drivers are numbered in production order: the highest one comes last
-    const int s_rep = wave_max_int(valid ? s : -1);
-    if (s_rep >= 0) wait_rep(&fw[s_rep], W_EMPTY, err, limit);
+    const uint64_t w = load_or_wait(fw, valid ? s : 0, valid, W_EMPTY, err, limit);
     if (valid) {
-      const uint64_t w = wait_pub(&fw[s], W_EMPTY, err, limit);
       const float a_in = __uint_as_float((uint32_t)w) + dn;
       float d;
       lut_lds<float>(s_lut, L.nt, L.ns, L.nl, ty, sink_slew<float>(L.net_model, __uint_as_float((uint32_t)(w >> 32)), dn),
@@ -592,109 +748,67 @@ __global__ void __launch_bounds__(256) k_forward_flow(Topo tp, LutView L, const 
     // first input attaining the maximum (the head when none does, e.g. NaN)
     const int arg0 = seg_min((valid && a == best) ? lane : 64, lane, head, tail);
     const int argl = arg0 <= tail ? arg0 : head;
-    const int tc = __shfl(t, argl & 63, 64);
-    const int pred = __shfl(s, argl & 63, 64);
     const bool is_head = valid && lane == head;
     const int v = tp.n_start + c;
+    if (is_head) pub_st(&fw[v], pack2(best, so));
+    const int tc = __shfl(t, argl & 63, 64);
+    const int pred = __shfl(s, argl & 63, 64);
+    const int2 exc = make_int2(__shfl(ex.x, argl & 63, 64), __shfl(ex.y, argl & 63, 64));
     if (is_head) {
       at[v] = best;
       slew[v] = so;
       crit[c] = argl - head;
-      hop[c] = make_int4(tc, pred, tp.snk_ext[tc], tp.drv_ext[pred]);
-      pub_st(&fw[v], pack2(best, so));
+      hop[c] = make_int4(tc, pred, exc.x, exc.y);
     }
-    // phase 2: chain depth (+1 in the published word) and deviation list
-    uint32_t cdp = 0;
-    uint64_t pe[KM > 1 ? KM : 1];
-    const bool chain = is_head && pred >= tp.n_start;
-    const int p_rep = wave_max_int(chain ? pred : -1);
-    if (p_rep >= 0) wait_rep(&fcd[p_rep], 0u, err, limit);
-    if (is_head) {
-      cdp = pub_ld(&fcd[pred]);
-      if constexpr (KM > 1) {
-        const size_t pb = (size_t)(pred - tp.n_start) * KM;
-#pragma unroll
-        for (int j = 0; j < KM; ++j) pe[j] = chain ? pub_ld(&fse[pb + j]) : W_EMPTY;
-      }
-      if (cdp == 0u) cdp = wait_pub(&fcd[pred], 0u, err, limit);
-      cdep[v] = (int32_t)cdp;
-    }
-    if constexpr (KM > 1) {
-      const float dl = (valid && lane != argl) ? best - a : __builtin_huge_valf();
-      const int width = wave_max_int(valid ? tail - head + 1 : 0);
-      float kc[KM];
-      int32_t kp[KM];
-#pragma unroll
-      for (int j = 0; j < KM; ++j) {
-        kc[j] = __builtin_huge_valf();
-        kp[j] = -1;
-      }
-      if (chain) {
-        const size_t pb = (size_t)(pred - tp.n_start) * KM;
-#pragma unroll
-        for (int j = 0; j < KM; ++j) {
-          const uint64_t e = pe[j] != W_EMPTY ? pe[j] : wait_pub(&fse[pb + j], W_EMPTY, err, limit);
-          kc[j] = __uint_as_float((uint32_t)e);
-          kp[j] = (int32_t)(uint32_t)(e >> 32);
-        }
-      }
-      for (int r = 0; r < width; ++r) {
-        const int j = tail - r;
-        const float dj = __shfl(dl, j & 63, 64);
-        const int tj = __shfl(t, j & 63, 64);
-        if (is_head && j >= head && dj < __builtin_huge_valf()) insert_front<float, KM>(kc, kp, dj, tj);
-      }
-      if (is_head) {
-        const size_t cb = (size_t)c * KM;
-#pragma unroll
-        for (int j = 0; j < KM; ++j) {
-          side_cost[cb + j] = kc[j];
-          side_pin[cb + j] = kp[j];
-          pub_st(&fse[cb + j], (uint64_t)__float_as_uint(kc[j]) | ((uint64_t)(uint32_t)kp[j] << 32));
-        }
-      }
-    }
-    if (is_head) pub_st(&fcd[v], cdp + 1);
+    if (pending) fw_flow_lists<KM>(tp, pend, cdep, side_cost, side_pin, fcd, fse, err, limit);
+    pend.rec = rec;
+    pend.a = a;
+    pend.best = best;
+    pend.argl = argl;
+    pend.pred = pred;
+    pending = true;
   }
+  if (pending) fw_flow_lists<KM>(tp, pend, cdep, side_cost, side_pin, fcd, fse, err, limit);
 }
 
-// Backward: a sink lane polls the required time of its cell's output (the D
-// pin of a flip-flop needs nothing); the driver lane publishes its own.
+// Backward: chunks from the last; a sink lane loads the required time of its
+// cell's output (the D pin of a flip-flop needs nothing), waiting only if it
+// is not out yet; the driver lane publishes its own.
 __global__ void __launch_bounds__(256) k_backward_flow(Topo tp, const float *__restrict__ dnet_nm,
                                                         const float *__restrict__ darc, float *__restrict__ rat,
                                                         uint32_t *__restrict__ fr, int32_t *__restrict__ err,
                                                         int limit) {
   const int lane = wave_lane();
   const float inf = __builtin_huge_valf();
-  const int q = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (q >= tp.n_nm_chunks) return;
-  {
-    const int chunk = tp.n_nm_chunks - 1 - q;
+  const int wpb = blockDim.x >> 6;
+  const int W = gridDim.x * wpb;
+  const int nch = tp.n_nm_chunks;
+  int q = blockIdx.x * wpb + (threadIdx.x >> 6);
+  int4 nrec = q < nch ? tp.nm_rec[(nch - 1 - q) * CHUNK + lane] : make_int4(-1, -1, -1, 0);
+  for (; q < nch; q += W) {
+    const int chunk = nch - 1 - q;
     const int k = chunk * CHUNK + lane;
-    const int4 rec = tp.nm_rec[k];
+    const int4 rec = nrec;
+    if (q + W < nch) nrec = tp.nm_rec[(nch - 1 - q - W) * CHUNK + lane];
     const int p = rec.x, vo = rec.z;
     const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
     const bool sink = p >= 0 && lane != head;
     const int t = p - tp.M;
     const bool comb_in = sink && vo >= 0;
-    // static data first, then the wave's representative: outputs are numbered
-    // in production order of the forward sweep, so the backward sweep
-    // publishes the lowest one last
     const float dn = sink ? dnet_nm[k] : 0.f, da = comb_in ? darc[t] : 0.f;
     const float rq = sink && !comb_in ? rat[p] : 0.f;  // a D pin's, set at the endpoint
-    const int v_rep = -wave_max_int(comb_in ? -vo : 1);
-    if (v_rep >= 0) wait_rep(&fr[v_rep], R_EMPTY, err, limit);
+    // outputs are numbered in production order of the forward sweep, so the
+    // backward sweep publishes the lowest one last
+    const uint32_t wr = load_or_wait<true>(fr, comb_in ? vo : 0, comb_in, R_EMPTY, err, limit);
     float r = inf;
     if (sink) {
-      // a flip-flop D pin's required time was set at the endpoint
-      const float rt =
-          comb_in ? sink_required<float>(p, __uint_as_float(wait_pub(&fr[vo], R_EMPTY, err, limit)), da, rat) : rq;
+      const float rt = comb_in ? sink_required<float>(p, __uint_as_float(wr), da, rat) : rq;
       if (rt != inf) r = rt - dn;
     }
     r = seg_min(r, lane, head, tail);
     if (p >= 0 && lane == head) {
-      rat[p] = r;
       pub_st(&fr[p], __float_as_uint(r));
+      rat[p] = r;
     }
   }
 }
@@ -773,11 +887,28 @@ static void forward_level(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipSt
   }
 }
 
+// workgroups of a resident grid of `waves`-wave workgroups over nch chunks:
+// flow_per_cu per compute unit, within the kernel's occupancy (cached per
+// wave count), and no more than the chunks need
+static int resident_blocks(tdp_graph g, const void *kern, int32_t *occ_cache, int waves, size_t lds, int nch) {
+  const int wi = waves == 1 ? 0 : (waves == 2 ? 1 : 2);
+  if (occ_cache[wi] < 0) {
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * waves, lds) != hipSuccess || occ < 1) occ = 1;
+    occ_cache[wi] = occ;
+  }
+  const long long per = std::min(occ_cache[wi], g->flow_per_cu);
+  const long long need = nblk(nch, waves);
+  return (int)std::max(1LL, std::min(per * std::max(1, g->num_cu), need));
+}
+
 template <int KM>
 static void launch_forward_flow(tdp_graph g, hipStream_t s) {
   const Topo &tp = g->topo;
   const int w = g->flow_waves;
-  hipLaunchKernelGGL((k_forward_flow<KM>), dim3(nblk(tp.n_fw_chunks, w)), dim3(64 * w), lut_bytes(g->lut), s, tp, g->lut,
+  const int nb = resident_blocks(g, reinterpret_cast<const void *>(&k_forward_flow<KM>), g->occ_fw, w,
+                                 lut_bytes(g->lut), tp.n_fw_chunks);
+  hipLaunchKernelGGL((k_forward_flow<KM>), dim3(nb), dim3(64 * w), lut_bytes(g->lut), s, tp, g->lut,
                      (const float *)g->load, (const float *)g->dnet, (float *)g->at, (float *)g->slew,
                      (float *)g->darc, g->crit, (int4 *)g->hop, g->cdep, (float *)g->side_cost, g->side_pin,
                      g->flow_w, g->flow_cd, g->flow_se, g->d_err, g->spin_limit);
@@ -799,20 +930,27 @@ template <typename T>
 void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   const Topo &tp = g->topo;
   const NetModel<T> nm = net_model<T>(g);
-  const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;
+  // sweep_mode 1 and 2: both sweeps as resident dataflow grids; 3: the
+  // backward one only
+  const bool flow = sizeof(T) == 4 && g->flow_ok && (g->sweep_mode == 1 || g->sweep_mode == 2);
+  const bool bflow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;
   FlowInit fl;
   fl.err = g->d_err;
   if (flow) {
     fl.w = g->flow_w;
-    fl.r = g->flow_r;
     fl.cd = g->flow_cd;
     fl.se = g->flow_se;
     fl.km = g->side_k > 1 ? g->side_k : 0;
     fl.seed = g->sweep_mode == 2 ? 0 : 1;
   }
+  if (bflow) {
+    fl.r = g->flow_r;
+    fl.reset_blocks = flow ? 1024 : 64;
+  }
   prof_begin(g, TDP_STAGE_NETPASS, s);
   pack_xy(x, y, g->xy, tp.N, s);
-  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, nm,
+  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4) + fl.reset_blocks), dim3(256), 0, s, tp, g->lut,
+                     g->xy, nm,
                      (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
                      g->cxy_nm, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
   if (tp.n_big > 0)
@@ -852,11 +990,13 @@ void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t 
 template <typename T>
 void sta_required_impl(tdp_graph g, hipStream_t s) {
   const Topo &tp = g->topo;
-  const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;
+  const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;  // modes 1-3
   prof_begin(g, TDP_STAGE_BACKWARD, s);
   if (flow) {
     const int w = g->flow_waves;
-    hipLaunchKernelGGL(k_backward_flow, dim3(nblk(tp.n_nm_chunks, w)), dim3(64 * w), 0, s, tp,
+    const int nb = resident_blocks(g, reinterpret_cast<const void *>(&k_backward_flow), g->occ_bw, w, 0,
+                                   tp.n_nm_chunks);
+    hipLaunchKernelGGL(k_backward_flow, dim3(nb), dim3(64 * w), 0, s, tp,
                        (const float *)g->dnet_nm, (const float *)g->darc, (float *)g->rat, g->flow_r, g->d_err,
                        g->spin_limit);
     prof_end(g, TDP_STAGE_BACKWARD, s);

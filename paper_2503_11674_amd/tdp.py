@@ -109,7 +109,7 @@ tdp_nesterov_step = _sig("tdp_nesterov_step", _p, _p, _p, _p, _p, _p, _p, _p, _p
 tdp_abs_sum = _sig("tdp_abs_sum", _p, _p, _p, _p, _p)
 tdp_profile_enable = _sig("tdp_profile_enable", _p, _i32)
 tdp_profile_read = _sig("tdp_profile_read", _p, _p, _p)
-tdp_set_tuning = _sig("tdp_set_tuning", _p, _i32, _i32, _i32)
+tdp_set_tuning = _sig("tdp_set_tuning", _p, _i32, _i32, _i32, _i32)
 tdp_autotune = _sig("tdp_autotune", _p, _p, _p, _i32, _i32, _i32, _i32, _p, _p)
 tdp_graph_info = _sig("tdp_graph_info", _p, _p)
 tdp_status_str = _lib.tdp_status_str
@@ -482,20 +482,22 @@ class TimingGraph:
         _check(tdp_profile_read(self.h, ms.ctypes.data, calls.ctypes.data), self.h)
         return {s: (float(ms[i]), int(calls[i])) for i, s in enumerate(STAGES)}
 
-    def set_tuning(self, flow_waves: int = 0, spin_log2: int = 0, sweep_mode: int = 1):
-        """sweep_mode 0: one launch per level; 1: dataflow sweeps; 2: self-test
-        of the dataflow sweeps' bounded waits.  flow_waves: waves per workgroup
-        of the dataflow sweeps (1, 2, 4; 0 keeps)."""
-        _check(tdp_set_tuning(self.h, flow_waves, spin_log2, sweep_mode), self.h)
+    def set_tuning(self, flow_waves: int = 0, spin_log2: int = 0, sweep_mode: int = 1, flow_per_cu: int = 0):
+        """sweep_mode 0: one launch per level; 1: dataflow sweeps on a resident
+        grid; 2: self-test of the dataflow sweeps' bounded waits.  flow_waves:
+        waves per workgroup of the resident grids (1, 2, 4; 0 keeps);
+        flow_per_cu: their workgroups per compute unit (1..4; 0 keeps)."""
+        _check(tdp_set_tuning(self.h, flow_waves, flow_per_cu, spin_log2, sweep_mode), self.h)
 
     def autotune(self, x, y, n: int = -1, k: int = 1, K: Optional[int] = None, reps: int = 3,
                  stream=None) -> Dict[str, int]:
         """Pick the fastest sweep configuration for update + extraction."""
         K = self.max_paths if K is None else K
-        ch = np.zeros(3, np.int32)
+        ch = np.zeros(4, np.int32)
         _check(tdp_autotune(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), n, k, K, reps, ch.ctypes.data,
                             _stream(stream)), self.h)
-        return {"sweep_mode": int(ch[0]), "flow_waves": int(ch[1]), "us_per_run": int(ch[2])}
+        return {"sweep_mode": int(ch[0]), "flow_waves": int(ch[1]), "flow_per_cu": int(ch[2]),
+                "us_per_run": int(ch[3])}
 
 
 def _scalar_out(out, device) -> torch.Tensor:

@@ -1,11 +1,14 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark times (single precision, persistent dataflow sweeps, one step =
-timing update, extraction, pair update, WA and p2p forward/backward).
+benchmark times (single precision, the sweep form its autotuner picks, the
+benchmark's step: timing update, extraction, pair update, WA and p2p
+forward/backward on three streams).
 
 * 2M cells (depth 100, 12 % flip-flops, K = 100k paths): every pin's timing,
   every path, the pair set and its weights, both losses and their gradients,
   against the FP64 oracle on the same input (the oracle runs the whole size
-  in seconds); then report_timing(K) on the same graph against the oracle's.
+  in seconds); every other sweep form (per level, both sweeps on resident
+  grids, required times only on a resident grid) bitwise against that; then
+  report_timing(K) on the same graph against the oracle's.
 * 1M cells (depth 80, K = 50k, exponential pair weights): the two
   differentiable objectives through torch.autograd against the oracle's
   gradients and against central finite differences (h = 1e-3 um) of the
@@ -109,15 +112,40 @@ def test_full_size_step_2m_cells(library):
     pp = torch.zeros((), dtype=torch.float64, device=_dev())
     one = torch.ones((), dtype=torch.float64, device=_dev())
 
-    # the benchmark's step, with its side streams (beta = 1 here)
+    # the benchmark's step, with its side streams (beta = 1 here), in the
+    # sweep form the benchmark's autotuner picks
     import bench
     step = bench.build_step(g, x, y, k, K, gx, gy, wl, pp, one, overlap=True)
+    tune = g.autotune(x, y, n=-1, k=k, K=K, reps=2)
+    _log(f"autotuner: {tune}")
+
+    def run():
+        g.pairs_reset()
+        step()
+        torch.cuda.synchronize()
+        o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+        w, inp = g.pairs_export()
+        return o, g.paths(), (w, inp), gx.cpu().numpy(), gy.cpu().numpy(), float(wl), float(pp), g.summary()
+
     step()
-    g.pairs_reset()
-    step()
-    torch.cuda.synchronize()
+    res0 = run()
     _log("GPU step done")
-    o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+    # every sweep form computes the same step bitwise
+    for mode in (0, 1, 3):
+        if mode == tune["sweep_mode"]:
+            continue
+        g.set_tuning(sweep_mode=mode)
+        r = run()
+        for key in res0[0]:
+            assert np.array_equal(res0[0][key], r[0][key]), (mode, key)
+        for key in ("path_ptr", "path_pins", "path_ep", "path_rank", "path_slack"):
+            assert np.array_equal(res0[1][key], r[1][key]), (mode, key)
+        assert np.array_equal(res0[2][0], r[2][0]) and np.array_equal(res0[2][1], r[2][1]), mode
+        assert np.array_equal(res0[3], r[3]) and np.array_equal(res0[4], r[4]), mode
+        assert res0[5:] == r[5:], mode
+        _log(f"sweep mode {mode}: bitwise equal to mode {tune['sweep_mode']}")
+    g.set_tuning(sweep_mode=tune["sweep_mode"])
+    o = res0[0]
     _timing_checks(nl, st, o)
     wns, tns, nf = g.summary()
     assert nf == st["n_fail"]
@@ -136,19 +164,19 @@ def test_full_size_step_2m_cells(library):
     tol = 1e-4 * max(abs(float(nl["clock_period"])), abs(st["wns"]))
     assert np.all(np.abs(np.sort(gp["path_slack"]) - np.sort(rp["path_slack"])) <= tol)
     # pairs (one Eq. 9 round)
-    w_gpu, in_gpu = g.pairs_export()
+    w_gpu, in_gpu = res0[2]
     ps = ref.PairState(nl["num_pins"])
     ref.pairs_update(ps, rp, st["wns"], rule=0)
     _pinned_pair_checks(nl, gp, rp, pinned, w_gpu, in_gpu.astype(bool), ps.w, ps.in_p.astype(bool))
     # losses on the GPU's own pair set
     sinks = np.nonzero(in_gpu)[0]
     l_ref, px_ref, py_ref = ref.p2p(nl, sinks, w_gpu[sinks].astype(np.float64))
-    assert abs(float(pp) - l_ref) <= 1e-4 * abs(l_ref)
+    assert abs(res0[6] - l_ref) <= 1e-4 * abs(l_ref)
     v_wa, wx_ref, wy_ref, ax, ay = ref.wa(nl, 5.0, with_abs=True)
-    assert abs(float(wl) - v_wa) <= 1e-4 * abs(v_wa)
+    assert abs(res0[5] - v_wa) <= 1e-4 * abs(v_wa)
     scale = _p2p_abs_scale(nl, sinks, w_gpu[sinks])
-    ex = np.abs(gx.cpu().numpy() - (wx_ref + px_ref))
-    ey = np.abs(gy.cpu().numpy() - (wy_ref + py_ref))
+    ex = np.abs(res0[3] - (wx_ref + px_ref))
+    ey = np.abs(res0[4] - (wy_ref + py_ref))
     _log(f"gradient: worst scaled error {(ex / np.maximum(ax + scale, 1e-12)).max():.3g}")
     assert np.all(ex <= 1e-4 * (ax + scale) + 1e-6)
     assert np.all(ey <= 1e-4 * (ay + scale) + 1e-6)
@@ -168,6 +196,12 @@ def test_full_size_step_2m_cells(library):
 
 # ------------------------------------------------------------------ 1M cells
 _U64 = 2.0 ** -53
+# smoothed TNS, single precision against the oracle: per cell, relative to
+# the summed magnitudes of its net-arc gradient terms.  Each term carries an
+# adjoint made of softmax weights exp((a - A) / gamma); with arrivals below
+# 2^17 ps held to about two ulps (2^-7 ps) each, the argument is off by up to
+# 4 * 2^-7 / 10 = 3.1e-3, which is what one weight's relative error can be
+STNS_RTOL = 4e-3
 
 
 def _central_fd(fwd, x, y, cells, axis, h=1e-3):
@@ -229,19 +263,28 @@ def test_objectives_1m_cells_against_oracle_and_finite_differences(library):
     # oracle values and gradients (p2p on the GPU's own pair set)
     sinks = np.nonzero(in_gpu)[0]
     l_ref, px_ref, py_ref = ref.p2p(nl, sinks, w_gpu[sinks].astype(np.float64))
-    v_ref, sx_ref, sy_ref = ref.stns(nl, library, st, gamma=10.0)
+    v_ref, sx_ref, sy_ref, sax, say = ref.stns(nl, library, st, gamma=10.0, with_abs=True)
     assert abs(float(pp) - l_ref) <= 1e-4 * abs(l_ref)
     assert abs(float(stns) - v_ref) <= 1e-4 * abs(v_ref)
-    # single-precision gradient of the sum against the oracle: p2p per-cell
-    # scale as at 2M cells; smoothed TNS with its largest entry as the scale
-    # (its log-sum-exp weights carry the arrival times' rounding)
+    # single-precision gradient of the sum against the oracle, per cell: p2p
+    # at 1e-4 of the magnitudes of its terms as at 2M cells; the smoothed TNS
+    # at STNS_RTOL of the magnitudes of its net-arc terms (each term carries
+    # an adjoint built from log-sum-exp weights exp((a - A) / gamma) of
+    # single-precision arrival times)
     p_scale = _p2p_abs_scale(nl, sinks, w_gpu[sinks])
-    s_scale = max(np.abs(sx_ref).max(), np.abs(sy_ref).max())
     ex = np.abs(gx32 - (px_ref + sx_ref))
     ey = np.abs(gy32 - (py_ref + sy_ref))
-    _log(f"autograd vs oracle: worst {max(ex.max(), ey.max()):.3g} (stns scale {s_scale:.3g})")
-    assert np.all(ex <= 1e-4 * p_scale + 1e-3 * s_scale)
-    assert np.all(ey <= 1e-4 * p_scale + 1e-3 * s_scale)
+    # single precision cannot carry an adjoint below its resolution of the
+    # largest entry (a far-from-critical endpoint's sigmoid underflows): an
+    # absolute floor of 2^-23 of the largest smoothed-TNS entry
+    s_floor = 2.0 ** -23 * max(np.abs(sx_ref).max(), np.abs(sy_ref).max())
+    big_x, big_y = sax > 64 * s_floor, say > 64 * s_floor
+    rx = (ex - 1e-4 * p_scale)[big_x] / sax[big_x]
+    ry = (ey - 1e-4 * p_scale)[big_y] / say[big_y]
+    _log(f"autograd vs oracle: {int(big_x.sum())} / {int(big_y.sum())} cells above the floor, worst smoothed-TNS "
+         f"excess per cell scale {max(rx.max(), ry.max()):.3g} (p99 {np.percentile(np.r_[rx, ry], 99):.3g})")
+    assert np.all(ex <= 1e-4 * p_scale + STNS_RTOL * sax + s_floor)
+    assert np.all(ey <= 1e-4 * p_scale + STNS_RTOL * say + s_floor)
     # central differences of the double-precision graph (same pair set and
     # weights) on 1,000 random movable cells
     g64 = tdp.TimingGraph(nl, library, precision="f64", max_paths=K, max_k=k)
@@ -268,8 +311,9 @@ def test_objectives_1m_cells_against_oracle_and_finite_differences(library):
         assert np.all(e_p <= atol_p + 1e-6 * np.abs(gref[0][cn])[keep])
         assert np.all(e_s <= atol_s + 1e-6 * np.abs(gref[1][cn])[keep])
         # and the single-precision autograd gradient against the differences
+        s_abs = (sax if axis == 0 else say)[cn][keep]
         e32 = np.abs(g32[cn] - (fd_p + fd_s))[keep]
-        assert np.all(e32 <= 1e-4 * p_scale[cn][keep] + 1e-3 * s_scale + atol_p + atol_s)
+        assert np.all(e32 <= 1e-4 * p_scale[cn][keep] + STNS_RTOL * s_abs + s_floor + atol_p + atol_s)
         assert np.count_nonzero(np.abs(fd_p[keep]) > 0) > 10 and np.count_nonzero(np.abs(fd_s[keep]) > 0) > 10
 
 
@@ -315,7 +359,10 @@ def test_batched_workload_matches_instances_and_oracle(library):
         singles.append((g, x, y))
     gb = tdp.TimingGraph(nls, library, max_paths=K, max_k=k)
     pb, _ = gb.batch_offsets()
-    gb.sta_update(torch.cat([s[1] for s in singles]), torch.cat([s[2] for s in singles]))
+    xb, yb = torch.cat([s[1] for s in singles]), torch.cat([s[2] for s in singles])
+    # the union in the configuration the benchmark's autotuner picks for it
+    _log(f"union autotuner: {gb.autotune(xb, yb, n=-1, k=k, K=K, reps=2)}")
+    gb.sta_update(xb, yb)
     gb.extract_paths(n=-1, k=k, K=K)
     ob = gb.export()
     P = gb.paths()

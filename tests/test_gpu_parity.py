@@ -407,6 +407,42 @@ def test_pairs_and_p2p(name, library):
     assert float(g.p2p_loss_fwd(c["x"], c["y"])) == l1
 
 
+def test_whole_chain_against_the_oracle_chain(library):
+    """On the 2k-cell design every extracted path is pinned (separated from
+    its neighbours by more than the comparison threshold), so the pair set
+    is determined: the GPU's chain (timing, extraction, two Eq. 9 rounds,
+    loss) against the oracle's own chain, with no GPU value fed to the
+    oracle."""
+    tdp = _tdp()
+    c = case("C1", library)
+    nl, st, g, k, K = c["nl"], c["st"], c["g"], c["k"], c["K"]
+    g.pairs_reset()
+    g.sta_update(c["x"], c["y"])
+    g.extract_paths(n=-1, k=k, K=K)
+    gp = g.paths()
+    rp = ref.extract(nl, library, st, n=-1, k=k, K=K)
+    res = compare_paths(gp, rp, st, Graph(nl), k)
+    assert res["pinned"] == rp["num_paths"] == gp["num_paths"] and res["pinned_ok"] == res["pinned"]
+    ps = ref.PairState(nl["num_pins"])
+    for _ in range(2):
+        g.pairs_update(rule=0, w0=10.0, w1=0.2)
+        ref.pairs_update(ps, rp, st["wns"], rule=0)
+    w_gpu, in_gpu = g.pairs_export()
+    assert np.array_equal(in_gpu.astype(bool), ps.in_p.astype(bool))
+    sinks, w_ref = ps.pairs()
+    np.testing.assert_allclose(w_gpu[sinks], w_ref, rtol=1e-4)
+    l_ref, gx_ref, gy_ref = ref.p2p(nl, sinks, w_ref)
+    xr = c["x"].clone().requires_grad_(True)
+    yr = c["y"].clone().requires_grad_(True)
+    loss = tdp.P2PLoss.apply(xr, yr, g)
+    loss.backward()
+    assert abs(float(loss.detach()) - l_ref) <= 1e-4 * abs(l_ref)
+    scale = _p2p_abs_scale(nl, sinks, w_ref)
+    assert np.all(np.abs(xr.grad.cpu().numpy() - gx_ref) <= 1e-4 * scale + 1e-6)
+    assert np.all(np.abs(yr.grad.cpu().numpy() - gy_ref) <= 1e-4 * scale + 1e-6)
+    g.pairs_reset()
+
+
 def test_autograd_on_column_views_of_a_position_matrix(library):
     # placers keep positions as one [N, 2] tensor; its columns are strided
     # views, which the autograd Functions must hand to the kernels as
@@ -597,13 +633,14 @@ def test_batch_matches_single_instances(library):
 
 # ------------------------------------------------------------ sweep modes
 def test_level_and_dataflow_sweeps_agree_bitwise(library):
-    """The persistent dataflow sweeps compute exactly what the one-launch-per-
-    level sweeps compute (same operations in the same order per value)."""
+    """The resident dataflow sweeps (both, or the required times only) compute
+    exactly what the one-launch-per-level sweeps compute (same operations in
+    the same order per value)."""
     tdp = _tdp()
     c = case("C2", library)
     nl = c["nl"]
     outs = []
-    for mode in (0, 1):
+    for mode in (0, 1, 3):
         g = tdp.TimingGraph(nl, library, max_paths=c["K"], max_k=c["k"])
         g.set_tuning(sweep_mode=mode)
         g.sta_update(c["x"], c["y"])
@@ -612,12 +649,13 @@ def test_level_and_dataflow_sweeps_agree_bitwise(library):
         p = g.paths()
         outs.append((o, p, g.summary()))
         g.close()
-    (o0, p0, s0), (o1, p1, s1) = outs
-    for key in o0:
-        assert np.array_equal(o0[key], o1[key]), key
-    for key in ("path_ptr", "path_pins", "path_ep", "path_rank", "path_slack"):
-        assert np.array_equal(p0[key], p1[key]), key
-    assert s0 == s1
+    o0, p0, s0 = outs[0]
+    for o1, p1, s1 in outs[1:]:
+        for key in o0:
+            assert np.array_equal(o0[key], o1[key]), key
+        for key in ("path_ptr", "path_pins", "path_ep", "path_rank", "path_slack"):
+            assert np.array_equal(p0[key], p1[key]), key
+        assert s0 == s1
 
 
 def test_wide_cells_match_oracle_and_dataflow(library):
@@ -633,7 +671,7 @@ def test_wide_cells_match_oracle_and_dataflow(library):
     assert widths.max() > 4 and (widths <= 4).mean() > 0.3
     k, K = 4, 2000
     outs = []
-    for mode in (0, 1):
+    for mode in (0, 1, 3):
         g = tdp.TimingGraph(nl, library, max_paths=K, max_k=k)
         g.set_tuning(sweep_mode=mode)
         g.sta_update(*_xy(nl))
@@ -641,11 +679,12 @@ def test_wide_cells_match_oracle_and_dataflow(library):
         g.extract_paths(n=-1, k=k, K=K)
         outs.append((o, g.paths()))
         g.close()
-    (o0, p0), (o1, p1) = outs
-    for key in o0:
-        assert np.array_equal(o0[key], o1[key]), key
-    for key in ("path_ptr", "path_pins", "path_slack"):
-        assert np.array_equal(p0[key], p1[key]), key
+    o0, p0 = outs[0]
+    for o1, p1 in outs[1:]:
+        for key in o0:
+            assert np.array_equal(o0[key], o1[key]), key
+        for key in ("path_ptr", "path_pins", "path_slack"):
+            assert np.array_equal(p0[key], p1[key]), key
     for key in ("at", "rat"):
         inf_ok, bad, worst = timing_close(o0[key], st[key],
                                           scale=np.maximum(np.abs(np.nan_to_num(st["at"], posinf=0, neginf=0)),
@@ -765,7 +804,8 @@ def test_autotune_keeps_results(library):
     g = tdp.TimingGraph(c["nl"], library, max_paths=c["K"], max_k=c["k"])
     ch = g.autotune(c["x"], c["y"], n=-1, k=c["k"], K=c["K"], reps=2)
     print("autotune choice", ch)
-    assert ch["sweep_mode"] in (0, 1) and ch["flow_waves"] in (1, 2, 4) and ch["us_per_run"] > 0
+    assert ch["sweep_mode"] in (0, 1, 3) and ch["flow_waves"] in (1, 2, 4) and ch["flow_per_cu"] in (1, 2, 4)
+    assert ch["us_per_run"] > 0
     o = {k: v.cpu().numpy() for k, v in g.export().items()}
     for key in o:
         assert np.array_equal(o[key], c["gpu"][key]), key

@@ -462,6 +462,13 @@ def test_stns_two_input_closed_form(flip, g):
     for got, want in zip(gx, (gx0, gx1, gx2)):
         assert math.isclose(got, want, rel_tol=1e-14, abs_tol=1e-16), (gx, (gx0, gx1, gx2))
     assert np.all(gy == 0.0)  # every wire is horizontal: sign(0) = 0
+    # the magnitudes of the same terms, per cell (the scale of rounding error)
+    _, _, _, ax, ay = ref.stns(nl, lib, st, gamma=g, with_abs=True)
+    a = abs(ab_end)
+    want_abs = (a * w_buf * (16.0 / 32 + 32.0 / 32), a * w_dir * (48.0 / 32) + a * w_buf + a, a)
+    for got, want in zip(ax, want_abs):
+        assert math.isclose(got, want, rel_tol=1e-14), (ax, want_abs)
+    assert np.all(ay == 0.0)
 
 
 def test_stns_tends_to_hard_tns_as_gamma_vanishes(c1, library):
