@@ -232,6 +232,20 @@ tdp_status tdp_extract_paths(tdp_graph, int32_t n, int32_t k, int32_t K, float s
  * TDP_E_CAPACITY if more paths tie at the K-th slack than the store holds
  * (8 * max_paths nodes, at least E * max_k). */
 tdp_status tdp_report_timing(tdp_graph, int32_t K, float slack_limit, hipStream_t, tdp_paths *out);
+/* For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc): tdp_report_timing with its node store and sort /
+ * scan scratch carved from a fixed 64 MiB device array that the library
+ * holds on every device it runs on until the process ends; the call
+ * allocates nothing.  Same arguments, outputs and results (bitwise) as
+ * tdp_report_timing.  The store holds max(8 * max_paths, E * max_k, 4096)
+ * nodes at 60 bytes each in single precision (68 in double) plus the sort's
+ * histograms, so graphs up to about a million nodes fit; a larger one gets
+ * TDP_E_CAPACITY with the size it needs, and nothing runs.  Every call on a
+ * device shares that device's array and leaves its contents behind: calls
+ * that overlap on one device (other host threads, other graphs) race, so
+ * the caller orders them.  Errors otherwise as tdp_report_timing, and
+ * TDP_E_DEVICE if the array's device address cannot be obtained. */
+tdp_status tdp_report_timing_noalloc(tdp_graph, int32_t K, float slack_limit, hipStream_t, tdp_paths *out);
 /* Number of paths and of path pins of the last extraction (synchronises). */
 tdp_status tdp_paths_count(tdp_graph, int32_t *num_paths, int32_t *num_pins, hipStream_t);
 

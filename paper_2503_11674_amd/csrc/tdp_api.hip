@@ -6,12 +6,21 @@
 #include <cstring>
 #include <limits>
 #include <vector>
+#include <mutex>
 #include <new>
+#include <string>
 
 #include "tdp_impl.h"
 #include "tdp_prims.h"
 
 using namespace tdp;
+
+// The no-allocation variant of report_timing keeps its node store in this
+// fixed array, one copy per device, held until the process ends.  Host code
+// never uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+static constexpr size_t kNoallocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
 
 namespace {
 
@@ -416,11 +425,22 @@ tdp_status tdp_extract_paths(tdp_graph g, int32_t n, int32_t k, int32_t K, float
 }
 
 // the node store of report_timing(K), made on its first call
-static tdp_status ensure_global(tdp_graph g) {
+}  // extern "C" (reopened below)
+
+namespace tdp {
+int report_node_cap(const tdp_graph_s *g) {
+  const int64_t want = std::max<int64_t>({(int64_t)8 * g->max_out, (int64_t)g->slot_cap, 4096});
+  return (int)std::min<int64_t>(want, (int64_t)1 << 27);
+}
+}  // namespace tdp
+
+namespace {
+
+// the graph's node store, allocated by the first report_timing call
+tdp_status ensure_global(tdp_graph g) {
   if (g->gcap > 0) return TDP_OK;
   const Topo &T = g->topo;
-  const int64_t want = std::max<int64_t>({(int64_t)8 * g->max_out, (int64_t)g->slot_cap, 4096});
-  const int cap = (int)std::min<int64_t>(want, (int64_t)1 << 27);
+  const int cap = report_node_cap(g);
   const size_t es = g->esz;
   const int scan_cap = std::max(cap, sort_hist_size(cap));
   const bool ok = dalloc(g, g->gt_cost, cap, es) && dalloc(g, g->gt_key, cap, es) &&
@@ -435,18 +455,94 @@ static tdp_status ensure_global(tdp_graph g) {
   return TDP_OK;
 }
 
-tdp_status tdp_report_timing(tdp_graph g, int32_t K, float slack_limit, hipStream_t s, tdp_paths *out) {
-  GUARD(g);
-  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
-  if (K < 0) return fail(g, TDP_E_INVALID, "K < 0");
-  if (std::isnan(slack_limit)) return fail(g, TDP_E_INVALID, "slack_limit is NaN");
-  tdp_status st = ensure_global(g);
-  if (st != TDP_OK) return st;
+GtStore graph_store(tdp_graph g) {
+  GtStore st;
+  st.cap = g->gcap;
+  st.gt_cost = g->gt_cost;
+  st.gt_key = g->gt_key;
+  st.gt_theta = g->gt_theta;
+  st.gt_dev = g->gt_dev;
+  st.gt_par = g->gt_par;
+  st.gt_ep = g->gt_ep;
+  st.gt_cells = g->gt_cells;
+  st.gt_nd = g->gt_nd;
+  st.gt_cnt = g->gt_cnt;
+  st.gt_off = g->gt_off;
+  st.gt_start = g->gt_start;
+  st.gt_end = g->gt_end;
+  st.gt_misc = g->gt_misc;
+  st.gt_k0 = g->gt_k0;
+  st.gt_k1 = g->gt_k1;
+  st.gt_v0 = g->gt_v0;
+  st.gt_v1 = g->gt_v1;
+  st.gt_hist = g->gt_hist;
+  st.gt_scan = g->gt_scan;
+  return st;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+tdp_status scratch_address(tdp_graph g, unsigned char **out) {
+  if (g->device < 0 || g->device >= kMaxDevices) return fail(g, TDP_E_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[g->device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(g, TDP_E_DEVICE, std::string("no-allocation scratch: hipGetSymbolAddress failed: ") +
+                                       hipGetErrorString(e));
+    g_scratch_ptr[g->device] = (unsigned char *)p;
+  }
+  *out = g_scratch_ptr[g->device];
+  return TDP_OK;
+}
+
+// carve the node store for `cap` nodes out of [base, base + limit); returns
+// the bytes it needs (more than limit: nothing carved)
+size_t carve_store(const tdp_graph_s *g, int cap, unsigned char *base, size_t limit, GtStore &st) {
+  const size_t es = g->esz, ni = (size_t)g->topo.num_inst;
+  const int scan_cap = std::max(cap, sort_hist_size(cap));
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void * {
+    void *p = base + off;
+    off += (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+    return p;
+  };
+  const size_t c = (size_t)cap;
+  st.cap = cap;
+  st.gt_cost = take(c * es);
+  st.gt_key = take(c * es);
+  st.gt_theta = take(ni * es);
+  st.gt_dev = (int32_t *)take(c * 4);
+  st.gt_par = (int32_t *)take(c * 4);
+  st.gt_ep = (int32_t *)take(c * 4);
+  st.gt_cells = (int32_t *)take(c * 4);
+  st.gt_nd = (int32_t *)take(c * 4);
+  st.gt_cnt = (int32_t *)take(c * 4);
+  st.gt_off = (int32_t *)take(c * 4);
+  st.gt_start = (int32_t *)take(ni * 4);
+  st.gt_end = (int32_t *)take(ni * 4);
+  st.gt_misc = (int32_t *)take(16);
+  st.gt_k0 = (uint64_t *)take(c * 8);
+  st.gt_k1 = (uint64_t *)take(c * 8);
+  st.gt_v0 = (uint32_t *)take(c * 4);
+  st.gt_v1 = (uint32_t *)take(c * 4);
+  st.gt_hist = (int32_t *)take((size_t)sort_hist_size(cap) * 4);
+  st.gt_scan = (int32_t *)take((size_t)scan_tmp_size(scan_cap) * 4);
+  if (off > limit) st = GtStore{};
+  return off;
+}
+
+tdp_status report_common(tdp_graph g, const GtStore &st, int32_t K, float slack_limit, hipStream_t s,
+                         tdp_paths *out) {
   const int Keff = std::min(K, g->max_out_inst);
-  dispatch(g, [&](auto z) { st = report_impl<decltype(z)>(g, Keff, slack_limit, s); });
-  if (st != TDP_OK) return st;
-  st = check_launch(g, "report_timing");
-  if (st != TDP_OK) return st;
+  tdp_status rs = TDP_OK;
+  dispatch(g, [&](auto z) { rs = report_impl<decltype(z)>(g, st, Keff, slack_limit, s); });
+  if (rs != TDP_OK) return rs;
+  rs = check_launch(g, "report_timing");
+  if (rs != TDP_OK) return rs;
   g->extracted = true;
   g->last_k = 1;
   if (out) {
@@ -459,6 +555,38 @@ tdp_status tdp_report_timing(tdp_graph g, int32_t K, float slack_limit, hipStrea
     out->path_slack = g->path_slack;
   }
   return TDP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdp_status tdp_report_timing(tdp_graph g, int32_t K, float slack_limit, hipStream_t s, tdp_paths *out) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (K < 0) return fail(g, TDP_E_INVALID, "K < 0");
+  if (std::isnan(slack_limit)) return fail(g, TDP_E_INVALID, "slack_limit is NaN");
+  tdp_status st = ensure_global(g);
+  if (st != TDP_OK) return st;
+  return report_common(g, graph_store(g), K, slack_limit, s, out);
+}
+
+tdp_status tdp_report_timing_noalloc(tdp_graph g, int32_t K, float slack_limit, hipStream_t s, tdp_paths *out) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (K < 0) return fail(g, TDP_E_INVALID, "K < 0");
+  if (std::isnan(slack_limit)) return fail(g, TDP_E_INVALID, "slack_limit is NaN");
+  unsigned char *base = nullptr;
+  tdp_status st = scratch_address(g, &base);
+  if (st != TDP_OK) return st;
+  GtStore gs;
+  const size_t need = carve_store(g, report_node_cap(g), base, kNoallocBytes, gs);
+  if (need > kNoallocBytes)
+    return fail(g, TDP_E_CAPACITY,
+                "report_timing_noalloc: this graph's node store needs " + std::to_string(need) +
+                    " bytes, more than the fixed " + std::to_string(kNoallocBytes) +
+                    " (max_paths and max_k set its size; use tdp_report_timing)");
+  return report_common(g, gs, K, slack_limit, s, out);
 }
 
 tdp_status tdp_paths_count(tdp_graph g, int32_t *num_paths, int32_t *num_pins, hipStream_t s) {

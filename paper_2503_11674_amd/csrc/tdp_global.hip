@@ -322,23 +322,25 @@ __global__ void k_gt_rank_write(const int32_t *__restrict__ d_num_paths, const i
 }
 
 template <typename T, int KM>
-void expand_round(tdp_graph g, const Ctx<T> &cx, const Nodes<T> &nd, int fb, int n, int fe, hipStream_t s) {
+void expand_round(tdp_graph g, const GtStore &st, const Ctx<T> &cx, const Nodes<T> &nd, int fb, int n, int fe,
+                  hipStream_t s) {
   const Topo &tp = g->topo;
-  hipLaunchKernelGGL((k_gt_count<T, KM>), dim3(nb(n, 256)), dim3(256), 0, s, tp, cx, nd, fb, n, g->gt_cnt);
-  scan_exclusive(g->gt_cnt, g->gt_off, n, nullptr, g->gt_misc, g->gt_scan, s);
-  hipLaunchKernelGGL((k_gt_emit<T, KM>), dim3(nb(n, 256)), dim3(256), 0, s, tp, cx, nd, fb, n, fe, g->gcap,
-                     g->gt_off);
+  hipLaunchKernelGGL((k_gt_count<T, KM>), dim3(nb(n, 256)), dim3(256), 0, s, tp, cx, nd, fb, n, st.gt_cnt);
+  scan_exclusive(st.gt_cnt, st.gt_off, n, nullptr, st.gt_misc, st.gt_scan, s);
+  hipLaunchKernelGGL((k_gt_emit<T, KM>), dim3(nb(n, 256)), dim3(256), 0, s, tp, cx, nd, fb, n, fe, st.cap,
+                     st.gt_off);
 }
 
 template <typename T>
-void expand(tdp_graph g, const Ctx<T> &cx, const Nodes<T> &nd, int fb, int n, int fe, hipStream_t s) {
+void expand(tdp_graph g, const GtStore &st, const Ctx<T> &cx, const Nodes<T> &nd, int fb, int n, int fe,
+            hipStream_t s) {
   switch (g->side_k) {
-    case 1: expand_round<T, 1>(g, cx, nd, fb, n, fe, s); break;
-    case 2: expand_round<T, 2>(g, cx, nd, fb, n, fe, s); break;
-    case 4: expand_round<T, 4>(g, cx, nd, fb, n, fe, s); break;
-    case 8: expand_round<T, 8>(g, cx, nd, fb, n, fe, s); break;
-    case 16: expand_round<T, 16>(g, cx, nd, fb, n, fe, s); break;
-    default: expand_round<T, 32>(g, cx, nd, fb, n, fe, s); break;
+    case 1: expand_round<T, 1>(g, st, cx, nd, fb, n, fe, s); break;
+    case 2: expand_round<T, 2>(g, st, cx, nd, fb, n, fe, s); break;
+    case 4: expand_round<T, 4>(g, st, cx, nd, fb, n, fe, s); break;
+    case 8: expand_round<T, 8>(g, st, cx, nd, fb, n, fe, s); break;
+    case 16: expand_round<T, 16>(g, st, cx, nd, fb, n, fe, s); break;
+    default: expand_round<T, 32>(g, st, cx, nd, fb, n, fe, s); break;
   }
 }
 
@@ -349,26 +351,26 @@ bool read_i32(const int32_t *d, int32_t *h, hipStream_t s) {
 // sort nodes [0, n) by (instance, slack) into gt_k0 / gt_v0 and find each
 // instance's range
 template <typename T>
-void sort_nodes(tdp_graph g, const Nodes<T> &nd, int n, hipStream_t s) {
+void sort_nodes(tdp_graph g, const GtStore &st, const Nodes<T> &nd, int n, hipStream_t s) {
   const Topo &tp = g->topo;
-  hipLaunchKernelGGL(k_gt_keys<T>, dim3(nb(n, 256)), dim3(256), 0, s, tp, n, nd.ep, nd.key, g->gt_k0, g->gt_v0);
-  radix_sort(g->gt_k0, g->gt_v0, g->gt_k1, g->gt_v1, n, nullptr, sizeof(T) == 4 ? g->key_bits32 : 64, g->gt_hist,
-             g->gt_scan, s);
-  fill_i32(g->gt_start, tp.num_inst, 0, s);
-  fill_i32(g->gt_end, tp.num_inst, 0, s);
-  hipLaunchKernelGGL(k_gt_segments, dim3(nb(n, 256)), dim3(256), 0, s, n, sizeof(T) == 4 ? 1 : 0, g->gt_k0,
-                     g->gt_start, g->gt_end);
+  hipLaunchKernelGGL(k_gt_keys<T>, dim3(nb(n, 256)), dim3(256), 0, s, tp, n, nd.ep, nd.key, st.gt_k0, st.gt_v0);
+  radix_sort(st.gt_k0, st.gt_v0, st.gt_k1, st.gt_v1, n, nullptr, sizeof(T) == 4 ? g->key_bits32 : 64, st.gt_hist,
+             st.gt_scan, s);
+  fill_i32(st.gt_start, tp.num_inst, 0, s);
+  fill_i32(st.gt_end, tp.num_inst, 0, s);
+  hipLaunchKernelGGL(k_gt_segments, dim3(nb(n, 256)), dim3(256), 0, s, n, sizeof(T) == 4 ? 1 : 0, st.gt_k0,
+                     st.gt_start, st.gt_end);
 }
 
 }  // namespace
 
 template <typename T>
-tdp_status report_impl(tdp_graph g, int K, float slack_limit, hipStream_t s) {
+tdp_status report_impl(tdp_graph g, const GtStore &st, int K, float slack_limit, hipStream_t s) {
   const Topo &tp = g->topo;
-  const int cap = g->gcap;
-  Nodes<T> nd{(T *)g->gt_cost, (T *)g->gt_key, g->gt_dev, g->gt_par, g->gt_ep, g->gt_cells, g->gt_nd};
+  const int cap = st.cap;
+  Nodes<T> nd{(T *)st.gt_cost, (T *)st.gt_key, st.gt_dev, st.gt_par, st.gt_ep, st.gt_cells, st.gt_nd};
   Ctx<T> cx{(const T *)g->at, (const T *)g->darc, (const T *)g->side_cost, (const T *)g->ep_slack,
-            (const T *)g->gt_theta, g->crit, g->side_pin, g->cdep, (T)slack_limit};
+            (const T *)st.gt_theta, g->crit, g->side_pin, g->cdep, (T)slack_limit};
   int total = 0;
   if (K > 0 && tp.E > 0) {
     // bound from the per-endpoint search at the K worst endpoints
@@ -377,25 +379,25 @@ tdp_status report_impl(tdp_graph g, int K, float slack_limit, hipStream_t s) {
     search_stage<T>(g, k, slack_limit, s);
     slot_sort_stage<T>(g, k, s);
     hipLaunchKernelGGL(k_gt_theta0<T>, dim3(1), dim3(1), 0, s, tp.num_inst, k, K, g->inst_nsel, g->inst_nvalid,
-                       g->sort_v0, (const T *)g->slot_key, (T *)g->gt_theta);
+                       g->sort_v0, (const T *)g->slot_key, (T *)st.gt_theta);
     constexpr int kMaxRestarts = 64;
     for (int attempt = 0;; ++attempt) {
       if (attempt == kMaxRestarts)
         return gt_fail(g, TDP_E_CAPACITY, "report_timing: too many paths share the K-th slack for the node store");
       hipLaunchKernelGGL(k_gt_root_flags<T>, dim3(nb(tp.E, 256)), dim3(256), 0, s, tp, (const T *)g->ep_slack,
-                         (const T *)g->gt_theta, (T)slack_limit, g->sel_flag);
-      scan_exclusive(g->sel_flag, g->sel_pos, tp.E, nullptr, g->gt_misc + 1, g->scan_tmp, s);
+                         (const T *)st.gt_theta, (T)slack_limit, g->sel_flag);
+      scan_exclusive(g->sel_flag, g->sel_pos, tp.E, nullptr, st.gt_misc + 1, g->scan_tmp, s);
       hipLaunchKernelGGL(k_gt_roots<T>, dim3(nb(tp.E, 256)), dim3(256), 0, s, tp, g->sel_flag, g->sel_pos,
                          (const T *)g->ep_slack, g->cdep, cap, nd);
       int32_t nroots = 0;
-      if (!read_i32(g->gt_misc + 1, &nroots, s)) return gt_fail(g, TDP_E_DEVICE, "report_timing: count copy failed");
+      if (!read_i32(st.gt_misc + 1, &nroots, s)) return gt_fail(g, TDP_E_DEVICE, "report_timing: count copy failed");
       bool over = nroots > cap;
       int fb = 0, fe = over ? cap : nroots;
       while (!over && fb < fe) {
         const int n = fe - fb;
-        expand<T>(g, cx, nd, fb, n, fe, s);
+        expand<T>(g, st, cx, nd, fb, n, fe, s);
         int32_t add = 0;
-        if (!read_i32(g->gt_misc, &add, s)) return gt_fail(g, TDP_E_DEVICE, "report_timing: count copy failed");
+        if (!read_i32(st.gt_misc, &add, s)) return gt_fail(g, TDP_E_DEVICE, "report_timing: count copy failed");
         if ((long long)fe + add > cap) {
           over = true;
           fe = cap;
@@ -407,27 +409,27 @@ tdp_status report_impl(tdp_graph g, int K, float slack_limit, hipStream_t s) {
       total = fe;
       if (!over) break;
       // the store is full of real paths: tighten the bound and start again
-      sort_nodes<T>(g, nd, cap, s);
-      hipLaunchKernelGGL(k_gt_refine<T>, dim3(1), dim3(1), 0, s, tp.num_inst, K, g->gt_start, g->gt_end, g->gt_v0,
-                         (const T *)g->gt_key, (T *)g->gt_theta, g->gt_misc);
+      sort_nodes<T>(g, st, nd, cap, s);
+      hipLaunchKernelGGL(k_gt_refine<T>, dim3(1), dim3(1), 0, s, tp.num_inst, K, st.gt_start, st.gt_end, st.gt_v0,
+                         (const T *)st.gt_key, (T *)st.gt_theta, st.gt_misc);
       int32_t moved = 0;
-      if (!read_i32(g->gt_misc + 2, &moved, s)) return gt_fail(g, TDP_E_DEVICE, "report_timing: count copy failed");
+      if (!read_i32(st.gt_misc + 2, &moved, s)) return gt_fail(g, TDP_E_DEVICE, "report_timing: count copy failed");
       if (!moved)
         return gt_fail(g, TDP_E_CAPACITY, "report_timing: more paths share the K-th slack than the node store holds");
     }
   }
   // order, cut to K per instance, walk
   if (total > 0) {
-    sort_nodes<T>(g, nd, total, s);
+    sort_nodes<T>(g, st, nd, total, s);
   } else {
-    fill_i32(g->gt_start, tp.num_inst, 0, s);
-    fill_i32(g->gt_end, tp.num_inst, 0, s);
+    fill_i32(st.gt_start, tp.num_inst, 0, s);
+    fill_i32(st.gt_end, tp.num_inst, 0, s);
   }
-  hipLaunchKernelGGL(k_gt_bases, dim3(1), dim3(1), 0, s, tp.num_inst, K, g->gt_start, g->gt_end, g->inst_outb,
+  hipLaunchKernelGGL(k_gt_bases, dim3(1), dim3(1), 0, s, tp.num_inst, K, st.gt_start, st.gt_end, g->inst_outb,
                      g->inst_kept, g->d_num_paths, g->d_nslots);
   if (total > 0)
     hipLaunchKernelGGL(k_gt_index<T>, dim3(nb(total, 256)), dim3(256), 0, s, total, sizeof(T) == 4 ? 1 : 0,
-                       g->gt_k0, g->gt_v0, g->gt_start, g->inst_outb, g->inst_kept, g->gt_cells, g->out_slot,
+                       st.gt_k0, st.gt_v0, st.gt_start, g->inst_outb, g->inst_kept, st.gt_cells, g->out_slot,
                        g->out_len, g->slot_out);
   scan_exclusive(g->out_len, g->path_ptr, g->max_out, g->d_num_paths, nullptr, g->scan_tmp, s);
   ptr_tail(g->d_num_paths, g->out_len, g->path_ptr, s);
@@ -436,19 +438,19 @@ tdp_status report_impl(tdp_graph g, int K, float slack_limit, hipStream_t s) {
                      (T *)g->path_slack, g->d_err, g->pin_cap);
   // ranks per endpoint (the node store is free again: its arrays serve as scratch)
   const int mo = g->max_out;
-  hipLaunchKernelGGL(k_gt_rank_keys, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, g->path_epi, g->gt_k0,
-                     g->gt_v0);
-  radix_sort(g->gt_k0, g->gt_v0, g->gt_k1, g->gt_v1, mo, g->d_num_paths, 32, g->gt_hist, g->gt_scan, s);
-  hipLaunchKernelGGL(k_gt_rank_heads, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, g->gt_k0, g->gt_cnt);
-  scan_exclusive(g->gt_cnt, g->gt_off, mo, g->d_num_paths, nullptr, g->gt_scan, s);
-  hipLaunchKernelGGL(k_gt_rank_starts, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, g->gt_cnt, g->gt_off,
-                     g->gt_dev);
-  hipLaunchKernelGGL(k_gt_rank_write, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, g->gt_cnt, g->gt_off,
-                     g->gt_dev, g->gt_v0, g->path_rank);
+  hipLaunchKernelGGL(k_gt_rank_keys, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, g->path_epi, st.gt_k0,
+                     st.gt_v0);
+  radix_sort(st.gt_k0, st.gt_v0, st.gt_k1, st.gt_v1, mo, g->d_num_paths, 32, st.gt_hist, st.gt_scan, s);
+  hipLaunchKernelGGL(k_gt_rank_heads, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, st.gt_k0, st.gt_cnt);
+  scan_exclusive(st.gt_cnt, st.gt_off, mo, g->d_num_paths, nullptr, st.gt_scan, s);
+  hipLaunchKernelGGL(k_gt_rank_starts, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, st.gt_cnt, st.gt_off,
+                     st.gt_dev);
+  hipLaunchKernelGGL(k_gt_rank_write, dim3(nb(mo, 256)), dim3(256), 0, s, g->d_num_paths, st.gt_cnt, st.gt_off,
+                     st.gt_dev, st.gt_v0, g->path_rank);
   return TDP_OK;
 }
 
-template tdp_status report_impl<float>(tdp_graph, int, float, hipStream_t);
-template tdp_status report_impl<double>(tdp_graph, int, float, hipStream_t);
+template tdp_status report_impl<float>(tdp_graph, const GtStore &, int, float, hipStream_t);
+template tdp_status report_impl<double>(tdp_graph, const GtStore &, int, float, hipStream_t);
 
 }  // namespace tdp

@@ -35,8 +35,22 @@ template <typename T> void select_stage(tdp_graph g, int n, hipStream_t s);
 template <typename T> void search_stage(tdp_graph g, int k, float slack_limit, hipStream_t s);
 template <typename T> void slot_sort_stage(tdp_graph g, int k, hipStream_t s);
 void ptr_tail(const int32_t *d_num_paths, const int32_t *len, int32_t *ptr, hipStream_t s);
+// report_timing(K)'s node store and its sort / scan scratch: the graph's own
+// (allocated by the first call) or carved from the fixed device array of the
+// no-allocation entry point
+struct GtStore {
+  int cap = 0;  // nodes
+  void *gt_cost = nullptr, *gt_key = nullptr, *gt_theta = nullptr;
+  int32_t *gt_dev = nullptr, *gt_par = nullptr, *gt_ep = nullptr, *gt_cells = nullptr, *gt_nd = nullptr;
+  int32_t *gt_cnt = nullptr, *gt_off = nullptr, *gt_start = nullptr, *gt_end = nullptr, *gt_misc = nullptr;
+  uint64_t *gt_k0 = nullptr, *gt_k1 = nullptr;
+  uint32_t *gt_v0 = nullptr, *gt_v1 = nullptr;
+  int32_t *gt_hist = nullptr, *gt_scan = nullptr;
+};
+// node capacity report_timing(K) uses for graph g
+int report_node_cap(const tdp_graph_s *g);
 // report_timing(K); returns a status (it synchronises on s)
-template <typename T> tdp_status report_impl(tdp_graph g, int K, float slack_limit, hipStream_t s);
+template <typename T> tdp_status report_impl(tdp_graph g, const GtStore &st, int K, float slack_limit, hipStream_t s);
 template <typename T> void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s);
 void pairs_rebuild(tdp_graph g, hipStream_t s);
 void pairs_compact(tdp_graph g, hipStream_t s);

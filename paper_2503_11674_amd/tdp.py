@@ -85,6 +85,7 @@ tdp_sta_export = _sig("tdp_sta_export", _p, _p, _p, _p, _p, _p, _p, _p, _p)
 tdp_sta_export_crit = _sig("tdp_sta_export_crit", _p, _p, _p)
 tdp_extract_paths = _sig("tdp_extract_paths", _p, _i32, _i32, _i32, _f32, _p, _P(tdp_paths))
 tdp_report_timing = _sig("tdp_report_timing", _p, _i32, _f32, _p, _P(tdp_paths))
+tdp_report_timing_noalloc = _sig("tdp_report_timing_noalloc", _p, _i32, _f32, _p, _P(tdp_paths))
 tdp_paths_count = _sig("tdp_paths_count", _p, _P(_i32), _P(_i32), _p)
 tdp_pairs_update = _sig("tdp_pairs_update", _p, _i32, _f32, _f32, _p)
 tdp_pairs_reset = _sig("tdp_pairs_reset", _p, _p)
@@ -121,7 +122,7 @@ tdp_last_error.argtypes = [_p]
 
 EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destroy", "tdp_sta_set_clock",
             "tdp_sta_update", "tdp_sta_update_arrivals", "tdp_sta_update_required", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit",
-            "tdp_extract_paths", "tdp_report_timing", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
+            "tdp_extract_paths", "tdp_report_timing", "tdp_report_timing_noalloc", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
             "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
             "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_wa_fwd_bwd_at_update", "tdp_sta_update_early",
@@ -305,6 +306,15 @@ class TimingGraph:
         Synchronises the stream."""
         p = tdp_paths()
         _check(tdp_report_timing(self.h, K, slack_limit, _stream(stream), ctypes.byref(p)), self.h)
+        self._paths = p
+        return p
+
+    def report_timing_noalloc(self, K: int, slack_limit: float = math.inf, stream=None) -> tdp_paths:
+        """report_timing(K) with its node store in the library's fixed device
+        array (no device allocation); TdpError (capacity) when the graph's
+        store does not fit it."""
+        p = tdp_paths()
+        _check(tdp_report_timing_noalloc(self.h, K, slack_limit, _stream(stream), ctypes.byref(p)), self.h)
         self._paths = p
         return p
 
