@@ -137,8 +137,9 @@ typedef struct {
 } tdp_paths;
 
 /* ---------------------------------------------------------------- build */
-/* Validate and levelise the timing graph, renumber it for the device and
- * upload it.  max_paths bounds n*k of any later extraction, max_k bounds k
+/* The timing graph of Sec. II-B (pins as nodes, net and cell arcs as edges,
+ * flip-flop Q pins and primary inputs as start points, D pins as endpoints):
+ * validate and levelise it, renumber it for the device and upload it.  max_paths bounds n*k of any later extraction, max_k bounds k
  * (1..32; max_k > 1 makes every update also keep, per cell, the max_k
  * cheapest deviations along its critical fan-in chain).  Errors:
  * TDP_E_INVALID (index out of range, a pin in zero or two nets, a port that
@@ -147,7 +148,8 @@ typedef struct {
 tdp_status tdp_sta_build(const tdp_netlist *netlist, const tdp_library *lib, tdp_precision prec,
                          int32_t max_paths, int32_t max_k, int device, tdp_graph *out);
 
-/* Batched form: the graphs of `count` netlists become one disjoint union
+/* Batched form (not in the paper: many designs or placement snapshots timed
+ * together): the graphs of `count` netlists become one disjoint union
  * (instance-major numbering, external ids offset by the preceding instances'
  * pin and cell counts); every later call runs all instances in the same
  * launches.  Per-instance quantities (clock period and setup, WNS/TNS,
@@ -162,15 +164,16 @@ tdp_status tdp_batch_offsets(tdp_graph, int32_t *pin_base, int32_t *cell_base);
 
 void tdp_destroy(tdp_graph);
 
-/* Change the required time at every D pin (period - setup), in every
- * instance of a batched graph.  Synchronous (a small host-to-device copy). */
+/* Change the required time at every D pin (period - setup, the endpoint
+ * required time of Eq. 2), in every instance of a batched graph.
+ * Synchronous (a small host-to-device copy). */
 tdp_status tdp_sta_set_clock(tdp_graph, float clock_period_ps, float setup_ps);
 
 /* ------------------------------------------------------------------ STA */
-/* Full timing update from cell positions (device float [num_cells] each):
- * net delays and loads, arrival times and transitions forward by level,
- * endpoint slacks and WNS / TNS / violated-endpoint count, required times and
- * slack backward.  Asynchronous. */
+/* Full timing update from cell positions (device float [num_cells] each),
+ * Sec. II-B: net delays (Eq. 7) and loads, arrival times and transitions
+ * forward by level, endpoint slacks and WNS / TNS / violated-endpoint count
+ * (Eqs. 3-4), required times (Eq. 2) and slack backward.  Asynchronous. */
 tdp_status tdp_sta_update(tdp_graph, const float *d_x, const float *d_y, hipStream_t);
 /* The same update in two passes, for callers that overlap work on several
  * streams:
@@ -192,8 +195,9 @@ tdp_status tdp_sta_update_required(tdp_graph, hipStream_t);
 tdp_status tdp_sta_summary(tdp_graph, double *wns, double *tns, int32_t *n_fail, hipStream_t);
 tdp_status tdp_batch_summary(tdp_graph, double *wns, double *tns, int32_t *n_fail, hipStream_t);
 
-/* Per-pin results of the last update in external pin order, as double device
- * arrays [num_pins] (any pointer may be NULL):
+/* Per-pin results of the last update (Sec. II-B: arrival, required time
+ * and slack = required - arrival per pin) in external pin order, as double
+ * device arrays [num_pins] (any pointer may be NULL):
  *   at, rat, slack, slew (at a sink pin, the transition its cell arc or
  *   setup check sees: degraded by the wire under net model 1);
  *   dnet (net delay into a sink pin, 0 elsewhere),
@@ -202,9 +206,19 @@ tdp_status tdp_batch_summary(tdp_graph, double *wns, double *tns, int32_t *n_fai
  * Unconstrained pins (no endpoint downstream) have rat = slack = +inf. */
 tdp_status tdp_sta_export(tdp_graph, double *d_at, double *d_rat, double *d_slack, double *d_slew,
                           double *d_dnet, double *d_load, double *d_darc, hipStream_t);
-/* Arc index of the input that sets each combinational cell's arrival
- * (lowest index on ties), -1 for flip-flops; int32 device [num_cells]. */
+/* Arc index of the input that sets each combinational cell's arrival (the
+ * maximum of Sec. II-B's forward propagation; lowest index on ties), -1 for
+ * flip-flops; int32 device [num_cells]. */
 tdp_status tdp_sta_export_crit(tdp_graph, int32_t *d_crit, hipStream_t);
+/* Zero-copy views of the last update's arrival and required times (Sec.
+ * II-B), in the graph's precision (float for TDP_F32, double for TDP_F64)
+ * and in the device's pin order, with the map from external pin id to that
+ * order: at[pin_index[p]] is pin p's arrival, rat[pin_index[p]] its
+ * required time (slack = rat - at; it is not stored, tdp_sta_export forms
+ * it).  All three are device pointers owned by the graph: read them on the
+ * update's stream, or after it; they hold the next update's values once it
+ * runs and are freed by tdp_destroy.  TDP_E_STATE before the first update. */
+tdp_status tdp_sta_views(tdp_graph, const void **d_at, const void **d_rat, const int32_t **d_pin_index);
 
 /* ------------------------------------------------------------- paths */
 /* report_timing_endpoint(n, k): endpoints ordered by (slack, pin id); n >= 0
@@ -289,7 +303,8 @@ tdp_status tdp_pair_loss_fwd(tdp_graph, int32_t kind, const float *d_x, const fl
 tdp_status tdp_pair_loss_bwd(tdp_graph, int32_t kind, const float *d_x, const float *d_y, const double *d_gout,
                              float *d_gx, float *d_gy, hipStream_t);
 
-/* Smoothed TNS: cell-arc delays and start arrivals frozen from the last
+/* Smoothed TNS (not in the paper: a differentiable stand-in for the TNS of
+ * Eq. 4): cell-arc delays and start arrivals frozen from the last
  * update, net delays from d_x/d_y; log-sum-exp over fan-in with temperature
  * gamma_ps, value = -gamma * sum over endpoints of softplus(-slack/gamma).
  * fwd overwrites *d_val; bwd (same positions as the last fwd) adds
@@ -299,8 +314,9 @@ tdp_status tdp_stns_fwd(tdp_graph, const float *d_x, const float *d_y, float gam
                         hipStream_t);
 tdp_status tdp_stns_bwd(tdp_graph, const double *d_gout, float *d_gx, float *d_gy, hipStream_t);
 
-/* Weighted-average wirelength over every net (driver and sinks, ports too),
- * both axes, temperature gamma_um.  *d_wl (one device double) is overwritten;
+/* Weighted-average wirelength (the WL term of Eq. 1, in the smooth form the
+ * paper's placer uses) over every net (driver and sinks, ports too), both
+ * axes, temperature gamma_um.  *d_wl (one device double) is overwritten;
  * d_gx/d_gy [num_cells] += gradient (movable cells only). */
 tdp_status tdp_wa_fwd_bwd(tdp_graph, const float *d_x, const float *d_y, float gamma_um, double *d_wl,
                           float *d_gx, float *d_gy, hipStream_t);
@@ -313,7 +329,9 @@ tdp_status tdp_wa_fwd_bwd_at_update(tdp_graph, float gamma_um, double *d_wl, flo
                                     hipStream_t);
 
 /* ------------------------------------------------ early (hold) analysis */
-/* The early half of an early/late timer, on the net delays and loads of the
+/* The early half of an early/late timer (the paper's timer, Sec. II-B /
+ * III-B, runs both; its objective uses the late half), on the net delays and
+ * loads of the
  * last tdp_sta_update (TDP_E_STATE before one).  Start points arrive as in
  * the late analysis; a sink at its driver's early arrival plus the net delay
  * (transition from the driver's early transition as the net model gives

@@ -399,6 +399,15 @@ tdp_status tdp_sta_export_crit(tdp_graph g, int32_t *crit, hipStream_t s) {
   return check_launch(g, "sta_export_crit");
 }
 
+tdp_status tdp_sta_views(tdp_graph g, const void **at, const void **rat, const int32_t **pin_index) {
+  GUARD(g);
+  if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
+  if (at) *at = g->at;
+  if (rat) *rat = g->rat;
+  if (pin_index) *pin_index = g->topo.ext_pin_int;
+  return TDP_OK;
+}
+
 tdp_status tdp_extract_paths(tdp_graph g, int32_t n, int32_t k, int32_t K, float slack_limit, hipStream_t s,
                              tdp_paths *out) {
   GUARD(g);

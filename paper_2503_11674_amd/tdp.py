@@ -85,6 +85,7 @@ tdp_sta_export = _sig("tdp_sta_export", _p, _p, _p, _p, _p, _p, _p, _p, _p)
 tdp_sta_export_crit = _sig("tdp_sta_export_crit", _p, _p, _p)
 tdp_extract_paths = _sig("tdp_extract_paths", _p, _i32, _i32, _i32, _f32, _p, _P(tdp_paths))
 tdp_report_timing = _sig("tdp_report_timing", _p, _i32, _f32, _p, _P(tdp_paths))
+tdp_sta_views = _sig("tdp_sta_views", _p, _P(_p), _P(_p), _P(_p))
 tdp_report_timing_noalloc = _sig("tdp_report_timing_noalloc", _p, _i32, _f32, _p, _P(tdp_paths))
 tdp_paths_count = _sig("tdp_paths_count", _p, _P(_i32), _P(_i32), _p)
 tdp_pairs_update = _sig("tdp_pairs_update", _p, _i32, _f32, _f32, _p)
@@ -121,7 +122,7 @@ tdp_last_error.restype = ctypes.c_char_p
 tdp_last_error.argtypes = [_p]
 
 EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destroy", "tdp_sta_set_clock",
-            "tdp_sta_update", "tdp_sta_update_arrivals", "tdp_sta_update_required", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit",
+            "tdp_sta_update", "tdp_sta_update_arrivals", "tdp_sta_update_required", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit", "tdp_sta_views",
             "tdp_extract_paths", "tdp_report_timing", "tdp_report_timing_noalloc", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
             "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
@@ -290,6 +291,21 @@ class TimingGraph:
         _check(tdp_sta_export_crit(self.h, _ptr(crit), _stream(stream)), self.h)
         out["crit"] = crit
         return out
+
+    def views(self) -> Dict[str, torch.Tensor]:
+        """Zero-copy tensors over the graph's own arrival and required times
+        (graph precision, device pin order) and the map from external pin id
+        to that order (int32): at[pin_index[p]] is pin p's arrival.  They
+        hold the next update's values once it runs; do not use them after
+        close(), and do not write to them (torch's import of a device array
+        has no read-only flag)."""
+        at, rat, idx = _p(), _p(), _p()
+        _check(tdp_sta_views(self.h, ctypes.byref(at), ctypes.byref(rat), ctypes.byref(idx)), self.h)
+        ts = "<f8" if self.prec == TDP_F64 else "<f4"
+        dev = torch.device("cuda", self.device)
+        return {"at": torch.as_tensor(_DeviceView(at.value, self.num_pins, ts, self), device=dev),
+                "rat": torch.as_tensor(_DeviceView(rat.value, self.num_pins, ts, self), device=dev),
+                "pin_index": torch.as_tensor(_DeviceView(idx.value, self.num_pins, "<i4", self), device=dev)}
 
     # ----------------------------------------------------------- paths
     def extract_paths(self, n: int = -1, k: int = 1, K: Optional[int] = None,
@@ -508,6 +524,16 @@ class TimingGraph:
                             _stream(stream)), self.h)
         return {"sweep_mode": int(ch[0]), "flow_waves": int(ch[1]), "flow_per_cu": int(ch[2]),
                 "us_per_run": int(ch[3])}
+
+
+class _DeviceView:
+    """A device array owned by a graph, exposed through the CUDA array
+    interface (which torch imports without a copy); keeps the graph alive."""
+
+    def __init__(self, ptr: int, n: int, typestr: str, owner):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 2,
+                                         "strides": None}
+        self._owner = owner
 
 
 def _scalar_out(out, device) -> torch.Tensor:

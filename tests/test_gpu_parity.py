@@ -443,6 +443,29 @@ def test_whole_chain_against_the_oracle_chain(library):
     g.pairs_reset()
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_zero_copy_timing_views(precision, library):
+    """tdp_sta_views: the graph's own arrival / required arrays in device pin
+    order, read through the external-to-device pin map, equal the export;
+    the same tensors show the next update's values."""
+    tdp = _tdp()
+    c = case("C1", library)
+    nl = c["nl"]
+    g = tdp.TimingGraph(nl, library, precision=precision, max_paths=200, max_k=4)
+    g.sta_update(c["x"], c["y"])
+    v = g.views()
+    assert v["at"].dtype == (torch.float64 if precision == "f64" else torch.float32)
+    idx = v["pin_index"].long()
+    o = g.export()
+    assert torch.equal(v["at"][idx].double(), o["at"]) and torch.equal(v["rat"][idx].double(), o["rat"])
+    g.sta_update(c["x"] + 7.0, c["y"])
+    o2 = g.export()
+    assert not torch.equal(o2["at"], o["at"])
+    assert torch.equal(v["at"][idx].double(), o2["at"]) and torch.equal(v["rat"][idx].double(), o2["rat"])
+    del v
+    g.close()
+
+
 def test_autograd_on_column_views_of_a_position_matrix(library):
     # placers keep positions as one [N, 2] tensor; its columns are strided
     # views, which the autograd Functions must hand to the kernels as
