@@ -111,6 +111,63 @@ def sta(nl, lib, x=None, y=None, clock_period: Optional[float] = None) -> Dict[s
     return out
 
 
+def sta_rf(nl, lib, x=None, y=None, clock_period: Optional[float] = None) -> Dict[str, np.ndarray]:
+    """Rise / fall timing.  `lib` carries, beside the single-transition
+    library (its tables are the rise tables), delay_fall / slew_fall and
+    unate[num_types] (0 positive, 1 negative, 2 non-unate).  Per-pin arrays
+    are [P, 2] (rise, fall); crit [N, 2] = 2 j + y per output transition;
+    ep_slack [P] at D pins (+inf elsewhere)."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    T = float(nl["clock_period"] if clock_period is None else clock_period)
+    P, N = int(nl["num_pins"]), int(nl["num_cells"])
+    out = {k: np.empty(2 * P, np.float64) for k in ("at", "slew", "rat", "slack")}
+    ep = np.empty(P, np.float64)
+    crit = np.empty(2 * N, np.int32)
+    summ = np.zeros(3, np.float64)
+    na, k1 = _netlist_args(nl)
+    la, k2 = _lib_args(lib)
+    df, sf, un = _f32(lib["delay_fall"]), _f32(lib["slew_fall"]), _i32(lib["unate"])
+    rc = L.ora_sta_rf(*na, *la, _p(df), _p(sf), _p(un), _p(x), _p(y), ctypes.c_double(T),
+                      ctypes.c_double(float(nl["setup"])), ctypes.c_double(float(nl["input_slew"])),
+                      ctypes.c_double(float(nl["clock_slew"])), _p(out["at"]), _p(out["slew"]), _p(out["rat"]),
+                      _p(out["slack"]), _p(ep), _p(crit), _p(summ))
+    if rc != 0:
+        raise ValueError("timing graph has a cycle")
+    res = {k: v.reshape(P, 2) for k, v in out.items()}
+    res["ep_slack"] = ep
+    res["crit"] = crit.reshape(N, 2)
+    res["wns"], res["tns"], res["n_fail"] = float(summ[0]), float(summ[1]), int(summ[2])
+    res["clock_period"] = T
+    return res
+
+
+def extract_rf(nl, st, n: int = -1, K: int = 1 << 30) -> Dict[str, np.ndarray]:
+    """report_timing_endpoint(n, 1) under rise / fall timing (from sta_rf's
+    results): paths with their pins' transitions (0 rise, 1 fall)."""
+    L = _load()
+    P = int(nl["num_pins"])
+    E = int(np.count_nonzero(np.asarray(nl["cell_is_ff"])))
+    cap = min(K, E)
+    depth = int(nl.get("depth", 0)) or P
+    ptr = np.zeros(cap + 1, np.int32)
+    pins = np.zeros(max(1, cap * min(P, 2 * depth + 2)), np.int32)
+    tran = np.zeros_like(pins)
+    slack = np.zeros(max(1, cap), np.float64)
+    eps = np.zeros(max(1, cap), np.int32)
+    na, keep = _netlist_args(nl)
+    sl, es, cr = _f64(st["slack"].reshape(-1)), _f64(st["ep_slack"]), _i32(st["crit"].reshape(-1))
+    m = L.ora_extract_rf(*na, _p(sl), _p(es), _p(cr), ctypes.c_int(n), ctypes.c_int(cap), _p(ptr), _p(pins),
+                         _p(tran), _p(slack), _p(eps))
+    if m < 0:
+        raise ValueError("timing graph has a cycle")
+    w = int(ptr[m])
+    return {"num_paths": int(m), "path_ptr": ptr[:m + 1].copy(), "path_pins": pins[:w].copy(),
+            "path_tran": tran[:w].copy(), "path_slack": slack[:m].copy(), "path_ep": eps[:m].copy(),
+            "path_rank": np.zeros(m, np.int32)}
+
+
 def endpoint_pins(nl) -> np.ndarray:
     ff = np.nonzero(np.asarray(nl["cell_is_ff"]) != 0)[0]
     ptr = np.asarray(nl["cell_in_ptr"])

@@ -24,6 +24,9 @@
  *                  arrivals at best-case transitions and the hold check at
  *                  the D pins (not used by the paper's objective, which is
  *                  setup TNS / WNS; a fuller timing model around it).
+ *   ora_sta_rf   - rise / fall timing: both transitions of every pin, cell
+ *                  arcs by unateness, with report_timing_endpoint(n, 1) on it
+ *                  (ora_extract_rf); a fuller timing model around the paper's.
  *   ora_extract  - report_timing_endpoint(n, k) (Sec. III-B, Table I): the n
  *                  most critical endpoints, and the k worst paths at each.
  *                  Reached by deviation (sidetrack) enumeration from the
@@ -1047,6 +1050,231 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
   free(A); free(Ab); free(dn);
   conn_free(&c);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* rise / fall timing                                                        */
+/* ------------------------------------------------------------------------ */
+/* A fuller timing model around the paper's (its timer, Sec. II-B / III-B,
+ * times both transitions of every pin; the paper fixes neither a library nor
+ * this detail, so the definition here is the contract).  Every pin carries
+ * two transitions, rise (index 0) and fall (index 1).  The arcs of a cell
+ * type have a unateness:
+ *   0 positive: an input rise causes an output rise, a fall a fall;
+ *   1 negative: an input rise causes an output fall, a fall a rise;
+ *   2 non-unate: either input transition causes either output transition.
+ * The output rise of type t is looked up in the rise tables (delay_lut /
+ * slew_lut), the output fall in delay_fall / slew_fall; a flip-flop's Q rises
+ * and falls by its clock-to-Q tables at the clock slew.  A net carries a
+ * transition unchanged, with the same delay and degradation either way.
+ *   sink t:           AT_y(t) = AT_y(drv) + dnet(t), slew_y(t) from slew_y(drv)
+ *   comb output o, transition x:
+ *     AT_x(o)   = max over inputs j and input transitions y that cause x of
+ *                 AT_y(i_j) + D_x(slew_y(i_j), load(o))
+ *     crit_x(o) = the first (j, y) attaining it, j ascending, rise before fall
+ *     slew_x(o) = max over the same (j, y) of S_x(slew_y(i_j), load(o))
+ *   D pin e:          slack_y(e) = (T - setup) - AT_y(e); the endpoint's slack
+ *                     is the smaller of the two (Eqs. 3-4 over endpoints)
+ *   required:         RAT_y(e) = T - setup at a D pin; RAT_y(i_j) = min over
+ *                     the x that y causes of RAT_x(o) - D_x(slew_y(i_j), load);
+ *                     RAT_y(drv) = min over sinks of RAT_y(t) - dnet(t)
+ * Arrays indexed [2 * pin + transition]; crit [2 * cell + x] = 2 j + y (-1 for
+ * flip-flops and unreached outputs); ep_slack [P] the endpoint slack at D pins
+ * (+inf elsewhere); summary[3] = {WNS, TNS, violated endpoints}. */
+static int rf_causes(int unate, int y, int x) {
+  if (unate == 2) return 1;
+  return unate == 0 ? y == x : y != x;
+}
+
+int ora_sta_rf(NETLIST_ARGS, LIB_ARGS, const float *delay_fall, const float *slew_fall, const int32_t *unate,
+               const float *x, const float *y, double clock_period, double setup, double input_slew,
+               double clock_slew, double *at, double *slew, double *rat, double *slack, double *ep_slack,
+               int32_t *crit, double *summary) {
+  FILL_NETLIST(n);
+  FILL_LIB(L);
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  int P = num_pins, N = num_cells, M = num_nets;
+  double *dnet = (double *)calloc(P, sizeof(double));
+  double *load = (double *)calloc(P, sizeof(double));
+  for (int q = 0; q < 2 * P; ++q) { at[q] = -INFINITY; slew[q] = 0.0; rat[q] = INFINITY; slack[q] = INFINITY; }
+  for (int p = 0; p < P; ++p) ep_slack[p] = INFINITY;
+  for (int q = 0; q < 2 * N; ++q) crit[q] = -1;
+  const float *dtab[2] = {delay_lut, delay_fall}, *stab[2] = {slew_lut, slew_fall};
+
+  for (int net = 0; net < M; ++net) {
+    int s = net_pins[net_ptr[net]];
+    double xs, ys;
+    pin_xy(&n, x, y, s, &xs, &ys);
+    double ld = 0.0;
+    for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
+      int t = net_pins[k];
+      double xt, yt;
+      pin_xy(&n, x, y, t, &xt, &yt);
+      double len = fabs(xs - xt) + fabs(ys - yt);
+      double cap = (double)pin_cap[cell_type[pin_cell[t]]];
+      dnet[t] = net_delay(&L, len, cap);
+      ld += cap + L.c * len;
+    }
+    load[s] = ld;
+  }
+
+  for (int q = 0; q < P; ++q) {
+    int p = c.topo[q];
+    int role = c.role[p];
+    if (role == ROLE_PORT) {
+      for (int tr = 0; tr < 2; ++tr) { at[2 * p + tr] = 0.0; slew[2 * p + tr] = input_slew; }
+    } else if (role == ROLE_FFQ) {
+      int type = cell_type[pin_cell[p]];
+      for (int tr = 0; tr < 2; ++tr) {
+        at[2 * p + tr] = lut_eval(&L, dtab[tr], type, clock_slew, load[p]);
+        slew[2 * p + tr] = lut_eval(&L, stab[tr], type, clock_slew, load[p]);
+      }
+    } else if (role == ROLE_CIN || role == ROLE_FFD) {
+      int d = c.driver[p];
+      if (d >= 0)
+        for (int tr = 0; tr < 2; ++tr) {
+          at[2 * p + tr] = at[2 * d + tr] + dnet[p];
+          slew[2 * p + tr] = sink_slew(&L, slew[2 * d + tr], dnet[p]);
+        }
+    } else { /* ROLE_COUT */
+      int cell = pin_cell[p], type = cell_type[cell];
+      for (int xo = 0; xo < 2; ++xo) {
+        double best = -INFINITY, sl = 0.0;
+        int arg = -1;
+        for (int k = cell_in_ptr[cell]; k < cell_in_ptr[cell + 1]; ++k) {
+          int i = cell_in_pins[k];
+          for (int yi = 0; yi < 2; ++yi) {
+            if (!rf_causes(unate[type], yi, xo) || at[2 * i + yi] == -INFINITY) continue;
+            double a = at[2 * i + yi] + lut_eval(&L, dtab[xo], type, slew[2 * i + yi], load[p]);
+            double so = lut_eval(&L, stab[xo], type, slew[2 * i + yi], load[p]);
+            if (a > best) { best = a; arg = 2 * (k - cell_in_ptr[cell]) + yi; }
+            if (so > sl) sl = so;
+          }
+        }
+        at[2 * p + xo] = best;
+        slew[2 * p + xo] = sl;
+        crit[2 * cell + xo] = arg;
+      }
+    }
+  }
+
+  double req = clock_period - setup, wns = 0.0, tns = 0.0;
+  int nfail = 0;
+  for (int p = 0; p < P; ++p) {
+    if (c.role[p] != ROLE_FFD) continue;
+    double worst = INFINITY;
+    for (int tr = 0; tr < 2; ++tr) {
+      rat[2 * p + tr] = req;
+      if (at[2 * p + tr] == -INFINITY) continue;
+      double sl = req - at[2 * p + tr];
+      if (sl < worst) worst = sl;
+    }
+    ep_slack[p] = worst;
+    if (worst < 0) { ++nfail; tns += worst; if (worst < wns) wns = worst; }
+  }
+  summary[0] = wns; summary[1] = tns; summary[2] = nfail;
+
+  for (int q = P - 1; q >= 0; --q) {
+    int p = c.topo[q];
+    int role = c.role[p];
+    if (role == ROLE_FFD) continue;
+    if (role == ROLE_CIN) {
+      int cell = pin_cell[p], type = cell_type[cell], o = cell_out_pin[cell];
+      for (int yi = 0; yi < 2; ++yi) {
+        double r = INFINITY;
+        for (int xo = 0; xo < 2; ++xo) {
+          if (!rf_causes(unate[type], yi, xo) || rat[2 * o + xo] == INFINITY) continue;
+          double v = rat[2 * o + xo] - lut_eval(&L, dtab[xo], type, slew[2 * p + yi], load[o]);
+          if (v < r) r = v;
+        }
+        rat[2 * p + yi] = r;
+      }
+    } else { /* a driver: port, comb output or Q */
+      int net = c.net_of[p];
+      for (int tr = 0; tr < 2; ++tr) {
+        double r = INFINITY;
+        if (net >= 0)
+          for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
+            int t = net_pins[k];
+            if (rat[2 * t + tr] == INFINITY) continue;
+            double v = rat[2 * t + tr] - dnet[t];
+            if (v < r) r = v;
+          }
+        rat[2 * p + tr] = r;
+      }
+    }
+  }
+  for (int q = 0; q < 2 * P; ++q)
+    slack[q] = (rat[q] == INFINITY || at[q] == -INFINITY) ? INFINITY : rat[q] - at[q];
+  free(dnet); free(load);
+  conn_free(&c);
+  return 0;
+}
+
+/* report_timing_endpoint(n, 1) under rise / fall timing: endpoints ordered by
+ * (endpoint slack, pin id), the first n (n < 0: the violated ones) with finite
+ * slack, cut to K; each endpoint's path ends in its worse transition (rise on
+ * a tie) and follows crit back to a start point.  Path pins are written start
+ * to end (path_ptr [K+1], path_pins / path_tran [K * (2 depth + 2)]), with
+ * the endpoint pin and the path slack (= the endpoint's slack).  Returns the
+ * number of paths. */
+typedef struct { double slack; int pin; } orfep;
+static int orfep_cmp(const void *a, const void *b) {
+  const orfep *u = (const orfep *)a, *v = (const orfep *)b;
+  if (u->slack < v->slack) return -1;
+  if (u->slack > v->slack) return 1;
+  return u->pin - v->pin;
+}
+
+int ora_extract_rf(NETLIST_ARGS, const double *rf_slack, const double *ep_slack, const int32_t *crit, int n_sel,
+                   int K, int32_t *path_ptr, int32_t *path_pins, int32_t *path_tran, double *path_slack,
+                   int32_t *path_ep) {
+  FILL_NETLIST(n);
+  oconn c;
+  if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
+  int P = num_pins;
+  orfep *eps = (orfep *)malloc(sizeof(orfep) * (P > 0 ? P : 1));
+  int ne = 0, nviol = 0;
+  for (int p = 0; p < P; ++p)
+    if (c.role[p] == ROLE_FFD && ep_slack[p] != INFINITY) {
+      eps[ne].slack = ep_slack[p];
+      eps[ne].pin = p;
+      if (ep_slack[p] < 0) ++nviol;
+      ++ne;
+    }
+  qsort(eps, ne, sizeof(orfep), orfep_cmp);
+  int m = n_sel < 0 ? nviol : (n_sel < ne ? n_sel : ne);
+  if (m > K) m = K;
+  int *rev = (int *)malloc(sizeof(int) * 2 * (P + 1));
+  int *revt = (int *)malloc(sizeof(int) * 2 * (P + 1));
+  int w = 0;
+  path_ptr[0] = 0;
+  for (int q = 0; q < m; ++q) {
+    int e = eps[q].pin;
+    int tr = rf_slack[2 * e] <= rf_slack[2 * e + 1] ? 0 : 1;
+    int len = 0, p = e;
+    for (;;) {
+      rev[len] = p; revt[len] = tr; ++len;
+      int d = c.driver[p];
+      if (d < 0) break;
+      rev[len] = d; revt[len] = tr; ++len;
+      if (c.role[d] != ROLE_COUT) break;
+      int cell = pin_cell[d];
+      int cr = crit[2 * cell + tr];
+      if (cr < 0) break;
+      p = cell_in_pins[cell_in_ptr[cell] + cr / 2];
+      tr = cr % 2;
+    }
+    for (int i = 0; i < len; ++i) { path_pins[w + i] = rev[len - 1 - i]; path_tran[w + i] = revt[len - 1 - i]; }
+    w += len;
+    path_ptr[q + 1] = w;
+    path_slack[q] = eps[q].slack;
+    path_ep[q] = e;
+  }
+  free(rev); free(revt); free(eps);
+  conn_free(&c);
+  return m;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -161,6 +161,26 @@ def make_library(seed: int = LIB_SEED) -> Dict[str, np.ndarray]:
     }
 
 
+RF_SEED = 2504
+
+
+def make_rf_library(lib: Dict, seed: int = RF_SEED) -> Dict[str, np.ndarray]:
+    """Rise / fall form of a library: its tables become the output-rise
+    tables; the output-fall tables follow the same recipe from another seed
+    (monotone, 5..80 ps; the transition table again equals the delay table);
+    arc unateness per type: types 0-2 positive, 3-5 negative, 6 non-unate (the
+    flip-flop, type 7, rises and falls by its own tables)."""
+    fall = make_library(seed)
+    out = dict(lib)
+    out["delay_fall"] = fall["delay_lut"].copy()
+    out["slew_fall"] = fall["delay_lut"].copy()
+    unate = np.zeros(int(lib["num_types"]), np.int32)
+    unate[3:6] = 1
+    unate[6] = 2
+    out["unate"] = unate
+    return out
+
+
 # --------------------------------------------------------------------------
 # netlist topology
 # --------------------------------------------------------------------------
