@@ -560,6 +560,28 @@ def main():
     early = {"ms": round(e0.elapsed_time(e1) / 10, 4), "hold_ps": round(hold, 1), "whs": round(whs, 1),
              "ths": round(ths, 1), "n_hold_fail": n_hold}
 
+    # rise / fall timing on the same positions, outside the step: the update
+    # and report_timing_endpoint(n_fail, 1) on it
+    rf_lib = netgen.make_rf_library(lib)
+    g.rf_setup(rf_lib)
+    g.sta_update_rf(x, y)
+    g.extract_paths_rf(n=-1)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(5):
+        g.sta_update_rf(x, y)
+    e1.record()
+    for _ in range(5):
+        g.extract_paths_rf(n=-1)
+    e2.record()
+    e2.synchronize()
+    rf_w, rf_t, rf_n = g.rf_summary()
+    rise_fall = {"update_ms": round(e0.elapsed_time(e1) / 5, 4), "extract_k1_ms": round(e1.elapsed_time(e2) / 5, 4),
+                 "wns": round(rf_w, 1), "tns": round(rf_t, 1), "n_fail": rf_n, "paths": g.paths_count()[0]}
+    g.sta_update(x, y)  # back to the single-transition state
+    torch.cuda.synchronize()
+
     sta_ms = sum(stages[s]["ms"] for s in ("netpass", "forward", "endpoint", "backward") if s in stages)
     ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
     loss_ms = sum(stages[s]["ms"] for s in ("p2p_fwd", "p2p_bwd") if s in stages)
@@ -609,6 +631,7 @@ def main():
         "stages": stages,
         "pair_losses_ms": pair_ms,
         "early_analysis": early,
+        "rise_fall": rise_fall,
         "roofline": roof,
         "graph_replay": bool(graph is not None),
         "streams": 1 if a.serial else 3,

@@ -220,6 +220,57 @@ tdp_status tdp_sta_export_crit(tdp_graph, int32_t *d_crit, hipStream_t);
  * runs and are freed by tdp_destroy.  TDP_E_STATE before the first update. */
 tdp_status tdp_sta_views(tdp_graph, const void **d_at, const void **d_rat, const int32_t **d_pin_index);
 
+/* ------------------------------------------------------- rise / fall */
+/* Rise / fall timing: a fuller model around the paper's (its timer, Sec.
+ * II-B / III-B, times both transitions of every pin; the paper fixes neither
+ * library nor this detail).  Every pin carries a rise and a fall.  A cell
+ * type's arcs are positive unate (unate 0: input rise -> output rise, fall ->
+ * fall), negative unate (1: rise -> fall, fall -> rise) or non-unate (2:
+ * either -> either).  The library's delay_lut / slew_lut give the output
+ * rise, these tables ([num_types][n_slew][n_load], host, copied) the output
+ * fall; a flip-flop's Q rises and falls by them at the clock slew.  A net
+ * passes a transition with the same delay either way.  Output transition x:
+ * arrival = max over (input j, input transition y that causes x) of arrival
+ * + table delay at y's transition, critical = the first (j, y) attaining it
+ * (j ascending, rise first), transition = the maximum of the table
+ * transitions.  An endpoint's slack is the smaller of its two; WNS / TNS /
+ * count as Eqs. 3-4 over endpoints.  Required times per transition: a D pin's
+ * is period - setup; an input's the minimum over the outputs it causes of
+ * (required - arc delay); a driver's the minimum over its sinks. */
+typedef struct {
+  const float *delay_fall, *slew_fall;
+  const int32_t *unate;  /* [num_types] */
+} tdp_rf_tables;
+/* Set (or replace) the tables and allocate the rise / fall arrays
+ * (synchronous).  TDP_E_UNSUPPORTED on a batched graph, TDP_E_INVALID on a
+ * bad unateness or a non-finite entry. */
+tdp_status tdp_rf_setup(tdp_graph, const tdp_rf_tables *tables);
+/* Rise / fall update from cell positions (device float [num_cells] each):
+ * net delays and loads as tdp_sta_update, arrivals, transitions, critical
+ * inputs, endpoint slacks, WNS / TNS, required times.  It replaces the graph's
+ * endpoint slacks and summary, so the single-transition results read as not
+ * updated (TDP_E_STATE) until the next tdp_sta_update.  Asynchronous;
+ * TDP_E_STATE before tdp_rf_setup. */
+tdp_status tdp_sta_update_rf(tdp_graph, const float *d_x, const float *d_y, hipStream_t);
+/* WNS, TNS and violated count of the last rise / fall update; synchronises. */
+tdp_status tdp_sta_rf_summary(tdp_graph, double *wns, double *tns, int32_t *n_fail, hipStream_t);
+/* Double device arrays [2 * num_pins] in external pin order, [2 p] the
+ * rise and [2 p + 1] the fall (any may be NULL): arrival, required time,
+ * slack (+inf where either is infinite) and transition. */
+tdp_status tdp_sta_rf_export(tdp_graph, double *d_at, double *d_rat, double *d_slack, double *d_slew,
+                             hipStream_t);
+/* report_timing_endpoint(n, 1) (Sec. III-B, Table I) on the rise / fall
+ * update: the n endpoints of smallest slack (n < 0: every violated one),
+ * ordered by (slack, pin id) and cut to K (and to max_paths), one path each,
+ * ending in the endpoint's worse transition (rise on a tie) and following the
+ * critical (input, transition) pairs back to a start point.  Output as
+ * tdp_extract_paths, plus *d_path_tran (may be NULL): a device uint8 view,
+ * parallel to path_pins, of each pin's transition (0 rise, 1 fall).  The pair
+ * update then takes these paths.  TDP_E_STATE before a rise / fall update,
+ * TDP_E_CAPACITY if n > max_paths. */
+tdp_status tdp_extract_paths_rf(tdp_graph, int32_t n, int32_t K, hipStream_t, tdp_paths *out,
+                                const uint8_t **d_path_tran);
+
 /* ------------------------------------------------------------- paths */
 /* report_timing_endpoint(n, k): endpoints ordered by (slack, pin id); n >= 0
  * takes the first n, n < 0 the violated ones (device-side count, no host

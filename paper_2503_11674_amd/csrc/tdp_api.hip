@@ -318,6 +318,7 @@ tdp_status tdp_sta_update(tdp_graph g, const float *x, const float *y, hipStream
   GUARD(g);
   if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
   g->ea_ready = false;  // the hold results belong to the previous placement
+  g->rf_updated = false;
   dispatch(g, [&](auto z) {
     sta_arrivals_impl<decltype(z)>(g, x, y, s);
     sta_required_impl<decltype(z)>(g, s);
@@ -331,6 +332,7 @@ tdp_status tdp_sta_update_arrivals(tdp_graph g, const float *x, const float *y, 
   GUARD(g);
   if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
   g->ea_ready = false;
+  g->rf_updated = false;
   dispatch(g, [&](auto z) { sta_arrivals_impl<decltype(z)>(g, x, y, s); });
   tdp_status st = check_launch(g, "sta_update_arrivals");
   if (st == TDP_OK) g->updated = true;
@@ -389,6 +391,95 @@ tdp_status tdp_sta_export(tdp_graph g, double *at, double *rat, double *slack, d
   if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
   dispatch(g, [&](auto z) { sta_export_impl<decltype(z)>(g, at, rat, slack, slew, dnet, load, darc, s); });
   return check_launch(g, "sta_export");
+}
+
+tdp_status tdp_rf_setup(tdp_graph g, const tdp_rf_tables *rt) {
+  GUARD(g);
+  if (!rt || !rt->delay_fall || !rt->slew_fall || !rt->unate) return fail(g, TDP_E_INVALID, "NULL rise/fall table");
+  if (g->topo.num_inst > 1) return fail(g, TDP_E_UNSUPPORTED, "rise / fall timing on a batched graph");
+  const Topo &T = g->topo;
+  const int nt = g->lut.nt, ntab = nt * g->lut.ns * g->lut.nl;
+  for (int t = 0; t < nt; ++t)
+    if (rt->unate[t] < 0 || rt->unate[t] > 2) return fail(g, TDP_E_INVALID, "unate must be 0, 1 or 2");
+  for (int i = 0; i < ntab; ++i)
+    if (!std::isfinite(rt->delay_fall[i]) || !std::isfinite(rt->slew_fall[i]))
+      return fail(g, TDP_E_INVALID, "rise/fall tables must be finite");
+  if (!g->rf_ready) {
+    const size_t es = g->esz;
+    const bool ok = dalloc(g, g->rf_at, (size_t)2 * T.P, es) && dalloc(g, g->rf_slew, (size_t)2 * T.P, es) &&
+                    dalloc(g, g->rf_rat, (size_t)2 * T.P, es) && dalloc(g, g->rf_darc4, (size_t)4 * T.A, es) &&
+                    dalloc(g, g->rf_crit, (size_t)2 * T.n_comb) && dalloc(g, g->rf_unate, nt) &&
+                    dalloc(g, g->rf_delay_fall, ntab) && dalloc(g, g->rf_slew_fall, ntab) &&
+                    dalloc(g, g->rf_path_tran, g->pin_cap);
+    if (!ok) return fail(g, TDP_E_NOMEM, "rise/fall: device allocation failed");
+  }
+  if (hipMemcpy(g->rf_unate, rt->unate, sizeof(int32_t) * nt, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->rf_delay_fall, rt->delay_fall, sizeof(float) * ntab, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g->rf_slew_fall, rt->slew_fall, sizeof(float) * ntab, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "rise/fall: table upload failed");
+  g->rf_ready = true;
+  g->rf_updated = false;
+  return TDP_OK;
+}
+
+tdp_status tdp_sta_update_rf(tdp_graph g, const float *x, const float *y, hipStream_t s) {
+  GUARD(g);
+  if (!g->rf_ready) return fail(g, TDP_E_STATE, "rise/fall tables not set (tdp_rf_setup)");
+  if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
+  // the single-transition results (and everything derived from them) are
+  // replaced: the endpoint slacks and WNS / TNS now hold the rise/fall ones
+  g->updated = false;
+  g->extracted = false;
+  g->ea_ready = false;
+  g->stns_ready = false;
+  dispatch(g, [&](auto z) { rf_update_impl<decltype(z)>(g, x, y, s); });
+  tdp_status st = check_launch(g, "sta_update_rf");
+  if (st == TDP_OK) g->rf_updated = true;
+  return st;
+}
+
+tdp_status tdp_sta_rf_summary(tdp_graph g, double *wns, double *tns, int32_t *n_fail, hipStream_t s) {
+  GUARD(g);
+  if (!g->rf_updated) return fail(g, TDP_E_STATE, "no rise/fall update yet");
+  double h[4] = {0, 0, 0, 0};
+  if (hipStreamSynchronize(s) != hipSuccess ||
+      hipMemcpy(h, g->summary, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(g, TDP_E_DEVICE, "summary copy failed");
+  if (wns) *wns = std::min(0.0, h[0]);
+  if (tns) *tns = h[1];
+  if (n_fail) *n_fail = (int32_t)h[2];
+  return TDP_OK;
+}
+
+tdp_status tdp_sta_rf_export(tdp_graph g, double *at, double *rat, double *slack, double *slew, hipStream_t s) {
+  GUARD(g);
+  if (!g->rf_updated) return fail(g, TDP_E_STATE, "no rise/fall update yet");
+  dispatch(g, [&](auto z) { rf_export_impl<decltype(z)>(g, at, rat, slack, slew, s); });
+  return check_launch(g, "sta_rf_export");
+}
+
+tdp_status tdp_extract_paths_rf(tdp_graph g, int32_t n, int32_t K, hipStream_t s, tdp_paths *out,
+                                const uint8_t **d_path_tran) {
+  GUARD(g);
+  if (!g->rf_updated) return fail(g, TDP_E_STATE, "no rise/fall update yet");
+  if (K < 0) return fail(g, TDP_E_INVALID, "K < 0");
+  if (n > g->max_paths) return fail(g, TDP_E_CAPACITY, "n > max_paths");
+  dispatch(g, [&](auto z) { rf_extract_impl<decltype(z)>(g, n, K, s); });
+  tdp_status st = check_launch(g, "extract_paths_rf");
+  if (st != TDP_OK) return st;
+  g->extracted = true;
+  g->last_k = 1;
+  if (out) {
+    out->max_paths = g->max_out;
+    out->d_num_paths = g->d_num_paths;
+    out->path_ptr = g->path_ptr;
+    out->path_pins = g->path_pins;
+    out->path_ep = g->path_ep;
+    out->path_rank = g->path_rank;
+    out->path_slack = g->path_slack;
+  }
+  if (d_path_tran) *d_path_tran = g->rf_path_tran;
+  return TDP_OK;
 }
 
 tdp_status tdp_sta_export_crit(tdp_graph g, int32_t *crit, hipStream_t s) {

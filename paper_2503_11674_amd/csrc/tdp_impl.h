@@ -24,6 +24,13 @@ inline void prof_end(tdp_graph g, int stage, hipStream_t s) {
   g->prof.open[stage] = nullptr;
 }
 
+template <typename T> void netpass_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
+// WNS / TNS / violated count per instance from the endpoint slacks
+template <typename T> void ep_reduce_impl(tdp_graph g, hipStream_t s);
+template <typename T> void rf_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
+template <typename T>
+void rf_export_impl(tdp_graph g, double *at, double *rat, double *slack, double *slew, hipStream_t s);
+template <typename T> void rf_extract_impl(tdp_graph g, int n, int K, hipStream_t s);
 template <typename T> void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
 template <typename T> void sta_required_impl(tdp_graph g, hipStream_t s);
 template <typename T>

@@ -314,6 +314,15 @@ struct tdp_graph_s {
   float ea_hold = 0;
   bool ea_ready = false;
 
+  // rise / fall timing (tdp_rf_setup): per-pin arrays [2 * pin + transition]
+  // in device pin order, arc delays [4 * input + 2 * x + y], critical (input,
+  // transition) per cell and output transition, the fall tables, unateness
+  bool rf_ready = false, rf_updated = false;
+  void *rf_at = nullptr, *rf_slew = nullptr, *rf_rat = nullptr, *rf_darc4 = nullptr;
+  int32_t *rf_crit = nullptr, *rf_unate = nullptr;
+  float *rf_delay_fall = nullptr, *rf_slew_fall = nullptr;
+  uint8_t *rf_path_tran = nullptr;  // [pin_cap] transition of each path pin
+
   // density term and Nesterov steps (tdp_density_setup)
   bool dn_ready = false;
   tdp::DensityGrid dn{};

@@ -925,6 +925,39 @@ static void forward_flow(tdp_graph g, hipStream_t s) {
   }
 }
 
+// net pass: pin positions, net delays, driver loads, start points (and the
+// reset of the dataflow words in trailing workgroups)
+template <typename T>
+static void netpass_launch(tdp_graph g, const float *x, const float *y, const FlowInit &fl, hipStream_t s) {
+  const Topo &tp = g->topo;
+  const NetModel<T> nm = net_model<T>(g);
+  pack_xy(x, y, g->xy, tp.N, s);
+  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4) + fl.reset_blocks), dim3(256), 0, s, tp, g->lut,
+                     g->xy, nm,
+                     (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
+                     g->cxy_nm, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
+  if (tp.n_big > 0)
+    hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, nm,
+                       (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
+                       (T *)g->slew, (V2<T> *)g->drv_as, g->cdep);
+}
+
+template <typename T>
+void ep_reduce_impl(tdp_graph g, hipStream_t s) {
+  const Topo &tp = g->topo;
+  hipLaunchKernelGGL(k_ep_partial<T>, dim3(tp.num_inst * g->ep_chunks), dim3(256), 0, s, g->d_ep_base,
+                     g->ep_chunks, (const T *)g->ep_slack, g->red_ep);
+  hipLaunchKernelGGL(k_ep_final, dim3(nblk(tp.num_inst, 64)), dim3(64), 0, s, tp.num_inst, g->ep_chunks, g->red_ep,
+                     g->summary, g->inst_nfail);
+}
+
+template <typename T>
+void netpass_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
+  FlowInit fl;
+  fl.err = g->d_err;
+  netpass_launch<T>(g, x, y, fl, s);
+}
+
 // arrivals: net pass, forward sweep, endpoint slacks and WNS / TNS
 template <typename T>
 void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
@@ -948,15 +981,7 @@ void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t 
     fl.reset_blocks = flow ? 1024 : 64;
   }
   prof_begin(g, TDP_STAGE_NETPASS, s);
-  pack_xy(x, y, g->xy, tp.N, s);
-  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4) + fl.reset_blocks), dim3(256), 0, s, tp, g->lut,
-                     g->xy, nm,
-                     (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
-                     g->cxy_nm, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
-  if (tp.n_big > 0)
-    hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, nm,
-                       (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
-                       (T *)g->slew, (V2<T> *)g->drv_as, g->cdep);
+  netpass_launch<T>(g, x, y, fl, s);
   prof_end(g, TDP_STAGE_NETPASS, s);
   prof_begin(g, TDP_STAGE_FORWARD, s);
   if (flow) {
@@ -980,10 +1005,7 @@ void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t 
   if (tp.E > 0)
     hipLaunchKernelGGL(k_endpoint<T>, dim3(nblk(tp.E, 256)), dim3(256), 0, s, tp, g->d_inst_req, (const T *)g->dnet,
                        (T *)g->at, (T *)g->rat, (T *)g->ep_slack);
-  hipLaunchKernelGGL(k_ep_partial<T>, dim3(tp.num_inst * g->ep_chunks), dim3(256), 0, s, g->d_ep_base,
-                     g->ep_chunks, (const T *)g->ep_slack, g->red_ep);
-  hipLaunchKernelGGL(k_ep_final, dim3(nblk(tp.num_inst, 64)), dim3(64), 0, s, tp.num_inst, g->ep_chunks, g->red_ep,
-                     g->summary, g->inst_nfail);
+  ep_reduce_impl<T>(g, s);
   prof_end(g, TDP_STAGE_ENDPOINT, s);
 }
 
@@ -1029,6 +1051,10 @@ void sta_export_crit(tdp_graph g, int32_t *out, hipStream_t s) {
   hipLaunchKernelGGL(k_export_crit, dim3(nblk(g->topo.N, 256)), dim3(256), 0, s, g->topo, g->crit, out);
 }
 
+template void ep_reduce_impl<float>(tdp_graph, hipStream_t);
+template void ep_reduce_impl<double>(tdp_graph, hipStream_t);
+template void netpass_impl<float>(tdp_graph, const float *, const float *, hipStream_t);
+template void netpass_impl<double>(tdp_graph, const float *, const float *, hipStream_t);
 template void sta_arrivals_impl<float>(tdp_graph, const float *, const float *, hipStream_t);
 template void sta_arrivals_impl<double>(tdp_graph, const float *, const float *, hipStream_t);
 template void sta_required_impl<float>(tdp_graph, hipStream_t);

@@ -85,6 +85,15 @@ tdp_sta_export = _sig("tdp_sta_export", _p, _p, _p, _p, _p, _p, _p, _p, _p)
 tdp_sta_export_crit = _sig("tdp_sta_export_crit", _p, _p, _p)
 tdp_extract_paths = _sig("tdp_extract_paths", _p, _i32, _i32, _i32, _f32, _p, _P(tdp_paths))
 tdp_report_timing = _sig("tdp_report_timing", _p, _i32, _f32, _p, _P(tdp_paths))
+class tdp_rf_tables(ctypes.Structure):
+    _fields_ = [("delay_fall", _p), ("slew_fall", _p), ("unate", _p)]
+
+
+tdp_rf_setup = _sig("tdp_rf_setup", _p, _P(tdp_rf_tables))
+tdp_sta_update_rf = _sig("tdp_sta_update_rf", _p, _p, _p, _p)
+tdp_sta_rf_summary = _sig("tdp_sta_rf_summary", _p, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i32), _p)
+tdp_sta_rf_export = _sig("tdp_sta_rf_export", _p, _p, _p, _p, _p, _p)
+tdp_extract_paths_rf = _sig("tdp_extract_paths_rf", _p, _i32, _i32, _p, _P(tdp_paths), _P(_p))
 tdp_sta_views = _sig("tdp_sta_views", _p, _P(_p), _P(_p), _P(_p))
 tdp_report_timing_noalloc = _sig("tdp_report_timing_noalloc", _p, _i32, _f32, _p, _P(tdp_paths))
 tdp_paths_count = _sig("tdp_paths_count", _p, _P(_i32), _P(_i32), _p)
@@ -123,7 +132,8 @@ tdp_last_error.argtypes = [_p]
 
 EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destroy", "tdp_sta_set_clock",
             "tdp_sta_update", "tdp_sta_update_arrivals", "tdp_sta_update_required", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit", "tdp_sta_views",
-            "tdp_extract_paths", "tdp_report_timing", "tdp_report_timing_noalloc", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
+            "tdp_extract_paths", "tdp_report_timing", "tdp_report_timing_noalloc", "tdp_rf_setup", "tdp_sta_update_rf",
+            "tdp_sta_rf_summary", "tdp_sta_rf_export", "tdp_extract_paths_rf", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
             "tdp_pair_loss_fwd", "tdp_pair_loss_bwd", "tdp_stns_fwd",
             "tdp_stns_bwd", "tdp_wa_fwd_bwd", "tdp_wa_fwd_bwd_at_update", "tdp_sta_update_early",
@@ -324,6 +334,52 @@ class TimingGraph:
         _check(tdp_report_timing(self.h, K, slack_limit, _stream(stream), ctypes.byref(p)), self.h)
         self._paths = p
         return p
+
+    # ----------------------------------------------------- rise / fall
+    def rf_setup(self, lib: Dict):
+        """Rise / fall tables (delay_fall, slew_fall, unate) of a library; its
+        main tables are the rise tables."""
+        df = np.ascontiguousarray(lib["delay_fall"], np.float32)
+        sf = np.ascontiguousarray(lib["slew_fall"], np.float32)
+        un = np.ascontiguousarray(lib["unate"], np.int32)
+        t = tdp_rf_tables(df.ctypes.data, sf.ctypes.data, un.ctypes.data)
+        _check(tdp_rf_setup(self.h, ctypes.byref(t)), self.h)
+
+    def sta_update_rf(self, x: torch.Tensor, y: torch.Tensor, stream=None):
+        _check(tdp_sta_update_rf(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), _stream(stream)), self.h)
+
+    def rf_summary(self, stream=None):
+        w, t, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(tdp_sta_rf_summary(self.h, ctypes.byref(w), ctypes.byref(t), ctypes.byref(n), _stream(stream)), self.h)
+        return w.value, t.value, n.value
+
+    def rf_export(self, stream=None) -> Dict[str, torch.Tensor]:
+        """[num_pins, 2] double tensors (rise, fall) in external pin order."""
+        dev = torch.device("cuda", self.device)
+        out = {k: torch.empty(2 * self.num_pins, dtype=torch.float64, device=dev)
+               for k in ("at", "rat", "slack", "slew")}
+        _check(tdp_sta_rf_export(self.h, *[_ptr(out[k]) for k in ("at", "rat", "slack", "slew")], _stream(stream)),
+               self.h)
+        return {k: v.view(self.num_pins, 2) for k, v in out.items()}
+
+    def extract_paths_rf(self, n: int = -1, K: Optional[int] = None, stream=None) -> tdp_paths:
+        K = self.max_paths if K is None else K
+        p = tdp_paths()
+        tran = _p()
+        _check(tdp_extract_paths_rf(self.h, n, K, _stream(stream), ctypes.byref(p), ctypes.byref(tran)), self.h)
+        self._paths = p
+        self._path_tran = tran.value
+        return p
+
+    def paths_rf(self, stream=None) -> Dict[str, np.ndarray]:
+        """paths() of the last rise / fall extraction, with path_tran."""
+        out = self.paths(stream)
+        n = int(out["path_ptr"][-1]) if len(out["path_ptr"]) else 0
+        tr = torch.empty(max(n, 1), dtype=torch.uint8, device=torch.device("cuda", self.device))
+        if n:
+            _copy_dev(tr, self._path_tran, n)
+        out["path_tran"] = tr[:n].cpu().numpy().astype(np.int32)
+        return out
 
     def report_timing_noalloc(self, K: int, slack_limit: float = math.inf, stream=None) -> tdp_paths:
         """report_timing(K) with its node store in the library's fixed device
