@@ -582,6 +582,35 @@ def main():
     g.sta_update(x, y)  # back to the single-transition state
     torch.cuda.synchronize()
 
+    # incremental arrival updates against the full arrival pass: m cells move
+    # (seeded jitter), and the positions alternate between the two placements
+    # so that every call is a genuine update of m moved cells
+    incremental = {}
+    rng = np.random.default_rng(11)
+    movable = np.nonzero(np.asarray(nl["cell_fixed"]) == 0)[0]
+    for m in (100, 1000, 10_000, 100_000):
+        cells = np.sort(rng.choice(movable, m, replace=False)).astype(np.int32)
+        ct = torch.tensor(cells, device=dev, dtype=torch.long)
+        xn, yn = x.clone(), y.clone()
+        xn[ct] += torch.tensor(rng.normal(0, 5.0, m).astype(np.float32), device=dev)
+        yn[ct] += torch.tensor(rng.normal(0, 5.0, m).astype(np.float32), device=dev)
+        cl = torch.tensor(cells, device=dev, dtype=torch.int32)
+        pos = ((xn, yn), (x, y))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        g.sta_update_arrivals(x, y)
+        ev[0].record()
+        for i in range(10):
+            g.sta_update_arrivals(*pos[i & 1])
+        ev[1].record()
+        for i in range(10):
+            g.sta_update_arrivals_incremental(*pos[i & 1], cl)
+        ev[2].record()
+        ev[2].synchronize()
+        incremental[str(m)] = {"full_arrivals_ms": round(ev[0].elapsed_time(ev[1]) / 10, 4),
+                               "incremental_ms": round(ev[1].elapsed_time(ev[2]) / 10, 4)}
+    g.sta_update(x, y)
+    torch.cuda.synchronize()
+
     sta_ms = sum(stages[s]["ms"] for s in ("netpass", "forward", "endpoint", "backward") if s in stages)
     ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
     loss_ms = sum(stages[s]["ms"] for s in ("p2p_fwd", "p2p_bwd") if s in stages)
@@ -632,6 +661,7 @@ def main():
         "pair_losses_ms": pair_ms,
         "early_analysis": early,
         "rise_fall": rise_fall,
+        "incremental_arrivals": incremental,
         "roofline": roof,
         "graph_replay": bool(graph is not None),
         "streams": 1 if a.serial else 3,

@@ -188,6 +188,25 @@ tdp_status tdp_sta_update(tdp_graph, const float *d_x, const float *d_y, hipStre
  * and before any export or summary (event waits between the streams). */
 tdp_status tdp_sta_update_arrivals(tdp_graph, const float *d_x, const float *d_y, hipStream_t);
 tdp_status tdp_sta_update_required(tdp_graph, hipStream_t);
+/* Incremental arrival pass (Sec. II-B's forward propagation, re-timing only
+ * what moved cells change): d_cells (device int32 [n_cells], external cell
+ * ids in any order, repeats allowed) lists every cell whose position differs
+ * from the previous update's.  Only the nets of those cells are re-timed;
+ * then, level by level, a 64-lane chunk of cells is re-timed only if the net
+ * pass changed one of its inputs' delays or its load, or a driver of one of
+ * its inputs changed arrival or transition; its deviation lists, hop records
+ * and chain depths only if it was re-timed or such a driver's changed.  The
+ * results equal tdp_sta_update_arrivals at the new positions bitwise; as
+ * after that call, tdp_sta_update_required must follow before required
+ * times, slacks or summaries are read.  The sweep stays one launch per level
+ * whatever moved, so this pays only where the moved cells' fan-out cones
+ * touch few chunks; on deep random logic a full update can be faster.  The
+ * first call allocates its marks and maps.  Ids outside [0, num_cells) are
+ * skipped and make tdp_sta_summary return TDP_E_DEVICE.  TDP_E_STATE without
+ * a previous update, TDP_E_UNSUPPORTED for a graph with a net wider than 63
+ * sinks. */
+tdp_status tdp_sta_update_arrivals_incremental(tdp_graph, const float *d_x, const float *d_y, const int32_t *d_cells,
+                                               int32_t n_cells, hipStream_t);
 
 /* WNS and TNS (Eqs. 3-4; both 0 without violations) and the number of
  * violated endpoints of the last update.  Synchronises the stream.  For a

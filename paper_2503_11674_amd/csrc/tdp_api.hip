@@ -328,6 +328,39 @@ tdp_status tdp_sta_update(tdp_graph g, const float *x, const float *y, hipStream
   return st;
 }
 
+tdp_status tdp_sta_update_arrivals_incremental(tdp_graph g, const float *x, const float *y, const int32_t *cells,
+                                               int32_t n_cells, hipStream_t s) {
+  GUARD(g);
+  if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
+  if (n_cells < 0 || (n_cells > 0 && !cells)) return fail(g, TDP_E_INVALID, "bad moved-cell list");
+  if (!g->updated) return fail(g, TDP_E_STATE, "an incremental update needs a full one first");
+  if (g->topo.n_big > 0) return fail(g, TDP_E_UNSUPPORTED, "incremental updates need every net within one chunk");
+  const Topo &T = g->topo;
+  if (!g->inc_ready) {
+    const bool ok = dalloc(g, g->inc_arr, T.n_fw_chunks) && dalloc(g, g->inc_lst, T.n_fw_chunks) &&
+                    dalloc(g, g->inc_drv_chg, T.M) && dalloc(g, g->inc_drv_lchg, T.M) &&
+                    dalloc(g, g->inc_nm, T.n_nm_chunks) && dalloc(g, g->inc_snk_chunk, T.A) &&
+                    dalloc(g, g->inc_drv_nm_chunk, T.M);
+    if (!ok) return fail(g, TDP_E_NOMEM, "incremental update: device allocation failed");
+    inc_maps(g, s);
+    g->inc_ready = true;
+    g->inc_epoch = 0;
+  }
+  if (g->inc_epoch == INT32_MAX) {  // the stamps start over
+    fill_i32(g->inc_arr, T.n_fw_chunks, 0, s);
+    fill_i32(g->inc_lst, T.n_fw_chunks, 0, s);
+    fill_i32(g->inc_drv_chg, T.M, 0, s);
+    fill_i32(g->inc_drv_lchg, T.M, 0, s);
+    fill_i32(g->inc_nm, T.n_nm_chunks, 0, s);
+    g->inc_epoch = 0;
+  }
+  ++g->inc_epoch;
+  g->ea_ready = false;
+  g->rf_updated = false;
+  dispatch(g, [&](auto z) { sta_arrivals_incremental_impl<decltype(z)>(g, x, y, cells, n_cells, s); });
+  return check_launch(g, "sta_update_arrivals_incremental");
+}
+
 tdp_status tdp_sta_update_arrivals(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   GUARD(g);
   if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
@@ -357,6 +390,7 @@ tdp_status tdp_sta_summary(tdp_graph g, double *wns, double *tns, int32_t *n_fai
       hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(g, TDP_E_DEVICE, "summary copy failed");
   if (err & 2) return fail(g, TDP_E_DEVICE, "a dataflow sweep gave up waiting (results are invalid)");
+  if (err & 4) return fail(g, TDP_E_DEVICE, "an incremental update was given a cell id outside [0, num_cells)");
   double w = 0, t = 0, n = 0;
   for (int i = 0; i < ni; ++i) {
     w = std::min(w, h[4 * i]);

@@ -32,6 +32,10 @@ template <typename T>
 void rf_export_impl(tdp_graph g, double *at, double *rat, double *slack, double *slew, hipStream_t s);
 template <typename T> void rf_extract_impl(tdp_graph g, int n, int K, hipStream_t s);
 template <typename T> void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
+template <typename T>
+void sta_arrivals_incremental_impl(tdp_graph g, const float *x, const float *y, const int32_t *cells, int n,
+                                   hipStream_t s);
+void inc_maps(tdp_graph g, hipStream_t s);
 template <typename T> void sta_required_impl(tdp_graph g, hipStream_t s);
 template <typename T>
 void sta_export_impl(tdp_graph g, double *at, double *rat, double *slack, double *slew, double *dnet,

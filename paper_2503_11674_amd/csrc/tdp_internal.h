@@ -256,6 +256,8 @@ struct tdp_graph_s {
   int32_t num_cu = 0;            // compute units of the device
   int32_t occ_fw[3] = {-1, -1, -1}, occ_bw[3] = {-1, -1, -1};  // occupancy per 1 / 2 / 4 waves, -1 = not yet
   bool flow_ok = false;          // the graph can use the dataflow sweeps
+  bool flow_r_clear = false;     // flow_r holds no published word (the last net pass reset it)
+  bool drv_as_stale = false;     // drv_as of the combinational drivers predates the last forward sweep
   double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;
   double *summary = nullptr;     // [4 * num_inst]: wns, tns, n_fail, 0
   int32_t *inst_nfail = nullptr, *d_ep_base = nullptr;
@@ -313,6 +315,15 @@ struct tdp_graph_s {
   double *ea_part = nullptr, *ea_summary = nullptr;
   float ea_hold = 0;
   bool ea_ready = false;
+
+  // incremental arrival update, allocated by its first call: marks as epoch
+  // stamps per forward chunk (arrivals, lists), per driver (arrival or
+  // transition changed, list changed) and per net chunk; the forward chunk of
+  // each combinational input and the net chunk of each driver
+  bool inc_ready = false;
+  int32_t inc_epoch = 0;
+  int32_t *inc_arr = nullptr, *inc_lst = nullptr, *inc_drv_chg = nullptr, *inc_drv_lchg = nullptr,
+          *inc_nm = nullptr, *inc_snk_chunk = nullptr, *inc_drv_nm_chunk = nullptr;
 
   // rise / fall timing (tdp_rf_setup): per-pin arrays [2 * pin + transition]
   // in device pin order, arc delays [4 * input + 2 * x + y], critical (input,

@@ -122,6 +122,28 @@ struct FlowInit {
   int reset_blocks = 0;  // trailing workgroups of the net pass that reset the words
 };
 
+// Marks of an incremental arrival update (all null for a full one), as
+// stamps: an entry equal to the update's epoch is set, any other value is
+// not, so nothing is cleared between updates.  A chunk is re-timed when the
+// net pass marked it or when a driver of one of its inputs changed in this
+// update, which each of its lanes reads for itself (no pushing of marks
+// along fanout lists).
+struct IncFlags {
+  int32_t epoch = 0;
+  int32_t *arr = nullptr;               // [n_fw_chunks] the net pass changed an input's delay or the load
+  int32_t *lst = nullptr;               // [n_fw_chunks] the chunk's arrivals were re-timed
+  int32_t *drv_chg = nullptr;           // [M] the driver's arrival or transition changed
+  int32_t *drv_lchg = nullptr;          // [M] its deviation list, hop records or chain depth changed
+  const int32_t *snk_chunk = nullptr;   // [A] forward chunk of a combinational input
+  const int32_t *nm = nullptr;          // [n_nm_chunks] the net chunk holds a moved cell's pin
+};
+
+template <typename T>
+__device__ __forceinline__ bool same_bits(T a, T b) {
+  if constexpr (sizeof(T) == 4) return __float_as_uint((float)a) == __float_as_uint((float)b);
+  else return __double_as_longlong((double)a) == __double_as_longlong((double)b);
+}
+
 // v[0, n) = x, 16-byte stores where the alignment allows
 __device__ __forceinline__ void fill_u32(uint32_t *p, size_t n, uint32_t x, size_t tid, size_t nth) {
   size_t h = ((16 - ((uintptr_t)p & 15)) & 15) / 4;
@@ -169,22 +191,15 @@ __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, in
 }
 
 // ------------------------------------------------------------- net pass
+// one net chunk of the net pass
 template <typename T>
-__global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, NetModel<T> nm,
-                                                  T cw, T in_slew,
-                                                  T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
-                                                  T *__restrict__ dnet_nm, float2 *__restrict__ cxy_nm,
-                                                  T *__restrict__ at, T *__restrict__ slew,
-                                                  V2<T> *__restrict__ as, int32_t *__restrict__ cdep, FlowInit fl) {
-  if (blockIdx.x == 0 && threadIdx.x == 0 && fl.err) *fl.err = 0;
-  const int main_blocks = (int)gridDim.x - fl.reset_blocks;
-  if ((int)blockIdx.x >= main_blocks) {
-    flow_reset(fl, tp, (int)blockIdx.x - main_blocks);
-    return;
-  }
+__device__ __forceinline__ void netpass_chunk(const Topo &tp, const LutView &L, int chunk, const float2 *__restrict__ xy,
+                                              const NetModel<T> &nm, T cw, T in_slew, T clk_slew,
+                                              T *__restrict__ load, T *__restrict__ dnet, T *__restrict__ dnet_nm,
+                                              float2 *__restrict__ cxy_nm, T *__restrict__ at, T *__restrict__ slew,
+                                              V2<T> *__restrict__ as, int32_t *__restrict__ cdep, const FlowInit &fl,
+                                              const IncFlags &inc) {
   const int lane = wave_lane();
-  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (chunk >= tp.n_nm_chunks) return;
   const int k = chunk * CHUNK + lane;
   const int4 rec = tp.nm_rec[k];
   const int p = rec.x, cell = rec.y;
@@ -204,13 +219,52 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
     const T dn = nm.delay(len, nm.elmore ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0);
     dnet[p - tp.M] = dn;
     dnet_nm[k] = dn;
+    // incremental: every sink of a re-timed net gets its chunk re-timed
+    if (inc.arr && p - tp.M < tp.A) inc.arr[inc.snk_chunk[p - tp.M]] = inc.epoch;
   }
   const T wl = seg_sum(len, lane, head, tail);
   if (p >= 0 && lane == head) {
     const T ld = (T)tp.net_cpin[p] + cw * wl;
     load[p] = ld;
     start_point<T>(tp, L, p, ld, in_slew, clk_slew, at, slew, as, cdep, fl);
+    // incremental: a combinational driver's cell sees its new load
+    if (inc.arr && p >= tp.n_start) inc.arr[inc.snk_chunk[tp.comb_inptr[p - tp.n_start]]] = inc.epoch;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, NetModel<T> nm,
+                                                  T cw, T in_slew,
+                                                  T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
+                                                  T *__restrict__ dnet_nm, float2 *__restrict__ cxy_nm,
+                                                  T *__restrict__ at, T *__restrict__ slew,
+                                                  V2<T> *__restrict__ as, int32_t *__restrict__ cdep, FlowInit fl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && fl.err) *fl.err = 0;
+  const int main_blocks = (int)gridDim.x - fl.reset_blocks;
+  if ((int)blockIdx.x >= main_blocks) {
+    flow_reset(fl, tp, (int)blockIdx.x - main_blocks);
+    return;
+  }
+  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= tp.n_nm_chunks) return;
+  netpass_chunk<T>(tp, L, chunk, xy, nm, cw, in_slew, clk_slew, load, dnet, dnet_nm, cxy_nm, at, slew, as, cdep, fl,
+                   IncFlags{});
+}
+
+// the net pass over the marked net chunks of an incremental update (the same
+// computation per chunk, so the results are those of a full pass)
+template <typename T>
+__global__ void __launch_bounds__(256) k_netpass_marked(Topo tp, LutView L, const float2 *__restrict__ xy,
+                                                         NetModel<T> nm, T cw, T in_slew, T clk_slew,
+                                                         T *__restrict__ load, T *__restrict__ dnet,
+                                                         T *__restrict__ dnet_nm, float2 *__restrict__ cxy_nm,
+                                                         T *__restrict__ at, T *__restrict__ slew,
+                                                         V2<T> *__restrict__ as, int32_t *__restrict__ cdep,
+                                                         IncFlags inc) {
+  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= tp.n_nm_chunks || inc.nm[chunk] != inc.epoch) return;
+  netpass_chunk<T>(tp, L, chunk, xy, nm, cw, in_slew, clk_slew, load, dnet, dnet_nm, cxy_nm, at, slew, as, cdep,
+                   FlowInit{}, inc);
 }
 
 // nets too wide for one chunk: one thread per net
@@ -268,23 +322,39 @@ template <typename T>
 __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, float *s_lut, int chunk, int ch1,
                                             const T *__restrict__ load, const T *__restrict__ dnet,
                                             T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
-                                            T *__restrict__ darc, int32_t *__restrict__ crit, T *__restrict__ fw_a) {
+                                            T *__restrict__ darc, int32_t *__restrict__ crit, T *__restrict__ fw_a,
+                                            const IncFlags &inc) {
   const int lane = wave_lane();
   const int k = chunk * CHUNK + lane;
-  // the record load is issued before the tables are staged, so the two
-  // latencies overlap (unconditionally: a wave past the level's last chunk
-  // reads that chunk again and then leaves)
+  // the record and the inputs' loads are issued before the tables are
+  // staged, so the latencies overlap (a wave past the level's last chunk
+  // reads that chunk's records again and then leaves)
   const int4 rec = tp.fw_rec[(chunk < ch1 ? chunk : ch1 - 1) * CHUNK + lane];
-  stage_lut(L, s_lut);
-  if (chunk >= ch1) return;
   const int t = rec.x, s = rec.y, c = rec.z;
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
-  const bool valid = t >= 0;
+  const bool valid = t >= 0 && chunk < ch1;
+  T ld = 0, dn = 0;
+  V2<T> w = v2<T>(0, 0), old = v2<T>(0, 0);
+  if (valid) {
+    ld = load[tp.n_start + c];
+    w = as[s];
+    dn = dnet[t];
+  }
+  // incremental: whether the net pass marked the chunk or an input's driver
+  // changed, and the cell's previous output (issued with the same loads)
+  bool mark = false;
+  if (inc.arr && valid) {
+    mark = inc.drv_chg[s] == inc.epoch || inc.arr[chunk] == inc.epoch;
+    if (lane == head) old = as[tp.n_start + c];
+  }
+  stage_lut(L, s_lut);
+  if (chunk >= ch1) return;
+  if (inc.arr) {  // only marked chunks, whose cells' lists follow
+    if (__ballot(mark) == 0) return;
+    if (lane == 0) inc.lst[chunk] = inc.epoch;
+  }
   T a = -pos_inf<T>(), o = 0;
   if (valid) {
-    const T ld = load[tp.n_start + c];
-    const V2<T> w = as[s];
-    const T dn = dnet[t];
     const T a_in = w.x + dn;
     T d;
     lut_lds<T>(s_lut, L.nt, L.ns, L.nl, (rec.w >> 16) & 255, sink_slew<T>(L.net_model, w.y, dn), ld, d, o);
@@ -313,6 +383,8 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
   }
   if (valid && lane == head) {  // (the list job records the critical input's hop)
     const int v = tp.n_start + c;
+    if (inc.arr && (!same_bits(old.x, best) || !same_bits(old.y, so)))
+      inc.drv_chg[v] = inc.epoch;  // a changed output re-times the cells it drives
     at[v] = best;
     slew[v] = so;
     as[v] = v2<T>(best, so);
@@ -325,17 +397,31 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
 // start point), so a path walk reads four hops per load
 template <typename T, int KM>
 __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, const T *__restrict__ fw_a,
+                                         const T *__restrict__ at, const T *__restrict__ darc,
                                          int32_t *__restrict__ cdep, T *__restrict__ side_cost,
-                                         int32_t *__restrict__ side_pin, int4 *__restrict__ hop4) {
+                                         int32_t *__restrict__ side_pin, int4 *__restrict__ hop4,
+                                         const IncFlags &inc) {
   if (chunk >= lc1) return;
   const int lane = wave_lane();
   const int k = chunk * CHUNK + lane;
   const int4 rec = tp.fw_rec[k];
-  const T a = fw_a[k];
   const int2 ex = tp.fw_ext[k];
   const int t = rec.x, s = rec.y, c = rec.z;
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   const bool valid = t >= 0;
+  T a;
+  if (!inc.lst) {
+    a = fw_a[k];
+  } else {
+    // incremental: a chunk whose arrivals this update left alone has no
+    // fw_a of its own from it (the dataflow sweep writes none), so the
+    // arrival through each arc is formed again from the two stored terms,
+    // the same sum; the chunk goes on if it was re-timed or an input's
+    // driver's list changed (the marks load with the two terms)
+    a = valid ? at[tp.M + t] + darc[t] : -pos_inf<T>();
+    const bool mark = (valid && inc.drv_lchg[s] == inc.epoch) || inc.lst[chunk] == inc.epoch;
+    if (__ballot(mark) == 0) return;
+  }
   // the same maximum and critical input as the arrival job found
   const bool narrow = ((rec.w >> 24) & 127) <= 4;  // wave-uniform
   T ua[4];
@@ -379,6 +465,8 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
       }
     }
   }
+  // incremental: whether this cell's list, hop records or chain depth change
+  bool changed = false;
   if (is_head) {
     const int4 none = make_int4(-1, -1, 0, 0);
     int4 up0 = none, up1 = none, up2 = none;
@@ -389,9 +477,14 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
       up2 = ph[2];
     }
     const int32_t cd = cdep[pred];
-    cdep[tp.n_start + c] = cd + 1;
     int4 *h = hop4 + (size_t)c * 4;
-    h[0] = make_int4(tc, pred, exc.x, exc.y);
+    const int4 h0 = make_int4(tc, pred, exc.x, exc.y);
+    if (inc.lst) {
+      auto ne = [](int4 a, int4 b) { return a.x != b.x || a.y != b.y || a.z != b.z || a.w != b.w; };
+      changed = cdep[tp.n_start + c] != cd + 1 || ne(h[0], h0) || ne(h[1], up0) || ne(h[2], up1) || ne(h[3], up2);
+    }
+    cdep[tp.n_start + c] = cd + 1;
+    h[0] = h0;
     h[1] = up0;
     h[2] = up1;
     h[3] = up2;
@@ -420,11 +513,14 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
       const size_t cb = (size_t)c * KM;
 #pragma unroll
       for (int j = 0; j < KM; ++j) {
+        if (inc.lst) changed = changed || !same_bits(side_cost[cb + j], kc[j]) || side_pin[cb + j] != kp[j];
         side_cost[cb + j] = kc[j];
         side_pin[cb + j] = kp[j];
       }
     }
   }
+  // the cells this one drives may take it as their critical input
+  if (changed) inc.drv_lchg[tp.n_start + c] = inc.epoch;
 }
 
 // arrival chunks [ch0, ch1) in workgroups [0, n_arr); list chunks [lc0, lc1)
@@ -436,14 +532,15 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
                                                   T *__restrict__ darc, int32_t *__restrict__ crit,
                                                   int32_t *__restrict__ cdep,
                                                   T *__restrict__ side_cost, int32_t *__restrict__ side_pin,
-                                                  T *__restrict__ fw_a, int4 *__restrict__ hop4) {
+                                                  T *__restrict__ fw_a, int4 *__restrict__ hop4, IncFlags inc) {
   extern __shared__ float4 s_lut4[];
   float *s_lut = (float *)s_lut4;
   const int wave = threadIdx.x >> 6;
   if ((int)blockIdx.x < n_arr)
-    fw_arrivals<T>(tp, L, s_lut, ch0 + blockIdx.x * 4 + wave, ch1, load, dnet, at, slew, as, darc, crit, fw_a);
+    fw_arrivals<T>(tp, L, s_lut, ch0 + blockIdx.x * 4 + wave, ch1, load, dnet, at, slew, as, darc, crit, fw_a, inc);
   else
-    fw_lists<T, KM>(tp, lc0 + (blockIdx.x - n_arr) * 4 + wave, lc1, fw_a, cdep, side_cost, side_pin, hop4);
+    fw_lists<T, KM>(tp, lc0 + (blockIdx.x - n_arr) * 4 + wave, lc1, fw_a, at, darc, cdep, side_cost, side_pin, hop4,
+                    inc);
 }
 
 // ------------------------------------------------------------- endpoints
@@ -863,7 +960,7 @@ static inline int nblk(long long n, int b) { return n > 0 ? (int)((n + b - 1) / 
 static inline size_t lut_bytes(const LutView &L) { return sizeof(float4) * (size_t)L.n4; }
 
 template <typename T, int KM>
-static void launch_forward(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipStream_t s) {
+static void launch_forward(tdp_graph g, int ch0, int ch1, int lc0, int lc1, const IncFlags &inc, hipStream_t s) {
   const Topo &tp = g->topo;
   const int n_arr = ch1 > ch0 ? nblk(ch1 - ch0, 4) : 0;
   const int n_lst = lc1 > lc0 ? nblk(lc1 - lc0, 4) : 0;
@@ -871,20 +968,35 @@ static void launch_forward(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipS
   hipLaunchKernelGGL((k_forward<T, KM>), dim3(n_arr + n_lst), dim3(256), n_arr ? lut_bytes(g->lut) : 0, s, tp,
                      g->lut, ch0, ch1, n_arr, lc0, lc1, (const T *)g->load, (const T *)g->dnet, (T *)g->at,
                      (T *)g->slew, (V2<T> *)g->drv_as, (T *)g->darc, g->crit, g->cdep,
-                     (T *)g->side_cost, g->side_pin, (T *)g->fw_a, (int4 *)g->hop4);
+                     (T *)g->side_cost, g->side_pin, (T *)g->fw_a, (int4 *)g->hop4, inc);
 }
 
 // arrivals of chunks [ch0, ch1) and the lists of [lc0, lc1), the level before
 template <typename T>
-static void forward_level(tdp_graph g, int ch0, int ch1, int lc0, int lc1, hipStream_t s) {
+static void forward_level(tdp_graph g, int ch0, int ch1, int lc0, int lc1, const IncFlags &inc, hipStream_t s) {
   switch (g->side_k) {
-    case 1: launch_forward<T, 1>(g, ch0, ch1, lc0, lc1, s); break;
-    case 2: launch_forward<T, 2>(g, ch0, ch1, lc0, lc1, s); break;
-    case 4: launch_forward<T, 4>(g, ch0, ch1, lc0, lc1, s); break;
-    case 8: launch_forward<T, 8>(g, ch0, ch1, lc0, lc1, s); break;
-    case 16: launch_forward<T, 16>(g, ch0, ch1, lc0, lc1, s); break;
-    default: launch_forward<T, 32>(g, ch0, ch1, lc0, lc1, s); break;
+    case 1: launch_forward<T, 1>(g, ch0, ch1, lc0, lc1, inc, s); break;
+    case 2: launch_forward<T, 2>(g, ch0, ch1, lc0, lc1, inc, s); break;
+    case 4: launch_forward<T, 4>(g, ch0, ch1, lc0, lc1, inc, s); break;
+    case 8: launch_forward<T, 8>(g, ch0, ch1, lc0, lc1, inc, s); break;
+    case 16: launch_forward<T, 16>(g, ch0, ch1, lc0, lc1, inc, s); break;
+    default: launch_forward<T, 32>(g, ch0, ch1, lc0, lc1, inc, s); break;
   }
+}
+
+// the per-level forward sweep over every level (incremental: with flags)
+template <typename T>
+static void forward_levels(tdp_graph g, const IncFlags &inc, hipStream_t s) {
+  const Topo &tp = g->topo;
+  int lc0 = 0, lc1 = 0;  // the previous non-empty level, whose lists are due
+  for (int l = 1; l <= tp.D; ++l) {
+    const int ch0 = g->lv.fw_lvl[l - 1], ch1 = g->lv.fw_lvl[l];
+    if (ch1 <= ch0) continue;
+    forward_level<T>(g, ch0, ch1, lc0, lc1, inc, s);
+    lc0 = ch0;
+    lc1 = ch1;
+  }
+  forward_level<T>(g, 0, 0, lc0, lc1, inc, s);
 }
 
 // workgroups of a resident grid of `waves`-wave workgroups over nch chunks:
@@ -982,23 +1094,17 @@ void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t 
   }
   prof_begin(g, TDP_STAGE_NETPASS, s);
   netpass_launch<T>(g, x, y, fl, s);
+  g->flow_r_clear = bflow;
   prof_end(g, TDP_STAGE_NETPASS, s);
   prof_begin(g, TDP_STAGE_FORWARD, s);
+  g->drv_as_stale = flow;  // the dataflow sweep publishes through its own words
   if (flow) {
     forward_flow(g, s);
     if (tp.n_comb > 0)
       hipLaunchKernelGGL(k_hop4_fill, dim3(nblk(tp.n_comb, 256)), dim3(256), 0, s, tp, (const int4 *)g->hop,
                          (int4 *)g->hop4);
   } else {
-    int lc0 = 0, lc1 = 0;  // the previous non-empty level, whose lists are due
-    for (int l = 1; l <= tp.D; ++l) {
-      const int ch0 = g->lv.fw_lvl[l - 1], ch1 = g->lv.fw_lvl[l];
-      if (ch1 <= ch0) continue;
-      forward_level<T>(g, ch0, ch1, lc0, lc1, s);
-      lc0 = ch0;
-      lc1 = ch1;
-    }
-    forward_level<T>(g, 0, 0, lc0, lc1, s);
+    forward_levels<T>(g, IncFlags{}, s);
   }
   prof_end(g, TDP_STAGE_FORWARD, s);
   prof_begin(g, TDP_STAGE_ENDPOINT, s);
@@ -1009,12 +1115,109 @@ void sta_arrivals_impl(tdp_graph g, const float *x, const float *y, hipStream_t 
   prof_end(g, TDP_STAGE_ENDPOINT, s);
 }
 
+// ---------------------------------------------------- incremental update
+// forward chunk of every combinational input; net chunk of every driver
+__global__ void k_inc_maps(Topo tp, int32_t *__restrict__ snk_chunk, int32_t *__restrict__ drv_nm_chunk) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nf = (long long)tp.n_fw_chunks * CHUNK, nn = (long long)tp.n_nm_chunks * CHUNK;
+  if (k < nf) {
+    const int t = tp.fw_rec[k].x;
+    if (t >= 0) snk_chunk[t] = (int)(k / CHUNK);
+  } else if (k < nf + nn) {
+    const long long q = k - nf;
+    const int4 rec = tp.nm_rec[q];
+    if (rec.x >= 0 && (int)(q % CHUNK) == (rec.w & 63)) drv_nm_chunk[rec.x] = (int)(q / CHUNK);
+  }
+}
+
+// {arrival, transition} pairs of the combinational drivers from the two
+// arrays, after a forward sweep that did not keep the pairs
+template <typename T>
+__global__ void k_pack_as(Topo tp, const T *__restrict__ at, const T *__restrict__ slew, V2<T> *__restrict__ as) {
+  const int v = tp.n_start + blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < tp.M) as[v] = v2<T>(at[v], slew[v]);
+}
+
+// the net chunks that hold a moved cell's pins: its output's net and the nets
+// of its inputs (bit 2 of err: an id outside [0, N))
+__global__ void k_inc_mark(Topo tp, const int32_t *__restrict__ cells, int n, const int32_t *__restrict__ drv_nm_chunk,
+                           int32_t *__restrict__ nm, int32_t epoch, int32_t *__restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int e = cells[i];
+  if (e < 0 || e >= tp.N) {
+    atomicOr(err, 4);
+    return;
+  }
+  const int ci = tp.cell_int[e];
+  auto mark = [&](int u) { nm[drv_nm_chunk[u]] = epoch; };
+  if (ci >= 0) {
+    mark(tp.n_start + ci);
+    for (int t = tp.comb_inptr[ci]; t < tp.comb_inptr[ci + 1]; ++t) mark(tp.snk_drv[t]);
+  } else {
+    const int f = -ci - 1;
+    mark(tp.n_pi + f);
+    mark(tp.snk_drv[tp.A + f]);
+  }
+}
+
+template <typename T>
+void sta_arrivals_incremental_impl(tdp_graph g, const float *x, const float *y, const int32_t *cells, int n,
+                                   hipStream_t s) {
+  const Topo &tp = g->topo;
+  const NetModel<T> nm = net_model<T>(g);
+  IncFlags inc;
+  inc.epoch = g->inc_epoch;
+  inc.arr = g->inc_arr;
+  inc.lst = g->inc_lst;
+  inc.drv_chg = g->inc_drv_chg;
+  inc.drv_lchg = g->inc_drv_lchg;
+  inc.snk_chunk = g->inc_snk_chunk;
+  inc.nm = g->inc_nm;
+  prof_begin(g, TDP_STAGE_NETPASS, s);
+  if (g->drv_as_stale && tp.n_comb > 0)
+    hipLaunchKernelGGL(k_pack_as<T>, dim3(nblk(tp.n_comb, 256)), dim3(256), 0, s, tp, (const T *)g->at,
+                       (const T *)g->slew, (V2<T> *)g->drv_as);
+  g->drv_as_stale = false;
+  fill_i32(g->d_err, 1, 0, s);
+  if (n > 0)
+    hipLaunchKernelGGL(k_inc_mark, dim3(nblk(n, 256)), dim3(256), 0, s, tp, cells, n, g->inc_drv_nm_chunk,
+                       g->inc_nm, inc.epoch, g->d_err);
+  pack_xy(x, y, g->xy, tp.N, s);
+  if (n > 0)
+    hipLaunchKernelGGL(k_netpass_marked<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, nm,
+                       (T)g->c,
+                       (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm, g->cxy_nm,
+                       (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, inc);
+  prof_end(g, TDP_STAGE_NETPASS, s);
+  prof_begin(g, TDP_STAGE_FORWARD, s);
+  forward_levels<T>(g, inc, s);
+  prof_end(g, TDP_STAGE_FORWARD, s);
+  prof_begin(g, TDP_STAGE_ENDPOINT, s);
+  if (tp.E > 0)
+    hipLaunchKernelGGL(k_endpoint<T>, dim3(nblk(tp.E, 256)), dim3(256), 0, s, tp, g->d_inst_req, (const T *)g->dnet,
+                       (T *)g->at, (T *)g->rat, (T *)g->ep_slack);
+  ep_reduce_impl<T>(g, s);
+  prof_end(g, TDP_STAGE_ENDPOINT, s);
+}
+
+void inc_maps(tdp_graph g, hipStream_t s) {
+  const Topo &tp = g->topo;
+  const long long total = ((long long)tp.n_fw_chunks + tp.n_nm_chunks) * CHUNK;
+  hipLaunchKernelGGL(k_inc_maps, dim3(nblk(total, 256)), dim3(256), 0, s, tp, g->inc_snk_chunk, g->inc_drv_nm_chunk);
+}
+
 template <typename T>
 void sta_required_impl(tdp_graph g, hipStream_t s) {
   const Topo &tp = g->topo;
   const bool flow = sizeof(T) == 4 && g->flow_ok && g->sweep_mode >= 1;  // modes 1-3
   prof_begin(g, TDP_STAGE_BACKWARD, s);
   if (flow) {
+    // the words are reset by a full arrival pass that plans this sweep; after
+    // any other (incremental, per-level, or none since the last sweep) they
+    // are reset here
+    if (!g->flow_r_clear) fill_i32(reinterpret_cast<int32_t *>(g->flow_r), tp.M, (int32_t)R_EMPTY, s);
+    g->flow_r_clear = false;
     const int w = g->flow_waves;
     const int nb = resident_blocks(g, reinterpret_cast<const void *>(&k_backward_flow), g->occ_bw, w, 0,
                                    tp.n_nm_chunks);
@@ -1055,6 +1258,10 @@ template void ep_reduce_impl<float>(tdp_graph, hipStream_t);
 template void ep_reduce_impl<double>(tdp_graph, hipStream_t);
 template void netpass_impl<float>(tdp_graph, const float *, const float *, hipStream_t);
 template void netpass_impl<double>(tdp_graph, const float *, const float *, hipStream_t);
+template void sta_arrivals_incremental_impl<float>(tdp_graph, const float *, const float *, const int32_t *, int,
+                                                   hipStream_t);
+template void sta_arrivals_incremental_impl<double>(tdp_graph, const float *, const float *, const int32_t *, int,
+                                                    hipStream_t);
 template void sta_arrivals_impl<float>(tdp_graph, const float *, const float *, hipStream_t);
 template void sta_arrivals_impl<double>(tdp_graph, const float *, const float *, hipStream_t);
 template void sta_required_impl<float>(tdp_graph, hipStream_t);

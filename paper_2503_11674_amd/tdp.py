@@ -94,6 +94,7 @@ tdp_sta_update_rf = _sig("tdp_sta_update_rf", _p, _p, _p, _p)
 tdp_sta_rf_summary = _sig("tdp_sta_rf_summary", _p, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i32), _p)
 tdp_sta_rf_export = _sig("tdp_sta_rf_export", _p, _p, _p, _p, _p, _p)
 tdp_extract_paths_rf = _sig("tdp_extract_paths_rf", _p, _i32, _i32, _p, _P(tdp_paths), _P(_p))
+tdp_sta_update_arrivals_incremental = _sig("tdp_sta_update_arrivals_incremental", _p, _p, _p, _p, _i32, _p)
 tdp_sta_views = _sig("tdp_sta_views", _p, _P(_p), _P(_p), _P(_p))
 tdp_report_timing_noalloc = _sig("tdp_report_timing_noalloc", _p, _i32, _f32, _p, _P(tdp_paths))
 tdp_paths_count = _sig("tdp_paths_count", _p, _P(_i32), _P(_i32), _p)
@@ -131,7 +132,7 @@ tdp_last_error.restype = ctypes.c_char_p
 tdp_last_error.argtypes = [_p]
 
 EXPORTED = ["tdp_sta_build", "tdp_batch_build", "tdp_batch_offsets", "tdp_destroy", "tdp_sta_set_clock",
-            "tdp_sta_update", "tdp_sta_update_arrivals", "tdp_sta_update_required", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit", "tdp_sta_views",
+            "tdp_sta_update", "tdp_sta_update_arrivals", "tdp_sta_update_required", "tdp_sta_update_arrivals_incremental", "tdp_sta_summary", "tdp_batch_summary", "tdp_sta_export", "tdp_sta_export_crit", "tdp_sta_views",
             "tdp_extract_paths", "tdp_report_timing", "tdp_report_timing_noalloc", "tdp_rf_setup", "tdp_sta_update_rf",
             "tdp_sta_rf_summary", "tdp_sta_rf_export", "tdp_extract_paths_rf", "tdp_paths_count", "tdp_pairs_update", "tdp_pairs_reset", "tdp_pairs_export",
             "tdp_pairs_import", "tdp_pairs_count", "tdp_p2p_loss_fwd", "tdp_p2p_loss_bwd",
@@ -269,6 +270,15 @@ class TimingGraph:
 
     def sta_update_arrivals(self, x: torch.Tensor, y: torch.Tensor, stream=None):
         _check(tdp_sta_update_arrivals(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), _stream(stream)), self.h)
+
+    def sta_update_arrivals_incremental(self, x: torch.Tensor, y: torch.Tensor, cells: torch.Tensor, stream=None):
+        """Arrival pass re-timing only what the listed (moved) cells change;
+        `cells` is a device int32 tensor of external cell ids."""
+        if not cells.is_cuda or cells.dtype != torch.int32:
+            raise ValueError("cells must be an int32 tensor on the GPU")
+        cells = cells.contiguous()
+        _check(tdp_sta_update_arrivals_incremental(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)),
+                                                   _ptr(cells), int(cells.numel()), _stream(stream)), self.h)
 
     def sta_update_required(self, stream=None):
         _check(tdp_sta_update_required(self.h, _stream(stream)), self.h)
@@ -566,7 +576,8 @@ class TimingGraph:
 
     def set_tuning(self, flow_waves: int = 0, spin_log2: int = 0, sweep_mode: int = 1, flow_per_cu: int = 0):
         """sweep_mode 0: one launch per level; 1: dataflow sweeps on a resident
-        grid; 2: self-test of the dataflow sweeps' bounded waits.  flow_waves:
+        grid; 2: self-test of the dataflow sweeps' bounded waits; 3: the
+        backward sweep as a dataflow grid, the forward one per level.  flow_waves:
         waves per workgroup of the resident grids (1, 2, 4; 0 keeps);
         flow_per_cu: their workgroups per compute unit (1..4; 0 keeps)."""
         _check(tdp_set_tuning(self.h, flow_waves, flow_per_cu, spin_log2, sweep_mode), self.h)
