@@ -65,9 +65,14 @@ __global__ void __launch_bounds__(256) k_pairs_acc(Topo tp, int rule, const int3
 // slots, i.e. the k paths of a few endpoints, which share most of their pins,
 // merges its occurrences in an LDS hash table with integer atomics, and sends
 // one global atomic per distinct pin.  The first occurrence is still the
-// smallest output index, whatever order the paths are visited in.
+// smallest output index, whatever order the paths are visited in.  The
+// block's paths are not walked one after another: their descriptors (range,
+// contribution) are loaded for all of them at once, and the threads then
+// take the concatenation of their sink occurrences in equal shares, so the
+// dependent loads are paid once per block rather than once per path.
 constexpr int HASH_BITS = 11;
 constexpr int HASH_SLOTS = 1 << HASH_BITS;  // 24 KB of LDS: several workgroups per CU
+constexpr int ACC_MAX_PATHS = 64;           // paths per workgroup at most
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int per_block,
@@ -84,37 +89,68 @@ __global__ void __launch_bounds__(256) k_pairs_acc_lds(Topo tp, int rule, int pe
   __shared__ int32_t hkey[HASH_SLOTS];
   __shared__ unsigned long long hacc[HASH_SLOTS];
   __shared__ int32_t hfirst[HASH_SLOTS];
+  __shared__ unsigned long long s_v[ACC_MAX_PATHS];
+  __shared__ int32_t s_b[ACC_MAX_PATHS], s_q[ACC_MAX_PATHS], s_pre[ACC_MAX_PATHS + 1];
   const int n = *d_nslots;
   const int j0 = blockIdx.x * per_block;
   if (j0 >= n) return;  // whole block: the grid is sized for the slot capacity
+  const int np = min(n - j0, per_block);
   for (int i = threadIdx.x; i < HASH_SLOTS; i += blockDim.x) {
     hkey[i] = -1;
     hacc[i] = 0ull;
     hfirst[i] = 0x7fffffff;
   }
-  __syncthreads();
-  const int j1 = min(n, j0 + per_block);
-  const int lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
-  for (int j = j0 + (threadIdx.x >> 6); j < j1; j += nwv) {
-    const int q = slot_out[j];
-    if (q < 0) continue;
-    const double wns = summary[4 * tp.ff_inst[path_epi[q]]];
-    unsigned long long v;
-    if (!pair_contrib<T>(rule, path_slack[q], wns, v)) continue;
-    const int b = path_ptr[q], e = path_ptr[q + 1];
-    for (int i = b + 1 + 2 * lane; i < e; i += 128) {
-      const int t = path_int[i] - tp.M;
-      if (t < 0 || t >= tp.S) continue;
-      unsigned h = ((unsigned)t * 2654435761u) >> (32 - HASH_BITS);
-      for (int probe = 0; probe < HASH_SLOTS; ++probe) {
-        const int k = atomicCAS(&hkey[h], -1, t);
-        if (k == -1 || k == t) {
-          atomicAdd(&hacc[h], v);
-          atomicMin(&hfirst[h], q);
-          break;
-        }
-        h = (h + 1) & (HASH_SLOTS - 1);
+  // path descriptors: first sink position, number of sinks (every second pin
+  // after the start point), contribution
+  int cnt = 0;
+  if ((int)threadIdx.x < np) {
+    const int q = slot_out[j0 + threadIdx.x];
+    unsigned long long v = 0ull;
+    if (q >= 0) {
+      const int b = path_ptr[q], e = path_ptr[q + 1];
+      const T sl = path_slack[q];
+      const double wns = summary[4 * tp.ff_inst[path_epi[q]]];
+      if (pair_contrib<T>(rule, sl, wns, v)) {
+        cnt = (e - b) / 2;
+        s_b[threadIdx.x] = b + 1;
+        s_q[threadIdx.x] = q;
+        s_v[threadIdx.x] = v;
       }
+    }
+  }
+  // inclusive scan of the counts over the first wave (np <= 64)
+  if (threadIdx.x < 64) {
+    int c = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(c, o, 64);
+      if ((int)threadIdx.x >= o) c += u;
+    }
+    s_pre[threadIdx.x + 1] = c;
+    if (threadIdx.x == 0) s_pre[0] = 0;
+  }
+  __syncthreads();
+  const int total = s_pre[np];
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    // the path holding occurrence idx: the last r with s_pre[r] <= idx
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= idx) lo = mid;
+      else hi = mid - 1;
+    }
+    const int t = path_int[s_b[lo] + 2 * (idx - s_pre[lo])] - tp.M;
+    if (t < 0 || t >= tp.S) continue;
+    const unsigned long long v = s_v[lo];
+    const int q = s_q[lo];
+    unsigned h = ((unsigned)t * 2654435761u) >> (32 - HASH_BITS);
+    for (int probe = 0; probe < HASH_SLOTS; ++probe) {
+      const int k = atomicCAS(&hkey[h], -1, t);
+      if (k == -1 || k == t) {
+        atomicAdd(&hacc[h], v);
+        atomicMin(&hfirst[h], q);
+        break;
+      }
+      h = (h + 1) & (HASH_SLOTS - 1);
     }
   }
   __syncthreads();
@@ -384,7 +420,7 @@ void pairs_update_impl(tdp_graph g, int rule, float w0, float w1, hipStream_t s)
                        g->pin_p);
   // a path has at most depth + 1 sinks; keep a block's occurrences within
   // 80 % of the hash table, otherwise fall back to plain global atomics
-  const int per_block = (HASH_SLOTS * 4 / 5) / (tp.D + 1);
+  const int per_block = std::min(ACC_MAX_PATHS, (HASH_SLOTS * 4 / 5) / (tp.D + 1));
   if (per_block >= 1)
     hipLaunchKernelGGL(k_pairs_acc_lds<T>, dim3(nb(std::max(g->slot_cap, g->max_out), per_block)), dim3(256), 0, s, tp, rule, per_block,
                        g->d_nslots, g->slot_out, g->path_ptr, g->path_int, g->path_epi, (const T *)g->path_slack,
