@@ -113,6 +113,9 @@ def parse():
                          "against timing-driven runs, and the time per iteration")
     ap.add_argument("--net-model", type=int, default=0, choices=(0, 1),
                     help="0: lumped RC wires (Eq. 7); 1: Elmore star nets with degraded sink transitions")
+    ap.add_argument("--configs", action="store_true",
+                    help="one line per workload (2k, 200k, 1M and 2M cells, and the batched union), each from its "
+                         "own run of this script, with the oracle's rate where it finishes in seconds")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MB",
                     help="after timing, run one plain device copy of MB MiB (counter calibration)")
     return ap.parse_args()
@@ -389,6 +392,8 @@ def main():
     from paper_2503_11674_amd import netgen
     from paper_2503_11674_amd.tdp import TimingGraph, STAGES, TdpError
 
+    if a.configs:
+        return bench_configs(a)
     if a.workload == "C4":
         return bench_batch(a)
     if a.table1:
@@ -589,6 +594,8 @@ def main():
     rng = np.random.default_rng(11)
     movable = np.nonzero(np.asarray(nl["cell_fixed"]) == 0)[0]
     for m in (100, 1000, 10_000, 100_000):
+        if m > len(movable) // 2:
+            break
         cells = np.sort(rng.choice(movable, m, replace=False)).astype(np.int32)
         ct = torch.tensor(cells, device=dev, dtype=torch.long)
         xn, yn = x.clone(), y.clone()
@@ -682,6 +689,42 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(nl, lib, k, K, pins)
     print(json.dumps(out))
+
+
+def bench_configs(a):
+    """The step on every workload: each in a child run of this script (its
+    own autotuning and timing), summarised in one JSON line."""
+    import subprocess
+    rows = {}
+    for w in ("C1", "C2", "C3", "C5", "C4"):
+        cmd = [sys.executable, os.path.abspath(__file__), "--workload", w, "--steps", str(a.steps), "--warmup",
+               str(a.warmup), "--no-batch"]
+        if w in ("C5", "C4") or a.no_cpu:  # the default run carries the 2M-cell oracle rate
+            cmd.append("--no-cpu")
+        print(f"[bench] workload {w}", file=sys.stderr, flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True, timeout=1200)
+        if r.returncode != 0:
+            sys.stderr.write(r.stderr[-3000:])
+            raise SystemExit(f"the run for {w} failed ({r.returncode})")
+        d = json.loads(r.stdout.strip().splitlines()[-1])
+        row = {"workload": d["config"]["workload"], "pins_per_s": d["value"], "ms_per_step": d["ms_per_step"]}
+        for key in ("sta_extract_pins_per_s", "p2p_fwd_bwd_GBps", "step_hbm_frac", "batched_graph_ms",
+                    "per_instance_eager_ms", "per_instance_graph_ms", "speedup_vs_per_instance_eager",
+                    "speedup_vs_per_instance_graph"):
+            if d.get(key) is not None:
+                row[key] = d[key]
+        if d.get("roofline"):
+            row["roofline"] = {k: d["roofline"][k] for k in ("kernel", "achieved", "frac")}
+        if d.get("cpu_baseline"):
+            cb = d["cpu_baseline"]
+            row["oracle_pins_per_s"] = cb["value"]
+            row["oracle_sta_extract_pins_per_s"] = cb["sta_extract_pins_per_s"]
+            row["oracle_cores"] = cb["cores"]
+        rows[w] = row
+        print(f"[bench] {w}: {json.dumps(row)}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "timing-graph pins/s for STA+top-K extraction; p2p loss fwd+bwd GB/s, per workload",
+                      "unit": "pins/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "dtype": "f32",
+                      "data": "synthetic", "per_config": rows}))
 
 
 def bench_batch(a):

@@ -210,7 +210,9 @@ tdp_status tdp_sta_update_arrivals_incremental(tdp_graph, const float *d_x, cons
 
 /* WNS and TNS (Eqs. 3-4; both 0 without violations) and the number of
  * violated endpoints of the last update.  Synchronises the stream.  For a
- * batched graph this is the union's; see tdp_batch_summary. */
+ * batched graph this is the union's; see tdp_batch_summary.  TDP_E_INVALID
+ * when a cell position given to the last arrival pass was NaN or infinite
+ * (the timing results of that pass are then meaningless). */
 tdp_status tdp_sta_summary(tdp_graph, double *wns, double *tns, int32_t *n_fail, hipStream_t);
 tdp_status tdp_batch_summary(tdp_graph, double *wns, double *tns, int32_t *n_fail, hipStream_t);
 
@@ -523,9 +525,14 @@ tdp_status tdp_set_tuning(tdp_graph, int32_t flow_waves, int32_t flow_per_cu, in
  * extract_paths(n, k, K) (k = 0: the update alone) under every sweep
  * configuration the graph supports (per-level launches; resident dataflow
  * grids for both sweeps or for the required times only, with 1, 2 or 4
- * waves per workgroup and 1, 2 or 4 workgroups per compute unit), one warm-up and `reps` timed runs each (1..1000), and keeps
- * the fastest.  h_choice (4 int32, host, may be NULL) receives {sweep_mode,
- * flow_waves, flow_per_cu, microseconds per run}.  Synchronises; on return
+ * waves per workgroup and 1, 2 or 4 workgroups per compute unit), one
+ * warm-up and `reps` timed runs each (1..1000), and keeps the fastest.
+ * Choices are kept for the life of the process by graph signature (device,
+ * precision, pin / cell / net / endpoint counts, depth, instances,
+ * deviation-list width, n, k, K): a later call for a graph with the same
+ * signature takes the kept choice without trials.  h_choice (4 int32, host,
+ * may be NULL) receives {sweep_mode, flow_waves, flow_per_cu, microseconds
+ * per run as measured when the choice was made}.  Synchronises; on return
  * the graph holds the chosen configuration's results for these positions.
  * Errors as tdp_sta_update / tdp_extract_paths. */
 tdp_status tdp_autotune(tdp_graph, const float *d_x, const float *d_y, int32_t n, int32_t k, int32_t K,

@@ -17,7 +17,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tdp_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "libtdp_oracle.so")
+# TDP_ORACLE_LIB: a separately built copy of the same source (the sanitizer
+# test builds one); it is loaded as it is, never rebuilt here
+_LIB_PATH = os.environ.get("TDP_ORACLE_LIB") or os.path.join(_HERE, "libtdp_oracle.so")
 _lib = None
 
 
@@ -30,7 +32,8 @@ def build_oracle() -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if not os.environ.get("TDP_ORACLE_LIB") and (not os.path.exists(_LIB_PATH) or
+                                                     os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
             build_oracle()
         _lib = ctypes.CDLL(_LIB_PATH)
     return _lib

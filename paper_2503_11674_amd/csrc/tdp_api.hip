@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <vector>
 #include <mutex>
 #include <new>
@@ -384,11 +385,13 @@ tdp_status tdp_sta_summary(tdp_graph g, double *wns, double *tns, int32_t *n_fai
   if (!g->updated) return fail(g, TDP_E_STATE, "no timing update yet");
   const int ni = g->topo.num_inst;
   std::vector<double> h(4 * ni);
-  int32_t err = 0;
+  int32_t errs[2] = {0, 0};
   if (hipStreamSynchronize(s) != hipSuccess ||
       hipMemcpy(h.data(), g->summary, sizeof(double) * 4 * ni, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(&err, g->d_err, 4, hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(errs, g->d_err, 8, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(g, TDP_E_DEVICE, "summary copy failed");
+  const int32_t err = errs[0];
+  if (errs[1] == g->pos_gen) return fail(g, TDP_E_INVALID, "a cell position of the last update is NaN or infinite");
   if (err & 2) return fail(g, TDP_E_DEVICE, "a dataflow sweep gave up waiting (results are invalid)");
   if (err & 4) return fail(g, TDP_E_DEVICE, "an incremental update was given a cell id outside [0, num_cells)");
   double w = 0, t = 0, n = 0;
@@ -1049,12 +1052,41 @@ tdp_status tdp_set_tuning(tdp_graph g, int32_t flow_waves, int32_t flow_per_cu, 
   return TDP_OK;
 }
 
+// autotuner choices of this process, by graph signature: device, precision,
+// sizes, depth, instances, deviation-list width and the extraction asked for
+struct TuneChoice {
+  int mode, waves, per_cu, us;
+};
+static std::mutex g_tune_mu;
+static std::map<std::vector<int64_t>, TuneChoice> g_tune_cache;
+
 tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, int32_t k, int32_t K, int32_t reps,
                         int32_t *choice, hipStream_t s) {
   GUARD(g);
   if (!x || !y) return fail(g, TDP_E_INVALID, "positions are NULL");
   if (reps < 1 || reps > 1000) return fail(g, TDP_E_INVALID, "reps must be 1..1000");
   if (k < 0 || k > g->max_k) return fail(g, TDP_E_CAPACITY, "k outside 0..max_k");
+  const Topo &T = g->topo;
+  const std::vector<int64_t> sig = {g->device, (int64_t)g->prec, T.N, T.P, T.M, T.S, T.A, T.E, T.D, T.n_comb,
+                                    T.num_inst, g->side_k, g->flow_ok ? 1 : 0, g->num_cu, n, k, K};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(sig);
+    if (it != g_tune_cache.end()) {  // tuned before: no trials
+      g->sweep_mode = it->second.mode;
+      g->flow_waves = it->second.waves;
+      g->flow_per_cu = it->second.per_cu;
+      if (choice) {
+        choice[0] = it->second.mode;
+        choice[1] = it->second.waves;
+        choice[2] = it->second.per_cu;
+        choice[3] = it->second.us;
+      }
+      tdp_status r = tdp_sta_update(g, x, y, s);
+      if (r == TDP_OK && k > 0) r = tdp_extract_paths(g, n, k, K, std::numeric_limits<float>::infinity(), s, nullptr);
+      return r;
+    }
+  }
   struct Cand {
     int mode, waves, per_cu;
   };
@@ -1112,11 +1144,16 @@ tdp_status tdp_autotune(tdp_graph g, const float *x, const float *y, int32_t n, 
   // leave the results of the chosen configuration behind
   st = run();
   if (st != TDP_OK) return st;
+  const int us = std::isfinite(best) ? (int32_t)std::lround(best * 1000.0f) : -1;
   if (choice) {
     choice[0] = best_c.mode;
     choice[1] = best_c.waves;
     choice[2] = best_c.per_cu;
-    choice[3] = std::isfinite(best) ? (int32_t)std::lround(best * 1000.0f) : -1;
+    choice[3] = us;
+  }
+  if (std::isfinite(best)) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[sig] = TuneChoice{best_c.mode, best_c.waves, best_c.per_cu, us};
   }
   return TDP_OK;
 }

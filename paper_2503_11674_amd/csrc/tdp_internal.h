@@ -256,6 +256,7 @@ struct tdp_graph_s {
   int32_t num_cu = 0;            // compute units of the device
   int32_t occ_fw[3] = {-1, -1, -1}, occ_bw[3] = {-1, -1, -1};  // occupancy per 1 / 2 / 4 waves, -1 = not yet
   bool flow_ok = false;          // the graph can use the dataflow sweeps
+  int32_t pos_gen = 0;           // arrival passes so far; d_err[1] == pos_gen: a position was not finite
   bool flow_r_clear = false;     // flow_r holds no published word (the last net pass reset it)
   bool drv_as_stale = false;     // drv_as of the combinational drivers predates the last forward sweep
   double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;

@@ -17,8 +17,10 @@ void radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int cap,
                 int32_t *hist, int32_t *scan_tmp, hipStream_t s);
 int sort_hist_size(int cap);
 void fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
-// xy[i] = (x[i], y[i]): one 8-byte gather per random position lookup
-void pack_xy(const float *x, const float *y, float2 *xy, int n, hipStream_t s);
+// xy[i] = (x[i], y[i]): one 8-byte gather per random position lookup; where
+// a coordinate is NaN or infinite, *bad = gen (if bad is given)
+void pack_xy(const float *x, const float *y, float2 *xy, int n, hipStream_t s, int32_t *bad = nullptr,
+             int32_t gen = 0);
 
 // order-preserving maps from floating point to unsigned integers
 __host__ __device__ __forceinline__ uint64_t order_key(float f) {

@@ -294,12 +294,17 @@ void radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int cap,
 }
 
 // ------------------------------------------------------ packed positions
-__global__ void k_pack_xy(const float *__restrict__ x, const float *__restrict__ y, float2 *__restrict__ xy, int n) {
+__global__ void k_pack_xy(const float *__restrict__ x, const float *__restrict__ y, float2 *__restrict__ xy, int n,
+                          int32_t *__restrict__ bad, int32_t gen) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) xy[i] = make_float2(x[i], y[i]);
+  if (i >= n) return;
+  const float a = x[i], b = y[i];
+  xy[i] = make_float2(a, b);
+  // every writer stores the same value, so no atomic is needed
+  if (bad && !(__builtin_isfinite(a) && __builtin_isfinite(b))) *bad = gen;
 }
-void pack_xy(const float *x, const float *y, float2 *xy, int n, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_pack_xy, dim3((n + 255) / 256), dim3(256), 0, s, x, y, xy, n);
+void pack_xy(const float *x, const float *y, float2 *xy, int n, hipStream_t s, int32_t *bad, int32_t gen) {
+  if (n > 0) hipLaunchKernelGGL(k_pack_xy, dim3((n + 255) / 256), dim3(256), 0, s, x, y, xy, n, bad, gen);
 }
 
 // ---------------------------------------------------------- small fills

@@ -1043,7 +1043,7 @@ template <typename T>
 static void netpass_launch(tdp_graph g, const float *x, const float *y, const FlowInit &fl, hipStream_t s) {
   const Topo &tp = g->topo;
   const NetModel<T> nm = net_model<T>(g);
-  pack_xy(x, y, g->xy, tp.N, s);
+  pack_xy(x, y, g->xy, tp.N, s, g->d_err + 1, ++g->pos_gen);
   hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4) + fl.reset_blocks), dim3(256), 0, s, tp, g->lut,
                      g->xy, nm,
                      (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
@@ -1183,7 +1183,7 @@ void sta_arrivals_incremental_impl(tdp_graph g, const float *x, const float *y, 
   if (n > 0)
     hipLaunchKernelGGL(k_inc_mark, dim3(nblk(n, 256)), dim3(256), 0, s, tp, cells, n, g->inc_drv_nm_chunk,
                        g->inc_nm, inc.epoch, g->d_err);
-  pack_xy(x, y, g->xy, tp.N, s);
+  pack_xy(x, y, g->xy, tp.N, s, g->d_err + 1, ++g->pos_gen);
   if (n > 0)
     hipLaunchKernelGGL(k_netpass_marked<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, nm,
                        (T)g->c,

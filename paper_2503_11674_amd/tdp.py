@@ -584,7 +584,9 @@ class TimingGraph:
 
     def autotune(self, x, y, n: int = -1, k: int = 1, K: Optional[int] = None, reps: int = 3,
                  stream=None) -> Dict[str, int]:
-        """Pick the fastest sweep configuration for update + extraction."""
+        """Pick the fastest sweep configuration for update + extraction; a
+        graph of a signature tuned before in this process takes the kept
+        choice (and its measured time) without trials."""
         K = self.max_paths if K is None else K
         ch = np.zeros(4, np.int32)
         _check(tdp_autotune(self.h, _ptr(self._cells(x)), _ptr(self._cells(y)), n, k, K, reps, ch.ctypes.data,

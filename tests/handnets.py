@@ -111,3 +111,30 @@ def diamond_netlist():
     x = [24.0, 48.0, 72.0]
     y = [0.0, 0.0, 0.0]
     return build(cells, 1, nets, x, y, port_xy=[(0.0, 0.0)], clock_period=50.0)
+
+
+def invalid_chain(mutation: str):
+    """The hand chain with one fault the build must reject (TDP_E_INVALID):
+    sink_in_two_nets, driver_is_input, dangling_input, ff_two_inputs,
+    bad_type, pin_out_of_range."""
+    nl, _ = chain_netlist()
+    nl = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in nl.items()}
+    if mutation == "sink_in_two_nets":
+        nl["net_pins"] = np.array([6, 0, 1, 2, 0, 3, 4, 5], np.int32)
+        nl["net_ptr"] = np.array([0, 2, 5, 7, 8], np.int32)
+    elif mutation == "driver_is_input":
+        nl["net_pins"][0] = 0
+    elif mutation == "dangling_input":
+        nl["net_pins"] = np.array([6, 1, 2, 3, 4, 5], np.int32)
+        nl["net_ptr"] = np.array([0, 1, 3, 5, 6], np.int32)
+    elif mutation == "ff_two_inputs":
+        cells = [(0, 1), (7, 2)]
+        nets = [(5, [0]), (1, [2, 3]), (4, [])]
+        nl, _ = build(cells, 1, nets, [1.0, 2.0], [0.0, 0.0])
+    elif mutation == "bad_type":
+        nl["cell_type"][0] = 99
+    elif mutation == "pin_out_of_range":
+        nl["net_pins"][1] = 1000
+    else:
+        raise KeyError(mutation)
+    return nl

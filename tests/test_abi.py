@@ -67,24 +67,7 @@ def test_cycle_is_rejected():
     ("pin_out_of_range", "out of range"),
 ])
 def test_invalid_netlists(mutation, expect):
-    nl, pins = handnets.chain_netlist()
-    nl = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in nl.items()}
-    if mutation == "sink_in_two_nets":
-        nl["net_pins"] = np.array([6, 0, 1, 2, 0, 3, 4, 5], np.int32)
-        nl["net_ptr"] = np.array([0, 2, 5, 7, 8], np.int32)
-    elif mutation == "driver_is_input":
-        nl["net_pins"][0] = 0
-    elif mutation == "dangling_input":
-        nl["net_pins"] = np.array([6, 1, 2, 3, 4, 5], np.int32)
-        nl["net_ptr"] = np.array([0, 1, 3, 5, 6], np.int32)
-    elif mutation == "ff_two_inputs":
-        cells = [(0, 1), (7, 2)]
-        nets = [(5, [0]), (1, [2, 3]), (4, [])]
-        nl, _ = handnets.build(cells, 1, nets, [1.0, 2.0], [0.0, 0.0])
-    elif mutation == "bad_type":
-        nl["cell_type"][0] = 99
-    elif mutation == "pin_out_of_range":
-        nl["net_pins"][1] = 1000
+    nl = handnets.invalid_chain(mutation)
     st, msg = _build_status(nl)
     assert st == 1 and expect in msg, (st, msg)
 

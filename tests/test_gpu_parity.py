@@ -466,6 +466,40 @@ def test_zero_copy_timing_views(precision, library):
     g.close()
 
 
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_non_finite_positions_are_reported(bad, library):
+    """A NaN or infinite cell coordinate makes the summary of that update an
+    invalid-argument error; the next update at finite positions is clean,
+    and so is its incremental form."""
+    tdp = _tdp()
+    c = case("C1", library)
+    nl = c["nl"]
+    g = tdp.TimingGraph(nl, library, max_paths=200, max_k=2)
+    g.sta_update(c["x"], c["y"])
+    ref_summary = g.summary()
+    for axis in (0, 1):
+        x, y = c["x"].clone(), c["y"].clone()
+        (x if axis == 0 else y)[17] = bad
+        g.sta_update(x, y)
+        with pytest.raises(tdp.TdpError) as e:
+            g.summary()
+        assert e.value.status == 1
+        g.sta_update(c["x"], c["y"])
+        assert g.summary() == ref_summary
+    x = c["x"].clone()
+    x[17] = bad
+    cells = torch.tensor([17], dtype=torch.int32, device=x.device)
+    g.sta_update_arrivals_incremental(x, c["y"], cells)
+    g.sta_update_required()
+    with pytest.raises(tdp.TdpError) as e:
+        g.summary()
+    assert e.value.status == 1
+    g.sta_update_arrivals_incremental(c["x"], c["y"], cells)
+    g.sta_update_required()
+    assert g.summary() == ref_summary
+    g.close()
+
+
 def test_autograd_on_column_views_of_a_position_matrix(library):
     # placers keep positions as one [N, 2] tensor; its columns are strided
     # views, which the autograd Functions must hand to the kernels as
@@ -840,6 +874,15 @@ def test_autotune_keeps_results(library):
         assert np.array_equal(p[key], p0[key]), key
     with pytest.raises(tdp.TdpError):
         g.autotune(c["x"], c["y"], reps=0)
+    # a second graph of the same signature takes the kept choice (the time
+    # reported is the one measured when the choice was made) and its results
+    g2 = tdp.TimingGraph(c["nl"], library, max_paths=c["K"], max_k=c["k"])
+    ch2 = g2.autotune(c["x"], c["y"], n=-1, k=c["k"], K=c["K"], reps=2)
+    assert ch2 == ch
+    o2 = {k: v.cpu().numpy() for k, v in g2.export().items()}
+    for key in o:
+        assert np.array_equal(o2[key], o[key]), key
+    g2.close()
     g.close()
 
 
