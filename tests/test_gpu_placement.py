@@ -248,3 +248,76 @@ def test_loop_trajectory_matches_the_oracle_composition(library):
     assert np.median(moved) > 0.1  # the cells did move
     err = np.abs(gpu_x - st["ux"]) + np.abs(gpu_y - st["uy"])
     assert np.all(err <= 1e-2 * moved + 1e-3), (err.max(), moved[err.argmax()])
+
+
+def test_loop_with_timing_matches_the_oracle_composition(library):
+    """Six iterations of the timing-driven placer (timing every second
+    iteration from iteration 1) against the same loop composed from the
+    oracle: at each refresh the oracle times the current placement, extracts
+    report_timing_endpoint(n_fail, 1) and applies Eq. 9 to its own pair set,
+    and its PP gradient (beta-scaled) joins WA and density in every later
+    step.  Refresh, extraction, pair update and loss all enter the
+    trajectory."""
+    import math
+
+    from paper_2503_11674_amd.placer import GlobalPlacer, LoopConfig
+    nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), library)
+    E = int(np.count_nonzero(nl["cell_is_ff"]))
+    cfg = LoopConfig(die=1000.0, bins=32, beta=1e-2, timing_start=1, timing_every=2, record_every=1 << 30)
+    p = GlobalPlacer(nl, library, cfg)
+    p.run(iters=6)
+    gpu_x, gpu_y = (t.cpu().numpy().astype(np.float64) for t in p.positions())
+    gpu_pairs = p.g.pairs_count()
+    p.g.close()
+    N = nl["num_cells"]
+    grid = dict(x0=0.0, y0=0.0, bw=1000.0 / 32, bh=1000.0 / 32, gx=32, gy=32, R=3)
+    area = np.full(N, np.float32(0.5 * 1000.0 * 1000.0 / N), np.float32)
+    fixed = np.asarray(nl["cell_fixed"], np.uint8)
+    pins = np.bincount(np.asarray(nl["pin_cell"])[np.asarray(nl["pin_cell"]) >= 0], minlength=N)
+    pdiv = np.maximum(pins, 1).astype(np.float32).astype(np.float64)
+    x0, y0 = np.asarray(nl["x"], np.float64), np.asarray(nl["y"], np.float64)
+    st = {"vx": x0.copy(), "vy": y0.copy(), "ux": x0.copy(), "uy": y0.copy(), "vpx": x0.copy(), "vpy": y0.copy(),
+          "gpx": np.zeros(N), "gpy": np.zeros(N)}
+    _, wgx, wgy = ref.wa(nl, cfg.wa_gamma, st["vx"], st["vy"])
+    d = ref.density(st["vx"], st["vy"], area, fixed, grid, cfg.target)
+    lam = cfg.lambda_init * (np.abs(wgx).sum() + np.abs(wgy).sum()) / (np.abs(d["grad_x"]).sum() + np.abs(d["grad_y"]).sum())
+    ps = ref.PairState(nl["num_pins"])
+    timing_on = False
+    a_k, wl_prev, wl_ref = 1.0, None, None
+    for it in range(6):
+        if it >= 1 and (it - 1) % 2 == 0:  # refresh at the current placement u
+            sta = ref.sta(nl, library, x=st["ux"].astype(np.float32), y=st["uy"].astype(np.float32))
+            paths = ref.extract(nl, library, sta, n=-1, k=1, K=E)
+            ref.pairs_update(ps, paths, sta["wns"], rule=0, w0=cfg.w0, w1=cfg.w1)
+            timing_on = True
+        wl, wgx, wgy = ref.wa(nl, cfg.wa_gamma, st["vx"], st["vy"])
+        d = ref.density(st["vx"], st["vy"], area, fixed, grid, cfg.target)
+        gx, gy = wgx + lam * d["grad_x"], wgy + lam * d["grad_y"]
+        if timing_on:
+            sinks, w = ps.pairs()
+            _, pgx, pgy = ref.p2p(nl, sinks, w, st["vx"], st["vy"])
+            gx, gy = gx + cfg.beta * pgx, gy + cfg.beta * pgy
+        a_n = (1 + math.sqrt(4 * a_k * a_k + 1)) / 2
+        ref.nesterov(st, gx, gy, pdiv, fixed, (a_k - 1) / a_n, cfg.alpha0, it == 0, (0.0, 1000.0, 0.0, 1000.0))
+        a_k = a_n
+        if wl_prev is None:
+            mu, wl_ref = cfg.mu_max, cfg.wl_ref_frac * abs(wl)
+        else:
+            mu = min(cfg.mu_max, max(cfg.mu_min, cfg.mu_max ** (1 - (wl - wl_prev) / wl_ref)))
+        wl_prev = wl
+        lam *= mu
+    sinks, _ = ps.pairs()
+    assert gpu_pairs == len(sinks) > 0
+    # the same bound as the loop without timing: 1 % of each cell's own move
+    # plus FP32 rounding of the position
+    moved = np.abs(st["ux"] - x0) + np.abs(st["uy"] - y0)
+    assert np.median(moved) > 0.1
+    err = np.abs(gpu_x - st["ux"]) + np.abs(gpu_y - st["uy"])
+    assert np.all(err <= 1e-2 * moved + 1e-3), (err.max(), moved[err.argmax()])
+    # and timing moved the placement: the loop without it ends elsewhere
+    cfg0 = LoopConfig(die=1000.0, bins=32, beta=0.0, record_every=1 << 30)
+    p0 = GlobalPlacer(nl, library, cfg0)
+    p0.run(iters=6)
+    x_off = p0.positions()[0].cpu().numpy().astype(np.float64)
+    p0.g.close()
+    assert np.abs(x_off - gpu_x).max() > 10 * err.max()
