@@ -231,16 +231,16 @@ void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStr
 __device__ __forceinline__ float wa_lane(float c, float o, bool valid, int lane, int head, int tail, float ig,
                                          float &grad) {
   const float X = c + o;
-  const float mx = seg_max(valid ? X : -3.0e38f, lane, head, tail);
-  const float mn = seg_min(valid ? X : 3.0e38f, lane, head, tail);
-  const int am = seg_min((valid && X == mx) ? lane : 64, lane, head, tail) & 63;
-  const int an = seg_min((valid && X == mn) ? lane : 64, lane, head, tail) & 63;
+  const float mx = seg_max_dpp(valid ? X : -3.0e38f, lane, head, tail);
+  const float mn = seg_min_dpp(valid ? X : 3.0e38f, lane, head, tail);
+  const int am = seg_min_dpp((valid && X == mx) ? lane : 64, lane, head, tail) & 63;
+  const int an = seg_min_dpp((valid && X == mn) ? lane : 64, lane, head, tail) & 63;
   const float cm = __shfl(c, am, 64), om = __shfl(o, am, 64);
   const float cn = __shfl(c, an, 64), on = __shfl(o, an, 64);
   const float d = valid ? (c - cm) + (o - om) : 0.f, e = valid ? (c - cn) + (o - on) : 0.f;
   const float a = valid ? expf(d * ig) : 0.f, b = valid ? expf(-e * ig) : 0.f;
-  const float sa = seg_sum(a, lane, head, tail), sda = seg_sum(a * d, lane, head, tail);
-  const float sb = seg_sum(b, lane, head, tail), seb = seg_sum(b * e, lane, head, tail);
+  const float sa = seg_sum_dpp(a, lane, head, tail), sda = seg_sum_dpp(a * d, lane, head, tail);
+  const float sb = seg_sum_dpp(b, lane, head, tail), seb = seg_sum_dpp(b * e, lane, head, tail);
   const float fp = valid ? sda / sa : 0.f, fm = valid ? seb / sb : 0.f;
   grad = valid ? a / sa * (1.f + (d - fp) * ig) - b / sb * (1.f - (e - fm) * ig) : 0.f;
   return valid ? ((cm - cn) + (om - on)) + fp - fm : 0.f;

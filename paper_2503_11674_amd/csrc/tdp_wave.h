@@ -3,6 +3,7 @@
 // the result is the same for every lane of a segment and is computed in a
 // fixed order, so it does not depend on timing.
 #pragma once
+
 #include <hip/hip_runtime.h>
 
 namespace tdp {
@@ -26,6 +27,12 @@ template <> __device__ __forceinline__ double pos_inf<double>() { return __built
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 
+// Segmented reductions over the 64 lanes of a wave (segment [head, tail],
+// the result broadcast to every lane).  These shuffle forms combine lane L
+// with lane L - d for d = 1, 2, 4, ..., so the order of the operations
+// depends only on the offsets within the segment: the same segment gives the
+// same bits wherever it sits in a wave (a batched graph's chunks equal its
+// instances' bitwise).  Every lane of the wave must call them.
 template <typename T>
 __device__ __forceinline__ T seg_sum(T v, int lane, int head, int tail) {
 #pragma unroll
@@ -54,6 +61,59 @@ __device__ __forceinline__ T seg_min(T v, int lane, int head, int tail) {
     if (lane - d >= head) v = u < v ? u : v;
   }
   return __shfl(v, tail, 64);
+}
+
+// The same reductions with DPP lane moves (no LDS traffic, a fraction of the
+// shuffles' cost): shifts by 1, 2, 4 and 8 within rows of 16 lanes, then
+// the last lane of rows 0 / 2 into rows 1 / 3, then lane 31 into rows 2 and
+// 3.  A lane takes a value only from lanes of its own segment, so after the
+// six steps lane L holds op over [head, L]; one shuffle broadcasts the tail
+// lane's.  The association follows the row boundaries, so a sum's rounding
+// depends on where the segment sits: for values that are not compared
+// across layouts.  Every lane of the wave must call them.
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_move_t(T v) {
+  static_assert(sizeof(T) == 4, "32-bit lanes");
+  return __builtin_bit_cast(T, dpp_move<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+template <typename T, typename Op>
+__device__ __forceinline__ T seg_scan_dpp(T v, int lane, int head, Op op) {
+  const int r = lane & 15, row = lane >> 4;
+  T u;
+  u = dpp_move_t<0x111>(v);  // row_shr:1
+  if (r >= 1 && lane - 1 >= head) v = op(v, u);
+  u = dpp_move_t<0x112>(v);  // row_shr:2
+  if (r >= 2 && lane - 2 >= head) v = op(v, u);
+  u = dpp_move_t<0x114>(v);  // row_shr:4
+  if (r >= 4 && lane - 4 >= head) v = op(v, u);
+  u = dpp_move_t<0x118>(v);  // row_shr:8
+  if (r >= 8 && lane - 8 >= head) v = op(v, u);
+  u = dpp_move_t<0x142>(v);  // row_bcast:15, taken by rows 1 and 3
+  if ((row & 1) && (lane & ~15) - 1 >= head) v = op(v, u);
+  u = dpp_move_t<0x143>(v);  // row_bcast:31, taken by rows 2 and 3
+  if (row >= 2 && 31 >= head) v = op(v, u);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_sum_dpp(T v, int lane, int head, int tail) {
+  return __shfl(seg_scan_dpp(v, lane, head, [](T a, T b) { return a + b; }), tail, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_max_dpp(T v, int lane, int head, int tail) {
+  return __shfl(seg_scan_dpp(v, lane, head, [](T a, T b) { return b > a ? b : a; }), tail, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T seg_min_dpp(T v, int lane, int head, int tail) {
+  return __shfl(seg_scan_dpp(v, lane, head, [](T a, T b) { return b < a ? b : a; }), tail, 64);
 }
 
 // For segments of at most WM lanes: every lane fetches the values of lanes
