@@ -26,6 +26,7 @@
 #include "tdp_impl.h"
 #include "tdp_prims.h"
 #include "tdp_walk.h"
+#include "tdp_wave.h"
 
 namespace tdp {
 
@@ -158,10 +159,14 @@ __global__ void __launch_bounds__(64) k_search(Topo tp, int k, T slack_limit, co
     if (r + 1 == k || u < tp.n_start) continue;
     // children: one more deviation on the critical chain above u
     const size_t lb = (size_t)(u - tp.n_start) * KM;
+    T dl[KM];
+    int32_t pl[KM];
+    load_list<KM>(side_cost + lb, dl);
+    load_list<KM>(side_pin + lb, pl);
 #pragma unroll
     for (int j = 0; j < KM; ++j) {
-      const T d = side_cost[lb + j];
-      const int32_t p = side_pin[lb + j];
+      const T d = dl[j];
+      const int32_t p = pl[j];
       if (!(d < inf_of<T>())) break;
       // insert behind every candidate of equal cost (they were created earlier)
       T c = cost + d;

@@ -458,11 +458,8 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
   if constexpr (KM > 1) {
     if (is_head && pred >= tp.n_start) {
       const size_t pb = (size_t)(pred - tp.n_start) * KM;
-#pragma unroll
-      for (int j = 0; j < KM; ++j) {
-        kc[j] = side_cost[pb + j];
-        kp[j] = side_pin[pb + j];
-      }
+      load_list<KM>(side_cost + pb, kc);
+      load_list<KM>(side_pin + pb, kp);
     }
   }
   // incremental: whether this cell's list, hop records or chain depth change
@@ -511,12 +508,16 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
     }
     if (is_head) {
       const size_t cb = (size_t)c * KM;
+      if (inc.lst) {
+        T oc[KM];
+        int32_t op[KM];
+        load_list<KM>(side_cost + cb, oc);
+        load_list<KM>(side_pin + cb, op);
 #pragma unroll
-      for (int j = 0; j < KM; ++j) {
-        if (inc.lst) changed = changed || !same_bits(side_cost[cb + j], kc[j]) || side_pin[cb + j] != kp[j];
-        side_cost[cb + j] = kc[j];
-        side_pin[cb + j] = kp[j];
+        for (int j = 0; j < KM; ++j) changed = changed || !same_bits(oc[j], kc[j]) || op[j] != kp[j];
       }
+      store_list<KM>(side_cost + cb, kc);
+      store_list<KM>(side_pin + cb, kp);
     }
   }
   // the cells this one drives may take it as their critical input

@@ -148,6 +148,39 @@ __device__ __forceinline__ int wave_max_int(int v) {
   return v;
 }
 
+// KM consecutive list entries at a KM-aligned index, moved 16 bytes at a
+// time where the list's size allows (the arrays come 256-byte aligned)
+template <int KM, typename V>
+__device__ __forceinline__ void load_list(const V *__restrict__ p, V (&out)[KM]) {
+  if constexpr ((KM * sizeof(V)) % 16 == 0) {
+    const int4 *q = reinterpret_cast<const int4 *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(KM * sizeof(V) / 16); ++i) {
+      const int4 w = q[i];
+      __builtin_memcpy(&out[i * (16 / sizeof(V))], &w, 16);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KM; ++j) out[j] = p[j];
+  }
+}
+
+template <int KM, typename V>
+__device__ __forceinline__ void store_list(V *__restrict__ p, const V (&in)[KM]) {
+  if constexpr ((KM * sizeof(V)) % 16 == 0) {
+    int4 *q = reinterpret_cast<int4 *>(p);
+#pragma unroll
+    for (int i = 0; i < (int)(KM * sizeof(V) / 16); ++i) {
+      int4 w;
+      __builtin_memcpy(&w, &in[i * (16 / sizeof(V))], 16);
+      q[i] = w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < KM; ++j) p[j] = in[j];
+  }
+}
+
 // the library's tables staged in LDS: [slew axes][load axes][delay][slew]
 template <typename T>
 __device__ __forceinline__ void lut_lds(const float *__restrict__ s_lut, int nt, int ns, int nl, int type, T s,
