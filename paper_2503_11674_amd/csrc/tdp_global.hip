@@ -262,26 +262,33 @@ __global__ void __launch_bounds__(128) k_walk_nodes(Topo tp, const int32_t *__re
                                                      int32_t *__restrict__ path_ep, int32_t *__restrict__ path_epi,
                                                      T *__restrict__ path_slack, int32_t *__restrict__ err,
                                                      int pin_cap) {
-  __shared__ int32_t stage[2][128 * 33];
+  __shared__ int32_t stage[128 * WALK_ROW];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= *d_num_paths) return;
-  const int node = out_slot[q];
-  const int f = nd.ep[node];
-  const int lo = path_ptr[q], hi = path_ptr[q + 1];
-  if (lo < 0 || hi > pin_cap || hi - lo < 2) {
-    atomicOr(err, 1);
-    return;
+  // every lane stays to the end: the wave shares the walk's flush points
+  bool live = q < *d_num_paths;
+  int node = 0, f = 0, lo = 0, hi = 0;
+  if (live) {
+    node = out_slot[q];
+    f = nd.ep[node];
+    lo = path_ptr[q];
+    hi = path_ptr[q + 1];
+    if (lo < 0 || hi > pin_cap || hi - lo < 2) {
+      atomicOr(err, 1);
+      live = false;
+    }
   }
   LinkDevs ds;
   ds.dev = nd.dev;
   ds.par = nd.par;
   ds.node = node;
-  ds.nd = nd.ndev[node];
+  ds.nd = live ? nd.ndev[node] : 0;
   ds.used = 0;
   ds.nb = 0;
   ds.bi = 0;
-  RevWriter w{path_pins, path_int, stage[0] + threadIdx.x * 33, stage[1] + threadIdx.x * 33, hi - 1, lo, hi};
-  if (!walk_path(tp, hop4, w, f, [&]() { return ds.next(); })) atomicOr(err, 1);
+  RevWriter w{path_pins, path_int, stage + threadIdx.x * WALK_ROW, live ? hi - 1 : -1, live ? lo : 0, live ? hi : 0};
+  const bool ok = walk_path(tp, hop4, w, f, live, [&]() { return ds.next(); });
+  if (!live) return;
+  if (!ok) atomicOr(err, 1);
   path_ep[q] = tp.snk_ext[tp.A + f];
   path_epi[q] = f;
   path_slack[q] = nd.key[node];

@@ -262,31 +262,38 @@ __global__ void __launch_bounds__(128) k_walk(Topo tp, int k, const int32_t *__r
                                                int32_t *__restrict__ path_int, int32_t *__restrict__ path_ep,
                                                int32_t *__restrict__ path_epi, int32_t *__restrict__ path_rank,
                                                T *__restrict__ path_slack, int32_t *__restrict__ err, int pin_cap) {
-  __shared__ int32_t stage[2][128 * 33];
+  __shared__ int32_t stage[128 * WALK_ROW];
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= *d_num_paths) return;
-  const int slot = out_slot[q];
-  const int qs = slot / k, r = slot - qs * k;
-  const int base = qs * k;
-  const int f = sel[qs];
-  // deviations, upstream-most first (the walk meets them last to first)
+  // every lane stays to the end: the wave shares the walk's flush points
+  bool live = q < *d_num_paths;
+  int slot = 0, r = 0, f = 0, lo = 0, hi = 0;
   int devs[TDP_MAX_K];
   int nd = 0;
-  for (int a = r; a >= 0 && nd < TDP_MAX_K;) {
-    const int d = slot_dev[base + a];
-    if (d < 0) break;
-    devs[nd++] = d;
-    a = slot_par[base + a];
+  if (live) {
+    slot = out_slot[q];
+    const int qs = slot / k;
+    r = slot - qs * k;
+    const int base = qs * k;
+    f = sel[qs];
+    // deviations, upstream-most first (the walk meets them last to first)
+    for (int a = r; a >= 0 && nd < TDP_MAX_K;) {
+      const int d = slot_dev[base + a];
+      if (d < 0) break;
+      devs[nd++] = d;
+      a = slot_par[base + a];
+    }
+    lo = path_ptr[q];
+    hi = path_ptr[q + 1];
+    if (lo < 0 || hi > pin_cap || hi - lo < 2) {  // only after a failed update
+      atomicOr(err, 1);
+      live = false;
+    }
   }
   int di = nd - 1;
-  const int lo = path_ptr[q];
-  const int hi = path_ptr[q + 1];
-  if (lo < 0 || hi > pin_cap || hi - lo < 2) {  // only after a failed update
-    atomicOr(err, 1);
-    return;
-  }
-  RevWriter w{path_pins, path_int, stage[0] + threadIdx.x * 33, stage[1] + threadIdx.x * 33, hi - 1, lo, hi};
-  if (!walk_path(tp, hop4, w, f, [&]() { return di >= 0 ? devs[di--] : -1; })) atomicOr(err, 1);
+  RevWriter w{path_pins, path_int, stage + threadIdx.x * WALK_ROW, live ? hi - 1 : -1, live ? lo : 0, live ? hi : 0};
+  const bool ok = walk_path(tp, hop4, w, f, live, [&]() { return di >= 0 ? devs[di--] : -1; });
+  if (!live) return;
+  if (!ok) atomicOr(err, 1);
   const int et = tp.A + f;
   path_ep[q] = tp.snk_ext[et];
   path_epi[q] = f;
