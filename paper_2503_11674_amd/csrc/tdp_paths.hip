@@ -126,8 +126,21 @@ __global__ void __launch_bounds__(64) k_search(Topo tp, int k, T slack_limit, co
   cc[0] = 0;
   int npop = 0;
   const int eroot = tp.snk_drv[tp.A + f];
-  for (int r = 0; r < k; ++r) {
-    if (!(cc[0] < inf_of<T>())) break;
+  // the slots found, kept in registers and written after the search: the
+  // loads of each round then never wait behind the stores of the last one
+  // (a wave's memory operations retire in order)
+  T okey[KM];
+  int32_t odev[KM], opar[KM], ocells[KM];
+#pragma unroll
+  for (int r = 0; r < KM; ++r) {
+    okey[r] = inf_of<T>();
+    odev[r] = -1;
+    opar[r] = -1;
+    ocells[r] = 0;
+  }
+#pragma unroll
+  for (int r = 0; r < KM; ++r) {
+    if (r >= k || !(cc[0] < inf_of<T>())) break;
     const T cost = cc[0];
     const int dev = cdv[0], par = cpr[0];
 #pragma unroll
@@ -148,13 +161,15 @@ __global__ void __launch_bounds__(64) k_search(Topo tp, int k, T slack_limit, co
     } else {
       u = tp.snk_drv[dev];
       const int dc = tp.snk_comb[dev];
-      cells = slot_cells[base + par] + 1 - cdep[tp.n_start + dc] + cdep[u];
+      int pc = 0;
+#pragma unroll
+      for (int j = 0; j < KM; ++j) pc = j == par ? ocells[j] : pc;
+      cells = pc + 1 - cdep[tp.n_start + dc] + cdep[u];
     }
-    slot_key[base + r] = sk;
-    slot_dev[base + r] = dev;
-    slot_par[base + r] = par;
-    slot_cells[base + r] = cells;
-    slot_len[base + r] = 2 * cells + 2;
+    okey[r] = sk;
+    odev[r] = dev;
+    opar[r] = par;
+    ocells[r] = cells;
     ++npop;
     if (r + 1 == k || u < tp.n_start) continue;
     // children: one more deviation on the critical chain above u
@@ -187,11 +202,15 @@ __global__ void __launch_bounds__(64) k_search(Topo tp, int k, T slack_limit, co
       }
     }
   }
-  for (int r = npop; r < k; ++r) {
-    slot_key[base + r] = inf_of<T>();
-    slot_len[base + r] = 0;
-    slot_dev[base + r] = -1;
-    slot_par[base + r] = -1;
+#pragma unroll
+  for (int r = 0; r < KM; ++r) {
+    if (r >= k) break;
+    const bool found = r < npop;
+    slot_key[base + r] = found ? okey[r] : inf_of<T>();
+    slot_dev[base + r] = found ? odev[r] : -1;
+    slot_par[base + r] = found ? opar[r] : -1;
+    slot_cells[base + r] = found ? ocells[r] : 0;
+    slot_len[base + r] = found ? 2 * ocells[r] + 2 : 0;
   }
   npop_out[q] = npop;
 }
