@@ -244,66 +244,52 @@ __global__ void k_cell_touched(int N, const int32_t *__restrict__ cnt, const int
   if (c < N && cnt[c] > 0) touched[tpos[c]] = c;
 }
 
-// incidence of pair q at a cell: the other cell (-1 for a port), this pin's
-// offset minus the other pin's, the weight; key orders the cell's list
+// incidences of pair q, first pass: a slot in each of its two cells' lists
+// (arbitrary order within a list) holding only the key that orders the list,
+// 2q at the sink's cell and 2q + 1 at the driver's
 __global__ void k_inc_fill(Topo tp, const int32_t *__restrict__ d_npairs, const int32_t *__restrict__ pair_cs,
-                           const int32_t *__restrict__ pair_ct, const float *__restrict__ pair_dox,
-                           const float *__restrict__ pair_doy, const float *__restrict__ pair_w,
-                           const int32_t *__restrict__ cell_ptr, int32_t *__restrict__ cell_cur,
-                           int32_t *__restrict__ inc_other, float *__restrict__ inc_dx, float *__restrict__ inc_dy,
-                           float *__restrict__ inc_w, int32_t *__restrict__ inc_key) {
+                           const int32_t *__restrict__ pair_ct, const int32_t *__restrict__ cell_ptr,
+                           int32_t *__restrict__ cell_cur, int32_t *__restrict__ inc_key) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= *d_npairs) return;
   const int cs = pair_cs[q], ct = pair_ct[q];
-  if (!tp.cell_fixed[ct]) {
-    const int slot = cell_ptr[ct] + atomicAdd(&cell_cur[ct], 1);
-    inc_other[slot] = cs;
-    inc_dx[slot] = -pair_dox[q];
-    inc_dy[slot] = -pair_doy[q];
-    inc_w[slot] = pair_w[q];
-    inc_key[slot] = 2 * q;
-  }
-  if (cs >= 0 && !tp.cell_fixed[cs]) {
-    const int slot = cell_ptr[cs] + atomicAdd(&cell_cur[cs], 1);
-    inc_other[slot] = ct;
-    inc_dx[slot] = pair_dox[q];
-    inc_dy[slot] = pair_doy[q];
-    inc_w[slot] = pair_w[q];
-    inc_key[slot] = 2 * q + 1;
-  }
+  if (!tp.cell_fixed[ct]) inc_key[cell_ptr[ct] + atomicAdd(&cell_cur[ct], 1)] = 2 * q;
+  if (cs >= 0 && !tp.cell_fixed[cs]) inc_key[cell_ptr[cs] + atomicAdd(&cell_cur[cs], 1)] = 2 * q + 1;
 }
 
-// order each touched cell's incidences by key (insertion sort; lists are
-// short) and reset the per-cell counters for the next build
-__global__ void k_inc_sort(const int32_t *__restrict__ d_ntouched, const int32_t *__restrict__ touched,
-                           const int32_t *__restrict__ cell_ptr, int32_t *__restrict__ cell_cnt,
+// second pass, one thread per slot: the slot's place in its cell's list is
+// the number of smaller keys in the list (keys are distinct), so every list
+// ends up in key order whatever order the first pass filled it in; writes
+// the incidence there (the other cell, -1 for a port; this pin's offset
+// minus the other pin's; the weight) and resets the cell's counters.  Only
+// loads precede the stores, so no load waits behind a store.
+__global__ void k_inc_rank(const int32_t *__restrict__ cell_ptr, int N, const int32_t *__restrict__ inc_key,
+                           const int32_t *__restrict__ pair_cs, const int32_t *__restrict__ pair_ct,
+                           const float *__restrict__ pair_dox, const float *__restrict__ pair_doy,
+                           const float *__restrict__ pair_w, int32_t *__restrict__ cell_cnt,
                            int32_t *__restrict__ cell_cur, int32_t *__restrict__ inc_other,
-                           float *__restrict__ inc_dx, float *__restrict__ inc_dy, float *__restrict__ inc_w,
-                           int32_t *__restrict__ inc_key) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= *d_ntouched) return;
-  const int c = touched[i];
-  const int b = cell_ptr[c], e = cell_ptr[c + 1];
-  for (int a = b + 1; a < e; ++a) {
-    const int key = inc_key[a], o = inc_other[a];
-    const float dx = inc_dx[a], dy = inc_dy[a], w = inc_w[a];
-    int z = a - 1;
-    while (z >= b && inc_key[z] > key) {
-      inc_key[z + 1] = inc_key[z];
-      inc_other[z + 1] = inc_other[z];
-      inc_dx[z + 1] = inc_dx[z];
-      inc_dy[z + 1] = inc_dy[z];
-      inc_w[z + 1] = inc_w[z];
-      --z;
+                           float *__restrict__ inc_dx, float *__restrict__ inc_dy, float *__restrict__ inc_w) {
+  const int total = cell_ptr[N];
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < total; a += gridDim.x * blockDim.x) {
+    const int key = inc_key[a];
+    const int q = key >> 1;
+    const bool drv = key & 1;  // this cell drives the pair
+    const int cs = pair_cs[q], ct = pair_ct[q];
+    const int c = drv ? cs : ct;
+    const int b = cell_ptr[c], e = cell_ptr[c + 1];
+    int rank = 0;
+    for (int z = b; z < e; ++z) rank += inc_key[z] < key;
+    const float dox = pair_dox[q], doy = pair_doy[q];
+    const int d = b + rank;
+    inc_other[d] = drv ? ct : cs;
+    inc_dx[d] = drv ? dox : -dox;
+    inc_dy[d] = drv ? doy : -doy;
+    inc_w[d] = pair_w[q];
+    if (rank == 0) {
+      cell_cnt[c] = 0;
+      cell_cur[c] = 0;
     }
-    inc_key[z + 1] = key;
-    inc_other[z + 1] = o;
-    inc_dx[z + 1] = dx;
-    inc_dy[z + 1] = dy;
-    inc_w[z + 1] = w;
   }
-  cell_cnt[c] = 0;
-  cell_cur[c] = 0;
 }
 
 // ------------------------------------------------------------------ loss
@@ -455,10 +441,10 @@ void pairs_compact(tdp_graph g, hipStream_t s) {
   hipLaunchKernelGGL(k_cell_touched, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp.N, g->cell_cnt, g->cell_flag,
                      g->touched);
   hipLaunchKernelGGL(k_inc_fill, dim3(nb(tp.S, 256)), dim3(256), 0, s, tp, g->d_npairs, g->pair_cs, g->pair_ct,
-                     g->pair_dox, g->pair_doy, g->pair_w, g->cell_ptr, g->cell_cur, g->inc_other, g->inc_dx,
-                     g->inc_dy, g->inc_w, g->inc_key);
-  hipLaunchKernelGGL(k_inc_sort, dim3(nb(tp.N, 256)), dim3(256), 0, s, g->d_ntouched, g->touched, g->cell_ptr,
-                     g->cell_cnt, g->cell_cur, g->inc_other, g->inc_dx, g->inc_dy, g->inc_w, g->inc_key);
+                     g->cell_ptr, g->cell_cur, g->inc_key);
+  hipLaunchKernelGGL(k_inc_rank, dim3(1024), dim3(256), 0, s, g->cell_ptr, tp.N, g->inc_key, g->pair_cs, g->pair_ct,
+                     g->pair_dox, g->pair_doy, g->pair_w, g->cell_cnt, g->cell_cur, g->inc_other, g->inc_dx,
+                     g->inc_dy, g->inc_w);
   g->pairs_built = true;
 }
 
