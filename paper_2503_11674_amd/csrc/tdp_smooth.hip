@@ -238,11 +238,15 @@ __device__ __forceinline__ float wa_lane(float c, float o, bool valid, int lane,
   const float cm = __shfl(c, am, 64), om = __shfl(o, am, 64);
   const float cn = __shfl(c, an, 64), on = __shfl(o, an, 64);
   const float d = valid ? (c - cm) + (o - om) : 0.f, e = valid ? (c - cn) + (o - on) : 0.f;
-  const float a = valid ? expf(d * ig) : 0.f, b = valid ? expf(-e * ig) : 0.f;
+  // exponents are <= 0 (d <= 0 <= e); the hardware exponential (2^(x log2 e))
+  // has a relative error of about |x| 2^-24 plus a few units in the last
+  // place, and terms with large |x| are negligible in the sums
+  const float a = valid ? __expf(d * ig) : 0.f, b = valid ? __expf(-e * ig) : 0.f;
   const float sa = seg_sum_dpp(a, lane, head, tail), sda = seg_sum_dpp(a * d, lane, head, tail);
   const float sb = seg_sum_dpp(b, lane, head, tail), seb = seg_sum_dpp(b * e, lane, head, tail);
-  const float fp = valid ? sda / sa : 0.f, fm = valid ? seb / sb : 0.f;
-  grad = valid ? a / sa * (1.f + (d - fp) * ig) - b / sb * (1.f - (e - fm) * ig) : 0.f;
+  const float ra = valid ? 1.f / sa : 0.f, rb = valid ? 1.f / sb : 0.f;  // sa, sb >= 1 (the extreme pin's term)
+  const float fp = sda * ra, fm = seb * rb;
+  grad = valid ? a * ra * (1.f + (d - fp) * ig) - b * rb * (1.f - (e - fm) * ig) : 0.f;
   return valid ? ((cm - cn) + (om - on)) + fp - fm : 0.f;
 }
 
@@ -256,16 +260,33 @@ __global__ void __launch_bounds__(256) k_wa_net(Topo tp, const float2 *__restric
   double acc = 0.0;
   const float ig = 1.0f / gam;
   const int lane = wave_lane();
-  for (int chunk = blockIdx.x * 4 + (threadIdx.x >> 6); chunk < tp.n_nm_chunks; chunk += gridDim.x * 4) {
+  const int stride = gridDim.x * 4;
+  // each chunk's inputs are loaded one chunk ahead, before the current
+  // chunk's stores: a wave's loads retire after its earlier stores, so a
+  // load issued after them would wait for them
+  auto fetch = [&](int chunk, int4 &rec, float2 &q, float &ox, float &oy) {
     const int k = chunk * CHUNK + lane;
-    const int4 rec = tp.nm_rec[k];
-    const int p = rec.x, cell = rec.y;
+    rec = tp.nm_rec[k];
+    q = cxy ? cxy[k] : (rec.y >= 0 ? xy[rec.y] : make_float2(0.f, 0.f));
+    ox = tp.nm_ox[k];
+    oy = tp.nm_oy[k];
+  };
+  int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  int4 nrec = make_int4(-1, -1, -1, 0);
+  float2 nq = make_float2(0.f, 0.f);
+  float nox = 0.f, noy = 0.f;
+  if (chunk < tp.n_nm_chunks) fetch(chunk, nrec, nq, nox, noy);
+  for (; chunk < tp.n_nm_chunks; chunk += stride) {
+    const int4 rec = nrec;
+    const float2 q = nq;
+    const float ox = nox, oy = noy;
+    if (chunk + stride < tp.n_nm_chunks) fetch(chunk + stride, nrec, nq, nox, noy);
+    const int p = rec.x;
     const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
     const bool valid = p >= 0;
     float gxp, gyp;
-    const float2 q = cxy ? cxy[k] : (cell >= 0 ? xy[cell] : make_float2(0.f, 0.f));
-    const float wx = wa_lane(q.x, tp.nm_ox[k], valid, lane, head, tail, ig, gxp);
-    const float wy = wa_lane(q.y, tp.nm_oy[k], valid, lane, head, tail, ig, gyp);
+    const float wx = wa_lane(q.x, ox, valid, lane, head, tail, ig, gxp);
+    const float wy = wa_lane(q.y, oy, valid, lane, head, tail, ig, gyp);
     if (valid) {
       gpin[2 * p] = gxp;
       gpin[2 * p + 1] = gyp;
