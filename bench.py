@@ -103,6 +103,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (40-instance) leg of the default run")
     ap.add_argument("--graph", action="store_true", help="replay the step as a captured HIP graph")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default launch configuration)")
+    ap.add_argument("--step-only", action="store_true",
+                    help="skip the legs after the timed steps (pair-loss variants, early analysis, rise / fall, "
+                         "incremental arrivals), e.g. for a profile of the step alone")
     ap.add_argument("--sweep-mode", type=int, default=-1, help="force a sweep form (0 per level, 1 dataflow)")
     ap.add_argument("--serial", action="store_true", help="run the whole step on one stream")
     ap.add_argument("--table1", action="store_true",
@@ -411,6 +414,101 @@ def bench_loop(a):
     print(json.dumps(out))
 
 
+def after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev):
+    """The legs timed after the step on the same graph: the three pair
+    distances, the early (hold) analysis, rise / fall timing and incremental
+    arrival updates; leaves the graph in the step's single-transition state."""
+    import torch
+
+    from paper_2503_11674_amd import netgen
+
+    # the three pair distances of Sec. III-C on the step's pair set, forward
+    # and backward, after the timed region (events on the current stream)
+    pair_ms = {}
+    one = torch.ones((), dtype=torch.float64, device=dev)
+    for kind, name in ((0, "quadratic"), (1, "manhattan"), (2, "euclidean")):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g.pair_loss_fwd(kind, x, y, out=pp)
+        g.pair_loss_bwd(kind, x, y, one, gx, gy)
+        e0.record()
+        for _ in range(20):
+            g.pair_loss_fwd(kind, x, y, out=pp)
+            g.pair_loss_bwd(kind, x, y, one, gx, gy)
+        e1.record()
+        e1.synchronize()
+        pair_ms[name] = round(e0.elapsed_time(e1) / 20, 4)
+    # the early (hold) analysis on the same update, outside the step: the hold
+    # time at which 5 % of the D pins fail
+    g.sta_update_early(0.0)
+    at_e = g.early_export()["at"].cpu().numpy()
+    hold = float(np.quantile(at_e[ep], 0.05))
+    g.sta_update_early(hold)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        g.sta_update_early(hold)
+    e1.record()
+    e1.synchronize()
+    whs, ths, n_hold = g.early_summary()
+    early = {"ms": round(e0.elapsed_time(e1) / 10, 4), "hold_ps": round(hold, 1), "whs": round(whs, 1),
+             "ths": round(ths, 1), "n_hold_fail": n_hold}
+
+    # rise / fall timing on the same positions, outside the step: the update
+    # and report_timing_endpoint(n_fail, 1) on it
+    rf_lib = netgen.make_rf_library(lib)
+    g.rf_setup(rf_lib)
+    g.sta_update_rf(x, y)
+    g.extract_paths_rf(n=-1)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    for _ in range(5):
+        g.sta_update_rf(x, y)
+    e1.record()
+    for _ in range(5):
+        g.extract_paths_rf(n=-1)
+    e2.record()
+    e2.synchronize()
+    rf_w, rf_t, rf_n = g.rf_summary()
+    rise_fall = {"update_ms": round(e0.elapsed_time(e1) / 5, 4), "extract_k1_ms": round(e1.elapsed_time(e2) / 5, 4),
+                 "wns": round(rf_w, 1), "tns": round(rf_t, 1), "n_fail": rf_n, "paths": g.paths_count()[0]}
+    g.sta_update(x, y)  # back to the single-transition state
+    torch.cuda.synchronize()
+
+    # incremental arrival updates against the full arrival pass: m cells move
+    # (seeded jitter), and the positions alternate between the two placements
+    # so that every call is a genuine update of m moved cells
+    incremental = {}
+    rng = np.random.default_rng(11)
+    movable = np.nonzero(np.asarray(nl["cell_fixed"]) == 0)[0]
+    for m in (100, 1000, 10_000, 100_000):
+        if m > len(movable) // 2:
+            break
+        cells = np.sort(rng.choice(movable, m, replace=False)).astype(np.int32)
+        ct = torch.tensor(cells, device=dev, dtype=torch.long)
+        xn, yn = x.clone(), y.clone()
+        xn[ct] += torch.tensor(rng.normal(0, 5.0, m).astype(np.float32), device=dev)
+        yn[ct] += torch.tensor(rng.normal(0, 5.0, m).astype(np.float32), device=dev)
+        cl = torch.tensor(cells, device=dev, dtype=torch.int32)
+        pos = ((xn, yn), (x, y))
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        g.sta_update_arrivals(x, y)
+        ev[0].record()
+        for i in range(10):
+            g.sta_update_arrivals(*pos[i & 1])
+        ev[1].record()
+        for i in range(10):
+            g.sta_update_arrivals_incremental(*pos[i & 1], cl)
+        ev[2].record()
+        ev[2].synchronize()
+        incremental[str(m)] = {"full_arrivals_ms": round(ev[0].elapsed_time(ev[1]) / 10, 4),
+                               "incremental_ms": round(ev[1].elapsed_time(ev[2]) / 10, 4)}
+    g.sta_update(x, y)
+    torch.cuda.synchronize()
+
+    return pair_ms, early, rise_fall, incremental
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -564,89 +662,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    # the three pair distances of Sec. III-C on the step's pair set, forward
-    # and backward, after the timed region (events on the current stream)
-    pair_ms = {}
-    one = torch.ones((), dtype=torch.float64, device=dev)
-    for kind, name in ((0, "quadratic"), (1, "manhattan"), (2, "euclidean")):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        g.pair_loss_fwd(kind, x, y, out=pp)
-        g.pair_loss_bwd(kind, x, y, one, gx, gy)
-        e0.record()
-        for _ in range(20):
-            g.pair_loss_fwd(kind, x, y, out=pp)
-            g.pair_loss_bwd(kind, x, y, one, gx, gy)
-        e1.record()
-        e1.synchronize()
-        pair_ms[name] = round(e0.elapsed_time(e1) / 20, 4)
-    # the early (hold) analysis on the same update, outside the step: the hold
-    # time at which 5 % of the D pins fail
-    g.sta_update_early(0.0)
-    at_e = g.early_export()["at"].cpu().numpy()
-    hold = float(np.quantile(at_e[ep], 0.05))
-    g.sta_update_early(hold)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        g.sta_update_early(hold)
-    e1.record()
-    e1.synchronize()
-    whs, ths, n_hold = g.early_summary()
-    early = {"ms": round(e0.elapsed_time(e1) / 10, 4), "hold_ps": round(hold, 1), "whs": round(whs, 1),
-             "ths": round(ths, 1), "n_hold_fail": n_hold}
-
-    # rise / fall timing on the same positions, outside the step: the update
-    # and report_timing_endpoint(n_fail, 1) on it
-    rf_lib = netgen.make_rf_library(lib)
-    g.rf_setup(rf_lib)
-    g.sta_update_rf(x, y)
-    g.extract_paths_rf(n=-1)
-    torch.cuda.synchronize()
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    e0.record()
-    for _ in range(5):
-        g.sta_update_rf(x, y)
-    e1.record()
-    for _ in range(5):
-        g.extract_paths_rf(n=-1)
-    e2.record()
-    e2.synchronize()
-    rf_w, rf_t, rf_n = g.rf_summary()
-    rise_fall = {"update_ms": round(e0.elapsed_time(e1) / 5, 4), "extract_k1_ms": round(e1.elapsed_time(e2) / 5, 4),
-                 "wns": round(rf_w, 1), "tns": round(rf_t, 1), "n_fail": rf_n, "paths": g.paths_count()[0]}
-    g.sta_update(x, y)  # back to the single-transition state
-    torch.cuda.synchronize()
-
-    # incremental arrival updates against the full arrival pass: m cells move
-    # (seeded jitter), and the positions alternate between the two placements
-    # so that every call is a genuine update of m moved cells
-    incremental = {}
-    rng = np.random.default_rng(11)
-    movable = np.nonzero(np.asarray(nl["cell_fixed"]) == 0)[0]
-    for m in (100, 1000, 10_000, 100_000):
-        if m > len(movable) // 2:
-            break
-        cells = np.sort(rng.choice(movable, m, replace=False)).astype(np.int32)
-        ct = torch.tensor(cells, device=dev, dtype=torch.long)
-        xn, yn = x.clone(), y.clone()
-        xn[ct] += torch.tensor(rng.normal(0, 5.0, m).astype(np.float32), device=dev)
-        yn[ct] += torch.tensor(rng.normal(0, 5.0, m).astype(np.float32), device=dev)
-        cl = torch.tensor(cells, device=dev, dtype=torch.int32)
-        pos = ((xn, yn), (x, y))
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        g.sta_update_arrivals(x, y)
-        ev[0].record()
-        for i in range(10):
-            g.sta_update_arrivals(*pos[i & 1])
-        ev[1].record()
-        for i in range(10):
-            g.sta_update_arrivals_incremental(*pos[i & 1], cl)
-        ev[2].record()
-        ev[2].synchronize()
-        incremental[str(m)] = {"full_arrivals_ms": round(ev[0].elapsed_time(ev[1]) / 10, 4),
-                               "incremental_ms": round(ev[1].elapsed_time(ev[2]) / 10, 4)}
-    g.sta_update(x, y)
-    torch.cuda.synchronize()
+    pair_ms, early, rise_fall, incremental = {}, None, None, {}
+    if not a.step_only:
+        pair_ms, early, rise_fall, incremental = after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev)
 
     sta_ms = sum(stages[s]["ms"] for s in ("netpass", "forward", "endpoint", "backward") if s in stages)
     ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
