@@ -114,7 +114,7 @@ def parse():
     ap.add_argument("--loop", action="store_true",
                     help="the placement loop around the step (Sec. IV, Fig. 5 analogue): wirelength-driven "
                          "against timing-driven runs, and the time per iteration")
-    ap.add_argument("--loop-beta", type=float, default=1e-3,
+    ap.add_argument("--loop-beta", type=float, default=2e-3,
                     help="PP weight of the timing-driven runs of --loop (um^-2 scale of these designs)")
     ap.add_argument("--net-model", type=int, default=0, choices=(0, 1),
                     help="0: lumped RC wires (Eq. 7); 1: Elmore star nets with degraded sink transitions")

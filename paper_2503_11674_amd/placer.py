@@ -44,13 +44,13 @@ class LoopConfig:
     max_iters: int = 600
     stop_overflow: float = 0.1
     # the paper starts timing at iteration 500 of a run of about a thousand;
-    # this schedule converges in about 400, so timing starts at 200
-    timing_start: int = 200
+    # this schedule converges in about 300 at 2M cells, so timing starts at 150
+    timing_start: int = 150
     timing_every: int = 15          # paper: m = 15
     # the paper's beta = 2.5e-5 is in its length units; at the micron scale
-    # of these designs 1e-3 gives a critical pair's PP gradient the order of
-    # the wirelength gradient (0: wirelength-driven)
-    beta: float = 1e-3
+    # of these designs 1e-3 to 4e-3 give a critical pair's PP gradient the
+    # order of the wirelength gradient (0: wirelength-driven)
+    beta: float = 2e-3
     w0: float = 10.0                # Eq. 9
     w1: float = 0.2
     alpha0: float = 1e-3            # first step, um per unit preconditioned gradient
