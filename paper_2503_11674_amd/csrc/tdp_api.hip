@@ -446,9 +446,14 @@ tdp_status tdp_rf_setup(tdp_graph g, const tdp_rf_tables *rt) {
     const bool ok = dalloc(g, g->rf_at, (size_t)2 * T.P, es) && dalloc(g, g->rf_slew, (size_t)2 * T.P, es) &&
                     dalloc(g, g->rf_rat, (size_t)2 * T.P, es) && dalloc(g, g->rf_darc4, (size_t)4 * T.A, es) &&
                     dalloc(g, g->rf_crit, (size_t)2 * T.n_comb) && dalloc(g, g->rf_unate, nt) &&
-                    dalloc(g, g->rf_delay_fall, ntab) && dalloc(g, g->rf_slew_fall, ntab) &&
-                    dalloc(g, g->rf_path_tran, g->pin_cap);
+                    dalloc(g, g->rf_flat, (size_t)g->lut.n4) && dalloc(g, g->rf_path_tran, g->pin_cap);
     if (!ok) return fail(g, TDP_E_NOMEM, "rise/fall: device allocation failed");
+    // the same axes as the rise tables, then the fall tables
+    const size_t n_ax = (size_t)nt * (g->lut.ns + g->lut.nl);
+    g->rf_delay_fall = (float *)g->rf_flat + n_ax;
+    g->rf_slew_fall = g->rf_delay_fall + ntab;
+    if (hipMemcpy(g->rf_flat, g->lut.flat4, sizeof(float) * n_ax, hipMemcpyDeviceToDevice) != hipSuccess)
+      return fail(g, TDP_E_DEVICE, "rise/fall: table upload failed");
   }
   if (hipMemcpy(g->rf_unate, rt->unate, sizeof(int32_t) * nt, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(g->rf_delay_fall, rt->delay_fall, sizeof(float) * ntab, hipMemcpyHostToDevice) != hipSuccess ||

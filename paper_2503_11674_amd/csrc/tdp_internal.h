@@ -332,7 +332,8 @@ struct tdp_graph_s {
   bool rf_ready = false, rf_updated = false;
   void *rf_at = nullptr, *rf_slew = nullptr, *rf_rat = nullptr, *rf_darc4 = nullptr;
   int32_t *rf_crit = nullptr, *rf_unate = nullptr;
-  float *rf_delay_fall = nullptr, *rf_slew_fall = nullptr;
+  float *rf_delay_fall = nullptr, *rf_slew_fall = nullptr;  // inside rf_flat
+  float4 *rf_flat = nullptr;  // the fall tables' image: [slew axes | load axes | delay | slew], as lut.flat4
   uint8_t *rf_path_tran = nullptr;  // [pin_cap] transition of each path pin
 
   // density term and Nesterov steps (tdp_density_setup)

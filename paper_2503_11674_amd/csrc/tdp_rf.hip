@@ -8,8 +8,9 @@
 // rise, the rise / fall extension the output fall.  A net passes a
 // transition through with the same delay either way.
 //
-//   forward    one launch per level, one thread per combinational cell: its
-//              sinks take their drivers' arrivals plus the net delay; for each
+//   forward    one launch per level, one lane per combinational input (the
+//              forward chunks): sinks take their drivers' arrivals plus the
+//              net delay; for each
 //              output transition x, the maximum over (input j, input
 //              transition y that causes x) of arrival + table delay, the first
 //              (j, y) attaining it (j ascending, rise first) and the worst
@@ -17,10 +18,12 @@
 //              pass
 //   endpoint   per D pin: both slacks, the worse one is the endpoint's;
 //              WNS / TNS / count by the single-transition reduction
-//   backward   one launch per level from the top: a cell output's required
-//              time per transition is the minimum over its sinks; each input
-//              transition y then takes the minimum over the outputs x it
-//              causes of (required x - arc delay); start points last
+//   backward   one launch per level from the top, one lane per pin of the
+//              nets driven at that level (the net chunks): an input
+//              transition y of a sink's cell takes the minimum over the
+//              outputs x it causes of (required x - arc delay), and the
+//              driver's required time per transition is the minimum over its
+//              sinks of (required - net delay); start points last
 //   paths      the n worst endpoints (or the violated ones) ordered by
 //              (slack, pin), cut to K; each path ends in its endpoint's worse
 //              transition (rise on a tie) and follows the critical (input,
@@ -60,49 +63,87 @@ __global__ void k_rf_start(Topo tp, LutView Lr, LutView Lf, T in_slew, T clk_sle
   slew[2 * v + 1] = so;
 }
 
-// cells [c0, c1) of one level
+// One level of the forward pass on the forward chunks: one lane per
+// combinational input (a cell's inputs on consecutive lanes), both
+// transitions' tables staged in LDS, and the cell's maxima by segmented
+// reductions over its lanes.  Candidate (j, y) of an
+// output transition carries the index 2 j + y; among equal arrivals the
+// smallest index wins (j ascending, rise first), as in the per-cell loop.
 template <typename T>
-__global__ void __launch_bounds__(256) k_rf_forward(Topo tp, LutView Lr, LutView Lf, int net_model,
-                                                    const int32_t *__restrict__ unate, int c0, int c1,
-                                                    const T *__restrict__ load, const T *__restrict__ dnet,
-                                                    T *__restrict__ at, T *__restrict__ slew,
-                                                    T *__restrict__ darc4, int32_t *__restrict__ crit) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
-  const int o = tp.n_start + c;
-  const int ty = tp.comb_type[c], un = unate[ty];
-  const T ld = load[o];
-  const int b = tp.comb_inptr[c], e = tp.comb_inptr[c + 1];
-  T best[2] = {-pos_inf<T>(), -pos_inf<T>()}, so[2] = {(T)0, (T)0};
-  int arg[2] = {-1, -1};
-  for (int t = b; t < e; ++t) {
-    const int s = tp.snk_drv[t];
-    const T dn = dnet[t];
+__global__ void __launch_bounds__(256) k_rf_forward_chunks(Topo tp, LutView Lr, LutView Lf, int net_model,
+                                                           const int32_t *__restrict__ unate, int ch0, int ch1,
+                                                           const T *__restrict__ load, const T *__restrict__ dnet,
+                                                           T *__restrict__ at, T *__restrict__ slew,
+                                                           T *__restrict__ darc4, int32_t *__restrict__ crit) {
+  extern __shared__ float4 s_rf4[];
+  float *s_r = (float *)s_rf4, *s_f = (float *)(s_rf4 + Lr.n4);
+  const int lane = wave_lane();
+  const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int4 rec = tp.fw_rec[(chunk < ch1 ? chunk : ch1 - 1) * CHUNK + lane];
+  const int t = rec.x, s = rec.y, c = rec.z;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
+  const bool valid = t >= 0 && chunk < ch1;
+  T a2[2] = {(T)0, (T)0}, w2[2] = {(T)0, (T)0}, dn = 0, ld = 0;
+  int ty = 0;
+  if (valid) {
+    a2[0] = at[2 * s];
+    a2[1] = at[2 * s + 1];
+    w2[0] = slew[2 * s];
+    w2[1] = slew[2 * s + 1];
+    dn = dnet[t];
+    ld = load[tp.n_start + c];
+    ty = tp.comb_type[c];
+  }
+  stage_lut(Lr, s_r);
+  stage_lut(Lf, s_f);
+  if (chunk >= ch1) return;
+  const int un = valid ? unate[ty] : 0;
+  const int j = lane - head;
+  // this lane's best candidate per output transition and its worst
+  // output transition
+  T cand[2] = {-pos_inf<T>(), -pos_inf<T>()}, osx[2] = {(T)0, (T)0};
+  int cidx[2] = {1 << 20, 1 << 20};
+  if (valid) {
     const int p = tp.M + t;
+    T ain[2], sin[2];
+#pragma unroll
     for (int y = 0; y < 2; ++y) {
-      const T ain = at[2 * s + y] + dn;
-      const T sin = sink_slew<T>(net_model, slew[2 * s + y], dn);
-      at[2 * p + y] = ain;
-      slew[2 * p + y] = sin;
+      ain[y] = a2[y] + dn;
+      sin[y] = sink_slew<T>(net_model, w2[y], dn);
+    }
+    at[2 * p] = ain[0];
+    at[2 * p + 1] = ain[1];
+    slew[2 * p] = sin[0];
+    slew[2 * p + 1] = sin[1];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
       for (int x = 0; x < 2; ++x) {
         if (!causes(un, y, x)) continue;
         T d, os;
-        lut_pair<T>(x == 0 ? Lr : Lf, ty, sin, ld, d, os);
+        lut_lds<T>(x == 0 ? s_r : s_f, Lr.nt, Lr.ns, Lr.nl, ty, sin[y], ld, d, os);
         darc4[4 * t + 2 * x + y] = d;
-        if (ain == -pos_inf<T>()) continue;
-        const T a = ain + d;
-        if (a > best[x]) {
-          best[x] = a;
-          arg[x] = 2 * (t - b) + y;
+        if (ain[y] == -pos_inf<T>()) continue;
+        const T a = ain[y] + d;
+        if (a > cand[x]) {  // y ascending: a tie keeps the rise
+          cand[x] = a;
+          cidx[x] = 2 * j + y;
         }
-        if (os > so[x]) so[x] = os;
+        if (os > osx[x]) osx[x] = os;
       }
-    }
   }
+#pragma unroll
   for (int x = 0; x < 2; ++x) {
-    at[2 * o + x] = best[x];
-    slew[2 * o + x] = so[x];
-    crit[2 * c + x] = arg[x];
+    const T best = seg_max(cand[x], lane, head, tail);
+    const T so = seg_max(osx[x], lane, head, tail);
+    const int arg = seg_min((valid && cand[x] == best && best != -pos_inf<T>()) ? cidx[x] : (1 << 20), lane, head,
+                            tail);
+    if (valid && lane == head) {
+      const int o = tp.n_start + c;
+      at[2 * o + x] = best;
+      slew[2 * o + x] = so;
+      crit[2 * c + x] = arg < (1 << 20) ? arg : -1;
+    }
   }
 }
 
@@ -129,55 +170,103 @@ __global__ void k_rf_endpoint(Topo tp, int net_model, const double *__restrict__
   ep_slack[f] = worst;
 }
 
-// required time of driver v per transition: minimum over its sinks
+// required times of an input pin's two transitions from its cell output's
+// and the arc delays [x][y]
 template <typename T>
-__device__ __forceinline__ void rf_driver_required(const Topo &tp, int v, const T *__restrict__ dnet,
-                                                   T *__restrict__ rat) {
-  T r[2] = {pos_inf<T>(), pos_inf<T>()};
-  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
-    const int t = tp.net_sink[k];
-    const int p = tp.M + t;
-    for (int y = 0; y < 2; ++y) {
-      const T rt = rat[2 * p + y];
-      if (rt == pos_inf<T>()) continue;
-      const T q = rt - dnet[t];
+__device__ __forceinline__ void rf_input_required(int un, const T (&ro)[2], const T (&da)[4], T (&r)[2]) {
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    r[y] = pos_inf<T>();
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      if (!causes(un, y, x) || ro[x] == pos_inf<T>()) continue;
+      const T q = ro[x] - da[2 * x + y];
       r[y] = q < r[y] ? q : r[y];
     }
   }
-  rat[2 * v] = r[0];
-  rat[2 * v + 1] = r[1];
 }
 
+// One level of the backward pass on the net chunks: one lane per pin of a
+// net driven at this level.  A sink that is a combinational input takes its
+// required times from its cell's output (a later level, already done) and
+// the arc delays; a D pin's are the endpoint's.  The driver's are the
+// minimum over its sinks of required - net delay.
 template <typename T>
-__global__ void __launch_bounds__(256) k_rf_backward(Topo tp, const int32_t *__restrict__ unate, int c0, int c1,
-                                                     const T *__restrict__ dnet, const T *__restrict__ darc4,
-                                                     T *__restrict__ rat) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
-  const int o = tp.n_start + c;
-  rf_driver_required<T>(tp, o, dnet, rat);
-  const T ro[2] = {rat[2 * o], rat[2 * o + 1]};
-  const int un = unate[tp.comb_type[c]];
-  for (int t = tp.comb_inptr[c]; t < tp.comb_inptr[c + 1]; ++t) {
-    const int p = tp.M + t;
-    for (int y = 0; y < 2; ++y) {
-      T r = pos_inf<T>();
-      for (int x = 0; x < 2; ++x) {
-        if (!causes(un, y, x) || ro[x] == pos_inf<T>()) continue;
-        const T q = ro[x] - darc4[4 * t + 2 * x + y];
-        r = q < r ? q : r;
-      }
-      rat[2 * p + y] = r;
+__global__ void __launch_bounds__(256) k_rf_backward_chunks(Topo tp, const int32_t *__restrict__ unate, int ch0,
+                                                            int ch1, const T *__restrict__ dnet_nm,
+                                                            const T *__restrict__ darc4, T *__restrict__ rat) {
+  const int lane = wave_lane();
+  const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= ch1) return;
+  const int k = chunk * CHUNK + lane;
+  const int4 rec = tp.nm_rec[k];
+  const int p = rec.x, vo = rec.z;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
+  const bool sink = p >= 0 && lane != head;
+  const int t = p - tp.M;
+  T q[2] = {pos_inf<T>(), pos_inf<T>()};
+  if (sink) {
+    const T dn = dnet_nm[k];
+    T r[2];
+    if (vo >= 0) {  // a combinational input
+      const T ro[2] = {rat[2 * vo], rat[2 * vo + 1]};
+      T da[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) da[i] = darc4[4 * t + i];
+      rf_input_required<T>(unate[tp.comb_type[vo - tp.n_start]], ro, da, r);
+      rat[2 * p] = r[0];
+      rat[2 * p + 1] = r[1];
+    } else {
+      r[0] = rat[2 * p];
+      r[1] = rat[2 * p + 1];
     }
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      if (r[y] != pos_inf<T>()) q[y] = r[y] - dn;
+  }
+  const T r0 = seg_min(q[0], lane, head, tail), r1 = seg_min(q[1], lane, head, tail);
+  if (p >= 0 && lane == head) {
+    rat[2 * p] = r0;
+    rat[2 * p + 1] = r1;
   }
 }
 
+// nets too wide for one chunk: one thread per net, the same arithmetic
 template <typename T>
-__global__ void k_rf_backward_start(Topo tp, const T *__restrict__ dnet, T *__restrict__ rat) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= tp.n_start) return;
-  rf_driver_required<T>(tp, v, dnet, rat);
+__global__ void k_rf_backward_big(Topo tp, const int32_t *__restrict__ unate, int i0, int i1,
+                                  const T *__restrict__ dnet, const T *__restrict__ darc4, T *__restrict__ rat) {
+  const int i = i0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= i1) return;
+  const int v = tp.big_net[i];
+  T q[2] = {pos_inf<T>(), pos_inf<T>()};
+  for (int kk = tp.net_ptr[v]; kk < tp.net_ptr[v + 1]; ++kk) {
+    const int t = tp.net_sink[kk];
+    const int p = tp.M + t;
+    T r[2];
+    if (t < tp.A) {
+      const int c = tp.snk_comb[t], vo = tp.n_start + c;
+      const T ro[2] = {rat[2 * vo], rat[2 * vo + 1]};
+      T da[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) da[j] = darc4[4 * t + j];
+      rf_input_required<T>(unate[tp.comb_type[c]], ro, da, r);
+      rat[2 * p] = r[0];
+      rat[2 * p + 1] = r[1];
+    } else {
+      r[0] = rat[2 * p];
+      r[1] = rat[2 * p + 1];
+    }
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      if (r[y] != pos_inf<T>()) {
+        const T qq = r[y] - dnet[t];
+        q[y] = qq < q[y] ? qq : q[y];
+      }
+  }
+  rat[2 * v] = q[0];
+  rat[2 * v + 1] = q[1];
 }
+
 
 template <typename T>
 __global__ void k_rf_export(Topo tp, const T *__restrict__ at, const T *__restrict__ rat,
@@ -295,32 +384,39 @@ template <typename T>
 void rf_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s) {
   const Topo &tp = g->topo;
   netpass_impl<T>(g, x, y, s);
+  // the fall tables' view: the same axes, its own image for the LDS staging
   LutView Lf = g->lut;
+  Lf.slew_axis = (const float *)g->rf_flat;
+  Lf.load_axis = (const float *)g->rf_flat + (size_t)g->lut.nt * g->lut.ns;
   Lf.delay = g->rf_delay_fall;
   Lf.slew = g->rf_slew_fall;
+  Lf.flat4 = g->rf_flat;
   T *at = (T *)g->rf_at, *sl = (T *)g->rf_slew, *rat = (T *)g->rf_rat, *darc4 = (T *)g->rf_darc4;
   if (tp.n_start > 0)
     hipLaunchKernelGGL(k_rf_start<T>, dim3(nb(tp.n_start, 256)), dim3(256), 0, s, tp, g->lut, Lf, (T)g->input_slew,
                        (T)g->clock_slew, (const T *)g->load, at, sl);
   for (int l = 1; l <= tp.D; ++l) {
-    const int c0 = g->lv.lvl[l - 1], c1 = g->lv.lvl[l];
-    if (c1 > c0)
-      hipLaunchKernelGGL(k_rf_forward<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, g->lut, Lf, g->lut.net_model,
-                         g->rf_unate, c0, c1, (const T *)g->load, (const T *)g->dnet, at, sl, darc4, g->rf_crit);
+    const int ch0 = g->lv.fw_lvl[l - 1], ch1 = g->lv.fw_lvl[l];
+    if (ch1 > ch0)
+      hipLaunchKernelGGL(k_rf_forward_chunks<T>, dim3(nb(ch1 - ch0, 4)), dim3(256), 2 * sizeof(float4) * g->lut.n4,
+                         s, tp, g->lut, Lf, g->lut.net_model, g->rf_unate, ch0, ch1, (const T *)g->load,
+                         (const T *)g->dnet, at, sl, darc4, g->rf_crit);
   }
   if (tp.E > 0)
     hipLaunchKernelGGL(k_rf_endpoint<T>, dim3(nb(tp.E, 256)), dim3(256), 0, s, tp, g->lut.net_model, g->d_inst_req,
                        (const T *)g->dnet, at, sl, rat, (T *)g->ep_slack);
   ep_reduce_impl<T>(g, s);
-  for (int l = tp.D; l >= 1; --l) {
-    const int c0 = g->lv.lvl[l - 1], c1 = g->lv.lvl[l];
-    if (c1 > c0)
-      hipLaunchKernelGGL(k_rf_backward<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, g->rf_unate, c0, c1,
+  // from the last level's nets down to the start points' (level 0)
+  for (int l = tp.D; l >= 0; --l) {
+    const int ch0 = g->lv.nm_lvl[l], ch1 = g->lv.nm_lvl[l + 1];
+    if (ch1 > ch0)
+      hipLaunchKernelGGL(k_rf_backward_chunks<T>, dim3(nb(ch1 - ch0, 4)), dim3(256), 0, s, tp, g->rf_unate, ch0, ch1,
+                         (const T *)g->dnet_nm, (const T *)darc4, rat);
+    const int b0 = g->lv.big_lvl[l], b1 = g->lv.big_lvl[l + 1];
+    if (b1 > b0)
+      hipLaunchKernelGGL(k_rf_backward_big<T>, dim3(nb(b1 - b0, 64)), dim3(64), 0, s, tp, g->rf_unate, b0, b1,
                          (const T *)g->dnet, (const T *)darc4, rat);
   }
-  if (tp.n_start > 0)
-    hipLaunchKernelGGL(k_rf_backward_start<T>, dim3(nb(tp.n_start, 256)), dim3(256), 0, s, tp, (const T *)g->dnet,
-                       rat);
 }
 
 template <typename T>

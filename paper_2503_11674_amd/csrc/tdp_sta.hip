@@ -30,21 +30,6 @@
 
 namespace tdp {
 
-__device__ __forceinline__ void stage_lut(const LutView &L, float *s_lut) {
-  // two float4 loads in flight per thread before their LDS writes (one
-  // memory latency for the usual table sizes)
-  float4 *dst = (float4 *)s_lut;
-  const int n4 = L.n4, bd = blockDim.x;
-  for (int i = threadIdx.x; i < n4; i += 2 * bd) {
-    const int i1 = i + bd;
-    const float4 v0 = L.flat4[i];
-    const float4 v1 = i1 < n4 ? L.flat4[i1] : make_float4(0.f, 0.f, 0.f, 0.f);
-    dst[i] = v0;
-    if (i1 < n4) dst[i1] = v1;
-  }
-  __syncthreads();
-}
-
 // published words of the dataflow sweeps (relaxed device-scope atomics; a
 // consumer polls one word, so no fences are needed)
 constexpr uint64_t W_EMPTY = ~0ull;

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "tdp_internal.h"
+
 namespace tdp {
 
 // {arrival, transition} of a driver, one load in the forward gathers
@@ -179,6 +181,23 @@ __device__ __forceinline__ void store_list(V *__restrict__ p, const V (&in)[KM])
 #pragma unroll
     for (int j = 0; j < KM; ++j) p[j] = in[j];
   }
+}
+
+// the library's table image (LutView::flat4) copied into LDS by the whole
+// workgroup; every thread of the workgroup must call it
+__device__ __forceinline__ void stage_lut(const LutView &L, float *s_lut) {
+  // two float4 loads in flight per thread before their LDS writes (one
+  // memory latency for the usual table sizes)
+  float4 *dst = (float4 *)s_lut;
+  const int n4 = L.n4, bd = blockDim.x;
+  for (int i = threadIdx.x; i < n4; i += 2 * bd) {
+    const int i1 = i + bd;
+    const float4 v0 = L.flat4[i];
+    const float4 v1 = i1 < n4 ? L.flat4[i1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    dst[i] = v0;
+    if (i1 < n4) dst[i1] = v1;
+  }
+  __syncthreads();
 }
 
 // the library's tables staged in LDS: [slew axes][load axes][delay][slew]

@@ -154,3 +154,36 @@ def test_rise_fall_double_precision_and_state(library):
         gb.rf_setup(lib)
     assert e.value.status == 7
     gb.close()
+
+
+@pytest.mark.parametrize("net_model", [0, 1])
+def test_rise_fall_nets_wider_than_a_chunk(net_model, library):
+    """Two nets of more than 63 sinks take the one-thread-per-net path of the
+    backward pass: both transitions' arrival, required time and slack match
+    the oracle, in double precision to 1e-12."""
+    from tests.test_gpu_net_model import _fanout_design
+    tdp = _tdp()
+    lib = netgen.make_rf_library(dict(library, net_model=net_model))
+    nl = _fanout_design()
+    assert (np.diff(nl["net_ptr"]) - 1 > 63).sum() == 2
+    nl["clock_period"] = np.float32(0.0)
+    rf0 = ref.sta_rf(nl, lib)
+    ep = ref.endpoint_pins(nl)
+    nl["clock_period"] = np.float32(netgen.clock_period_for_fail_fraction(np.max(rf0["at"][ep], axis=1), 0.3))
+    rf = ref.sta_rf(nl, lib)
+    for precision, rtol in (("f64", 1e-12), ("f32", None)):
+        g = tdp.TimingGraph(nl, lib, precision=precision, max_paths=len(ep), max_k=1)
+        g.rf_setup(lib)
+        g.sta_update_rf(*_xy(nl))
+        o = {k: v.cpu().numpy() for k, v in g.rf_export().items()}
+        for key in ("at", "rat", "slack"):
+            if rtol is None:  # single precision: relative to the pin's timing magnitudes, as above
+                scale = np.maximum(np.abs(np.where(np.isfinite(rf["at"]), rf["at"], 0)),
+                                   np.abs(np.where(np.isfinite(rf["rat"]), rf["rat"], 0)))
+                scale = np.maximum(scale, abs(float(nl["clock_period"])))
+                inf_ok, bad, worst = timing_close(o[key].reshape(-1), rf[key].reshape(-1),
+                                                  scale=scale.reshape(-1) if key != "at" else None)
+            else:
+                inf_ok, bad, worst = timing_close(o[key].reshape(-1), rf[key].reshape(-1), rtol=rtol)
+            assert inf_ok and bad == 0, (precision, key, bad, worst)
+        g.close()
