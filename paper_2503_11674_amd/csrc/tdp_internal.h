@@ -258,7 +258,7 @@ struct tdp_graph_s {
   bool flow_ok = false;          // the graph can use the dataflow sweeps
   int32_t pos_gen = 0;           // arrival passes so far; d_err[1] == pos_gen: a position was not finite
   bool flow_r_clear = false;     // flow_r holds no published word (the last net pass reset it)
-  bool drv_as_stale = false;     // drv_as of the combinational drivers predates the last forward sweep
+  bool drv_as_stale = false;     // drv_as (combinational drivers) and fw_a predate the last forward sweep
   double *red_ep = nullptr, *red_loss = nullptr, *red_wa = nullptr;
   double *summary = nullptr;     // [4 * num_inst]: wns, tns, n_fail, 0
   int32_t *inst_nfail = nullptr, *d_ep_base = nullptr;

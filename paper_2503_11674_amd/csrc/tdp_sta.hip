@@ -382,7 +382,6 @@ __device__ __forceinline__ void fw_arrivals(const Topo &tp, const LutView &L, fl
 // start point), so a path walk reads four hops per load
 template <typename T, int KM>
 __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, const T *__restrict__ fw_a,
-                                         const T *__restrict__ at, const T *__restrict__ darc,
                                          int32_t *__restrict__ cdep, T *__restrict__ side_cost,
                                          int32_t *__restrict__ side_pin, int4 *__restrict__ hop4,
                                          const IncFlags &inc) {
@@ -394,16 +393,8 @@ __device__ __forceinline__ void fw_lists(const Topo &tp, int chunk, int lc1, con
   const int t = rec.x, s = rec.y, c = rec.z;
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   const bool valid = t >= 0;
-  T a;
-  if (!inc.lst) {
-    a = fw_a[k];
-  } else {
-    // incremental: a chunk whose arrivals this update left alone has no
-    // fw_a of its own from it (the dataflow sweep writes none), so the
-    // arrival through each arc is formed again from the two stored terms,
-    // the same sum; the chunk goes on if it was re-timed or an input's
-    // driver's list changed (the marks load with the two terms)
-    a = valid ? at[tp.M + t] + darc[t] : -pos_inf<T>();
+  const T a = fw_a[k];
+  if (inc.lst) {  // incremental: the chunk was re-timed or an input's driver's list changed
     const bool mark = (valid && inc.drv_lchg[s] == inc.epoch) || inc.lst[chunk] == inc.epoch;
     if (__ballot(mark) == 0) return;
   }
@@ -525,8 +516,7 @@ __global__ void __launch_bounds__(256) k_forward(Topo tp, LutView L, int ch0, in
   if ((int)blockIdx.x < n_arr)
     fw_arrivals<T>(tp, L, s_lut, ch0 + blockIdx.x * 4 + wave, ch1, load, dnet, at, slew, as, darc, crit, fw_a, inc);
   else
-    fw_lists<T, KM>(tp, lc0 + (blockIdx.x - n_arr) * 4 + wave, lc1, fw_a, at, darc, cdep, side_cost, side_pin, hop4,
-                    inc);
+    fw_lists<T, KM>(tp, lc0 + (blockIdx.x - n_arr) * 4 + wave, lc1, fw_a, cdep, side_cost, side_pin, hop4, inc);
 }
 
 // ------------------------------------------------------------- endpoints
@@ -1117,11 +1107,18 @@ __global__ void k_inc_maps(Topo tp, int32_t *__restrict__ snk_chunk, int32_t *__
 }
 
 // {arrival, transition} pairs of the combinational drivers from the two
-// arrays, after a forward sweep that did not keep the pairs
+// arrays, and each forward slot's arrival through its arc (the same sum the
+// arrival job forms), after a forward sweep that kept neither
 template <typename T>
-__global__ void k_pack_as(Topo tp, const T *__restrict__ at, const T *__restrict__ slew, V2<T> *__restrict__ as) {
-  const int v = tp.n_start + blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_pack_as(Topo tp, const T *__restrict__ at, const T *__restrict__ slew, const T *__restrict__ darc,
+                          V2<T> *__restrict__ as, T *__restrict__ fw_a) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = tp.n_start + (int)i;
   if (v < tp.M) as[v] = v2<T>(at[v], slew[v]);
+  if (i < (long long)tp.n_fw_chunks * CHUNK) {
+    const int t = tp.fw_rec[i].x;
+    fw_a[i] = t >= 0 ? at[tp.M + t] + darc[t] : -pos_inf<T>();
+  }
 }
 
 // the net chunks that hold a moved cell's pins: its output's net and the nets
@@ -1162,8 +1159,9 @@ void sta_arrivals_incremental_impl(tdp_graph g, const float *x, const float *y, 
   inc.nm = g->inc_nm;
   prof_begin(g, TDP_STAGE_NETPASS, s);
   if (g->drv_as_stale && tp.n_comb > 0)
-    hipLaunchKernelGGL(k_pack_as<T>, dim3(nblk(tp.n_comb, 256)), dim3(256), 0, s, tp, (const T *)g->at,
-                       (const T *)g->slew, (V2<T> *)g->drv_as);
+    hipLaunchKernelGGL(k_pack_as<T>, dim3(nblk(std::max<long long>(tp.n_comb, (long long)tp.n_fw_chunks * CHUNK), 256)),
+                       dim3(256), 0, s, tp, (const T *)g->at, (const T *)g->slew, (const T *)g->darc,
+                       (V2<T> *)g->drv_as, (T *)g->fw_a);
   g->drv_as_stale = false;
   fill_i32(g->d_err, 1, 0, s);
   if (n > 0)
