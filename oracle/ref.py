@@ -114,6 +114,19 @@ def sta(nl, lib, x=None, y=None, clock_period: Optional[float] = None) -> Dict[s
     return out
 
 
+def rc_tree(nl, x=None, y=None) -> np.ndarray:
+    """Topology of net model 2: the parent of every sink pin in its net's
+    spanning tree (-1 at drivers and at pins on no net)."""
+    L = _load()
+    x = _f32(nl["x"] if x is None else x)
+    y = _f32(nl["y"] if y is None else y)
+    parent = np.empty(int(nl["num_pins"]), np.int32)
+    na, k1 = _netlist_args(nl)
+    if L.ora_rc_tree(*na, _p(x), _p(y), _p(parent)) != 0:
+        raise MemoryError("oracle: allocation failed")
+    return parent
+
+
 def sta_rf(nl, lib, x=None, y=None, clock_period: Optional[float] = None) -> Dict[str, np.ndarray]:
     """Rise / fall timing.  `lib` carries, beside the single-transition
     library (its tables are the rise tables), delay_fall / slew_fall and

@@ -17,9 +17,9 @@
  *                  Net delay is R*C, with R and C linear in wire length
  *                  (Sec. III-C, Eq. 7), i.e. r*c*L^2 with L the Manhattan
  *                  distance, or, as a fuller model of the same wires, the
- *                  Elmore delay of a star RC net with degraded sink
- *                  transitions (net model section below); cell arcs come
- *                  from slew x load tables.
+ *                  Elmore delay of a star RC net or of a spanning-tree RC
+ *                  net, with degraded sink transitions (net model section
+ *                  below); cell arcs come from slew x load tables.
  *   ora_sta_early - the early half of an early/late timer: earliest
  *                  arrivals at best-case transitions and the hold check at
  *                  the D pins (not used by the paper's objective, which is
@@ -81,7 +81,8 @@ typedef struct {
   int num_types, n_slew, n_load;
   const float *slew_axis, *load_axis, *delay_lut, *slew_lut, *pin_cap;
   double r, c, scale;
-  int model; /* net model: 0 lumped (Eq. 7), 1 Elmore star with slew degradation */
+  int model; /* net model: 0 lumped (Eq. 7), 1 Elmore star, 2 Elmore spanning tree; 1 and 2
+                degrade the sink transitions */
 } olib;
 
 /* ------------------------------------------------------------------------ */
@@ -216,7 +217,23 @@ static void pin_xy(const onl *n, const float *x, const float *y, int p, double *
  * and Devgan, IEEE TCAD 2004): the root sum of squares of the input
  * transition and the wire's own step-response transition, the latter taken
  * as ln(9) times the Elmore delay (the 10-90% time of a single-pole
- * response with that time constant). */
+ * response with that time constant); model 2 does the same.
+ *
+ * Model 2: the net is an RC tree whose topology is a rectilinear minimum
+ * spanning tree of its pins, grown from the driver by Prim's algorithm: start
+ * with the driver; repeatedly add the pin outside the tree closest (Manhattan
+ * distance) to any pin inside it, joined to that pin.  Ties go to the pin
+ * first in the net's pin list and, for its parent, to the pin that joined
+ * the tree first.  The distances that decide the topology are single
+ * precision, (cell coordinate difference) + (offset difference) per axis, so
+ * that a single-precision timer takes the same decisions.  Every tree edge is
+ * a uniform wire of its Manhattan length L (resistance r L, capacitance c L).
+ * With C_below(u) the capacitance at and below pin u (its pin capacitance and
+ * the wires and pins of its subtree), the Elmore delay to a pin is the sum,
+ * over the edges e = (parent, v) on its path from the driver, of
+ * r L_e (c L_e / 2 + C_below(v)), times scale.  The driver's load is again the
+ * net's total capacitance: the pin capacitances plus c times the tree's total
+ * length.  A two-pin net gives model 1's delay. */
 static double net_delay(const olib *L, double len, double sink_cap) {
   if (L->model == 1) return L->scale * L->r * len * (0.5 * L->c * len + sink_cap);
   return L->scale * L->r * L->c * len * len;
@@ -229,9 +246,137 @@ static double net_delay_dlen(const olib *L, double len, double sink_cap) {
 }
 
 static double sink_slew(const olib *L, double drv_slew, double dnet) {
-  if (L->model != 1) return drv_slew;
+  if (L->model == 0) return drv_slew;
   double w = log(9.0) * dnet;
   return sqrt(drv_slew * drv_slew + w * w);
+}
+
+/* one net's tree: node 0 is the driver, node i >= 1 the net's i-th sink */
+typedef struct {
+  int m;          /* number of sinks */
+  int32_t *pin;   /* [m+1] pin id of each node */
+  int *par;       /* [m+1] parent node, -1 at the driver */
+  int *ord;       /* [m]   sink nodes in the order they join the tree */
+  double *len;    /* [m+1] length of the wire from the parent */
+  double *cd;     /* [m+1] capacitance at and below the node */
+  double *delay;  /* [m+1] Elmore delay from the driver */
+  double *aux;    /* [m+1] scratch of the adjoint */
+  float *dist;    /* [m+1] Prim's distance to the tree */
+  char *in;       /* [m+1] node is in the tree */
+} otree;
+
+static int otree_alloc(otree *T, int max_pins) {
+  size_t k = (size_t)(max_pins > 1 ? max_pins : 1);
+  T->pin = (int32_t *)malloc(sizeof(int32_t) * k);
+  T->par = (int *)malloc(sizeof(int) * k);
+  T->ord = (int *)malloc(sizeof(int) * k);
+  T->len = (double *)malloc(sizeof(double) * k);
+  T->cd = (double *)malloc(sizeof(double) * k);
+  T->delay = (double *)malloc(sizeof(double) * k);
+  T->aux = (double *)malloc(sizeof(double) * k);
+  T->dist = (float *)malloc(sizeof(float) * k);
+  T->in = (char *)malloc(k);
+  return T->pin && T->par && T->ord && T->len && T->cd && T->delay && T->aux && T->dist && T->in ? 0 : -1;
+}
+
+static void otree_free(otree *T) {
+  free(T->pin); free(T->par); free(T->ord); free(T->len); free(T->cd); free(T->delay); free(T->aux);
+  free(T->dist); free(T->in);
+}
+
+static int max_net_pins(const int32_t *net_ptr, int num_nets) {
+  int w = 1;
+  for (int net = 0; net < num_nets; ++net)
+    if (net_ptr[net + 1] - net_ptr[net] > w) w = net_ptr[net + 1] - net_ptr[net];
+  return w;
+}
+
+/* single-precision Manhattan distance of two pins (the topology's metric) */
+static float pin_fdist(const onl *n, const float *x, const float *y, int a, int b) {
+  int ca = n->pin_cell[a], cb = n->pin_cell[b];
+  float ax = ca >= 0 ? x[ca] : 0.0f, ay = ca >= 0 ? y[ca] : 0.0f;
+  float bx = cb >= 0 ? x[cb] : 0.0f, by = cb >= 0 ? y[cb] : 0.0f;
+  float dx = (ax - bx) + (n->pin_off_x[a] - n->pin_off_x[b]);
+  float dy = (ay - by) + (n->pin_off_y[a] - n->pin_off_y[b]);
+  return fabsf(dx) + fabsf(dy);
+}
+
+/* Prim's spanning tree of one net (model 2's topology) */
+static void tree_topology(const onl *n, const float *x, const float *y, int net, otree *T) {
+  int b = n->net_ptr[net], m = n->net_ptr[net + 1] - b - 1;
+  T->m = m;
+  for (int i = 0; i <= m; ++i) { T->pin[i] = n->net_pins[b + i]; T->par[i] = -1; T->in[i] = 0; }
+  T->in[0] = 1;
+  for (int i = 1; i <= m; ++i) { T->dist[i] = pin_fdist(n, x, y, T->pin[0], T->pin[i]); T->par[i] = 0; }
+  for (int step = 0; step < m; ++step) {
+    int j = -1;
+    for (int i = 1; i <= m; ++i)
+      if (!T->in[i] && (j < 0 || T->dist[i] < T->dist[j])) j = i;
+    T->in[j] = 1;
+    T->ord[step] = j;
+    for (int i = 1; i <= m; ++i)
+      if (!T->in[i]) {
+        float d = pin_fdist(n, x, y, T->pin[j], T->pin[i]);
+        if (d < T->dist[i]) { T->dist[i] = d; T->par[i] = j; }
+      }
+  }
+}
+
+/* wire lengths, capacitances below each node and Elmore delays on the tree */
+static void tree_elmore(const onl *n, const olib *L, const float *x, const float *y, otree *T) {
+  int m = T->m;
+  T->len[0] = 0.0; T->cd[0] = 0.0; T->delay[0] = 0.0;
+  for (int i = 1; i <= m; ++i) {
+    double xi, yi, xp, yp;
+    pin_xy(n, x, y, T->pin[i], &xi, &yi);
+    pin_xy(n, x, y, T->pin[T->par[i]], &xp, &yp);
+    T->len[i] = fabs(xp - xi) + fabs(yp - yi);
+    T->cd[i] = (double)L->pin_cap[n->cell_type[n->pin_cell[T->pin[i]]]];
+  }
+  /* children join after their parents: the reverse joining order visits
+   * every subtree before its root */
+  for (int step = m - 1; step >= 0; --step) {
+    int j = T->ord[step], p = T->par[j];
+    if (p > 0) T->cd[p] += L->c * T->len[j] + T->cd[j];
+  }
+  for (int step = 0; step < m; ++step) {
+    int j = T->ord[step];
+    T->delay[j] = T->delay[T->par[j]] + L->scale * L->r * T->len[j] * (0.5 * L->c * T->len[j] + T->cd[j]);
+  }
+}
+
+/* net delay into every sink and the load of every driver, in the library's
+ * net model */
+static void net_pass(const onl *n, const olib *L, const float *x, const float *y, double *dnet, double *load) {
+  otree T;
+  if (L->model == 2 && otree_alloc(&T, max_net_pins(n->net_ptr, n->num_nets)) != 0) { otree_free(&T); abort(); }
+  for (int net = 0; net < n->num_nets; ++net) {
+    int s = n->net_pins[n->net_ptr[net]];
+    double ld = 0.0;
+    if (L->model == 2) {
+      tree_topology(n, x, y, net, &T);
+      tree_elmore(n, L, x, y, &T);
+      for (int i = 1; i <= T.m; ++i) {
+        int t = T.pin[i];
+        dnet[t] = T.delay[i];
+        ld += (double)L->pin_cap[n->cell_type[n->pin_cell[t]]] + L->c * T.len[i];
+      }
+    } else {
+      double xs, ys;
+      pin_xy(n, x, y, s, &xs, &ys);
+      for (int k = n->net_ptr[net] + 1; k < n->net_ptr[net + 1]; ++k) {
+        int t = n->net_pins[k];
+        double xt, yt;
+        pin_xy(n, x, y, t, &xt, &yt);
+        double len = fabs(xs - xt) + fabs(ys - yt);
+        double cap = (double)L->pin_cap[n->cell_type[n->pin_cell[t]]];
+        dnet[t] = net_delay(L, len, cap);
+        ld += cap + L->c * len;
+      }
+    }
+    load[s] = ld;
+  }
+  if (L->model == 2) otree_free(&T);
 }
 
 #define NETLIST_ARGS                                                                             \
@@ -278,30 +423,15 @@ int ora_sta(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double clock
   FILL_LIB(L);
   oconn c;
   if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
-  int P = num_pins, N = num_cells, M = num_nets;
+  int P = num_pins, N = num_cells;
   for (int p = 0; p < P; ++p) {
     at[p] = -INFINITY; slew[p] = 0; rat[p] = INFINITY; slack[p] = INFINITY;
     dnet[p] = 0; load[p] = 0; darc[p] = 0;
   }
   for (int cell = 0; cell < N; ++cell) crit[cell] = -1;
 
-  /* net pass: Manhattan length, net delay, star-model driver load */
-  for (int net = 0; net < M; ++net) {
-    int s = net_pins[net_ptr[net]];
-    double xs, ys;
-    pin_xy(&n, x, y, s, &xs, &ys);
-    double ld = 0.0;
-    for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
-      int t = net_pins[k];
-      double xt, yt;
-      pin_xy(&n, x, y, t, &xt, &yt);
-      double len = fabs(xs - xt) + fabs(ys - yt);
-      double cap = (double)pin_cap[cell_type[pin_cell[t]]];
-      dnet[t] = net_delay(&L, len, cap);
-      ld += cap + L.c * len;
-    }
-    load[s] = ld;
-  }
+  /* net pass: wire lengths, net delays, driver loads */
+  net_pass(&n, &L, x, y, dnet, load);
 
   /* forward arrival times in topological order */
   for (int q = 0; q < P; ++q) {
@@ -407,22 +537,7 @@ int ora_sta_early(NETLIST_ARGS, LIB_ARGS, const float *x, const float *y, double
   int P = num_pins;
   double *dnet = (double *)calloc(P, sizeof(double)), *load = (double *)calloc(P, sizeof(double));
   for (int p = 0; p < P; ++p) { at_e[p] = INFINITY; slew_e[p] = 0; darc_e[p] = 0; hold_slack[p] = INFINITY; }
-  for (int net = 0; net < num_nets; ++net) {
-    int s = net_pins[net_ptr[net]];
-    double xs, ys;
-    pin_xy(&n, x, y, s, &xs, &ys);
-    double ld = 0.0;
-    for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
-      int t = net_pins[k];
-      double xt, yt;
-      pin_xy(&n, x, y, t, &xt, &yt);
-      double len = fabs(xs - xt) + fabs(ys - yt);
-      double cap = (double)pin_cap[cell_type[pin_cell[t]]];
-      dnet[t] = net_delay(&L, len, cap);
-      ld += cap + L.c * len;
-    }
-    load[s] = ld;
-  }
+  net_pass(&n, &L, x, y, dnet, load);
   for (int q = 0; q < P; ++q) {
     int p = c.topo[q];
     switch (c.role[p]) {
@@ -963,19 +1078,9 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
   double *A = (double *)malloc(sizeof(double) * P);
   double *Ab = (double *)calloc(P, sizeof(double));
   double *dn = (double *)calloc(P, sizeof(double));
+  double *ld = (double *)calloc(P, sizeof(double)); /* loads stay frozen; not used */
   for (int p = 0; p < P; ++p) A[p] = -INFINITY;
-  for (int net = 0; net < num_nets; ++net) {
-    int s = net_pins[net_ptr[net]];
-    double xs, ys;
-    pin_xy(&n, x, y, s, &xs, &ys);
-    for (int k2 = net_ptr[net] + 1; k2 < net_ptr[net + 1]; ++k2) {
-      int t = net_pins[k2];
-      double xt, yt;
-      pin_xy(&n, x, y, t, &xt, &yt);
-      double len = fabs(xs - xt) + fabs(ys - yt);
-      dn[t] = net_delay(&L, len, (double)pin_cap[cell_type[pin_cell[t]]]);
-    }
-  }
+  net_pass(&n, &L, x, y, dn, ld);
   for (int q = 0; q < P; ++q) {
     int p = c.topo[q];
     int r = c.role[p];
@@ -1023,7 +1128,46 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
   for (int cell = 0; cell < num_cells; ++cell) { grad_x[cell] = 0; grad_y[cell] = 0; }
   if (gabs_x && gabs_y)
     for (int cell = 0; cell < num_cells; ++cell) { gabs_x[cell] = 0; gabs_y[cell] = 0; }
+  otree T;
+  if (L.model == 2 && otree_alloc(&T, max_net_pins(net_ptr, num_nets)) != 0) { otree_free(&T); abort(); }
   for (int net = 0; net < num_nets; ++net) {
+    if (L.model == 2) {
+      /* the net's tree at these positions; the topology is piecewise
+       * constant, so only the wire lengths carry the gradient.  With A(v) the
+       * adjoint summed over v's subtree and B(v) the sum, over the edges on
+       * v's path, of scale r L_e A(child end), the derivative of the value
+       * by the length of the edge into v is
+       *   scale r (c L_v + C_below(v)) A(v) + c B(parent(v)):
+       * the edge's own term and, through C_below, the edges above it. */
+      tree_topology(&n, x, y, net, &T);
+      tree_elmore(&n, &L, x, y, &T);
+      double *Asub = T.aux, *B = T.delay; /* the delays are not needed again */
+      for (int i = 0; i <= T.m; ++i) Asub[i] = i > 0 ? Ab[T.pin[i]] : 0.0;
+      for (int step = T.m - 1; step >= 0; --step) {
+        int j = T.ord[step], p = T.par[j];
+        if (p > 0) Asub[p] += Asub[j];
+      }
+      B[0] = 0.0;
+      for (int step = 0; step < T.m; ++step) {
+        int j = T.ord[step], p = T.par[j];
+        double rs = L.scale * L.r;
+        B[j] = B[p] + rs * T.len[j] * Asub[j];
+        double gl = rs * (L.c * T.len[j] + T.cd[j]) * Asub[j] + L.c * B[p];
+        double xp, yp, xj, yj;
+        pin_xy(&n, x, y, T.pin[p], &xp, &yp);
+        pin_xy(&n, x, y, T.pin[j], &xj, &yj);
+        double dx = xp - xj, dy = yp - yj;
+        double gx = gl * ((dx > 0) - (dx < 0)), gy = gl * ((dy > 0) - (dy < 0)); /* d value / d X_parent */
+        int cp = pin_cell[T.pin[p]], cj = pin_cell[T.pin[j]];
+        if (cp >= 0 && !cell_fixed[cp]) { grad_x[cp] += gx; grad_y[cp] += gy; }
+        if (cj >= 0 && !cell_fixed[cj]) { grad_x[cj] -= gx; grad_y[cj] -= gy; }
+        if (gabs_x && gabs_y) {
+          if (cp >= 0 && !cell_fixed[cp]) { gabs_x[cp] += fabs(gx); gabs_y[cp] += fabs(gy); }
+          if (cj >= 0 && !cell_fixed[cj]) { gabs_x[cj] += fabs(gx); gabs_y[cj] += fabs(gy); }
+        }
+      }
+      continue;
+    }
     int s = net_pins[net_ptr[net]];
     double xs, ys;
     pin_xy(&n, x, y, s, &xs, &ys);
@@ -1047,8 +1191,25 @@ int ora_stns(NETLIST_ARGS, LIB_ARGS, const uint8_t *cell_fixed, const float *x, 
       }
     }
   }
-  free(A); free(Ab); free(dn);
+  if (L.model == 2) otree_free(&T);
+  free(A); free(Ab); free(dn); free(ld);
   conn_free(&c);
+  return 0;
+}
+
+/* The topology of net model 2: parent[p] is the pin that p hangs from in its
+ * net's spanning tree (the driver for the pins joined to it directly), -1 at
+ * drivers and at pins on no net. */
+int ora_rc_tree(NETLIST_ARGS, const float *x, const float *y, int32_t *parent) {
+  FILL_NETLIST(n);
+  otree T;
+  if (otree_alloc(&T, max_net_pins(net_ptr, num_nets)) != 0) { otree_free(&T); return -1; }
+  for (int p = 0; p < num_pins; ++p) parent[p] = -1;
+  for (int net = 0; net < num_nets; ++net) {
+    tree_topology(&n, x, y, net, &T);
+    for (int i = 1; i <= T.m; ++i) parent[T.pin[i]] = T.pin[T.par[i]];
+  }
+  otree_free(&T);
   return 0;
 }
 
@@ -1094,7 +1255,7 @@ int ora_sta_rf(NETLIST_ARGS, LIB_ARGS, const float *delay_fall, const float *sle
   FILL_LIB(L);
   oconn c;
   if (conn_build(&n, &c) != 0) { conn_free(&c); return -1; }
-  int P = num_pins, N = num_cells, M = num_nets;
+  int P = num_pins, N = num_cells;
   double *dnet = (double *)calloc(P, sizeof(double));
   double *load = (double *)calloc(P, sizeof(double));
   for (int q = 0; q < 2 * P; ++q) { at[q] = -INFINITY; slew[q] = 0.0; rat[q] = INFINITY; slack[q] = INFINITY; }
@@ -1102,22 +1263,7 @@ int ora_sta_rf(NETLIST_ARGS, LIB_ARGS, const float *delay_fall, const float *sle
   for (int q = 0; q < 2 * N; ++q) crit[q] = -1;
   const float *dtab[2] = {delay_lut, delay_fall}, *stab[2] = {slew_lut, slew_fall};
 
-  for (int net = 0; net < M; ++net) {
-    int s = net_pins[net_ptr[net]];
-    double xs, ys;
-    pin_xy(&n, x, y, s, &xs, &ys);
-    double ld = 0.0;
-    for (int k = net_ptr[net] + 1; k < net_ptr[net + 1]; ++k) {
-      int t = net_pins[k];
-      double xt, yt;
-      pin_xy(&n, x, y, t, &xt, &yt);
-      double len = fabs(xs - xt) + fabs(ys - yt);
-      double cap = (double)pin_cap[cell_type[pin_cell[t]]];
-      dnet[t] = net_delay(&L, len, cap);
-      ld += cap + L.c * len;
-    }
-    load[s] = ld;
-  }
+  net_pass(&n, &L, x, y, dnet, load);
 
   for (int q = 0; q < P; ++q) {
     int p = c.topo[q];

@@ -22,7 +22,7 @@ def _tiny(seed, n=24, depth=5):
 
 
 @pytest.mark.parametrize("seed", range(8))
-@pytest.mark.parametrize("net_model", [0, 1])
+@pytest.mark.parametrize("net_model", [0, 1, 2])
 def test_early_arrivals_are_the_shortest_paths(seed, net_model, library):
     lib = dict(library, net_model=net_model)
     nl = _tiny(seed)
@@ -58,7 +58,7 @@ def test_hand_diamond_takes_the_short_branch():
     assert (ok["whs"], ok["ths"], ok["n_hold_fail"]) == (0.0, 0.0, 0)  # slack exactly 0 is met
 
 
-@pytest.mark.parametrize("net_model", [0, 1])
+@pytest.mark.parametrize("net_model", [0, 1, 2])
 def test_single_fan_in_chain_has_equal_early_and_late(net_model):
     nl, _ = handnets.chain_netlist()
     lib = dict(handnets.dyadic_library(), net_model=net_model)
@@ -67,7 +67,7 @@ def test_single_fan_in_chain_has_equal_early_and_late(net_model):
     assert np.array_equal(e["at"], late["at"]) and np.array_equal(e["slew"], late["slew"])
 
 
-@pytest.mark.parametrize("net_model", [0, 1])
+@pytest.mark.parametrize("net_model", [0, 1, 2])
 def test_early_bounds_late_on_a_generated_design(net_model, library):
     lib = dict(library, net_model=net_model)
     nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), lib)

@@ -39,7 +39,7 @@ def _same_tables(lib):
     return out
 
 
-@pytest.mark.parametrize("net_model", [0, 1])
+@pytest.mark.parametrize("net_model", [0, 1, 2])
 def test_equal_tables_and_positive_arcs_reduce_to_one_transition(net_model, library):
     lib = dict(library, net_model=net_model)
     nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), lib)
