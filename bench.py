@@ -34,7 +34,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2m_cells.md")
 # the kernel that carries each stage's work (per-level sweeps launch it once
 # per level, the dataflow sweeps once)
 STAGE_KERNEL = {
-    "netpass": ("tdp::k_netpass<float>",), "forward": ("tdp::k_forward<float, 8>", "tdp::k_forward_flow<8>"),
+    "netpass": ("tdp::k_netpass<float, false>", "tdp::k_netpass<float, true>"), "forward": ("tdp::k_forward<float, 8>", "tdp::k_forward_flow<8>"),
     "backward": ("tdp::k_backward<float>", "tdp::k_backward_flow"), "walk": ("tdp::k_walk<float>",),
     "pairs": ("tdp::k_pairs_acc_lds<float>",), "wa": ("tdp::k_wa_net",), "search": ("tdp::k_search<float, 8>",),
 }
@@ -116,8 +116,9 @@ def parse():
                          "against timing-driven runs, and the time per iteration")
     ap.add_argument("--loop-beta", type=float, default=2e-3,
                     help="PP weight of the timing-driven runs of --loop (um^-2 scale of these designs)")
-    ap.add_argument("--net-model", type=int, default=0, choices=(0, 1),
-                    help="0: lumped RC wires (Eq. 7); 1: Elmore star nets with degraded sink transitions")
+    ap.add_argument("--net-model", type=int, default=0, choices=(0, 1, 2),
+                    help="0: lumped RC wires (Eq. 7); 1: Elmore star nets with degraded sink transitions; "
+                         "2: Elmore delays on each net's rectilinear minimum spanning tree, degraded transitions")
     ap.add_argument("--configs", action="store_true",
                     help="one line per workload (2k, 200k, 1M and 2M cells, and the batched union), each from its "
                          "own run of this script, with the oracle's rate where it finishes in seconds")
@@ -706,7 +707,8 @@ def main():
         "config": {"workload": f"{a.workload}: {nl['num_cells']} cells, {pins} pins, depth {g.depth}, "
                                f"{E} endpoints, (n_fail, k, K) = ({nfail}, {k}, {K}), clustered placement "
                                f"in {cfg.die:.0f} um die; step = STA + extraction + Eq. 9 pairs + WA + p2p "
-                               f"fwd/bwd" + ("; Elmore net model" if a.net_model else ""),
+                               f"fwd/bwd" + {0: "", 1: "; Elmore star nets",
+                                             2: "; Elmore spanning-tree nets"}[a.net_model],
                    "parallelism": "none"},
         "sta_extract_pins_per_s": round(pins / ((sta_ms + ext_ms) * 1e-3), 1) if sta_ms else None,
         "p2p_fwd_bwd_GBps": round((sb["p2p_fwd"] + sb["p2p_bwd"]) / (loss_ms * 1e-3) / 1e9, 2) if loss_ms else None,

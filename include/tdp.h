@@ -98,10 +98,10 @@ typedef struct {
  *  delay_lut, slew_lut [num_types][n_slew][n_load]: arc delay and output
  *    transition (slew_lut may equal delay_lut).
  *  pin_cap[num_types]: input-pin capacitance.
- *  Every sink sits on a wire of its own from the driver, of length L, the
- *  Manhattan driver-to-sink distance, with resistance r_per_um * L and
- *  capacitance c_per_um * L (Eq. 7: R and C both linear in length).  A
- *  driver's load = sum over its sinks of (pin_cap + c_per_um * L).
+ *  In models 0 and 1 every sink sits on a wire of its own from the driver,
+ *  of length L, the Manhattan driver-to-sink distance, with resistance
+ *  r_per_um * L and capacitance c_per_um * L (Eq. 7: R and C both linear in
+ *  length).  A driver's load = sum over its sinks of (pin_cap + c_per_um * L).
  *  net_model selects the net delay into a sink and the transition it sees:
  *    0  lumped (Eq. 7): delay_scale * r_per_um * c_per_um * L^2; the sink
  *       sees its driver's transition.
@@ -109,6 +109,19 @@ typedef struct {
  *       (c_per_um * L / 2 + pin_cap of the sink); the sink's transition is
  *       the driver's degraded by the wire (PERI, Kashyap et al., TCAD 2004):
  *       sqrt(s_drv^2 + (ln 9 * delay)^2).
+ *    2  Elmore delay of an RC tree on the net's rectilinear minimum spanning
+ *       tree (Prim's algorithm from the driver on single-precision Manhattan
+ *       distances; ties to the pin first in the net's list, and a pin keeps
+ *       the first tree pin that reached it).  Each edge is a wire of its
+ *       Manhattan length L (r_per_um * L, c_per_um * L); the delay to a pin
+ *       is delay_scale times the sum, over the edges (parent, u) on its path,
+ *       of r_per_um * L * (c_per_um * L / 2 + capacitance at and below u);
+ *       the driver's load is the sum of the sink pin capacitances plus
+ *       c_per_um times the tree's length; transitions degrade as in model 1.
+ *       The smoothed TNS differentiates the delays through the wire lengths
+ *       of the tree at the given positions.  Sec. III-C's wires as the RC
+ *       trees of the paper's timer (Sec. II-B); the spanning tree stands in
+ *       for a Steiner tree.
  *  Any other value fails the build with TDP_E_INVALID. */
 typedef struct {
   int32_t num_types, n_slew, n_load;

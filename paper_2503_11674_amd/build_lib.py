@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtdp.so")
 SOURCES = ["tdp_build.cpp", "tdp_prims.hip", "tdp_sta.hip", "tdp_paths.hip", "tdp_global.hip", "tdp_pairs.hip",
-           "tdp_smooth.hip", "tdp_place.hip", "tdp_early.hip", "tdp_rf.hip",
+           "tdp_smooth.hip", "tdp_place.hip", "tdp_early.hip", "tdp_rf.hip", "tdp_tree.hip",
            "tdp_api.hip"]
 ARCH = os.environ.get("TDP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

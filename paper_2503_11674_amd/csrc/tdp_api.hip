@@ -246,6 +246,15 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   ok = ok && dalloc(g, g->st_at, T.P, es) && dalloc(g, g->st_adj, T.P, es) && dalloc(g, g->st_dnet, T.S, es) &&
        dalloc(g, g->wa_gpin, (size_t)2 * T.P) && dalloc(g, g->xy, T.N) &&
        dalloc(g, g->xy_wa, T.N) && dalloc(g, g->cxy_nm, (size_t)T.n_nm_chunks * CHUNK);
+  // spanning-tree net model: scratch of the net pass and of the smoothed TNS
+  if (lib->net_model == 2) {
+    auto tree_alloc = [&](TreeBuf &b) {
+      return dalloc(g, b.dist, T.S) && dalloc(g, b.par, T.S) && dalloc(g, b.ord, T.S) && dalloc(g, b.len, T.S, es) &&
+             dalloc(g, b.cd, T.S, es) && dalloc(g, b.aux, T.S, es) && dalloc(g, b.aux2, T.S, es) &&
+             dalloc(g, b.wl, T.M, es);
+    };
+    ok = ok && tree_alloc(g->tree) && tree_alloc(g->st_tree) && dalloc(g, g->st_tree_gp, (size_t)2 * T.P, es);
+  }
   if (!ok || hipDeviceSynchronize() != hipSuccess) {
     free_all(g);
     delete g;

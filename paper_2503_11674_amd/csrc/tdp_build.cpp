@@ -45,7 +45,7 @@ bool check_library(const tdp_library *lib, std::string &err) {
       return fail(err, "library: table entry not finite");
   if (!std::isfinite(lib->r_per_um) || !std::isfinite(lib->c_per_um) || !std::isfinite(lib->delay_scale))
     return fail(err, "library: wire parameters not finite");
-  if (lib->net_model != 0 && lib->net_model != 1) return fail(err, "library: net_model must be 0 or 1");
+  if (lib->net_model < 0 || lib->net_model > 2) return fail(err, "library: net_model must be 0, 1 or 2");
   return true;
 }
 

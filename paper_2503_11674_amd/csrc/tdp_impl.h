@@ -25,6 +25,14 @@ inline void prof_end(tdp_graph g, int stage, hipStream_t s) {
 }
 
 template <typename T> void netpass_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);
+// spanning-tree net model, one thread per net: the net delays of every net
+// (list null) or of the n nets listed, and the trees' lengths
+template <typename T>
+void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y, T *dnet, const int32_t *list,
+                   int n, hipStream_t s);
+// the smoothed TNS's gradient per pin through the trees (into st_tree_gp)
+template <typename T>
+void st_tree_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s);
 // WNS / TNS / violated count per instance from the endpoint slacks
 template <typename T> void ep_reduce_impl(tdp_graph g, hipStream_t s);
 template <typename T> void rf_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);

@@ -40,7 +40,9 @@ struct LutView {
 // linear in length).  Lumped: the wire's R times its C, kappa * len^2 with
 // kappa = scale * r * c.  Elmore: each sink on a branch of its own from the
 // driver, a uniform RC line loaded by the sink's pin capacitance; the first
-// moment of its response is scale * r * len * (c * len / 2 + cap).
+// moment of its response is scale * r * len * (c * len / 2 + cap).  The
+// spanning-tree model (elmore == 2) takes its delays from each net's tree
+// instead (the tree kernels); delay() and slope() serve models 0 and 1.
 template <typename T>
 struct NetModel {
   int elmore;
@@ -55,6 +57,22 @@ struct NetModel {
     return elmore ? rs * ((T)2 * hc * len + cap) : (T)2 * kappa * len;
   }
 };
+
+// Scratch of the spanning-tree net model (element type T of the timing values
+// for len, cd, aux, aux2 and wl)
+struct TreeBuf {
+  float *dist;
+  int32_t *par, *ord;
+  void *len, *cd, *aux, *aux2, *wl;
+};
+
+// The spanning-tree model's topology metric: the single-precision Manhattan
+// distance of two pins, each given as cell coordinates and offset, each axis
+// taken as (cell difference) + (offset difference)
+__device__ __forceinline__ float tree_fdist(float ax, float ay, float aox, float aoy, float bx, float by, float box,
+                                            float boy) {
+  return fabsf((ax - bx) + (aox - box)) + fabsf((ay - by) + (aoy - boy));
+}
 
 // Transition at a sink: the driver's, or under the Elmore model that one
 // degraded by the wire (PERI: root sum of squares of the input transition and
@@ -349,6 +367,15 @@ struct tdp_graph_s {
   float *dn_w = nullptr;                       // [2 (2R+1)][N] window weights of the sorted cells
   float *dn_map = nullptr;                     // [bins]
   double *dn_part = nullptr, *nest_part = nullptr, *nest_alpha = nullptr;
+
+  // net model 2 (spanning-tree RC nets), allocated at build when the library
+  // selects it: the net pass's scratch and the smoothed TNS's, per sink slot
+  // of net_sink (Prim's distance, parent slot or -1 for the driver, joining
+  // order, wire length, capacitance below, two adjoint sums) and per net (the
+  // tree's length); st_tree_gp holds the smoothed TNS's gradient per pin and
+  // axis [2P]
+  tdp::TreeBuf tree{}, st_tree{};
+  void *st_tree_gp = nullptr;
 
   // weighted-average wirelength: per-pin gradient [2P]
   float *wa_gpin = nullptr;

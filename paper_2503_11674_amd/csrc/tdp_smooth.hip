@@ -114,10 +114,12 @@ __global__ void __launch_bounds__(256) k_st_bwd(Topo tp, int c0, int c1, T gam, 
 }
 
 // gradient per cell: its output pin's net arcs and its input pins' net arcs
+// (tree_gp: the spanning-tree model's gradient per pin and axis, summed here
+// over the cell's pins instead)
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
                                                   NetModel<T> nm, const T *__restrict__ adj,
-                                                  const double *__restrict__ gout,
+                                                  const T *__restrict__ tree_gp, const double *__restrict__ gout,
                                                   float *__restrict__ gx, float *__restrict__ gy) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= tp.N || tp.cell_fixed[cell]) return;
@@ -134,6 +136,18 @@ __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restric
     t1 = t0 + 1;
   }
   T ax = 0, ay = 0;
+  if (tree_gp) {
+    ax = tree_gp[v];
+    ay = tree_gp[tp.P + v];
+    for (int t = t0; t < t1; ++t) {
+      ax += tree_gp[tp.M + t];
+      ay += tree_gp[tp.P + tp.M + t];
+    }
+    const T go = (T)*gout;
+    gx[cell] += (float)(go * ax);
+    gy[cell] += (float)(go * ay);
+    return;
+  }
   {  // this cell drives the net of v
     const T cx = (T)x[cell], cy = (T)y[cell], ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
     for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
@@ -180,8 +194,11 @@ void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, dou
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_STNS, s);
   const T gam = (T)gamma;
-  hipLaunchKernelGGL(k_st_net<T>, dim3(nb(tp.M, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
-                     (T *)g->st_dnet);
+  if (g->lut.net_model == 2)
+    tree_net_impl<T>(g, g->st_tree, x, y, (T *)g->st_dnet, nullptr, 0, s);
+  else
+    hipLaunchKernelGGL(k_st_net<T>, dim3(nb(tp.M, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
+                       (T *)g->st_dnet);
   if (tp.n_start > 0)
     hipLaunchKernelGGL(k_st_start<T>, dim3(nb(tp.n_start, 256)), dim3(256), 0, s, tp, (const T *)g->at,
                        (T *)g->st_at);
@@ -212,8 +229,10 @@ void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStr
       hipLaunchKernelGGL(k_st_bwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
                          (const T *)g->darc, (const T *)g->st_at, (T *)g->st_adj);
   }
+  const bool tree = g->lut.net_model == 2;
+  if (tree) st_tree_grad_impl<T>(g, g->st_x, g->st_y, (const T *)g->st_adj, s);
   hipLaunchKernelGGL(k_st_grad<T>, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->st_x, g->st_y, net_model<T>(g),
-                     (const T *)g->st_adj, gout, gx, gy);
+                     (const T *)g->st_adj, tree ? (const T *)g->st_tree_gp : nullptr, gout, gx, gy);
   prof_end(g, TDP_STAGE_STNS, s);
 }
 

@@ -176,8 +176,71 @@ __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, in
 }
 
 // ------------------------------------------------------------- net pass
-// one net chunk of the net pass
+// The spanning-tree model on a net chunk: Prim's algorithm on every segment
+// at once, one pin joining each unfinished segment per round (the segment's
+// nearest outside pin, ties to the lowest lane, which is the net's order;
+// it hangs from the tree pin that reached it first at that distance), then
+// each sink's wire from its parent, the capacitance at and below it (reverse
+// joining order) and its Elmore delay (joining order): the operations of the
+// one-thread-per-net form, in its order.  The minima are exact, so the DPP
+// reductions give the same picks wherever a segment sits.  Returns the lane's
+// wire length (0 off the sinks) and its delay in dn.  Every lane of the wave
+// must call it.
 template <typename T>
+__device__ __forceinline__ T tree_chunk(const NetModel<T> &nm, T cw, int lane, int head, int tail, bool sink,
+                                        float fx, float fy, float fox, float foy, T cx, T cy, T ox, T oy, T cap,
+                                        T &dn) {
+  const float hx = __shfl(fx, head, 64), hy = __shfl(fy, head, 64);
+  const float hox = __shfl(fox, head, 64), hoy = __shfl(foy, head, 64);
+  bool out = sink;  // not yet in the tree
+  float dist = sink ? tree_fdist(hx, hy, hox, hoy, fx, fy, fox, foy) : 0.f;
+  int par = head, st = -1, who = lane;  // lane head + 1 + j records who joined in round j
+  int rounds = 0;
+  while (__ballot(out)) {
+    // non-finite distances (non-finite positions) rank last
+    const float key = out && dist == dist ? dist : __builtin_huge_valf();
+    const float mn = seg_min_dpp(key, lane, head, tail);
+    const int pick = seg_min_dpp(out && key == mn ? lane : 64, lane, head, tail);
+    const bool got = pick < 64;
+    if (got && lane == pick) {
+      out = false;
+      st = rounds;
+    }
+    if (got && lane == head + 1 + rounds) who = pick;
+    const int src = got ? pick : lane;
+    const float px = __shfl(fx, src, 64), py = __shfl(fy, src, 64);
+    const float pox = __shfl(fox, src, 64), poy = __shfl(foy, src, 64);
+    if (out && got) {
+      const float d = tree_fdist(px, py, pox, poy, fx, fy, fox, foy);
+      if (d < dist) {
+        dist = d;
+        par = pick;
+      }
+    }
+    ++rounds;
+  }
+  const T pcx = __shfl(cx, par, 64), pcy = __shfl(cy, par, 64);
+  const T pox = __shfl(ox, par, 64), poy = __shfl(oy, par, 64);
+  const T len = sink ? fabs((pcx - cx) + (pox - ox)) + fabs((pcy - cy) + (poy - oy)) : (T)0;
+  T cd = sink ? cap : (T)0;
+  for (int j = rounds - 1; j >= 0; --j) {
+    const int slot = head + 1 + j;
+    const int w = __shfl(who, slot < 64 ? slot : 63, 64);
+    const T c = __shfl(cw * len + cd, w, 64);
+    const int pw = __shfl(par, w, 64);
+    if (slot <= tail && lane == pw && pw != head) cd += c;
+  }
+  T dl = 0;
+  for (int j = 0; j < rounds; ++j) {
+    const T pd = __shfl(dl, par, 64);
+    if (st == j) dl = pd + nm.rs * len * (nm.hc * len + cd);
+  }
+  dn = dl;
+  return len;
+}
+
+// one net chunk of the net pass (TREE: the spanning-tree model)
+template <typename T, bool TREE>
 __device__ __forceinline__ void netpass_chunk(const Topo &tp, const LutView &L, int chunk, const float2 *__restrict__ xy,
                                               const NetModel<T> &nm, T cw, T in_slew, T clk_slew,
                                               T *__restrict__ load, T *__restrict__ dnet, T *__restrict__ dnet_nm,
@@ -199,9 +262,15 @@ __device__ __forceinline__ void netpass_chunk(const Topo &tp, const LutView &L, 
   const T cxd = __shfl(cx, head, 64), cyd = __shfl(cy, head, 64);
   const T oxd = __shfl(ox, head, 64), oyd = __shfl(oy, head, 64);
   const bool sink = p >= 0 && lane != head;
-  const T len = sink ? fabs((cxd - cx) + (oxd - ox)) + fabs((cyd - cy) + (oyd - oy)) : (T)0;
+  T len, dn = 0;
+  if constexpr (TREE) {
+    len = tree_chunk<T>(nm, cw, lane, head, tail, sink, q.x, q.y, tp.nm_ox[k], tp.nm_oy[k], cx, cy, ox, oy,
+                        sink ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0, dn);
+  } else {
+    len = sink ? fabs((cxd - cx) + (oxd - ox)) + fabs((cyd - cy) + (oyd - oy)) : (T)0;
+  }
   if (sink) {
-    const T dn = nm.delay(len, nm.elmore ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0);
+    if constexpr (!TREE) dn = nm.delay(len, nm.elmore ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0);
     dnet[p - tp.M] = dn;
     dnet_nm[k] = dn;
     // incremental: every sink of a re-timed net gets its chunk re-timed
@@ -217,7 +286,7 @@ __device__ __forceinline__ void netpass_chunk(const Topo &tp, const LutView &L, 
   }
 }
 
-template <typename T>
+template <typename T, bool TREE>
 __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float2 *__restrict__ xy, NetModel<T> nm,
                                                   T cw, T in_slew,
                                                   T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
@@ -232,13 +301,13 @@ __global__ void __launch_bounds__(256) k_netpass(Topo tp, LutView L, const float
   }
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
-  netpass_chunk<T>(tp, L, chunk, xy, nm, cw, in_slew, clk_slew, load, dnet, dnet_nm, cxy_nm, at, slew, as, cdep, fl,
-                   IncFlags{});
+  netpass_chunk<T, TREE>(tp, L, chunk, xy, nm, cw, in_slew, clk_slew, load, dnet, dnet_nm, cxy_nm, at, slew, as,
+                         cdep, fl, IncFlags{});
 }
 
 // the net pass over the marked net chunks of an incremental update (the same
 // computation per chunk, so the results are those of a full pass)
-template <typename T>
+template <typename T, bool TREE>
 __global__ void __launch_bounds__(256) k_netpass_marked(Topo tp, LutView L, const float2 *__restrict__ xy,
                                                          NetModel<T> nm, T cw, T in_slew, T clk_slew,
                                                          T *__restrict__ load, T *__restrict__ dnet,
@@ -248,14 +317,16 @@ __global__ void __launch_bounds__(256) k_netpass_marked(Topo tp, LutView L, cons
                                                          IncFlags inc) {
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks || inc.nm[chunk] != inc.epoch) return;
-  netpass_chunk<T>(tp, L, chunk, xy, nm, cw, in_slew, clk_slew, load, dnet, dnet_nm, cxy_nm, at, slew, as, cdep,
-                   FlowInit{}, inc);
+  netpass_chunk<T, TREE>(tp, L, chunk, xy, nm, cw, in_slew, clk_slew, load, dnet, dnet_nm, cxy_nm, at, slew, as,
+                         cdep, FlowInit{}, inc);
 }
 
-// nets too wide for one chunk: one thread per net
+// nets too wide for one chunk: one thread per net (tree_wl: the spanning-tree
+// model, whose delays the tree kernel wrote)
 template <typename T>
 __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, const float *__restrict__ y, NetModel<T> nm,
-                              T cw, T in_slew, T clk_slew, T *__restrict__ load, T *__restrict__ dnet,
+                              const T *__restrict__ tree_wl, T cw, T in_slew, T clk_slew, T *__restrict__ load,
+                              T *__restrict__ dnet,
                               T *__restrict__ at, T *__restrict__ slew, V2<T> *__restrict__ as,
                               int32_t *__restrict__ cdep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -264,8 +335,8 @@ __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, c
   const int dc = tp.drv_cell[v];
   const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
   const T ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
-  T wl = 0;
-  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
+  T wl = tree_wl ? tree_wl[v] : (T)0;
+  for (int k = tp.net_ptr[v]; !tree_wl && k < tp.net_ptr[v + 1]; ++k) {
     const int t = tp.net_sink[k];
     const int sc = tp.snk_cell[t];
     const T len = fabs((cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t])) + fabs((cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]));
@@ -1019,13 +1090,18 @@ template <typename T>
 static void netpass_launch(tdp_graph g, const float *x, const float *y, const FlowInit &fl, hipStream_t s) {
   const Topo &tp = g->topo;
   const NetModel<T> nm = net_model<T>(g);
+  const bool tree = g->lut.net_model == 2;
+  const T *tree_wl = tree ? (const T *)g->tree.wl : nullptr;
   pack_xy(x, y, g->xy, tp.N, s, g->d_err + 1, ++g->pos_gen);
-  hipLaunchKernelGGL(k_netpass<T>, dim3(nblk(tp.n_nm_chunks, 4) + fl.reset_blocks), dim3(256), 0, s, tp, g->lut,
-                     g->xy, nm,
+  const auto k_np = tree ? k_netpass<T, true> : k_netpass<T, false>;
+  hipLaunchKernelGGL(k_np, dim3(nblk(tp.n_nm_chunks, 4) + fl.reset_blocks),
+                     dim3(256), 0, s, tp, g->lut, g->xy, nm,
                      (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm,
                      g->cxy_nm, (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, fl);
+  // nets wider than a chunk: their trees one thread per net first
+  if (tp.n_big > 0 && tree) tree_net_impl<T>(g, g->tree, x, y, (T *)g->dnet, tp.big_net, tp.n_big, s);
   if (tp.n_big > 0)
-    hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, nm,
+    hipLaunchKernelGGL(k_netpass_big<T>, dim3(nblk(tp.n_big, 64)), dim3(64), 0, s, tp, g->lut, x, y, nm, tree_wl,
                        (T)g->c, (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->at,
                        (T *)g->slew, (V2<T> *)g->drv_as, g->cdep);
 }
@@ -1168,9 +1244,11 @@ void sta_arrivals_incremental_impl(tdp_graph g, const float *x, const float *y, 
     hipLaunchKernelGGL(k_inc_mark, dim3(nblk(n, 256)), dim3(256), 0, s, tp, cells, n, g->inc_drv_nm_chunk,
                        g->inc_nm, inc.epoch, g->d_err);
   pack_xy(x, y, g->xy, tp.N, s, g->d_err + 1, ++g->pos_gen);
+  // (every net fits a chunk here: graphs with wider nets take full updates)
+  const auto k_npm = g->lut.net_model == 2 ? k_netpass_marked<T, true> : k_netpass_marked<T, false>;
   if (n > 0)
-    hipLaunchKernelGGL(k_netpass_marked<T>, dim3(nblk(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->lut, g->xy, nm,
-                       (T)g->c,
+    hipLaunchKernelGGL(k_npm, dim3(nblk(tp.n_nm_chunks, 4)),
+                       dim3(256), 0, s, tp, g->lut, g->xy, nm, (T)g->c,
                        (T)g->input_slew, (T)g->clock_slew, (T *)g->load, (T *)g->dnet, (T *)g->dnet_nm, g->cxy_nm,
                        (T *)g->at, (T *)g->slew, (V2<T> *)g->drv_as, g->cdep, inc);
   prof_end(g, TDP_STAGE_NETPASS, s);

@@ -1,0 +1,210 @@
+// Net model 2: every net an RC tree on the rectilinear minimum spanning tree
+// of its pins (a fuller model of the wires of Eq. 7, Sec. III-C; the paper's
+// timer times nets as RC trees).
+//
+// Topology: Prim's algorithm from the driver.  The pin outside the tree
+// nearest to it joins next (ties: the pin first in the net's list), hung from
+// the tree pin that reached it first at that distance (a later pin at equal
+// distance does not take it over).  Distances are single precision,
+// |(cell x - cell x) + (offset x - offset x)| + the same in y, whatever the
+// precision of the timing values, so every precision and every layout of the
+// same net takes the same decisions.
+// Delays: each edge a uniform wire of its Manhattan length L (resistance
+// r L, capacitance c L).  With C_below(v) the capacitance at and below v (its
+// pin and the wires and pins of its subtree), the Elmore delay to v is the
+// sum over the edges e = (parent, u) on its path of r L_e (c L_e / 2 +
+// C_below(u)), times scale; the driver's load is the pin capacitances plus c
+// times the tree's length.  Children join after their parents, so the
+// reverse joining order accumulates C_below and the joining order the delays.
+//
+// Here one thread per net, its scratch in global memory per sink slot: the
+// form for nets wider than a 64-lane chunk and for the smoothed TNS; the net
+// pass runs the same steps on its chunks, a lane per pin.
+#include "tdp_impl.h"
+
+namespace tdp {
+
+static inline int nbt(long long n, int b) { return n > 0 ? (int)((n + b - 1) / b) : 1; }
+
+template <typename T>
+struct TreeView {
+  float *dist;
+  int32_t *par, *ord;
+  T *len, *cd, *aux, *aux2, *wl;
+};
+
+template <typename T>
+static TreeView<T> view(const TreeBuf &b) {
+  return TreeView<T>{b.dist, b.par, b.ord, (T *)b.len, (T *)b.cd, (T *)b.aux, (T *)b.aux2, (T *)b.wl};
+}
+
+// a pin of net v: its cell's coordinates and its offset (slot -1: the driver)
+struct PinXY {
+  float cx, cy, ox, oy;
+};
+
+__device__ __forceinline__ PinXY tree_pin(const Topo &tp, const float *__restrict__ x, const float *__restrict__ y,
+                                          int v, int k) {
+  if (k < 0) {
+    const int dc = tp.drv_cell[v];
+    return PinXY{dc >= 0 ? x[dc] : 0.f, dc >= 0 ? y[dc] : 0.f, tp.drv_ox[v], tp.drv_oy[v]};
+  }
+  const int t = tp.net_sink[k];
+  const int sc = tp.snk_cell[t];
+  return PinXY{x[sc], y[sc], tp.snk_ox[t], tp.snk_oy[t]};
+}
+
+__device__ __forceinline__ float tree_fdist(const PinXY &a, const PinXY &b) {
+  return tree_fdist(a.cx, a.cy, a.ox, a.oy, b.cx, b.cy, b.ox, b.oy);
+}
+
+// (parent - child) per axis in T: (cell difference) + (offset difference)
+template <typename T>
+__device__ __forceinline__ void tree_diff(const PinXY &p, const PinXY &c, T &dx, T &dy) {
+  dx = ((T)p.cx - (T)c.cx) + ((T)p.ox - (T)c.ox);
+  dy = ((T)p.cy - (T)c.cy) + ((T)p.oy - (T)c.oy);
+}
+
+// Prim's tree of net v, then each slot's wire length and capacitance below;
+// returns the tree's length
+template <typename T>
+__device__ T tree_build(const Topo &tp, const float *__restrict__ x, const float *__restrict__ y, T cw, int v,
+                        const TreeView<T> &tb) {
+  const int k0 = tp.net_ptr[v], k1 = tp.net_ptr[v + 1];
+  const PinXY drv = tree_pin(tp, x, y, v, -1);
+  for (int k = k0; k < k1; ++k) {
+    tb.dist[k] = tree_fdist(drv, tree_pin(tp, x, y, v, k));
+    tb.par[k] = -1;
+  }
+  // a slot in the tree holds distance -1 (a non-finite position gives NaN
+  // distances, which still count as outside, so every step takes a slot)
+  for (int step = 0; step < k1 - k0; ++step) {
+    int j = -1;
+    float bd = 0.f;
+    for (int k = k0; k < k1; ++k) {
+      const float d = tb.dist[k];
+      if (!(d < 0.f) && (j < 0 || d < bd)) {
+        j = k;
+        bd = d;
+      }
+    }
+    tb.ord[k0 + step] = j;
+    tb.dist[j] = -1.f;
+    const PinXY pj = tree_pin(tp, x, y, v, j);
+    for (int k = k0; k < k1; ++k) {
+      const float dk = tb.dist[k];
+      if (dk < 0.f) continue;
+      const float d = tree_fdist(pj, tree_pin(tp, x, y, v, k));
+      if (d < dk) {
+        tb.dist[k] = d;
+        tb.par[k] = j;
+      }
+    }
+  }
+  T wl = 0;
+  for (int k = k0; k < k1; ++k) {
+    T dx, dy;
+    tree_diff<T>(tree_pin(tp, x, y, v, tb.par[k]), tree_pin(tp, x, y, v, k), dx, dy);
+    const T len = fabs(dx) + fabs(dy);
+    tb.len[k] = len;
+    tb.cd[k] = (T)tp.snk_cap[tp.net_sink[k]];
+    wl += len;
+  }
+  for (int step = k1 - k0 - 1; step >= 0; --step) {
+    const int k = tb.ord[k0 + step], p = tb.par[k];
+    if (p >= 0) tb.cd[p] += cw * tb.len[k] + tb.cd[k];
+  }
+  return wl;
+}
+
+// net delays of the sinks of every net (or of the n nets listed) and each
+// net's tree length
+template <typename T>
+__global__ void __launch_bounds__(256) k_tree_net(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
+                                                   NetModel<T> nm, T cw, TreeView<T> tb, T *__restrict__ dnet,
+                                                   const int32_t *__restrict__ list, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int v = list ? list[i] : i;
+  tb.wl[v] = tree_build<T>(tp, x, y, cw, v, tb);
+  const int k0 = tp.net_ptr[v], k1 = tp.net_ptr[v + 1];
+  for (int step = 0; step < k1 - k0; ++step) {
+    const int k = tb.ord[k0 + step], p = tb.par[k];
+    const T dp = p >= 0 ? dnet[tp.net_sink[p]] : (T)0;
+    const T len = tb.len[k];
+    dnet[tp.net_sink[k]] = dp + nm.rs * len * (nm.hc * len + tb.cd[k]);
+  }
+}
+
+// Gradient of the smoothed TNS through the trees, per pin.  The topology is
+// piecewise constant in the positions, so the wire lengths carry the whole
+// derivative.  With A(u) the adjoint (d value / d net delay) summed over u's
+// subtree and B(u) the sum over the edges e on u's path of scale r L_e
+// A(child end of e), the derivative by the length of the edge into u is
+//   scale r (c L_u + C_below(u)) A(u) + c B(parent(u)):
+// the edge's own term and its capacitance in C_below of every edge above.
+// gp[pin] (x) and gp[P + pin] (y) collect d value / d position of each pin.
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_tree_grad(Topo tp, const float *__restrict__ x,
+                                                       const float *__restrict__ y, NetModel<T> nm, T cw,
+                                                       TreeView<T> tb, const T *__restrict__ adj, T *__restrict__ gp) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= tp.M) return;
+  tree_build<T>(tp, x, y, cw, v, tb);
+  const int k0 = tp.net_ptr[v], k1 = tp.net_ptr[v + 1];
+  T *gpx = gp, *gpy = gp + tp.P;
+  gpx[v] = 0;
+  gpy[v] = 0;
+  for (int k = k0; k < k1; ++k) {
+    const int t = tp.net_sink[k];
+    tb.aux[k] = adj[tp.M + t];
+    gpx[tp.M + t] = 0;
+    gpy[tp.M + t] = 0;
+  }
+  for (int step = k1 - k0 - 1; step >= 0; --step) {
+    const int k = tb.ord[k0 + step], p = tb.par[k];
+    if (p >= 0) tb.aux[p] += tb.aux[k];
+  }
+  for (int step = 0; step < k1 - k0; ++step) {
+    const int k = tb.ord[k0 + step], p = tb.par[k];
+    const T bp = p >= 0 ? tb.aux2[p] : (T)0;
+    const T len = tb.len[k], a = tb.aux[k];
+    tb.aux2[k] = bp + nm.rs * len * a;
+    const T gl = nm.rs * (cw * len + tb.cd[k]) * a + cw * bp;
+    T dx, dy;
+    tree_diff<T>(tree_pin(tp, x, y, v, p), tree_pin(tp, x, y, v, k), dx, dy);
+    const T gx = gl * (T)((dx > (T)0) - (dx < (T)0)), gy = gl * (T)((dy > (T)0) - (dy < (T)0));
+    const int pp = p >= 0 ? tp.M + tp.net_sink[p] : v, pk = tp.M + tp.net_sink[k];
+    gpx[pp] += gx;
+    gpy[pp] += gy;
+    gpx[pk] -= gx;
+    gpy[pk] -= gy;
+  }
+}
+
+template <typename T>
+void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y, T *dnet, const int32_t *list,
+                   int n, hipStream_t s) {
+  const Topo &tp = g->topo;
+  if (!list) n = tp.M;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_tree_net<T>, dim3(nbt(n, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g), (T)g->c,
+                     view<T>(b), dnet, list, n);
+}
+
+template <typename T>
+void st_tree_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s) {
+  const Topo &tp = g->topo;
+  if (tp.M == 0) return;
+  hipLaunchKernelGGL(k_st_tree_grad<T>, dim3(nbt(tp.M, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
+                     (T)g->c, view<T>(g->st_tree), adj, (T *)g->st_tree_gp);
+}
+
+template void tree_net_impl<float>(tdp_graph, const TreeBuf &, const float *, const float *, float *,
+                                   const int32_t *, int, hipStream_t);
+template void tree_net_impl<double>(tdp_graph, const TreeBuf &, const float *, const float *, double *,
+                                    const int32_t *, int, hipStream_t);
+template void st_tree_grad_impl<float>(tdp_graph, const float *, const float *, const float *, hipStream_t);
+template void st_tree_grad_impl<double>(tdp_graph, const float *, const float *, const double *, hipStream_t);
+
+}  // namespace tdp

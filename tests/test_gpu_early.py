@@ -35,8 +35,8 @@ def _hold_between(arrivals, frac=0.05):
     return float(0.5 * (a[q - 1] + a[q]))
 
 
-@pytest.mark.parametrize("name,net_model,prec", [("C1", 0, "f32"), ("C1", 1, "f32"), ("C2", 0, "f32"),
-                                                 ("C2", 1, "f64")])
+@pytest.mark.parametrize("name,net_model,prec", [("C1", 0, "f32"), ("C1", 1, "f32"), ("C1", 2, "f32"),
+                                                 ("C2", 0, "f32"), ("C2", 1, "f64")])
 def test_early_parity(name, net_model, prec, library):
     tdp = _tdp()
     lib = dict(library, net_model=net_model)

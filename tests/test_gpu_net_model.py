@@ -206,7 +206,7 @@ def test_net_model_is_validated(library):
     tdp = _tdp()
     nl = with_clock(netgen.make_netlist(netgen.CONFIGS["C1"]), library)
     with pytest.raises(Exception, match="net_model"):
-        tdp.TimingGraph(nl, dict(library, net_model=2), max_paths=10, max_k=1)
+        tdp.TimingGraph(nl, dict(library, net_model=3), max_paths=10, max_k=1)
     # cell types travel in 8-bit fields: a library with more is refused
     nt = 300
     wide = {"num_types": nt,

@@ -62,7 +62,7 @@ def _roles(nl):
     return role
 
 
-@pytest.mark.parametrize("name,net_model", [("C1", 0), ("C2", 0), ("C2", 1)])
+@pytest.mark.parametrize("name,net_model", [("C1", 0), ("C2", 0), ("C2", 1), ("C2", 2)])
 def test_rise_fall_timing_and_paths(name, net_model, library):
     tdp = _tdp()
     nl, lib, rf, ep = _case(name, library, net_model)
