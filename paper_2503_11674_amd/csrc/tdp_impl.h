@@ -30,6 +30,9 @@ template <typename T> void netpass_impl(tdp_graph g, const float *x, const float
 template <typename T>
 void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y, T *dnet, const int32_t *list,
                    int n, hipStream_t s);
+// the smoothed TNS's net delays through the trees
+template <typename T>
+void st_tree_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s);
 // the smoothed TNS's gradient per pin through the trees (into st_tree_gp)
 template <typename T>
 void st_tree_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s);

@@ -195,7 +195,7 @@ void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, dou
   prof_begin(g, TDP_STAGE_STNS, s);
   const T gam = (T)gamma;
   if (g->lut.net_model == 2)
-    tree_net_impl<T>(g, g->st_tree, x, y, (T *)g->st_dnet, nullptr, 0, s);
+    st_tree_fwd_impl<T>(g, x, y, (T *)g->st_dnet, s);
   else
     hipLaunchKernelGGL(k_st_net<T>, dim3(nb(tp.M, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
                        (T *)g->st_dnet);

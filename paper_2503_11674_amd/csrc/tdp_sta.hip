@@ -27,6 +27,7 @@
 #include "tdp_impl.h"
 #include "tdp_prims.h"
 #include "tdp_wave.h"
+#include "tdp_tree.h"
 
 namespace tdp {
 
@@ -176,69 +177,6 @@ __device__ __forceinline__ void start_point(const Topo &tp, const LutView &L, in
 }
 
 // ------------------------------------------------------------- net pass
-// The spanning-tree model on a net chunk: Prim's algorithm on every segment
-// at once, one pin joining each unfinished segment per round (the segment's
-// nearest outside pin, ties to the lowest lane, which is the net's order;
-// it hangs from the tree pin that reached it first at that distance), then
-// each sink's wire from its parent, the capacitance at and below it (reverse
-// joining order) and its Elmore delay (joining order): the operations of the
-// one-thread-per-net form, in its order.  The minima are exact, so the DPP
-// reductions give the same picks wherever a segment sits.  Returns the lane's
-// wire length (0 off the sinks) and its delay in dn.  Every lane of the wave
-// must call it.
-template <typename T>
-__device__ __forceinline__ T tree_chunk(const NetModel<T> &nm, T cw, int lane, int head, int tail, bool sink,
-                                        float fx, float fy, float fox, float foy, T cx, T cy, T ox, T oy, T cap,
-                                        T &dn) {
-  const float hx = __shfl(fx, head, 64), hy = __shfl(fy, head, 64);
-  const float hox = __shfl(fox, head, 64), hoy = __shfl(foy, head, 64);
-  bool out = sink;  // not yet in the tree
-  float dist = sink ? tree_fdist(hx, hy, hox, hoy, fx, fy, fox, foy) : 0.f;
-  int par = head, st = -1, who = lane;  // lane head + 1 + j records who joined in round j
-  int rounds = 0;
-  while (__ballot(out)) {
-    // non-finite distances (non-finite positions) rank last
-    const float key = out && dist == dist ? dist : __builtin_huge_valf();
-    const float mn = seg_min_dpp(key, lane, head, tail);
-    const int pick = seg_min_dpp(out && key == mn ? lane : 64, lane, head, tail);
-    const bool got = pick < 64;
-    if (got && lane == pick) {
-      out = false;
-      st = rounds;
-    }
-    if (got && lane == head + 1 + rounds) who = pick;
-    const int src = got ? pick : lane;
-    const float px = __shfl(fx, src, 64), py = __shfl(fy, src, 64);
-    const float pox = __shfl(fox, src, 64), poy = __shfl(foy, src, 64);
-    if (out && got) {
-      const float d = tree_fdist(px, py, pox, poy, fx, fy, fox, foy);
-      if (d < dist) {
-        dist = d;
-        par = pick;
-      }
-    }
-    ++rounds;
-  }
-  const T pcx = __shfl(cx, par, 64), pcy = __shfl(cy, par, 64);
-  const T pox = __shfl(ox, par, 64), poy = __shfl(oy, par, 64);
-  const T len = sink ? fabs((pcx - cx) + (pox - ox)) + fabs((pcy - cy) + (poy - oy)) : (T)0;
-  T cd = sink ? cap : (T)0;
-  for (int j = rounds - 1; j >= 0; --j) {
-    const int slot = head + 1 + j;
-    const int w = __shfl(who, slot < 64 ? slot : 63, 64);
-    const T c = __shfl(cw * len + cd, w, 64);
-    const int pw = __shfl(par, w, 64);
-    if (slot <= tail && lane == pw && pw != head) cd += c;
-  }
-  T dl = 0;
-  for (int j = 0; j < rounds; ++j) {
-    const T pd = __shfl(dl, par, 64);
-    if (st == j) dl = pd + nm.rs * len * (nm.hc * len + cd);
-  }
-  dn = dl;
-  return len;
-}
-
 // one net chunk of the net pass (TREE: the spanning-tree model)
 template <typename T, bool TREE>
 __device__ __forceinline__ void netpass_chunk(const Topo &tp, const LutView &L, int chunk, const float2 *__restrict__ xy,
@@ -264,8 +202,10 @@ __device__ __forceinline__ void netpass_chunk(const Topo &tp, const LutView &L, 
   const bool sink = p >= 0 && lane != head;
   T len, dn = 0;
   if constexpr (TREE) {
-    len = tree_chunk<T>(nm, cw, lane, head, tail, sink, q.x, q.y, tp.nm_ox[k], tp.nm_oy[k], cx, cy, ox, oy,
-                        sink ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0, dn);
+    const ChunkTree<T> tr = tree_chunk_build<T>(cw, lane, head, tail, sink, q.x, q.y, tp.nm_ox[k], tp.nm_oy[k], cx,
+                                                cy, ox, oy, sink ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0);
+    len = tr.len;
+    dn = tree_chunk_delay<T>(nm, tr);
   } else {
     len = sink ? fabs((cxd - cx) + (oxd - ox)) + fabs((cyd - cy) + (oyd - oy)) : (T)0;
   }

@@ -17,10 +17,12 @@
 // times the tree's length.  Children join after their parents, so the
 // reverse joining order accumulates C_below and the joining order the delays.
 //
-// Here one thread per net, its scratch in global memory per sink slot: the
-// form for nets wider than a 64-lane chunk and for the smoothed TNS; the net
-// pass runs the same steps on its chunks, a lane per pin.
+// Two forms: on net chunks, a lane per pin (tdp_tree.h), for every net that
+// fits one; and one thread per net with its scratch in global memory per
+// sink slot, for nets wider than a chunk.  The net pass builds its chunks'
+// trees itself; the kernels here serve its wide nets and the smoothed TNS.
 #include "tdp_impl.h"
+#include "tdp_tree.h"
 
 namespace tdp {
 
@@ -147,9 +149,11 @@ __global__ void __launch_bounds__(256) k_tree_net(Topo tp, const float *__restri
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_tree_grad(Topo tp, const float *__restrict__ x,
                                                        const float *__restrict__ y, NetModel<T> nm, T cw,
-                                                       TreeView<T> tb, const T *__restrict__ adj, T *__restrict__ gp) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= tp.M) return;
+                                                       TreeView<T> tb, const T *__restrict__ adj, T *__restrict__ gp,
+                                                       const int32_t *__restrict__ list, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int v = list[i];
   tree_build<T>(tp, x, y, cw, v, tb);
   const int k0 = tp.net_ptr[v], k1 = tp.net_ptr[v + 1];
   T *gpx = gp, *gpy = gp + tp.P;
@@ -182,6 +186,107 @@ __global__ void __launch_bounds__(256) k_st_tree_grad(Topo tp, const float *__re
   }
 }
 
+// the chunk form of the two kernels above, over the net chunks: a net chunk's
+// lane data, its trees, and (forward) the sinks' delays
+struct ChunkLane {
+  int lane, p, head, tail;
+  bool sink;
+  float fx, fy, fox, foy;
+  int ty;
+};
+
+__device__ __forceinline__ ChunkLane chunk_lane(const Topo &tp, const float *__restrict__ x,
+                                                const float *__restrict__ y, int chunk) {
+  ChunkLane c;
+  c.lane = wave_lane();
+  const int k = chunk * CHUNK + c.lane;
+  const int4 rec = tp.nm_rec[k];
+  c.p = rec.x;
+  c.head = rec.w & 63;
+  c.tail = (rec.w >> 8) & 63;
+  c.ty = (rec.w >> 16) & 255;
+  c.sink = c.p >= 0 && c.lane != c.head;
+  c.fx = rec.y >= 0 ? x[rec.y] : 0.f;
+  c.fy = rec.y >= 0 ? y[rec.y] : 0.f;
+  c.fox = tp.nm_ox[k];
+  c.foy = tp.nm_oy[k];
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ ChunkTree<T> chunk_tree(const Topo &tp, const ChunkLane &c, T cw) {
+  return tree_chunk_build<T>(cw, c.lane, c.head, c.tail, c.sink, c.fx, c.fy, c.fox, c.foy, (T)c.fx, (T)c.fy,
+                             (T)c.fox, (T)c.foy, c.sink ? (T)tp.type_cap[c.ty] : (T)0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_tree_chunks(Topo tp, const float *__restrict__ x,
+                                                         const float *__restrict__ y, NetModel<T> nm, T cw,
+                                                         T *__restrict__ dnl) {
+  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= tp.n_nm_chunks) return;
+  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  const ChunkTree<T> tr = chunk_tree<T>(tp, c, cw);
+  const T dn = tree_chunk_delay<T>(nm, tr);
+  if (c.sink) dnl[c.p - tp.M] = dn;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_tree_grad_chunks(Topo tp, const float *__restrict__ x,
+                                                              const float *__restrict__ y, NetModel<T> nm, T cw,
+                                                              const T *__restrict__ adj, T *__restrict__ gp) {
+  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= tp.n_nm_chunks) return;
+  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  const ChunkTree<T> tr = chunk_tree<T>(tp, c, cw);
+  const int lane = c.lane, head = c.head, tail = c.tail;
+  // A: the adjoint summed over the subtree (reverse joining order)
+  T a = c.sink ? adj[c.p] : (T)0;
+  for (int j = tr.rounds - 1; j >= 0; --j) {
+    const int slot = head + 1 + j;
+    const int w = __shfl(tr.who, slot < 64 ? slot : 63, 64);
+    const T aw = __shfl(a, w, 64);
+    const int pw = __shfl(tr.par, w, 64);
+    if (slot <= tail && lane == pw && pw != head) a += aw;
+  }
+  // B along the path and the derivative by the lane's own wire length
+  T b = 0, gl = 0;
+  for (int j = 0; j < tr.rounds; ++j) {
+    const T bp = __shfl(b, tr.par, 64);
+    if (tr.st == j) {
+      b = bp + nm.rs * tr.len * a;
+      gl = nm.rs * (cw * tr.len + tr.cd) * a + cw * bp;
+    }
+  }
+  const T pcx = __shfl((T)c.fx, tr.par, 64), pcy = __shfl((T)c.fy, tr.par, 64);
+  const T pox = __shfl((T)c.fox, tr.par, 64), poy = __shfl((T)c.foy, tr.par, 64);
+  const T dx = (pcx - (T)c.fx) + (pox - (T)c.fox), dy = (pcy - (T)c.fy) + (poy - (T)c.foy);
+  const T ex = c.sink ? gl * (T)((dx > (T)0) - (dx < (T)0)) : (T)0;
+  const T ey = c.sink ? gl * (T)((dy > (T)0) - (dy < (T)0)) : (T)0;
+  // per pin, in joining order: minus its own wire's term, plus its children's
+  T gx = 0, gy = 0;
+  for (int j = 0; j < tr.rounds; ++j) {
+    const int slot = head + 1 + j;
+    const int w = __shfl(tr.who, slot < 64 ? slot : 63, 64);
+    const T exw = __shfl(ex, w, 64), eyw = __shfl(ey, w, 64);
+    const int pw = __shfl(tr.par, w, 64);
+    if (slot <= tail) {
+      if (lane == pw) {
+        gx += exw;
+        gy += eyw;
+      }
+      if (lane == w) {
+        gx -= ex;
+        gy -= ey;
+      }
+    }
+  }
+  if (c.p >= 0) {
+    gp[c.p] = gx;
+    gp[tp.P + c.p] = gy;
+  }
+}
+
 template <typename T>
 void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y, T *dnet, const int32_t *list,
                    int n, hipStream_t s) {
@@ -193,17 +298,31 @@ void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y
 }
 
 template <typename T>
+void st_tree_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s) {
+  const Topo &tp = g->topo;
+  if (tp.n_nm_chunks > 0)
+    hipLaunchKernelGGL(k_st_tree_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+                       net_model<T>(g), (T)g->c, dnl);
+  if (tp.n_big > 0) tree_net_impl<T>(g, g->st_tree, x, y, dnl, tp.big_net, tp.n_big, s);
+}
+
+template <typename T>
 void st_tree_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s) {
   const Topo &tp = g->topo;
-  if (tp.M == 0) return;
-  hipLaunchKernelGGL(k_st_tree_grad<T>, dim3(nbt(tp.M, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
-                     (T)g->c, view<T>(g->st_tree), adj, (T *)g->st_tree_gp);
+  if (tp.n_nm_chunks > 0)
+    hipLaunchKernelGGL(k_st_tree_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+                       net_model<T>(g), (T)g->c, adj, (T *)g->st_tree_gp);
+  if (tp.n_big > 0)
+    hipLaunchKernelGGL(k_st_tree_grad<T>, dim3(nbt(tp.n_big, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
+                       (T)g->c, view<T>(g->st_tree), adj, (T *)g->st_tree_gp, tp.big_net, tp.n_big);
 }
 
 template void tree_net_impl<float>(tdp_graph, const TreeBuf &, const float *, const float *, float *,
                                    const int32_t *, int, hipStream_t);
 template void tree_net_impl<double>(tdp_graph, const TreeBuf &, const float *, const float *, double *,
                                     const int32_t *, int, hipStream_t);
+template void st_tree_fwd_impl<float>(tdp_graph, const float *, const float *, float *, hipStream_t);
+template void st_tree_fwd_impl<double>(tdp_graph, const float *, const float *, double *, hipStream_t);
 template void st_tree_grad_impl<float>(tdp_graph, const float *, const float *, const float *, hipStream_t);
 template void st_tree_grad_impl<double>(tdp_graph, const float *, const float *, const double *, hipStream_t);
 
