@@ -648,8 +648,12 @@ def test_bitwise_determinism(library):
 
 
 # -------------------------------------------------------------- batching
-def test_batch_matches_single_instances(library):
+@pytest.mark.parametrize("net_model", [0, 2])
+def test_batch_matches_single_instances(net_model, library):
+    # the spanning-tree model builds its trees per chunk segment: an instance's
+    # nets give the same bits wherever they sit in the union's chunks
     tdp = _tdp()
+    library = dict(library, net_model=net_model)
     nls = []
     for i, n in enumerate((3000, 800, 5000)):
         cfg = netgen.NetlistConfig(f"b{i}", n, depth=10 + 5 * i, fanout_cap=16, die=600.0, seed=40 + i)
@@ -676,7 +680,8 @@ def test_batch_matches_single_instances(library):
         w, t, n = g.summary()
         assert (w, n) == (wb[i], nb[i]) and abs(t - tb[i]) <= 1e-9 * max(1.0, abs(t))
         o = g.export()
-        assert torch.equal(o["slack"], ob["slack"][pb[i]:pb[i + 1]])
+        for key in ("slack", "dnet", "load", "slew"):
+            assert torch.equal(o[key], ob[key][pb[i]:pb[i + 1]]), key
         g.extract_paths(n=-1, k=4, K=300)
         p = g.paths()
         sel = (P["path_ep"] >= pb[i]) & (P["path_ep"] < pb[i + 1])
