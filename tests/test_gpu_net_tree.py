@@ -212,3 +212,41 @@ def test_tree_incremental_equals_full(library):
         assert inf_ok and bad == 0, (key, bad, worst)
     gi.close()
     gf.close()
+
+
+@pytest.mark.parametrize("wide", [False, True])
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_tree_hand_net_is_exact(wide, precision):
+    """Dyadic positions and library: every wire length, capacitance and
+    Elmore delay is a short binary fraction, so both sides compute them
+    exactly.  A port drives sinks at (8, 0), (16, 0), (16, 8), (24, 0): the
+    tree is port -> (8, 0) -> (16, 0) -> {(16, 8), (24, 0)}, the last two tied
+    at distance 8 (the first listed joins first).  C_below = 14, 10, 2, 2 fF,
+    delays 7.5, 13, 14.5, 14.5 ps, load 16 fF.  The wide form adds 64 sinks
+    on the line y = 0 (one thread per net instead of a chunk's lanes)."""
+    from tests import handnets
+    tdp = _tdp()
+    lib = dict(handnets.dyadic_library(), net_model=2)
+    sx = [8.0, 16.0, 16.0, 24.0] + ([32.0 + 8 * i for i in range(64)] if wide else [])
+    sy = [0.0, 0.0, 8.0, 0.0] + ([0.0] * 64 if wide else [])
+    n = len(sx)
+    cells = [(0, 1)] * n + [(netgen.FF_TYPE, 1)] * n
+    port = 4 * n
+    nets = [(port, [2 * i for i in range(n)])] + [(2 * i + 1, [2 * n + 2 * i]) for i in range(n)] + \
+        [(2 * n + 2 * i + 1, []) for i in range(n)]
+    x = sx + [v + 4.0 for v in sx]
+    y = sy + sy
+    nl, _ = handnets.build(cells, 1, nets, x, y, port_xy=[(0.0, 0.0)], clock_period=400.0)
+    st = ref.sta(nl, lib)
+    par = ref.rc_tree(nl)
+    assert [int(par[2 * i]) for i in range(4)] == [port, 0, 2, 2]
+    if not wide:
+        assert st["dnet"][[0, 2, 4, 6]].tolist() == [7.5, 13.0, 14.5, 14.5]
+        assert st["load"][port] == 16.0
+    g = tdp.TimingGraph(nl, lib, precision=precision, max_paths=4 * n, max_k=2)
+    g.sta_update(*_xy(nl))
+    o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+    assert np.array_equal(o["dnet"], st["dnet"]) and np.array_equal(o["load"], st["load"])
+    inf_ok, bad, worst = timing_close(o["at"], st["at"], rtol=1e-6 if precision == "f32" else 1e-12)
+    assert inf_ok and bad == 0, (bad, worst)
+    g.close()
