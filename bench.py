@@ -510,6 +510,45 @@ def after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev):
     return pair_ms, early, rise_fall, incremental
 
 
+def tree_net_leg(nl, lib, x, y, k, K, ep, tune, dev, steps=20):
+    """The same step on a graph built with the spanning-tree net model
+    (net_model 2: Elmore delays on each net's rectilinear minimum spanning
+    tree), its clock again failing 5 % of the endpoints under this model, in
+    the sweep form the step chose; outside the timed region."""
+    import time
+
+    import torch
+
+    from paper_2503_11674_amd import netgen
+    from paper_2503_11674_amd.tdp import TimingGraph
+
+    g2 = TimingGraph(nl, dict(lib, net_model=2), max_paths=K, max_k=k)
+    g2.sta_update(x, y)
+    at = g2.export()["at"].cpu().numpy()
+    g2.set_clock(netgen.clock_period_for_fail_fraction(at[ep], 0.05))
+    if tune and "sweep_mode" in tune:
+        g2.set_tuning(sweep_mode=tune["sweep_mode"])
+    gx, gy = torch.zeros_like(x), torch.zeros_like(y)
+    wl = torch.zeros((), dtype=torch.float64, device=dev)
+    pp = torch.zeros((), dtype=torch.float64, device=dev)
+    beta = torch.full((), BETA, dtype=torch.float64, device=dev)
+    step = build_step(g2, x, y, k, K, gx, gy, wl, pp, beta)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    w, t, n = g2.summary()
+    out = {"ms_per_step": round(ms, 4), "pins_per_s": round(g2.num_pins / (ms * 1e-3), 1), "wns": round(w, 1),
+           "tns": round(t, 1), "n_fail": n}
+    g2.close()
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -663,9 +702,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    pair_ms, early, rise_fall, incremental = {}, None, None, {}
+    pair_ms, early, rise_fall, incremental, tree_nets = {}, None, None, {}, None
     if not a.step_only:
         pair_ms, early, rise_fall, incremental = after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev)
+        if a.net_model == 0:
+            tree_nets = tree_net_leg(nl, lib, x, y, k, K, ep, tune, dev)
 
     sta_ms = sum(stages[s]["ms"] for s in ("netpass", "forward", "endpoint", "backward") if s in stages)
     ext_ms = sum(stages[s]["ms"] for s in ("select", "search", "order", "walk") if s in stages)
@@ -719,6 +760,7 @@ def main():
         "early_analysis": early,
         "rise_fall": rise_fall,
         "incremental_arrivals": incremental,
+        "spanning_tree_nets": tree_nets,
         "roofline": roof,
         "graph_replay": bool(graph is not None),
         "streams": 1 if a.serial else 3,
