@@ -156,7 +156,7 @@ def test_rise_fall_double_precision_and_state(library):
     gb.close()
 
 
-@pytest.mark.parametrize("net_model", [0, 1])
+@pytest.mark.parametrize("net_model", [0, 1, 2])
 def test_rise_fall_nets_wider_than_a_chunk(net_model, library):
     """Two nets of more than 63 sinks take the one-thread-per-net path of the
     backward pass: both transitions' arrival, required time and slack match
