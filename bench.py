@@ -417,8 +417,9 @@ def bench_loop(a):
 
 def after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev):
     """The legs timed after the step on the same graph: the three pair
-    distances, the early (hold) analysis, rise / fall timing and incremental
-    arrival updates; leaves the graph in the step's single-transition state."""
+    distances, the smoothed TNS and its adjoint, the early (hold) analysis,
+    rise / fall timing and incremental arrival updates; leaves the graph in
+    the step's single-transition state."""
     import torch
 
     from paper_2503_11674_amd import netgen
@@ -438,6 +439,23 @@ def after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev):
         e1.record()
         e1.synchronize()
         pair_ms[name] = round(e0.elapsed_time(e1) / 20, 4)
+    # the smoothed TNS (gamma 10 ps) at the step's positions, forward and
+    # adjoint
+    st_v = torch.zeros((), dtype=torch.float64, device=dev)
+    g.stns_fwd(x, y, 10.0, out=st_v)
+    g.stns_bwd(one, gx, gy)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(10):
+        g.stns_fwd(x, y, 10.0, out=st_v)
+    ev[1].record()
+    for _ in range(10):
+        g.stns_bwd(one, gx, gy)
+    ev[2].record()
+    ev[2].synchronize()
+    stns = {"fwd_ms": round(ev[0].elapsed_time(ev[1]) / 10, 4), "bwd_ms": round(ev[1].elapsed_time(ev[2]) / 10, 4),
+            "value": round(float(st_v), 1)}
+
     # the early (hold) analysis on the same update, outside the step: the hold
     # time at which 5 % of the D pins fail
     g.sta_update_early(0.0)
@@ -507,7 +525,7 @@ def after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev):
     g.sta_update(x, y)
     torch.cuda.synchronize()
 
-    return pair_ms, early, rise_fall, incremental
+    return pair_ms, stns, early, rise_fall, incremental
 
 
 def tree_net_leg(nl, lib, x, y, k, K, ep, tune, dev, steps=20):
@@ -702,9 +720,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
-    pair_ms, early, rise_fall, incremental, tree_nets = {}, None, None, {}, None
+    pair_ms, stns, early, rise_fall, incremental, tree_nets = {}, None, None, None, {}, None
     if not a.step_only:
-        pair_ms, early, rise_fall, incremental = after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev)
+        pair_ms, stns, early, rise_fall, incremental = after_step_legs(g, nl, lib, x, y, gx, gy, pp, ep, dev)
         if a.net_model == 0:
             tree_nets = tree_net_leg(nl, lib, x, y, k, K, ep, tune, dev)
 
@@ -760,6 +778,7 @@ def main():
         "early_analysis": early,
         "rise_fall": rise_fall,
         "incremental_arrivals": incremental,
+        "smoothed_tns": stns,
         "spanning_tree_nets": tree_nets,
         "roofline": roof,
         "graph_replay": bool(graph is not None),

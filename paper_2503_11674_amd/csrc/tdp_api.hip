@@ -244,6 +244,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
        dalloc(g, g->inc_w, (size_t)2 * T.S);
   // smoothed TNS, WA
   ok = ok && dalloc(g, g->st_at, T.P, es) && dalloc(g, g->st_adj, T.P, es) && dalloc(g, g->st_dnet, T.S, es) &&
+       dalloc(g, g->st_gp, (size_t)2 * T.P, es) &&
        dalloc(g, g->wa_gpin, (size_t)2 * T.P) && dalloc(g, g->xy, T.N) &&
        dalloc(g, g->xy_wa, T.N) && dalloc(g, g->cxy_nm, (size_t)T.n_nm_chunks * CHUNK);
   // spanning-tree net model: scratch of the net pass and of the smoothed TNS
@@ -253,7 +254,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
              dalloc(g, b.cd, T.S, es) && dalloc(g, b.aux, T.S, es) && dalloc(g, b.aux2, T.S, es) &&
              dalloc(g, b.wl, T.M, es);
     };
-    ok = ok && tree_alloc(g->tree) && tree_alloc(g->st_tree) && dalloc(g, g->st_tree_gp, (size_t)2 * T.P, es);
+    ok = ok && tree_alloc(g->tree) && tree_alloc(g->st_tree);
   }
   if (!ok || hipDeviceSynchronize() != hipSuccess) {
     free_all(g);

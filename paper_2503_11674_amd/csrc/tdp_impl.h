@@ -30,12 +30,13 @@ template <typename T> void netpass_impl(tdp_graph g, const float *x, const float
 template <typename T>
 void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y, T *dnet, const int32_t *list,
                    int n, hipStream_t s);
-// the smoothed TNS's net delays through the trees
+// the smoothed TNS's net delays at positions (x, y), in the graph's net model
 template <typename T>
-void st_tree_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s);
-// the smoothed TNS's gradient per pin through the trees (into st_tree_gp)
+void st_net_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s);
+// the smoothed TNS's gradient per pin and axis (into st_gp) from the adjoint
+// of the net delays
 template <typename T>
-void st_tree_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s);
+void st_net_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s);
 // WNS / TNS / violated count per instance from the endpoint slacks
 template <typename T> void ep_reduce_impl(tdp_graph g, hipStream_t s);
 template <typename T> void rf_update_impl(tdp_graph g, const float *x, const float *y, hipStream_t s);

@@ -323,8 +323,8 @@ struct tdp_graph_s {
   int32_t *inc_other = nullptr, *inc_key = nullptr;
   float *inc_dx = nullptr, *inc_dy = nullptr, *inc_w = nullptr;
 
-  // smoothed TNS
-  void *st_at = nullptr, *st_adj = nullptr, *st_dnet = nullptr;
+  // smoothed TNS (st_gp: the gradient per pin and axis [2P])
+  void *st_at = nullptr, *st_adj = nullptr, *st_dnet = nullptr, *st_gp = nullptr;
   float st_gamma = 0;
   const float *st_x = nullptr, *st_y = nullptr;
 
@@ -372,10 +372,8 @@ struct tdp_graph_s {
   // selects it: the net pass's scratch and the smoothed TNS's, per sink slot
   // of net_sink (Prim's distance, parent slot or -1 for the driver, joining
   // order, wire length, capacitance below, two adjoint sums) and per net (the
-  // tree's length); st_tree_gp holds the smoothed TNS's gradient per pin and
-  // axis [2P]
+  // tree's length)
   tdp::TreeBuf tree{}, st_tree{};
-  void *st_tree_gp = nullptr;
 
   // weighted-average wirelength: per-pin gradient [2P]
   float *wa_gpin = nullptr;

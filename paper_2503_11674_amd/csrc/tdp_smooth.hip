@@ -1,7 +1,7 @@
 // Differentiable objectives: a log-sum-exp smoothed TNS with its adjoint, and
 // weighted-average wirelength.  Both give gradients on cell positions with a
-// fixed summation order per cell (gathers over the cell's own pins and nets;
-// no floating-point atomics).
+// fixed summation order per cell (terms per pin computed per net, then
+// gathered over the cell's own pins; no floating-point atomics).
 //
 // Smoothed TNS (not in the paper; this is its definition here): cell-arc
 // delays and start-point arrivals are frozen from the last timing update, net
@@ -14,7 +14,9 @@
 // The adjoint runs the levels top-down: dv/dA(e) = -sigmoid(-s(e)/g); an
 // output passes its adjoint to input j in proportion to softmax_j(a/g); a
 // driver collects the adjoints of its sinks.  dv/d dnet(t) is the adjoint at
-// t, and d dnet/dX_s = dnet'(L) sign(X_s - X_t) = -d dnet/dX_t.
+// t, and on a star net d dnet/dX_s = dnet'(L) sign(X_s - X_t) = -d dnet/dX_t
+// (the spanning-tree model differentiates through its tree).  The net delays
+// and the per-pin terms come from the net kernels of tdp_tree.hip.
 //
 // Weighted-average wirelength (the smoothed WL of Eq. 1): per net and axis,
 // sum x e^{x/g} / sum e^{x/g} - sum x e^{-x/g} / sum e^{-x/g}, with the
@@ -30,23 +32,6 @@ static inline int nb(long long n, int b) { return n > 0 ? (int)((n + b - 1) / b)
 template <typename T>
 __device__ __forceinline__ T sgn(T v) {
   return (T)((v > (T)0) - (v < (T)0));
-}
-
-template <typename T>
-__global__ void k_st_net(Topo tp, const float *__restrict__ x, const float *__restrict__ y, NetModel<T> nm,
-                         T *__restrict__ dnl) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= tp.M) return;
-  const int dc = tp.drv_cell[v];
-  // (cell - cell) + (offset - offset): see the net pass
-  const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
-  const T ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
-  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
-    const int t = tp.net_sink[k];
-    const int sc = tp.snk_cell[t];
-    const T len = fabs((cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t])) + fabs((cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]));
-    dnl[t] = nm.delay(len, nm.elmore ? (T)tp.snk_cap[t] : (T)0);
-  }
 }
 
 template <typename T>
@@ -113,13 +98,10 @@ __global__ void __launch_bounds__(256) k_st_bwd(Topo tp, int c0, int c1, T gam, 
     adj[tp.M + t] = ab * exp((sa[tp.M + t] + darc[t] - av) / gam);
 }
 
-// gradient per cell: its output pin's net arcs and its input pins' net arcs
-// (tree_gp: the spanning-tree model's gradient per pin and axis, summed here
-// over the cell's pins instead)
+// gradient per cell: the sum of its pins' gradients (its output pin, then its
+// input pins), which the net kernels computed per pin
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restrict__ x, const float *__restrict__ y,
-                                                  NetModel<T> nm, const T *__restrict__ adj,
-                                                  const T *__restrict__ tree_gp, const double *__restrict__ gout,
+__global__ void __launch_bounds__(256) k_st_grad(Topo tp, const T *__restrict__ gp, const double *__restrict__ gout,
                                                   float *__restrict__ gx, float *__restrict__ gy) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= tp.N || tp.cell_fixed[cell]) return;
@@ -135,39 +117,10 @@ __global__ void __launch_bounds__(256) k_st_grad(Topo tp, const float *__restric
     t0 = tp.A + f;
     t1 = t0 + 1;
   }
-  T ax = 0, ay = 0;
-  if (tree_gp) {
-    ax = tree_gp[v];
-    ay = tree_gp[tp.P + v];
-    for (int t = t0; t < t1; ++t) {
-      ax += tree_gp[tp.M + t];
-      ay += tree_gp[tp.P + tp.M + t];
-    }
-    const T go = (T)*gout;
-    gx[cell] += (float)(go * ax);
-    gy[cell] += (float)(go * ay);
-    return;
-  }
-  {  // this cell drives the net of v
-    const T cx = (T)x[cell], cy = (T)y[cell], ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
-    for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
-      const int t = tp.net_sink[k];
-      const int sc = tp.snk_cell[t];
-      const T dx = (cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t]), dy = (cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]);
-      const T g = adj[tp.M + t] * nm.slope(fabs(dx) + fabs(dy), nm.elmore ? (T)tp.snk_cap[t] : (T)0);
-      ax += g * sgn(dx);
-      ay += g * sgn(dy);
-    }
-  }
-  for (int t = t0; t < t1; ++t) {  // this cell's input pins are sinks
-    const int s = tp.snk_drv[t];
-    const int dc = tp.drv_cell[s];
-    const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
-    const T dx = (cx - (T)x[cell]) + ((T)tp.drv_ox[s] - (T)tp.snk_ox[t]);
-    const T dy = (cy - (T)y[cell]) + ((T)tp.drv_oy[s] - (T)tp.snk_oy[t]);
-    const T g = adj[tp.M + t] * nm.slope(fabs(dx) + fabs(dy), nm.elmore ? (T)tp.snk_cap[t] : (T)0);
-    ax -= g * sgn(dx);
-    ay -= g * sgn(dy);
+  T ax = gp[v], ay = gp[tp.P + v];
+  for (int t = t0; t < t1; ++t) {
+    ax += gp[tp.M + t];
+    ay += gp[tp.P + tp.M + t];
   }
   const T go = (T)*gout;
   gx[cell] += (float)(go * ax);
@@ -194,11 +147,7 @@ void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, dou
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_STNS, s);
   const T gam = (T)gamma;
-  if (g->lut.net_model == 2)
-    st_tree_fwd_impl<T>(g, x, y, (T *)g->st_dnet, s);
-  else
-    hipLaunchKernelGGL(k_st_net<T>, dim3(nb(tp.M, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
-                       (T *)g->st_dnet);
+  st_net_fwd_impl<T>(g, x, y, (T *)g->st_dnet, s);
   if (tp.n_start > 0)
     hipLaunchKernelGGL(k_st_start<T>, dim3(nb(tp.n_start, 256)), dim3(256), 0, s, tp, (const T *)g->at,
                        (T *)g->st_at);
@@ -229,10 +178,8 @@ void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStr
       hipLaunchKernelGGL(k_st_bwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
                          (const T *)g->darc, (const T *)g->st_at, (T *)g->st_adj);
   }
-  const bool tree = g->lut.net_model == 2;
-  if (tree) st_tree_grad_impl<T>(g, g->st_x, g->st_y, (const T *)g->st_adj, s);
-  hipLaunchKernelGGL(k_st_grad<T>, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, g->st_x, g->st_y, net_model<T>(g),
-                     (const T *)g->st_adj, tree ? (const T *)g->st_tree_gp : nullptr, gout, gx, gy);
+  st_net_grad_impl<T>(g, g->st_x, g->st_y, (const T *)g->st_adj, s);
+  hipLaunchKernelGGL(k_st_grad<T>, dim3(nb(tp.N, 256)), dim3(256), 0, s, tp, (const T *)g->st_gp, gout, gx, gy);
   prof_end(g, TDP_STAGE_STNS, s);
 }
 

@@ -20,7 +20,9 @@
 // Two forms: on net chunks, a lane per pin (tdp_tree.h), for every net that
 // fits one; and one thread per net with its scratch in global memory per
 // sink slot, for nets wider than a chunk.  The net pass builds its chunks'
-// trees itself; the kernels here serve its wide nets and the smoothed TNS.
+// trees itself; the kernels here serve its wide nets and the smoothed TNS,
+// whose net delays and position gradients for the star models (0 and 1)
+// are here too, in the same two forms.
 #include "tdp_impl.h"
 #include "tdp_tree.h"
 
@@ -287,6 +289,85 @@ __global__ void __launch_bounds__(256) k_st_tree_grad_chunks(Topo tp, const floa
   }
 }
 
+// The star models on net chunks: a sink's wire runs from the driver (the
+// head lane); (driver - sink) per axis as (cell difference) + (offset
+// difference), its Manhattan length (0 off the sinks) returned
+template <typename T>
+__device__ __forceinline__ T star_diff(const ChunkLane &c, T &dx, T &dy) {
+  const T cxd = __shfl((T)c.fx, c.head, 64), cyd = __shfl((T)c.fy, c.head, 64);
+  const T oxd = __shfl((T)c.fox, c.head, 64), oyd = __shfl((T)c.foy, c.head, 64);
+  dx = (cxd - (T)c.fx) + (oxd - (T)c.fox);
+  dy = (cyd - (T)c.fy) + (oyd - (T)c.foy);
+  return c.sink ? fabs(dx) + fabs(dy) : (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_star_chunks(Topo tp, const float *__restrict__ x,
+                                                         const float *__restrict__ y, NetModel<T> nm,
+                                                         T *__restrict__ dnl) {
+  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= tp.n_nm_chunks) return;
+  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  T dx, dy;
+  const T len = star_diff<T>(c, dx, dy);
+  if (c.sink) dnl[c.p - tp.M] = nm.delay(len, nm.elmore ? (T)tp.type_cap[c.ty] : (T)0);
+}
+
+// per pin: a sink minus its wire's term, the driver the sum of its sinks'
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_star_grad_chunks(Topo tp, const float *__restrict__ x,
+                                                              const float *__restrict__ y, NetModel<T> nm,
+                                                              const T *__restrict__ adj, T *__restrict__ gp) {
+  const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= tp.n_nm_chunks) return;
+  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  T dx, dy;
+  const T len = star_diff<T>(c, dx, dy);
+  const T gl = c.sink ? adj[c.p] * nm.slope(len, nm.elmore ? (T)tp.type_cap[c.ty] : (T)0) : (T)0;
+  const T ex = gl * (T)((dx > (T)0) - (dx < (T)0)), ey = gl * (T)((dy > (T)0) - (dy < (T)0));
+  const T sx = seg_sum(ex, c.lane, c.head, c.tail), sy = seg_sum(ey, c.lane, c.head, c.tail);
+  if (c.p >= 0) {
+    gp[c.p] = c.sink ? -ex : sx;
+    gp[tp.P + c.p] = c.sink ? -ey : sy;
+  }
+}
+
+// the star models on the n nets listed (nets wider than a chunk), one thread
+// per net: the sinks' delays (adj null) or the pins' gradients
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_star_big(Topo tp, const float *__restrict__ x,
+                                                      const float *__restrict__ y, NetModel<T> nm,
+                                                      const T *__restrict__ adj, T *__restrict__ dnl,
+                                                      T *__restrict__ gp, const int32_t *__restrict__ list, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int v = list[i];
+  const int dc = tp.drv_cell[v];
+  const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
+  const T ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
+  T sx = 0, sy = 0;
+  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
+    const int t = tp.net_sink[k];
+    const int sc = tp.snk_cell[t];
+    const T dx = (cx - (T)x[sc]) + (ox - (T)tp.snk_ox[t]), dy = (cy - (T)y[sc]) + (oy - (T)tp.snk_oy[t]);
+    const T len = fabs(dx) + fabs(dy), cap = nm.elmore ? (T)tp.snk_cap[t] : (T)0;
+    if (!adj) {
+      dnl[t] = nm.delay(len, cap);
+      continue;
+    }
+    const T gl = adj[tp.M + t] * nm.slope(len, cap);
+    const T ex = gl * (T)((dx > (T)0) - (dx < (T)0)), ey = gl * (T)((dy > (T)0) - (dy < (T)0));
+    gp[tp.M + t] = -ex;
+    gp[tp.P + tp.M + t] = -ey;
+    sx += ex;
+    sy += ey;
+  }
+  if (adj) {
+    gp[v] = sx;
+    gp[tp.P + v] = sy;
+  }
+}
+
 template <typename T>
 void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y, T *dnet, const int32_t *list,
                    int n, hipStream_t s) {
@@ -298,32 +379,56 @@ void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y
 }
 
 template <typename T>
-void st_tree_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s) {
+void st_net_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s) {
   const Topo &tp = g->topo;
-  if (tp.n_nm_chunks > 0)
-    hipLaunchKernelGGL(k_st_tree_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
-                       net_model<T>(g), (T)g->c, dnl);
-  if (tp.n_big > 0) tree_net_impl<T>(g, g->st_tree, x, y, dnl, tp.big_net, tp.n_big, s);
+  const bool tree = g->lut.net_model == 2;
+  if (tp.n_nm_chunks > 0) {
+    if (tree)
+      hipLaunchKernelGGL(k_st_tree_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+                         net_model<T>(g), (T)g->c, dnl);
+    else
+      hipLaunchKernelGGL(k_st_star_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+                         net_model<T>(g), dnl);
+  }
+  if (tp.n_big > 0) {
+    if (tree)
+      tree_net_impl<T>(g, g->st_tree, x, y, dnl, tp.big_net, tp.n_big, s);
+    else
+      hipLaunchKernelGGL(k_st_star_big<T>, dim3(nbt(tp.n_big, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
+                         (const T *)nullptr, dnl, (T *)nullptr, tp.big_net, tp.n_big);
+  }
 }
 
 template <typename T>
-void st_tree_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s) {
+void st_net_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s) {
   const Topo &tp = g->topo;
-  if (tp.n_nm_chunks > 0)
-    hipLaunchKernelGGL(k_st_tree_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
-                       net_model<T>(g), (T)g->c, adj, (T *)g->st_tree_gp);
-  if (tp.n_big > 0)
-    hipLaunchKernelGGL(k_st_tree_grad<T>, dim3(nbt(tp.n_big, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
-                       (T)g->c, view<T>(g->st_tree), adj, (T *)g->st_tree_gp, tp.big_net, tp.n_big);
+  const bool tree = g->lut.net_model == 2;
+  T *gp = (T *)g->st_gp;
+  if (tp.n_nm_chunks > 0) {
+    if (tree)
+      hipLaunchKernelGGL(k_st_tree_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+                         net_model<T>(g), (T)g->c, adj, gp);
+    else
+      hipLaunchKernelGGL(k_st_star_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+                         net_model<T>(g), adj, gp);
+  }
+  if (tp.n_big > 0) {
+    if (tree)
+      hipLaunchKernelGGL(k_st_tree_grad<T>, dim3(nbt(tp.n_big, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
+                         (T)g->c, view<T>(g->st_tree), adj, gp, tp.big_net, tp.n_big);
+    else
+      hipLaunchKernelGGL(k_st_star_big<T>, dim3(nbt(tp.n_big, 256)), dim3(256), 0, s, tp, x, y, net_model<T>(g),
+                         adj, (T *)nullptr, gp, tp.big_net, tp.n_big);
+  }
 }
 
 template void tree_net_impl<float>(tdp_graph, const TreeBuf &, const float *, const float *, float *,
                                    const int32_t *, int, hipStream_t);
 template void tree_net_impl<double>(tdp_graph, const TreeBuf &, const float *, const float *, double *,
                                     const int32_t *, int, hipStream_t);
-template void st_tree_fwd_impl<float>(tdp_graph, const float *, const float *, float *, hipStream_t);
-template void st_tree_fwd_impl<double>(tdp_graph, const float *, const float *, double *, hipStream_t);
-template void st_tree_grad_impl<float>(tdp_graph, const float *, const float *, const float *, hipStream_t);
-template void st_tree_grad_impl<double>(tdp_graph, const float *, const float *, const double *, hipStream_t);
+template void st_net_fwd_impl<float>(tdp_graph, const float *, const float *, float *, hipStream_t);
+template void st_net_fwd_impl<double>(tdp_graph, const float *, const float *, double *, hipStream_t);
+template void st_net_grad_impl<float>(tdp_graph, const float *, const float *, const float *, hipStream_t);
+template void st_net_grad_impl<double>(tdp_graph, const float *, const float *, const double *, hipStream_t);
 
 }  // namespace tdp
