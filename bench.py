@@ -96,8 +96,10 @@ WA_GAMMA = 5.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # about a second of timed GPU work at 2M cells, long enough for an
+    # outside sampler of GPU activity to see it
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="C5")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (40-instance) leg of the default run")
