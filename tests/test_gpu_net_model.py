@@ -199,6 +199,19 @@ def test_nets_wider_than_a_chunk(library, net_model):
     res = compare_paths(gp, rp, st, Graph(nl), 4)
     assert res["missing"] == 0 and res["extra"] == 0
     assert res["pinned_ok"] == res["pinned"] and res["unpinned_ok"] == res["unpinned"]
+    # the smoothed TNS through the wide nets (one thread per net) and the
+    # others (net chunks)
+    v_ref, gx_ref, gy_ref, ax, ay = ref.stns(nl, lib, st, gamma=10.0, with_abs=True)
+    x, y = _xy(nl)
+    xr, yr = x.clone().requires_grad_(True), y.clone().requires_grad_(True)
+    v = tdp.SmoothTNS.apply(xr, yr, g, 10.0)
+    v.backward()
+    assert abs(float(v) - v_ref) <= 1e-4 * abs(v_ref)
+    for got, want, mag in ((xr.grad, gx_ref, ax), (yr.grad, gy_ref, ay)):
+        got = got.cpu().numpy().astype(np.float64)
+        lim = 1e-4 * np.maximum(mag, 1e-3 * np.abs(want).max())
+        assert np.all(np.abs(got - want) <= lim), np.max(np.abs(got - want) / lim)
+    assert np.abs(gx_ref[:160]).max() > 0  # the wide nets' cells carry gradient
     g.close()
 
 
