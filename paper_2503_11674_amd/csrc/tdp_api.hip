@@ -246,7 +246,7 @@ tdp_status build_common(const tdp_netlist *const *nls, int32_t count, const tdp_
   ok = ok && dalloc(g, g->st_at, T.P, es) && dalloc(g, g->st_adj, T.P, es) && dalloc(g, g->st_dnet, T.S, es) &&
        dalloc(g, g->st_gp, (size_t)2 * T.P, es) &&
        dalloc(g, g->wa_gpin, (size_t)2 * T.P) && dalloc(g, g->xy, T.N) &&
-       dalloc(g, g->xy_wa, T.N) && dalloc(g, g->cxy_nm, (size_t)T.n_nm_chunks * CHUNK);
+       dalloc(g, g->xy_wa, T.N) && dalloc(g, g->xy_st, T.N) && dalloc(g, g->cxy_nm, (size_t)T.n_nm_chunks * CHUNK);
   // spanning-tree net model: scratch of the net pass and of the smoothed TNS
   if (lib->net_model == 2) {
     auto tree_alloc = [&](TreeBuf &b) {

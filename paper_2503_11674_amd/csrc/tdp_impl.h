@@ -34,7 +34,8 @@ void tree_net_impl(tdp_graph g, const TreeBuf &b, const float *x, const float *y
 template <typename T>
 void st_net_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s);
 // the smoothed TNS's gradient per pin and axis (into st_gp) from the adjoint
-// of the net delays
+// of the net delays, at the positions of the last st_net_fwd_impl call (its
+// packed copy; x and y serve the nets wider than a chunk)
 template <typename T>
 void st_net_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj, hipStream_t s);
 // WNS / TNS / violated count per instance from the endpoint slacks

@@ -379,6 +379,7 @@ struct tdp_graph_s {
   float *wa_gpin = nullptr;
   float2 *xy = nullptr;        // [N] positions packed by the last timing update
   float2 *xy_wa = nullptr;     // [N] positions packed by a WA call
+  float2 *xy_st = nullptr;     // [N] positions packed by the last smoothed-TNS forward call
   float2 *cxy_nm = nullptr;    // [net-chunk slots] cell coordinates the last update gathered
 
   tdp::Profiler prof;

@@ -13,7 +13,8 @@
 //   value:           -g * sum_e softplus(-s(e)/g)
 // The adjoint runs the levels top-down: dv/dA(e) = -sigmoid(-s(e)/g); an
 // output passes its adjoint to input j in proportion to softmax_j(a/g); a
-// driver collects the adjoints of its sinks.  dv/d dnet(t) is the adjoint at
+// driver collects the adjoints of its sinks (per level over the net chunks,
+// as the required-time pass runs).  dv/d dnet(t) is the adjoint at
 // t, and on a star net d dnet/dX_s = dnet'(L) sign(X_s - X_t) = -d dnet/dX_t
 // (the spanning-tree model differentiates through its tree).  The net delays
 // and the per-pin terms come from the net kernels of tdp_tree.hip.
@@ -84,18 +85,55 @@ __global__ void __launch_bounds__(256) k_st_end(Topo tp, const double *__restric
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// The adjoint of one level's nets (drivers at that level, top-down), a lane
+// per net pin: a combinational-input sink takes its cell output's adjoint
+// times its softmax weight (the output's level is higher, so it is final), an
+// endpoint keeps the seed the endpoint kernel wrote; the driver collects its
+// sinks' (a segment sum).
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_bwd(Topo tp, int c0, int c1, T gam, const T *__restrict__ darc,
+__global__ void __launch_bounds__(256) k_st_bwd(Topo tp, int ch0, int ch1, T gam, const T *__restrict__ darc,
                                                  const T *__restrict__ sa, T *__restrict__ adj) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
-  const int v = tp.n_start + c;
+  const int lane = wave_lane();
+  const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= ch1) return;
+  const int4 rec = tp.nm_rec[chunk * CHUNK + lane];
+  const int p = rec.x, vo = rec.z;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
+  T a = 0;
+  if (p >= 0 && lane != head) {
+    if (vo >= 0) {
+      a = adj[vo] * exp((sa[p] + darc[p - tp.M] - sa[vo]) / gam);
+      adj[p] = a;
+    } else {
+      a = adj[p];
+    }
+  }
+  a = seg_sum(a, lane, head, tail);
+  if (p >= 0 && lane == head) adj[p] = a;
+}
+
+// the same for nets wider than a chunk, one thread per net
+template <typename T>
+__global__ void k_st_bwd_big(Topo tp, int i0, int i1, T gam, const T *__restrict__ darc, const T *__restrict__ sa,
+                             T *__restrict__ adj) {
+  const int i = i0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= i1) return;
+  const int v = tp.big_net[i];
   T ab = 0;
-  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) ab += adj[tp.M + tp.net_sink[k]];
+  for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
+    const int t = tp.net_sink[k];
+    const int p = tp.M + t;
+    T a;
+    if (t < tp.A) {
+      const int vo = tp.n_start + tp.snk_comb[t];
+      a = adj[vo] * exp((sa[p] + darc[t] - sa[vo]) / gam);
+      adj[p] = a;
+    } else {
+      a = adj[p];
+    }
+    ab += a;
+  }
   adj[v] = ab;
-  const T av = sa[v];
-  for (int t = tp.comb_inptr[c]; t < tp.comb_inptr[c + 1]; ++t)
-    adj[tp.M + t] = ab * exp((sa[tp.M + t] + darc[t] - av) / gam);
 }
 
 // gradient per cell: the sum of its pins' gradients (its output pin, then its
@@ -172,10 +210,14 @@ void stns_bwd_impl(tdp_graph g, const double *gout, float *gx, float *gy, hipStr
   const Topo &tp = g->topo;
   prof_begin(g, TDP_STAGE_STNS, s);
   const T gam = (T)g->st_gamma;
-  for (int l = tp.D; l >= 1; --l) {
-    const int c0 = g->lv.lvl[l - 1], c1 = g->lv.lvl[l];
-    if (c1 > c0)
-      hipLaunchKernelGGL(k_st_bwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
+  for (int l = tp.D; l >= 0; --l) {
+    const int ch0 = g->lv.nm_lvl[l], ch1 = g->lv.nm_lvl[l + 1];
+    if (ch1 > ch0)
+      hipLaunchKernelGGL(k_st_bwd<T>, dim3(nb(ch1 - ch0, 4)), dim3(256), 0, s, tp, ch0, ch1, gam,
+                         (const T *)g->darc, (const T *)g->st_at, (T *)g->st_adj);
+    const int b0 = g->lv.big_lvl[l], b1 = g->lv.big_lvl[l + 1];
+    if (b1 > b0)
+      hipLaunchKernelGGL(k_st_bwd_big<T>, dim3(nb(b1 - b0, 64)), dim3(64), 0, s, tp, b0, b1, gam,
                          (const T *)g->darc, (const T *)g->st_at, (T *)g->st_adj);
   }
   st_net_grad_impl<T>(g, g->st_x, g->st_y, (const T *)g->st_adj, s);

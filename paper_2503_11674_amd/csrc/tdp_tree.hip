@@ -24,6 +24,7 @@
 // whose net delays and position gradients for the star models (0 and 1)
 // are here too, in the same two forms.
 #include "tdp_impl.h"
+#include "tdp_prims.h"
 #include "tdp_tree.h"
 
 namespace tdp {
@@ -197,8 +198,7 @@ struct ChunkLane {
   int ty;
 };
 
-__device__ __forceinline__ ChunkLane chunk_lane(const Topo &tp, const float *__restrict__ x,
-                                                const float *__restrict__ y, int chunk) {
+__device__ __forceinline__ ChunkLane chunk_lane(const Topo &tp, const float2 *__restrict__ xy, int chunk) {
   ChunkLane c;
   c.lane = wave_lane();
   const int k = chunk * CHUNK + c.lane;
@@ -208,8 +208,9 @@ __device__ __forceinline__ ChunkLane chunk_lane(const Topo &tp, const float *__r
   c.tail = (rec.w >> 8) & 63;
   c.ty = (rec.w >> 16) & 255;
   c.sink = c.p >= 0 && c.lane != c.head;
-  c.fx = rec.y >= 0 ? x[rec.y] : 0.f;
-  c.fy = rec.y >= 0 ? y[rec.y] : 0.f;
+  const float2 q = rec.y >= 0 ? xy[rec.y] : make_float2(0.f, 0.f);
+  c.fx = q.x;
+  c.fy = q.y;
   c.fox = tp.nm_ox[k];
   c.foy = tp.nm_oy[k];
   return c;
@@ -222,24 +223,22 @@ __device__ __forceinline__ ChunkTree<T> chunk_tree(const Topo &tp, const ChunkLa
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_tree_chunks(Topo tp, const float *__restrict__ x,
-                                                         const float *__restrict__ y, NetModel<T> nm, T cw,
-                                                         T *__restrict__ dnl) {
+__global__ void __launch_bounds__(256) k_st_tree_chunks(Topo tp, const float2 *__restrict__ xy, NetModel<T> nm, T cw,
+                                                        T *__restrict__ dnl) {
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
-  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  const ChunkLane c = chunk_lane(tp, xy, chunk);
   const ChunkTree<T> tr = chunk_tree<T>(tp, c, cw);
   const T dn = tree_chunk_delay<T>(nm, tr);
   if (c.sink) dnl[c.p - tp.M] = dn;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_tree_grad_chunks(Topo tp, const float *__restrict__ x,
-                                                              const float *__restrict__ y, NetModel<T> nm, T cw,
-                                                              const T *__restrict__ adj, T *__restrict__ gp) {
+__global__ void __launch_bounds__(256) k_st_tree_grad_chunks(Topo tp, const float2 *__restrict__ xy, NetModel<T> nm,
+                                                             T cw, const T *__restrict__ adj, T *__restrict__ gp) {
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
-  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  const ChunkLane c = chunk_lane(tp, xy, chunk);
   const ChunkTree<T> tr = chunk_tree<T>(tp, c, cw);
   const int lane = c.lane, head = c.head, tail = c.tail;
   // A: the adjoint summed over the subtree (reverse joining order)
@@ -302,12 +301,11 @@ __device__ __forceinline__ T star_diff(const ChunkLane &c, T &dx, T &dy) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_star_chunks(Topo tp, const float *__restrict__ x,
-                                                         const float *__restrict__ y, NetModel<T> nm,
-                                                         T *__restrict__ dnl) {
+__global__ void __launch_bounds__(256) k_st_star_chunks(Topo tp, const float2 *__restrict__ xy, NetModel<T> nm,
+                                                        T *__restrict__ dnl) {
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
-  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  const ChunkLane c = chunk_lane(tp, xy, chunk);
   T dx, dy;
   const T len = star_diff<T>(c, dx, dy);
   if (c.sink) dnl[c.p - tp.M] = nm.delay(len, nm.elmore ? (T)tp.type_cap[c.ty] : (T)0);
@@ -315,12 +313,11 @@ __global__ void __launch_bounds__(256) k_st_star_chunks(Topo tp, const float *__
 
 // per pin: a sink minus its wire's term, the driver the sum of its sinks'
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_star_grad_chunks(Topo tp, const float *__restrict__ x,
-                                                              const float *__restrict__ y, NetModel<T> nm,
-                                                              const T *__restrict__ adj, T *__restrict__ gp) {
+__global__ void __launch_bounds__(256) k_st_star_grad_chunks(Topo tp, const float2 *__restrict__ xy, NetModel<T> nm,
+                                                             const T *__restrict__ adj, T *__restrict__ gp) {
   const int chunk = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (chunk >= tp.n_nm_chunks) return;
-  const ChunkLane c = chunk_lane(tp, x, y, chunk);
+  const ChunkLane c = chunk_lane(tp, xy, chunk);
   T dx, dy;
   const T len = star_diff<T>(c, dx, dy);
   const T gl = c.sink ? adj[c.p] * nm.slope(len, nm.elmore ? (T)tp.type_cap[c.ty] : (T)0) : (T)0;
@@ -382,12 +379,14 @@ template <typename T>
 void st_net_fwd_impl(tdp_graph g, const float *x, const float *y, T *dnl, hipStream_t s) {
   const Topo &tp = g->topo;
   const bool tree = g->lut.net_model == 2;
+  // the chunk kernels read the positions packed once per forward call
+  pack_xy(x, y, g->xy_st, tp.N, s);
   if (tp.n_nm_chunks > 0) {
     if (tree)
-      hipLaunchKernelGGL(k_st_tree_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+      hipLaunchKernelGGL(k_st_tree_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->xy_st,
                          net_model<T>(g), (T)g->c, dnl);
     else
-      hipLaunchKernelGGL(k_st_star_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+      hipLaunchKernelGGL(k_st_star_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->xy_st,
                          net_model<T>(g), dnl);
   }
   if (tp.n_big > 0) {
@@ -406,10 +405,10 @@ void st_net_grad_impl(tdp_graph g, const float *x, const float *y, const T *adj,
   T *gp = (T *)g->st_gp;
   if (tp.n_nm_chunks > 0) {
     if (tree)
-      hipLaunchKernelGGL(k_st_tree_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+      hipLaunchKernelGGL(k_st_tree_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->xy_st,
                          net_model<T>(g), (T)g->c, adj, gp);
     else
-      hipLaunchKernelGGL(k_st_star_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, x, y,
+      hipLaunchKernelGGL(k_st_star_grad_chunks<T>, dim3(nbt(tp.n_nm_chunks, 4)), dim3(256), 0, s, tp, g->xy_st,
                          net_model<T>(g), adj, gp);
   }
   if (tp.n_big > 0) {
