@@ -41,22 +41,28 @@ __global__ void k_st_start(Topo tp, const T *__restrict__ at, T *__restrict__ sa
   if (v < tp.n_start) sa[v] = at[v];
 }
 
+// one level's combinational cells on the forward chunks, a lane per input
+// (each cell a segment): the input's arrival, then the cell's log-sum-exp
+// over its inputs by segment reductions
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_fwd(Topo tp, int c0, int c1, T gam, const T *__restrict__ dnl,
+__global__ void __launch_bounds__(256) k_st_fwd(Topo tp, int ch0, int ch1, T gam, const T *__restrict__ dnl,
                                                  const T *__restrict__ darc, T *__restrict__ sa) {
-  const int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= c1) return;
-  const int b = tp.comb_inptr[c], e = tp.comb_inptr[c + 1];
-  T m = -__builtin_huge_val();
-  for (int t = b; t < e; ++t) {
-    const T ai = sa[tp.snk_drv[t]] + dnl[t];
+  const int lane = wave_lane();
+  const int chunk = ch0 + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (chunk >= ch1) return;
+  const int4 rec = tp.fw_rec[chunk * CHUNK + lane];
+  const int t = rec.x;
+  const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
+  const bool valid = t >= 0;
+  T a = -pos_inf<T>();
+  if (valid) {
+    const T ai = sa[rec.y] + dnl[t];
     sa[tp.M + t] = ai;
-    const T a = ai + darc[t];
-    m = a > m ? a : m;
+    a = ai + darc[t];
   }
-  T sum = 0;
-  for (int t = b; t < e; ++t) sum += exp((sa[tp.M + t] + darc[t] - m) / gam);
-  sa[tp.n_start + c] = m + gam * log(sum);
+  const T m = seg_max(a, lane, head, tail);
+  const T sum = seg_sum(valid ? exp((a - m) / gam) : (T)0, lane, head, tail);
+  if (valid && lane == head) sa[tp.n_start + rec.z] = m + gam * log(sum);
 }
 
 // endpoint values and adjoint seeds; per-block partial sums of the value
@@ -190,9 +196,9 @@ void stns_fwd_impl(tdp_graph g, const float *x, const float *y, float gamma, dou
     hipLaunchKernelGGL(k_st_start<T>, dim3(nb(tp.n_start, 256)), dim3(256), 0, s, tp, (const T *)g->at,
                        (T *)g->st_at);
   for (int l = 1; l <= tp.D; ++l) {
-    const int c0 = g->lv.lvl[l - 1], c1 = g->lv.lvl[l];
-    if (c1 > c0)
-      hipLaunchKernelGGL(k_st_fwd<T>, dim3(nb(c1 - c0, 256)), dim3(256), 0, s, tp, c0, c1, gam,
+    const int ch0 = g->lv.fw_lvl[l - 1], ch1 = g->lv.fw_lvl[l];
+    if (ch1 > ch0)
+      hipLaunchKernelGGL(k_st_fwd<T>, dim3(nb(ch1 - ch0, 4)), dim3(256), 0, s, tp, ch0, ch1, gam,
                          (const T *)g->st_dnet, (const T *)g->darc, (T *)g->st_at);
   }
   hipLaunchKernelGGL(k_st_end<T>, dim3(RED_BLOCKS), dim3(256), 0, s, tp, g->d_inst_req, gam, (const T *)g->st_dnet,
