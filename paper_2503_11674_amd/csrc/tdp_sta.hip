@@ -192,18 +192,22 @@ __device__ __forceinline__ void netpass_chunk(const Topo &tp, const LutView &L, 
   const int head = rec.w & 63, tail = (rec.w >> 8) & 63;
   // pin coordinate = cell coordinate + offset; differences are taken as
   // (cell - cell) + (offset - offset), exact to the rounding of the result
-  // rather than of a die-scale sum
+  // rather than of a die-scale sum.  A port has no cell and its offset is its
+  // position: for the wire lengths it is taken as the base (offset 0), so a
+  // port next to a cell far from the origin does not cancel two die-scale
+  // numbers
   const float2 q = cell >= 0 ? xy[cell] : make_float2(0.f, 0.f);
   cxy_nm[k] = q;  // kept for the weighted-average wirelength at these positions
-  const T cx = (T)q.x, cy = (T)q.y;
-  const T ox = (T)tp.nm_ox[k], oy = (T)tp.nm_oy[k];
+  const float fox = tp.nm_ox[k], foy = tp.nm_oy[k];
+  const T cx = cell >= 0 ? (T)q.x : (T)fox, cy = cell >= 0 ? (T)q.y : (T)foy;
+  const T ox = cell >= 0 ? (T)fox : (T)0, oy = cell >= 0 ? (T)foy : (T)0;
   const T cxd = __shfl(cx, head, 64), cyd = __shfl(cy, head, 64);
   const T oxd = __shfl(ox, head, 64), oyd = __shfl(oy, head, 64);
   const bool sink = p >= 0 && lane != head;
   T len, dn = 0;
   if constexpr (TREE) {
-    const ChunkTree<T> tr = tree_chunk_build<T>(cw, lane, head, tail, sink, q.x, q.y, tp.nm_ox[k], tp.nm_oy[k], cx,
-                                                cy, ox, oy, sink ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0);
+    const ChunkTree<T> tr = tree_chunk_build<T>(cw, lane, head, tail, sink, q.x, q.y, fox, foy, cx, cy, ox, oy,
+                                                sink ? (T)tp.type_cap[(rec.w >> 16) & 255] : (T)0);
     len = tr.len;
     dn = tree_chunk_delay<T>(nm, tr);
   } else {
@@ -273,8 +277,9 @@ __global__ void k_netpass_big(Topo tp, LutView L, const float *__restrict__ x, c
   if (i >= tp.n_big) return;
   const int v = tp.big_net[i];
   const int dc = tp.drv_cell[v];
-  const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
-  const T ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
+  // a port driver: its position as the base (see the chunk form)
+  const T cx = dc >= 0 ? (T)x[dc] : (T)tp.drv_ox[v], cy = dc >= 0 ? (T)y[dc] : (T)tp.drv_oy[v];
+  const T ox = dc >= 0 ? (T)tp.drv_ox[v] : (T)0, oy = dc >= 0 ? (T)tp.drv_oy[v] : (T)0;
   T wl = tree_wl ? tree_wl[v] : (T)0;
   for (int k = tp.net_ptr[v]; !tree_wl && k < tp.net_ptr[v + 1]; ++k) {
     const int t = tp.net_sink[k];

@@ -10,7 +10,10 @@
 // each sink's wire from its parent, the capacitance at and below it (reverse
 // joining order) and its Elmore delay (joining order): the operations of the
 // one-thread-per-net form, in its order.  Every lane of the wave must call
-// these functions.
+// these functions.  (fx, fy, fox, foy) are a pin's cell coordinates and
+// offset as given (a port: no cell, its position as the offset), which
+// decide the topology; (cx, cy, ox, oy) the same position in the timing
+// precision with a port's position as the base, for the wire lengths.
 #pragma once
 
 #include "tdp_wave.h"

@@ -43,31 +43,38 @@ static TreeView<T> view(const TreeBuf &b) {
   return TreeView<T>{b.dist, b.par, b.ord, (T *)b.len, (T *)b.cd, (T *)b.aux, (T *)b.aux2, (T *)b.wl};
 }
 
-// a pin of net v: its cell's coordinates and its offset (slot -1: the driver)
+// a pin of net v: its cell's coordinates and its offset (slot -1: the
+// driver; a port has no cell, and its offset is its position)
 struct PinXY {
   float cx, cy, ox, oy;
+  bool port;
 };
 
 __device__ __forceinline__ PinXY tree_pin(const Topo &tp, const float *__restrict__ x, const float *__restrict__ y,
                                           int v, int k) {
   if (k < 0) {
     const int dc = tp.drv_cell[v];
-    return PinXY{dc >= 0 ? x[dc] : 0.f, dc >= 0 ? y[dc] : 0.f, tp.drv_ox[v], tp.drv_oy[v]};
+    return PinXY{dc >= 0 ? x[dc] : 0.f, dc >= 0 ? y[dc] : 0.f, tp.drv_ox[v], tp.drv_oy[v], dc < 0};
   }
   const int t = tp.net_sink[k];
   const int sc = tp.snk_cell[t];
-  return PinXY{x[sc], y[sc], tp.snk_ox[t], tp.snk_oy[t]};
+  return PinXY{x[sc], y[sc], tp.snk_ox[t], tp.snk_oy[t], false};
 }
 
 __device__ __forceinline__ float tree_fdist(const PinXY &a, const PinXY &b) {
   return tree_fdist(a.cx, a.cy, a.ox, a.oy, b.cx, b.cy, b.ox, b.oy);
 }
 
-// (parent - child) per axis in T: (cell difference) + (offset difference)
+// (parent - child) per axis in T: (base difference) + (offset difference),
+// a port's position taken as its base (no die-scale cancellation)
 template <typename T>
 __device__ __forceinline__ void tree_diff(const PinXY &p, const PinXY &c, T &dx, T &dy) {
-  dx = ((T)p.cx - (T)c.cx) + ((T)p.ox - (T)c.ox);
-  dy = ((T)p.cy - (T)c.cy) + ((T)p.oy - (T)c.oy);
+  auto bx = [](const PinXY &a) { return a.port ? (T)a.ox : (T)a.cx; };
+  auto by = [](const PinXY &a) { return a.port ? (T)a.oy : (T)a.cy; };
+  auto fx = [](const PinXY &a) { return a.port ? (T)0 : (T)a.ox; };
+  auto fy = [](const PinXY &a) { return a.port ? (T)0 : (T)a.oy; };
+  dx = (bx(p) - bx(c)) + (fx(p) - fx(c));
+  dy = (by(p) - by(c)) + (fy(p) - fy(c));
 }
 
 // Prim's tree of net v, then each slot's wire length and capacitance below;
@@ -193,10 +200,20 @@ __global__ void __launch_bounds__(256) k_st_tree_grad(Topo tp, const float *__re
 // lane data, its trees, and (forward) the sinks' delays
 struct ChunkLane {
   int lane, p, head, tail;
-  bool sink;
+  bool sink, port;
   float fx, fy, fox, foy;
   int ty;
 };
+
+// a chunk lane's position in T for the wire lengths: a port's position as
+// the base (see the net pass)
+template <typename T>
+__device__ __forceinline__ void lane_base(const ChunkLane &c, T &cx, T &cy, T &ox, T &oy) {
+  cx = c.port ? (T)c.fox : (T)c.fx;
+  cy = c.port ? (T)c.foy : (T)c.fy;
+  ox = c.port ? (T)0 : (T)c.fox;
+  oy = c.port ? (T)0 : (T)c.foy;
+}
 
 __device__ __forceinline__ ChunkLane chunk_lane(const Topo &tp, const float2 *__restrict__ xy, int chunk) {
   ChunkLane c;
@@ -209,6 +226,7 @@ __device__ __forceinline__ ChunkLane chunk_lane(const Topo &tp, const float2 *__
   c.ty = (rec.w >> 16) & 255;
   c.sink = c.p >= 0 && c.lane != c.head;
   const float2 q = rec.y >= 0 ? xy[rec.y] : make_float2(0.f, 0.f);
+  c.port = rec.y < 0;
   c.fx = q.x;
   c.fy = q.y;
   c.fox = tp.nm_ox[k];
@@ -218,8 +236,10 @@ __device__ __forceinline__ ChunkLane chunk_lane(const Topo &tp, const float2 *__
 
 template <typename T>
 __device__ __forceinline__ ChunkTree<T> chunk_tree(const Topo &tp, const ChunkLane &c, T cw) {
-  return tree_chunk_build<T>(cw, c.lane, c.head, c.tail, c.sink, c.fx, c.fy, c.fox, c.foy, (T)c.fx, (T)c.fy,
-                             (T)c.fox, (T)c.foy, c.sink ? (T)tp.type_cap[c.ty] : (T)0);
+  T cx, cy, ox, oy;
+  lane_base<T>(c, cx, cy, ox, oy);
+  return tree_chunk_build<T>(cw, c.lane, c.head, c.tail, c.sink, c.fx, c.fy, c.fox, c.foy, cx, cy, ox, oy,
+                             c.sink ? (T)tp.type_cap[c.ty] : (T)0);
 }
 
 template <typename T>
@@ -259,9 +279,11 @@ __global__ void __launch_bounds__(256) k_st_tree_grad_chunks(Topo tp, const floa
       gl = nm.rs * (cw * tr.len + tr.cd) * a + cw * bp;
     }
   }
-  const T pcx = __shfl((T)c.fx, tr.par, 64), pcy = __shfl((T)c.fy, tr.par, 64);
-  const T pox = __shfl((T)c.fox, tr.par, 64), poy = __shfl((T)c.foy, tr.par, 64);
-  const T dx = (pcx - (T)c.fx) + (pox - (T)c.fox), dy = (pcy - (T)c.fy) + (poy - (T)c.foy);
+  T cx, cy, ox, oy;
+  lane_base<T>(c, cx, cy, ox, oy);
+  const T pcx = __shfl(cx, tr.par, 64), pcy = __shfl(cy, tr.par, 64);
+  const T pox = __shfl(ox, tr.par, 64), poy = __shfl(oy, tr.par, 64);
+  const T dx = (pcx - cx) + (pox - ox), dy = (pcy - cy) + (poy - oy);
   const T ex = c.sink ? gl * (T)((dx > (T)0) - (dx < (T)0)) : (T)0;
   const T ey = c.sink ? gl * (T)((dy > (T)0) - (dy < (T)0)) : (T)0;
   // per pin, in joining order: minus its own wire's term, plus its children's
@@ -293,10 +315,12 @@ __global__ void __launch_bounds__(256) k_st_tree_grad_chunks(Topo tp, const floa
 // difference), its Manhattan length (0 off the sinks) returned
 template <typename T>
 __device__ __forceinline__ T star_diff(const ChunkLane &c, T &dx, T &dy) {
-  const T cxd = __shfl((T)c.fx, c.head, 64), cyd = __shfl((T)c.fy, c.head, 64);
-  const T oxd = __shfl((T)c.fox, c.head, 64), oyd = __shfl((T)c.foy, c.head, 64);
-  dx = (cxd - (T)c.fx) + (oxd - (T)c.fox);
-  dy = (cyd - (T)c.fy) + (oyd - (T)c.foy);
+  T cx, cy, ox, oy;
+  lane_base<T>(c, cx, cy, ox, oy);
+  const T cxd = __shfl(cx, c.head, 64), cyd = __shfl(cy, c.head, 64);
+  const T oxd = __shfl(ox, c.head, 64), oyd = __shfl(oy, c.head, 64);
+  dx = (cxd - cx) + (oxd - ox);
+  dy = (cyd - cy) + (oyd - oy);
   return c.sink ? fabs(dx) + fabs(dy) : (T)0;
 }
 
@@ -340,8 +364,9 @@ __global__ void __launch_bounds__(256) k_st_star_big(Topo tp, const float *__res
   if (i >= n) return;
   const int v = list[i];
   const int dc = tp.drv_cell[v];
-  const T cx = dc >= 0 ? (T)x[dc] : (T)0, cy = dc >= 0 ? (T)y[dc] : (T)0;
-  const T ox = (T)tp.drv_ox[v], oy = (T)tp.drv_oy[v];
+  // a port driver: its position as the base
+  const T cx = dc >= 0 ? (T)x[dc] : (T)tp.drv_ox[v], cy = dc >= 0 ? (T)y[dc] : (T)tp.drv_oy[v];
+  const T ox = dc >= 0 ? (T)tp.drv_ox[v] : (T)0, oy = dc >= 0 ? (T)tp.drv_oy[v] : (T)0;
   T sx = 0, sy = 0;
   for (int k = tp.net_ptr[v]; k < tp.net_ptr[v + 1]; ++k) {
     const int t = tp.net_sink[k];

@@ -250,3 +250,34 @@ def test_tree_hand_net_is_exact(wide, precision):
     inf_ok, bad, worst = timing_close(o["at"], st["at"], rtol=1e-6 if precision == "f32" else 1e-12)
     assert inf_ok and bad == 0, (bad, worst)
     g.close()
+
+
+def test_tree_full_size_2m_cells(library):
+    """The 2M-cell workload under the spanning-tree model: every pin's timing
+    against the oracle in the library's default sweep form and in the
+    per-level one, the summary, and the extraction's path count."""
+    from tests.test_gpu_fullsize import _timing_checks
+    tdp = _tdp()
+    lib = _tree(library)
+    cfg = netgen.CONFIGS["C5"]
+    print("[tree] generating the 2M-cell workload", flush=True)
+    nl = with_clock(netgen.make_netlist(cfg), lib)
+    st = ref.sta(nl, lib)
+    K = cfg.top_k_paths
+    k = max(1, K // st["n_fail"])
+    print(f"[tree] oracle timing done: n_fail={st['n_fail']} k={k}", flush=True)
+    g = tdp.TimingGraph(nl, lib, max_paths=K, max_k=k)
+    x, y = _xy(nl)
+    for mode in (None, 0):
+        if mode is not None:
+            g.set_tuning(sweep_mode=mode)
+        g.sta_update(x, y)
+        o = {kk: v.cpu().numpy() for kk, v in g.export().items()}
+        _timing_checks(nl, st, o)
+        wns, tns, nf = g.summary()
+        assert nf == st["n_fail"]
+        assert abs(wns - st["wns"]) <= 1e-4 * abs(st["wns"]) and abs(tns - st["tns"]) <= 1e-4 * abs(st["tns"])
+        g.extract_paths(n=-1, k=k, K=K)
+        assert g.paths_count()[0] == min(K, st["n_fail"] * k)
+        print(f"[tree] sweep form {mode}: timing and summary match the oracle", flush=True)
+    g.close()
