@@ -338,3 +338,32 @@ def test_stns_gradient_on_a_deep_tree_matches_finite_differences(library):
             gr = (gx if axis == 0 else gy)[cc]
             assert abs(fd - gr) <= 1e-5 * max(1e-2, abs(gr)), (cc, axis, fd, gr)
         assert abs(gx[cc]) + abs(gy[cc]) > 1e-4
+
+
+def test_dyadic_hand_tree_by_hand():
+    """A port at the origin drives sinks at (8, 0), (16, 0), (16, 8) and
+    (24, 0) under the dyadic library (r = 1/16, c = 1/4, pin capacitance 2,
+    scale 1).  The tree is port -> A(8, 0) -> B(16, 0) -> {C(16, 8), D(24, 0)}
+    (C and D tie at distance 8 from B; C, listed first, joins first, and D
+    still hangs from B, which reached it first).  By hand, every wire 8 um
+    (c L = 2, r L = 1/2): C_below(C) = C_below(D) = 2, C_below(B) = 2 + (2 + 2)
+    + (2 + 2) = 10, C_below(A) = 2 + 2 + 10 = 14; delays
+    A = 1/2 (1 + 14) = 7.5, B = 7.5 + 1/2 (1 + 10) = 13,
+    C = D = 13 + 1/2 (1 + 2) = 14.5; load 4 x 2 + 32 / 4 = 16."""
+    from tests import handnets
+    lib = dict(handnets.dyadic_library(), net_model=2)
+    sx, sy = [8.0, 16.0, 16.0, 24.0], [0.0, 0.0, 8.0, 0.0]
+    n = 4
+    cells = [(0, 1)] * n + [(netgen.FF_TYPE, 1)] * n
+    port = 4 * n
+    nets = [(port, [2 * i for i in range(n)])] + [(2 * i + 1, [2 * n + 2 * i]) for i in range(n)] + \
+        [(2 * n + 2 * i + 1, []) for i in range(n)]
+    nl, _ = handnets.build(cells, 1, nets, sx + [v + 4.0 for v in sx], sy + sy, port_xy=[(0.0, 0.0)],
+                           clock_period=400.0)
+    par = ref.rc_tree(nl)
+    assert [int(par[2 * i]) for i in range(n)] == [port, 0, 2, 2]
+    st = ref.sta(nl, lib)
+    assert st["dnet"][[0, 2, 4, 6]].tolist() == [7.5, 13.0, 14.5, 14.5]
+    assert st["load"][port] == 16.0
+    # each two-pin net from a cell to its flip-flop is a 4 um wire: 1/4 (1/2 + 2)
+    assert st["dnet"][[2 * n + 2 * i for i in range(n)]].tolist() == [0.625] * n
